@@ -1,0 +1,30 @@
+"""Plane-wave excitation (Sec. 2 of the paper, the entries of e).
+
+e_m = (n x f_m, n x E^i) = int f_m . E^i dS for tangential f_m, with
+E^i(r) = pol exp(i k khat . r) (unit amplitude, e^{-i omega t} convention).
+On cell c the RWG piece is sigma (r - r_m^c)/(2 A_c), so with the 7-point rule
+
+  e_m = sum_{c in m} sigma/2 sum_q w_q (r_q - r_m^c) . pol exp(i k khat . r_q).
+"""
+
+import numpy as np
+
+from .quadrature import tri7_points
+
+__all__ = ["planewave"]
+
+
+def planewave(top, k, khat, pol):
+    """e [nrhs, N] complex128 for plane waves khat [nrhs,3], pol [nrhs,3]."""
+    khat = np.atleast_2d(np.asarray(khat, dtype=np.float64))
+    pol = np.atleast_2d(np.asarray(pol, dtype=np.float64))
+    pts, w = tri7_points(top.xyz, top.tri)
+    e = np.zeros((len(khat), top.N), dtype=np.complex128)
+    for l in range(len(khat)):
+        phase = np.exp(1j * k * (pts @ khat[l]))            # [C,7]
+        for c in range(top.C):
+            for i in range(3):
+                m = top.cell_edges[c, i]
+                arm = pts[c] - top.xyz[top.tri[c, i]]          # [7,3]
+                e[l, m] += top.cell_sign[c, i] / 2.0 * np.sum(w * (arm @ pol[l]) * phase[c])
+    return e
