@@ -1,0 +1,184 @@
+/*
+ * rfcmp -- refinement-free Calderon multiplicative preconditioner (RF-CMP)
+ * for the electric field integral equation on closed PEC surfaces, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. B. Adrian, F. P. Andriulli, T. F. Eibert, "On a Refinement-Free
+ * Calderon Multiplicative Preconditioner for the Electric Field Integral
+ * Equation", arXiv:1803.08333.
+ *
+ * Problem (Sec. 2): closed, oriented triangulation Gamma; RWG expansion
+ * functions not normalised by edge length (eq. RWGdef); Petrov-Galerkin
+ * system T j = -e with T = i k T_A + T_Phi/(i k), time convention e^{-i w t},
+ * j normalised by the wave impedance.  Preconditioned system (Sec. 3,
+ * eq. NewFormulation, with the scalings of Sec. 4):
+ *     P_o^H T^H P_m T P_o i = -P_o^H T^H P_m e,   j = P_o i.
+ *
+ * Conventions shared by every entry point
+ *   - Status: negative = error (outputs untouched), 0 = OK, positive =
+ *     warning.  rfcmp_last_error() describes the last failure on the calling
+ *     thread.  No C++ exception crosses this interface.
+ *   - Host pointers are read during the call only; the library copies what
+ *     it keeps.  Device pointers are caller-owned, must stay valid until the
+ *     enqueued work on `stream` completes, and are never freed here.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     is enqueued on it; calls that return host values synchronise it.
+ *   - Complex vectors are interleaved (re, im).  "c128" = two doubles per
+ *     entry, "c64" = two floats.  Batched vectors are [nrhs][n], contiguous.
+ *   - RWG (edge) order: edges sorted by (min vertex, max vertex); c+ is the
+ *     cell that walks the edge from its min to its max vertex in its CCW
+ *     order.  Sigma[n,c+] = +1, Sigma[n,c-] = -1; Lambda[n,min] = +1,
+ *     Lambda[n,max] = -1.
+ *   - Handles are not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef RFCMP_H
+#define RFCMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RFCMP_OK = 0,
+  RFCMP_W_NOT_CONVERGED = 1,      /* solve stopped at maxit; best iterate returned */
+  RFCMP_E_ARG = -1,               /* invalid argument (NULL, size, k <= 0, non-unit vector, ...) */
+  RFCMP_E_MESH_OPEN = -2,         /* an edge with fewer or more than two cells */
+  RFCMP_E_MESH_NONMANIFOLD = -3,  /* a vertex index out of range or a repeated cell vertex */
+  RFCMP_E_MESH_ORIENT = -4,       /* two cells walk an edge in the same direction */
+  RFCMP_E_MESH_DISCONNECTED = -5, /* more than one connected component */
+  RFCMP_E_MESH_DEGENERATE = -6,   /* a cell of zero area */
+  RFCMP_E_OOM = -7,               /* device or host allocation failed */
+  RFCMP_E_HIP = -8,               /* a HIP runtime call failed */
+  RFCMP_E_BREAKDOWN = -9,         /* CG breakdown: p^H A p <= 0 or not finite */
+  RFCMP_E_STATE = -10             /* call not valid in the handle's state */
+} rfcmp_status;
+
+/* Description of the last error on the calling thread (valid until the next
+ * failing call on that thread); "" if none. */
+const char* rfcmp_last_error(void);
+const char* rfcmp_version(void);
+
+/* ------------------------------------------------------------------ mesh */
+typedef struct rfcmp_mesh_s* rfcmp_mesh;
+
+/* Topology and sparse structure of a closed triangle mesh (Sec. 2: RWG
+ * functions eq. RWGdef, star/loop matrices, Gram matrices; Sec. 3: closed
+ * form of the mixed Gram matrix).  xyz: host double [n_vertices][3] in
+ * metres; tri: host int32 [n_cells][3], counter-clockwise seen from outside.
+ * Validates: closed, 2-manifold, consistently oriented, connected, no
+ * zero-area cell (RFCMP_E_MESH_*).  Host work only. */
+rfcmp_status rfcmp_mesh_create(const double* xyz, int64_t n_vertices,
+                               const int32_t* tri, int64_t n_cells, rfcmp_mesh* out);
+/* N = RWG count (= edges), V, C, genus g = (2 - V + N - C)/2. */
+rfcmp_status rfcmp_mesh_sizes(rfcmp_mesh m, int64_t* N, int64_t* V, int64_t* C, int32_t* genus);
+/* Host outputs, each nullable: edge_vtx int32 [N][2] (min, max vertex),
+ * edge_cell int32 [N][2] (c+, c-), edge_local int32 [N][2] (local index of
+ * the edge in c+ and in c-; local edge i of a cell is opposite its vertex i). */
+rfcmp_status rfcmp_mesh_edges(rfcmp_mesh m, int32_t* edge_vtx, int32_t* edge_cell, int32_t* edge_local);
+/* Near pairs (c <= c') of the quadrature spec for the given factor: centroid
+ * distance below near_factor * max(longest edge of c, of c') * (1 + 1e-9).
+ * Writes *count; if pairs != NULL it must hold 2*count int32 (first call
+ * with NULL to size it). */
+rfcmp_status rfcmp_mesh_near_pairs(rfcmp_mesh m, double near_factor, int64_t* count, int32_t* pairs);
+void rfcmp_mesh_destroy(rfcmp_mesh m);
+
+/* -------------------------------------------------------------- options */
+typedef struct {
+  double near_factor;     /* near-pair criterion factor, default 2.0 */
+  int32_t outer_star;     /* 0 = P_Sigma (Sec. 4, default), 1 = Gram-weighted P_gSigma (Sec. 3) */
+  int32_t scaling;        /* 0 = alpha/beta/gamma by power iteration (Sec. 4, default),
+                             1 = alpha = sqrt(k), beta = 1/sqrt(k), gamma = k */
+  int32_t power_iters;    /* power-iteration steps, default 30 */
+  int32_t precision;      /* 0 = complex64 operator, FP64 accumulation (default);
+                             1 = BF16x3 split products on MFMA for batched solves,
+                                 FP64-accumulated residual refinement */
+} rfcmp_options;
+rfcmp_status rfcmp_options_default(rfcmp_options* opt);
+
+/* ----------------------------------------------------------- operators */
+typedef struct rfcmp_op_s* rfcmp_op;
+
+/* Assemble the EFIE blocks for wavenumber k > 0 [rad/m] (Sec. 2):
+ *   T_A[m,n] = int int f_m(r).f_n(r') G_k dS dS'          (complex64, N x N)
+ *   V[c,c']  = (A_c A_c')^-1 int_c int_c' G_k dS dS'     (complex64, C x C)
+ * with G_k = exp(ikR)/(4 pi R), so T_Phi = Sigma V Sigma^T.  Far pairs use the
+ * 7x7-point rule in FP32; near pairs (see rfcmp_mesh_near_pairs) extract the
+ * 1/R singularity in closed form in FP64.  On the first call for a mesh the
+ * projector matrices (L^+ = (Sigma^T Sigma)^+, G_ll^-1, and for outer_star = 1
+ * G_tp^-1) are built on the device in FP64 and cached on the mesh.
+ * power_start: device c128 [N], the start vector of the power iterations
+ * that estimate alpha, beta, gamma (Sec. 4); required when opt->scaling == 0,
+ * ignored otherwise.  opt may be NULL (defaults).  The mesh must outlive the
+ * operator. */
+rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt,
+                             const void* power_start, void* stream, rfcmp_op* out);
+/* Current scalings (Sec. 4).  lam (nullable, host double [3]) receives the
+ * three power-iteration norm estimates (0 for k-scaling). */
+rfcmp_status rfcmp_op_scalings(rfcmp_op op, double* alpha, double* beta, double* gamma, double* lam);
+/* Override the scalings (all > 0).  The solution j does not depend on them. */
+rfcmp_status rfcmp_op_set_scalings(rfcmp_op op, double alpha, double beta, double gamma);
+/* Copy the blocks to caller device buffers: TA c64 [N][N], V c64 [C][C]
+ * (either nullable). */
+rfcmp_status rfcmp_op_export(rfcmp_op op, void* TA, void* V, void* stream);
+void rfcmp_op_destroy(rfcmp_op op);
+
+/* Plane-wave excitation e_m = int f_m . pol exp(i k khat.r) dS (Sec. 2),
+ * 7-point rule, FP64.  khat, pol: host double [nrhs][3], unit (1e-12) and
+ * orthogonal (1e-12).  e: device c128 [nrhs][N]. */
+rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* pol,
+                                 int32_t nrhs, void* e, void* stream);
+
+/* b = -P_o^H T^H P_m e (right side of eq. NewFormulation).  e, b: device c128
+ * [nrhs][N]; may not alias. */
+rfcmp_status rfcmp_precond_rhs(rfcmp_op op, const void* e, void* b, int32_t nrhs, void* stream);
+/* y = A x with A = P_o^H T^H P_m T P_o, in cancellation-free order (the
+ * products P_LH T_Phi, T_Phi P_LH, Lambda^T T_Phi and Sigma^T P_mL vanish
+ * identically and are never formed).  x, y: device c128 [nrhs][N]. */
+rfcmp_status rfcmp_apply(rfcmp_op op, const void* x, void* y, int32_t nrhs, void* stream);
+/* j = P_o i = P_LH i/alpha + i P_s i/beta.  device c128 [nrhs][N]. */
+rfcmp_status rfcmp_recover(rfcmp_op op, const void* i, void* j, int32_t nrhs, void* stream);
+
+/* Projector primitives (Sec. 2 and Sec. 3), FP64, device c128 vectors:
+ *   RFCMP_PROJ_SIGMA     y = P_Sigma x = Sigma L^+ Sigma^T x        N -> N
+ *   RFCMP_PROJ_LH        y = P_LH x = x - P_Sigma x                 N -> N
+ *   RFCMP_PROJ_GSIGMA    y = P_gSigma x = Sigma L^+ G_tp^-1 Sigma^T x   N -> N
+ *   RFCMP_PROJ_LPINV     y = L^+ x                                  C -> C
+ *   RFCMP_PROJ_GLL_INV   y = G_ll^-1 x                              V -> V
+ *   RFCMP_PROJ_SIGMA_T   y = Sigma^T x                              N -> C
+ *   RFCMP_PROJ_LAMBDA_T  y = Lambda^T x                             N -> V */
+enum {
+  RFCMP_PROJ_SIGMA = 0, RFCMP_PROJ_LH = 1, RFCMP_PROJ_GSIGMA = 2, RFCMP_PROJ_LPINV = 3,
+  RFCMP_PROJ_GLL_INV = 4, RFCMP_PROJ_SIGMA_T = 5, RFCMP_PROJ_LAMBDA_T = 6
+};
+rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* x, void* y, int32_t nrhs, void* stream);
+
+/* Dense block product (Sec. 3.4 adjoint: T^H x = conj(T conj x)):
+ *   which 0: y = M x with M = T_A (n = N);  which 1: M = V (n = C)
+ *   conj != 0: y = conj(M) x.
+ * Complex64 storage, FP64 accumulation.  x, y: device c128 [nrhs][n]. */
+rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* x, void* y,
+                          int32_t nrhs, void* stream);
+
+/* Per-right-hand-side solve report. */
+typedef struct {
+  int32_t iters;          /* CG iterations (all restarts) */
+  int32_t restarts;       /* residual refinements after the first CG pass */
+  double rel_residual;    /* final |b - A i|/|b|, FP64-accumulated */
+  double ms_solve;        /* wall time of the solve (all right-hand sides) */
+} rfcmp_info;
+
+/* Solve T j = -e through the RF-CMP system with CG (Sec. 3.4; x0 = 0), until
+ * the true relative residual |b - A i|/|b| <= tol (b = preconditioned rhs).
+ * e, j: device c128 [nrhs][N].  info: host [nrhs], nullable.  Returns
+ * RFCMP_W_NOT_CONVERGED (best iterate in j) when maxit is reached,
+ * RFCMP_E_BREAKDOWN on a non-positive curvature. */
+rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol,
+                         int32_t maxit, void* stream, rfcmp_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFCMP_H */

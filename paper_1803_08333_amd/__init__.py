@@ -1,0 +1,265 @@
+"""Python binding of librfcmp (RF-CMP EFIE solver on MI355X / gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are torch tensors on the current CUDA (HIP) device
+and work is enqueued on torch's current stream.  The functions keep the C
+names of include/rfcmp.h; ``Mesh`` and ``Operator`` wrap the handles.
+
+The library must be built first (``python -m paper_1803_08333_amd.build``);
+importing this module without it raises, there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "LIB_PATH", "RfcmpError", "Options", "Info", "Mesh", "Operator", "lib",
+    "PROJ_SIGMA", "PROJ_LH", "PROJ_GSIGMA", "PROJ_LPINV", "PROJ_GLL_INV", "PROJ_SIGMA_T", "PROJ_LAMBDA_T",
+    "EXPORTED",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfcmp.so")
+
+PROJ_SIGMA, PROJ_LH, PROJ_GSIGMA, PROJ_LPINV, PROJ_GLL_INV, PROJ_SIGMA_T, PROJ_LAMBDA_T = range(7)
+
+_STATUS = {
+    0: "OK", 1: "W_NOT_CONVERGED", -1: "E_ARG", -2: "E_MESH_OPEN", -3: "E_MESH_NONMANIFOLD",
+    -4: "E_MESH_ORIENT", -5: "E_MESH_DISCONNECTED", -6: "E_MESH_DEGENERATE", -7: "E_OOM",
+    -8: "E_HIP", -9: "E_BREAKDOWN", -10: "E_STATE",
+}
+
+
+class RfcmpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rfcmp {_STATUS.get(status, status)} ({status}): {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("near_factor", ctypes.c_double), ("outer_star", ctypes.c_int32),
+                ("scaling", ctypes.c_int32), ("power_iters", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("ms_solve", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PD = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes)
+EXPORTED = {
+    "rfcmp_last_error": (ctypes.c_char_p, []),
+    "rfcmp_version": (ctypes.c_char_p, []),
+    "rfcmp_mesh_create": (_I32, [_PD, _I64, _PI32, _I64, ctypes.POINTER(_P)]),
+    "rfcmp_mesh_sizes": (_I32, [_P, _PI64, _PI64, _PI64, _PI32]),
+    "rfcmp_mesh_edges": (_I32, [_P, _PI32, _PI32, _PI32]),
+    "rfcmp_mesh_near_pairs": (_I32, [_P, _D, _PI64, _PI32]),
+    "rfcmp_mesh_destroy": (None, [_P]),
+    "rfcmp_options_default": (_I32, [ctypes.POINTER(Options)]),
+    "rfcmp_op_create": (_I32, [_P, _D, ctypes.POINTER(Options), _P, _P, ctypes.POINTER(_P)]),
+    "rfcmp_op_scalings": (_I32, [_P, _PD, _PD, _PD, _PD]),
+    "rfcmp_op_set_scalings": (_I32, [_P, _D, _D, _D]),
+    "rfcmp_op_export": (_I32, [_P, _P, _P, _P]),
+    "rfcmp_op_destroy": (None, [_P]),
+    "rfcmp_rhs_planewave": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
+    "rfcmp_precond_rhs": (_I32, [_P, _P, _P, _I32, _P]),
+    "rfcmp_apply": (_I32, [_P, _P, _P, _I32, _P]),
+    "rfcmp_recover": (_I32, [_P, _P, _P, _I32, _P]),
+    "rfcmp_project": (_I32, [_P, _I32, _P, _P, _I32, _P]),
+    "rfcmp_matvec": (_I32, [_P, _I32, _I32, _P, _P, _I32, _P]),
+    "rfcmp_solve": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, ctypes.POINTER(Info)]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1803_08333_amd.build`")
+    h = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in EXPORTED.items():
+        fn = getattr(h, name)
+        fn.restype = res
+        fn.argtypes = args
+    return h
+
+
+lib = _load()
+
+
+def _check(status):
+    if status < 0:
+        raise RfcmpError(status, lib.rfcmp_last_error().decode())
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, dtype=None, numel=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def options(**kw):
+    o = Options()
+    _check(lib.rfcmp_options_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Mesh:
+    """rfcmp_mesh_create: topology of a closed triangle mesh (host work)."""
+
+    def __init__(self, xyz, tri):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        h = _P()
+        _check(lib.rfcmp_mesh_create(xyz.ctypes.data_as(_PD), len(xyz), tri.ctypes.data_as(_PI32), len(tri),
+                                     ctypes.byref(h)))
+        self.handle = h
+        N, V, C, g = _I64(), _I64(), _I64(), _I32()
+        _check(lib.rfcmp_mesh_sizes(h, ctypes.byref(N), ctypes.byref(V), ctypes.byref(C), ctypes.byref(g)))
+        self.N, self.V, self.C, self.genus = N.value, V.value, C.value, g.value
+
+    def edges(self):
+        """(edge_vtx, edge_cell, edge_local), each int32 [N, 2]."""
+        out = [np.zeros((self.N, 2), dtype=np.int32) for _ in range(3)]
+        _check(lib.rfcmp_mesh_edges(self.handle, *[a.ctypes.data_as(_PI32) for a in out]))
+        return tuple(out)
+
+    def near_pairs(self, near_factor=2.0):
+        cnt = _I64()
+        _check(lib.rfcmp_mesh_near_pairs(self.handle, near_factor, ctypes.byref(cnt), None))
+        p = np.zeros((cnt.value, 2), dtype=np.int32)
+        _check(lib.rfcmp_mesh_near_pairs(self.handle, near_factor, ctypes.byref(cnt), p.ctypes.data_as(_PI32)))
+        return p
+
+    def close(self):
+        if self.handle:
+            lib.rfcmp_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """rfcmp_op_create: assembled T_A, V and scalings for one wavenumber."""
+
+    def __init__(self, mesh, k, power_start=None, **opts):
+        torch = _torch()
+        self.mesh = mesh
+        self.k = float(k)
+        self.opts = options(**opts)
+        ps = None
+        if power_start is not None:
+            ps = _dptr(power_start, torch.complex128, mesh.N)
+        h = _P()
+        _check(lib.rfcmp_op_create(mesh.handle, self.k, ctypes.byref(self.opts), ps, _stream(), ctypes.byref(h)))
+        self.handle = h
+
+    def scalings(self):
+        a, b, g = _D(), _D(), _D()
+        lam = (_D * 3)()
+        _check(lib.rfcmp_op_scalings(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(g), lam))
+        return a.value, b.value, g.value, tuple(lam)
+
+    def set_scalings(self, alpha, beta, gamma):
+        _check(lib.rfcmp_op_set_scalings(self.handle, alpha, beta, gamma))
+
+    def export(self):
+        torch = _torch()
+        N, C = self.mesh.N, self.mesh.C
+        TA = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+        V = torch.empty((C, C), dtype=torch.complex64, device="cuda")
+        _check(lib.rfcmp_op_export(self.handle, _dptr(TA), _dptr(V), _stream()))
+        return TA, V
+
+    def rhs_planewave(self, khat, pol):
+        torch = _torch()
+        khat = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        pol = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.float64)
+        e = torch.empty((len(khat), self.mesh.N), dtype=torch.complex128, device="cuda")
+        _check(lib.rfcmp_rhs_planewave(self.handle, khat.ctypes.data_as(_PD), pol.ctypes.data_as(_PD), len(khat),
+                                       _dptr(e), _stream()))
+        return e
+
+    def _unary(self, fn, x, nout=None, *pre):
+        torch = _torch()
+        x = x.contiguous()
+        nr = x.shape[0] if x.dim() == 2 else 1
+        n_in = x.shape[-1]
+        y = torch.empty((nr, nout or n_in) if x.dim() == 2 else (nout or n_in,), dtype=torch.complex128,
+                        device=x.device)
+        _check(fn(self.handle, *pre, _dptr(x, torch.complex128), _dptr(y), nr, _stream()))
+        return y
+
+    def precond_rhs(self, e):
+        return self._unary(lib.rfcmp_precond_rhs, e)
+
+    def apply(self, x):
+        return self._unary(lib.rfcmp_apply, x)
+
+    def recover(self, i):
+        return self._unary(lib.rfcmp_recover, i)
+
+    def project(self, which, x):
+        m = self.mesh
+        nout = {PROJ_SIGMA: m.N, PROJ_LH: m.N, PROJ_GSIGMA: m.N, PROJ_LPINV: m.C, PROJ_GLL_INV: m.V,
+                PROJ_SIGMA_T: m.C, PROJ_LAMBDA_T: m.V}[which]
+        return self._unary(lib.rfcmp_project, x, nout, ctypes.c_int32(which))
+
+    def matvec(self, which, x, conj=False):
+        return self._unary(lib.rfcmp_matvec, x, None, ctypes.c_int32(which), ctypes.c_int32(int(conj)))
+
+    def solve(self, e, tol=1e-6, maxit=1000):
+        """Returns (j, status, [info dict per rhs])."""
+        torch = _torch()
+        e = e.contiguous()
+        nr = e.shape[0] if e.dim() == 2 else 1
+        j = torch.empty_like(e)
+        info = (Info * nr)()
+        st = _check(lib.rfcmp_solve(self.handle, _dptr(e, torch.complex128), _dptr(j), nr, tol, maxit, _stream(),
+                                    info))
+        return j, st, [i.as_dict() for i in info]
+
+    def close(self):
+        if self.handle:
+            lib.rfcmp_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

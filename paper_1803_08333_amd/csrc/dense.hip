@@ -1,0 +1,461 @@
+// Dense kernels: streaming matrix-vector products and the FP64 inverse used
+// to build the projector matrices.
+//
+// The RF-CMP iteration streams two complex64 blocks (T_A, V) and the dense
+// FP64 projector matrices (L^+ = (Sigma^T Sigma)^+, G_ll^-1) once per use:
+// every product here is HBM-bound (about one flop per byte), so the kernels
+// are built around wide coalesced row loads and FP64 accumulation, which
+// costs nothing at this arithmetic intensity.
+#include <cmath>
+#include <map>
+
+#include "internal.h"
+
+namespace rfcmp {
+
+namespace {
+
+constexpr int kWave = 64;
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+constexpr int kRowsPerWave = 2;
+constexpr int kRowsPerBlock = 4 * kRowsPerWave;  // 256 threads = 4 waves
+constexpr int kChunk = 512;                      // columns staged per pass
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// y[r][row] = sum_j M[row][j] x[r][j];  M complex64 rows padded to ld (a
+// multiple of 64 entries, padding zero); x, y complex128.  Each wave owns
+// kRowsPerWave rows and reads them as float4 (two entries) per lane.
+template <int NR, bool CONJ>
+__global__ __launch_bounds__(256) void k_cmatvec(const float2* __restrict__ M, int n, long ld,
+                                                 const double2* __restrict__ x,
+                                                 double2* __restrict__ y) {
+  __shared__ double2 xs[NR][kChunk];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int row0 = blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
+  double accr[kRowsPerWave][NR], acci[kRowsPerWave][NR];
+#pragma unroll
+  for (int i = 0; i < kRowsPerWave; ++i)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) accr[i][r] = acci[i][r] = 0.0;
+
+  for (int j0 = 0; j0 < n; j0 += kChunk) {
+    for (int t = threadIdx.x; t < NR * kChunk; t += 256) {
+      const int r = t / kChunk, j = t % kChunk;
+      xs[r][j] = (j0 + j < n) ? x[(long)r * n + j0 + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRowsPerWave; ++i) {
+      const int row = row0 + i;
+      if (row >= n) break;
+      const vf4* mr = reinterpret_cast<const vf4*>(M + (long)row * ld + j0);
+#pragma unroll
+      for (int t = 0; t < kChunk / (2 * kWave); ++t) {
+        const int jj = 2 * lane + 2 * kWave * t;
+        if (j0 + jj < n) {
+          const vf4 m = __builtin_nontemporal_load(mr + lane + kWave * t);
+          const double a0 = m.x, b0 = CONJ ? -(double)m.y : (double)m.y;
+          const double a1 = m.z, b1 = CONJ ? -(double)m.w : (double)m.w;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double2 x0 = xs[r][jj], x1 = xs[r][jj + 1];
+            accr[i][r] += a0 * x0.x - b0 * x0.y + a1 * x1.x - b1 * x1.y;
+            acci[i][r] += a0 * x0.y + b0 * x0.x + a1 * x1.y + b1 * x1.x;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < kRowsPerWave; ++i) {
+    const int row = row0 + i;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double sr = wave_sum(accr[i][r]);
+      const double si = wave_sum(acci[i][r]);
+      if (lane == 0 && row < n) y[(long)r * n + row] = make_double2(sr, si);
+    }
+  }
+}
+
+// y[r][row] = sum_j M[row][j] x[r][j];  M real FP64 [n][ld] (ld a multiple of
+// 64, padding zero); x, y complex128.
+template <int NR>
+__global__ __launch_bounds__(256) void k_dmatvec(const double* __restrict__ M, int n, long ld,
+                                                 const double2* __restrict__ x,
+                                                 double2* __restrict__ y) {
+  __shared__ double2 xs[NR][kChunk];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int row0 = blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
+  double accr[kRowsPerWave][NR], acci[kRowsPerWave][NR];
+#pragma unroll
+  for (int i = 0; i < kRowsPerWave; ++i)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) accr[i][r] = acci[i][r] = 0.0;
+
+  for (int j0 = 0; j0 < n; j0 += kChunk) {
+    for (int t = threadIdx.x; t < NR * kChunk; t += 256) {
+      const int r = t / kChunk, j = t % kChunk;
+      xs[r][j] = (j0 + j < n) ? x[(long)r * n + j0 + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRowsPerWave; ++i) {
+      const int row = row0 + i;
+      if (row >= n) break;
+      const vd2* mr = reinterpret_cast<const vd2*>(M + (long)row * ld + j0);
+#pragma unroll
+      for (int t = 0; t < kChunk / (2 * kWave); ++t) {
+        const int jj = 2 * lane + 2 * kWave * t;
+        if (j0 + jj < n) {
+          const vd2 m = __builtin_nontemporal_load(mr + lane + kWave * t);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double2 x0 = xs[r][jj], x1 = xs[r][jj + 1];
+            accr[i][r] += m.x * x0.x + m.y * x1.x;
+            acci[i][r] += m.x * x0.y + m.y * x1.y;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < kRowsPerWave; ++i) {
+    const int row = row0 + i;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double sr = wave_sum(accr[i][r]);
+      const double si = wave_sum(acci[i][r]);
+      if (lane == 0 && row < n) y[(long)r * n + row] = make_double2(sr, si);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// Blocked Gauss-Jordan inverse of an SPD matrix (no pivoting: every Schur
+// complement of an SPD matrix is SPD).  Pivot block P (64 x 64):
+//   D = A_PP^-1,  A_PO <- D A_PO,  A_OP <- -A_OP D,  A_OO <- A_OO - A_OP_old D A_PO_old,
+//   A_PP <- D.
+// After all pivot blocks the matrix holds A^-1 (the sweep operator).
+constexpr int kB = 64;
+
+// In-LDS unblocked sweep of the 64 x 64 pivot block.
+__global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld, int K) {
+  __shared__ double a[kB][kB + 1];
+  const long base = (long)K * kB;
+  for (int t = threadIdx.x; t < kB * kB; t += 256) {
+    const int i = t / kB, j = t % kB;
+    a[i][j] = A[(base + i) * ld + base + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < kB; ++k) {
+    const double d = 1.0 / a[k][k];
+    double upd[kB * kB / 256];
+    int cnt = 0;
+    for (int t = threadIdx.x; t < kB * kB; t += 256, ++cnt) {
+      const int i = t / kB, j = t % kB;
+      upd[cnt] = (i != k && j != k) ? a[i][j] - a[i][k] * a[k][j] * d : 0.0;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int t = threadIdx.x; t < kB * kB; t += 256, ++cnt) {
+      const int i = t / kB, j = t % kB;
+      if (i != k && j != k) a[i][j] = upd[cnt];
+    }
+    __syncthreads();
+    if (threadIdx.x < kB) {
+      const int j = threadIdx.x;
+      if (j != k) {
+        a[k][j] *= d;   // row k
+        a[j][k] *= -d;  // column k
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a[k][k] = d;
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < kB * kB; t += 256) {
+    const int i = t / kB, j = t % kB;
+    A[(base + i) * ld + base + j] = a[i][j];
+  }
+}
+
+// Column panel: Ccol = A_OP (old), A_OP <- -A_OP D.  Row panel: A_PO <- D A_PO.
+// blockIdx.x = block index b (skip b == K); blockIdx.y = 0 column panel, 1 row panel.
+// The old panel block is staged in LDS (the product overwrites it in place);
+// D = A_PP is read from global memory (this kernel does not modify it).
+__global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long ld, int K,
+                                                   double* __restrict__ Ccol) {
+  const int b = blockIdx.x;
+  if (b == K) return;
+  __shared__ double S[kB][kB + 1];
+  const long pb = (long)K * kB, ob = (long)b * kB;
+  const bool col = blockIdx.y == 0;
+  for (int t = threadIdx.x; t < kB * kB; t += 256) {
+    const int i = t / kB, j = t % kB;
+    if (col) {
+      const double v = A[(ob + i) * ld + pb + j];  // row ob+i, pivot column j
+      S[i][j] = v;
+      Ccol[(ob + i) * kB + j] = v;
+    } else {
+      S[i][j] = A[(pb + i) * ld + ob + j];  // pivot row i, column ob+j
+    }
+  }
+  __syncthreads();
+  const double* D = A + pb * ld + pb;
+  for (int t = threadIdx.x; t < kB * kB; t += 256) {
+    const int i = t / kB, j = t % kB;
+    double s = 0.0;
+    if (col) {
+      for (int q = 0; q < kB; ++q) s += S[i][q] * D[q * ld + j];
+      A[(ob + i) * ld + pb + j] = -s;
+    } else {
+      for (int q = 0; q < kB; ++q) s += D[i * ld + q] * S[q][j];
+      A[(pb + i) * ld + ob + j] = s;
+    }
+  }
+}
+
+// A_IJ -= Ccol_I R_J for I, J != K, with R = the updated pivot row panel.
+// 64 x 64 output tile per block, 4 x 4 per thread, k-chunks of 32 in LDS.
+__global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long ld, int K,
+                                                   const double* __restrict__ Ccol) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I == K || J == K) return;
+  constexpr int KC = 32;
+  __shared__ double a[kB][KC + 1];
+  __shared__ double r[KC][kB + 1];
+  const long ib = (long)I * kB, jb = (long)J * kB, pb = (long)K * kB;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < kB; k0 += KC) {
+    for (int t = threadIdx.x; t < kB * KC; t += 256) {
+      const int i = t / KC, q = t % KC;
+      a[i][q] = Ccol[(ib + i) * kB + k0 + q];
+    }
+    for (int t = threadIdx.x; t < KC * kB; t += 256) {
+      const int q = t / kB, j = t % kB;
+      r[q][j] = A[(pb + k0 + q) * ld + jb + j];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int q = 0; q < KC; ++q) {
+      double av[4], rv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = a[ty * 4 + u][q];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rv[u] = r[q][tx + 16 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * rv[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) A[(ib + ty * 4 + u) * ld + jb + tx + 16 * v] -= acc[u][v];
+}
+
+// Dense fills from a coordinate list of unique entries.
+__global__ void k_fill(double* __restrict__ A, long ld, long nvalid, double inner, long total) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const long i = t / ld, j = t % ld;
+  A[t] = (i < nvalid && j < nvalid) ? inner : (i == j ? 1.0 : 0.0);
+}
+__global__ void k_scatter_add(double* __restrict__ A, long ld, const int* __restrict__ ij,
+                              const double* __restrict__ v, long nnz) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nnz) return;
+  A[(long)ij[2 * t] * ld + ij[2 * t + 1]] += v[t];
+}
+__global__ void k_sub_const(double* __restrict__ A, long ld, long nvalid, double c) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nvalid * nvalid) return;
+  const long i = t / nvalid, j = t % nvalid;
+  A[i * ld + j] -= c;
+}
+
+inline unsigned blocks_for(long n, int per) { return unsigned((n + per - 1) / per); }
+
+}  // namespace
+
+rfcmp_status cmatvec(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y,
+                     int nrhs, hipStream_t s) {
+  for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    const int nr = std::min(4, nrhs - r0);
+    const double2* xr = x + (long)r0 * n;
+    double2* yr = y + (long)r0 * n;
+    dim3 grid(blocks_for(n, kRowsPerBlock));
+#define RF_CMV(NRV)                                                                              \
+  if (conj)                                                                                     \
+    hipLaunchKernelGGL((k_cmatvec<NRV, true>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_cmatvec<NRV, false>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr);
+    switch (nr) {
+      case 1: RF_CMV(1) break;
+      case 2: RF_CMV(2) break;
+      case 3: RF_CMV(3) break;
+      default: RF_CMV(4) break;
+    }
+#undef RF_CMV
+  }
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+
+rfcmp_status dmatvec(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
+                     hipStream_t s) {
+  for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    const int nr = std::min(4, nrhs - r0);
+    const double2* xr = x + (long)r0 * n;
+    double2* yr = y + (long)r0 * n;
+    dim3 grid(blocks_for(n, kRowsPerBlock));
+    switch (nr) {
+      case 1: hipLaunchKernelGGL((k_dmatvec<1>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); break;
+      case 2: hipLaunchKernelGGL((k_dmatvec<2>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); break;
+      case 3: hipLaunchKernelGGL((k_dmatvec<3>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); break;
+      default: hipLaunchKernelGGL((k_dmatvec<4>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); break;
+    }
+  }
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+
+rfcmp_status spd_inverse(double* A, int64_t n, hipStream_t s) {
+  if (n % kB != 0) {
+    set_error("spd_inverse: n=%lld not a multiple of %d", (long long)n, kB);
+    return RFCMP_E_ARG;
+  }
+  const int nb = int(n / kB);
+  DevBuf ccol;
+  RF_TRY(ccol.alloc(sizeof(double) * n * kB));
+  for (int K = 0; K < nb; ++K) {
+    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, A, (long)n, K);
+    if (nb > 1) {
+      hipLaunchKernelGGL(k_gj_panels, dim3(nb, 2), dim3(256), 0, s, A, (long)n, K, ccol.as<double>());
+      hipLaunchKernelGGL(k_gj_update, dim3(nb, nb), dim3(256), 0, s, A, (long)n, K, ccol.as<double>());
+    }
+  }
+  RF_HIP(hipGetLastError());
+  // the scratch panel is released when ccol goes out of scope: wait first
+  RF_HIP(hipStreamSynchronize(s));
+  return RFCMP_OK;
+}
+
+// Build L^+, G_ll^-1 (and G_tp^-1) of a mesh on the device, in FP64.
+//   L = Sigma^T Sigma: 3 on the diagonal, -1 for cells sharing an edge;
+//   L^+ = (L + 1 1^T/C)^-1 - 1 1^T/C (identity of Sec. 3.2).
+//   G_ll (P1 mass): A/6 on the diagonal, A/12 off it, per cell.
+//   G_tp: closed form of Sec. 3 (mixed dual-hat / cell Gram matrix).
+rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
+  const MeshHost& h = m->h;
+  MeshDev& d = m->d;
+  const int64_t C = h.C, V = h.V, N = h.N;
+
+  auto build = [&](DevBuf& buf, int64_t nvalid, int64_t& ld, double inner,
+                   const std::vector<int>& ij, const std::vector<double>& val,
+                   bool sub_inner_after) -> rfcmp_status {
+    ld = (int64_t)round_up(nvalid, kB);
+    RF_TRY(buf.alloc(sizeof(double) * ld * ld));
+    const long total = ld * ld;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(total, 256)), dim3(256), 0, s, buf.as<double>(), (long)ld,
+                       (long)nvalid, inner, total);
+    DevBuf dij, dv;
+    RF_TRY(dij.alloc(sizeof(int) * ij.size()));
+    RF_TRY(dv.alloc(sizeof(double) * val.size()));
+    RF_HIP(hipMemcpyAsync(dij.p, ij.data(), sizeof(int) * ij.size(), hipMemcpyHostToDevice, s));
+    RF_HIP(hipMemcpyAsync(dv.p, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_scatter_add, dim3(blocks_for((long)val.size(), 256)), dim3(256), 0, s,
+                       buf.as<double>(), (long)ld, dij.as<int>(), dv.as<double>(), (long)val.size());
+    RF_HIP(hipGetLastError());
+    RF_TRY(spd_inverse(buf.as<double>(), ld, s));  // synchronises before dij/dv are freed
+    if (sub_inner_after) {
+      hipLaunchKernelGGL(k_sub_const, dim3(blocks_for(nvalid * nvalid, 256)), dim3(256), 0, s,
+                         buf.as<double>(), (long)ld, (long)nvalid, inner);
+      RF_HIP(hipGetLastError());
+    }
+    return RFCMP_OK;
+  };
+
+  // L + J
+  {
+    std::vector<int> ij;
+    std::vector<double> v;
+    ij.reserve(2 * (C + 2 * N));
+    for (int64_t c = 0; c < C; ++c) {
+      ij.push_back(int(c));
+      ij.push_back(int(c));
+      v.push_back(3.0);
+    }
+    for (int64_t n = 0; n < N; ++n) {
+      const int a = h.edge_cell[2 * n], b = h.edge_cell[2 * n + 1];
+      ij.push_back(a); ij.push_back(b); v.push_back(-1.0);
+      ij.push_back(b); ij.push_back(a); v.push_back(-1.0);
+    }
+    RF_TRY(build(d.Lp, C, d.ldL, 1.0 / double(C), ij, v, true));
+  }
+  // G_ll
+  {
+    std::map<std::pair<int, int>, double> acc;
+    for (int64_t c = 0; c < C; ++c)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          const int a = h.tri[3 * c + i], b = h.tri[3 * c + j];
+          acc[{a, b}] += (i == j) ? h.area[c] / 6.0 : h.area[c] / 12.0;
+        }
+    std::vector<int> ij;
+    std::vector<double> v;
+    for (auto& kv : acc) {
+      ij.push_back(kv.first.first);
+      ij.push_back(kv.first.second);
+      v.push_back(kv.second);
+    }
+    RF_TRY(build(d.Gll_inv, V, d.ldG, 0.0, ij, v, false));
+  }
+  if (need_gtp) {
+    std::vector<int> ij;
+    std::vector<double> v;
+    for (int64_t m2 = 0; m2 < C; ++m2) {
+      const int* tm = &h.tri[3 * m2];
+      for (int q = h.cell_nb_ptr[m2]; q < h.cell_nb_ptr[m2 + 1]; ++q) {
+        const int n2 = h.cell_nb_idx[q];
+        const int* tn = &h.tri[3 * n2];
+        double val;
+        if (n2 == m2) {
+          val = 4.5;
+          for (int i = 0; i < 3; ++i) val += 1.0 / h.noc[tm[i]];
+        } else {
+          int shared[3], ns = 0;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              if (tm[i] == tn[j]) shared[ns++] = tm[i];
+          if (ns == 2)
+            val = 0.5 + 1.0 / h.noc[shared[0]] + 1.0 / h.noc[shared[1]];
+          else
+            val = 1.0 / h.noc[shared[0]];
+        }
+        ij.push_back(int(m2));
+        ij.push_back(n2);
+        v.push_back(val * (2.0 / 18.0));
+      }
+    }
+    RF_TRY(build(d.Gtp_inv, C, d.ldT, 0.0, ij, v, false));
+    d.has_gtp = true;
+  }
+  RF_HIP(hipStreamSynchronize(s));
+  return RFCMP_OK;
+}
+
+}  // namespace rfcmp

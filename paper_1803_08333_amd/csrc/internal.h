@@ -1,0 +1,154 @@
+// Internal declarations of the rfcmp library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/rfcmp.h"
+
+namespace rfcmp {
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define RF_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::rfcmp::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                         __LINE__);                                                    \
+      return e_ == hipErrorOutOfMemory ? RFCMP_E_OOM : RFCMP_E_HIP;                    \
+    }                                                                                  \
+  } while (0)
+
+#define RF_TRY(expr)                       \
+  do {                                     \
+    rfcmp_status s_ = (expr);              \
+    if (s_ < 0) return s_;                 \
+  } while (0)
+
+// Owning device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  rfcmp_status alloc(size_t n) {
+    release();
+    if (n == 0) return RFCMP_OK;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      set_error("hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+      return RFCMP_E_OOM;
+    }
+    bytes = n;
+    return RFCMP_OK;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+inline size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+// Host-side topology and geometry (FP64), built by rfcmp_mesh_create.
+struct MeshHost {
+  int64_t V = 0, C = 0, N = 0;
+  int32_t genus = 0;
+  std::vector<double> xyz;            // [V][3]
+  std::vector<int32_t> tri;           // [C][3]
+  std::vector<int32_t> edge_vtx;      // [N][2] (min, max)
+  std::vector<int32_t> edge_cell;     // [N][2] (c+, c-)
+  std::vector<int32_t> edge_local;    // [N][2] local index in c+, c-
+  std::vector<int32_t> cell_edge;     // [C][3] edge of local edge i
+  std::vector<int8_t> cell_sign;      // [C][3] Sigma[edge, cell]
+  std::vector<double> area;           // [C]
+  std::vector<double> centroid;       // [C][3]
+  std::vector<double> hmax;           // [C] longest edge of each cell
+  std::vector<int32_t> noc;           // [V] cells at each vertex
+  std::vector<int32_t> vtx_edge_ptr;  // [V+1] CSR: edges at each vertex
+  std::vector<int32_t> vtx_edge_idx;  // [2N]
+  std::vector<int8_t> vtx_edge_sgn;   // [2N] Lambda[edge, vertex]
+  std::vector<int32_t> cell_nb_ptr;   // [C+1] CSR: cells sharing a vertex (incl. self)
+  std::vector<int32_t> cell_nb_idx;
+};
+
+// Device copies and the dense FP64 projector matrices of one mesh.
+struct MeshDev {
+  bool ready = false;
+  bool has_gtp = false;
+  int64_t ldL = 0, ldG = 0, ldT = 0;  // padded leading dims of L^+, G_ll^-1, G_tp^-1
+  DevBuf cen;        // double [C][3]
+  DevBuf vtx;        // double [C][9]  cell vertices
+  DevBuf area;       // double [C]
+  DevBuf qoff;       // float4 [C][7]  quadrature points minus centroid
+  DevBuf fvoff;      // float4 [C][3]  vertex i minus centroid
+  DevBuf sgn;        // float  [C][3]
+  DevBuf cell_edge;  // int [C][3]
+  DevBuf edge_cell;  // int [N][2]
+  DevBuf edge_slot;  // int [N][2]  3*c+ + l+, 3*c- + l-
+  DevBuf edge_vtx;   // int [N][2]
+  DevBuf ve_ptr, ve_idx, ve_sgn;  // Lambda^T CSR
+  DevBuf Lp;         // double [ldL][ldL]: (Sigma^T Sigma)^+
+  DevBuf Gll_inv;    // double [ldG][ldG]
+  DevBuf Gtp_inv;    // double [ldT][ldT]
+};
+
+}  // namespace rfcmp
+
+struct rfcmp_mesh_s {
+  rfcmp::MeshHost h;
+  rfcmp::MeshDev d;
+  int device = -1;
+};
+
+struct rfcmp_op_s {
+  rfcmp_mesh mesh = nullptr;
+  double k = 0;
+  rfcmp_options opt{};
+  double alpha = 0, beta = 0, gamma = 0;
+  double lam[3] = {0, 0, 0};
+  int64_t ldA = 0, ldV = 0;  // leading dims (complex entries) of T_A and V
+  rfcmp::DevBuf TA;          // float2 [N][ldA]
+  rfcmp::DevBuf Vb;          // float2 [C][ldV]
+  rfcmp::DevBuf work;        // complex128 workspace
+  int work_nrhs = 0;
+  rfcmp::DevBuf scal;        // device scalars (doubles)
+  double* host_scal = nullptr;  // pinned
+};
+
+namespace rfcmp {
+
+// mesh.cpp
+rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, int64_t nc, MeshHost& h);
+void near_pairs(const MeshHost& h, double factor, std::vector<int32_t>& out);
+
+// assemble.hip
+rfcmp_status mesh_upload(rfcmp_mesh m, hipStream_t s);
+rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s);
+rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, int nrhs,
+                           double2* e, hipStream_t s);
+
+// dense.hip
+rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s);
+// y[r] = M x[r] for r < nrhs; M complex64 [n][ld]; x, y complex128 [nrhs][n]
+rfcmp_status cmatvec(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y,
+                     int nrhs, hipStream_t s);
+// y[r] = M x[r]; M real FP64 [n][ld]; x, y complex128 [nrhs][n]
+rfcmp_status dmatvec(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
+                     hipStream_t s);
+// In-place inverse of an SPD matrix, FP64, n padded to a multiple of 64.
+rfcmp_status spd_inverse(double* A, int64_t n, hipStream_t s);
+
+}  // namespace rfcmp

@@ -1,0 +1,275 @@
+// Host topology of a closed triangle mesh: RWG edges, star/loop incidence,
+// validation and the near-pair list of the quadrature spec.
+//
+// RWG functions (Sec. 2, eq. RWGdef) live on the interior edges; on a closed
+// mesh every edge is one RWG.  Edge order, c+/c- and the signs of Sigma and
+// Lambda follow the convention stated in rfcmp.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace rfcmp {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+static rfcmp_status fail(rfcmp_status s, const char* msg, long long a = -1) {
+  if (a >= 0)
+    set_error("%s (index %lld)", msg, a);
+  else
+    set_error("%s", msg);
+  return s;
+}
+
+rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, int64_t nc,
+                             MeshHost& h) {
+  if (!xyz || !tri || nv < 4 || nc < 4) return fail(RFCMP_E_ARG, "mesh needs >= 4 vertices and cells");
+  if (nc > (int64_t(1) << 30) || nv > (int64_t(1) << 30)) return fail(RFCMP_E_ARG, "mesh too large");
+  for (int64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(xyz[i])) return fail(RFCMP_E_ARG, "non-finite vertex coordinate", i / 3);
+  h = MeshHost{};
+  h.V = nv;
+  h.C = nc;
+  h.xyz.assign(xyz, xyz + 3 * nv);
+  h.tri.assign(tri, tri + 3 * nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int32_t* t = &tri[3 * c];
+    for (int i = 0; i < 3; ++i)
+      if (t[i] < 0 || t[i] >= nv) return fail(RFCMP_E_MESH_NONMANIFOLD, "cell vertex out of range", c);
+    if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2])
+      return fail(RFCMP_E_MESH_NONMANIFOLD, "cell with a repeated vertex", c);
+  }
+
+  // directed half-edges: local edge i of cell c runs from vertex i+1 to i+2
+  struct Half {
+    int64_t key;  // min*nv + max
+    int32_t cell;
+    int8_t local;
+    int8_t forward;  // 1 if walked min -> max
+  };
+  std::vector<Half> he(3 * nc);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int i = 0; i < 3; ++i) {
+      int32_t a = tri[3 * c + (i + 1) % 3], b = tri[3 * c + (i + 2) % 3];
+      int32_t lo = std::min(a, b), hi = std::max(a, b);
+      he[3 * c + i] = Half{int64_t(lo) * nv + hi, int32_t(c), int8_t(i), int8_t(a < b)};
+    }
+  std::sort(he.begin(), he.end(), [](const Half& x, const Half& y) {
+    return x.key < y.key || (x.key == y.key && x.forward > y.forward);
+  });
+  // every undirected edge must appear exactly twice, once per direction
+  std::vector<int64_t> starts;
+  for (size_t i = 0; i < he.size();) {
+    size_t j = i;
+    while (j < he.size() && he[j].key == he[i].key) ++j;
+    if (j - i == 1) return fail(RFCMP_E_MESH_OPEN, "open edge (one cell)", he[i].cell);
+    if (j - i > 2) return fail(RFCMP_E_MESH_NONMANIFOLD, "edge shared by more than two cells", he[i].cell);
+    if (he[i].forward != 1 || he[i + 1].forward != 0)
+      return fail(RFCMP_E_MESH_ORIENT, "two cells walk an edge in the same direction", he[i].cell);
+    starts.push_back(int64_t(i));
+    i = j;
+  }
+  const int64_t N = int64_t(starts.size());
+  h.N = N;
+  h.edge_vtx.resize(2 * N);
+  h.edge_cell.resize(2 * N);
+  h.edge_local.resize(2 * N);
+  h.cell_edge.assign(3 * nc, -1);
+  h.cell_sign.assign(3 * nc, 0);
+  for (int64_t n = 0; n < N; ++n) {
+    const Half& p = he[starts[n]];      // walked min -> max: c+
+    const Half& q = he[starts[n] + 1];  // c-
+    h.edge_vtx[2 * n] = int32_t(p.key / nv);
+    h.edge_vtx[2 * n + 1] = int32_t(p.key % nv);
+    h.edge_cell[2 * n] = p.cell;
+    h.edge_cell[2 * n + 1] = q.cell;
+    h.edge_local[2 * n] = p.local;
+    h.edge_local[2 * n + 1] = q.local;
+    h.cell_edge[3 * p.cell + p.local] = int32_t(n);
+    h.cell_sign[3 * p.cell + p.local] = 1;
+    h.cell_edge[3 * q.cell + q.local] = int32_t(n);
+    h.cell_sign[3 * q.cell + q.local] = -1;
+  }
+
+  // geometry
+  h.area.resize(nc);
+  h.centroid.resize(3 * nc);
+  h.hmax.resize(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const double* P[3] = {&xyz[3 * tri[3 * c]], &xyz[3 * tri[3 * c + 1]], &xyz[3 * tri[3 * c + 2]]};
+    double u[3], v[3], w[3];
+    for (int d = 0; d < 3; ++d) {
+      u[d] = P[1][d] - P[0][d];
+      v[d] = P[2][d] - P[0][d];
+    }
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+    double a2 = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double hm = 0;
+    for (int i = 0; i < 3; ++i) {
+      const double* A = P[(i + 1) % 3];
+      const double* B = P[(i + 2) % 3];
+      double e2 = 0;
+      for (int d = 0; d < 3; ++d) e2 += (B[d] - A[d]) * (B[d] - A[d]);
+      hm = std::max(hm, std::sqrt(e2));
+    }
+    if (!(a2 > 1e-14 * hm * hm)) return fail(RFCMP_E_MESH_DEGENERATE, "zero-area cell", c);
+    h.area[c] = 0.5 * a2;
+    h.hmax[c] = hm;
+    for (int d = 0; d < 3; ++d) h.centroid[3 * c + d] = (P[0][d] + P[1][d] + P[2][d]) / 3.0;
+  }
+
+  // cells at each vertex, fan check (one cycle of cells around every vertex)
+  h.noc.assign(nv, 0);
+  for (int64_t i = 0; i < 3 * nc; ++i) h.noc[tri[i]]++;
+  for (int64_t v = 0; v < nv; ++v)
+    if (h.noc[v] == 0) return fail(RFCMP_E_MESH_DISCONNECTED, "vertex used by no cell", v);
+  std::vector<int32_t> vc_ptr(nv + 1, 0), vc_idx(3 * nc);
+  for (int64_t v = 0; v < nv; ++v) vc_ptr[v + 1] = vc_ptr[v] + h.noc[v];
+  {
+    std::vector<int32_t> fill(vc_ptr.begin(), vc_ptr.end() - 1);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int i = 0; i < 3; ++i) vc_idx[fill[tri[3 * c + i]]++] = int32_t(c);
+  }
+  // around vertex v, cell c with v at local position i: the next cell across
+  // the edge (v, vertex i+1) is the other cell of that edge
+  for (int64_t v = 0; v < nv; ++v) {
+    int32_t c0 = vc_idx[vc_ptr[v]], c = c0;
+    int count = 0;
+    do {
+      int i = 0;
+      while (tri[3 * c + i] != v) ++i;
+      // local edge opposite vertex i+2 joins v and vertex i+1
+      int32_t e = h.cell_edge[3 * c + (i + 2) % 3];
+      c = h.edge_cell[2 * e] == c ? h.edge_cell[2 * e + 1] : h.edge_cell[2 * e];
+      if (++count > h.noc[v]) break;
+    } while (c != c0);
+    if (count != h.noc[v]) return fail(RFCMP_E_MESH_NONMANIFOLD, "vertex with more than one fan", v);
+  }
+
+  // connectivity over edges
+  {
+    std::vector<char> seen(nc, 0);
+    std::vector<int32_t> stack{0};
+    seen[0] = 1;
+    int64_t reached = 1;
+    while (!stack.empty()) {
+      int32_t c = stack.back();
+      stack.pop_back();
+      for (int i = 0; i < 3; ++i) {
+        int32_t e = h.cell_edge[3 * c + i];
+        int32_t o = h.edge_cell[2 * e] == c ? h.edge_cell[2 * e + 1] : h.edge_cell[2 * e];
+        if (!seen[o]) {
+          seen[o] = 1;
+          ++reached;
+          stack.push_back(o);
+        }
+      }
+    }
+    if (reached != nc) return fail(RFCMP_E_MESH_DISCONNECTED, "mesh has more than one component");
+  }
+  const int64_t chi = nv - N + nc;
+  if ((2 - chi) % 2 != 0 || chi > 2) return fail(RFCMP_E_MESH_NONMANIFOLD, "odd Euler characteristic");
+  h.genus = int32_t((2 - chi) / 2);
+
+  // Lambda^T as CSR over vertices: Lambda[n, min] = +1, Lambda[n, max] = -1
+  h.vtx_edge_ptr.assign(nv + 1, 0);
+  for (int64_t n = 0; n < N; ++n) {
+    h.vtx_edge_ptr[h.edge_vtx[2 * n] + 1]++;
+    h.vtx_edge_ptr[h.edge_vtx[2 * n + 1] + 1]++;
+  }
+  for (int64_t v = 0; v < nv; ++v) h.vtx_edge_ptr[v + 1] += h.vtx_edge_ptr[v];
+  h.vtx_edge_idx.resize(2 * N);
+  h.vtx_edge_sgn.resize(2 * N);
+  {
+    std::vector<int32_t> fill(h.vtx_edge_ptr.begin(), h.vtx_edge_ptr.end() - 1);
+    for (int64_t n = 0; n < N; ++n) {
+      int32_t a = h.edge_vtx[2 * n], b = h.edge_vtx[2 * n + 1];
+      h.vtx_edge_idx[fill[a]] = int32_t(n);
+      h.vtx_edge_sgn[fill[a]++] = 1;
+      h.vtx_edge_idx[fill[b]] = int32_t(n);
+      h.vtx_edge_sgn[fill[b]++] = -1;
+    }
+  }
+
+  // cells sharing at least one vertex with each cell (for the mixed Gram matrix)
+  h.cell_nb_ptr.assign(nc + 1, 0);
+  h.cell_nb_idx.clear();
+  std::vector<int32_t> nb;
+  for (int64_t c = 0; c < nc; ++c) {
+    nb.clear();
+    for (int i = 0; i < 3; ++i) {
+      int32_t v = tri[3 * c + i];
+      for (int32_t k = vc_ptr[v]; k < vc_ptr[v + 1]; ++k) nb.push_back(vc_idx[k]);
+    }
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    h.cell_nb_idx.insert(h.cell_nb_idx.end(), nb.begin(), nb.end());
+    h.cell_nb_ptr[c + 1] = int32_t(h.cell_nb_idx.size());
+  }
+  return RFCMP_OK;
+}
+
+// Near pairs c <= c': |x_c - x_c'| < factor * max(h_c, h_c') * (1 + 1e-9),
+// found through a uniform grid of bins of the largest possible threshold.
+void near_pairs(const MeshHost& h, double factor, std::vector<int32_t>& out) {
+  out.clear();
+  const int64_t C = h.C;
+  double hm = 0;
+  for (double x : h.hmax) hm = std::max(hm, x);
+  const double bin = factor * hm * (1.0 + 1e-9);
+  double lo[3] = {1e300, 1e300, 1e300};
+  for (int64_t c = 0; c < C; ++c)
+    for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], h.centroid[3 * c + d]);
+  auto key = [](int64_t x, int64_t y, int64_t z) { return (x * 2097152 + y) * 2097152 + z; };
+  std::unordered_map<int64_t, std::vector<int32_t>> grid;
+  std::vector<int64_t> cb(3 * C);
+  for (int64_t c = 0; c < C; ++c) {
+    for (int d = 0; d < 3; ++d) cb[3 * c + d] = int64_t(std::floor((h.centroid[3 * c + d] - lo[d]) / bin));
+    grid[key(cb[3 * c], cb[3 * c + 1], cb[3 * c + 2])].push_back(int32_t(c));
+  }
+  std::vector<int32_t> cand;
+  for (int64_t c = 0; c < C; ++c) {
+    cand.clear();
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          auto it = grid.find(key(cb[3 * c] + dx, cb[3 * c + 1] + dy, cb[3 * c + 2] + dz));
+          if (it == grid.end()) continue;
+          for (int32_t o : it->second)
+            if (o >= c) cand.push_back(o);
+        }
+    std::sort(cand.begin(), cand.end());
+    for (int32_t o : cand) {
+      double d2 = 0;
+      for (int d = 0; d < 3; ++d) {
+        double t = h.centroid[3 * c + d] - h.centroid[3 * int64_t(o) + d];
+        d2 += t * t;
+      }
+      double thr = factor * std::max(h.hmax[c], h.hmax[o]) * (1.0 + 1e-9);
+      if (std::sqrt(d2) < thr) {
+        out.push_back(int32_t(c));
+        out.push_back(o);
+      }
+    }
+  }
+}
+
+}  // namespace rfcmp

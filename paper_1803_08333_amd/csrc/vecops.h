@@ -1,0 +1,48 @@
+// Launch wrappers of the sparse incidence products and fused vector steps.
+#pragma once
+
+#include "internal.h"
+
+namespace rfcmp {
+
+// t = Sigma^T x  (N -> C)
+rfcmp_status sigma_t(const MeshDev& d, int64_t C, int64_t N, const double2* x, double2* t, int nr, hipStream_t s);
+// g = Lambda^T x  (N -> V)
+rfcmp_status lambda_t(const MeshDev& d, int64_t V, int64_t N, const double2* x, double2* g, int nr, hipStream_t s);
+// out = Lambda h  (V -> N)
+rfcmp_status lambda_n(const MeshDev& d, int64_t N, int64_t V, const double2* h, double2* out, int nr, hipStream_t s);
+// out = ca*x (times i if ca_imag; x nullable) + cs * Sigma z
+rfcmp_status axpy_sigma(const MeshDev& d, int64_t N, int64_t C, double ca, bool ca_imag, const double2* x,
+                        double cs, const double2* z, double2* out, int nr, hipStream_t s);
+// out = i ka (x - Sigma s1) - kb Sigma s1g
+rfcmp_status vin(const MeshDev& d, int64_t N, int64_t C, double ka, double kb, const double2* x,
+                 const double2* s1, const double2* s1g, double2* out, int nr, hipStream_t s);
+// m[r] = mean of x[r] (length n)
+rfcmp_status mean(int64_t n, const double2* x, double2* m, int nr, hipStream_t s);
+// out = [area .*] (fa a + fb (b - mb))   (a, b, area nullable)
+rfcmp_status comb_c(int64_t C, const double* area, double fa, const double2* a, double fb, const double2* b,
+                    const double2* mb, double2* out, int nr, hipStream_t s);
+// w = Lambda h ia2 + (a - Sigma s2) ig + Sigma s3 ib2
+rfcmp_status middle_w(const MeshDev& d, int64_t N, int64_t C, int64_t V, double ia2, double ig, double ib2,
+                      const double2* h, const double2* a, const double2* s2, const double2* s3, double2* w,
+                      int nr, hipStream_t s);
+// y = -i ka (zA - Sigma s4) + Sigma g6
+rfcmp_status left_y(const MeshDev& d, int64_t N, int64_t C, double ka, const double2* zA, const double2* s4,
+                    const double2* g6, double2* y, int nr, hipStream_t s);
+// j = ia (x - Sigma sv) + i ib Sigma sg
+rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double ib, const double2* x,
+                       const double2* sv, const double2* sg, double2* j, int nr, hipStream_t s);
+// out[r] = sum conj(a[r]) b[r]; part needs dot_partials()*nr entries
+rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, double2* out, int nr,
+                 hipStream_t s);
+int dot_partials();
+rfcmp_status normalize(int64_t n, const double2* nrm2, double2* x, int nr, hipStream_t s);
+rfcmp_status cg_xr(int64_t n, const double* sc, int rho_slot, double2* x, double2* r, const double2* p,
+                   const double2* q, hipStream_t s);
+rfcmp_status cg_p(int64_t n, const double* sc, int old_slot, int new_slot, const double2* r, double2* p,
+                  hipStream_t s);
+rfcmp_status take_real(const double2* d, double* sc, int slot, hipStream_t s);
+rfcmp_status vsub(int64_t n, const double2* a, const double2* b, double2* out, hipStream_t s);
+rfcmp_status vadd_to(int64_t n, const double2* a, double2* x, hipStream_t s);
+
+}  // namespace rfcmp

@@ -1,0 +1,374 @@
+// Sparse incidence products and fused vector steps of the RF-CMP operator.
+//
+// Sigma and Lambda have two non-zeros per row (Sec. 2): Sigma^T x and
+// Lambda^T x are short gathers, Sigma z and Lambda h are differences of two
+// entries.  Each fused kernel below evaluates one line of the
+// cancellation-free application on complex128 vectors; nrhs runs in
+// blockIdx.y, vectors are [nrhs][n] contiguous.
+#include "vecops.h"
+
+namespace rfcmp {
+
+namespace {
+
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+// multiply by i*s
+__device__ inline double2 cimul(double s, double2 a) { return make_double2(-s * a.y, s * a.x); }
+
+__global__ void k_sigma_t(int C, int N, const int* __restrict__ cell_edge, const float* __restrict__ sgn,
+                          const double2* __restrict__ x, double2* __restrict__ t) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const long r = blockIdx.y;
+  const double2* xr = x + r * N;
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double2 v = xr[cell_edge[3 * c + i]];
+    const double g = sgn[3 * c + i];
+    s.x += g * v.x;
+    s.y += g * v.y;
+  }
+  t[r * C + c] = s;
+}
+
+__global__ void k_lambda_t(int V, int N, const int* __restrict__ ptr, const int* __restrict__ idx,
+                           const float* __restrict__ sg, const double2* __restrict__ x,
+                           double2* __restrict__ g) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const long r = blockIdx.y;
+  const double2* xr = x + r * N;
+  double2 s = make_double2(0.0, 0.0);
+  for (int q = ptr[v]; q < ptr[v + 1]; ++q) {
+    const double2 e = xr[idx[q]];
+    s.x += sg[q] * e.x;
+    s.y += sg[q] * e.y;
+  }
+  g[r * V + v] = s;
+}
+
+// out[n] = ca*x[n] + cs*(z[c+] - z[c-])  (real ca, complex-by-real cs, with
+// optional multiplication of the first term by i)
+__global__ void k_axpy_sigma(int N, int C, const int* __restrict__ edge_cell, double ca, int ca_imag,
+                             const double2* __restrict__ x, double cs, const double2* __restrict__ z,
+                             double2* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const long r = blockIdx.y;
+  const double2 zd = csub(z[r * C + edge_cell[2 * n]], z[r * C + edge_cell[2 * n + 1]]);
+  double2 a = x ? x[r * N + n] : make_double2(0.0, 0.0);
+  a = ca_imag ? cimul(ca, a) : cscale(ca, a);
+  out[r * N + n] = cadd(a, cscale(cs, zd));
+}
+
+// v_in = (ik/alpha)(x - Sigma s1) - (k/beta) Sigma s1g
+__global__ void k_vin(int N, int C, const int* __restrict__ edge_cell, double ka, double kb,
+                      const double2* __restrict__ x, const double2* __restrict__ s1,
+                      const double2* __restrict__ s1g, double2* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const long r = blockIdx.y;
+  const int cp = edge_cell[2 * n], cm = edge_cell[2 * n + 1];
+  const double2 us = csub(s1[r * C + cp], s1[r * C + cm]);
+  const double2 ug = csub(s1g[r * C + cp], s1g[r * C + cm]);
+  const double2 ul = csub(x[r * N + n], us);
+  out[r * N + n] = csub(cimul(ka, ul), cscale(kb, ug));
+}
+
+// Per-rhs mean of a length-n vector; one block per rhs, fixed-order tree.
+__global__ __launch_bounds__(1024) void k_mean(int n, const double2* __restrict__ x, double2* __restrict__ m) {
+  __shared__ double sr[1024], si[1024];
+  const long r = blockIdx.x;
+  double ar = 0.0, ai = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    ar += x[r * n + i].x;
+    ai += x[r * n + i].y;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) m[r] = make_double2(sr[0] / n, si[0] / n);
+}
+
+// out[c] = fa * a[c] + fb * (b[c] - mean_b) (+ area weighting when area != null:
+// out[c] = A_c * (...)).  b, mean_b nullable.
+__global__ void k_comb_c(int C, const double* __restrict__ area, double fa, const double2* __restrict__ a,
+                         double fb, const double2* __restrict__ b, const double2* __restrict__ mb,
+                         double2* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const long r = blockIdx.y;
+  double2 v = a ? cscale(fa, a[r * C + c]) : make_double2(0.0, 0.0);
+  if (b) v = cadd(v, cscale(fb, csub(b[r * C + c], mb[r])));
+  if (area) v = cscale(area[c], v);
+  out[r * C + c] = v;
+}
+
+// w = Lambda h/alpha^2 + (a - Sigma s2)/gamma + Sigma s3/beta^2
+__global__ void k_middle_w(int N, int C, int V, const int* __restrict__ edge_cell,
+                           const int* __restrict__ edge_vtx, double ia2, double ig, double ib2,
+                           const double2* __restrict__ h, const double2* __restrict__ a,
+                           const double2* __restrict__ s2, const double2* __restrict__ s3,
+                           double2* __restrict__ w) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const long r = blockIdx.y;
+  const int cp = edge_cell[2 * n], cm = edge_cell[2 * n + 1];
+  const double2 lh = csub(h[r * V + edge_vtx[2 * n]], h[r * V + edge_vtx[2 * n + 1]]);
+  const double2 pl = csub(a[r * N + n], csub(s2[r * C + cp], s2[r * C + cm]));
+  const double2 ss = csub(s3[r * C + cp], s3[r * C + cm]);
+  w[r * N + n] = cadd(cadd(cscale(ia2, lh), cscale(ig, pl)), cscale(ib2, ss));
+}
+
+// y = -(ik/alpha)(zA - Sigma s4) + Sigma g6
+__global__ void k_left_y(int N, int C, const int* __restrict__ edge_cell, double ka,
+                         const double2* __restrict__ zA, const double2* __restrict__ s4,
+                         const double2* __restrict__ g6, double2* __restrict__ y) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const long r = blockIdx.y;
+  const int cp = edge_cell[2 * n], cm = edge_cell[2 * n + 1];
+  const double2 pl = csub(zA[r * N + n], csub(s4[r * C + cp], s4[r * C + cm]));
+  y[r * N + n] = cadd(cimul(-ka, pl), csub(g6[r * C + cp], g6[r * C + cm]));
+}
+
+// j = (i - Sigma s)/alpha + i (Sigma sg)/beta
+__global__ void k_recover(int N, int C, const int* __restrict__ edge_cell, double ia, double ib,
+                          const double2* __restrict__ x, const double2* __restrict__ s,
+                          const double2* __restrict__ sg, double2* __restrict__ j) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const long r = blockIdx.y;
+  const int cp = edge_cell[2 * n], cm = edge_cell[2 * n + 1];
+  const double2 ps = csub(s[r * C + cp], s[r * C + cm]);
+  const double2 pg = csub(sg[r * C + cp], sg[r * C + cm]);
+  j[r * N + n] = cadd(cscale(ia, csub(x[r * N + n], ps)), cimul(ib, pg));
+}
+
+// out = Lambda h (n from the vertex differences)
+__global__ void k_lambda(int N, int V, const int* __restrict__ edge_vtx, const double2* __restrict__ h,
+                         double2* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const long r = blockIdx.y;
+  out[r * N + n] = csub(h[r * V + edge_vtx[2 * n]], h[r * V + edge_vtx[2 * n + 1]]);
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int kRedBlocks = 240;
+
+// partial[b][r] = sum_{i in block b} conj(a[r][i]) b[r][i]
+__global__ __launch_bounds__(256) void k_dot_partial(long n, const double2* __restrict__ a,
+                                                     const double2* __restrict__ b,
+                                                     double2* __restrict__ part) {
+  __shared__ double sr[256], si[256];
+  const long r = blockIdx.y;
+  double ar = 0.0, ai = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const double2 x = a[r * n + i], y = b[r * n + i];
+    ar += x.x * y.x + x.y * y.y;
+    ai += x.x * y.y - x.y * y.x;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[r * gridDim.x + blockIdx.x] = make_double2(sr[0], si[0]);
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(int nb, const double2* __restrict__ part,
+                                                   double2* __restrict__ out) {
+  __shared__ double sr[256], si[256];
+  const long r = blockIdx.x;
+  double ar = 0.0, ai = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    ar += part[r * nb + i].x;
+    ai += part[r * nb + i].y;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = make_double2(sr[0], si[0]);
+}
+
+// x[r] *= 1/sqrt(re(nrm2[r]))
+__global__ void k_normalize(long n, const double2* __restrict__ nrm2, double2* __restrict__ x) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long r = blockIdx.y;
+  const double s = 1.0 / sqrt(nrm2[r].x);
+  x[r * n + i] = cscale(s, x[r * n + i]);
+}
+
+// CG: alpha = rho/pq; x += alpha p; r -= alpha q
+__global__ void k_cg_xr(long n, const double* __restrict__ sc, int rho_slot, double2* __restrict__ x,
+                        double2* __restrict__ r, const double2* __restrict__ p,
+                        const double2* __restrict__ q) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double al = sc[rho_slot] / sc[2];
+  x[i] = cadd(x[i], cscale(al, p[i]));
+  r[i] = csub(r[i], cscale(al, q[i]));
+}
+// CG: p = r + (rho_new/rho_old) p
+__global__ void k_cg_p(long n, const double* __restrict__ sc, int old_slot, int new_slot,
+                       const double2* __restrict__ r, double2* __restrict__ p) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double be = sc[new_slot] / sc[old_slot];
+  p[i] = cadd(r[i], cscale(be, p[i]));
+}
+// copy the real part of a complex scalar into a slot
+__global__ void k_take_real(const double2* __restrict__ d, double* __restrict__ sc, int slot) {
+  sc[slot] = d[0].x;
+}
+__global__ void k_sub(long n, const double2* __restrict__ a, const double2* __restrict__ b,
+                      double2* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = csub(a[i], b[i]);
+}
+__global__ void k_add_to(long n, const double2* __restrict__ a, double2* __restrict__ x) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] = cadd(x[i], a[i]);
+}
+
+inline dim3 g1(long n, int nr = 1) { return dim3(unsigned((n + 255) / 256), unsigned(nr)); }
+
+}  // namespace
+
+#define RF_LAUNCH_CHECK() RF_HIP(hipGetLastError())
+
+rfcmp_status sigma_t(const MeshDev& d, int64_t C, int64_t N, const double2* x, double2* t, int nr,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_sigma_t, g1(C, nr), dim3(256), 0, s, (int)C, (int)N, d.cell_edge.as<int>(),
+                     d.sgn.as<float>(), x, t);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status lambda_t(const MeshDev& d, int64_t V, int64_t N, const double2* x, double2* g, int nr,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_lambda_t, g1(V, nr), dim3(256), 0, s, (int)V, (int)N, d.ve_ptr.as<int>(),
+                     d.ve_idx.as<int>(), d.ve_sgn.as<float>(), x, g);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status lambda_n(const MeshDev& d, int64_t N, int64_t V, const double2* h, double2* out, int nr,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_lambda, g1(N, nr), dim3(256), 0, s, (int)N, (int)V, d.edge_vtx.as<int>(), h, out);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status axpy_sigma(const MeshDev& d, int64_t N, int64_t C, double ca, bool ca_imag, const double2* x,
+                        double cs, const double2* z, double2* out, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_sigma, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, d.edge_cell.as<int>(), ca,
+                     (int)ca_imag, x, cs, z, out);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status vin(const MeshDev& d, int64_t N, int64_t C, double ka, double kb, const double2* x,
+                 const double2* s1, const double2* s1g, double2* out, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_vin, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, d.edge_cell.as<int>(), ka, kb, x, s1,
+                     s1g, out);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status mean(int64_t n, const double2* x, double2* m, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_mean, dim3(nr), dim3(1024), 0, s, (int)n, x, m);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status comb_c(int64_t C, const double* area, double fa, const double2* a, double fb, const double2* b,
+                    const double2* mb, double2* out, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_comb_c, g1(C, nr), dim3(256), 0, s, (int)C, area, fa, a, fb, b, mb, out);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status middle_w(const MeshDev& d, int64_t N, int64_t C, int64_t V, double ia2, double ig, double ib2,
+                      const double2* h, const double2* a, const double2* s2, const double2* s3, double2* w,
+                      int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_middle_w, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, (int)V, d.edge_cell.as<int>(),
+                     d.edge_vtx.as<int>(), ia2, ig, ib2, h, a, s2, s3, w);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status left_y(const MeshDev& d, int64_t N, int64_t C, double ka, const double2* zA, const double2* s4,
+                    const double2* g6, double2* y, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_left_y, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, d.edge_cell.as<int>(), ka, zA, s4,
+                     g6, y);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double ib, const double2* x,
+                       const double2* sv, const double2* sg, double2* j, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_recover, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, d.edge_cell.as<int>(), ia, ib, x,
+                     sv, sg, j);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, double2* out, int nr,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks, nr), dim3(256), 0, s, (long)n, a, b, part);
+  hipLaunchKernelGGL(k_dot_final, dim3(nr), dim3(256), 0, s, kRedBlocks, part, out);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+int dot_partials() { return kRedBlocks; }
+rfcmp_status normalize(int64_t n, const double2* nrm2, double2* x, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize, g1(n, nr), dim3(256), 0, s, (long)n, nrm2, x);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status cg_xr(int64_t n, const double* sc, int rho_slot, double2* x, double2* r, const double2* p,
+                   const double2* q, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_xr, g1(n), dim3(256), 0, s, (long)n, sc, rho_slot, x, r, p, q);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status cg_p(int64_t n, const double* sc, int old_slot, int new_slot, const double2* r, double2* p,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p, g1(n), dim3(256), 0, s, (long)n, sc, old_slot, new_slot, r, p);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status take_real(const double2* d, double* sc, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_take_real, dim3(1), dim3(1), 0, s, d, sc, slot);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status vsub(int64_t n, const double2* a, const double2* b, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, g1(n), dim3(256), 0, s, (long)n, a, b, out);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status vadd_to(int64_t n, const double2* a, double2* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_to, g1(n), dim3(256), 0, s, (long)n, a, x);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+
+}  // namespace rfcmp

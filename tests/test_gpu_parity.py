@@ -1,0 +1,221 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances: far-pair entries are FP32 7x7 sums of O(1) terms in
+centroid-relative coordinates (relative rounding ~1e-7 per entry, 2e-6
+allowed); every other step is FP64 on top of the stored complex64 blocks, so
+operator steps evaluated on the *exported* blocks agree with the oracle to
+~1e-12.  Solutions are compared with the oracle's own blocks: the complex64
+storage and FP32 quadrature perturb A by ~1e-7 relative, amplified at most by
+cond(A) (< 10 here), hence 1e-5 (the FP32-path target).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import assembly, rfcmp, rhs
+from oracle.topology import Topology
+
+from ._meshes import rel
+
+pytestmark = pytest.mark.gpu
+
+MESHES = {
+    "ico1": lambda: synth.icosphere(1),
+    "ico2": lambda: synth.icosphere(2),
+    "torus_small": lambda: synth.torus(12, 8, jitter=0.01, seed=3),
+    "cube3": lambda: synth.cube(3),               # C = 108: ragged against every tile size
+    "ellipsoid1": lambda: synth.ellipsoid(1, (1.3, 0.8, 0.6)),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _mesh(name):
+    return MESHES[name]()
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(name, k):
+    top = Topology(*_mesh(name))
+    TA, V = assembly.assemble(top, k)
+    return top, TA, V
+
+
+def _gpu():
+    import torch
+    import paper_1803_08333_amd as rf
+    assert torch.cuda.is_available()
+    return torch, rf
+
+
+@functools.lru_cache(maxsize=None)
+def _gpu_mesh(name):
+    torch, rf = _gpu()
+    return rf.Mesh(*_mesh(name))
+
+
+@functools.lru_cache(maxsize=None)
+def _gpu_op(name, k, star=0, scaling=1):
+    torch, rf = _gpu()
+    m = _gpu_mesh(name)
+    start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
+    return rf.Operator(m, k, power_start=start, outer_star=star, scaling=scaling)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+CASES = [("ico1", 0.5), ("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5), ("cube3", 2.0),
+         ("ellipsoid1", 0.05)]
+
+
+@pytest.mark.parametrize("name,k", CASES)
+def test_blocks_match_oracle(name, k):
+    top, TA, V = _oracle(name, k)
+    op = _gpu_op(name, k)
+    gTA, gV = (_np(t).astype(np.complex128) for t in op.export())
+    assert rel(gTA, TA) < 2e-6
+    assert rel(gV, V) < 2e-6
+    assert np.abs(gTA - TA).max() < 2e-6 * np.abs(TA).max()
+    assert np.abs(gV - V).max() < 2e-6 * np.abs(V).max()
+    # exact complex symmetry of the stored blocks
+    assert np.array_equal(gTA, gTA.T) and np.array_equal(gV, gV.T)
+    # low-frequency: imaginary parts carry their own relative accuracy
+    assert rel(gV.imag, V.imag) < 1e-5
+
+
+@pytest.mark.parametrize("name,k", [("ico2", 1.0), ("cube3", 0.3)])
+def test_rhs_match_oracle(name, k):
+    top, _, _ = _oracle(name, k)
+    op = _gpu_op(name, k)
+    kh, pol = synth.plane_waves(3, 7)
+    e = _np(op.rhs_planewave(kh, pol))
+    ref = rhs.planewave(top, k, kh, pol)
+    assert rel(e, ref) < 1e-13
+
+
+@pytest.mark.parametrize("name", ["ico2", "torus_small", "cube3"])
+def test_projectors_match_oracle(name):
+    import paper_1803_08333_amd as rf
+    top, TA, V = _oracle(name, 0.5)
+    op = _gpu_op(name, 0.5)
+    pre = rfcmp.Preconditioner(top, TA, V, 0.5)
+    x = np.stack([synth.complex_start(top.N, 1), synth.complex_start(top.N, 2)])
+    xc = np.stack([synth.complex_start(top.C, 3)])
+    xv = np.stack([synth.complex_start(top.V, 4)])
+    cases = [
+        (rf.PROJ_SIGMA, x, (pre.P_S @ x.T).T),
+        (rf.PROJ_LH, x, (pre.P_LH @ x.T).T),
+        (rf.PROJ_GSIGMA, x, (pre.P_gS @ x.T).T),
+        (rf.PROJ_LPINV, xc, (pre.Lp @ xc.T).T),
+        (rf.PROJ_GLL_INV, xv, (pre.Gll_inv @ xv.T).T),
+        (rf.PROJ_SIGMA_T, x, (top.Sigma.T @ x.T).T),
+        (rf.PROJ_LAMBDA_T, x, (top.Lambda.T @ x.T).T),
+    ]
+    for which, xin, ref in cases:
+        got = _np(op.project(which, _cuda(xin)))
+        assert rel(got, ref) < 1e-11, which
+
+
+@pytest.mark.parametrize("name,k", [("ico2", 1.0), ("cube3", 2.0)])
+def test_matvec_exact_on_stored_blocks(name, k):
+    op = _gpu_op(name, k)
+    gTA, gV = (_np(t).astype(np.complex128) for t in op.export())
+    N, C = len(gTA), len(gV)
+    x = np.stack([synth.complex_start(N, r) for r in range(5)])     # 5 rhs: a 4 + 1 split
+    y = np.stack([synth.complex_start(C, r) for r in range(3)])
+    for conj in (False, True):
+        M = np.conj(gTA) if conj else gTA
+        assert rel(_np(op.matvec(0, _cuda(x), conj)), (M @ x.T).T) < 1e-13
+        M = np.conj(gV) if conj else gV
+        assert rel(_np(op.matvec(1, _cuda(y), conj)), (M @ y.T).T) < 1e-13
+
+
+def _oracle_on_gpu_blocks(name, k, star):
+    """Oracle preconditioner built on the GPU's own (exported) blocks."""
+    top, _, _ = _oracle(name, k)
+    op = _gpu_op(name, k, star)
+    gTA, gV = (_np(t).astype(np.complex128) for t in op.export())
+    pre = rfcmp.Preconditioner(top, gTA, gV, k, outer_star="gsigma" if star else "sigma")
+    a, b, g, _ = op.scalings()
+    pre.set_scalings(a, b, g)
+    return op, pre
+
+
+@pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5), ("cube3", 2.0)])
+@pytest.mark.parametrize("star", [0, 1])
+def test_operator_steps_exact_on_stored_blocks(name, k, star):
+    op, pre = _oracle_on_gpu_blocks(name, k, star)
+    N = pre.top.N
+    x = np.stack([synth.complex_start(N, 21 + r) for r in range(6)])
+    assert rel(_np(op.apply(_cuda(x))), pre.apply(x.T).T) < 1e-11
+    e = np.stack([synth.complex_start(N, 31)])
+    assert rel(_np(op.precond_rhs(_cuda(e))), pre.rhs(e.T).T) < 1e-11
+    assert rel(_np(op.recover(_cuda(x))), pre.recover(x.T).T) < 1e-12
+
+
+@pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5)])
+def test_power_scalings_match_oracle(name, k):
+    torch, rf = _gpu()
+    top, _, _ = _oracle(name, k)
+    op = _gpu_op(name, k, 0, 0)
+    gTA, gV = (_np(t).astype(np.complex128) for t in op.export())
+    pre = rfcmp.Preconditioner(top, gTA, gV, k)
+    ref = pre.power_scalings(synth.complex_start(top.N, 11), 30)
+    a, b, g, lam = op.scalings()
+    assert abs(a - ref[0]) < 1e-10 * ref[0]
+    assert abs(b - ref[1]) < 1e-10 * ref[1]
+    assert abs(g - ref[2]) < 1e-10 * ref[2]
+
+
+@pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 0.1), ("ico2", 1e-4), ("torus_small", 0.5),
+                                    ("cube3", 2.0), ("ellipsoid1", 0.05)])
+@pytest.mark.parametrize("star,scaling", [(0, 0), (1, 1)])
+def test_solution_matches_oracle(name, k, star, scaling):
+    """j from the GPU solve vs the oracle's dense solution on its own FP64
+    blocks (the plain Galerkin solution j = -T^-1 e, reached by RF-CMP)."""
+    top, TA, V = _oracle(name, k)
+    op = _gpu_op(name, k, star, scaling)
+    kh, pol = synth.default_plane_wave()
+    e = rhs.planewave(top, k, kh, pol)
+    pre = rfcmp.Preconditioner(top, TA, V, k)
+    pre.power_scalings(synth.complex_start(top.N, 11), 30)
+    jref = pre.recover(np.linalg.solve(pre.system_split(), pre.rhs(e[0])))
+    j, st, info = op.solve(_cuda(e), tol=1e-8, maxit=500)
+    j = _np(j)[0]
+    assert st == 0 and info[0]["rel_residual"] <= 1e-8
+    assert rel(j, jref) < 1e-5
+    # loop/star parts separately (at ka = 1e-4 the star part is ~1e-4 of |j|)
+    assert rel(pre.P_LH @ j, pre.P_LH @ jref) < 1e-5
+    assert rel(pre.P_S @ j, pre.P_S @ jref) < 1e-5
+
+
+def test_errors_are_reported():
+    torch, rf = _gpu()
+    m = _gpu_mesh("ico1")
+    with pytest.raises(rf.RfcmpError):
+        rf.Operator(m, -1.0, scaling=1)
+    with pytest.raises(rf.RfcmpError):
+        rf.Operator(m, 1.0, scaling=0)          # power scalings need a start vector
+    op = _gpu_op("ico1", 0.5)
+    with pytest.raises(rf.RfcmpError):
+        op.rhs_planewave(np.array([[0, 0, 1.0]]), np.array([[0, 0.6, 0.8]]))   # not transverse
+    with pytest.raises(rf.RfcmpError):
+        op.set_scalings(0.0, 1.0, 1.0)
+
+
+def test_not_converged_returns_best_iterate():
+    torch, rf = _gpu()
+    op = _gpu_op("ico2", 1.0)
+    kh, pol = synth.default_plane_wave()
+    e = op.rhs_planewave(kh, pol)
+    j, st, info = op.solve(e, tol=1e-12, maxit=2)
+    assert st == 1 and info[0]["iters"] == 2
+    assert np.all(np.isfinite(_np(j)))
