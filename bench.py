@@ -1,0 +1,199 @@
+"""Benchmark: RF-CMP EFIE solve on one MI355X.
+
+One step = one pass of the whole hot path over the workload, from the mesh
+to the RWG currents:
+  PEC sphere r = 1 m, icosphere level 4 (C = 5120 cells, N = 7680 RWG),
+  ka = 1.0 and ka = 1e-4, one x-polarised plane wave along +z, CG to 1e-6:
+  topology, projector matrices (L^+, G_ll^-1), far/near-pair assembly of T_A
+  and V, power-iteration scalings, excitation, preconditioned rhs, CG, and
+  recovery j = P_o i -- for both wavenumbers.
+
+Prints one JSON line.  ``value`` = RF-CMP solves per second over the timed
+steps (two solves per step); kernel durations come from HIP events recorded
+by the library on the launch stream during the timed steps.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+import synth  # noqa: E402
+
+# MI355X published peaks
+HBM_GBS = 8000.0
+FP32_VALU_TFLOPS = 157.3
+FP64_VALU_TFLOPS = 78.6
+
+WORKLOAD = {"workload": "PEC sphere r=1 m, icosphere level 4 (5120 cells, 7680 RWG), ka=1.0 and ka=1e-4, "
+                        "x-polarised plane wave along +z, CG to relative residual 1e-6",
+            "mesh": "icosphere4", "ka": [1.0, 1e-4], "nrhs": 1, "tol": 1e-6}
+TOL = 1e-6
+KS = (1.0, 1e-4)
+FAR_FLOPS_PER_POINT_PAIR = 30     # see the design doc: sub 3, R^2 5, rsqrt 1, R 1, kR 1, sin+cos 2, G 3, sums 14
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-slab", type=int, default=32, help="1/slab of the test cells for the oracle sample")
+    return p.parse_args()
+
+
+def cpu_baseline(xyz, tri, slab):
+    """The FP64 oracle on a bounded sample of the same workload: the far- and
+    near-pair assembly of a 1/slab row slab of the level-4 sphere at ka = 1.0.
+    Converted to solves/s assuming assembly is the oracle's only cost (an upper
+    bound on its throughput: setup, scalings and CG are left out)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import assembly, quadrature
+    from oracle.topology import Topology
+    top = Topology(xyz, tri)
+    C = top.C
+    rows = np.arange(0, C, slab)
+    pts, w = quadrature.tri7_points(top.xyz, top.tri)
+    cores = os.cpu_count() or 1
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        c0 = time.process_time()
+        near = assembly.near_mask(top)
+        k = 1.0
+        arm = pts[:, :, None, :] - top.xyz[top.tri][:, None, :, :]
+        ww = np.outer(w, w)
+        for s in range(0, len(rows), 8):
+            cs = rows[s:s + 8]
+            R = np.linalg.norm(pts[cs, :, None, None, :] - pts[None, None, :, :, :], axis=-1)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                G = np.exp(1j * k * R) / (4.0 * np.pi * R)
+            G[~np.isfinite(G)] = 0.0
+            Gw = G * ww[None, :, None, :]
+            Gw.sum(axis=(1, 3))
+            np.einsum("apid,apbq,bqjd->aibj", arm[cs], Gw, arm, optimize=True)
+        for c in rows:
+            for cp in np.nonzero(near[c])[0]:
+                assembly.near_block(top, c, cp, k, pts, w)
+        dt = time.perf_counter() - t0
+        used = max(1, int(round((time.process_time() - c0) / dt)))
+    pairs = len(rows) * C
+    pairs_per_s = pairs / dt
+    full_assembly_s = C * C / pairs_per_s
+    return {"value": 1.0 / full_assembly_s, "unit": "solves/s", "cores": used,
+            "kind": "oracle",
+            "sample": f"oracle far+near assembly of 1/{slab} of the test cells ({len(rows)} x {C} cell pairs, "
+                      f"ka=1.0) in {dt:.1f} s; solves/s = 1/(C^2 / pairs_per_s), i.e. assembly only "
+                      f"(upper bound on the oracle's throughput)",
+            "assembly_pairs_per_s": pairs_per_s}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
+              "see DESIGN.md for how the operator would shard.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1803_08333_amd as rf
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    xyz, tri = synth.icosphere(4)
+    kh, pol = synth.default_plane_wave()
+    N = len(tri) * 3 // 2
+    C = len(tri)
+    start = torch.from_numpy(synth.complex_start(N, 11)).to(dev)
+    out = {}
+
+    def step(record):
+        m = rf.Mesh(xyz, tri)
+        for k in KS:
+            op = rf.Operator(m, k, power_start=start)
+            e = op.rhs_planewave(kh, pol)
+            j, st, info = op.solve(e, tol=TOL, maxit=2000)
+            if record:
+                a, b, g, lam = op.scalings()
+                out[k] = {"status": st, "iters": info[0]["iters"], "restarts": info[0]["restarts"],
+                          "rel_residual": info[0]["rel_residual"], "solve_ms": info[0]["ms_solve"],
+                          "alpha": a, "beta": b, "gamma": g}
+            op.close()
+        m.close()
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    rf.profile_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i == args.steps - 1)
+        print(f"# step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tags = ["far_pairs", "near_pairs", "gather_ta", "cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll",
+            "spd_inverse"]
+    prof = {t: rf.profile_read(t) for t in tags}
+    rf.profile_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = len(KS) / (ms_step / 1e3)
+
+    # assembly rate (per wavenumber: C^2 ordered cell pairs)
+    asm_ms = sum(prof[t][0] for t in ("far_pairs", "near_pairs", "gather_ta")) / (args.steps * len(KS))
+    pairs_per_s = C * C / (asm_ms / 1e3)
+
+    # roofline of the dominant kernel (largest total time)
+    def model(tag, avg_ms):
+        if tag == "cmatvec_ta":
+            byt = 8.0 * N * N + 32.0 * N
+            return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s"}
+        if tag in ("cmatvec_v", "dmatvec_lp"):
+            byt = 8.0 * C * C + 32.0 * C
+            return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s"}
+        if tag == "far_pairs":
+            fl = C * (C - 1) / 2 * 49 * FAR_FLOPS_PER_POINT_PAIR
+            return {"bound": "alu", "achieved": fl / (avg_ms * 1e-3) / 1e12, "peak": FP32_VALU_TFLOPS,
+                    "unit": "TFLOP/s"}
+        return None
+
+    ranked = sorted((v[0], t) for t, v in prof.items() if v[1] > 0 and model(t, 1.0) is not None)
+    dom = ranked[-1][1]
+    avg = prof[dom][0] / prof[dom][1]
+    roof = model(dom, avg)
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_ms"] = avg
+    roof["launches"] = prof[dom][1]
+
+    res = {
+        "metric": "RF-CMP solve time + EFIE assembly pairs/s; BF16x3 vs FP32 at 1e-6 residual",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 blocks (FP32 far-pair quadrature, FP64 near pairs), FP64 accumulation and projectors",
+        "data": "synthetic (seeded icosphere, analytic plane wave)",
+        "config": WORKLOAD,
+        "solve_ms": {str(k): out[k]["solve_ms"] for k in KS},
+        "iterations": {str(k): out[k]["iters"] for k in KS},
+        "rel_residual": {str(k): out[k]["rel_residual"] for k in KS},
+        "scalings": {str(k): [out[k]["alpha"], out[k]["beta"], out[k]["gamma"]] for k in KS},
+        "assembly_pairs_per_s": pairs_per_s,
+        "assembly_ms": asm_ms,
+        "kernel_ms_per_step": {t: prof[t][0] / args.steps for t in tags},
+        "bf16x3_vs_fp32": None,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(xyz, tri, args.cpu_slab)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -178,6 +178,18 @@ typedef struct {
 rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol,
                          int32_t maxit, void* stream, rfcmp_info* info);
 
+/* ------------------------------------------------------------ profiling */
+/* Kernel timing for benchmarks.  While enabled, the library records a HIP
+ * event pair on the launch stream around every launch of its timed kernels:
+ * "far_pairs", "near_pairs", "gather_ta" (assembly), "cmatvec_ta",
+ * "cmatvec_v" (complex64 block products), "dmatvec" (FP64 projector
+ * products), "spd_inverse" (whole FP64 inverse).  rfcmp_profile_enable
+ * clears the records (waiting for recorded events first); rfcmp_profile_read
+ * waits for the events of one tag and returns their summed duration and
+ * count.  Not thread-safe; adds two event records per timed launch. */
+rfcmp_status rfcmp_profile_enable(int32_t on);
+rfcmp_status rfcmp_profile_read(const char* tag, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,7 +5,7 @@ library.  Device buffers are torch tensors on the current CUDA (HIP) device
 and work is enqueued on torch's current stream.  The functions keep the C
 names of include/rfcmp.h; ``Mesh`` and ``Operator`` wrap the handles.
 
-The library must be built first (``python -m paper_1803_08333_amd.build``);
+The library must be built first (``python paper_1803_08333_amd/build.py``);
 importing this module without it raises, there is no fallback path.
 """
 
@@ -81,12 +81,14 @@ EXPORTED = {
     "rfcmp_project": (_I32, [_P, _I32, _P, _P, _I32, _P]),
     "rfcmp_matvec": (_I32, [_P, _I32, _I32, _P, _P, _I32, _P]),
     "rfcmp_solve": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, ctypes.POINTER(Info)]),
+    "rfcmp_profile_enable": (_I32, [_I32]),
+    "rfcmp_profile_read": (_I32, [ctypes.c_char_p, _PD, _PI64]),
 }
 
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1803_08333_amd.build`")
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python paper_1803_08333_amd/build.py`")
     h = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in EXPORTED.items():
         fn = getattr(h, name)
@@ -124,6 +126,18 @@ def _dptr(t, dtype=None, numel=None):
     if numel is not None and t.numel() != numel:
         raise ValueError(f"expected {numel} elements, got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def profile_enable(on=True):
+    """rfcmp_profile_enable: start (or stop) HIP-event timing of tagged kernels."""
+    _check(lib.rfcmp_profile_enable(int(bool(on))))
+
+
+def profile_read(tag):
+    """rfcmp_profile_read: (total ms, launches) of one kernel tag."""
+    t, n = _D(), _I64()
+    _check(lib.rfcmp_profile_read(tag.encode(), ctypes.byref(t), ctypes.byref(n)))
+    return t.value, n.value
 
 
 def options(**kw):

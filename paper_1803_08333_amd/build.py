@@ -1,6 +1,6 @@
 """Build librfcmp.so (HIP for gfx950) in-tree.
 
-    python -m paper_1803_08333_amd.build        # or build() from Python
+    python paper_1803_08333_amd/build.py     (standalone: does not import the package)
 
 Every source is compiled with hipcc for gfx950 only.  Packed FP32 instructions
 are disabled (-packed-fp32-ops): the FP32 kernels are written as scalar code.

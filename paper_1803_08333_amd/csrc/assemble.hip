@@ -501,18 +501,25 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
 
   const long nt = (long)((C + kTile - 1) / kTile);
   const long ntiles = nt * (nt + 1) / 2;
+  {
+  ProfScope prof("far_pairs", s);
   hipLaunchKernelGGL(k_far_pairs, dim3((unsigned)ntiles), dim3(256), 0, s, (int)C, ntiles, d.cen.as<double>(),
                      d.qoff.as<float4>(), d.fvoff.as<float4>(), d.sgn.as<float>(), (float)op->k, ra,
                      B.as<float2>(), (long)ldB, op->Vb.as<float2>(), (long)op->ldV);
+  }
   RF_HIP(hipGetLastError());
   if (npairs > 0) {
+    ProfScope prof("near_pairs", s);
     hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, s, npairs,
                        dp.as<int>(), d.vtx.as<double>(), d.area.as<double>(), d.sgn.as<float>(), op->k, ra,
                        B.as<float2>(), (long)ldB, op->Vb.as<float2>(), (long)op->ldV);
     RF_HIP(hipGetLastError());
   }
+  {
+  ProfScope prof("gather_ta", s);
   hipLaunchKernelGGL(k_gather_ta, dim3((unsigned)N), dim3(256), 0, s, (int)N, d.edge_slot.as<int>(),
                      B.as<float2>(), (long)ldB, op->TA.as<float2>(), (long)op->ldA);
+  }
   RF_HIP(hipGetLastError());
   RF_HIP(hipStreamSynchronize(s));  // B and the pair list are released on return
   return RFCMP_OK;

@@ -292,8 +292,9 @@ inline unsigned blocks_for(long n, int per) { return unsigned((n + per - 1) / pe
 }  // namespace
 
 rfcmp_status cmatvec(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y,
-                     int nrhs, hipStream_t s) {
+                     int nrhs, hipStream_t s, const char* tag) {
   for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    ProfScope prof(tag, s);
     const int nr = std::min(4, nrhs - r0);
     const double2* xr = x + (long)r0 * n;
     double2* yr = y + (long)r0 * n;
@@ -316,8 +317,9 @@ rfcmp_status cmatvec(const float2* M, int64_t n, int64_t ld, bool conj, const do
 }
 
 rfcmp_status dmatvec(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
-                     hipStream_t s) {
+                     hipStream_t s, const char* tag) {
   for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    ProfScope prof(tag, s);
     const int nr = std::min(4, nrhs - r0);
     const double2* xr = x + (long)r0 * n;
     double2* yr = y + (long)r0 * n;
@@ -339,6 +341,7 @@ rfcmp_status spd_inverse(double* A, int64_t n, hipStream_t s) {
     return RFCMP_E_ARG;
   }
   const int nb = int(n / kB);
+  ProfScope prof("spd_inverse", s);
   DevBuf ccol;
   RF_TRY(ccol.alloc(sizeof(double) * n * kB));
   for (int K = 0; K < nb; ++K) {

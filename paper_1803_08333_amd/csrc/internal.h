@@ -62,6 +62,30 @@ struct DevBuf {
 
 inline size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
 
+// Optional kernel timing for benchmarks: when enabled, a start/stop HIP event
+// pair is recorded on the launch stream around each tagged launch.
+bool profiling_enabled();
+void profile_record(const char* tag, hipEvent_t start, hipEvent_t stop);
+hipEvent_t profile_event();
+struct ProfScope {
+  const char* tag;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(const char* t, hipStream_t st) : tag(t), s(st) {
+    if (profiling_enabled()) {
+      a = profile_event();
+      b = profile_event();
+      if (a && b) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      profile_record(tag, a, b);
+    }
+  }
+};
+
 // Host-side topology and geometry (FP64), built by rfcmp_mesh_create.
 struct MeshHost {
   int64_t V = 0, C = 0, N = 0;
@@ -144,10 +168,10 @@ rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, i
 rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s);
 // y[r] = M x[r] for r < nrhs; M complex64 [n][ld]; x, y complex128 [nrhs][n]
 rfcmp_status cmatvec(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y,
-                     int nrhs, hipStream_t s);
+                     int nrhs, hipStream_t s, const char* tag = "cmatvec");
 // y[r] = M x[r]; M real FP64 [n][ld]; x, y complex128 [nrhs][n]
 rfcmp_status dmatvec(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
-                     hipStream_t s);
+                     hipStream_t s, const char* tag = "dmatvec");
 // In-place inverse of an SPD matrix, FP64, n padded to a multiple of 64.
 rfcmp_status spd_inverse(double* A, int64_t n, hipStream_t s);
 

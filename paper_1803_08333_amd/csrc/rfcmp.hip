@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <tuple>
 
 #include "vecops.h"
 
@@ -74,15 +75,15 @@ rfcmp_status left_half(rfcmp_op op, const Work& W, double2* y, int nr, double sg
   const int64_t N = h.N, C = h.C;
   const double k = op->k, al = op->alpha, be = op->beta;
   double2 *t5 = W.c[9], *s4 = W.c[10], *vw = W.c[11], *t6 = W.c[12], *g6 = W.c[13];
-  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, true, W.nC, W.nD, nr, s));      // zA
-  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, true, W.c[8], vw, nr, s));      // vw
+  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, true, W.nC, W.nD, nr, s, "cmatvec_ta"));      // zA
+  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, true, W.c[8], vw, nr, s, "cmatvec_v"));      // vw
   RF_TRY(sigma_t(d, C, N, W.nD, t5, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t5, s4, nr, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t5, s4, nr, s, "dmatvec_lp"));
   RF_TRY(mean(C, vw, W.m3, nr, s));
   RF_TRY(comb_c(C, nullptr, -sgn * (k / be), s4, sgn / (k * be), vw, W.m3, t6, nr, s));
   const double2* gsel = t6;
   if (use_gsigma(op)) {
-    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, t6, g6, nr, s));
+    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, t6, g6, nr, s, "dmatvec_gtp"));
     gsel = g6;
   }
   RF_TRY(left_y(d, N, C, sgn * k / al, W.nD, s4, gsel, y, nr, s));
@@ -99,26 +100,26 @@ rfcmp_status apply_batch(rfcmp_op op, const double2* x, double2* y, int nr, hipS
   double2 *t1 = W.c[0], *s1 = W.c[1], *g1 = W.c[2], *s1g = W.c[3], *vphi = W.c[4], *t2 = W.c[5],
           *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8], *s3 = W.c[9];
   RF_TRY(sigma_t(d, C, N, x, t1, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t1, s1, nr, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t1, s1, nr, s, "dmatvec_lp"));
   const double2* sus = t1;   // Sig^T u_S
   const double2* s_us = s1;  // u_S = Sig s_us
   if (use_gsigma(op)) {
-    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, t1, g1, nr, s));
-    RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, g1, s1g, nr, s));
+    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, t1, g1, nr, s, "dmatvec_gtp"));
+    RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, g1, s1g, nr, s, "dmatvec_lp"));
     sus = g1;
     s_us = s1g;
   }
   RF_TRY(vin(d, N, C, k / al, k / be, x, s1, s_us, W.nA, nr, s));
-  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, false, W.nA, W.nB, nr, s));   // a
-  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, false, sus, vphi, nr, s));     // vphi
+  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, false, W.nA, W.nB, nr, s, "cmatvec_ta"));   // a
+  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, false, sus, vphi, nr, s, "cmatvec_v"));     // vphi
   RF_TRY(sigma_t(d, C, N, W.nB, t2, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t2, s2, nr, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t2, s2, nr, s, "dmatvec_lp"));
   RF_TRY(lambda_t(d, V, N, W.nB, W.v1, nr, s));
-  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, nr, s));
+  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, nr, s, "dmatvec_gll"));
   RF_TRY(mean(C, vphi, W.m1, nr, s));
   RF_TRY(comb_c(C, d.area.as<double>(), 1.0, s2, 1.0 / (k * be), vphi, W.m1, t4, nr, s));
   // s3 lives in c[9]: written before left_half reuses that slot as t5
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t4, s3, nr, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t4, s3, nr, s, "dmatvec_lp"));
   RF_TRY(middle_w(d, N, C, V, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be), W.v2, W.nB, s2, s3, W.nC, nr, s));
   RF_TRY(mean(C, t4, W.m2, nr, s));
   RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0 / (be * be), t4, W.m2, sw, nr, s));
@@ -133,11 +134,11 @@ rfcmp_status rhs_batch(rfcmp_op op, const double2* e, double2* b, int nr, hipStr
   const Work W = carve(op);
   double2 *t2 = W.c[5], *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8], *s3 = W.c[9];
   RF_TRY(sigma_t(d, C, N, e, t2, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t2, s2, nr, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t2, s2, nr, s, "dmatvec_lp"));
   RF_TRY(lambda_t(d, V, N, e, W.v1, nr, s));
-  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, nr, s));
+  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, nr, s, "dmatvec_gll"));
   RF_TRY(comb_c(C, d.area.as<double>(), 1.0, s2, 0.0, nullptr, nullptr, t4, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t4, s3, nr, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t4, s3, nr, s, "dmatvec_lp"));
   RF_TRY(middle_w(d, N, C, V, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be), W.v2, e, s2, s3, W.nC, nr, s));
   RF_TRY(mean(C, t4, W.m2, nr, s));
   RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0 / (be * be), t4, W.m2, sw, nr, s));
@@ -150,11 +151,11 @@ rfcmp_status recover_batch(rfcmp_op op, const double2* x, double2* j, int nr, hi
   const int64_t N = h.N, C = h.C;
   const Work W = carve(op);
   RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, s, "dmatvec_lp"));
   const double2* sg = W.c[1];
   if (use_gsigma(op)) {
-    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, s));
-    RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[3], nr, s));
+    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, s, "dmatvec_gtp"));
+    RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[3], nr, s, "dmatvec_lp"));
     sg = W.c[3];
   }
   return recover_j(d, N, C, 1.0 / op->alpha, 1.0 / op->beta, x, W.c[1], sg, j, nr, s);
@@ -182,27 +183,27 @@ rfcmp_status power_apply(rfcmp_op op, const Work& W, hipStream_t s) {
   double2* va = W.pv;
   double2* vb = W.pv + 2 * N;
   RF_TRY(sigma_t(d, C, N, va, W.c[0], 2, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], 2, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], 2, s, "dmatvec_lp"));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, va, -1.0, W.c[1], W.nA, 2, s));          // P_LH v
-  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, false, W.nA, W.nB, 2, s));
+  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, false, W.nA, W.nB, 2, s, "cmatvec_ta"));
   RF_TRY(lambda_t(d, V, N, W.nB, W.v1, 1, s));
-  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, 1, s));
+  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, 1, s, "dmatvec_gll"));
   RF_TRY(lambda_n(d, N, V, W.v2, W.nC, 1, s));                                   // alpha branch
   RF_TRY(sigma_t(d, C, N, W.nB + N, W.c[2], 1, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[3], 1, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[3], 1, s, "dmatvec_lp"));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nB + N, -1.0, W.c[3], W.nC + N, 1, s));  // gamma branch
-  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, true, W.nC, W.nD, 2, s));
+  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, true, W.nC, W.nD, 2, s, "cmatvec_ta"));
   RF_TRY(sigma_t(d, C, N, W.nD, W.c[4], 2, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[4], W.c[5], 2, s));
+  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[4], W.c[5], 2, s, "dmatvec_lp"));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nD, -1.0, W.c[5], W.pw, 2, s));
   // beta
   RF_TRY(sigma_t(d, C, N, vb, W.c[6], 1, s));
-  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, false, W.c[6], W.c[7], 1, s));
+  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, false, W.c[6], W.c[7], 1, s, "cmatvec_v"));
   RF_TRY(mean(C, W.c[7], W.m1, 1, s));
   RF_TRY(comb_c(C, d.area.as<double>(), 0.0, nullptr, 1.0, W.c[7], W.m1, W.c[8], 1, s));
   RF_TRY(mean(C, W.c[8], W.m2, 1, s));
   RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0, W.c[8], W.m2, W.c[9], 1, s));
-  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, true, W.c[9], W.c[10], 1, s));
+  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, true, W.c[9], W.c[10], 1, s, "cmatvec_v"));
   RF_TRY(axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[10], W.pw + 2 * N, 1, s));
   return RFCMP_OK;
 }
@@ -329,6 +330,32 @@ bool unit(const double* v) {
 }  // namespace
 }  // namespace rfcmp
 
+namespace rfcmp {
+namespace {
+struct ProfState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;  // all events ever created (reused)
+  size_t next = 0;
+  std::vector<std::tuple<std::string, hipEvent_t, hipEvent_t>> rec;
+};
+ProfState& prof() {
+  static ProfState p;
+  return p;
+}
+}  // namespace
+bool profiling_enabled() { return prof().on; }
+hipEvent_t profile_event() {
+  ProfState& p = prof();
+  if (p.next == p.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p.pool.push_back(e);
+  }
+  return p.pool[p.next++];
+}
+void profile_record(const char* tag, hipEvent_t a, hipEvent_t b) { prof().rec.emplace_back(tag, a, b); }
+}  // namespace rfcmp
+
 using namespace rfcmp;
 
 #define RF_ARG(cond, msg)              \
@@ -343,6 +370,32 @@ extern "C" {
 
 const char* rfcmp_last_error(void) { return rfcmp::last_error(); }
 const char* rfcmp_version(void) { return "rfcmp 0.1 (gfx950)"; }
+
+rfcmp_status rfcmp_profile_enable(int32_t on) {
+  ProfState& p = prof();
+  for (auto& r : p.rec) (void)hipEventSynchronize(std::get<2>(r));
+  p.rec.clear();
+  p.next = 0;
+  p.on = on != 0;
+  return RFCMP_OK;
+}
+
+rfcmp_status rfcmp_profile_read(const char* tag, double* total_ms, int64_t* launches) {
+  RF_ARG(tag && total_ms && launches, "NULL argument");
+  double t = 0.0;
+  int64_t n = 0;
+  for (auto& r : prof().rec) {
+    if (std::get<0>(r) != tag) continue;
+    RF_HIP(hipEventSynchronize(std::get<2>(r)));
+    float ms = 0.f;
+    RF_HIP(hipEventElapsedTime(&ms, std::get<1>(r), std::get<2>(r)));
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return RFCMP_OK;
+}
 
 rfcmp_status rfcmp_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t nc, rfcmp_mesh* out) {
   RF_ARG(out, "out is NULL");
@@ -533,14 +586,14 @@ rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* xv, void* yv,
                      case RFCMP_PROJ_SIGMA:
                      case RFCMP_PROJ_LH:
                        RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-                       RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, s));
+                       RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, s, "dmatvec_lp"));
                        return which == RFCMP_PROJ_SIGMA
                                   ? axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[1], y, nr, s)
                                   : axpy_sigma(d, N, C, 1.0, false, x, -1.0, W.c[1], y, nr, s);
                      case RFCMP_PROJ_GSIGMA:
                        RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-                       RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, s));
-                       RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[1], nr, s));
+                       RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, s, "dmatvec_gtp"));
+                       RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[1], nr, s, "dmatvec_lp"));
                        return axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[1], y, nr, s);
                      case RFCMP_PROJ_LPINV:
                        return dmatvec(d.Lp.as<double>(), C, d.ldL, x, y, nr, s);

@@ -1,0 +1,102 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/rfcmp.h declares, and its topology, near-pair list and
+mesh validation agree with the oracle exactly."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import assembly
+from oracle.topology import Topology
+
+from ._meshes import mesh
+
+
+def _header_functions(root):
+    src = open(os.path.join(root, "include", "rfcmp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rfcmp_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(root):
+    import paper_1803_08333_amd as rf
+    declared = _header_functions(root)
+    assert len(declared) >= 20
+    raw = ctypes.CDLL(rf.LIB_PATH)
+    for name in declared:
+        assert hasattr(raw, name), name
+        assert name in rf.EXPORTED, name
+    assert set(rf.EXPORTED) == set(declared)
+
+
+@pytest.mark.parametrize("name", ["ico0", "ico2", "torus_small", "cube2", "ellipsoid1"])
+def test_topology_matches_oracle(name):
+    import paper_1803_08333_amd as rf
+    xyz, tri = mesh(name)
+    top = Topology(xyz, tri)
+    m = rf.Mesh(xyz, tri)
+    assert (m.N, m.V, m.C, m.genus) == (top.N, top.V, top.C, top.genus)
+    ev, ec, el = m.edges()
+    assert np.array_equal(ev, top.edges)
+    assert np.array_equal(ec, np.stack([top.cplus, top.cminus], 1))
+    assert np.array_equal(el, np.stack([top.lplus, top.lminus], 1))
+
+
+@pytest.mark.parametrize("name,factor", [("ico2", 2.0), ("cube2", 2.0), ("cube2", 1.0), ("torus_small", 3.0)])
+def test_near_pairs_match_oracle(name, factor):
+    """Includes the structured cube, where exact distance ties sit on the
+    threshold (resolved as near by the 1e-9 slack on both sides)."""
+    import paper_1803_08333_amd as rf
+    xyz, tri = mesh(name)
+    top = Topology(xyz, tri)
+    ref = np.argwhere(np.triu(assembly.near_mask(top, factor)))
+    got = rf.Mesh(xyz, tri).near_pairs(factor)
+    assert np.array_equal(got, ref)
+
+
+def _status(xyz, tri):
+    import paper_1803_08333_amd as rf
+    try:
+        rf.Mesh(xyz, tri)
+    except rf.RfcmpError as e:
+        return e.status
+    return 0
+
+
+def test_mesh_validation_codes():
+    xyz, tri = synth.icosphere(1)
+    assert _status(xyz, tri) == 0
+    assert _status(xyz, tri[:-1]) == -2                          # open
+    bad = tri.copy()
+    bad[0] = bad[0][[0, 2, 1]]
+    assert _status(xyz, bad) == -4                                # orientation
+    bad = tri.copy()
+    bad[0, 0] = bad[0, 1]
+    assert _status(xyz, bad) == -3                                # repeated vertex
+    bad = tri.copy()
+    bad[0, 0] = len(xyz)
+    assert _status(xyz, bad) == -3                                # out of range
+    deg = xyz.copy()
+    t0 = tri[0]
+    deg[t0[2]] = 0.5 * (deg[t0[0]] + deg[t0[1]])
+    assert _status(deg, tri) == -6                                # zero area
+    # two disjoint spheres
+    x2 = np.concatenate([xyz, xyz + 5.0])
+    t2 = np.concatenate([tri, tri + len(xyz)])
+    assert _status(x2, t2) == -5
+    # two spheres glued at one vertex (pinch: one vertex, two fans)
+    # second sphere: reflect so that its vertex 0 lands on the first one's vertex 0
+    xb = -xyz + 2 * xyz[0]
+    x3 = np.concatenate([xyz, xb[1:]])
+    tb = np.where(tri == 0, 0, tri + len(xyz) - 1)[:, [0, 2, 1]]  # reflection flips orientation
+    assert _status(x3, np.concatenate([tri, tb])) == -3
+    assert _status(xyz, np.zeros((0, 3), np.int32)) == -1
+
+
+def test_options_defaults():
+    import paper_1803_08333_amd as rf
+    o = rf.options()
+    assert (o.near_factor, o.outer_star, o.scaling, o.power_iters, o.precision) == (2.0, 0, 0, 30, 0)
