@@ -155,10 +155,16 @@ enum {
 };
 rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* x, void* y, int32_t nrhs, void* stream);
 
-/* Dense block product (Sec. 3.4 adjoint: T^H x = conj(T conj x)):
- *   which 0: y = M x with M = T_A (n = N);  which 1: M = V (n = C)
- *   conj != 0: y = conj(M) x.
- * Complex64 storage, FP64 accumulation.  x, y: device c128 [nrhs][n]. */
+/* Dense block products (Sec. 3.4 adjoint: T^H x = conj(T conj x)):
+ *   which 0: y = M x, M = T_A (n = N), complex64 storage, FP64 accumulation
+ *   which 1: M = V (n = C), likewise
+ *   which 2: M = T_A as BF16x3 split products on MFMA, FP32 accumulation
+ *   which 3: M = V as BF16x3
+ *   which 4: M = L^+ (real, n = C) as BF16x3
+ *   which 5: M = G_ll^-1 (real, n = V) as BF16x3
+ *   conj != 0 (which 0-3): y = conj(M) x.
+ * x, y: device c128 [nrhs][n].  The BF16x3 planes (hi/lo bf16 of every
+ * entry, same bytes as complex64) are built on first use. */
 rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* x, void* y,
                           int32_t nrhs, void* stream);
 
@@ -171,9 +177,17 @@ typedef struct {
 } rfcmp_info;
 
 /* Solve T j = -e through the RF-CMP system with CG (Sec. 3.4; x0 = 0), until
- * the true relative residual |b - A i|/|b| <= tol (b = preconditioned rhs).
- * e, j: device c128 [nrhs][N].  info: host [nrhs], nullable.  Returns
- * RFCMP_W_NOT_CONVERGED (best iterate in j) when maxit is reached,
+ * the true relative residual |b - A i|/|b| <= tol (b = preconditioned rhs),
+ * for nrhs right-hand sides advanced together (up to 64 per block; each has
+ * its own CG scalars and stops on its own).
+ *   precision 0: CG on the complex64 / FP64 operator, restarted from the
+ *                true residual when the recursive one has drifted;
+ *   precision 1: iterative refinement: inner CG on the BF16x3 operator to
+ *                1e-4 of the current residual, outer residual with the
+ *                complex64 / FP64 operator.
+ * e, j: device c128 [nrhs][N].  info: host [nrhs], nullable (iters counts
+ * all inner iterations, restarts the residual rounds after the first).
+ * Returns RFCMP_W_NOT_CONVERGED (best iterate in j) when maxit is reached,
  * RFCMP_E_BREAKDOWN on a non-positive curvature. */
 rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol,
                          int32_t maxit, void* stream, rfcmp_info* info);

@@ -1,0 +1,293 @@
+// BF16x3 split-precision products on the gfx950 matrix cores (MFMA), for
+// many right-hand sides at once:  Y = M X,  M complex (or real) n x K,
+// X complex128 [nrhs][K].
+//
+// Split precision (Henry, Tang, Heinecke, "Leveraging the bfloat16 artificial
+// intelligence datatype for higher-precision computations", ARITH 2019):
+// every operand v is stored as hi = bf16(v), lo = bf16(v - hi), and a product
+// a b is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo lo term, 2^-18
+// relative, is dropped), accumulated in FP32 by the MFMA.  The relative error
+// of a product is ~2^-16, so these products serve inner iterations whose
+// residual is recomputed with the FP64-accumulated complex64 product.
+//
+// Storage: a complex matrix is four bf16 planes (Re hi, Re lo, Im hi, Im lo),
+// 8 bytes per entry -- the same as complex64; a real matrix two planes.
+// Planes are row-major [rows_pad][kpad] with rows_pad a multiple of 128 and
+// kpad a multiple of 64, zero-padded.  X is split per call into two planes
+// [ncp][kpad] (column 2r + 0/1 = Re/Im of right-hand side r; ncp = 2 nrhs
+// rounded up to 32, at most 128).
+//
+// Kernel: a workgroup (4 waves) owns 128 rows and all ncp columns over one
+// slice of K (split-K for occupancy).  Each wave computes 32 rows with
+// v_mfma_f32_32x32x16_bf16; the X tile of a 64-wide K chunk is staged in LDS.
+// Within a chunk, lane l of a wave covers k = 32 (l / 32) + 8 s + e for
+// sub-step s and element e on both operands (the contraction order is free),
+// so each lane reads 64 contiguous bytes of its matrix row.  Partial sums go
+// to an FP32 buffer [slice][plane][rows_pad][ncp]; a combine kernel adds the
+// slices in a fixed order in FP64 and forms the complex result.
+#include "internal.h"
+#include "gemm.h"
+
+namespace rfcmp {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned short u16;
+
+constexpr int kRowsWG = 128;
+constexpr int kKc = 64;          // K chunk staged per LDS pass
+constexpr int kLdsK = kKc + 8;   // padded column stride in LDS (bf16 units)
+
+__device__ inline u16 bf16_bits(float x) {
+  const __bf16 h = (__bf16)x;  // round to nearest even
+  return __builtin_bit_cast(u16, h);
+}
+__device__ inline float bf16_val(u16 b) { return (float)__builtin_bit_cast(__bf16, b); }
+
+// complex64 [n][ld] -> planes [4][rows_pad][kpad]
+__global__ void k_split_c64(const float2* __restrict__ M, long n, long ncol, long ld, u16* __restrict__ P,
+                            long rows_pad, long kpad) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows_pad * kpad) return;
+  const long i = t / kpad, k = t % kpad;
+  float re = 0.f, im = 0.f;
+  if (i < n && k < ncol) {
+    const float2 v = M[i * ld + k];
+    re = v.x;
+    im = v.y;
+  }
+  const long plane = rows_pad * kpad;
+  const u16 rh = bf16_bits(re), ih = bf16_bits(im);
+  P[t] = rh;
+  P[plane + t] = bf16_bits(re - bf16_val(rh));
+  P[2 * plane + t] = ih;
+  P[3 * plane + t] = bf16_bits(im - bf16_val(ih));
+}
+
+// real FP64 [n][ld] -> planes [2][rows_pad][kpad]
+__global__ void k_split_f64(const double* __restrict__ M, long n, long ld, u16* __restrict__ P, long rows_pad,
+                            long kpad) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows_pad * kpad) return;
+  const long i = t / kpad, k = t % kpad;
+  const float v = (i < n && k < n) ? (float)M[i * ld + k] : 0.f;
+  const u16 h = bf16_bits(v);
+  P[t] = h;
+  P[rows_pad * kpad + t] = bf16_bits(v - bf16_val(h));
+}
+
+// X complex128 [nrhs][K] -> planes [2][ncp][kpad], column 2r + part
+__global__ void k_split_x(const double2* __restrict__ X, int nrhs, long K, u16* __restrict__ P, int ncp,
+                          long kpad, int conj_x) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)ncp * kpad) return;
+  const long col = t / kpad, k = t % kpad;
+  const long r = col / 2;
+  float v = 0.f;
+  if (r < nrhs && k < K) {
+    const double2 x = X[r * K + k];
+    v = (col & 1) ? (float)(conj_x ? -x.y : x.y) : (float)x.x;
+  }
+  const u16 h = bf16_bits(v);
+  P[t] = h;
+  P[(long)ncp * kpad + t] = bf16_bits(v - bf16_val(h));
+}
+
+template <int NCT, bool CPLX>
+__global__ __launch_bounds__(256) void k_gemm_bf16x3(const u16* __restrict__ A, long rows_pad, long kpad,
+                                                     const u16* __restrict__ Xs, int ncp, long kslice,
+                                                     float* __restrict__ part) {
+  constexpr int NPL = CPLX ? 2 : 1;  // matrix planes pairs (Re, Im)
+  __shared__ u16 bs[2][NCT * 32][kLdsK];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long row0 = (long)blockIdx.x * kRowsWG + wave * 32;
+  const long k_begin = (long)blockIdx.y * kslice;
+  const long k_end = min(kpad, k_begin + kslice);
+  const long plane = rows_pad * kpad;
+  const long xplane = (long)ncp * kpad;
+
+  f32x16 acc[NPL][NCT];
+#pragma unroll
+  for (int p = 0; p < NPL; ++p)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[p][c][q] = 0.f;
+
+  const long my_row = row0 + (lane & 31);
+  const int khalf = (lane >> 5) * 32;
+  for (long k0 = k_begin; k0 < k_end; k0 += kKc) {
+    // stage X chunk: NCT*32 columns x 64 k, two planes; 16 B per store
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * NCT * 32 * (kKc / 8); e += 256) {
+      const int pl = e / (NCT * 32 * (kKc / 8));
+      const int rem = e % (NCT * 32 * (kKc / 8));
+      const int col = rem / (kKc / 8), kk = (rem % (kKc / 8)) * 8;
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(Xs + pl * xplane + (long)col * kpad + k0 + kk);
+      *reinterpret_cast<bf16x8*>(&bs[pl][col][kk]) = v;
+    }
+    __syncthreads();
+    // this lane's 32 contiguous k of its row, per matrix plane
+    bf16x8 a[2 * NPL][4];
+#pragma unroll
+    for (int p = 0; p < 2 * NPL; ++p) {
+      const bf16x8* src = reinterpret_cast<const bf16x8*>(A + p * plane + my_row * kpad + k0 + khalf);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[p][s] = __builtin_nontemporal_load(src + s);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      bf16x8 bh[NCT], bl[NCT];
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const int col = c * 32 + (lane & 31);
+        bh[c] = *reinterpret_cast<const bf16x8*>(&bs[0][col][khalf + 8 * s]);
+        bl[c] = *reinterpret_cast<const bf16x8*>(&bs[1][col][khalf + 8 * s]);
+      }
+      // three passes over independent accumulators (hi.hi, hi.lo, lo.hi)
+#pragma unroll
+      for (int p = 0; p < NPL; ++p)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c)
+          acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2 * p][s], bh[c], acc[p][c], 0, 0, 0);
+#pragma unroll
+      for (int p = 0; p < NPL; ++p)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c)
+          acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2 * p][s], bl[c], acc[p][c], 0, 0, 0);
+#pragma unroll
+      for (int p = 0; p < NPL; ++p)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c)
+          acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2 * p + 1][s], bh[c], acc[p][c], 0, 0, 0);
+    }
+  }
+  // partial[slice][p][row][col]
+#pragma unroll
+  for (int p = 0; p < NPL; ++p)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const long row = row0 + 8 * (q / 4) + (lane >> 5) * 4 + (q % 4);
+        const int col = c * 32 + (lane & 31);
+        part[(((long)blockIdx.y * NPL + p) * rows_pad + row) * ncp + col] = acc[p][c][q];
+      }
+}
+
+// Y[r][i] from the slice partials (fixed summation order, FP64):
+//   complex: re = P1[2r] - s P2[2r+1], im = P1[2r+1] + s P2[2r] (s = -1 for conj(M))
+//   real:    re = P1[2r], im = P1[2r+1]
+__global__ void k_gemm_combine(const float* __restrict__ part, int nslice, int npl, long rows_pad, int ncp,
+                               long n, int nrhs, int conj_m, double2* __restrict__ Y) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const long i = t % n, r = t / n;
+  double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
+  for (int s = 0; s < nslice; ++s) {
+    const float* b1 = part + (((long)s * npl + 0) * rows_pad + i) * ncp;
+    p1r += b1[2 * r];
+    p1i += b1[2 * r + 1];
+    if (npl == 2) {
+      const float* b2 = part + (((long)s * npl + 1) * rows_pad + i) * ncp;
+      p2r += b2[2 * r];
+      p2i += b2[2 * r + 1];
+    }
+  }
+  const double sg = conj_m ? -1.0 : 1.0;
+  Y[r * n + i] = make_double2(p1r - sg * p2i, p1i + sg * p2r);
+}
+
+}  // namespace
+
+rfcmp_status SplitMatrix::from_c64(const float2* M, int64_t n_, int64_t ld, hipStream_t s) {
+  n = n_;
+  cplx = true;
+  rows_pad = (int64_t)round_up(n, kRowsWG);
+  kpad = (int64_t)round_up(n, kKc);
+  RF_TRY(planes.alloc(sizeof(u16) * 4 * rows_pad * kpad));
+  const long tot = rows_pad * kpad;
+  hipLaunchKernelGGL(k_split_c64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, (long)n, (long)n,
+                     (long)ld, planes.as<u16>(), (long)rows_pad, (long)kpad);
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+
+rfcmp_status SplitMatrix::from_f64(const double* M, int64_t n_, int64_t ld, hipStream_t s) {
+  n = n_;
+  cplx = false;
+  rows_pad = (int64_t)round_up(n, kRowsWG);
+  kpad = (int64_t)round_up(n, kKc);
+  RF_TRY(planes.alloc(sizeof(u16) * 2 * rows_pad * kpad));
+  const long tot = rows_pad * kpad;
+  hipLaunchKernelGGL(k_split_f64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, (long)n, (long)ld,
+                     planes.as<u16>(), (long)rows_pad, (long)kpad);
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+
+size_t gemm_scratch_bytes(int64_t n, int nrhs) {
+  const int64_t rows_pad = (int64_t)round_up(n, kRowsWG), kpad = (int64_t)round_up(n, kKc);
+  const int nr = std::min(nrhs, 64);
+  const int ncp = (int)round_up(2 * nr, 32);
+  return round_up(sizeof(u16) * 2 * ncp * kpad, 256) + sizeof(float) * 16 * 2 * rows_pad * ncp + 1024;
+}
+
+rfcmp_status gemm_bf16x3(const SplitMatrix& M, bool conj_m, const double2* X, double2* Y, int nrhs, void* scratch,
+                         size_t scratch_bytes, hipStream_t s, const char* tag) {
+  const int64_t n = M.n;
+  for (int r0 = 0; r0 < nrhs; r0 += 64) {
+    const int nr = std::min(64, nrhs - r0);
+    const int ncp = (int)round_up(2 * nr, 32);
+    const int nct = ncp / 32;
+    const long nrb = (long)(M.rows_pad / kRowsWG);
+    // split K so that the grid holds about 512 workgroups
+    long nslice = std::max(1L, std::min(16L, (512 + nrb - 1) / nrb));
+    long kslice = (long)round_up((M.kpad + nslice - 1) / nslice, kKc);
+    nslice = (M.kpad + kslice - 1) / kslice;
+    const int npl = M.cplx ? 2 : 1;
+    const size_t xs_bytes = round_up(sizeof(u16) * 2 * ncp * M.kpad, 256);
+    const size_t need = xs_bytes + sizeof(float) * nslice * npl * M.rows_pad * ncp;
+    if (need > scratch_bytes) {
+      set_error("gemm_bf16x3: scratch of %zu bytes too small (%zu needed)", scratch_bytes, need);
+      return RFCMP_E_STATE;
+    }
+    u16* xs = static_cast<u16*>(scratch);
+    float* part = reinterpret_cast<float*>(static_cast<char*>(scratch) + xs_bytes);
+    ProfScope prof(tag, s);
+    const long xt = (long)ncp * M.kpad;
+    // conj(M) X = conj(M conj X) is handled in the combine; X is split as is
+    hipLaunchKernelGGL(k_split_x, dim3((unsigned)((xt + 255) / 256)), dim3(256), 0, s, X + (long)r0 * n, nr,
+                       (long)n, xs, ncp, (long)M.kpad, 0);
+    dim3 grid((unsigned)nrb, (unsigned)nslice);
+#define RF_GEMM(NCTV)                                                                                       \
+  if (M.cplx)                                                                                              \
+    hipLaunchKernelGGL((k_gemm_bf16x3<NCTV, true>), grid, dim3(256), 0, s, M.planes.as<u16>(),              \
+                       (long)M.rows_pad, (long)M.kpad, xs, ncp, kslice, part);                              \
+  else                                                                                                     \
+    hipLaunchKernelGGL((k_gemm_bf16x3<NCTV, false>), grid, dim3(256), 0, s, M.planes.as<u16>(),             \
+                       (long)M.rows_pad, (long)M.kpad, xs, ncp, kslice, part);
+    switch (nct) {
+      case 1: RF_GEMM(1) break;
+      case 2: RF_GEMM(2) break;
+      case 3: RF_GEMM(3) break;
+      default: RF_GEMM(4) break;
+    }
+#undef RF_GEMM
+    const long ot = (long)n * nr;
+    hipLaunchKernelGGL(k_gemm_combine, dim3((unsigned)((ot + 255) / 256)), dim3(256), 0, s, part, (int)nslice, npl,
+                       (long)M.rows_pad, ncp, (long)n, nr, conj_m ? 1 : 0, Y + (long)r0 * n);
+    RF_HIP(hipGetLastError());
+  }
+  return RFCMP_OK;
+}
+
+MeshDev::MeshDev() = default;
+MeshDev::~MeshDev() = default;
+
+}  // namespace rfcmp
+
+rfcmp_op_s::rfcmp_op_s() = default;
+rfcmp_op_s::~rfcmp_op_s() = default;

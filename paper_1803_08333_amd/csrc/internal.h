@@ -108,6 +108,8 @@ struct MeshHost {
   std::vector<int32_t> cell_nb_idx;
 };
 
+struct SplitMatrix;  // BF16x3 planes of a matrix (gemm.h)
+
 // Device copies and the dense FP64 projector matrices of one mesh.
 struct MeshDev {
   bool ready = false;
@@ -127,6 +129,9 @@ struct MeshDev {
   DevBuf Lp;         // double [ldL][ldL]: (Sigma^T Sigma)^+
   DevBuf Gll_inv;    // double [ldG][ldG]
   DevBuf Gtp_inv;    // double [ldT][ldT]
+  std::unique_ptr<SplitMatrix> Lp16, Gll16, Gtp16;  // BF16x3 planes, built on demand
+  MeshDev();
+  ~MeshDev();
 };
 
 }  // namespace rfcmp
@@ -138,6 +143,8 @@ struct rfcmp_mesh_s {
 };
 
 struct rfcmp_op_s {
+  rfcmp_op_s();
+  ~rfcmp_op_s();
   rfcmp_mesh mesh = nullptr;
   double k = 0;
   rfcmp_options opt{};
@@ -146,10 +153,11 @@ struct rfcmp_op_s {
   int64_t ldA = 0, ldV = 0;  // leading dims (complex entries) of T_A and V
   rfcmp::DevBuf TA;          // float2 [N][ldA]
   rfcmp::DevBuf Vb;          // float2 [C][ldV]
-  rfcmp::DevBuf work;        // complex128 workspace
+  rfcmp::DevBuf work;        // complex128 workspace for work_nrhs right-hand sides
   int work_nrhs = 0;
-  rfcmp::DevBuf scal;        // device scalars (doubles)
-  double* host_scal = nullptr;  // pinned
+  double* host_scal = nullptr;  // pinned, 16 + 8 * work_nrhs doubles
+  std::unique_ptr<rfcmp::SplitMatrix> TA16, V16;  // BF16x3 planes (precision 1)
+  rfcmp::DevBuf gemm_scratch;
 };
 
 namespace rfcmp {

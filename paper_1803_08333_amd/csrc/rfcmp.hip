@@ -21,6 +21,7 @@
 #include <cstring>
 #include <tuple>
 
+#include "gemm.h"
 #include "vecops.h"
 
 namespace rfcmp {
@@ -28,143 +29,209 @@ const char* last_error();
 
 namespace {
 
-constexpr int kR = 4;  // right-hand sides per batched operator pass
-
+// ------------------------------------------------------------------ workspace
+// Complex128 scratch of one operator for R right-hand sides per pass.
 struct Work {
-  double2 *nA, *nB, *nC, *nD;                  // [kR][N]
-  double2* c[14];                              // [kR][C]
-  double2 *v1, *v2;                            // [kR][V]
-  double2 *m1, *m2, *m3;                       // [kR] means
-  double2 *part, *dout;                        // reductions
-  double2 *cx, *cr, *cp, *cq, *cb;             // CG [N]
-  double2 *pv, *pw;                            // power iteration [3][N]
+  int R = 0;
+  double2 *nA, *nB, *nC, *nD;        // [R][N]
+  double2* c[14];                    // [R][C]
+  double2 *v1, *v2;                  // [R][V]
+  double2 *m1, *m2, *m3;             // [R] means
+  double2 *part, *dout;              // reductions
+  double2 *x, *r, *p, *q, *b, *d, *b0;  // block CG vectors [R][N]
+  double2 *pv, *pw;                  // power iteration [3][N]
+  double *rho, *pq;                  // device CG scalars: rho[2][R], pq[R]
+  int* active;                       // [R]
 };
 
-size_t work_bytes(int64_t N, int64_t C, int64_t V) {
-  const size_t z = sizeof(double2);
-  return z * (4 * kR * N + 14 * kR * C + 2 * kR * V + 3 * kR + (dot_partials() + 1) * kR + 5 * N + 6 * N) + 4096;
+size_t work_doubles2(int64_t N, int64_t C, int64_t V, int R) {
+  return (size_t)(4 * R * N + 14 * R * C + 2 * R * V + 3 * R + (dot_partials() + 1) * R + 7 * R * N + 6 * N +
+                  2 * R + 2 * R);
 }
 
 Work carve(rfcmp_op op) {
   const MeshHost& h = op->mesh->h;
   const int64_t N = h.N, C = h.C, V = h.V;
+  const int R = op->work_nrhs;
   double2* p = op->work.as<double2>();
   Work w;
+  w.R = R;
   auto take = [&](int64_t n) {
     double2* q = p;
     p += n;
     return q;
   };
-  w.nA = take(kR * N); w.nB = take(kR * N); w.nC = take(kR * N); w.nD = take(kR * N);
-  for (auto& c : w.c) c = take(kR * C);
-  w.v1 = take(kR * V); w.v2 = take(kR * V);
-  w.m1 = take(kR); w.m2 = take(kR); w.m3 = take(kR);
-  w.part = take((int64_t)dot_partials() * kR);
-  w.dout = take(kR);
-  w.cx = take(N); w.cr = take(N); w.cp = take(N); w.cq = take(N); w.cb = take(N);
+  w.nA = take(R * N); w.nB = take(R * N); w.nC = take(R * N); w.nD = take(R * N);
+  for (auto& c : w.c) c = take(R * C);
+  w.v1 = take(R * V); w.v2 = take(R * V);
+  w.m1 = take(R); w.m2 = take(R); w.m3 = take(R);
+  w.part = take((int64_t)dot_partials() * R);
+  w.dout = take(R);
+  w.x = take(R * N); w.r = take(R * N); w.p = take(R * N); w.q = take(R * N); w.b = take(R * N); w.d = take(R * N);
+  w.b0 = take(R * N);
   w.pv = take(3 * N); w.pw = take(3 * N);
+  w.rho = reinterpret_cast<double*>(take(R));     // 2R doubles
+  w.pq = reinterpret_cast<double*>(take(R / 2 + 1));
+  w.active = reinterpret_cast<int*>(take(R / 4 + 1));
   return w;
 }
+
+// Grow the workspace (and pinned host scalars) to at least R right-hand sides.
+rfcmp_status ensure_work(rfcmp_op op, int R) {
+  R = std::max(R, 4);
+  if (op->work.p && op->work_nrhs >= R) return RFCMP_OK;
+  const MeshHost& h = op->mesh->h;
+  RF_HIP(hipDeviceSynchronize());  // the old workspace may still be in use by queued work
+  RF_TRY(op->work.alloc(sizeof(double2) * work_doubles2(h.N, h.C, h.V, R) + 4096));
+  op->work_nrhs = R;
+  if (op->host_scal) (void)hipHostFree(op->host_scal);
+  op->host_scal = nullptr;
+  RF_HIP(hipHostMalloc((void**)&op->host_scal, sizeof(double) * (16 + 8 * R), hipHostMallocDefault));
+  return RFCMP_OK;
+}
+
+// ------------------------------------------------------------------ dense products
+// The five dense products of the operator, in complex64/FP64 (FP64
+// accumulation, <= 4 right-hand sides per matrix pass) or as BF16x3 MFMA
+// products (<= 64 right-hand sides per pass).
+struct Dense {
+  rfcmp_op op;
+  hipStream_t s;
+  bool bf16;
+  rfcmp_status ta(bool conj, const double2* x, double2* y, int nr) const {
+    if (bf16)
+      return gemm_bf16x3(*op->TA16, conj, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_ta");
+    return cmatvec(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj, x, y, nr, s, "cmatvec_ta");
+  }
+  rfcmp_status v(bool conj, const double2* x, double2* y, int nr) const {
+    if (bf16)
+      return gemm_bf16x3(*op->V16, conj, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_v");
+    return cmatvec(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj, x, y, nr, s, "cmatvec_v");
+  }
+  rfcmp_status lp(const double2* x, double2* y, int nr) const {
+    const MeshDev& d = op->mesh->d;
+    if (bf16)
+      return gemm_bf16x3(*d.Lp16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_lp");
+    return dmatvec(d.Lp.as<double>(), op->mesh->h.C, d.ldL, x, y, nr, s, "dmatvec_lp");
+  }
+  rfcmp_status gll(const double2* x, double2* y, int nr) const {
+    const MeshDev& d = op->mesh->d;
+    if (bf16)
+      return gemm_bf16x3(*d.Gll16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_gll");
+    return dmatvec(d.Gll_inv.as<double>(), op->mesh->h.V, d.ldG, x, y, nr, s, "dmatvec_gll");
+  }
+  rfcmp_status gtp(const double2* x, double2* y, int nr) const {
+    const MeshDev& d = op->mesh->d;
+    if (bf16)
+      return gemm_bf16x3(*d.Gtp16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_gtp");
+    return dmatvec(d.Gtp_inv.as<double>(), op->mesh->h.C, d.ldT, x, y, nr, s, "dmatvec_gtp");
+  }
+};
 
 bool use_gsigma(rfcmp_op op) { return op->opt.outer_star == 1; }
 
 // Left half: y = sgn * P_o^H T^H w for w in W.nC with Sig^T w_S in W.c[8].
-rfcmp_status left_half(rfcmp_op op, const Work& W, double2* y, int nr, double sgn, hipStream_t s) {
+rfcmp_status left_half(const Dense& D, const Work& W, double2* y, int nr, double sgn) {
+  rfcmp_op op = D.op;
+  hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
   const int64_t N = h.N, C = h.C;
   const double k = op->k, al = op->alpha, be = op->beta;
   double2 *t5 = W.c[9], *s4 = W.c[10], *vw = W.c[11], *t6 = W.c[12], *g6 = W.c[13];
-  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, true, W.nC, W.nD, nr, s, "cmatvec_ta"));      // zA
-  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, true, W.c[8], vw, nr, s, "cmatvec_v"));      // vw
+  RF_TRY(D.ta(true, W.nC, W.nD, nr));  // zA
+  RF_TRY(D.v(true, W.c[8], vw, nr));   // vw
   RF_TRY(sigma_t(d, C, N, W.nD, t5, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t5, s4, nr, s, "dmatvec_lp"));
+  RF_TRY(D.lp(t5, s4, nr));
   RF_TRY(mean(C, vw, W.m3, nr, s));
   RF_TRY(comb_c(C, nullptr, -sgn * (k / be), s4, sgn / (k * be), vw, W.m3, t6, nr, s));
   const double2* gsel = t6;
   if (use_gsigma(op)) {
-    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, t6, g6, nr, s, "dmatvec_gtp"));
+    RF_TRY(D.gtp(t6, g6, nr));
     gsel = g6;
   }
-  RF_TRY(left_y(d, N, C, sgn * k / al, W.nD, s4, gsel, y, nr, s));
-  return RFCMP_OK;
+  return left_y(d, N, C, sgn * k / al, W.nD, s4, gsel, y, nr, s);
 }
 
-// y = A x for nr <= kR right-hand sides.
-rfcmp_status apply_batch(rfcmp_op op, const double2* x, double2* y, int nr, hipStream_t s) {
+// y = A x for nr <= W.R right-hand sides.
+rfcmp_status apply_batch(const Dense& D, const Work& W, const double2* x, double2* y, int nr) {
+  rfcmp_op op = D.op;
+  hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
   const int64_t N = h.N, C = h.C, V = h.V;
   const double k = op->k, al = op->alpha, be = op->beta, ga = op->gamma;
-  const Work W = carve(op);
   double2 *t1 = W.c[0], *s1 = W.c[1], *g1 = W.c[2], *s1g = W.c[3], *vphi = W.c[4], *t2 = W.c[5],
           *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8], *s3 = W.c[9];
   RF_TRY(sigma_t(d, C, N, x, t1, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t1, s1, nr, s, "dmatvec_lp"));
+  RF_TRY(D.lp(t1, s1, nr));
   const double2* sus = t1;   // Sig^T u_S
   const double2* s_us = s1;  // u_S = Sig s_us
   if (use_gsigma(op)) {
-    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, t1, g1, nr, s, "dmatvec_gtp"));
-    RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, g1, s1g, nr, s, "dmatvec_lp"));
+    RF_TRY(D.gtp(t1, g1, nr));
+    RF_TRY(D.lp(g1, s1g, nr));
     sus = g1;
     s_us = s1g;
   }
   RF_TRY(vin(d, N, C, k / al, k / be, x, s1, s_us, W.nA, nr, s));
-  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, false, W.nA, W.nB, nr, s, "cmatvec_ta"));   // a
-  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, false, sus, vphi, nr, s, "cmatvec_v"));     // vphi
+  RF_TRY(D.ta(false, W.nA, W.nB, nr));   // a
+  RF_TRY(D.v(false, sus, vphi, nr));     // vphi
   RF_TRY(sigma_t(d, C, N, W.nB, t2, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t2, s2, nr, s, "dmatvec_lp"));
+  RF_TRY(D.lp(t2, s2, nr));
   RF_TRY(lambda_t(d, V, N, W.nB, W.v1, nr, s));
-  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, nr, s, "dmatvec_gll"));
+  RF_TRY(D.gll(W.v1, W.v2, nr));
   RF_TRY(mean(C, vphi, W.m1, nr, s));
   RF_TRY(comb_c(C, d.area.as<double>(), 1.0, s2, 1.0 / (k * be), vphi, W.m1, t4, nr, s));
-  // s3 lives in c[9]: written before left_half reuses that slot as t5
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t4, s3, nr, s, "dmatvec_lp"));
+  // s3 lives in c[9]: consumed by middle_w before left_half reuses that slot
+  RF_TRY(D.lp(t4, s3, nr));
   RF_TRY(middle_w(d, N, C, V, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be), W.v2, W.nB, s2, s3, W.nC, nr, s));
   RF_TRY(mean(C, t4, W.m2, nr, s));
   RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0 / (be * be), t4, W.m2, sw, nr, s));
-  return left_half(op, W, y, nr, 1.0, s);
+  return left_half(D, W, y, nr, 1.0);
 }
 
-rfcmp_status rhs_batch(rfcmp_op op, const double2* e, double2* b, int nr, hipStream_t s) {
+rfcmp_status rhs_batch(const Dense& D, const Work& W, const double2* e, double2* b, int nr) {
+  rfcmp_op op = D.op;
+  hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
   const int64_t N = h.N, C = h.C, V = h.V;
   const double al = op->alpha, be = op->beta, ga = op->gamma;
-  const Work W = carve(op);
   double2 *t2 = W.c[5], *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8], *s3 = W.c[9];
   RF_TRY(sigma_t(d, C, N, e, t2, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t2, s2, nr, s, "dmatvec_lp"));
+  RF_TRY(D.lp(t2, s2, nr));
   RF_TRY(lambda_t(d, V, N, e, W.v1, nr, s));
-  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, nr, s, "dmatvec_gll"));
+  RF_TRY(D.gll(W.v1, W.v2, nr));
   RF_TRY(comb_c(C, d.area.as<double>(), 1.0, s2, 0.0, nullptr, nullptr, t4, nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, t4, s3, nr, s, "dmatvec_lp"));
+  RF_TRY(D.lp(t4, s3, nr));
   RF_TRY(middle_w(d, N, C, V, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be), W.v2, e, s2, s3, W.nC, nr, s));
   RF_TRY(mean(C, t4, W.m2, nr, s));
   RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0 / (be * be), t4, W.m2, sw, nr, s));
-  return left_half(op, W, b, nr, -1.0, s);
+  return left_half(D, W, b, nr, -1.0);
 }
 
-rfcmp_status recover_batch(rfcmp_op op, const double2* x, double2* j, int nr, hipStream_t s) {
+rfcmp_status recover_batch(const Dense& D, const Work& W, const double2* x, double2* j, int nr) {
+  rfcmp_op op = D.op;
+  hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
   const int64_t N = h.N, C = h.C;
-  const Work W = carve(op);
   RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, s, "dmatvec_lp"));
+  RF_TRY(D.lp(W.c[0], W.c[1], nr));
   const double2* sg = W.c[1];
   if (use_gsigma(op)) {
-    RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, s, "dmatvec_gtp"));
-    RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[3], nr, s, "dmatvec_lp"));
+    RF_TRY(D.gtp(W.c[0], W.c[2], nr));
+    RF_TRY(D.lp(W.c[2], W.c[3], nr));
     sg = W.c[3];
   }
   return recover_j(d, N, C, 1.0 / op->alpha, 1.0 / op->beta, x, W.c[1], sg, j, nr, s);
 }
 
+// Run f over chunks of at most W.R right-hand sides.
 template <class F>
-rfcmp_status batched(int nrhs, int64_t nin, int64_t nout, const double2* x, double2* y, F f) {
-  for (int r0 = 0; r0 < nrhs; r0 += kR) {
-    const int nr = std::min(kR, nrhs - r0);
+rfcmp_status batched(int nrhs, int R, int64_t nin, int64_t nout, const double2* x, double2* y, F f) {
+  for (int r0 = 0; r0 < nrhs; r0 += R) {
+    const int nr = std::min(R, nrhs - r0);
     RF_TRY(f(x + (int64_t)r0 * nin, y + (int64_t)r0 * nout, nr));
   }
   return RFCMP_OK;
@@ -176,48 +243,52 @@ rfcmp_status batched(int nrhs, int64_t nin, int64_t nout, const double2* x, doub
 //   O_gamma v = P_LH conj(T_A) P_LH T_A P_LH v
 //   O_beta  v = P_Sigma T_Phi^H P_mS_hat T_Phi P_Sigma v
 //             = Sig conj(V) (I - J) diag(A) (I - J) V Sig^T v
-rfcmp_status power_apply(rfcmp_op op, const Work& W, hipStream_t s) {
+rfcmp_status power_apply(const Dense& D, const Work& W) {
+  rfcmp_op op = D.op;
+  hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
   const int64_t N = h.N, C = h.C, V = h.V;
   double2* va = W.pv;
   double2* vb = W.pv + 2 * N;
   RF_TRY(sigma_t(d, C, N, va, W.c[0], 2, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], 2, s, "dmatvec_lp"));
+  RF_TRY(D.lp(W.c[0], W.c[1], 2));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, va, -1.0, W.c[1], W.nA, 2, s));          // P_LH v
-  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, false, W.nA, W.nB, 2, s, "cmatvec_ta"));
+  RF_TRY(D.ta(false, W.nA, W.nB, 2));
   RF_TRY(lambda_t(d, V, N, W.nB, W.v1, 1, s));
-  RF_TRY(dmatvec(d.Gll_inv.as<double>(), V, d.ldG, W.v1, W.v2, 1, s, "dmatvec_gll"));
+  RF_TRY(D.gll(W.v1, W.v2, 1));
   RF_TRY(lambda_n(d, N, V, W.v2, W.nC, 1, s));                                   // alpha branch
   RF_TRY(sigma_t(d, C, N, W.nB + N, W.c[2], 1, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[3], 1, s, "dmatvec_lp"));
+  RF_TRY(D.lp(W.c[2], W.c[3], 1));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nB + N, -1.0, W.c[3], W.nC + N, 1, s));  // gamma branch
-  RF_TRY(cmatvec(op->TA.as<float2>(), N, op->ldA, true, W.nC, W.nD, 2, s, "cmatvec_ta"));
+  RF_TRY(D.ta(true, W.nC, W.nD, 2));
   RF_TRY(sigma_t(d, C, N, W.nD, W.c[4], 2, s));
-  RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[4], W.c[5], 2, s, "dmatvec_lp"));
+  RF_TRY(D.lp(W.c[4], W.c[5], 2));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nD, -1.0, W.c[5], W.pw, 2, s));
   // beta
   RF_TRY(sigma_t(d, C, N, vb, W.c[6], 1, s));
-  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, false, W.c[6], W.c[7], 1, s, "cmatvec_v"));
+  RF_TRY(D.v(false, W.c[6], W.c[7], 1));
   RF_TRY(mean(C, W.c[7], W.m1, 1, s));
   RF_TRY(comb_c(C, d.area.as<double>(), 0.0, nullptr, 1.0, W.c[7], W.m1, W.c[8], 1, s));
   RF_TRY(mean(C, W.c[8], W.m2, 1, s));
   RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0, W.c[8], W.m2, W.c[9], 1, s));
-  RF_TRY(cmatvec(op->Vb.as<float2>(), C, op->ldV, true, W.c[9], W.c[10], 1, s, "cmatvec_v"));
+  RF_TRY(D.v(true, W.c[9], W.c[10], 1));
   RF_TRY(axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[10], W.pw + 2 * N, 1, s));
   return RFCMP_OK;
 }
 
 rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStream_t s) {
   const int64_t N = op->mesh->h.N;
+  RF_TRY(ensure_work(op, 4));
   const Work W = carve(op);
+  const Dense D{op, s, false};
   for (int r = 0; r < 3; ++r)
     RF_HIP(hipMemcpyAsync(W.pw + r * N, start, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
   for (int it = 0; it < steps; ++it) {
     RF_TRY(dot(N, W.pw, W.pw, W.part, W.dout, 3, s));
     RF_HIP(hipMemcpyAsync(W.pv, W.pw, sizeof(double2) * 3 * N, hipMemcpyDeviceToDevice, s));
     RF_TRY(normalize(N, W.dout, W.pv, 3, s));
-    RF_TRY(power_apply(op, W, s));
+    RF_TRY(power_apply(D, W));
   }
   RF_TRY(dot(N, W.pw, W.pw, W.part, W.dout, 3, s));
   double2 nr2[3];
@@ -238,76 +309,165 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStr
   return RFCMP_OK;
 }
 
-// Complex CG on the HPD system for one right-hand side.
-rfcmp_status cg_one(rfcmp_op op, const double2* e, double2* j, double tol, int maxit, hipStream_t s,
-                    rfcmp_info* info) {
+// ------------------------------------------------------------------ CG
+// Block of nr independent complex CGs on the HPD system (Sec. 3.4) sharing
+// the operator passes: solves A x = W.b from x = 0 (x in W.x), stopping
+// right-hand side r once its recursive residual norm is <= target[r] (it is
+// then frozen: step length 0), or after maxit iterations.  The CG scalars
+// stay on the device; the host examines iteration i while iteration i+1 runs
+// (pinned copies and events), so the GPU never waits for the test.  iters[r]
+// counts the iterations in which r was still active.
+rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* target, int maxit, int* iters) {
+  rfcmp_op op = D.op;
+  hipStream_t s = D.s;
   const int64_t N = op->mesh->h.N;
-  const Work W = carve(op);
-  double* sc = op->scal.as<double>();  // slots: 0/1 rho ping-pong, 2 pq
-  double* hs = op->host_scal;
-  RF_TRY(rhs_batch(op, e, W.cb, 1, s));
-  RF_TRY(dot(N, W.cb, W.cb, W.part, W.dout, 1, s));
-  RF_HIP(hipMemcpyAsync(hs, W.dout, sizeof(double2), hipMemcpyDeviceToHost, s));
-  RF_HIP(hipStreamSynchronize(s));
-  const double bn = std::sqrt(hs[0]);
-  RF_HIP(hipMemsetAsync(W.cx, 0, sizeof(double2) * N, s));
-  if (!(bn > 0)) {
-    RF_HIP(hipMemsetAsync(j, 0, sizeof(double2) * N, s));
-    if (info) *info = rfcmp_info{0, 0, 0.0, 0.0};
-    return RFCMP_OK;
-  }
-  RF_HIP(hipMemcpyAsync(W.cr, W.cb, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
-  int it = 0, restarts = -1;
-  double rel = 1.0;
-  rfcmp_status st = RFCMP_OK;
-  while (true) {
-    ++restarts;
-    RF_HIP(hipMemcpyAsync(W.cp, W.cr, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
-    RF_TRY(dot(N, W.cr, W.cr, W.part, W.dout, 1, s));
-    RF_TRY(take_real(W.dout, sc, 0, s));
-    int cur = 0;
-    while (it < maxit) {
-      RF_TRY(apply_batch(op, W.cp, W.cq, 1, s));
-      RF_TRY(dot(N, W.cp, W.cq, W.part, W.dout, 1, s));
-      RF_TRY(take_real(W.dout, sc, 2, s));
-      RF_TRY(cg_xr(N, sc, cur, W.cx, W.cr, W.cp, W.cq, s));
-      const int nxt = 1 - cur;
-      RF_TRY(dot(N, W.cr, W.cr, W.part, W.dout, 1, s));
-      RF_TRY(take_real(W.dout, sc, nxt, s));
-      RF_HIP(hipMemcpyAsync(hs, sc, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
-      RF_HIP(hipStreamSynchronize(s));
-      ++it;
-      const double pq = hs[2], rho = hs[nxt];
-      if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rho)) {
-        set_error("CG breakdown at iteration %d: p^H A p = %g", it, pq);
-        st = RFCMP_E_BREAKDOWN;
-        break;
-      }
-      if (std::sqrt(rho) / bn <= tol) break;
-      RF_TRY(cg_p(N, sc, cur, nxt, W.cr, W.cp, s));
-      cur = nxt;
+  const int64_t NR = (int64_t)nr * N;
+  double* hs = op->host_scal;  // per parity p: rho_new at 4Rp, pq at 4Rp + R; active flags at 6R
+  const int R = W.R;
+  std::vector<int> act(nr, 1);
+  for (int r = 0; r < nr; ++r) iters[r] = 0;
+  RF_HIP(hipMemsetAsync(W.x, 0, sizeof(double2) * NR, s));
+  RF_HIP(hipMemcpyAsync(W.r, W.b, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
+  RF_HIP(hipMemcpyAsync(W.p, W.b, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
+  RF_TRY(set_active(W.active, 1, nr, s));
+  RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, s));
+  RF_TRY(take_real_n(W.dout, W.rho, nr, s));  // rho[0][r]
+  hipEvent_t ev[2];
+  RF_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  RF_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
     }
-    if (st < 0) break;
-    // true residual of the (stored) operator, FP64-accumulated
-    RF_TRY(apply_batch(op, W.cx, W.cq, 1, s));
-    RF_TRY(vsub(N, W.cb, W.cq, W.cr, s));
-    RF_TRY(dot(N, W.cr, W.cr, W.part, W.dout, 1, s));
-    RF_HIP(hipMemcpyAsync(hs, W.dout, sizeof(double2), hipMemcpyDeviceToHost, s));
+  } guard{ev};
+  int cur = 0, it = 0, last_checked = -1, nactive = nr;
+  while (true) {
+    bool issued = false;
+    if (it < maxit && nactive > 0) {
+      const int slot = it & 1;
+      RF_TRY(apply_batch(D, W, W.p, W.q, nr));
+      RF_TRY(dot(N, W.p, W.q, W.part, W.dout, nr, s));
+      RF_TRY(take_real_n(W.dout, W.pq, nr, s));
+      RF_TRY(cg_xr_blk(N, nr, W.rho + cur * R, W.pq, W.active, W.x, W.r, W.p, W.q, s));
+      const int nxt = 1 - cur;
+      RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, s));
+      RF_TRY(take_real_n(W.dout, W.rho + nxt * R, nr, s));
+      RF_HIP(hipMemcpyAsync(hs + slot * 4 * R, W.rho + nxt * R, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+      RF_HIP(hipMemcpyAsync(hs + slot * 4 * R + R, W.pq, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+      RF_HIP(hipEventRecord(ev[slot], s));
+      RF_TRY(cg_p_blk(N, nr, W.rho + nxt * R, W.rho + cur * R, W.active, W.r, W.p, s));
+      cur = nxt;
+      ++it;
+      for (int r = 0; r < nr; ++r) iters[r] += act[r];
+      issued = true;
+    }
+    const int look = issued ? it - 2 : it - 1;
+    if (look <= last_checked) {
+      if (!issued) break;
+      continue;
+    }
+    RF_HIP(hipEventSynchronize(ev[look & 1]));
+    last_checked = look;
+    const double* h = hs + (look & 1) * 4 * R;
+    bool changed = false;
+    for (int r = 0; r < nr; ++r) {
+      if (!act[r]) continue;
+      const double rho = h[r], pq = h[R + r];
+      if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rho)) {
+        set_error("CG breakdown at iteration %d (rhs %d): p^H A p = %g", look + 1, r, pq);
+        return RFCMP_E_BREAKDOWN;
+      }
+      if (std::sqrt(rho) <= target[r]) {
+        act[r] = 0;
+        --nactive;
+        changed = true;
+      }
+    }
+    if (changed) {
+      // freeze converged right-hand sides from the next enqueued iteration on
+      int* ha = reinterpret_cast<int*>(hs + 6 * R);
+      for (int r = 0; r < nr; ++r) ha[r] = act[r];
+      RF_HIP(hipMemcpyAsync(W.active, ha, sizeof(int) * nr, hipMemcpyHostToDevice, s));
+      RF_HIP(hipStreamSynchronize(s));  // ha is reused by the next change
+    }
+    if (nactive == 0 || !issued) break;
+  }
+  return RFCMP_OK;
+}
+
+// Solve for nr <= W.R right-hand sides e (device) into j:
+//   precision 0: block CG on the complex64/FP64 operator to |r| <= tol |b|,
+//                restarted from the true residual until that meets tol too;
+//   precision 1: iterative refinement: inner block CG on the BF16x3 operator
+//                to 1e-4 of the current residual, i += d, true residual
+//                r = b - A i with the complex64/FP64 operator, until
+//                |r| <= tol |b|.
+rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, double tol, int maxit, hipStream_t s,
+                         rfcmp_info* info) {
+  const int64_t N = op->mesh->h.N;
+  const int64_t NR = (int64_t)nr * N;
+  const Work W = carve(op);
+  const Dense D64{op, s, false};
+  const Dense D16{op, s, true};
+  const bool split = op->opt.precision == 1;
+  RF_TRY(rhs_batch(D64, W, e, W.b0, nr));
+  RF_HIP(hipMemcpyAsync(W.b, W.b0, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
+  RF_HIP(hipMemsetAsync(W.d, 0, sizeof(double2) * NR, s));  // accumulated solution
+  RF_TRY(dot(N, W.b, W.b, W.part, W.dout, nr, s));
+  std::vector<double2> hd(nr);
+  RF_HIP(hipMemcpyAsync(hd.data(), W.dout, sizeof(double2) * nr, hipMemcpyDeviceToHost, s));
+  RF_HIP(hipStreamSynchronize(s));
+  std::vector<double> bn(nr), res(nr), target(nr), rel(nr, 1.0);
+  for (int r = 0; r < nr; ++r) res[r] = bn[r] = std::sqrt(hd[r].x);
+  std::vector<int> its(nr, 0), tot(nr, 0), rst(nr, -1);
+  rfcmp_status st = RFCMP_OK;
+  bool zero = true;
+  for (int r = 0; r < nr; ++r) zero &= !(bn[r] > 0);
+  for (int round = 0; round < 40 && !zero; ++round) {
+    for (int r = 0; r < nr; ++r)
+      target[r] = split ? std::max(1e-4 * res[r], 0.5 * tol * bn[r]) : tol * bn[r];
+    int budget = maxit;
+    for (int r = 0; r < nr; ++r) budget = std::min(budget, maxit - tot[r]);
+    if (budget <= 0) {
+      st = RFCMP_W_NOT_CONVERGED;
+      break;
+    }
+    RF_TRY(block_cg(split ? D16 : D64, W, nr, target.data(), budget, its.data()));
+    for (int r = 0; r < nr; ++r) {
+      tot[r] += its[r];
+      rst[r] += 1;
+    }
+    RF_TRY(vadd_to(NR, W.x, W.d, s));
+    // true residual of the stored operator, FP64-accumulated
+    RF_TRY(apply_batch(D64, W, W.d, W.q, nr));
+    RF_TRY(vsub(NR, W.b0, W.q, W.b, s));
+    RF_TRY(dot(N, W.b, W.b, W.part, W.dout, nr, s));
+    RF_HIP(hipMemcpyAsync(hd.data(), W.dout, sizeof(double2) * nr, hipMemcpyDeviceToHost, s));
     RF_HIP(hipStreamSynchronize(s));
-    rel = std::sqrt(hs[0]) / bn;
-    if (rel <= tol) break;
-    if (it >= maxit || restarts >= 20) {
+    bool all = true, exhausted = false;
+    for (int r = 0; r < nr; ++r) {
+      res[r] = std::sqrt(hd[r].x);
+      rel[r] = bn[r] > 0 ? res[r] / bn[r] : 0.0;
+      if (!(rel[r] <= tol)) {
+        all = false;
+        exhausted |= tot[r] >= maxit;
+      }
+    }
+    if (all) break;
+    if (exhausted || round == 39) {
       st = RFCMP_W_NOT_CONVERGED;
       break;
     }
   }
-  if (info) {
-    info->iters = it;
-    info->restarts = restarts;
-    info->rel_residual = rel;
-  }
-  if (st < 0) return st;
-  RF_TRY(recover_batch(op, W.cx, j, 1, s));
+  if (info)
+    for (int r = 0; r < nr; ++r) {
+      info[r].iters = tot[r];
+      info[r].restarts = std::max(rst[r], 0);
+      info[r].rel_residual = zero ? 0.0 : rel[r];
+    }
+  RF_TRY(recover_batch(D64, W, W.d, j, nr));
   return st;
 }
 
@@ -319,6 +479,32 @@ rfcmp_status ensure_mesh_device(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
   } else if (need_gtp && !m->d.has_gtp) {
     RF_TRY(mesh_projectors(m, true, s));
   }
+  return RFCMP_OK;
+}
+
+// BF16x3 planes of the operator's blocks and of the mesh's projector matrices.
+rfcmp_status ensure_split(rfcmp_op op, hipStream_t s) {
+  rfcmp_mesh m = op->mesh;
+  MeshDev& d = m->d;
+  const MeshHost& h = m->h;
+  if (!d.Lp16) {
+    d.Lp16 = std::make_unique<SplitMatrix>();
+    RF_TRY(d.Lp16->from_f64(d.Lp.as<double>(), h.C, d.ldL, s));
+    d.Gll16 = std::make_unique<SplitMatrix>();
+    RF_TRY(d.Gll16->from_f64(d.Gll_inv.as<double>(), h.V, d.ldG, s));
+  }
+  if (d.has_gtp && !d.Gtp16) {
+    d.Gtp16 = std::make_unique<SplitMatrix>();
+    RF_TRY(d.Gtp16->from_f64(d.Gtp_inv.as<double>(), h.C, d.ldT, s));
+  }
+  if (!op->TA16) {
+    op->TA16 = std::make_unique<SplitMatrix>();
+    RF_TRY(op->TA16->from_c64(op->TA.as<float2>(), h.N, op->ldA, s));
+    op->V16 = std::make_unique<SplitMatrix>();
+    RF_TRY(op->V16->from_c64(op->Vb.as<float2>(), h.C, op->ldV, s));
+  }
+  const size_t need = gemm_scratch_bytes(std::max(h.N, std::max(h.C, h.V)), 64);
+  if (op->gemm_scratch.bytes < need) RF_TRY(op->gemm_scratch.alloc(need));
   return RFCMP_OK;
 }
 
@@ -476,16 +662,17 @@ rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt, c
   const int64_t N = m->h.N, C = m->h.C, V = m->h.V;
   op->ldA = (int64_t)round_up(N, 64);
   op->ldV = (int64_t)round_up(C, 64);
+  (void)V;
   RF_TRY(op->TA.alloc(sizeof(float2) * N * op->ldA));
   RF_TRY(op->Vb.alloc(sizeof(float2) * C * op->ldV));
-  RF_TRY(op->work.alloc(work_bytes(N, C, V)));
-  RF_TRY(op->scal.alloc(sizeof(double) * 8));
-  RF_HIP(hipHostMalloc((void**)&op->host_scal, sizeof(double) * 8, hipHostMallocDefault));
+  RF_TRY(ensure_work(op.get(), 4));
   RF_TRY(assemble_blocks(op.get(), s));
   op->alpha = std::sqrt(k);
   op->beta = 1.0 / std::sqrt(k);
   op->gamma = k;
   if (o.scaling == 0) RF_TRY(power_scalings(op.get(), static_cast<const double2*>(power_start), o.power_iters, s));
+  if (o.precision == 1) RF_TRY(ensure_split(op.get(), s));
+  RF_HIP(hipStreamSynchronize(s));
   *out = op.release();
   return RFCMP_OK;
 }
@@ -546,8 +733,11 @@ rfcmp_status rfcmp_precond_rhs(rfcmp_op op, const void* e, void* b, int32_t nrhs
   RF_ARG(nrhs > 0, "nrhs must be > 0");
   const int64_t N = op->mesh->h.N;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return batched(nrhs, N, N, static_cast<const double2*>(e), static_cast<double2*>(b),
-                 [&](const double2* x, double2* y, int nr) { return rhs_batch(op, x, y, nr, s); });
+  RF_TRY(ensure_work(op, std::min(nrhs, 64)));
+  const Work W = carve(op);
+  const Dense D{op, s, false};
+  return batched(nrhs, W.R, N, N, static_cast<const double2*>(e), static_cast<double2*>(b),
+                 [&](const double2* x, double2* y, int nr) { return rhs_batch(D, W, x, y, nr); });
 }
 
 rfcmp_status rfcmp_apply(rfcmp_op op, const void* x, void* y, int32_t nrhs, void* stream) {
@@ -555,8 +745,11 @@ rfcmp_status rfcmp_apply(rfcmp_op op, const void* x, void* y, int32_t nrhs, void
   RF_ARG(nrhs > 0, "nrhs must be > 0");
   const int64_t N = op->mesh->h.N;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return batched(nrhs, N, N, static_cast<const double2*>(x), static_cast<double2*>(y),
-                 [&](const double2* a, double2* b, int nr) { return apply_batch(op, a, b, nr, s); });
+  RF_TRY(ensure_work(op, std::min(nrhs, 64)));
+  const Work W = carve(op);
+  const Dense D{op, s, false};
+  return batched(nrhs, W.R, N, N, static_cast<const double2*>(x), static_cast<double2*>(y),
+                 [&](const double2* a, double2* b, int nr) { return apply_batch(D, W, a, b, nr); });
 }
 
 rfcmp_status rfcmp_recover(rfcmp_op op, const void* i, void* j, int32_t nrhs, void* stream) {
@@ -564,8 +757,11 @@ rfcmp_status rfcmp_recover(rfcmp_op op, const void* i, void* j, int32_t nrhs, vo
   RF_ARG(nrhs > 0, "nrhs must be > 0");
   const int64_t N = op->mesh->h.N;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return batched(nrhs, N, N, static_cast<const double2*>(i), static_cast<double2*>(j),
-                 [&](const double2* a, double2* b, int nr) { return recover_batch(op, a, b, nr, s); });
+  RF_TRY(ensure_work(op, std::min(nrhs, 64)));
+  const Work W = carve(op);
+  const Dense D{op, s, false};
+  return batched(nrhs, W.R, N, N, static_cast<const double2*>(i), static_cast<double2*>(j),
+                 [&](const double2* a, double2* b, int nr) { return recover_batch(D, W, a, b, nr); });
 }
 
 rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* xv, void* yv, int32_t nrhs, void* stream) {
@@ -579,9 +775,10 @@ rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* xv, void* yv,
   const int64_t N = m->h.N, C = m->h.C, V = m->h.V;
   const int64_t nin = (which == RFCMP_PROJ_LPINV) ? C : (which == RFCMP_PROJ_GLL_INV ? V : N);
   const int64_t nout = (which <= RFCMP_PROJ_GSIGMA) ? N : (which == RFCMP_PROJ_LAMBDA_T || which == RFCMP_PROJ_GLL_INV ? V : C);
-  return batched(nrhs, nin, nout, static_cast<const double2*>(xv), static_cast<double2*>(yv),
+  RF_TRY(ensure_work(op, std::min(nrhs, 64)));
+  const Work W = carve(op);
+  return batched(nrhs, W.R, nin, nout, static_cast<const double2*>(xv), static_cast<double2*>(yv),
                  [&](const double2* x, double2* y, int nr) -> rfcmp_status {
-                   const Work W = carve(op);
                    switch (which) {
                      case RFCMP_PROJ_SIGMA:
                      case RFCMP_PROJ_LH:
@@ -610,13 +807,20 @@ rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* xv, void* yv,
 rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* x, void* y, int32_t nrhs,
                           void* stream) {
   RF_ARG(op && x && y && x != y, "NULL or aliased argument");
-  RF_ARG(nrhs > 0 && (which == 0 || which == 1), "bad which/nrhs");
+  RF_ARG(nrhs > 0 && which >= 0 && which <= 5, "bad which/nrhs");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (which == 0)
-    return cmatvec(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, static_cast<const double2*>(x),
-                   static_cast<double2*>(y), nrhs, s);
-  return cmatvec(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj != 0, static_cast<const double2*>(x),
-                 static_cast<double2*>(y), nrhs, s);
+  const double2* xx = static_cast<const double2*>(x);
+  double2* yy = static_cast<double2*>(y);
+  if (which == 0) return cmatvec(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, xx, yy, nrhs, s);
+  if (which == 1) return cmatvec(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj != 0, xx, yy, nrhs, s);
+  RF_TRY(ensure_split(op, s));
+  const Dense D{op, s, true};
+  switch (which) {
+    case 2: return D.ta(conj != 0, xx, yy, nrhs);
+    case 3: return D.v(conj != 0, xx, yy, nrhs);
+    case 4: return D.lp(xx, yy, nrhs);
+    default: return D.gll(xx, yy, nrhs);
+  }
 }
 
 rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,
@@ -626,14 +830,17 @@ rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, doub
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t N = op->mesh->h.N;
   const auto t0 = std::chrono::steady_clock::now();
+  RF_TRY(ensure_work(op, std::min(nrhs, 64)));
+  if (op->opt.precision == 1) RF_TRY(ensure_split(op, s));
   rfcmp_status worst = RFCMP_OK;
-  for (int r = 0; r < nrhs; ++r) {
-    rfcmp_info one{};
-    rfcmp_status st = cg_one(op, static_cast<const double2*>(e) + r * N, static_cast<double2*>(j) + r * N, tol,
-                             maxit, s, &one);
+  const int R = op->work_nrhs;
+  for (int r0 = 0; r0 < nrhs; r0 += R) {
+    const int nr = std::min(R, nrhs - r0);
+    rfcmp_status st = solve_batch(op, static_cast<const double2*>(e) + (int64_t)r0 * N,
+                                  static_cast<double2*>(j) + (int64_t)r0 * N, nr, tol, maxit, s,
+                                  info ? info + r0 : nullptr);
     if (st < 0) return st;
     if (st > worst) worst = st;
-    if (info) info[r] = one;
   }
   RF_HIP(hipStreamSynchronize(s));
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -42,6 +42,13 @@ rfcmp_status cg_xr(int64_t n, const double* sc, int rho_slot, double2* x, double
 rfcmp_status cg_p(int64_t n, const double* sc, int old_slot, int new_slot, const double2* r, double2* p,
                   hipStream_t s);
 rfcmp_status take_real(const double2* d, double* sc, int slot, hipStream_t s);
+// block CG updates over nr right-hand sides (frozen where active[r] == 0)
+rfcmp_status cg_xr_blk(int64_t n, int nr, const double* rho, const double* pq, const int* active, double2* x,
+                       double2* r, const double2* p, const double2* q, hipStream_t s);
+rfcmp_status cg_p_blk(int64_t n, int nr, const double* rnew, const double* rold, const int* active,
+                      const double2* r, double2* p, hipStream_t s);
+rfcmp_status take_real_n(const double2* d, double* out, int nr, hipStream_t s);
+rfcmp_status set_active(int* a, int v, int n, hipStream_t s);
 rfcmp_status vsub(int64_t n, const double2* a, const double2* b, double2* out, hipStream_t s);
 rfcmp_status vadd_to(int64_t n, const double2* a, double2* x, hipStream_t s);
 

@@ -257,6 +257,38 @@ __global__ void k_add_to(long n, const double2* __restrict__ a, double2* __restr
   x[i] = cadd(x[i], a[i]);
 }
 
+// block CG: alpha_r = rho_r/pq_r for active r; x_r += alpha p_r; r_r -= alpha q_r
+__global__ void k_cg_xr_blk(long n, const double* __restrict__ rho, const double* __restrict__ pq,
+                            const int* __restrict__ active, double2* __restrict__ x, double2* __restrict__ r,
+                            const double2* __restrict__ p, const double2* __restrict__ q) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const double al = rho[k] / pq[k];
+  const long o = (long)k * n + i;
+  x[o] = cadd(x[o], cscale(al, p[o]));
+  r[o] = csub(r[o], cscale(al, q[o]));
+}
+// block CG: p_r = r_r + (rho_new/rho_old) p_r for active r
+__global__ void k_cg_p_blk(long n, const double* __restrict__ rnew, const double* __restrict__ rold,
+                           const int* __restrict__ active, const double2* __restrict__ r, double2* __restrict__ p) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const long o = (long)k * n + i;
+  p[o] = cadd(r[o], cscale(rnew[k] / rold[k], p[o]));
+}
+__global__ void k_take_real_n(int nr, const double2* __restrict__ d, double* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k < nr) out[k] = d[k].x;
+}
+__global__ void k_set_int(int* __restrict__ a, int v, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) a[k] = v;
+}
+
 inline dim3 g1(long n, int nr = 1) { return dim3(unsigned((n + 255) / 256), unsigned(nr)); }
 
 }  // namespace
@@ -352,6 +384,28 @@ rfcmp_status cg_xr(int64_t n, const double* sc, int rho_slot, double2* x, double
 rfcmp_status cg_p(int64_t n, const double* sc, int old_slot, int new_slot, const double2* r, double2* p,
                   hipStream_t s) {
   hipLaunchKernelGGL(k_cg_p, g1(n), dim3(256), 0, s, (long)n, sc, old_slot, new_slot, r, p);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status cg_xr_blk(int64_t n, int nr, const double* rho, const double* pq, const int* active, double2* x,
+                       double2* r, const double2* p, const double2* q, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_xr_blk, g1(n, nr), dim3(256), 0, s, (long)n, rho, pq, active, x, r, p, q);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status cg_p_blk(int64_t n, int nr, const double* rnew, const double* rold, const int* active,
+                      const double2* r, double2* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p_blk, g1(n, nr), dim3(256), 0, s, (long)n, rnew, rold, active, r, p);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status take_real_n(const double2* d, double* out, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_take_real_n, dim3(1), dim3(256), 0, s, nr, d, out);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status set_active(int* a, int v, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3((n + 255) / 256), dim3(256), 0, s, a, v, n);
   RF_LAUNCH_CHECK();
   return RFCMP_OK;
 }

@@ -219,3 +219,57 @@ def test_not_converged_returns_best_iterate():
     j, st, info = op.solve(e, tol=1e-12, maxit=2)
     assert st == 1 and info[0]["iters"] == 2
     assert np.all(np.isfinite(_np(j)))
+
+
+# ---------------------------------------------------------------- BF16x3 (a8)
+# Split-precision products: each operand is hi + lo bf16 (16 significant
+# bits), the product keeps hi.hi + hi.lo + lo.hi (dropping a 2^-18 relative
+# term) and accumulates in FP32.  Against the FP64 product of the same stored
+# blocks the relative error of a row is bounded by ~3 * 2^-16 * cond-free
+# cancellation; 3e-5 on the Frobenius-relative error leaves margin for the
+# FP32 accumulation over ~10^4 terms.
+@pytest.mark.parametrize("name,k", [("ico2", 1.0), ("cube3", 2.0), ("torus_small", 0.5)])
+@pytest.mark.parametrize("nrhs", [1, 5, 64, 70])
+def test_bf16x3_products_match_fp64(name, k, nrhs):
+    op = _gpu_op(name, k)
+    gTA, gV = (_np(t).astype(np.complex128) for t in op.export())
+    top, _, _ = _oracle(name, k)
+    pre = rfcmp.Preconditioner(top, gTA, gV, k)
+    N, C, V = len(gTA), len(gV), top.V
+    x = np.stack([synth.complex_start(N, 100 + r) for r in range(nrhs)])
+    xc = np.stack([synth.complex_start(C, 200 + r) for r in range(nrhs)])
+    xv = np.stack([synth.complex_start(V, 300 + r) for r in range(nrhs)])
+    for conj in (False, True):
+        M = np.conj(gTA) if conj else gTA
+        assert rel(_np(op.matvec(2, _cuda(x), conj)), (M @ x.T).T) < 3e-5
+        M = np.conj(gV) if conj else gV
+        assert rel(_np(op.matvec(3, _cuda(xc), conj)), (M @ xc.T).T) < 3e-5
+    assert rel(_np(op.matvec(4, _cuda(xc))), (pre.Lp @ xc.T).T) < 3e-5
+    assert rel(_np(op.matvec(5, _cuda(xv))), (pre.Gll_inv @ xv.T).T) < 3e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5)])
+def test_block_solve_matches_oracle(precision, name, k):
+    """Many right-hand sides advanced together, in both precisions, against
+    the oracle's dense solution for each plane wave."""
+    torch, rf = _gpu()
+    top, TA, V = _oracle(name, k)
+    m = _gpu_mesh(name)
+    start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
+    op = rf.Operator(m, k, power_start=start, precision=precision)
+    kh, pol = synth.plane_waves(7, 5)
+    e = rhs.planewave(top, k, kh, pol)
+    pre = rfcmp.Preconditioner(top, TA, V, k)
+    pre.power_scalings(synth.complex_start(top.N, 11), 30)
+    A = pre.system_split()
+    jref = pre.recover(np.linalg.solve(A, pre.rhs(e.T))).T
+    j, st, info = op.solve(_cuda(e), tol=1e-8, maxit=400)
+    j = _np(j)
+    assert st == 0
+    for r in range(len(e)):
+        assert info[r]["rel_residual"] <= 1e-8
+        assert rel(j[r], jref[r]) < 1e-5, r
+        assert rel(pre.P_S @ j[r], pre.P_S @ jref[r]) < 1e-5, r
+    if precision == 1:
+        assert max(i["restarts"] for i in info) >= 1       # refinement rounds happened
