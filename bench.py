@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-slab", type=int, default=32, help="1/slab of the test cells for the oracle sample")
+    p.add_argument("--no-precision-study", action="store_true")
+    p.add_argument("--batch-rhs", type=int, default=64)
     return p.parse_args()
 
 
@@ -94,6 +96,65 @@ def cpu_baseline(xyz, tri, slab):
                       f"ka=1.0) in {dt:.1f} s; solves/s = 1/(C^2 / pairs_per_s), i.e. assembly only "
                       f"(upper bound on the oracle's throughput)",
             "assembly_pairs_per_s": pairs_per_s}
+
+
+BF16_MFMA_TFLOPS = 2500.0
+
+
+def precision_study(rf, torch, xyz, tri, kh, pol, start, nb):
+    """BF16x3 (precision 1) against the complex64/FP64 path (precision 0), both
+    to the same true relative residual 1e-6, on the same mesh: single plane
+    wave at both wavenumbers, and a batch of nb seeded plane waves at ka = 1.
+    Also the BF16x3 T_A product's MFMA and HBM rates from HIP events."""
+    out = {"tol": TOL}
+    m = rf.Mesh(xyz, tri)
+    N = m.N
+    for k in KS:
+        row = {}
+        for prec in (0, 1):
+            op = rf.Operator(m, k, power_start=start, precision=prec)
+            e = op.rhs_planewave(kh, pol)
+            op.solve(e, tol=TOL, maxit=2000)          # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            j, st, info = op.solve(e, tol=TOL, maxit=2000)
+            torch.cuda.synchronize()
+            row["bf16x3" if prec else "fp32"] = {"solve_ms": (time.perf_counter() - t0) * 1e3,
+                                                 "iters": info[0]["iters"], "rounds": info[0]["restarts"] + 1,
+                                                 "rel_residual": info[0]["rel_residual"], "status": st}
+            op.close()
+        out[f"ka={k}, 1 rhs"] = row
+    kb, pb = synth.plane_waves(nb, 4)
+    row = {}
+    for prec in (0, 1):
+        op = rf.Operator(m, 1.0, power_start=start, precision=prec)
+        e = op.rhs_planewave(kb, pb)
+        op.solve(e, tol=TOL, maxit=2000)
+        torch.cuda.synchronize()
+        rf.profile_enable(True)
+        t0 = time.perf_counter()
+        j, st, info = op.solve(e, tol=TOL, maxit=2000)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        gt, gn = rf.profile_read("gemm_ta")
+        ct, cn = rf.profile_read("cmatvec_ta")
+        rf.profile_enable(False)
+        r = {"solve_ms": ms, "ms_per_rhs": ms / nb, "max_iters": max(i["iters"] for i in info),
+             "max_rel_residual": max(i["rel_residual"] for i in info), "status": st}
+        if prec == 1 and gn:
+            avg = gt / gn
+            mfma_flops = 3 * 8.0 * N * N * nb      # three bf16 products per real MAC, 4 real MACs per complex
+            r["gemm_ta"] = {"avg_ms": avg, "launches": gn,
+                            "mfma_tflops": mfma_flops / (avg * 1e-3) / 1e12,
+                            "mfma_frac": mfma_flops / (avg * 1e-3) / 1e12 / BF16_MFMA_TFLOPS,
+                            "hbm_gbs": 8.0 * N * N / (avg * 1e-3) / 1e9}
+        if prec == 0 and cn:
+            r["cmatvec_ta"] = {"avg_ms": ct / cn, "launches": cn}
+        row["bf16x3" if prec else "fp32"] = r
+        op.close()
+    out[f"ka=1.0, {nb} rhs"] = row
+    m.close()
+    return out
 
 
 def main():
@@ -190,6 +251,8 @@ def main():
         "bf16x3_vs_fp32": None,
         "roofline": roof,
     }
+    if not args.no_precision_study:
+        res["bf16x3_vs_fp32"] = precision_study(rf, torch, xyz, tri, kh, pol, start, args.batch_rhs)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(xyz, tri, args.cpu_slab)
     print(json.dumps(res))

@@ -174,6 +174,8 @@ typedef struct {
   int32_t restarts;       /* residual refinements after the first CG pass */
   double rel_residual;    /* final |b - A i|/|b|, FP64-accumulated */
   double ms_solve;        /* wall time of the solve (all right-hand sides) */
+  double cond_estimate;   /* lambda_max/lambda_min of the Lanczos tridiagonal of
+                             the first CG pass (0 if fewer than 2 iterations) */
 } rfcmp_info;
 
 /* Solve T j = -e through the RF-CMP system with CG (Sec. 3.4; x0 = 0), until

@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double), ("ms_solve", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("ms_solve", ctypes.c_double),
+                ("cond_estimate", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

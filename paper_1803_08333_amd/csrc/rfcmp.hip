@@ -310,6 +310,47 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStr
 }
 
 // ------------------------------------------------------------------ CG
+// Extreme eigenvalues of the CG Lanczos tridiagonal (Sec. 3.4: the iteration
+// count is governed by cond(A)).  With step lengths a_i and b_i = rho_{i+1}/rho_i
+// the tridiagonal has diagonal 1/a_1, 1/a_i + b_{i-1}/a_{i-1} and off-diagonal
+// sqrt(b_i)/a_i; its eigenvalues are found by Sturm-sequence bisection.
+double lanczos_cond(const std::vector<double>& a, const std::vector<double>& b) {
+  const size_t m = a.size();
+  if (m < 2) return 0.0;
+  std::vector<double> d(m), e(m, 0.0);
+  for (size_t i = 0; i < m; ++i) {
+    d[i] = 1.0 / a[i] + (i ? b[i - 1] / a[i - 1] : 0.0);
+    if (i + 1 < m) e[i] = std::sqrt(b[i]) / a[i];
+  }
+  double lo = 1e300, hi = -1e300;
+  for (size_t i = 0; i < m; ++i) {
+    const double r = (i ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto count_below = [&](double x) {  // number of eigenvalues < x
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (size_t i = 1; i < m; ++i) {
+      const double qq = (q == 0.0) ? 1e-300 : q;
+      q = d[i] - x - e[i - 1] * e[i - 1] / qq;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  auto kth = [&](int k) {  // k-th smallest (0-based)
+    double a0 = lo, b0 = hi;
+    for (int it = 0; it < 200 && b0 - a0 > 1e-13 * std::max(std::fabs(a0), std::fabs(b0)); ++it) {
+      const double mid = 0.5 * (a0 + b0);
+      if (count_below(mid) > k) b0 = mid; else a0 = mid;
+    }
+    return 0.5 * (a0 + b0);
+  };
+  const double lmin = kth(0), lmax = kth((int)m - 1);
+  return lmin > 0 ? lmax / lmin : 0.0;
+}
+
 // Block of nr independent complex CGs on the HPD system (Sec. 3.4) sharing
 // the operator passes: solves A x = W.b from x = 0 (x in W.x), stopping
 // right-hand side r once its recursive residual norm is <= target[r] (it is
@@ -317,7 +358,8 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStr
 // stay on the device; the host examines iteration i while iteration i+1 runs
 // (pinned copies and events), so the GPU never waits for the test.  iters[r]
 // counts the iterations in which r was still active.
-rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* target, int maxit, int* iters) {
+rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* target, int maxit, int* iters,
+                      double* cond = nullptr) {
   rfcmp_op op = D.op;
   hipStream_t s = D.s;
   const int64_t N = op->mesh->h.N;
@@ -332,6 +374,11 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
   RF_TRY(set_active(W.active, 1, nr, s));
   RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, s));
   RF_TRY(take_real_n(W.dout, W.rho, nr, s));  // rho[0][r]
+  std::vector<double> rho_prev(nr);
+  RF_HIP(hipMemcpyAsync(hs, W.rho, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+  RF_HIP(hipStreamSynchronize(s));
+  for (int r = 0; r < nr; ++r) rho_prev[r] = hs[r];
+  std::vector<std::vector<double>> la(nr), lb(nr);
   hipEvent_t ev[2];
   RF_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   RF_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -379,6 +426,9 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
         set_error("CG breakdown at iteration %d (rhs %d): p^H A p = %g", look + 1, r, pq);
         return RFCMP_E_BREAKDOWN;
       }
+      la[r].push_back(rho_prev[r] / pq);
+      lb[r].push_back(rho / rho_prev[r]);
+      rho_prev[r] = rho;
       if (std::sqrt(rho) <= target[r]) {
         act[r] = 0;
         --nactive;
@@ -394,6 +444,8 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
     }
     if (nactive == 0 || !issued) break;
   }
+  if (cond)
+    for (int r = 0; r < nr; ++r) cond[r] = lanczos_cond(la[r], lb[r]);
   return RFCMP_OK;
 }
 
@@ -422,6 +474,7 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
   std::vector<double> bn(nr), res(nr), target(nr), rel(nr, 1.0);
   for (int r = 0; r < nr; ++r) res[r] = bn[r] = std::sqrt(hd[r].x);
   std::vector<int> its(nr, 0), tot(nr, 0), rst(nr, -1);
+  std::vector<double> cond(nr, 0.0);
   rfcmp_status st = RFCMP_OK;
   bool zero = true;
   for (int r = 0; r < nr; ++r) zero &= !(bn[r] > 0);
@@ -434,7 +487,7 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
       st = RFCMP_W_NOT_CONVERGED;
       break;
     }
-    RF_TRY(block_cg(split ? D16 : D64, W, nr, target.data(), budget, its.data()));
+    RF_TRY(block_cg(split ? D16 : D64, W, nr, target.data(), budget, its.data(), round == 0 ? cond.data() : nullptr));
     for (int r = 0; r < nr; ++r) {
       tot[r] += its[r];
       rst[r] += 1;
@@ -466,6 +519,7 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
       info[r].iters = tot[r];
       info[r].restarts = std::max(rst[r], 0);
       info[r].rel_residual = zero ? 0.0 : rel[r];
+      info[r].cond_estimate = cond[r];
     }
   RF_TRY(recover_batch(D64, W, W.d, j, nr));
   return st;
