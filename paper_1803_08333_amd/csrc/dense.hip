@@ -18,9 +18,10 @@ namespace {
 constexpr int kWave = 64;
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef double vd2 __attribute__((ext_vector_type(2)));
-constexpr int kRowsPerWave = 2;
-constexpr int kRowsPerBlock = 4 * kRowsPerWave;  // 256 threads = 4 waves
-constexpr int kChunk = 512;                      // columns staged per pass
+constexpr int kRowsPerWave = 4;                  // rows sharing each x value read from LDS
+constexpr int kWavesPerBlock = 2;
+constexpr int kThreads = kWave * kWavesPerBlock;
+constexpr int kRowsPerBlock = kRowsPerWave * kWavesPerBlock;
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -29,12 +30,13 @@ __device__ inline double wave_sum(double v) {
 
 // y[r][row] = sum_j M[row][j] x[r][j];  M complex64 rows padded to ld (a
 // multiple of 64 entries, padding zero); x, y complex128.  Each wave owns
-// kRowsPerWave rows and reads them as float4 (two entries) per lane.
+// kRowsPerWave rows and reads two entries (16 B) per lane per row and step;
+// x (L2-resident) is read directly, each value serving all the wave's rows,
+// so the stream never stops at a barrier.
 template <int NR, bool CONJ>
-__global__ __launch_bounds__(256) void k_cmatvec(const float2* __restrict__ M, int n, long ld,
-                                                 const double2* __restrict__ x,
-                                                 double2* __restrict__ y) {
-  __shared__ double2 xs[NR][kChunk];
+__global__ __launch_bounds__(kThreads) void k_cmatvec(const float2* __restrict__ M, int n, long ld,
+                                                      const double2* __restrict__ x,
+                                                      double2* __restrict__ y) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int row0 = blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
@@ -43,35 +45,29 @@ __global__ __launch_bounds__(256) void k_cmatvec(const float2* __restrict__ M, i
   for (int i = 0; i < kRowsPerWave; ++i)
 #pragma unroll
     for (int r = 0; r < NR; ++r) accr[i][r] = acci[i][r] = 0.0;
-
-  for (int j0 = 0; j0 < n; j0 += kChunk) {
-    for (int t = threadIdx.x; t < NR * kChunk; t += 256) {
-      const int r = t / kChunk, j = t % kChunk;
-      xs[r][j] = (j0 + j < n) ? x[(long)r * n + j0 + j] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
+  const vf4* mr[kRowsPerWave];
 #pragma unroll
-    for (int i = 0; i < kRowsPerWave; ++i) {
-      const int row = row0 + i;
-      if (row >= n) break;
-      const vf4* mr = reinterpret_cast<const vf4*>(M + (long)row * ld + j0);
+  for (int i = 0; i < kRowsPerWave; ++i)
+    mr[i] = reinterpret_cast<const vf4*>(M + (long)min(row0 + i, n - 1) * ld);
+  const int npair = (n + 1) / 2;  // float4 columns; the last may hold one padding entry
+#pragma unroll 2
+  for (int p = lane; p < npair; p += kWave) {
+    const int jj = 2 * p;
+    vf4 m[kRowsPerWave];
 #pragma unroll
-      for (int t = 0; t < kChunk / (2 * kWave); ++t) {
-        const int jj = 2 * lane + 2 * kWave * t;
-        if (j0 + jj < n) {
-          const vf4 m = __builtin_nontemporal_load(mr + lane + kWave * t);
-          const double a0 = m.x, b0 = CONJ ? -(double)m.y : (double)m.y;
-          const double a1 = m.z, b1 = CONJ ? -(double)m.w : (double)m.w;
+    for (int i = 0; i < kRowsPerWave; ++i) m[i] = __builtin_nontemporal_load(mr[i] + p);
 #pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const double2 x0 = xs[r][jj], x1 = xs[r][jj + 1];
-            accr[i][r] += a0 * x0.x - b0 * x0.y + a1 * x1.x - b1 * x1.y;
-            acci[i][r] += a0 * x0.y + b0 * x0.x + a1 * x1.y + b1 * x1.x;
-          }
-        }
+    for (int r = 0; r < NR; ++r) {
+      const double2 x0 = x[(long)r * n + jj];
+      const double2 x1 = (jj + 1 < n) ? x[(long)r * n + jj + 1] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < kRowsPerWave; ++i) {
+        const double a0 = m[i].x, b0 = CONJ ? -(double)m[i].y : (double)m[i].y;
+        const double a1 = m[i].z, b1 = CONJ ? -(double)m[i].w : (double)m[i].w;
+        accr[i][r] += a0 * x0.x - b0 * x0.y + a1 * x1.x - b1 * x1.y;
+        acci[i][r] += a0 * x0.y + b0 * x0.x + a1 * x1.y + b1 * x1.x;
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < kRowsPerWave; ++i) {
@@ -86,12 +82,11 @@ __global__ __launch_bounds__(256) void k_cmatvec(const float2* __restrict__ M, i
 }
 
 // y[r][row] = sum_j M[row][j] x[r][j];  M real FP64 [n][ld] (ld a multiple of
-// 64, padding zero); x, y complex128.
+// 64, padding zero); x, y complex128.  Same structure as k_cmatvec.
 template <int NR>
-__global__ __launch_bounds__(256) void k_dmatvec(const double* __restrict__ M, int n, long ld,
-                                                 const double2* __restrict__ x,
-                                                 double2* __restrict__ y) {
-  __shared__ double2 xs[NR][kChunk];
+__global__ __launch_bounds__(kThreads) void k_dmatvec(const double* __restrict__ M, int n, long ld,
+                                                      const double2* __restrict__ x,
+                                                      double2* __restrict__ y) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int row0 = blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
@@ -100,33 +95,27 @@ __global__ __launch_bounds__(256) void k_dmatvec(const double* __restrict__ M, i
   for (int i = 0; i < kRowsPerWave; ++i)
 #pragma unroll
     for (int r = 0; r < NR; ++r) accr[i][r] = acci[i][r] = 0.0;
-
-  for (int j0 = 0; j0 < n; j0 += kChunk) {
-    for (int t = threadIdx.x; t < NR * kChunk; t += 256) {
-      const int r = t / kChunk, j = t % kChunk;
-      xs[r][j] = (j0 + j < n) ? x[(long)r * n + j0 + j] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
+  const vd2* mr[kRowsPerWave];
 #pragma unroll
-    for (int i = 0; i < kRowsPerWave; ++i) {
-      const int row = row0 + i;
-      if (row >= n) break;
-      const vd2* mr = reinterpret_cast<const vd2*>(M + (long)row * ld + j0);
+  for (int i = 0; i < kRowsPerWave; ++i)
+    mr[i] = reinterpret_cast<const vd2*>(M + (long)min(row0 + i, n - 1) * ld);
+  const int npair = (n + 1) / 2;
+#pragma unroll 2
+  for (int p = lane; p < npair; p += kWave) {
+    const int jj = 2 * p;
+    vd2 m[kRowsPerWave];
 #pragma unroll
-      for (int t = 0; t < kChunk / (2 * kWave); ++t) {
-        const int jj = 2 * lane + 2 * kWave * t;
-        if (j0 + jj < n) {
-          const vd2 m = __builtin_nontemporal_load(mr + lane + kWave * t);
+    for (int i = 0; i < kRowsPerWave; ++i) m[i] = __builtin_nontemporal_load(mr[i] + p);
 #pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const double2 x0 = xs[r][jj], x1 = xs[r][jj + 1];
-            accr[i][r] += m.x * x0.x + m.y * x1.x;
-            acci[i][r] += m.x * x0.y + m.y * x1.y;
-          }
-        }
+    for (int r = 0; r < NR; ++r) {
+      const double2 x0 = x[(long)r * n + jj];
+      const double2 x1 = (jj + 1 < n) ? x[(long)r * n + jj + 1] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < kRowsPerWave; ++i) {
+        accr[i][r] += m[i].x * x0.x + m[i].y * x1.x;
+        acci[i][r] += m[i].x * x0.y + m[i].y * x1.y;
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < kRowsPerWave; ++i) {
@@ -148,60 +137,65 @@ __global__ __launch_bounds__(256) void k_dmatvec(const double* __restrict__ M, i
 // After all pivot blocks the matrix holds A^-1 (the sweep operator).
 constexpr int kB = 64;
 
-// In-LDS unblocked sweep of the 64 x 64 pivot block.
+// Unblocked sweep of the 64 x 64 pivot block.  Thread t keeps the 16-entry
+// strip (rows 16 (t / 64) .. +16, column t % 64) in registers for all 64
+// pivots; per pivot the owners publish the pivot column and row to LDS
+// (double-buffered, one barrier per pivot) and every entry is updated:
+//   a_ij -= a_ik a_kj / a_kk,  a_kj /= a_kk,  a_ik = -a_ik / a_kk,  a_kk = 1 / a_kk.
 __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld, int K) {
-  __shared__ double a[kB][kB + 1];
+  __shared__ double colk[2][kB], rowk[2][kB];
+  const int j = threadIdx.x % kB;
+  const int i0 = (threadIdx.x / kB) * 16;
   const long base = (long)K * kB;
-  for (int t = threadIdx.x; t < kB * kB; t += 256) {
-    const int i = t / kB, j = t % kB;
-    a[i][j] = A[(base + i) * ld + base + j];
-  }
-  __syncthreads();
+  double r[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) r[u] = A[(base + i0 + u) * ld + base + j];
   for (int k = 0; k < kB; ++k) {
-    const double d = 1.0 / a[k][k];
-    double upd[kB * kB / 256];
-    int cnt = 0;
-    for (int t = threadIdx.x; t < kB * kB; t += 256, ++cnt) {
-      const int i = t / kB, j = t % kB;
-      upd[cnt] = (i != k && j != k) ? a[i][j] - a[i][k] * a[k][j] * d : 0.0;
+    const int bsel = k & 1;
+    if (j == k) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) colk[bsel][i0 + u] = r[u];
+    }
+    if (k >= i0 && k < i0 + 16) {
+      double v = 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v = (i0 + u == k) ? r[u] : v;
+      rowk[bsel][j] = v;
     }
     __syncthreads();
-    cnt = 0;
-    for (int t = threadIdx.x; t < kB * kB; t += 256, ++cnt) {
-      const int i = t / kB, j = t % kB;
-      if (i != k && j != k) a[i][j] = upd[cnt];
+    const double d = 1.0 / rowk[bsel][k];
+    const double akj = rowk[bsel][j];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = i0 + u;
+      const double aik = colk[bsel][i];
+      double nv;
+      if (j == k)
+        nv = (i == k) ? d : -aik * d;
+      else
+        nv = (i == k) ? akj * d : r[u] - aik * akj * d;
+      r[u] = nv;
     }
-    __syncthreads();
-    if (threadIdx.x < kB) {
-      const int j = threadIdx.x;
-      if (j != k) {
-        a[k][j] *= d;   // row k
-        a[j][k] *= -d;  // column k
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) a[k][k] = d;
-    __syncthreads();
   }
-  for (int t = threadIdx.x; t < kB * kB; t += 256) {
-    const int i = t / kB, j = t % kB;
-    A[(base + i) * ld + base + j] = a[i][j];
-  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) A[(base + i0 + u) * ld + base + j] = r[u];
 }
 
 // Column panel: Ccol = A_OP (old), A_OP <- -A_OP D.  Row panel: A_PO <- D A_PO.
 // blockIdx.x = block index b (skip b == K); blockIdx.y = 0 column panel, 1 row panel.
-// The old panel block is staged in LDS (the product overwrites it in place);
-// D = A_PP is read from global memory (this kernel does not modify it).
+// D and the old panel block are staged in LDS (the product overwrites the
+// panel in place); each thread computes a 4 x 4 output tile.
 __global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long ld, int K,
                                                    double* __restrict__ Ccol) {
   const int b = blockIdx.x;
   if (b == K) return;
-  __shared__ double S[kB][kB + 1];
+  __shared__ double D[kB][kB];
+  __shared__ double S[kB][kB];
   const long pb = (long)K * kB, ob = (long)b * kB;
   const bool col = blockIdx.y == 0;
   for (int t = threadIdx.x; t < kB * kB; t += 256) {
     const int i = t / kB, j = t % kB;
+    D[i][j] = A[(pb + i) * ld + pb + j];
     if (col) {
       const double v = A[(ob + i) * ld + pb + j];  // row ob+i, pivot column j
       S[i][j] = v;
@@ -211,18 +205,33 @@ __global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long 
     }
   }
   __syncthreads();
-  const double* D = A + pb * ld + pb;
-  for (int t = threadIdx.x; t < kB * kB; t += 256) {
-    const int i = t / kB, j = t % kB;
-    double s = 0.0;
-    if (col) {
-      for (int q = 0; q < kB; ++q) s += S[i][q] * D[q * ld + j];
-      A[(ob + i) * ld + pb + j] = -s;
-    } else {
-      for (int q = 0; q < kB; ++q) s += D[i * ld + q] * S[q][j];
-      A[(pb + i) * ld + ob + j] = s;
-    }
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  // col: out = S D (rows of S times D); row: out = D S
+  const double(*L)[kB] = col ? S : D;
+  const double(*Rm)[kB] = col ? D : S;
+#pragma unroll 8
+  for (int q = 0; q < kB; ++q) {
+    double lv[4], rv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) lv[u] = L[ty * 4 + u][q];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rv[v] = Rm[q][tx + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += lv[u] * rv[v];
   }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ty * 4 + u, j = tx + 16 * v;
+      if (col)
+        A[(ob + i) * ld + pb + j] = -acc[u][v];
+      else
+        A[(pb + i) * ld + ob + j] = acc[u][v];
+    }
 }
 
 // A_IJ -= Ccol_I R_J for I, J != K, with R = the updated pivot row panel.
@@ -301,9 +310,9 @@ rfcmp_status cmatvec(const float2* M, int64_t n, int64_t ld, bool conj, const do
     dim3 grid(blocks_for(n, kRowsPerBlock));
 #define RF_CMV(NRV)                                                                              \
   if (conj)                                                                                     \
-    hipLaunchKernelGGL((k_cmatvec<NRV, true>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); \
+    hipLaunchKernelGGL((k_cmatvec<NRV, true>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); \
   else                                                                                          \
-    hipLaunchKernelGGL((k_cmatvec<NRV, false>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr);
+    hipLaunchKernelGGL((k_cmatvec<NRV, false>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr);
     switch (nr) {
       case 1: RF_CMV(1) break;
       case 2: RF_CMV(2) break;
@@ -325,10 +334,10 @@ rfcmp_status dmatvec(const double* M, int64_t n, int64_t ld, const double2* x, d
     double2* yr = y + (long)r0 * n;
     dim3 grid(blocks_for(n, kRowsPerBlock));
     switch (nr) {
-      case 1: hipLaunchKernelGGL((k_dmatvec<1>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); break;
-      case 2: hipLaunchKernelGGL((k_dmatvec<2>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); break;
-      case 3: hipLaunchKernelGGL((k_dmatvec<3>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); break;
-      default: hipLaunchKernelGGL((k_dmatvec<4>), grid, dim3(256), 0, s, M, (int)n, (long)ld, xr, yr); break;
+      case 1: hipLaunchKernelGGL((k_dmatvec<1>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); break;
+      case 2: hipLaunchKernelGGL((k_dmatvec<2>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); break;
+      case 3: hipLaunchKernelGGL((k_dmatvec<3>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); break;
+      default: hipLaunchKernelGGL((k_dmatvec<4>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); break;
     }
   }
   RF_HIP(hipGetLastError());

@@ -278,14 +278,20 @@ def test_block_solve_matches_oracle(precision, name, k):
 @pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5)])
 def test_lanczos_condition_estimate(name, k):
     """The CG-Lanczos estimate of cond(A) reported by the solve agrees with
-    the oracle's dense eigenvalues of A (same scalings, GPU blocks)."""
+    the oracle's dense eigenvalues of A (same scalings, GPU blocks).  Lanczos
+    sees only the Krylov space of the right-hand side, so the estimate is a
+    lower bound; a generic (random) excitation exposes the extremes, a
+    symmetric plane wave on the sphere does not.  At ka = 1e-4 even a random
+    e gives a b dominated by one of the two blocks (P_m weights the loop part
+    by 1/gamma ~ 1e5), so after convergence the estimate reaches ~0.9."""
     op, pre = _oracle_on_gpu_blocks(name, k, 0)
-    kh, pol = synth.default_plane_wave()
-    e = op.rhs_planewave(kh, pol)
+    e = _cuda(np.stack([synth.complex_start(pre.top.N, 41)]))
     _, st, info = op.solve(e, tol=1e-10, maxit=500)
     A = pre.system_split()
     ev = np.linalg.eigvalsh(0.5 * (A + A.conj().T))
-    assert abs(info[0]["cond_estimate"] / (ev[-1] / ev[0]) - 1.0) < 0.05
+    cond = ev[-1] / ev[0]
+    assert info[0]["cond_estimate"] <= cond * (1 + 1e-6)
+    assert info[0]["cond_estimate"] > 0.85 * cond
 
 
 @pytest.mark.parametrize("k", [0.5, 1.0])
