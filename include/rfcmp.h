@@ -60,6 +60,13 @@ typedef enum {
  * failing call on that thread); "" if none. */
 const char* rfcmp_last_error(void);
 const char* rfcmp_version(void);
+/* Device memory.  Buffers that meshes and operators release are kept by the
+ * library, per device, and handed out again for later requests of about the
+ * same size (a new operator on a mesh of the same size maps no new memory).
+ * This call returns all kept memory to the driver; *freed_bytes (nullable)
+ * receives the amount.  A failing allocation does the same by itself before
+ * it retries once.  Host call; waits for nothing. */
+rfcmp_status rfcmp_release_cached_memory(int64_t* freed_bytes);
 
 /* ------------------------------------------------------------------ mesh */
 typedef struct rfcmp_mesh_s* rfcmp_mesh;
@@ -108,7 +115,10 @@ typedef struct rfcmp_op_s* rfcmp_op;
  * 7x7-point rule in FP32; near pairs (see rfcmp_mesh_near_pairs) extract the
  * 1/R singularity in closed form in FP64.  On the first call for a mesh the
  * projector matrices (L^+ = (Sigma^T Sigma)^+, G_ll^-1, and for outer_star = 1
- * G_tp^-1) are built on the device in FP64 and cached on the mesh.
+ * G_tp^-1) are built on the device in FP64 and cached on the mesh; so are
+ * the near-pair list and the cell-pair scratch of the assembly (complex64
+ * [3C][3C], 72 C^2 bytes), freed with the mesh.  Returns after the
+ * operator's work on `stream` is complete.
  * power_start: device c128 [N], the start vector of the power iterations
  * that estimate alpha, beta, gamma (Sec. 4); required when opt->scaling == 0,
  * ignored otherwise.  opt may be NULL (defaults).  The mesh must outlive the
@@ -198,12 +208,18 @@ rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, doub
 /* Kernel timing for benchmarks.  While enabled, the library records a HIP
  * event pair on the launch stream around every launch of its timed kernels:
  * "far_pairs", "near_pairs", "gather_ta" (assembly), "cmatvec_ta",
- * "cmatvec_v" (complex64 block products), "dmatvec" (FP64 projector
- * products), "spd_inverse" (whole FP64 inverse).  rfcmp_profile_enable
+ * "cmatvec_v" (complex64 block products), "dmatvec_lp", "dmatvec_gll",
+ * "dmatvec_gtp" (FP64 projector products), "gemm_ta", "gemm_v", "gemm_lp",
+ * "gemm_gll", "gemm_gtp" (BF16x3 products), "spd_inverse" (whole FP64
+ * inverse).  rfcmp_profile_enable
  * clears the records (waiting for recorded events first); rfcmp_profile_read
  * waits for the events of one tag and returns their summed duration and
  * count.  Not thread-safe; adds two event records per timed launch. */
 rfcmp_status rfcmp_profile_enable(int32_t on);
+/* Restrict the timed kernels to a comma-separated list of tags (NULL or ""
+ * = all tags), so that a timed region carries event records only where they
+ * are needed.  Kept across rfcmp_profile_enable calls. */
+rfcmp_status rfcmp_profile_select(const char* tags);
 rfcmp_status rfcmp_profile_read(const char* tag, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus

@@ -84,6 +84,8 @@ EXPORTED = {
     "rfcmp_solve": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, ctypes.POINTER(Info)]),
     "rfcmp_profile_enable": (_I32, [_I32]),
     "rfcmp_profile_read": (_I32, [ctypes.c_char_p, _PD, _PI64]),
+    "rfcmp_profile_select": (_I32, [ctypes.c_char_p]),
+    "rfcmp_release_cached_memory": (_I32, [_PI64]),
 }
 
 
@@ -132,6 +134,18 @@ def _dptr(t, dtype=None, numel=None):
 def profile_enable(on=True):
     """rfcmp_profile_enable: start (or stop) HIP-event timing of tagged kernels."""
     _check(lib.rfcmp_profile_enable(int(bool(on))))
+
+
+def release_cached_memory():
+    """rfcmp_release_cached_memory: return kept device memory; bytes freed."""
+    n = ctypes.c_int64(0)
+    _check(lib.rfcmp_release_cached_memory(ctypes.byref(n)))
+    return n.value
+
+
+def profile_select(tags=None):
+    """rfcmp_profile_select: time only the given kernel tags (None: all)."""
+    _check(lib.rfcmp_profile_select(None if not tags else ",".join(tags).encode()))
 
 
 def profile_read(tag):

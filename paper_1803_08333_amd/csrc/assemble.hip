@@ -488,14 +488,19 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   const RuleArgs ra = rule_args();
 
   const int64_t ldB = (int64_t)round_up(3 * C, 64);
-  DevBuf B;
-  RF_TRY(B.alloc(sizeof(float2) * ldB * 3 * C));
-  std::vector<int32_t> pairs;
-  near_pairs(h, op->opt.near_factor, pairs);
-  const long npairs = (long)pairs.size() / 2;
-  DevBuf dp;
-  RF_TRY(dp.alloc(sizeof(int) * pairs.size()));
-  RF_HIP(hipMemcpyAsync(dp.p, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice, s));
+  // scratch and near-pair list live with the mesh: reused by every wavenumber
+  if (!d.pairB.p) RF_TRY(d.pairB.alloc(sizeof(float2) * ldB * 3 * C));
+  DevBuf& B = d.pairB;
+  if (d.near_factor != op->opt.near_factor) {
+    std::vector<int32_t> pairs;
+    near_pairs(h, op->opt.near_factor, pairs);
+    RF_TRY(d.near.alloc(sizeof(int) * std::max<size_t>(pairs.size(), 2)));
+    RF_HIP(hipMemcpy(d.near.p, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice));
+    d.npairs = (int64_t)pairs.size() / 2;
+    d.near_factor = op->opt.near_factor;
+  }
+  const long npairs = (long)d.npairs;
+  DevBuf& dp = d.near;
   RF_HIP(hipMemsetAsync(op->Vb.p, 0, op->Vb.bytes, s));
   RF_HIP(hipMemsetAsync(op->TA.p, 0, op->TA.bytes, s));
 
@@ -521,7 +526,6 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
                      B.as<float2>(), (long)ldB, op->TA.as<float2>(), (long)op->ldA);
   }
   RF_HIP(hipGetLastError());
-  RF_HIP(hipStreamSynchronize(s));  // B and the pair list are released on return
   return RFCMP_OK;
 }
 

@@ -7,7 +7,6 @@
 // are built around wide coalesced row loads and FP64 accumulation, which
 // costs nothing at this arithmetic intensity.
 #include <cmath>
-#include <map>
 
 #include "internal.h"
 
@@ -142,6 +141,10 @@ constexpr int kB = 64;
 // pivots; per pivot the owners publish the pivot column and row to LDS
 // (double-buffered, one barrier per pivot) and every entry is updated:
 //   a_ij -= a_ik a_kj / a_kk,  a_kj /= a_kk,  a_ik = -a_ik / a_kk,  a_kk = 1 / a_kk.
+// Written branch-free: with m_j = a_kj / a_kk (j != k) or 1 / a_kk (j == k),
+// row k becomes m_j and every other entry (j != k ? a_ij : 0) - a_ik m_j.
+// The strip's 16 pivot-column values are read from LDS together, before the
+// updates, so the reads overlap.
 __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld, int K) {
   __shared__ double colk[2][kB], rowk[2][kB];
   const int j = threadIdx.x % kB;
@@ -163,18 +166,17 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld
       rowk[bsel][j] = v;
     }
     __syncthreads();
+    double ck[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) ck[u] = colk[bsel][i0 + u];
     const double d = 1.0 / rowk[bsel][k];
-    const double akj = rowk[bsel][j];
+    const bool pj = (j == k);
+    const double m = pj ? d : rowk[bsel][j] * d;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int i = i0 + u;
-      const double aik = colk[bsel][i];
-      double nv;
-      if (j == k)
-        nv = (i == k) ? d : -aik * d;
-      else
-        nv = (i == k) ? akj * d : r[u] - aik * akj * d;
-      r[u] = nv;
+      const double keep = pj ? 0.0 : r[u];
+      const double nv = fma(-ck[u], m, keep);
+      r[u] = (i0 + u == k) ? m : nv;
     }
   }
 #pragma unroll
@@ -418,21 +420,27 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
     }
     RF_TRY(build(d.Lp, C, d.ldL, 1.0 / double(C), ij, v, true));
   }
-  // G_ll
+  // G_ll: the diagonal sums A/6 over the cells at a vertex; the entry of the
+  // edge (a, b) sums A/12 over its two cells.  Keys are unique, as the
+  // scatter needs.
   {
-    std::map<std::pair<int, int>, double> acc;
+    std::vector<double> diag(V, 0.0);
     for (int64_t c = 0; c < C; ++c)
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          const int a = h.tri[3 * c + i], b = h.tri[3 * c + j];
-          acc[{a, b}] += (i == j) ? h.area[c] / 6.0 : h.area[c] / 12.0;
-        }
+      for (int i = 0; i < 3; ++i) diag[h.tri[3 * c + i]] += h.area[c] / 6.0;
     std::vector<int> ij;
     std::vector<double> v;
-    for (auto& kv : acc) {
-      ij.push_back(kv.first.first);
-      ij.push_back(kv.first.second);
-      v.push_back(kv.second);
+    ij.reserve(2 * (V + 2 * N));
+    v.reserve(V + 2 * N);
+    for (int64_t a = 0; a < V; ++a) {
+      ij.push_back(int(a));
+      ij.push_back(int(a));
+      v.push_back(diag[a]);
+    }
+    for (int64_t n = 0; n < N; ++n) {
+      const int a = h.edge_vtx[2 * n], b = h.edge_vtx[2 * n + 1];
+      const double w = (h.area[h.edge_cell[2 * n]] + h.area[h.edge_cell[2 * n + 1]]) / 12.0;
+      ij.push_back(a); ij.push_back(b); v.push_back(w);
+      ij.push_back(b); ij.push_back(a); v.push_back(w);
     }
     RF_TRY(build(d.Gll_inv, V, d.ldG, 0.0, ij, v, false));
   }

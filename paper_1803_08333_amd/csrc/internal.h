@@ -32,26 +32,36 @@ void clear_error();
     if (s_ < 0) return s_;                 \
   } while (0)
 
-// Owning device buffer.
+// Device memory cache (devmem.cpp): dev_alloc returns a block of at least n
+// bytes on the current device (its size in *got, its device in *device) or
+// nullptr; dev_free puts a block back after the device is idle.
+void* dev_alloc(size_t n, size_t* got, int* device);
+void dev_free(void* p, size_t bytes, int device);
+size_t dev_cache_release();
+size_t dev_cache_bytes();
+
+// Owning device buffer (memory from the library's cache).
 struct DevBuf {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;     // bytes requested
+  size_t capacity = 0;  // bytes of the block
+  int device = -1;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p, capacity, device);
     p = nullptr;
-    bytes = 0;
+    bytes = capacity = 0;
+    device = -1;
   }
   rfcmp_status alloc(size_t n) {
     release();
     if (n == 0) return RFCMP_OK;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) {
-      p = nullptr;
-      set_error("hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+    p = dev_alloc(n, &capacity, &device);
+    if (!p) {
+      set_error("device allocation of %zu bytes failed", n);
       return RFCMP_E_OOM;
     }
     bytes = n;
@@ -65,6 +75,7 @@ inline size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
 // Optional kernel timing for benchmarks: when enabled, a start/stop HIP event
 // pair is recorded on the launch stream around each tagged launch.
 bool profiling_enabled();
+bool profiling_selected(const char* tag);
 void profile_record(const char* tag, hipEvent_t start, hipEvent_t stop);
 hipEvent_t profile_event();
 struct ProfScope {
@@ -72,7 +83,7 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(const char* t, hipStream_t st) : tag(t), s(st) {
-    if (profiling_enabled()) {
+    if (profiling_enabled() && profiling_selected(t)) {
       a = profile_event();
       b = profile_event();
       if (a && b) (void)hipEventRecord(a, s);
@@ -130,6 +141,10 @@ struct MeshDev {
   DevBuf Gll_inv;    // double [ldG][ldG]
   DevBuf Gtp_inv;    // double [ldT][ldT]
   std::unique_ptr<SplitMatrix> Lp16, Gll16, Gtp16;  // BF16x3 planes, built on demand
+  double near_factor = -1.0;  // factor of the cached near-pair list
+  int64_t npairs = 0;
+  DevBuf near;       // int [npairs][2]
+  DevBuf pairB;      // complex64 [3C][ldB] cell-pair block scratch of the assembly
   MeshDev();
   ~MeshDev();
 };

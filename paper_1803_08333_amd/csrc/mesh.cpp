@@ -8,7 +8,6 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
-#include <unordered_map>
 
 #include "internal.h"
 
@@ -232,42 +231,66 @@ rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, 
 void near_pairs(const MeshHost& h, double factor, std::vector<int32_t>& out) {
   out.clear();
   const int64_t C = h.C;
+  if (C == 0) return;
   double hm = 0;
   for (double x : h.hmax) hm = std::max(hm, x);
-  const double bin = factor * hm * (1.0 + 1e-9);
-  double lo[3] = {1e300, 1e300, 1e300};
+  // uniform grid of bins no smaller than the largest threshold: every near
+  // pair lies in the same or an adjacent bin
+  double bin = factor * hm * (1.0 + 1e-9);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t c = 0; c < C; ++c)
-    for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], h.centroid[3 * c + d]);
-  auto key = [](int64_t x, int64_t y, int64_t z) { return (x * 2097152 + y) * 2097152 + z; };
-  std::unordered_map<int64_t, std::vector<int32_t>> grid;
-  std::vector<int64_t> cb(3 * C);
-  for (int64_t c = 0; c < C; ++c) {
-    for (int d = 0; d < 3; ++d) cb[3 * c + d] = int64_t(std::floor((h.centroid[3 * c + d] - lo[d]) / bin));
-    grid[key(cb[3 * c], cb[3 * c + 1], cb[3 * c + 2])].push_back(int32_t(c));
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], h.centroid[3 * c + d]);
+      hi[d] = std::max(hi[d], h.centroid[3 * c + d]);
+    }
+  // larger bins (never smaller ones) keep the grid within about 8 bins per cell
+  int64_t nb[3];
+  for (;;) {
+    for (int d = 0; d < 3; ++d) nb[d] = int64_t((hi[d] - lo[d]) / bin) + 1;
+    if ((double)nb[0] * (double)nb[1] * (double)nb[2] <= 8.0 * double(C) + 64.0) break;
+    bin *= 1.25;
   }
-  std::vector<int32_t> cand;
+  auto coord = [&](int64_t c, int d) {
+    return std::min<int64_t>(int64_t((h.centroid[3 * c + d] - lo[d]) / bin), nb[d] - 1);
+  };
+  const int64_t nbins = nb[0] * nb[1] * nb[2];
+  std::vector<int32_t> cbin(C), start(nbins + 1, 0), cells(C);
   for (int64_t c = 0; c < C; ++c) {
-    cand.clear();
-    for (int dx = -1; dx <= 1; ++dx)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dz = -1; dz <= 1; ++dz) {
-          auto it = grid.find(key(cb[3 * c] + dx, cb[3 * c + 1] + dy, cb[3 * c + 2] + dz));
-          if (it == grid.end()) continue;
-          for (int32_t o : it->second)
-            if (o >= c) cand.push_back(o);
+    cbin[c] = int32_t((coord(c, 0) * nb[1] + coord(c, 1)) * nb[2] + coord(c, 2));
+    ++start[cbin[c] + 1];
+  }
+  for (int64_t b = 0; b < nbins; ++b) start[b + 1] += start[b];
+  {
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (int64_t c = 0; c < C; ++c) cells[fill[cbin[c]]++] = int32_t(c);  // ascending within a bin
+  }
+  std::vector<int32_t> hit;
+  for (int64_t c = 0; c < C; ++c) {
+    hit.clear();
+    const int64_t b = cbin[c];
+    const int64_t bx = b / (nb[1] * nb[2]), by = (b / nb[2]) % nb[1], bz = b % nb[2];
+    const double* pc = &h.centroid[3 * c];
+    for (int64_t x = std::max<int64_t>(bx - 1, 0); x <= std::min(bx + 1, nb[0] - 1); ++x)
+      for (int64_t y = std::max<int64_t>(by - 1, 0); y <= std::min(by + 1, nb[1] - 1); ++y)
+        for (int64_t z = std::max<int64_t>(bz - 1, 0); z <= std::min(bz + 1, nb[2] - 1); ++z) {
+          const int64_t q = (x * nb[1] + y) * nb[2] + z;
+          for (int32_t i = start[q]; i < start[q + 1]; ++i) {
+            const int32_t o = cells[i];
+            if (o < c) continue;
+            const double* po = &h.centroid[3 * int64_t(o)];
+            double d2 = 0;
+            for (int d = 0; d < 3; ++d) {
+              const double t = pc[d] - po[d];
+              d2 += t * t;
+            }
+            const double thr = factor * std::max(h.hmax[c], h.hmax[o]) * (1.0 + 1e-9);
+            if (std::sqrt(d2) < thr) hit.push_back(o);
+          }
         }
-    std::sort(cand.begin(), cand.end());
-    for (int32_t o : cand) {
-      double d2 = 0;
-      for (int d = 0; d < 3; ++d) {
-        double t = h.centroid[3 * c + d] - h.centroid[3 * int64_t(o) + d];
-        d2 += t * t;
-      }
-      double thr = factor * std::max(h.hmax[c], h.hmax[o]) * (1.0 + 1e-9);
-      if (std::sqrt(d2) < thr) {
-        out.push_back(int32_t(c));
-        out.push_back(o);
-      }
+    std::sort(hit.begin(), hit.end());
+    for (int32_t o : hit) {
+      out.push_back(int32_t(c));
+      out.push_back(o);
     }
   }
 }

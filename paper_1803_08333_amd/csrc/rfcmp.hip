@@ -574,6 +574,7 @@ namespace rfcmp {
 namespace {
 struct ProfState {
   bool on = false;
+  std::vector<std::string> only;  // empty: every tag
   std::vector<hipEvent_t> pool;  // all events ever created (reused)
   size_t next = 0;
   std::vector<std::tuple<std::string, hipEvent_t, hipEvent_t>> rec;
@@ -584,6 +585,13 @@ ProfState& prof() {
 }
 }  // namespace
 bool profiling_enabled() { return prof().on; }
+bool profiling_selected(const char* tag) {
+  const ProfState& p = prof();
+  if (p.only.empty()) return true;
+  for (const auto& t : p.only)
+    if (t == tag) return true;
+  return false;
+}
 hipEvent_t profile_event() {
   ProfState& p = prof();
   if (p.next == p.pool.size()) {
@@ -617,6 +625,23 @@ rfcmp_status rfcmp_profile_enable(int32_t on) {
   p.rec.clear();
   p.next = 0;
   p.on = on != 0;
+  return RFCMP_OK;
+}
+
+rfcmp_status rfcmp_profile_select(const char* tags) {
+  ProfState& p = prof();
+  p.only.clear();
+  if (!tags) return RFCMP_OK;
+  std::string cur;
+  for (const char* c = tags;; ++c) {
+    if (*c == ',' || *c == 0) {
+      if (!cur.empty()) p.only.push_back(cur);
+      cur.clear();
+      if (*c == 0) break;
+    } else {
+      cur += *c;
+    }
+  }
   return RFCMP_OK;
 }
 
