@@ -207,12 +207,14 @@ def main():
     pairs_per_s = C * C / (asm_ms / 1e3)
 
     # roofline of the dominant kernel (largest total time)
+    # symmetric products: the algorithmic bytes are the n (n + 1) / 2 distinct
+    # entries (8 B each) plus x read and y written (16 B each, complex128)
     def model(tag, avg_ms):
         if tag == "cmatvec_ta":
-            byt = 8.0 * N * N + 32.0 * N
+            byt = 8.0 * N * (N + 1) / 2 + 32.0 * N
             return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s"}
         if tag in ("cmatvec_v", "dmatvec_lp"):
-            byt = 8.0 * C * C + 32.0 * C
+            byt = 8.0 * C * (C + 1) / 2 + 32.0 * C
             return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s"}
         if tag == "far_pairs":
             fl = C * (C - 1) / 2 * 49 * FAR_FLOPS_PER_POINT_PAIR

@@ -1,11 +1,5 @@
-// Dense kernels: streaming matrix-vector products and the FP64 inverse used
-// to build the projector matrices.
-//
-// The RF-CMP iteration streams two complex64 blocks (T_A, V) and the dense
-// FP64 projector matrices (L^+ = (Sigma^T Sigma)^+, G_ll^-1) once per use:
-// every product here is HBM-bound (about one flop per byte), so the kernels
-// are built around wide coalesced row loads and FP64 accumulation, which
-// costs nothing at this arithmetic intensity.
+// The FP64 inverse used to build the dense projector matrices
+// (L^+ = (Sigma^T Sigma)^+, G_ll^-1, G_tp^-1) of a mesh.
 #include <cmath>
 
 #include "internal.h"
@@ -13,120 +7,6 @@
 namespace rfcmp {
 
 namespace {
-
-constexpr int kWave = 64;
-typedef float vf4 __attribute__((ext_vector_type(4)));
-typedef double vd2 __attribute__((ext_vector_type(2)));
-constexpr int kRowsPerWave = 4;                  // rows sharing each x value read from LDS
-constexpr int kWavesPerBlock = 2;
-constexpr int kThreads = kWave * kWavesPerBlock;
-constexpr int kRowsPerBlock = kRowsPerWave * kWavesPerBlock;
-
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-
-// y[r][row] = sum_j M[row][j] x[r][j];  M complex64 rows padded to ld (a
-// multiple of 64 entries, padding zero); x, y complex128.  Each wave owns
-// kRowsPerWave rows and reads two entries (16 B) per lane per row and step;
-// x (L2-resident) is read directly, each value serving all the wave's rows,
-// so the stream never stops at a barrier.
-template <int NR, bool CONJ>
-__global__ __launch_bounds__(kThreads) void k_cmatvec(const float2* __restrict__ M, int n, long ld,
-                                                      const double2* __restrict__ x,
-                                                      double2* __restrict__ y) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int row0 = blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
-  double accr[kRowsPerWave][NR], acci[kRowsPerWave][NR];
-#pragma unroll
-  for (int i = 0; i < kRowsPerWave; ++i)
-#pragma unroll
-    for (int r = 0; r < NR; ++r) accr[i][r] = acci[i][r] = 0.0;
-  const vf4* mr[kRowsPerWave];
-#pragma unroll
-  for (int i = 0; i < kRowsPerWave; ++i)
-    mr[i] = reinterpret_cast<const vf4*>(M + (long)min(row0 + i, n - 1) * ld);
-  const int npair = (n + 1) / 2;  // float4 columns; the last may hold one padding entry
-#pragma unroll 2
-  for (int p = lane; p < npair; p += kWave) {
-    const int jj = 2 * p;
-    vf4 m[kRowsPerWave];
-#pragma unroll
-    for (int i = 0; i < kRowsPerWave; ++i) m[i] = __builtin_nontemporal_load(mr[i] + p);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double2 x0 = x[(long)r * n + jj];
-      const double2 x1 = (jj + 1 < n) ? x[(long)r * n + jj + 1] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int i = 0; i < kRowsPerWave; ++i) {
-        const double a0 = m[i].x, b0 = CONJ ? -(double)m[i].y : (double)m[i].y;
-        const double a1 = m[i].z, b1 = CONJ ? -(double)m[i].w : (double)m[i].w;
-        accr[i][r] += a0 * x0.x - b0 * x0.y + a1 * x1.x - b1 * x1.y;
-        acci[i][r] += a0 * x0.y + b0 * x0.x + a1 * x1.y + b1 * x1.x;
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < kRowsPerWave; ++i) {
-    const int row = row0 + i;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double sr = wave_sum(accr[i][r]);
-      const double si = wave_sum(acci[i][r]);
-      if (lane == 0 && row < n) y[(long)r * n + row] = make_double2(sr, si);
-    }
-  }
-}
-
-// y[r][row] = sum_j M[row][j] x[r][j];  M real FP64 [n][ld] (ld a multiple of
-// 64, padding zero); x, y complex128.  Same structure as k_cmatvec.
-template <int NR>
-__global__ __launch_bounds__(kThreads) void k_dmatvec(const double* __restrict__ M, int n, long ld,
-                                                      const double2* __restrict__ x,
-                                                      double2* __restrict__ y) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int row0 = blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
-  double accr[kRowsPerWave][NR], acci[kRowsPerWave][NR];
-#pragma unroll
-  for (int i = 0; i < kRowsPerWave; ++i)
-#pragma unroll
-    for (int r = 0; r < NR; ++r) accr[i][r] = acci[i][r] = 0.0;
-  const vd2* mr[kRowsPerWave];
-#pragma unroll
-  for (int i = 0; i < kRowsPerWave; ++i)
-    mr[i] = reinterpret_cast<const vd2*>(M + (long)min(row0 + i, n - 1) * ld);
-  const int npair = (n + 1) / 2;
-#pragma unroll 2
-  for (int p = lane; p < npair; p += kWave) {
-    const int jj = 2 * p;
-    vd2 m[kRowsPerWave];
-#pragma unroll
-    for (int i = 0; i < kRowsPerWave; ++i) m[i] = __builtin_nontemporal_load(mr[i] + p);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double2 x0 = x[(long)r * n + jj];
-      const double2 x1 = (jj + 1 < n) ? x[(long)r * n + jj + 1] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int i = 0; i < kRowsPerWave; ++i) {
-        accr[i][r] += m[i].x * x0.x + m[i].y * x1.x;
-        acci[i][r] += m[i].x * x0.y + m[i].y * x1.y;
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < kRowsPerWave; ++i) {
-    const int row = row0 + i;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double sr = wave_sum(accr[i][r]);
-      const double si = wave_sum(acci[i][r]);
-      if (lane == 0 && row < n) y[(long)r * n + row] = make_double2(sr, si);
-    }
-  }
-}
 
 // ------------------------------------------------------------------------
 // Blocked Gauss-Jordan inverse of an SPD matrix (no pivoting: every Schur
@@ -301,50 +181,6 @@ __global__ void k_sub_const(double* __restrict__ A, long ld, long nvalid, double
 inline unsigned blocks_for(long n, int per) { return unsigned((n + per - 1) / per); }
 
 }  // namespace
-
-rfcmp_status cmatvec(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y,
-                     int nrhs, hipStream_t s, const char* tag) {
-  for (int r0 = 0; r0 < nrhs; r0 += 4) {
-    ProfScope prof(tag, s);
-    const int nr = std::min(4, nrhs - r0);
-    const double2* xr = x + (long)r0 * n;
-    double2* yr = y + (long)r0 * n;
-    dim3 grid(blocks_for(n, kRowsPerBlock));
-#define RF_CMV(NRV)                                                                              \
-  if (conj)                                                                                     \
-    hipLaunchKernelGGL((k_cmatvec<NRV, true>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); \
-  else                                                                                          \
-    hipLaunchKernelGGL((k_cmatvec<NRV, false>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr);
-    switch (nr) {
-      case 1: RF_CMV(1) break;
-      case 2: RF_CMV(2) break;
-      case 3: RF_CMV(3) break;
-      default: RF_CMV(4) break;
-    }
-#undef RF_CMV
-  }
-  RF_HIP(hipGetLastError());
-  return RFCMP_OK;
-}
-
-rfcmp_status dmatvec(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
-                     hipStream_t s, const char* tag) {
-  for (int r0 = 0; r0 < nrhs; r0 += 4) {
-    ProfScope prof(tag, s);
-    const int nr = std::min(4, nrhs - r0);
-    const double2* xr = x + (long)r0 * n;
-    double2* yr = y + (long)r0 * n;
-    dim3 grid(blocks_for(n, kRowsPerBlock));
-    switch (nr) {
-      case 1: hipLaunchKernelGGL((k_dmatvec<1>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); break;
-      case 2: hipLaunchKernelGGL((k_dmatvec<2>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); break;
-      case 3: hipLaunchKernelGGL((k_dmatvec<3>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); break;
-      default: hipLaunchKernelGGL((k_dmatvec<4>), grid, dim3(kThreads), 0, s, M, (int)n, (long)ld, xr, yr); break;
-    }
-  }
-  RF_HIP(hipGetLastError());
-  return RFCMP_OK;
-}
 
 rfcmp_status spd_inverse(double* A, int64_t n, hipStream_t s) {
   if (n % kB != 0) {

@@ -173,6 +173,7 @@ struct rfcmp_op_s {
   double* host_scal = nullptr;  // pinned, 16 + 8 * work_nrhs doubles
   std::unique_ptr<rfcmp::SplitMatrix> TA16, V16;  // BF16x3 planes (precision 1)
   rfcmp::DevBuf gemm_scratch;
+  rfcmp::DevBuf symv_scratch;  // partial sums of the symmetric products
 };
 
 namespace rfcmp {
@@ -189,12 +190,15 @@ rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, i
 
 // dense.hip
 rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s);
-// y[r] = M x[r] for r < nrhs; M complex64 [n][ld]; x, y complex128 [nrhs][n]
-rfcmp_status cmatvec(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y,
-                     int nrhs, hipStream_t s, const char* tag = "cmatvec");
-// y[r] = M x[r]; M real FP64 [n][ld]; x, y complex128 [nrhs][n]
-rfcmp_status dmatvec(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
-                     hipStream_t s, const char* tag = "dmatvec");
+// symv.hip: y[r] = M x[r] for a symmetric M (M = M^T, complex-symmetric for
+// the complex64 case), reading the upper block triangle of M only.  Scratch:
+// symv_scratch_bytes(n, nrhs) bytes of device memory (partial sums); calls
+// sharing a scratch must not overlap.
+size_t symv_scratch_bytes(int64_t n, int nrhs);
+rfcmp_status csymv(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y, int nrhs,
+                   void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag = "csymv");
+rfcmp_status dsymv(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
+                   void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag = "dsymv");
 // In-place inverse of an SPD matrix, FP64, n padded to a multiple of 64.
 rfcmp_status spd_inverse(double* A, int64_t n, hipStream_t s);
 

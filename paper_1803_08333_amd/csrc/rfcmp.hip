@@ -90,6 +90,10 @@ rfcmp_status ensure_work(rfcmp_op op, int R) {
   return RFCMP_OK;
 }
 
+// Scratch of the symmetric products (partial sums), sized at creation for
+// the largest matrix and four right-hand sides per pass.
+#define SYMV op->symv_scratch.p, op->symv_scratch.bytes
+
 // ------------------------------------------------------------------ dense products
 // The five dense products of the operator, in complex64/FP64 (FP64
 // accumulation, <= 4 right-hand sides per matrix pass) or as BF16x3 MFMA
@@ -101,30 +105,30 @@ struct Dense {
   rfcmp_status ta(bool conj, const double2* x, double2* y, int nr) const {
     if (bf16)
       return gemm_bf16x3(*op->TA16, conj, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_ta");
-    return cmatvec(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj, x, y, nr, s, "cmatvec_ta");
+    return csymv(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj, x, y, nr, SYMV, s, "cmatvec_ta");
   }
   rfcmp_status v(bool conj, const double2* x, double2* y, int nr) const {
     if (bf16)
       return gemm_bf16x3(*op->V16, conj, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_v");
-    return cmatvec(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj, x, y, nr, s, "cmatvec_v");
+    return csymv(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj, x, y, nr, SYMV, s, "cmatvec_v");
   }
   rfcmp_status lp(const double2* x, double2* y, int nr) const {
     const MeshDev& d = op->mesh->d;
     if (bf16)
       return gemm_bf16x3(*d.Lp16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_lp");
-    return dmatvec(d.Lp.as<double>(), op->mesh->h.C, d.ldL, x, y, nr, s, "dmatvec_lp");
+    return dsymv(d.Lp.as<double>(), op->mesh->h.C, d.ldL, x, y, nr, SYMV, s, "dmatvec_lp");
   }
   rfcmp_status gll(const double2* x, double2* y, int nr) const {
     const MeshDev& d = op->mesh->d;
     if (bf16)
       return gemm_bf16x3(*d.Gll16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_gll");
-    return dmatvec(d.Gll_inv.as<double>(), op->mesh->h.V, d.ldG, x, y, nr, s, "dmatvec_gll");
+    return dsymv(d.Gll_inv.as<double>(), op->mesh->h.V, d.ldG, x, y, nr, SYMV, s, "dmatvec_gll");
   }
   rfcmp_status gtp(const double2* x, double2* y, int nr) const {
     const MeshDev& d = op->mesh->d;
     if (bf16)
       return gemm_bf16x3(*d.Gtp16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_gtp");
-    return dmatvec(d.Gtp_inv.as<double>(), op->mesh->h.C, d.ldT, x, y, nr, s, "dmatvec_gtp");
+    return dsymv(d.Gtp_inv.as<double>(), op->mesh->h.C, d.ldT, x, y, nr, SYMV, s, "dmatvec_gtp");
   }
 };
 
@@ -741,10 +745,10 @@ rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt, c
   const int64_t N = m->h.N, C = m->h.C, V = m->h.V;
   op->ldA = (int64_t)round_up(N, 64);
   op->ldV = (int64_t)round_up(C, 64);
-  (void)V;
   RF_TRY(op->TA.alloc(sizeof(float2) * N * op->ldA));
   RF_TRY(op->Vb.alloc(sizeof(float2) * C * op->ldV));
   RF_TRY(ensure_work(op.get(), 4));
+  RF_TRY(op->symv_scratch.alloc(symv_scratch_bytes(std::max(N, std::max(C, V)), 4)));
   RF_TRY(assemble_blocks(op.get(), s));
   op->alpha = std::sqrt(k);
   op->beta = 1.0 / std::sqrt(k);
@@ -862,19 +866,19 @@ rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* xv, void* yv,
                      case RFCMP_PROJ_SIGMA:
                      case RFCMP_PROJ_LH:
                        RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-                       RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, s, "dmatvec_lp"));
+                       RF_TRY(dsymv(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, SYMV, s, "dmatvec_lp"));
                        return which == RFCMP_PROJ_SIGMA
                                   ? axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[1], y, nr, s)
                                   : axpy_sigma(d, N, C, 1.0, false, x, -1.0, W.c[1], y, nr, s);
                      case RFCMP_PROJ_GSIGMA:
                        RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-                       RF_TRY(dmatvec(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, s, "dmatvec_gtp"));
-                       RF_TRY(dmatvec(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[1], nr, s, "dmatvec_lp"));
+                       RF_TRY(dsymv(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, SYMV, s, "dmatvec_gtp"));
+                       RF_TRY(dsymv(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[1], nr, SYMV, s, "dmatvec_lp"));
                        return axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[1], y, nr, s);
                      case RFCMP_PROJ_LPINV:
-                       return dmatvec(d.Lp.as<double>(), C, d.ldL, x, y, nr, s);
+                       return dsymv(d.Lp.as<double>(), C, d.ldL, x, y, nr, SYMV, s, "dmatvec_lp");
                      case RFCMP_PROJ_GLL_INV:
-                       return dmatvec(d.Gll_inv.as<double>(), V, d.ldG, x, y, nr, s);
+                       return dsymv(d.Gll_inv.as<double>(), V, d.ldG, x, y, nr, SYMV, s, "dmatvec_gll");
                      case RFCMP_PROJ_SIGMA_T:
                        return sigma_t(d, C, N, x, y, nr, s);
                      default:
@@ -890,8 +894,10 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double2* xx = static_cast<const double2*>(x);
   double2* yy = static_cast<double2*>(y);
-  if (which == 0) return cmatvec(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, xx, yy, nrhs, s);
-  if (which == 1) return cmatvec(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj != 0, xx, yy, nrhs, s);
+  if (which == 0)
+    return csymv(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, xx, yy, nrhs, SYMV, s, "cmatvec_ta");
+  if (which == 1)
+    return csymv(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj != 0, xx, yy, nrhs, SYMV, s, "cmatvec_v");
   RF_TRY(ensure_split(op, s));
   const Dense D{op, s, true};
   switch (which) {

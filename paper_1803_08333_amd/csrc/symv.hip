@@ -1,0 +1,310 @@
+// Symmetric streaming matrix-vector products.
+//
+// Every dense matrix the operator applies is symmetric: T_A and V are
+// complex-symmetric Galerkin blocks (T_A = T_A^T, V = V^T), and L^+, G_ll^-1
+// and G_tp^-1 are real symmetric.  The products are HBM-bound (about one flop
+// per byte), so reading each off-diagonal entry once and using it for two
+// outputs halves the time:  with the matrix cut into S x S blocks,
+//   block (P, Q), P < Q:  y_P += M_PQ x_Q   and   y_Q += M_PQ^T x_P,
+//   block (P, P):         y_P += M_PP x_P   (read whole),
+// only blocks with Q >= P are read.  Each workgroup owns one block and writes
+// its two partial outputs to a slot of a partial buffer, part[K][L] = the
+// contribution to output block K from the block pairing K with L; a second
+// kernel sums the slots of each output block in a fixed order.  The result
+// is deterministic (no atomics) and the matrix is read from its upper block
+// triangle only.
+//
+// A block is streamed in sub-tiles of 32 rows x S columns: each thread loads
+// 16-byte column pairs of several rows into registers (coalesced: a wave
+// reads a whole row), accumulates the transposed product M^T x_P for its
+// column pair straight from registers, and stores the sub-tile to LDS, from
+// where eight threads per row form the row sums M x_Q (thread s of a row
+// takes pairs s, s + 8, ..., so a row's threads read adjacent LDS words).
+// Two sub-tiles are in flight per workgroup: the loads of sub-tile t + 2 are
+// issued as soon as sub-tile t sits in LDS.  Products are formed
+// and accumulated in FP64 (complex64 entries are widened), x and y are
+// complex128.
+#include "internal.h"
+
+namespace rfcmp {
+
+namespace {
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+constexpr int kThreads = 256;
+constexpr int kRowsSub = 32;   // rows per sub-tile
+constexpr int kMaxNR = 4;      // right-hand sides per pass
+
+// Entry e (0, 1) of a 16-byte column pair, widened to FP64 (re, im).
+struct C64 {
+  typedef vf4 Pair;
+  __device__ static inline Pair first_only(Pair v) {
+    v.z = 0.0f;
+    v.w = 0.0f;
+    return v;
+  }
+  template <bool CONJ>
+  __device__ static inline void entry(const Pair& v, int e, double& re, double& im) {
+    re = e ? (double)v.z : (double)v.x;
+    const double t = e ? (double)v.w : (double)v.y;
+    im = CONJ ? -t : t;
+  }
+};
+struct F64 {
+  typedef vd2 Pair;
+  __device__ static inline Pair first_only(Pair v) {
+    v.y = 0.0;
+    return v;
+  }
+  template <bool CONJ>
+  __device__ static inline void entry(const Pair& v, int e, double& re, double& im) {
+    re = e ? v.y : v.x;
+    im = 0.0;
+  }
+};
+
+template <class T>
+__device__ inline typename T::Pair zero_pair() {
+  typename T::Pair z;
+  z = 0;
+  return z;
+}
+
+// Partial buffer layout: part[((K * nsb + L) * NR + r) * S + i], complex128.
+template <class T, int S, int NR, bool CONJ>
+__global__ __launch_bounds__(kThreads) void k_symv(const typename T::Pair* __restrict__ M, int n, long ldp,
+                                                   int nsb, const double2* __restrict__ x,
+                                                   double2* __restrict__ part) {
+  typedef typename T::Pair Pair;
+  constexpr int PP = S / 2;                       // column pairs per row
+  constexpr int G = kThreads / PP;                // row groups in the load layout
+  constexpr int LPT = kRowsSub / G;               // loads per thread per sub-tile
+  constexpr int NSUB = S / kRowsSub;              // sub-tiles per block
+  constexpr int TPR = kThreads / kRowsSub;        // threads per row in the row sums
+  constexpr int PPT = PP / TPR;                   // pairs per thread in the row sums
+  static_assert(kRowsSub % G == 0 && PP % TPR == 0 && NSUB % 2 == 0, "block shape");
+
+  // block (P, Q), Q >= P, from the linear upper-triangle index
+  int P = 0, rem = blockIdx.x;
+  while (rem >= nsb - P) {
+    rem -= nsb - P;
+    ++P;
+  }
+  const int Q = P + rem;
+  const bool diag = (P == Q);
+
+  __shared__ Pair tile[kRowsSub][PP + 1];
+  __shared__ double2 xs[2][NR][S];  // x_P (rows), x_Q (columns)
+  const int tid = threadIdx.x;
+
+  // load layout: column pair p, rows g0 + G q
+  const int p = tid % PP, g0 = tid / PP;
+  const int gc = Q * S + 2 * p;  // first global column of the pair
+  const bool c0 = gc < n, c1 = gc + 1 < n;
+  Pair ra[LPT], rb[LPT];  // two sub-tiles in flight
+  auto load = [&](Pair(&reg)[LPT], int sub) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int gr = P * S + sub * kRowsSub + g0 + G * q;
+      Pair v = zero_pair<T>();
+      if (gr < n && c0) v = __builtin_nontemporal_load(M + (long)gr * ldp + (gc >> 1));
+      reg[q] = c1 ? v : T::first_only(v);  // a column beyond n reads as zero
+    }
+  };
+  load(ra, 0);
+  load(rb, 1);
+  for (int t = tid; t < 2 * NR * S; t += kThreads) {
+    const int side = t / (NR * S), r = (t / S) % NR, i = t % S;
+    const int g = (side == 0 ? P : Q) * S + i;
+    xs[side][r][i] = (g < n) ? x[(long)r * n + g] : make_double2(0.0, 0.0);
+  }
+
+  double cr[2][NR], ci[2][NR];  // transposed sums of the two columns
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) cr[e][r] = ci[e][r] = 0.0;
+  const int rrow = tid / TPR, seg = tid % TPR;  // row-sum layout
+  __syncthreads();  // xs ready
+
+  auto consume = [&](Pair(&reg)[LPT], int sub) {
+    if (!diag) {
+#pragma unroll
+      for (int q = 0; q < LPT; ++q) {
+        const int lr = sub * kRowsSub + g0 + G * q;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          double ar, ai;
+          T::template entry<CONJ>(reg[q], e, ar, ai);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double2 xv = xs[0][r][lr];
+            cr[e][r] = fma(ar, xv.x, fma(-ai, xv.y, cr[e][r]));
+            ci[e][r] = fma(ar, xv.y, fma(ai, xv.x, ci[e][r]));
+          }
+        }
+      }
+    }
+    __syncthreads();  // the previous row sums are done with the tile
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) tile[g0 + G * q][p] = reg[q];
+    if (sub + 2 < NSUB) load(reg, sub + 2);
+    __syncthreads();
+    double rr[NR], ri[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) rr[r] = ri[r] = 0.0;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int pc = seg + TPR * u;  // neighbouring threads read neighbouring pairs
+      const Pair v = tile[rrow][pc];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        double ar, ai;
+        T::template entry<CONJ>(v, e, ar, ai);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double2 xv = xs[1][r][2 * pc + e];
+          rr[r] = fma(ar, xv.x, fma(-ai, xv.y, rr[r]));
+          ri[r] = fma(ar, xv.y, fma(ai, xv.x, ri[r]));
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+      for (int o = TPR / 2; o > 0; o >>= 1) {
+        rr[r] += __shfl_xor(rr[r], o, 64);
+        ri[r] += __shfl_xor(ri[r], o, 64);
+      }
+    }
+    if (seg == 0) {
+      const int i = sub * kRowsSub + rrow;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        part[(((long)P * nsb + Q) * NR + r) * S + i] = make_double2(rr[r], ri[r]);
+    }
+  };
+#pragma unroll 1
+  for (int sub = 0; sub < NSUB; sub += 2) {
+    consume(ra, sub);
+    consume(rb, sub + 1);
+  }
+
+  if (!diag) {
+    // reduce the transposed sums over the G row groups through LDS
+    __syncthreads();
+    double2* red = reinterpret_cast<double2*>(&tile[0][0]);  // [G][S][NR]
+    static_assert(sizeof(double2) * G * S * NR <= sizeof(Pair) * kRowsSub * (PP + 1), "reduction fits the tile");
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) red[(g0 * S + 2 * p + e) * NR + r] = make_double2(cr[e][r], ci[e][r]);
+    __syncthreads();
+    for (int t = tid; t < S * NR; t += kThreads) {
+      const int c = t % S, r = t / S;
+      double sr = 0.0, si = 0.0;
+      for (int g = 0; g < G; ++g) {
+        const double2 v = red[(g * S + c) * NR + r];
+        sr += v.x;
+        si += v.y;
+      }
+      part[(((long)Q * nsb + P) * NR + r) * S + c] = make_double2(sr, si);
+    }
+  }
+}
+
+// y[r][K S + i] = sum over L (in order) of part[K][L][r][i].  Workgroup
+// (K, r): four threads per row each add a quarter of the slots (unrolled, so
+// the loads overlap), then the quarters are added in order through LDS.
+template <int S, int NR>
+__global__ __launch_bounds__(4 * S) void k_symv_reduce(int n, int nsb, const double2* __restrict__ part,
+                                                       double2* __restrict__ y) {
+  __shared__ double2 q4[4][S];
+  const int K = blockIdx.x, r = blockIdx.y;
+  const int i = threadIdx.x % S, qt = threadIdx.x / S;
+  const int per = (nsb + 3) / 4;
+  const int L0 = qt * per, L1 = min(nsb, L0 + per);
+  const double2* src = part + (((long)K * nsb) * NR + r) * S + i;
+  double sr = 0.0, si = 0.0;
+#pragma unroll 4
+  for (int L = L0; L < L1; ++L) {
+    const double2 v = src[(long)L * NR * S];
+    sr += v.x;
+    si += v.y;
+  }
+  q4[qt][i] = make_double2(sr, si);
+  __syncthreads();
+  const int row = K * S + i;
+  if (qt == 0 && row < n) {
+    double2 t = q4[0][i];
+    for (int u = 1; u < 4; ++u) {
+      t.x += q4[u][i].x;
+      t.y += q4[u][i].y;
+    }
+    y[(long)r * n + row] = t;
+  }
+}
+
+constexpr int kS = 128;
+
+template <class T, int NR, bool CONJ>
+void launch(const void* M, int n, long ld, int nsb, const double2* x, double2* part, double2* y, hipStream_t s) {
+  const long nblk = (long)nsb * (nsb + 1) / 2;
+  hipLaunchKernelGGL((k_symv<T, kS, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s,
+                     static_cast<const typename T::Pair*>(M), n, ld / 2, nsb, x, part);
+  hipLaunchKernelGGL((k_symv_reduce<kS, NR>), dim3((unsigned)nsb, NR), dim3(4 * kS), 0, s, n, nsb, part, y);
+}
+
+template <class T, bool CONJ>
+rfcmp_status symv_any(const void* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
+                      void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag) {
+  if (n <= 0 || nrhs <= 0) return RFCMP_OK;
+  if (ld % 2 != 0) {
+    set_error("symv: leading dimension %lld is odd", (long long)ld);
+    return RFCMP_E_ARG;
+  }
+  const int nsb = int((n + kS - 1) / kS);
+  if (symv_scratch_bytes(n, std::min(nrhs, kMaxNR)) > scratch_bytes) {
+    set_error("symv: n = %lld needs more scratch than the %zu bytes given", (long long)n, scratch_bytes);
+    return RFCMP_E_ARG;
+  }
+  double2* part = static_cast<double2*>(scratch);
+  for (int r0 = 0; r0 < nrhs; r0 += kMaxNR) {
+    ProfScope prof(tag, s);
+    const int nr = std::min(kMaxNR, nrhs - r0);
+    const double2* xr = x + (long)r0 * n;
+    double2* yr = y + (long)r0 * n;
+    switch (nr) {
+      case 1: launch<T, 1, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s); break;
+      case 2: launch<T, 2, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s); break;
+      case 3: launch<T, 3, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s); break;
+      default: launch<T, 4, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s); break;
+    }
+  }
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+
+}  // namespace
+
+size_t symv_scratch_bytes(int64_t n, int nrhs) {
+  const int64_t nsb = (n + kS - 1) / kS;
+  const int nr = std::min(std::max(nrhs, 1), kMaxNR);
+  return sizeof(double2) * (size_t)(nsb * nsb * nr * kS);
+}
+
+rfcmp_status csymv(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y, int nrhs,
+                   void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag) {
+  // ld counts complex entries; the kernels address 16-byte pairs (two entries)
+  if (conj) return symv_any<C64, true>(M, n, ld, x, y, nrhs, scratch, scratch_bytes, s, tag);
+  return symv_any<C64, false>(M, n, ld, x, y, nrhs, scratch, scratch_bytes, s, tag);
+}
+
+rfcmp_status dsymv(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
+                   void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag) {
+  return symv_any<F64, false>(M, n, ld, x, y, nrhs, scratch, scratch_bytes, s, tag);
+}
+
+}  // namespace rfcmp
