@@ -9,24 +9,26 @@ namespace rfcmp {
 namespace {
 
 // ------------------------------------------------------------------------
-// Blocked Gauss-Jordan inverse of an SPD matrix (no pivoting: every Schur
-// complement of an SPD matrix is SPD).  Pivot block P (64 x 64):
-//   D = A_PP^-1,  A_PO <- D A_PO,  A_OP <- -A_OP D,  A_OO <- A_OO - A_OP_old D A_PO_old,
-//   A_PP <- D.
-// After all pivot blocks the matrix holds A^-1 (the sweep operator).
+// Blocked symmetric sweep of an SPD matrix (no pivoting: every Schur
+// complement of an SPD matrix is SPD).  The scalar sweep on pivot k,
+//   d = 1 / a_kk,  a_ij -= a_ik a_kj d,  a_ik *= d,  a_kj *= d,  a_kk = -d,
+// keeps a symmetric matrix symmetric, and sweeping every index yields -A^-1.
+// Sweeping the 64 indices of pivot block P at once, with E = A_PP^-1:
+//   A_PP <- -E,  A_PJ <- E A_PJ,  A_IJ <- A_IJ - A_PI^T E A_PJ   (I, J != P).
+// Only the upper block triangle (tiles I <= J) is kept up to date, which
+// halves the traffic and the flops of the rank-64 updates; a final pass
+// mirrors it, flips the sign and applies the requested shift.
 constexpr int kB = 64;
 
-// Unblocked sweep of the 64 x 64 pivot block.  Thread t keeps the 16-entry
-// strip (rows 16 (t / 64) .. +16, column t % 64) in registers for all 64
-// pivots; per pivot the owners publish the pivot column and row to LDS
-// (double-buffered, one barrier per pivot) and every entry is updated:
-//   a_ij -= a_ik a_kj / a_kk,  a_kj /= a_kk,  a_ik = -a_ik / a_kk,  a_kk = 1 / a_kk.
-// Written branch-free: with m_j = a_kj / a_kk (j != k) or 1 / a_kk (j == k),
-// row k becomes m_j and every other entry (j != k ? a_ij : 0) - a_ik m_j.
-// The strip's 16 pivot-column values are read from LDS together, before the
-// updates, so the reads overlap.
+// Scalar sweep of the 64 pivots of diagonal tile P, in place (leaves -E).
+// Thread t keeps the 16-entry strip (rows 16 (t / 64) .. +16, column t % 64)
+// in registers.  By symmetry the pivot row equals the pivot column, so per
+// pivot only the column is published to LDS (by the four threads that own
+// it; double-buffered, one barrier per pivot).  Branch-free update: with
+// m_j = -d (j == k) or a_kj d (j != k), row k becomes m_j and every other
+// entry (j == k ? 0 : a_ij) - a_ik m_j.
 __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld, int K) {
-  __shared__ double colk[2][kB], rowk[2][kB];
+  __shared__ double colk[2][kB];
   const int j = threadIdx.x % kB;
   const int i0 = (threadIdx.x / kB) * 16;
   const long base = (long)K * kB;
@@ -39,19 +41,13 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld
 #pragma unroll
       for (int u = 0; u < 16; ++u) colk[bsel][i0 + u] = r[u];
     }
-    if (k >= i0 && k < i0 + 16) {
-      double v = 0.0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) v = (i0 + u == k) ? r[u] : v;
-      rowk[bsel][j] = v;
-    }
     __syncthreads();
     double ck[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) ck[u] = colk[bsel][i0 + u];
-    const double d = 1.0 / rowk[bsel][k];
+    const double d = 1.0 / colk[bsel][k];
     const bool pj = (j == k);
-    const double m = pj ? d : rowk[bsel][j] * d;
+    const double m = pj ? -d : colk[bsel][j] * d;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const double keep = pj ? 0.0 : r[u];
@@ -63,92 +59,96 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld
   for (int u = 0; u < 16; ++u) A[(base + i0 + u) * ld + base + j] = r[u];
 }
 
-// Column panel: Ccol = A_OP (old), A_OP <- -A_OP D.  Row panel: A_PO <- D A_PO.
-// blockIdx.x = block index b (skip b == K); blockIdx.y = 0 column panel, 1 row panel.
-// D and the old panel block are staged in LDS (the product overwrites the
-// panel in place); each thread computes a 4 x 4 output tile.
+// Panels of pivot block K: for each J != K, U_J = A_KJ (old; read from tile
+// (J, K) transposed when J < K) and R_J = E U_J with E = -(tile K, K).
+// Writes U_J and R_J to the compact panel buffers ([nb][64][64] each) and
+// R_J back into the upper tile.  E and U_J are staged in LDS; each thread
+// computes a 4 x 4 tile of R_J.
 __global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long ld, int K,
-                                                   double* __restrict__ Ccol) {
-  const int b = blockIdx.x;
-  if (b == K) return;
-  __shared__ double D[kB][kB];
-  __shared__ double S[kB][kB];
-  const long pb = (long)K * kB, ob = (long)b * kB;
-  const bool col = blockIdx.y == 0;
+                                                   double* __restrict__ Ubuf, double* __restrict__ Rbuf) {
+  const int J = blockIdx.x;
+  if (J == K) return;
+  __shared__ double E[kB][kB];
+  __shared__ double U[kB][kB];
+  const long pb = (long)K * kB, jb = (long)J * kB;
   for (int t = threadIdx.x; t < kB * kB; t += 256) {
-    const int i = t / kB, j = t % kB;
-    D[i][j] = A[(pb + i) * ld + pb + j];
-    if (col) {
-      const double v = A[(ob + i) * ld + pb + j];  // row ob+i, pivot column j
-      S[i][j] = v;
-      Ccol[(ob + i) * kB + j] = v;
-    } else {
-      S[i][j] = A[(pb + i) * ld + ob + j];  // pivot row i, column ob+j
-    }
+    const int i = t / kB, c = t % kB;
+    E[i][c] = -A[(pb + i) * ld + pb + c];
+    if (J > K)
+      U[i][c] = A[(pb + i) * ld + jb + c];
+    else
+      U[c][i] = A[(jb + i) * ld + pb + c];
   }
   __syncthreads();
+  double* Uo = Ubuf + (long)J * kB * kB;
+  double* Ro = Rbuf + (long)J * kB * kB;
+  for (int t = threadIdx.x; t < kB * kB; t += 256) Uo[t] = U[t / kB][t % kB];
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double acc[4][4] = {};
-  // col: out = S D (rows of S times D); row: out = D S
-  const double(*L)[kB] = col ? S : D;
-  const double(*Rm)[kB] = col ? D : S;
 #pragma unroll 8
   for (int q = 0; q < kB; ++q) {
     double lv[4], rv[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) lv[u] = L[ty * 4 + u][q];
+    for (int u = 0; u < 4; ++u) lv[u] = E[ty * 4 + u][q];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) rv[v] = Rm[q][tx + 16 * v];
+    for (int v = 0; v < 4; ++v) rv[v] = U[q][tx + 16 * v];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += lv[u] * rv[v];
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(lv[u], rv[v], acc[u][v]);
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = ty * 4 + u, j = tx + 16 * v;
-      if (col)
-        A[(ob + i) * ld + pb + j] = -acc[u][v];
+      const int i = ty * 4 + u, c = tx + 16 * v;
+      Ro[i * kB + c] = acc[u][v];
+      if (J > K)
+        A[(pb + i) * ld + jb + c] = acc[u][v];
       else
-        A[(pb + i) * ld + ob + j] = acc[u][v];
+        A[(jb + c) * ld + pb + i] = acc[u][v];
     }
 }
 
-// A_IJ -= Ccol_I R_J for I, J != K, with R = the updated pivot row panel.
-// 64 x 64 output tile per block, 4 x 4 per thread, k-chunks of 32 in LDS.
-__global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long ld, int K,
-                                                   const double* __restrict__ Ccol) {
-  const int I = blockIdx.y, J = blockIdx.x;
+// Rank-64 update of the upper tiles: A_IJ -= U_I^T R_J for I <= J, I, J != K.
+// One 64 x 64 tile per workgroup (upper-triangle index -> (I, J)), 4 x 4 per
+// thread, K-chunks of 32 rows of U_I and R_J in LDS.
+__global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long ld, int nb, int K,
+                                                   const double* __restrict__ Ubuf,
+                                                   const double* __restrict__ Rbuf) {
+  int I = 0, rem = blockIdx.x;
+  while (rem >= nb - I) {
+    rem -= nb - I;
+    ++I;
+  }
+  const int J = I + rem;
   if (I == K || J == K) return;
   constexpr int KC = 32;
-  __shared__ double a[kB][KC + 1];
-  __shared__ double r[KC][kB + 1];
-  const long ib = (long)I * kB, jb = (long)J * kB, pb = (long)K * kB;
+  __shared__ double uu[KC][kB + 1];
+  __shared__ double rr[KC][kB + 1];
+  const long ib = (long)I * kB, jb = (long)J * kB;
+  const double* Ui = Ubuf + (long)I * kB * kB;
+  const double* Rj = Rbuf + (long)J * kB * kB;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double acc[4][4] = {};
   for (int k0 = 0; k0 < kB; k0 += KC) {
-    for (int t = threadIdx.x; t < kB * KC; t += 256) {
-      const int i = t / KC, q = t % KC;
-      a[i][q] = Ccol[(ib + i) * kB + k0 + q];
-    }
     for (int t = threadIdx.x; t < KC * kB; t += 256) {
-      const int q = t / kB, j = t % kB;
-      r[q][j] = A[(pb + k0 + q) * ld + jb + j];
+      const int q = t / kB, c = t % kB;
+      uu[q][c] = Ui[(k0 + q) * kB + c];
+      rr[q][c] = Rj[(k0 + q) * kB + c];
     }
     __syncthreads();
 #pragma unroll 4
     for (int q = 0; q < KC; ++q) {
       double av[4], rv[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = a[ty * 4 + u][q];
+      for (int u = 0; u < 4; ++u) av[u] = uu[q][ty * 4 + u];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) rv[u] = r[q][tx + 16 * u];
+      for (int u = 0; u < 4; ++u) rv[u] = rr[q][tx + 16 * u];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * rv[v];
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], rv[v], acc[u][v]);
     }
     __syncthreads();
   }
@@ -156,6 +156,24 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) A[(ib + ty * 4 + u) * ld + jb + tx + 16 * v] -= acc[u][v];
+}
+
+// Final pass over the upper triangle (i <= j): the swept matrix holds -A^-1
+// in its upper tiles; write -a_ij - shift to (i, j) and (j, i) inside the
+// valid n x n block, the identity in the padding.
+__global__ void k_gj_finish(double* __restrict__ A, long ld, long nvalid, double shift) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ld * ld) return;
+  const long i = t / ld, j = t % ld;
+  if (i > j) return;
+  if (i < nvalid && j < nvalid) {
+    const double w = -A[i * ld + j] - shift;
+    A[i * ld + j] = w;
+    A[j * ld + i] = w;
+  } else {
+    A[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    A[j * ld + i] = (i == j) ? 1.0 : 0.0;
+  }
 }
 
 // Dense fills from a coordinate list of unique entries.
@@ -171,36 +189,34 @@ __global__ void k_scatter_add(double* __restrict__ A, long ld, const int* __rest
   if (t >= nnz) return;
   A[(long)ij[2 * t] * ld + ij[2 * t + 1]] += v[t];
 }
-__global__ void k_sub_const(double* __restrict__ A, long ld, long nvalid, double c) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nvalid * nvalid) return;
-  const long i = t / nvalid, j = t % nvalid;
-  A[i * ld + j] -= c;
-}
-
 inline unsigned blocks_for(long n, int per) { return unsigned((n + per - 1) / per); }
 
 }  // namespace
 
-rfcmp_status spd_inverse(double* A, int64_t n, hipStream_t s) {
-  if (n % kB != 0) {
-    set_error("spd_inverse: n=%lld not a multiple of %d", (long long)n, kB);
+rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, hipStream_t s) {
+  if (n % kB != 0 || nvalid > n || nvalid < 0) {
+    set_error("spd_inverse: n=%lld (valid %lld) not a multiple of %d", (long long)n, (long long)nvalid, kB);
     return RFCMP_E_ARG;
   }
   const int nb = int(n / kB);
   ProfScope prof("spd_inverse", s);
-  DevBuf ccol;
-  RF_TRY(ccol.alloc(sizeof(double) * n * kB));
+  DevBuf ubuf, rbuf;  // released (after the device is idle) on return
+  RF_TRY(ubuf.alloc(sizeof(double) * n * kB));
+  RF_TRY(rbuf.alloc(sizeof(double) * n * kB));
+  const unsigned ntiles = unsigned((long)nb * (nb + 1) / 2);
   for (int K = 0; K < nb; ++K) {
     hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, A, (long)n, K);
     if (nb > 1) {
-      hipLaunchKernelGGL(k_gj_panels, dim3(nb, 2), dim3(256), 0, s, A, (long)n, K, ccol.as<double>());
-      hipLaunchKernelGGL(k_gj_update, dim3(nb, nb), dim3(256), 0, s, A, (long)n, K, ccol.as<double>());
+      hipLaunchKernelGGL(k_gj_panels, dim3(nb), dim3(256), 0, s, A, (long)n, K, ubuf.as<double>(),
+                         rbuf.as<double>());
+      hipLaunchKernelGGL(k_gj_update, dim3(ntiles), dim3(256), 0, s, A, (long)n, nb, K, ubuf.as<double>(),
+                         rbuf.as<double>());
     }
   }
+  const long total = (long)n * n;
+  hipLaunchKernelGGL(k_gj_finish, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, A, (long)n,
+                     (long)nvalid, shift);
   RF_HIP(hipGetLastError());
-  // the scratch panel is released when ccol goes out of scope: wait first
-  RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;
 }
 
@@ -230,13 +246,7 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_add, dim3(blocks_for((long)val.size(), 256)), dim3(256), 0, s,
                        buf.as<double>(), (long)ld, dij.as<int>(), dv.as<double>(), (long)val.size());
     RF_HIP(hipGetLastError());
-    RF_TRY(spd_inverse(buf.as<double>(), ld, s));  // synchronises before dij/dv are freed
-    if (sub_inner_after) {
-      hipLaunchKernelGGL(k_sub_const, dim3(blocks_for(nvalid * nvalid, 256)), dim3(256), 0, s,
-                         buf.as<double>(), (long)ld, (long)nvalid, inner);
-      RF_HIP(hipGetLastError());
-    }
-    return RFCMP_OK;
+    return spd_inverse(buf.as<double>(), ld, nvalid, sub_inner_after ? inner : 0.0, s);
   };
 
   // L + J

@@ -199,7 +199,10 @@ rfcmp_status csymv(const float2* M, int64_t n, int64_t ld, bool conj, const doub
                    void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag = "csymv");
 rfcmp_status dsymv(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
                    void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag = "dsymv");
-// In-place inverse of an SPD matrix, FP64, n padded to a multiple of 64.
-rfcmp_status spd_inverse(double* A, int64_t n, hipStream_t s);
+// In-place inverse of an SPD matrix, FP64: A [n][n] (n a multiple of 64)
+// holds an SPD matrix in its leading nvalid x nvalid block and the identity
+// in the padding; on return that block holds A^-1 - shift 1 1^T (exactly
+// symmetric), the padding the identity again.
+rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, hipStream_t s);
 
 }  // namespace rfcmp
