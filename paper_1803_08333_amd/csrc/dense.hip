@@ -20,21 +20,16 @@ namespace {
 // mirrors it, flips the sign and applies the requested shift.
 constexpr int kB = 64;
 
-// Scalar sweep of the 64 pivots of diagonal tile P, in place (leaves -E).
-// Thread t keeps the 16-entry strip (rows 16 (t / 64) .. +16, column t % 64)
-// in registers.  By symmetry the pivot row equals the pivot column, so per
-// pivot only the column is published to LDS (by the four threads that own
-// it; double-buffered, one barrier per pivot).  Branch-free update: with
+// Scalar sweep of the 64 pivots of a diagonal tile held in registers (leaves
+// -E).  Thread t keeps the 16-entry strip (rows 16 (t / 64) .. +16, column
+// t % 64).  By symmetry the pivot row equals the pivot column, so per pivot
+// only the column is published to LDS (by the four threads that own it;
+// double-buffered, one barrier per pivot).  Branch-free update: with
 // m_j = -d (j == k) or a_kj d (j != k), row k becomes m_j and every other
 // entry (j == k ? 0 : a_ij) - a_ik m_j.
-__global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld, int K) {
-  __shared__ double colk[2][kB];
+__device__ void sweep_tile(double (&r)[16], double (*colk)[kB]) {
   const int j = threadIdx.x % kB;
   const int i0 = (threadIdx.x / kB) * 16;
-  const long base = (long)K * kB;
-  double r[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) r[u] = A[(base + i0 + u) * ld + base + j];
   for (int k = 0; k < kB; ++k) {
     const int bsel = k & 1;
     if (j == k) {
@@ -55,34 +50,48 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld
       r[u] = (i0 + u == k) ? m : nv;
     }
   }
+}
+
+// Sweep of diagonal tile K in place (the first pivot block only: later
+// diagonal tiles are swept by the update kernel of the previous step).
+__global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld, int K) {
+  __shared__ double colk[2][kB];
+  const int j = threadIdx.x % kB;
+  const int i0 = (threadIdx.x / kB) * 16;
+  const long base = (long)K * kB;
+  double r[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) r[u] = A[(base + i0 + u) * ld + base + j];
+  sweep_tile(r, colk);
 #pragma unroll
   for (int u = 0; u < 16; ++u) A[(base + i0 + u) * ld + base + j] = r[u];
 }
 
-// Panels of pivot block K: for each J != K, U_J = A_KJ (old; read from tile
-// (J, K) transposed when J < K) and R_J = E U_J with E = -(tile K, K).
-// Writes U_J and R_J to the compact panel buffers ([nb][64][64] each) and
-// R_J back into the upper tile.  E and U_J are staged in LDS; each thread
-// computes a 4 x 4 tile of R_J.
+// Panels of pivot block K: for each J != K, U_J = A_KJ (old; tile (J, K)
+// transposed when J < K) and R_J = E U_J with E = -(tile K, K).  Writes U_J
+// and R_J to the compact panel buffers ([nb][64][64] each) and R_J back into
+// the upper tile.  Tiles are read and written row by row (coalesced); the
+// transposes happen in LDS.  Each thread computes a 4 x 4 tile of R_J.
 __global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long ld, int K,
                                                    double* __restrict__ Ubuf, double* __restrict__ Rbuf) {
   const int J = blockIdx.x;
   if (J == K) return;
   __shared__ double E[kB][kB];
-  __shared__ double U[kB][kB];
+  __shared__ double T[kB][kB + 1];  // the stored tile: A_KJ (J > K) or A_JK (J < K)
   const long pb = (long)K * kB, jb = (long)J * kB;
+  const bool up = J > K;
   for (int t = threadIdx.x; t < kB * kB; t += 256) {
     const int i = t / kB, c = t % kB;
     E[i][c] = -A[(pb + i) * ld + pb + c];
-    if (J > K)
-      U[i][c] = A[(pb + i) * ld + jb + c];
-    else
-      U[c][i] = A[(jb + i) * ld + pb + c];
+    T[i][c] = up ? A[(pb + i) * ld + jb + c] : A[(jb + i) * ld + pb + c];
   }
   __syncthreads();
   double* Uo = Ubuf + (long)J * kB * kB;
   double* Ro = Rbuf + (long)J * kB * kB;
-  for (int t = threadIdx.x; t < kB * kB; t += 256) Uo[t] = U[t / kB][t % kB];
+  for (int t = threadIdx.x; t < kB * kB; t += 256) {
+    const int i = t / kB, c = t % kB;
+    Uo[t] = up ? T[i][c] : T[c][i];
+  }
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double acc[4][4] = {};
 #pragma unroll 8
@@ -91,32 +100,52 @@ __global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long 
 #pragma unroll
     for (int u = 0; u < 4; ++u) lv[u] = E[ty * 4 + u][q];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) rv[v] = U[q][tx + 16 * v];
+    for (int v = 0; v < 4; ++v) rv[v] = up ? T[q][tx + 16 * v] : T[tx + 16 * v][q];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[u][v] = fma(lv[u], rv[v], acc[u][v]);
   }
+  __syncthreads();  // every thread is done reading T
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = ty * 4 + u, c = tx + 16 * v;
       Ro[i * kB + c] = acc[u][v];
-      if (J > K)
-        A[(pb + i) * ld + jb + c] = acc[u][v];
+      if (up)
+        T[i][c] = acc[u][v];
       else
-        A[(jb + c) * ld + pb + i] = acc[u][v];
+        T[c][i] = acc[u][v];  // the stored tile is R_J^T
     }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kB * kB; t += 256) {
+    const int i = t / kB, c = t % kB;
+    if (up)
+      A[(pb + i) * ld + jb + c] = T[i][c];
+    else
+      A[(jb + i) * ld + pb + c] = T[i][c];
+  }
 }
 
 // Rank-64 update of the upper tiles: A_IJ -= U_I^T R_J for I <= J, I, J != K.
-// One 64 x 64 tile per workgroup (upper-triangle index -> (I, J)), 4 x 4 per
-// thread, K-chunks of 32 rows of U_I and R_J in LDS.
+// One 64 x 64 tile per workgroup, 4 x 4 per thread (loaded first, so the
+// read overlaps the products), K-chunks of 32 rows of U_I and R_J in LDS.
+// Workgroup 0 takes the next diagonal tile (K+1, K+1) and, once it is
+// updated, sweeps it: the serial sweep of the next pivot block runs while
+// the rest of the update streams.
 __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long ld, int nb, int K,
                                                    const double* __restrict__ Ubuf,
                                                    const double* __restrict__ Rbuf) {
-  int I = 0, rem = blockIdx.x;
+  // upper-triangle index, with 0 and the index of (K+1, K+1) swapped
+  const int nx = K + 1;
+  const int inext = nx < nb ? nx * nb - nx * (nx - 1) / 2 : 0;
+  int lin = blockIdx.x;
+  if (lin == 0)
+    lin = inext;
+  else if (lin == inext)
+    lin = 0;
+  int I = 0, rem = lin;
   while (rem >= nb - I) {
     rem -= nb - I;
     ++I;
@@ -124,13 +153,18 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
   const int J = I + rem;
   if (I == K || J == K) return;
   constexpr int KC = 32;
-  __shared__ double uu[KC][kB + 1];
-  __shared__ double rr[KC][kB + 1];
+  __shared__ double lds[2 * KC * (kB + 1)];
+  double(*uu)[kB + 1] = reinterpret_cast<double(*)[kB + 1]>(lds);
+  double(*rr)[kB + 1] = reinterpret_cast<double(*)[kB + 1]>(lds + KC * (kB + 1));
   const long ib = (long)I * kB, jb = (long)J * kB;
   const double* Ui = Ubuf + (long)I * kB * kB;
   const double* Rj = Rbuf + (long)J * kB * kB;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4] = {};
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = A[(ib + ty * 4 + u) * ld + jb + tx + 16 * v];
   for (int k0 = 0; k0 < kB; k0 += KC) {
     for (int t = threadIdx.x; t < KC * kB; t += 256) {
       const int q = t / kB, c = t % kB;
@@ -148,14 +182,33 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], rv[v], acc[u][v]);
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(-av[u], rv[v], acc[u][v]);
     }
     __syncthreads();
+  }
+  if (I == nx && J == nx) {
+    // hand the tile to the sweep layout through LDS (uu and rr are free)
+    double* t = lds;  // [64][64]
+    static_assert(2 * KC * (kB + 1) >= kB * kB, "LDS tile");
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) t[(ty * 4 + u) * kB + tx + 16 * v] = acc[u][v];
+    __syncthreads();
+    const int j = threadIdx.x % kB, i0 = (threadIdx.x / kB) * 16;
+    double r[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) r[u] = t[(i0 + u) * kB + j];
+    __shared__ double colk[2][kB];
+    sweep_tile(r, colk);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) A[(ib + i0 + u) * ld + jb + j] = r[u];
+    return;
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) A[(ib + ty * 4 + u) * ld + jb + tx + 16 * v] -= acc[u][v];
+    for (int v = 0; v < 4; ++v) A[(ib + ty * 4 + u) * ld + jb + tx + 16 * v] = acc[u][v];
 }
 
 // Final pass over the upper triangle (i <= j): the swept matrix holds -A^-1
@@ -204,8 +257,8 @@ rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, hip
   RF_TRY(ubuf.alloc(sizeof(double) * n * kB));
   RF_TRY(rbuf.alloc(sizeof(double) * n * kB));
   const unsigned ntiles = unsigned((long)nb * (nb + 1) / 2);
+  hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, A, (long)n, 0);
   for (int K = 0; K < nb; ++K) {
-    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, A, (long)n, K);
     if (nb > 1) {
       hipLaunchKernelGGL(k_gj_panels, dim3(nb), dim3(256), 0, s, A, (long)n, K, ubuf.as<double>(),
                          rbuf.as<double>());
