@@ -50,14 +50,18 @@ def parse():
     p.add_argument("--cpu-slab", type=int, default=32, help="1/slab of the test cells for the oracle sample")
     p.add_argument("--no-precision-study", action="store_true")
     p.add_argument("--batch-rhs", type=int, default=64)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     return p.parse_args()
 
 
 def cpu_baseline(xyz, tri, slab):
-    """The FP64 oracle on a bounded sample of the same workload: the far- and
-    near-pair assembly of a 1/slab row slab of the level-4 sphere at ka = 1.0.
-    Converted to solves/s assuming assembly is the oracle's only cost (an upper
-    bound on its throughput: setup, scalings and CG are left out)."""
+    """The FP64 oracle on a bounded sample of the same workload: its far-pair
+    quadrature and near-pair integrals for every slab-th test cell of the
+    level-4 sphere at ka = 1.0 (its own functions, row by row, in the order
+    its assembly runs them).  Converted to solves/s assuming assembly is the
+    oracle's only cost, an upper bound on its throughput: setup, scalings and
+    CG are left out."""
     from threadpoolctl import threadpool_limits
     from oracle import assembly, quadrature
     from oracle.topology import Topology
@@ -71,19 +75,10 @@ def cpu_baseline(xyz, tri, slab):
         c0 = time.process_time()
         near = assembly.near_mask(top)
         k = 1.0
-        arm = pts[:, :, None, :] - top.xyz[top.tri][:, None, :, :]
-        ww = np.outer(w, w)
         for s in range(0, len(rows), 8):
-            cs = rows[s:s + 8]
-            R = np.linalg.norm(pts[cs, :, None, None, :] - pts[None, None, :, :, :], axis=-1)
-            with np.errstate(divide="ignore", invalid="ignore"):
-                G = np.exp(1j * k * R) / (4.0 * np.pi * R)
-            G[~np.isfinite(G)] = 0.0
-            Gw = G * ww[None, :, None, :]
-            Gw.sum(axis=(1, 3))
-            np.einsum("apid,apbq,bqjd->aibj", arm[cs], Gw, arm, optimize=True)
+            assembly.far_rows(top, k, rows[s:s + 8], pts, w)
         for c in rows:
-            for cp in np.nonzero(near[c])[0]:
+            for cp in np.nonzero(near[c, c:])[0] + c:
                 assembly.near_block(top, c, cp, k, pts, w)
         dt = time.perf_counter() - t0
         used = max(1, int(round((time.process_time() - c0) / dt)))
@@ -98,7 +93,49 @@ def cpu_baseline(xyz, tri, slab):
             "assembly_pairs_per_s": pairs_per_s}
 
 
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB (5 launches), for scaling the
+    HBM byte counters of a profiler run: each launch reads and writes
+    exactly 2^30 bytes."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}))
+
+
 BF16_MFMA_TFLOPS = 2500.0
+
+# HBM bytes per launch of the symmetric products (k_symv, level-4 sphere) from
+# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch, mean
+# over the dispatches of the tag's instantiation), each scaled by what the
+# same counter reads for a plain 1 GiB device copy (FETCH_SIZE reads 2^19
+# KiB for 2^30 bytes fetched: scale 2.0; WRITE_SIZE reads 2^20 KiB: scale
+# 1.0).  Valid only for the kernel source they were taken on: reported as
+# null once symv.hip changes.
+TRAFFIC_SOURCE = {"path": "paper_1803_08333_amd/csrc/symv.hip",
+                  "sha256": "a889c8763e53b1df7e8a91bcef822e7735ed2c0b6b53a7f74a13632ab3f49b25"}
+TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
+TRAFFIC_KIB = {  # tag: (FETCH_SIZE, WRITE_SIZE)
+    "cmatvec_ta": (117664.5, 7200.0), "cmatvec_ta_nr2": (118166.0, 14400.0),
+    "cmatvec_v": (52864.5, 3200.0), "dmatvec_lp": (52862.0, 3200.0), "dmatvec_lp_nr2": (53200.5, 6400.0),
+    "dmatvec_gll": (13822.6, 882.0)}
+
+
+def measured_traffic(tag):
+    import hashlib
+    if tag not in TRAFFIC_KIB:
+        return None
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), TRAFFIC_SOURCE["path"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC_SOURCE["sha256"]:
+            return None
+    fk, wk = TRAFFIC_KIB[tag]
+    return 1024.0 * (fk * TRAFFIC_SCALE["fetch"] + wk * TRAFFIC_SCALE["write"])
 
 
 def precision_study(rf, torch, xyz, tri, kh, pol, start, nb):
@@ -163,6 +200,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
               "see DESIGN.md for how the operator would shard.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     import paper_1803_08333_amd as rf
 
@@ -195,8 +235,9 @@ def main():
 
     # one untimed step with every kernel tag timed: the per-kernel breakdown
     # and the choice of the dominant kernel
-    tags = ["far_pairs", "near_pairs", "gather_ta", "cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll",
-            "spd_inverse"]
+    base = ["cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll"]
+    tags = ["far_pairs", "near_pairs", "gather_ta"] + base + [f"{t}_nr{r}" for t in base for r in (2, 3, 4)] + \
+        ["symv_reduce", "spd_inverse"]
     rf.profile_select(None)
     rf.profile_enable(True)
     step(False)
@@ -208,14 +249,17 @@ def main():
 
     # roofline of the dominant kernel (largest total time)
     # symmetric products: the algorithmic bytes are the n (n + 1) / 2 distinct
-    # entries (8 B each) plus x read and y written (16 B each, complex128)
+    # entries (8 B each) plus x read and y written (16 B each, complex128) per
+    # right-hand side; tags "<name>_nr<k>" are k right-hand sides per launch
     def model(tag, avg_ms):
-        if tag == "cmatvec_ta":
-            byt = 8.0 * N * (N + 1) / 2 + 32.0 * N
-            return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s"}
-        if tag in ("cmatvec_v", "dmatvec_lp"):
-            byt = 8.0 * C * (C + 1) / 2 + 32.0 * C
-            return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s"}
+        name, nr = tag, 1
+        if "_nr" in tag:
+            name, nr = tag.split("_nr")[0], int(tag.split("_nr")[1])
+        n = {"cmatvec_ta": N, "cmatvec_v": C, "dmatvec_lp": C, "dmatvec_gll": len(xyz)}.get(name)
+        if n is not None:
+            byt = 8.0 * n * (n + 1) / 2 + 32.0 * n * nr
+            return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s",
+                    "algorithmic_bytes": byt}
         if tag == "far_pairs":
             fl = C * (C - 1) / 2 * 49 * FAR_FLOPS_PER_POINT_PAIR
             return {"bound": "alu", "achieved": fl / (avg_ms * 1e-3) / 1e12, "peak": FP32_VALU_TFLOPS,
@@ -243,7 +287,9 @@ def main():
     avg = prof[dom][0] / prof[dom][1]
     roof = model(dom, avg)
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom)
+    if roof["traffic"] is not None and "algorithmic_bytes" in roof:
+        roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes"]
     roof["kernel"] = dom
     roof["avg_ms"] = avg
     roof["launches"] = prof[dom][1]
@@ -261,7 +307,7 @@ def main():
         "scalings": {str(k): [out[k]["alpha"], out[k]["beta"], out[k]["gamma"]] for k in KS},
         "assembly_pairs_per_s": pairs_per_s,
         "assembly_ms": asm_ms,
-        "kernel_ms_per_step": {t: brk[t][0] for t in tags},
+        "kernel_ms_per_step": {t: brk[t][0] for t in tags if brk[t][1] > 0},
         "bf16x3_vs_fp32": None,
         "roofline": roof,
     }

@@ -85,27 +85,35 @@ def near_block(top, c, cp, k, pts, w):
     return sig * (sing + smooth), v
 
 
+def far_rows(top, k, cs, pts, w):
+    """7x7-point quadrature of every pair (c, c'), c in the test cells cs
+    (an index array or slice), c' any cell: (V rows [len(cs), C],
+    cell-slot block rows [len(cs), 3, C, 3]).  Near pairs get values here
+    too; assemble() overwrites them."""
+    vert = top.xyz[top.tri]                                  # [C,3,3]
+    arm = pts[:, :, None, :] - vert[:, None, :, :]           # [C,7,3(i),3]: r_p - r_i
+    sig = top.cell_sign / 2.0                                # sigma/2 per (c,i)
+    ww = np.outer(w, w)
+    R = np.linalg.norm(pts[cs, :, None, None, :] - pts[None, None, :, :, :], axis=-1)  # [cc,7,C,7]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        G = np.exp(1j * k * R) / (4.0 * np.pi * R)
+    G[~np.isfinite(G)] = 0.0          # only self pairs, replaced by the near path
+    Gw = G * ww[None, :, None, :]
+    v = Gw.sum(axis=(1, 3))
+    blk = np.einsum("apid,apbq,bqjd->aibj", arm[cs], Gw, arm, optimize=True)
+    return v, blk * sig[cs][:, :, None, None] * sig[None, None, :, :]
+
+
 def assemble(top, k, near_factor=2.0, chunk=32, return_blocks=False):
     """Dense (T_A [N,N], V [C,C]) complex128 by the quadrature spec."""
     pts, w = tri7_points(top.xyz, top.tri)
     C = top.C
     near = near_mask(top, near_factor)
-    vert = top.xyz[top.tri]                                  # [C,3,3]
-    arm = pts[:, :, None, :] - vert[:, None, :, :]           # [C,7,3(i),3]: r_p - r_i
-    sig = top.cell_sign / 2.0                                # sigma/2 per (c,i)
     B = np.zeros((C, 3, C, 3), dtype=np.complex128)
     Vm = np.zeros((C, C), dtype=np.complex128)
-    ww = np.outer(w, w)
     for s in range(0, C, chunk):
         cs = slice(s, min(C, s + chunk))
-        R = np.linalg.norm(pts[cs, :, None, None, :] - pts[None, None, :, :, :], axis=-1)  # [cc,7,C,7]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            G = np.exp(1j * k * R) / (4.0 * np.pi * R)
-        G[~np.isfinite(G)] = 0.0          # only self pairs, replaced below
-        Gw = G * ww[None, :, None, :]
-        Vm[cs] = Gw.sum(axis=(1, 3))
-        blk = np.einsum("apid,apbq,bqjd->aibj", arm[cs], Gw, arm, optimize=True)
-        B[cs] = blk * sig[cs][:, :, None, None] * sig[None, None, :, :]
+        Vm[cs], B[cs] = far_rows(top, k, cs, pts, w)
     for c in range(C):
         for cp in range(c, C):
             if not near[c, cp]:

@@ -76,6 +76,8 @@ inline size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
 // pair is recorded on the launch stream around each tagged launch.
 bool profiling_enabled();
 bool profiling_selected(const char* tag);
+// "<tag>_nr<k>", interned (valid for the life of the process).
+const char* profile_tag_suffix(const char* tag, int k);
 void profile_record(const char* tag, hipEvent_t start, hipEvent_t stop);
 hipEvent_t profile_event();
 struct ProfScope {

@@ -19,6 +19,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <set>
 #include <tuple>
 
 #include "gemm.h"
@@ -589,6 +591,12 @@ ProfState& prof() {
 }
 }  // namespace
 bool profiling_enabled() { return prof().on; }
+const char* profile_tag_suffix(const char* tag, int k) {
+  static std::mutex mu;
+  static std::set<std::string> names;
+  std::lock_guard<std::mutex> g(mu);
+  return names.insert(std::string(tag) + "_nr" + std::to_string(k)).first->c_str();
+}
 bool profiling_selected(const char* tag) {
   const ProfState& p = prof();
   if (p.only.empty()) return true;

@@ -249,11 +249,18 @@ __global__ __launch_bounds__(4 * S) void k_symv_reduce(int n, int nsb, const dou
 
 constexpr int kS = 128;
 
+// The product kernel is timed under `tag` (one right-hand side) or
+// "<tag>_nr<k>" (k right-hand sides), the slot sums under "symv_reduce".
 template <class T, int NR, bool CONJ>
-void launch(const void* M, int n, long ld, int nsb, const double2* x, double2* part, double2* y, hipStream_t s) {
+void launch(const void* M, int n, long ld, int nsb, const double2* x, double2* part, double2* y, hipStream_t s,
+            const char* tag) {
   const long nblk = (long)nsb * (nsb + 1) / 2;
-  hipLaunchKernelGGL((k_symv<T, kS, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s,
-                     static_cast<const typename T::Pair*>(M), n, ld / 2, nsb, x, part);
+  {
+    ProfScope prof(NR == 1 ? tag : profile_tag_suffix(tag, NR), s);
+    hipLaunchKernelGGL((k_symv<T, kS, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s,
+                       static_cast<const typename T::Pair*>(M), n, ld / 2, nsb, x, part);
+  }
+  ProfScope prof("symv_reduce", s);
   hipLaunchKernelGGL((k_symv_reduce<kS, NR>), dim3((unsigned)nsb, NR), dim3(4 * kS), 0, s, n, nsb, part, y);
 }
 
@@ -272,15 +279,14 @@ rfcmp_status symv_any(const void* M, int64_t n, int64_t ld, const double2* x, do
   }
   double2* part = static_cast<double2*>(scratch);
   for (int r0 = 0; r0 < nrhs; r0 += kMaxNR) {
-    ProfScope prof(tag, s);
     const int nr = std::min(kMaxNR, nrhs - r0);
     const double2* xr = x + (long)r0 * n;
     double2* yr = y + (long)r0 * n;
     switch (nr) {
-      case 1: launch<T, 1, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s); break;
-      case 2: launch<T, 2, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s); break;
-      case 3: launch<T, 3, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s); break;
-      default: launch<T, 4, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s); break;
+      case 1: launch<T, 1, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s, tag); break;
+      case 2: launch<T, 2, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s, tag); break;
+      case 3: launch<T, 3, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s, tag); break;
+      default: launch<T, 4, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s, tag); break;
     }
   }
   RF_HIP(hipGetLastError());
