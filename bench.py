@@ -235,7 +235,7 @@ def main():
 
     # one untimed step with every kernel tag timed: the per-kernel breakdown
     # and the choice of the dominant kernel
-    base = ["cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll"]
+    base = ["cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll", "cmatvec_ta+v", "dmatvec_lp+gll"]
     tags = ["far_pairs", "near_pairs", "gather_ta"] + base + [f"{t}_nr{r}" for t in base for r in (2, 3, 4)] + \
         ["symv_reduce", "spd_inverse"]
     rf.profile_select(None)
@@ -250,14 +250,16 @@ def main():
     # roofline of the dominant kernel (largest total time)
     # symmetric products: the algorithmic bytes are the n (n + 1) / 2 distinct
     # entries (8 B each) plus x read and y written (16 B each, complex128) per
-    # right-hand side; tags "<name>_nr<k>" are k right-hand sides per launch
+    # right-hand side; tags "<name>_nr<k>" are k right-hand sides per launch,
+    # "<a>+<b>" two products sharing one launch
     def model(tag, avg_ms):
         name, nr = tag, 1
         if "_nr" in tag:
             name, nr = tag.split("_nr")[0], int(tag.split("_nr")[1])
-        n = {"cmatvec_ta": N, "cmatvec_v": C, "dmatvec_lp": C, "dmatvec_gll": len(xyz)}.get(name)
-        if n is not None:
-            byt = 8.0 * n * (n + 1) / 2 + 32.0 * n * nr
+        sizes = {"cmatvec_ta": [N], "cmatvec_v": [C], "dmatvec_lp": [C], "dmatvec_gll": [len(xyz)],
+                 "cmatvec_ta+v": [N, C], "dmatvec_lp+gll": [C, len(xyz)]}.get(name)
+        if sizes is not None:
+            byt = sum(8.0 * n * (n + 1) / 2 + 32.0 * n * nr for n in sizes)
             return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s",
                     "algorithmic_bytes": byt}
         if tag == "far_pairs":

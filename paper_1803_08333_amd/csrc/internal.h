@@ -192,15 +192,6 @@ rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, i
 
 // dense.hip
 rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s);
-// symv.hip: y[r] = M x[r] for a symmetric M (M = M^T, complex-symmetric for
-// the complex64 case), reading the upper block triangle of M only.  Scratch:
-// symv_scratch_bytes(n, nrhs) bytes of device memory (partial sums); calls
-// sharing a scratch must not overlap.
-size_t symv_scratch_bytes(int64_t n, int nrhs);
-rfcmp_status csymv(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y, int nrhs,
-                   void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag = "csymv");
-rfcmp_status dsymv(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
-                   void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag = "dsymv");
 // In-place inverse of an SPD matrix, FP64: A [n][n] (n a multiple of 64)
 // holds an SPD matrix in its leading nvalid x nvalid block and the identity
 // in the padding; on return that block holds A^-1 - shift 1 1^T (exactly

@@ -24,6 +24,7 @@
 #include <tuple>
 
 #include "gemm.h"
+#include "symv.h"
 #include "vecops.h"
 
 namespace rfcmp {
@@ -38,17 +39,17 @@ struct Work {
   double2 *nA, *nB, *nC, *nD;        // [R][N]
   double2* c[14];                    // [R][C]
   double2 *v1, *v2;                  // [R][V]
-  double2 *m1, *m2, *m3;             // [R] means
   double2 *part, *dout;              // reductions
   double2 *x, *r, *p, *q, *b, *d, *b0;  // block CG vectors [R][N]
   double2 *pv, *pw;                  // power iteration [3][N]
+  double2 *xN, *xC, *xV;             // formed product inputs for the BF16x3 path [R][N|C|V]
   double *rho, *pq;                  // device CG scalars: rho[2][R], pq[R]
   int* active;                       // [R]
 };
 
 size_t work_doubles2(int64_t N, int64_t C, int64_t V, int R) {
-  return (size_t)(4 * R * N + 14 * R * C + 2 * R * V + 3 * R + (dot_partials() + 1) * R + 7 * R * N + 6 * N +
-                  2 * R + 2 * R);
+  return (size_t)(4 * R * N + 14 * R * C + 2 * R * V + (dot_partials() + 1) * R + 7 * R * N + 6 * N +
+                  2 * R + 2 * R + R * (N + C + V));
 }
 
 Work carve(rfcmp_op op) {
@@ -66,12 +67,12 @@ Work carve(rfcmp_op op) {
   w.nA = take(R * N); w.nB = take(R * N); w.nC = take(R * N); w.nD = take(R * N);
   for (auto& c : w.c) c = take(R * C);
   w.v1 = take(R * V); w.v2 = take(R * V);
-  w.m1 = take(R); w.m2 = take(R); w.m3 = take(R);
   w.part = take((int64_t)dot_partials() * R);
   w.dout = take(R);
   w.x = take(R * N); w.r = take(R * N); w.p = take(R * N); w.q = take(R * N); w.b = take(R * N); w.d = take(R * N);
   w.b0 = take(R * N);
   w.pv = take(3 * N); w.pw = take(3 * N);
+  w.xN = take(R * N); w.xC = take(R * C); w.xV = take(R * V);
   w.rho = reinterpret_cast<double*>(take(R));     // 2R doubles
   w.pq = reinterpret_cast<double*>(take(R / 2 + 1));
   w.active = reinterpret_cast<int*>(take(R / 4 + 1));
@@ -92,68 +93,173 @@ rfcmp_status ensure_work(rfcmp_op op, int R) {
   return RFCMP_OK;
 }
 
-// Scratch of the symmetric products (partial sums), sized at creation for
-// the largest matrix and four right-hand sides per pass.
-#define SYMV op->symv_scratch.p, op->symv_scratch.bytes
-
 // ------------------------------------------------------------------ dense products
-// The five dense products of the operator, in complex64/FP64 (FP64
-// accumulation, <= 4 right-hand sides per matrix pass) or as BF16x3 MFMA
-// products (<= 64 right-hand sides per pass).
+// The five dense matrices of the operator.  In complex64/FP64 each product is
+// a symmetric streaming pass (<= 4 right-hand sides per pass) whose input is
+// formed while it is staged (plain vector, Sigma^T / Lambda^T gather, or a
+// fused operator line); two independent products of the same element type
+// share one launch.  As BF16x3 MFMA products (<= 64 right-hand sides per
+// pass) the input is formed into the workspace first.
+enum Mat { kTA, kV, kLP, kGLL, kGTP };
+
 struct Dense {
   rfcmp_op op;
   hipStream_t s;
   bool bf16;
-  rfcmp_status ta(bool conj, const double2* x, double2* y, int nr) const {
-    if (bf16)
-      return gemm_bf16x3(*op->TA16, conj, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_ta");
-    return csymv(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj, x, y, nr, SYMV, s, "cmatvec_ta");
-  }
-  rfcmp_status v(bool conj, const double2* x, double2* y, int nr) const {
-    if (bf16)
-      return gemm_bf16x3(*op->V16, conj, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_v");
-    return csymv(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj, x, y, nr, SYMV, s, "cmatvec_v");
-  }
-  rfcmp_status lp(const double2* x, double2* y, int nr) const {
+  const Work* W = nullptr;  // workspace for formed inputs (BF16x3 path)
+
+  SymvJob job(Mat m, const SymvInput& in, double2* y) const {
+    const MeshHost& h = op->mesh->h;
     const MeshDev& d = op->mesh->d;
-    if (bf16)
-      return gemm_bf16x3(*d.Lp16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_lp");
-    return dsymv(d.Lp.as<double>(), op->mesh->h.C, d.ldL, x, y, nr, SYMV, s, "dmatvec_lp");
+    SymvJob j;
+    switch (m) {
+      case kTA: j.M = op->TA.p; j.n = h.N; j.ld = op->ldA; break;
+      case kV: j.M = op->Vb.p; j.n = h.C; j.ld = op->ldV; break;
+      case kLP: j.M = d.Lp.p; j.n = h.C; j.ld = d.ldL; break;
+      case kGLL: j.M = d.Gll_inv.p; j.n = h.V; j.ld = d.ldG; break;
+      default: j.M = d.Gtp_inv.p; j.n = h.C; j.ld = d.ldT; break;
+    }
+    j.in = in;
+    j.y = y;
+    return j;
   }
-  rfcmp_status gll(const double2* x, double2* y, int nr) const {
+  const SplitMatrix& split(Mat m) const {
     const MeshDev& d = op->mesh->d;
-    if (bf16)
-      return gemm_bf16x3(*d.Gll16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_gll");
-    return dsymv(d.Gll_inv.as<double>(), op->mesh->h.V, d.ldG, x, y, nr, SYMV, s, "dmatvec_gll");
+    switch (m) {
+      case kTA: return *op->TA16;
+      case kV: return *op->V16;
+      case kLP: return *d.Lp16;
+      case kGLL: return *d.Gll16;
+      default: return *d.Gtp16;
+    }
   }
-  rfcmp_status gtp(const double2* x, double2* y, int nr) const {
+  static const char* tag(Mat m) {
+    static const char* t[] = {"cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll", "dmatvec_gtp"};
+    return t[m];
+  }
+  static const char* gemm_tag(Mat m) {
+    static const char* t[] = {"gemm_ta", "gemm_v", "gemm_lp", "gemm_gll", "gemm_gtp"};
+    return t[m];
+  }
+  static bool complex_matrix(Mat m) { return m == kTA || m == kV; }
+
+  // BF16x3: form the input (unless plain) and run the GEMM.
+  rfcmp_status gemm(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
+    const SymvJob j = job(m, in, y);
+    const double2* x = in.p[0];
+    if (in.mode != SymvInput::kPlain || in.stride[0] != j.n) {
+      double2* buf = j.n == op->mesh->h.N ? W->xN : (j.n == op->mesh->h.C ? W->xC : W->xV);
+      RF_TRY(symv_form_input(in, j.n, nr, buf, s));
+      x = buf;
+    }
+    return gemm_bf16x3(split(m), conj, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, gemm_tag(m));
+  }
+
+  // y = M x (conj: conj(M) x, complex matrices only).
+  rfcmp_status prod(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
+    if (bf16) return gemm(m, conj, in, y, nr);
+    const SymvJob j = job(m, in, y);
+    if (complex_matrix(m))
+      return csymv_jobs(&j, 1, conj, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, tag(m));
+    return dsymv_jobs(&j, 1, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, tag(m));
+  }
+  rfcmp_status prod(Mat m, bool conj, const double2* x, double2* y, int nr) const {
+    return prod(m, conj, plain(x, job(m, SymvInput{}, y).n), y, nr);
+  }
+  // Two independent products of the same element type in one launch.
+  rfcmp_status pair(Mat m0, const SymvInput& in0, double2* y0, Mat m1, const SymvInput& in1, double2* y1,
+                    bool conj, int nr) const {
+    if (bf16) {
+      RF_TRY(gemm(m0, conj, in0, y0, nr));
+      return gemm(m1, conj, in1, y1, nr);
+    }
+    const SymvJob j[2] = {job(m0, in0, y0), job(m1, in1, y1)};
+    static const char* pair_tag[] = {"cmatvec_ta+v", "dmatvec_lp+gll", "dmatvec_lp+gtp"};
+    if (complex_matrix(m0))
+      return csymv_jobs(j, 2, conj, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, pair_tag[0]);
+    return dsymv_jobs(j, 2, nr, op->symv_scratch.p, op->symv_scratch.bytes, s,
+                      m1 == kGLL ? pair_tag[1] : pair_tag[2]);
+  }
+
+  // --- inputs
+  static SymvInput plain(const double2* x, int64_t n) {
+    SymvInput in;
+    in.p[0] = x;
+    in.stride[0] = n;
+    return in;
+  }
+  SymvInput sigma_t(const double2* x) const {  // Sigma^T x, x [nr][N]
     const MeshDev& d = op->mesh->d;
-    if (bf16)
-      return gemm_bf16x3(*d.Gtp16, false, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, "gemm_gtp");
-    return dsymv(d.Gtp_inv.as<double>(), op->mesh->h.C, d.ldT, x, y, nr, SYMV, s, "dmatvec_gtp");
+    SymvInput in;
+    in.mode = SymvInput::kSigmaT;
+    in.p[0] = x;
+    in.stride[0] = op->mesh->h.N;
+    in.idx0 = d.cell_edge.as<int>();
+    in.sgn = d.sgn.as<float>();
+    return in;
+  }
+  SymvInput lambda_t(const double2* x) const {  // Lambda^T x, x [nr][N]
+    const MeshDev& d = op->mesh->d;
+    SymvInput in;
+    in.mode = SymvInput::kLambdaT;
+    in.p[0] = x;
+    in.stride[0] = op->mesh->h.N;
+    in.idx0 = d.ve_ptr.as<int>();
+    in.idx1 = d.ve_idx.as<int>();
+    in.sgn = d.ve_sgn.as<float>();
+    return in;
+  }
+  SymvInput vin(const double2* x, const double2* s1, const double2* sg, double ka, double kb) const {
+    SymvInput in;
+    in.mode = SymvInput::kVin;
+    in.p[0] = x; in.stride[0] = op->mesh->h.N;
+    in.p[1] = s1; in.stride[1] = op->mesh->h.C;
+    in.p[2] = sg; in.stride[2] = op->mesh->h.C;
+    in.c[0] = ka; in.c[1] = kb;
+    in.idx0 = op->mesh->d.edge_cell.as<int>();
+    return in;
+  }
+  SymvInput middle_w(const double2* h, const double2* a, const double2* s2, const double2* s3, double ia2,
+                     double ig, double ib2) const {
+    SymvInput in;
+    in.mode = SymvInput::kMiddleW;
+    in.p[0] = h; in.stride[0] = op->mesh->h.V;
+    in.p[1] = a; in.stride[1] = op->mesh->h.N;
+    in.p[2] = s2; in.stride[2] = op->mesh->h.C;
+    in.p[3] = s3; in.stride[3] = op->mesh->h.C;
+    in.c[0] = ia2; in.c[1] = ig; in.c[2] = ib2;
+    in.idx0 = op->mesh->d.edge_cell.as<int>();
+    in.idx1 = op->mesh->d.edge_vtx.as<int>();
+    return in;
+  }
+  SymvInput proj_lh(const double2* x, const double2* sl) const {  // x - Sigma sl
+    SymvInput in;
+    in.mode = SymvInput::kProjLH;
+    in.p[0] = x; in.stride[0] = op->mesh->h.N;
+    in.p[1] = sl; in.stride[1] = op->mesh->h.C;
+    in.idx0 = op->mesh->d.edge_cell.as<int>();
+    return in;
   }
 };
 
 bool use_gsigma(rfcmp_op op) { return op->opt.outer_star == 1; }
 
-// Left half: y = sgn * P_o^H T^H w for w in W.nC with Sig^T w_S in W.c[8].
-rfcmp_status left_half(const Dense& D, const Work& W, double2* y, int nr, double sgn) {
+// Left half: y = sgn * P_o^H T^H w, with w = middle_w(v2, a, s2, s3) and
+// Sig^T w_S (= (t4 - mean t4)/beta^2) in W.c[8].
+rfcmp_status left_half(const Dense& D, const Work& W, const SymvInput& w_in, double2* y, int nr, double sgn) {
   rfcmp_op op = D.op;
   hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
   const int64_t N = h.N, C = h.C;
   const double k = op->k, al = op->alpha, be = op->beta;
-  double2 *t5 = W.c[9], *s4 = W.c[10], *vw = W.c[11], *t6 = W.c[12], *g6 = W.c[13];
-  RF_TRY(D.ta(true, W.nC, W.nD, nr));  // zA
-  RF_TRY(D.v(true, W.c[8], vw, nr));   // vw
-  RF_TRY(sigma_t(d, C, N, W.nD, t5, nr, s));
-  RF_TRY(D.lp(t5, s4, nr));
-  RF_TRY(mean(C, vw, W.m3, nr, s));
-  RF_TRY(comb_c(C, nullptr, -sgn * (k / be), s4, sgn / (k * be), vw, W.m3, t6, nr, s));
+  double2 *s4 = W.c[10], *vw = W.c[11], *t6 = W.c[12], *g6 = W.c[13];
+  RF_TRY(D.pair(kTA, w_in, W.nD, kV, Dense::plain(W.c[8], C), vw, true, nr));  // zA, vw
+  RF_TRY(D.prod(kLP, false, D.sigma_t(W.nD), s4, nr));
+  RF_TRY(comb_mean(C, nullptr, -sgn * (k / be), s4, sgn / (k * be), vw, t6, 0.0, nullptr, nr, s));
   const double2* gsel = t6;
   if (use_gsigma(op)) {
-    RF_TRY(D.gtp(t6, g6, nr));
+    RF_TRY(D.prod(kGTP, false, t6, g6, nr));
     gsel = g6;
   }
   return left_y(d, N, C, sgn * k / al, W.nD, s4, gsel, y, nr, s);
@@ -165,35 +271,30 @@ rfcmp_status apply_batch(const Dense& D, const Work& W, const double2* x, double
   hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
-  const int64_t N = h.N, C = h.C, V = h.V;
+  const int64_t C = h.C;
   const double k = op->k, al = op->alpha, be = op->beta, ga = op->gamma;
-  double2 *t1 = W.c[0], *s1 = W.c[1], *g1 = W.c[2], *s1g = W.c[3], *vphi = W.c[4], *t2 = W.c[5],
-          *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8], *s3 = W.c[9];
-  RF_TRY(sigma_t(d, C, N, x, t1, nr, s));
-  RF_TRY(D.lp(t1, s1, nr));
-  const double2* sus = t1;   // Sig^T u_S
+  double2 *s1 = W.c[1], *g1 = W.c[2], *s1g = W.c[3], *vphi = W.c[4], *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8],
+          *s3 = W.c[9];
+  const SymvInput sx = D.sigma_t(x);
+  SymvInput sus = sx;      // Sig^T u_S
   const double2* s_us = s1;  // u_S = Sig s_us
   if (use_gsigma(op)) {
-    RF_TRY(D.gtp(t1, g1, nr));
-    RF_TRY(D.lp(g1, s1g, nr));
-    sus = g1;
+    RF_TRY(D.pair(kLP, sx, s1, kGTP, sx, g1, false, nr));
+    RF_TRY(D.prod(kLP, false, g1, s1g, nr));
+    sus = Dense::plain(g1, C);
     s_us = s1g;
+  } else {
+    RF_TRY(D.prod(kLP, false, sx, s1, nr));
   }
-  RF_TRY(vin(d, N, C, k / al, k / be, x, s1, s_us, W.nA, nr, s));
-  RF_TRY(D.ta(false, W.nA, W.nB, nr));   // a
-  RF_TRY(D.v(false, sus, vphi, nr));     // vphi
-  RF_TRY(sigma_t(d, C, N, W.nB, t2, nr, s));
-  RF_TRY(D.lp(t2, s2, nr));
-  RF_TRY(lambda_t(d, V, N, W.nB, W.v1, nr, s));
-  RF_TRY(D.gll(W.v1, W.v2, nr));
-  RF_TRY(mean(C, vphi, W.m1, nr, s));
-  RF_TRY(comb_c(C, d.area.as<double>(), 1.0, s2, 1.0 / (k * be), vphi, W.m1, t4, nr, s));
-  // s3 lives in c[9]: consumed by middle_w before left_half reuses that slot
-  RF_TRY(D.lp(t4, s3, nr));
-  RF_TRY(middle_w(d, N, C, V, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be), W.v2, W.nB, s2, s3, W.nC, nr, s));
-  RF_TRY(mean(C, t4, W.m2, nr, s));
-  RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0 / (be * be), t4, W.m2, sw, nr, s));
-  return left_half(D, W, y, nr, 1.0);
+  // a = T_A((ik/alpha) u_L - (k/beta) u_S),  vphi = V Sig^T u_S
+  RF_TRY(D.pair(kTA, D.vin(x, s1, s_us, k / al, k / be), W.nB, kV, sus, vphi, false, nr));
+  // s2 = L^+ Sig^T a,  h = G_ll^-1 Lam^T a
+  RF_TRY(D.pair(kLP, D.sigma_t(W.nB), s2, kGLL, D.lambda_t(W.nB), W.v2, false, nr));
+  // t4 = A (s2 + (vphi - mean vphi)/(k beta)),  Sig^T w_S = (t4 - mean t4)/beta^2
+  RF_TRY(comb_mean(C, d.area.as<double>(), 1.0, s2, 1.0 / (k * be), vphi, t4, 1.0 / (be * be), sw, nr, s));
+  RF_TRY(D.prod(kLP, false, t4, s3, nr));
+  return left_half(D, W, D.middle_w(W.v2, W.nB, s2, s3, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be)), y, nr,
+                   1.0);
 }
 
 rfcmp_status rhs_batch(const Dense& D, const Work& W, const double2* e, double2* b, int nr) {
@@ -201,19 +302,13 @@ rfcmp_status rhs_batch(const Dense& D, const Work& W, const double2* e, double2*
   hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
-  const int64_t N = h.N, C = h.C, V = h.V;
+  const int64_t C = h.C;
   const double al = op->alpha, be = op->beta, ga = op->gamma;
-  double2 *t2 = W.c[5], *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8], *s3 = W.c[9];
-  RF_TRY(sigma_t(d, C, N, e, t2, nr, s));
-  RF_TRY(D.lp(t2, s2, nr));
-  RF_TRY(lambda_t(d, V, N, e, W.v1, nr, s));
-  RF_TRY(D.gll(W.v1, W.v2, nr));
-  RF_TRY(comb_c(C, d.area.as<double>(), 1.0, s2, 0.0, nullptr, nullptr, t4, nr, s));
-  RF_TRY(D.lp(t4, s3, nr));
-  RF_TRY(middle_w(d, N, C, V, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be), W.v2, e, s2, s3, W.nC, nr, s));
-  RF_TRY(mean(C, t4, W.m2, nr, s));
-  RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0 / (be * be), t4, W.m2, sw, nr, s));
-  return left_half(D, W, b, nr, -1.0);
+  double2 *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8], *s3 = W.c[9];
+  RF_TRY(D.pair(kLP, D.sigma_t(e), s2, kGLL, D.lambda_t(e), W.v2, false, nr));
+  RF_TRY(comb_mean(C, d.area.as<double>(), 1.0, s2, 0.0, nullptr, t4, 1.0 / (be * be), sw, nr, s));
+  RF_TRY(D.prod(kLP, false, t4, s3, nr));
+  return left_half(D, W, D.middle_w(W.v2, e, s2, s3, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be)), b, nr, -1.0);
 }
 
 rfcmp_status recover_batch(const Dense& D, const Work& W, const double2* x, double2* j, int nr) {
@@ -222,13 +317,14 @@ rfcmp_status recover_batch(const Dense& D, const Work& W, const double2* x, doub
   const MeshHost& h = op->mesh->h;
   const MeshDev& d = op->mesh->d;
   const int64_t N = h.N, C = h.C;
-  RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-  RF_TRY(D.lp(W.c[0], W.c[1], nr));
+  const SymvInput sx = D.sigma_t(x);
   const double2* sg = W.c[1];
   if (use_gsigma(op)) {
-    RF_TRY(D.gtp(W.c[0], W.c[2], nr));
-    RF_TRY(D.lp(W.c[2], W.c[3], nr));
+    RF_TRY(D.pair(kLP, sx, W.c[1], kGTP, sx, W.c[2], false, nr));
+    RF_TRY(D.prod(kLP, false, W.c[2], W.c[3], nr));
     sg = W.c[3];
+  } else {
+    RF_TRY(D.prod(kLP, false, sx, W.c[1], nr));
   }
   return recover_j(d, N, C, 1.0 / op->alpha, 1.0 / op->beta, x, W.c[1], sg, j, nr, s);
 }
@@ -257,28 +353,18 @@ rfcmp_status power_apply(const Dense& D, const Work& W) {
   const int64_t N = h.N, C = h.C, V = h.V;
   double2* va = W.pv;
   double2* vb = W.pv + 2 * N;
-  RF_TRY(sigma_t(d, C, N, va, W.c[0], 2, s));
-  RF_TRY(D.lp(W.c[0], W.c[1], 2));
-  RF_TRY(axpy_sigma(d, N, C, 1.0, false, va, -1.0, W.c[1], W.nA, 2, s));          // P_LH v
-  RF_TRY(D.ta(false, W.nA, W.nB, 2));
-  RF_TRY(lambda_t(d, V, N, W.nB, W.v1, 1, s));
-  RF_TRY(D.gll(W.v1, W.v2, 1));
+  RF_TRY(D.prod(kLP, false, D.sigma_t(va), W.c[1], 2));
+  RF_TRY(D.prod(kTA, false, D.proj_lh(va, W.c[1]), W.nB, 2));                   // T_A P_LH v
+  RF_TRY(D.pair(kLP, D.sigma_t(W.nB + N), W.c[3], kGLL, D.lambda_t(W.nB), W.v2, false, 1));
   RF_TRY(lambda_n(d, N, V, W.v2, W.nC, 1, s));                                   // alpha branch
-  RF_TRY(sigma_t(d, C, N, W.nB + N, W.c[2], 1, s));
-  RF_TRY(D.lp(W.c[2], W.c[3], 1));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nB + N, -1.0, W.c[3], W.nC + N, 1, s));  // gamma branch
-  RF_TRY(D.ta(true, W.nC, W.nD, 2));
-  RF_TRY(sigma_t(d, C, N, W.nD, W.c[4], 2, s));
-  RF_TRY(D.lp(W.c[4], W.c[5], 2));
+  RF_TRY(D.prod(kTA, true, W.nC, W.nD, 2));
+  RF_TRY(D.prod(kLP, false, D.sigma_t(W.nD), W.c[5], 2));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nD, -1.0, W.c[5], W.pw, 2, s));
   // beta
-  RF_TRY(sigma_t(d, C, N, vb, W.c[6], 1, s));
-  RF_TRY(D.v(false, W.c[6], W.c[7], 1));
-  RF_TRY(mean(C, W.c[7], W.m1, 1, s));
-  RF_TRY(comb_c(C, d.area.as<double>(), 0.0, nullptr, 1.0, W.c[7], W.m1, W.c[8], 1, s));
-  RF_TRY(mean(C, W.c[8], W.m2, 1, s));
-  RF_TRY(comb_c(C, nullptr, 0.0, nullptr, 1.0, W.c[8], W.m2, W.c[9], 1, s));
-  RF_TRY(D.v(true, W.c[9], W.c[10], 1));
+  RF_TRY(D.prod(kV, false, D.sigma_t(vb), W.c[7], 1));
+  RF_TRY(comb_mean(C, d.area.as<double>(), 0.0, nullptr, 1.0, W.c[7], W.c[8], 1.0, W.c[9], 1, s));
+  RF_TRY(D.prod(kV, true, W.c[9], W.c[10], 1));
   RF_TRY(axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[10], W.pw + 2 * N, 1, s));
   return RFCMP_OK;
 }
@@ -292,8 +378,7 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStr
     RF_HIP(hipMemcpyAsync(W.pw + r * N, start, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
   for (int it = 0; it < steps; ++it) {
     RF_TRY(dot(N, W.pw, W.pw, W.part, W.dout, 3, s));
-    RF_HIP(hipMemcpyAsync(W.pv, W.pw, sizeof(double2) * 3 * N, hipMemcpyDeviceToDevice, s));
-    RF_TRY(normalize(N, W.dout, W.pv, 3, s));
+    RF_TRY(normalize(N, W.dout, W.pw, W.pv, 3, s));
     RF_TRY(power_apply(D, W));
   }
   RF_TRY(dot(N, W.pw, W.pw, W.part, W.dout, 3, s));
@@ -467,8 +552,8 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
   const int64_t N = op->mesh->h.N;
   const int64_t NR = (int64_t)nr * N;
   const Work W = carve(op);
-  const Dense D64{op, s, false};
-  const Dense D16{op, s, true};
+  const Dense D64{op, s, false, &W};
+  const Dense D16{op, s, true, &W};
   const bool split = op->opt.precision == 1;
   RF_TRY(rhs_batch(D64, W, e, W.b0, nr));
   RF_HIP(hipMemcpyAsync(W.b, W.b0, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
@@ -756,7 +841,7 @@ rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt, c
   RF_TRY(op->TA.alloc(sizeof(float2) * N * op->ldA));
   RF_TRY(op->Vb.alloc(sizeof(float2) * C * op->ldV));
   RF_TRY(ensure_work(op.get(), 4));
-  RF_TRY(op->symv_scratch.alloc(symv_scratch_bytes(std::max(N, std::max(C, V)), 4)));
+  RF_TRY(op->symv_scratch.alloc(symv_scratch_bytes(N, 4) + symv_scratch_bytes(C, 4) + symv_scratch_bytes(V, 4)));
   RF_TRY(assemble_blocks(op.get(), s));
   op->alpha = std::sqrt(k);
   op->beta = 1.0 / std::sqrt(k);
@@ -874,19 +959,19 @@ rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* xv, void* yv,
                      case RFCMP_PROJ_SIGMA:
                      case RFCMP_PROJ_LH:
                        RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-                       RF_TRY(dsymv(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, SYMV, s, "dmatvec_lp"));
+                       RF_TRY(dsymv(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_lp"));
                        return which == RFCMP_PROJ_SIGMA
                                   ? axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[1], y, nr, s)
                                   : axpy_sigma(d, N, C, 1.0, false, x, -1.0, W.c[1], y, nr, s);
                      case RFCMP_PROJ_GSIGMA:
                        RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-                       RF_TRY(dsymv(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, SYMV, s, "dmatvec_gtp"));
-                       RF_TRY(dsymv(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[1], nr, SYMV, s, "dmatvec_lp"));
+                       RF_TRY(dsymv(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_gtp"));
+                       RF_TRY(dsymv(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[1], nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_lp"));
                        return axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[1], y, nr, s);
                      case RFCMP_PROJ_LPINV:
-                       return dsymv(d.Lp.as<double>(), C, d.ldL, x, y, nr, SYMV, s, "dmatvec_lp");
+                       return dsymv(d.Lp.as<double>(), C, d.ldL, x, y, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_lp");
                      case RFCMP_PROJ_GLL_INV:
-                       return dsymv(d.Gll_inv.as<double>(), V, d.ldG, x, y, nr, SYMV, s, "dmatvec_gll");
+                       return dsymv(d.Gll_inv.as<double>(), V, d.ldG, x, y, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_gll");
                      case RFCMP_PROJ_SIGMA_T:
                        return sigma_t(d, C, N, x, y, nr, s);
                      default:
@@ -903,16 +988,20 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
   const double2* xx = static_cast<const double2*>(x);
   double2* yy = static_cast<double2*>(y);
   if (which == 0)
-    return csymv(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, xx, yy, nrhs, SYMV, s, "cmatvec_ta");
+    return csymv(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, xx, yy, nrhs, op->symv_scratch.p,
+                 op->symv_scratch.bytes, s, "cmatvec_ta");
   if (which == 1)
-    return csymv(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj != 0, xx, yy, nrhs, SYMV, s, "cmatvec_v");
+    return csymv(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj != 0, xx, yy, nrhs, op->symv_scratch.p,
+                 op->symv_scratch.bytes, s, "cmatvec_v");
   RF_TRY(ensure_split(op, s));
-  const Dense D{op, s, true};
+  RF_TRY(ensure_work(op, 4));
+  const Work W = carve(op);
+  const Dense D{op, s, true, &W};
   switch (which) {
-    case 2: return D.ta(conj != 0, xx, yy, nrhs);
-    case 3: return D.v(conj != 0, xx, yy, nrhs);
-    case 4: return D.lp(xx, yy, nrhs);
-    default: return D.gll(xx, yy, nrhs);
+    case 2: return D.prod(kTA, conj != 0, xx, yy, nrhs);
+    case 3: return D.prod(kV, conj != 0, xx, yy, nrhs);
+    case 4: return D.prod(kLP, false, xx, yy, nrhs);
+    default: return D.prod(kGLL, false, xx, yy, nrhs);
   }
 }
 

@@ -24,7 +24,14 @@
 // issued as soon as sub-tile t sits in LDS.  Products are formed
 // and accumulated in FP64 (complex64 entries are widened), x and y are
 // complex128.
-#include "internal.h"
+//
+// The input x is formed while it is staged (SymvInput): a plain vector, or a
+// sparse incidence product (Sigma^T, Lambda^T) or fused operator line of
+// vectors already in HBM.  Each workgroup forms only the 2 x 128 entries it
+// needs, reading a few source entries per entry from L2.  One launch can
+// carry two products of the same element type (their blocks side by side in
+// the grid), so a small matrix rides along with a large one.
+#include "symv.h"
 
 namespace rfcmp {
 
@@ -72,12 +79,95 @@ __device__ inline typename T::Pair zero_pair() {
   return z;
 }
 
+__device__ inline double2 csub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// x[r][g] of a SymvInput (g < n).
+__device__ inline double2 input_entry(const SymvInput& in, int r, int g) {
+  const double2* p0 = in.p[0] + r * in.stride[0];
+  switch (in.mode) {
+    case SymvInput::kSigmaT: {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const double2 v = p0[in.idx0[3 * g + l]];
+        const double sg = in.sgn[3 * g + l];
+        sr = fma(sg, v.x, sr);
+        si = fma(sg, v.y, si);
+      }
+      return make_double2(sr, si);
+    }
+    case SymvInput::kLambdaT: {
+      double sr = 0.0, si = 0.0;
+      for (int q = in.idx0[g]; q < in.idx0[g + 1]; ++q) {
+        const double2 v = p0[in.idx1[q]];
+        const double sg = in.sgn[q];
+        sr = fma(sg, v.x, sr);
+        si = fma(sg, v.y, si);
+      }
+      return make_double2(sr, si);
+    }
+    case SymvInput::kVin: {
+      const int cp = in.idx0[2 * g], cm = in.idx0[2 * g + 1];
+      const double2* p1 = in.p[1] + r * in.stride[1];
+      const double2* p2 = in.p[2] + r * in.stride[2];
+      const double2 ul = csub2(p0[g], csub2(p1[cp], p1[cm]));
+      const double2 ug = csub2(p2[cp], p2[cm]);
+      const double ka = in.c[0], kb = in.c[1];
+      return make_double2(-ka * ul.y - kb * ug.x, ka * ul.x - kb * ug.y);
+    }
+    case SymvInput::kMiddleW: {
+      const int cp = in.idx0[2 * g], cm = in.idx0[2 * g + 1];
+      const double2* p1 = in.p[1] + r * in.stride[1];
+      const double2* p2 = in.p[2] + r * in.stride[2];
+      const double2* p3 = in.p[3] + r * in.stride[3];
+      const double2 lh = csub2(p0[in.idx1[2 * g]], p0[in.idx1[2 * g + 1]]);
+      const double2 pl = csub2(p1[g], csub2(p2[cp], p2[cm]));
+      const double2 ss = csub2(p3[cp], p3[cm]);
+      return make_double2(in.c[0] * lh.x + in.c[1] * pl.x + in.c[2] * ss.x,
+                          in.c[0] * lh.y + in.c[1] * pl.y + in.c[2] * ss.y);
+    }
+    case SymvInput::kProjLH: {
+      const int cp = in.idx0[2 * g], cm = in.idx0[2 * g + 1];
+      const double2* p1 = in.p[1] + r * in.stride[1];
+      return csub2(p0[g], csub2(p1[cp], p1[cm]));
+    }
+    default:
+      return p0[g];
+  }
+}
+
+__global__ void k_form_input(const SymvInput in, int n, double2* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (g < n) out[(long)r * n + g] = input_entry(in, r, g);
+}
+
+// Kernel arguments: up to two products; blocks [0, nblk0) belong to job 0.
+struct JobArg {
+  const void* M;
+  int n;
+  long ldp;  // row length in 16-byte pairs
+  int nsb;
+  SymvInput in;
+  double2* part;
+  double2* y;
+};
+struct JobsArg {
+  JobArg j[2];
+  int nblk0;
+  int nsb0;
+};
+
 // Partial buffer layout: part[((K * nsb + L) * NR + r) * S + i], complex128.
 template <class T, int S, int NR, bool CONJ>
-__global__ __launch_bounds__(kThreads) void k_symv(const typename T::Pair* __restrict__ M, int n, long ldp,
-                                                   int nsb, const double2* __restrict__ x,
-                                                   double2* __restrict__ part) {
+__global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
   typedef typename T::Pair Pair;
+  const int job = (int)blockIdx.x < args.nblk0 ? 0 : 1;
+  const JobArg& ja = args.j[job];
+  const Pair* __restrict__ M = static_cast<const Pair*>(ja.M);
+  const int n = ja.n, nsb = ja.nsb;
+  const long ldp = ja.ldp;
+  double2* __restrict__ part = ja.part;
   constexpr int PP = S / 2;                       // column pairs per row
   constexpr int G = kThreads / PP;                // row groups in the load layout
   constexpr int LPT = kRowsSub / G;               // loads per thread per sub-tile
@@ -87,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_symv(const typename T::Pair* __res
   static_assert(kRowsSub % G == 0 && PP % TPR == 0 && NSUB % 2 == 0, "block shape");
 
   // block (P, Q), Q >= P, from the linear upper-triangle index
-  int P = 0, rem = blockIdx.x;
+  int P = 0, rem = (int)blockIdx.x - (job ? args.nblk0 : 0);
   while (rem >= nsb - P) {
     rem -= nsb - P;
     ++P;
@@ -118,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_symv(const typename T::Pair* __res
   for (int t = tid; t < 2 * NR * S; t += kThreads) {
     const int side = t / (NR * S), r = (t / S) % NR, i = t % S;
     const int g = (side == 0 ? P : Q) * S + i;
-    xs[side][r][i] = (g < n) ? x[(long)r * n + g] : make_double2(0.0, 0.0);
+    xs[side][r][i] = (g < n) ? input_entry(ja.in, r, g) : make_double2(0.0, 0.0);
   }
 
   double cr[2][NR], ci[2][NR];  // transposed sums of the two columns
@@ -218,15 +308,18 @@ __global__ __launch_bounds__(kThreads) void k_symv(const typename T::Pair* __res
 // y[r][K S + i] = sum over L (in order) of part[K][L][r][i].  Workgroup
 // (K, r): four threads per row each add a quarter of the slots (unrolled, so
 // the loads overlap), then the quarters are added in order through LDS.
+// Blocks [0, nsb0) of the grid reduce job 0, the rest job 1.
 template <int S, int NR>
-__global__ __launch_bounds__(4 * S) void k_symv_reduce(int n, int nsb, const double2* __restrict__ part,
-                                                       double2* __restrict__ y) {
+__global__ __launch_bounds__(4 * S) void k_symv_reduce(const JobsArg args) {
   __shared__ double2 q4[4][S];
-  const int K = blockIdx.x, r = blockIdx.y;
+  const int job = (int)blockIdx.x < args.nsb0 ? 0 : 1;
+  const JobArg& ja = args.j[job];
+  const int n = ja.n, nsb = ja.nsb;
+  const int K = (int)blockIdx.x - (job ? args.nsb0 : 0), r = blockIdx.y;
   const int i = threadIdx.x % S, qt = threadIdx.x / S;
   const int per = (nsb + 3) / 4;
   const int L0 = qt * per, L1 = min(nsb, L0 + per);
-  const double2* src = part + (((long)K * nsb) * NR + r) * S + i;
+  const double2* src = ja.part + (((long)K * nsb) * NR + r) * S + i;
   double sr = 0.0, si = 0.0;
 #pragma unroll 4
   for (int L = L0; L < L1; ++L) {
@@ -243,7 +336,7 @@ __global__ __launch_bounds__(4 * S) void k_symv_reduce(int n, int nsb, const dou
       t.x += q4[u][i].x;
       t.y += q4[u][i].y;
     }
-    y[(long)r * n + row] = t;
+    ja.y[(long)r * n + row] = t;
   }
 }
 
@@ -252,41 +345,70 @@ constexpr int kS = 128;
 // The product kernel is timed under `tag` (one right-hand side) or
 // "<tag>_nr<k>" (k right-hand sides), the slot sums under "symv_reduce".
 template <class T, int NR, bool CONJ>
-void launch(const void* M, int n, long ld, int nsb, const double2* x, double2* part, double2* y, hipStream_t s,
-            const char* tag) {
-  const long nblk = (long)nsb * (nsb + 1) / 2;
+void launch(const JobsArg& a, int nblk, int nsbsum, hipStream_t s, const char* tag) {
   {
     ProfScope prof(NR == 1 ? tag : profile_tag_suffix(tag, NR), s);
-    hipLaunchKernelGGL((k_symv<T, kS, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s,
-                       static_cast<const typename T::Pair*>(M), n, ld / 2, nsb, x, part);
+    hipLaunchKernelGGL((k_symv<T, kS, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s, a);
   }
   ProfScope prof("symv_reduce", s);
-  hipLaunchKernelGGL((k_symv_reduce<kS, NR>), dim3((unsigned)nsb, NR), dim3(4 * kS), 0, s, n, nsb, part, y);
+  hipLaunchKernelGGL((k_symv_reduce<kS, NR>), dim3((unsigned)nsbsum, NR), dim3(4 * kS), 0, s, a);
+}
+
+// Advance every source pointer of an input by r0 right-hand sides.
+SymvInput shift_input(SymvInput in, int r0) {
+  for (int q = 0; q < 4; ++q)
+    if (in.p[q]) in.p[q] += (long)r0 * in.stride[q];
+  return in;
 }
 
 template <class T, bool CONJ>
-rfcmp_status symv_any(const void* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
-                      void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag) {
-  if (n <= 0 || nrhs <= 0) return RFCMP_OK;
-  if (ld % 2 != 0) {
-    set_error("symv: leading dimension %lld is odd", (long long)ld);
+rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, size_t scratch_bytes,
+                      hipStream_t s, const char* tag) {
+  if (njobs < 1 || njobs > 2) {
+    set_error("symv: %d jobs (1 or 2 allowed)", njobs);
     return RFCMP_E_ARG;
   }
-  const int nsb = int((n + kS - 1) / kS);
-  if (symv_scratch_bytes(n, std::min(nrhs, kMaxNR)) > scratch_bytes) {
-    set_error("symv: n = %lld needs more scratch than the %zu bytes given", (long long)n, scratch_bytes);
+  if (nrhs <= 0) return RFCMP_OK;
+  size_t need = 0;
+  for (int q = 0; q < njobs; ++q) {
+    if (jobs[q].n <= 0 || jobs[q].ld % 2 != 0 || jobs[q].ld < jobs[q].n) {
+      set_error("symv: job %d has n = %lld, ld = %lld", q, (long long)jobs[q].n, (long long)jobs[q].ld);
+      return RFCMP_E_ARG;
+    }
+    need += symv_scratch_bytes(jobs[q].n, std::min(nrhs, kMaxNR));
+  }
+  if (need > scratch_bytes) {
+    set_error("symv: needs %zu bytes of scratch, %zu given", need, scratch_bytes);
     return RFCMP_E_ARG;
   }
-  double2* part = static_cast<double2*>(scratch);
   for (int r0 = 0; r0 < nrhs; r0 += kMaxNR) {
     const int nr = std::min(kMaxNR, nrhs - r0);
-    const double2* xr = x + (long)r0 * n;
-    double2* yr = y + (long)r0 * n;
+    JobsArg a{};
+    char* sp = static_cast<char*>(scratch);
+    int nblk = 0, nsbsum = 0;
+    for (int q = 0; q < njobs; ++q) {
+      const SymvJob& jb = jobs[q];
+      JobArg& ja = a.j[q];
+      ja.M = jb.M;
+      ja.n = (int)jb.n;
+      ja.ldp = (long)(jb.ld / 2);
+      ja.nsb = int((jb.n + kS - 1) / kS);
+      ja.in = shift_input(jb.in, r0);
+      ja.part = reinterpret_cast<double2*>(sp);
+      ja.y = jb.y + (long)r0 * jb.n;
+      sp += symv_scratch_bytes(jb.n, nr);
+      if (q == 0) {
+        a.nblk0 = ja.nsb * (ja.nsb + 1) / 2;
+        a.nsb0 = ja.nsb;
+      }
+      nblk += ja.nsb * (ja.nsb + 1) / 2;
+      nsbsum += ja.nsb;
+    }
     switch (nr) {
-      case 1: launch<T, 1, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s, tag); break;
-      case 2: launch<T, 2, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s, tag); break;
-      case 3: launch<T, 3, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s, tag); break;
-      default: launch<T, 4, CONJ>(M, (int)n, ld, nsb, xr, part, yr, s, tag); break;
+      case 1: launch<T, 1, CONJ>(a, nblk, nsbsum, s, tag); break;
+      case 2: launch<T, 2, CONJ>(a, nblk, nsbsum, s, tag); break;
+      case 3: launch<T, 3, CONJ>(a, nblk, nsbsum, s, tag); break;
+      default: launch<T, 4, CONJ>(a, nblk, nsbsum, s, tag); break;
     }
   }
   RF_HIP(hipGetLastError());
@@ -301,16 +423,46 @@ size_t symv_scratch_bytes(int64_t n, int nrhs) {
   return sizeof(double2) * (size_t)(nsb * nsb * nr * kS);
 }
 
+rfcmp_status symv_form_input(const SymvInput& in, int64_t n, int nrhs, double2* out, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return RFCMP_OK;
+  hipLaunchKernelGGL(k_form_input, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, in, (int)n, out);
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+
+rfcmp_status csymv_jobs(const SymvJob* jobs, int njobs, bool conj, int nrhs, void* scratch, size_t scratch_bytes,
+                        hipStream_t s, const char* tag) {
+  if (conj) return symv_any<C64, true>(jobs, njobs, nrhs, scratch, scratch_bytes, s, tag);
+  return symv_any<C64, false>(jobs, njobs, nrhs, scratch, scratch_bytes, s, tag);
+}
+
+rfcmp_status dsymv_jobs(const SymvJob* jobs, int njobs, int nrhs, void* scratch, size_t scratch_bytes,
+                        hipStream_t s, const char* tag) {
+  return symv_any<F64, false>(jobs, njobs, nrhs, scratch, scratch_bytes, s, tag);
+}
+
 rfcmp_status csymv(const float2* M, int64_t n, int64_t ld, bool conj, const double2* x, double2* y, int nrhs,
                    void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag) {
-  // ld counts complex entries; the kernels address 16-byte pairs (two entries)
-  if (conj) return symv_any<C64, true>(M, n, ld, x, y, nrhs, scratch, scratch_bytes, s, tag);
-  return symv_any<C64, false>(M, n, ld, x, y, nrhs, scratch, scratch_bytes, s, tag);
+  SymvJob j;
+  j.M = M;
+  j.n = n;
+  j.ld = ld;
+  j.in.p[0] = x;
+  j.in.stride[0] = n;
+  j.y = y;
+  return csymv_jobs(&j, 1, conj, nrhs, scratch, scratch_bytes, s, tag);
 }
 
 rfcmp_status dsymv(const double* M, int64_t n, int64_t ld, const double2* x, double2* y, int nrhs,
                    void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag) {
-  return symv_any<F64, false>(M, n, ld, x, y, nrhs, scratch, scratch_bytes, s, tag);
+  SymvJob j;
+  j.M = M;
+  j.n = n;
+  j.ld = ld;
+  j.in.p[0] = x;
+  j.in.stride[0] = n;
+  j.y = y;
+  return dsymv_jobs(&j, 1, nrhs, scratch, scratch_bytes, s, tag);
 }
 
 }  // namespace rfcmp

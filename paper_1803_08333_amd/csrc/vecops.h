@@ -14,18 +14,10 @@ rfcmp_status lambda_n(const MeshDev& d, int64_t N, int64_t V, const double2* h, 
 // out = ca*x (times i if ca_imag; x nullable) + cs * Sigma z
 rfcmp_status axpy_sigma(const MeshDev& d, int64_t N, int64_t C, double ca, bool ca_imag, const double2* x,
                         double cs, const double2* z, double2* out, int nr, hipStream_t s);
-// out = i ka (x - Sigma s1) - kb Sigma s1g
-rfcmp_status vin(const MeshDev& d, int64_t N, int64_t C, double ka, double kb, const double2* x,
-                 const double2* s1, const double2* s1g, double2* out, int nr, hipStream_t s);
-// m[r] = mean of x[r] (length n)
-rfcmp_status mean(int64_t n, const double2* x, double2* m, int nr, hipStream_t s);
-// out = [area .*] (fa a + fb (b - mb))   (a, b, area nullable)
-rfcmp_status comb_c(int64_t C, const double* area, double fa, const double2* a, double fb, const double2* b,
-                    const double2* mb, double2* out, int nr, hipStream_t s);
-// w = Lambda h ia2 + (a - Sigma s2) ig + Sigma s3 ib2
-rfcmp_status middle_w(const MeshDev& d, int64_t N, int64_t C, int64_t V, double ia2, double ig, double ib2,
-                      const double2* h, const double2* a, const double2* s2, const double2* s3, double2* w,
-                      int nr, hipStream_t s);
+// out1 = [area .*] (fa a + fb (b - mean b)), out2 = f2 (out1 - mean out1), the
+// means formed in the same launch (area, a, b, out2 nullable)
+rfcmp_status comb_mean(int64_t C, const double* area, double fa, const double2* a, double fb, const double2* b,
+                       double2* out1, double f2, double2* out2, int nr, hipStream_t s);
 // y = -i ka (zA - Sigma s4) + Sigma g6
 rfcmp_status left_y(const MeshDev& d, int64_t N, int64_t C, double ka, const double2* zA, const double2* s4,
                     const double2* g6, double2* y, int nr, hipStream_t s);
@@ -36,12 +28,8 @@ rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double
 rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, double2* out, int nr,
                  hipStream_t s);
 int dot_partials();
-rfcmp_status normalize(int64_t n, const double2* nrm2, double2* x, int nr, hipStream_t s);
-rfcmp_status cg_xr(int64_t n, const double* sc, int rho_slot, double2* x, double2* r, const double2* p,
-                   const double2* q, hipStream_t s);
-rfcmp_status cg_p(int64_t n, const double* sc, int old_slot, int new_slot, const double2* r, double2* p,
-                  hipStream_t s);
-rfcmp_status take_real(const double2* d, double* sc, int slot, hipStream_t s);
+// out[r] = x[r] / sqrt(re nrm2[r])
+rfcmp_status normalize(int64_t n, const double2* nrm2, const double2* x, double2* out, int nr, hipStream_t s);
 // block CG updates over nr right-hand sides (frozen where active[r] == 0)
 rfcmp_status cg_xr_blk(int64_t n, int nr, const double* rho, const double* pq, const int* active, double2* x,
                        double2* r, const double2* p, const double2* q, hipStream_t s);

@@ -64,29 +64,8 @@ __global__ void k_axpy_sigma(int N, int C, const int* __restrict__ edge_cell, do
   out[r * N + n] = cadd(a, cscale(cs, zd));
 }
 
-// v_in = (ik/alpha)(x - Sigma s1) - (k/beta) Sigma s1g
-__global__ void k_vin(int N, int C, const int* __restrict__ edge_cell, double ka, double kb,
-                      const double2* __restrict__ x, const double2* __restrict__ s1,
-                      const double2* __restrict__ s1g, double2* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  const long r = blockIdx.y;
-  const int cp = edge_cell[2 * n], cm = edge_cell[2 * n + 1];
-  const double2 us = csub(s1[r * C + cp], s1[r * C + cm]);
-  const double2 ug = csub(s1g[r * C + cp], s1g[r * C + cm]);
-  const double2 ul = csub(x[r * N + n], us);
-  out[r * N + n] = csub(cimul(ka, ul), cscale(kb, ug));
-}
-
-// Per-rhs mean of a length-n vector; one block per rhs, fixed-order tree.
-__global__ __launch_bounds__(1024) void k_mean(int n, const double2* __restrict__ x, double2* __restrict__ m) {
-  __shared__ double sr[1024], si[1024];
-  const long r = blockIdx.x;
-  double ar = 0.0, ai = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024) {
-    ar += x[r * n + i].x;
-    ai += x[r * n + i].y;
-  }
+// Sum over the workgroup (1024 threads), fixed-order tree; every thread gets the result.
+__device__ double2 block_sum_1024(double ar, double ai, double* sr, double* si) {
   sr[threadIdx.x] = ar;
   si[threadIdx.x] = ai;
   __syncthreads();
@@ -97,37 +76,43 @@ __global__ __launch_bounds__(1024) void k_mean(int n, const double2* __restrict_
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) m[r] = make_double2(sr[0] / n, si[0] / n);
+  const double2 t = make_double2(sr[0], si[0]);
+  __syncthreads();  // sr/si may be reused
+  return t;
 }
 
-// out[c] = fa * a[c] + fb * (b[c] - mean_b) (+ area weighting when area != null:
-// out[c] = A_c * (...)).  b, mean_b nullable.
-__global__ void k_comb_c(int C, const double* __restrict__ area, double fa, const double2* __restrict__ a,
-                         double fb, const double2* __restrict__ b, const double2* __restrict__ mb,
-                         double2* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  const long r = blockIdx.y;
-  double2 v = a ? cscale(fa, a[r * C + c]) : make_double2(0.0, 0.0);
-  if (b) v = cadd(v, cscale(fb, csub(b[r * C + c], mb[r])));
-  if (area) v = cscale(area[c], v);
-  out[r * C + c] = v;
-}
-
-// w = Lambda h/alpha^2 + (a - Sigma s2)/gamma + Sigma s3/beta^2
-__global__ void k_middle_w(int N, int C, int V, const int* __restrict__ edge_cell,
-                           const int* __restrict__ edge_vtx, double ia2, double ig, double ib2,
-                           const double2* __restrict__ h, const double2* __restrict__ a,
-                           const double2* __restrict__ s2, const double2* __restrict__ s3,
-                           double2* __restrict__ w) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  const long r = blockIdx.y;
-  const int cp = edge_cell[2 * n], cm = edge_cell[2 * n + 1];
-  const double2 lh = csub(h[r * V + edge_vtx[2 * n]], h[r * V + edge_vtx[2 * n + 1]]);
-  const double2 pl = csub(a[r * N + n], csub(s2[r * C + cp], s2[r * C + cm]));
-  const double2 ss = csub(s3[r * C + cp], s3[r * C + cm]);
-  w[r * N + n] = cadd(cadd(cscale(ia2, lh), cscale(ig, pl)), cscale(ib2, ss));
+// out1[c] = [A_c] (fa a[c] + fb (b[c] - mean b));  out2[c] = f2 (out1[c] - mean out1)
+// (area, a, b, out2 nullable).  One workgroup per right-hand side, so the
+// means need no second launch; each thread revisits only entries it wrote.
+__global__ __launch_bounds__(1024) void k_comb_mean(int C, const double* __restrict__ area, double fa,
+                                                    const double2* __restrict__ a, double fb,
+                                                    const double2* __restrict__ b, double2* __restrict__ out1,
+                                                    double f2, double2* __restrict__ out2) {
+  __shared__ double sr[1024], si[1024];
+  const long r = blockIdx.x;
+  double2 mb = make_double2(0.0, 0.0);
+  if (b) {
+    double ar = 0.0, ai = 0.0;
+    for (int i = threadIdx.x; i < C; i += 1024) {
+      ar += b[r * C + i].x;
+      ai += b[r * C + i].y;
+    }
+    const double2 t = block_sum_1024(ar, ai, sr, si);
+    mb = make_double2(t.x / C, t.y / C);
+  }
+  double ar = 0.0, ai = 0.0;
+  for (int i = threadIdx.x; i < C; i += 1024) {
+    double2 v = a ? cscale(fa, a[r * C + i]) : make_double2(0.0, 0.0);
+    if (b) v = cadd(v, cscale(fb, csub(b[r * C + i], mb)));
+    if (area) v = cscale(area[i], v);
+    out1[r * C + i] = v;
+    ar += v.x;
+    ai += v.y;
+  }
+  if (!out2) return;
+  const double2 t = block_sum_1024(ar, ai, sr, si);
+  const double2 m1 = make_double2(t.x / C, t.y / C);
+  for (int i = threadIdx.x; i < C; i += 1024) out2[r * C + i] = cscale(f2, csub(out1[r * C + i], m1));
 }
 
 // y = -(ik/alpha)(zA - Sigma s4) + Sigma g6
@@ -215,36 +200,15 @@ __global__ __launch_bounds__(256) void k_dot_final(int nb, const double2* __rest
 }
 
 // x[r] *= 1/sqrt(re(nrm2[r]))
-__global__ void k_normalize(long n, const double2* __restrict__ nrm2, double2* __restrict__ x) {
+__global__ void k_normalize(long n, const double2* __restrict__ nrm2, const double2* __restrict__ x,
+                            double2* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const long r = blockIdx.y;
   const double s = 1.0 / sqrt(nrm2[r].x);
-  x[r * n + i] = cscale(s, x[r * n + i]);
+  out[r * n + i] = cscale(s, x[r * n + i]);
 }
 
-// CG: alpha = rho/pq; x += alpha p; r -= alpha q
-__global__ void k_cg_xr(long n, const double* __restrict__ sc, int rho_slot, double2* __restrict__ x,
-                        double2* __restrict__ r, const double2* __restrict__ p,
-                        const double2* __restrict__ q) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double al = sc[rho_slot] / sc[2];
-  x[i] = cadd(x[i], cscale(al, p[i]));
-  r[i] = csub(r[i], cscale(al, q[i]));
-}
-// CG: p = r + (rho_new/rho_old) p
-__global__ void k_cg_p(long n, const double* __restrict__ sc, int old_slot, int new_slot,
-                       const double2* __restrict__ r, double2* __restrict__ p) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double be = sc[new_slot] / sc[old_slot];
-  p[i] = cadd(r[i], cscale(be, p[i]));
-}
-// copy the real part of a complex scalar into a slot
-__global__ void k_take_real(const double2* __restrict__ d, double* __restrict__ sc, int slot) {
-  sc[slot] = d[0].x;
-}
 __global__ void k_sub(long n, const double2* __restrict__ a, const double2* __restrict__ b,
                       double2* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,30 +286,10 @@ rfcmp_status axpy_sigma(const MeshDev& d, int64_t N, int64_t C, double ca, bool 
   RF_LAUNCH_CHECK();
   return RFCMP_OK;
 }
-rfcmp_status vin(const MeshDev& d, int64_t N, int64_t C, double ka, double kb, const double2* x,
-                 const double2* s1, const double2* s1g, double2* out, int nr, hipStream_t s) {
-  hipLaunchKernelGGL(k_vin, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, d.edge_cell.as<int>(), ka, kb, x, s1,
-                     s1g, out);
-  RF_LAUNCH_CHECK();
-  return RFCMP_OK;
-}
-rfcmp_status mean(int64_t n, const double2* x, double2* m, int nr, hipStream_t s) {
-  hipLaunchKernelGGL(k_mean, dim3(nr), dim3(1024), 0, s, (int)n, x, m);
-  RF_LAUNCH_CHECK();
-  return RFCMP_OK;
-}
-rfcmp_status comb_c(int64_t C, const double* area, double fa, const double2* a, double fb, const double2* b,
-                    const double2* mb, double2* out, int nr, hipStream_t s) {
-  hipLaunchKernelGGL(k_comb_c, g1(C, nr), dim3(256), 0, s, (int)C, area, fa, a, fb, b, mb, out);
-  RF_LAUNCH_CHECK();
-  return RFCMP_OK;
-}
-rfcmp_status middle_w(const MeshDev& d, int64_t N, int64_t C, int64_t V, double ia2, double ig, double ib2,
-                      const double2* h, const double2* a, const double2* s2, const double2* s3, double2* w,
-                      int nr, hipStream_t s) {
-  hipLaunchKernelGGL(k_middle_w, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, (int)V, d.edge_cell.as<int>(),
-                     d.edge_vtx.as<int>(), ia2, ig, ib2, h, a, s2, s3, w);
-  RF_LAUNCH_CHECK();
+rfcmp_status comb_mean(int64_t C, const double* area, double fa, const double2* a, double fb, const double2* b,
+                       double2* out1, double f2, double2* out2, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_comb_mean, dim3(nr), dim3(1024), 0, s, (int)C, area, fa, a, fb, b, out1, f2, out2);
+  RF_HIP(hipGetLastError());
   return RFCMP_OK;
 }
 rfcmp_status left_y(const MeshDev& d, int64_t N, int64_t C, double ka, const double2* zA, const double2* s4,
@@ -370,20 +314,8 @@ rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, d
   return RFCMP_OK;
 }
 int dot_partials() { return kRedBlocks; }
-rfcmp_status normalize(int64_t n, const double2* nrm2, double2* x, int nr, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize, g1(n, nr), dim3(256), 0, s, (long)n, nrm2, x);
-  RF_LAUNCH_CHECK();
-  return RFCMP_OK;
-}
-rfcmp_status cg_xr(int64_t n, const double* sc, int rho_slot, double2* x, double2* r, const double2* p,
-                   const double2* q, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_xr, g1(n), dim3(256), 0, s, (long)n, sc, rho_slot, x, r, p, q);
-  RF_LAUNCH_CHECK();
-  return RFCMP_OK;
-}
-rfcmp_status cg_p(int64_t n, const double* sc, int old_slot, int new_slot, const double2* r, double2* p,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_p, g1(n), dim3(256), 0, s, (long)n, sc, old_slot, new_slot, r, p);
+rfcmp_status normalize(int64_t n, const double2* nrm2, const double2* x, double2* out, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize, g1(n, nr), dim3(256), 0, s, (long)n, nrm2, x, out);
   RF_LAUNCH_CHECK();
   return RFCMP_OK;
 }
@@ -406,11 +338,6 @@ rfcmp_status take_real_n(const double2* d, double* out, int nr, hipStream_t s) {
 }
 rfcmp_status set_active(int* a, int v, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_set_int, dim3((n + 255) / 256), dim3(256), 0, s, a, v, n);
-  RF_LAUNCH_CHECK();
-  return RFCMP_OK;
-}
-rfcmp_status take_real(const double2* d, double* sc, int slot, hipStream_t s) {
-  hipLaunchKernelGGL(k_take_real, dim3(1), dim3(1), 0, s, d, sc, slot);
   RF_LAUNCH_CHECK();
   return RFCMP_OK;
 }
