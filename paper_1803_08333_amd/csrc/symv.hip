@@ -19,7 +19,8 @@
 // reads a whole row), accumulates the transposed product M^T x_P for its
 // column pair straight from registers, and stores the sub-tile to LDS, from
 // where eight threads per row form the row sums M x_Q (thread s of a row
-// takes pairs s, s + 8, ..., so a row's threads read adjacent LDS words).
+// takes pairs s, s + 8, ..., so a row's threads read adjacent LDS words; the
+// eight partial sums meet through DPP lane moves).
 // Two sub-tiles are in flight per workgroup: the loads of sub-tile t + 2 are
 // issued as soon as sub-tile t sits in LDS.  Products are formed
 // and accumulated in FP64 (complex64 entries are widened), x and y are
@@ -158,57 +159,69 @@ struct JobsArg {
   int nsb0;
 };
 
-// Partial buffer layout: part[((K * nsb + L) * NR + r) * S + i], complex128.
-template <class T, int S, int NR, bool CONJ>
-__global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
+// DPP move of a double: lane i takes the value of the lane CTRL selects
+// (quad_perm or row shift); lanes without a source get 0.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over each aligned group of 8 lanes; lanes 4..7 of a group hold it.
+__device__ inline double sum8(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_move<0x114>(v);  // row_shr:4: lanes 4..7 add lanes 0..3
+  return v;
+}
+
+// One block (P, Q) of a product.  EDGE: the block reaches past n, so loads
+// are masked (rows beyond n are not read, columns beyond n read as zero).
+// The block's rows start at the uniform address `strip`; each thread
+// addresses its 16-byte pairs by 32-bit offsets from it.
+template <class T, int S, int NR, bool CONJ, bool EDGE>
+__device__ void symv_block(const char* __restrict__ strip, int n, int ldp, int P, int Q,
+                           const SymvInput& in, double2* __restrict__ part, int nsb,
+                           typename T::Pair (*tile)[S / 2 + 1], double2 (*xs)[NR][S]) {
   typedef typename T::Pair Pair;
-  const int job = (int)blockIdx.x < args.nblk0 ? 0 : 1;
-  const JobArg& ja = args.j[job];
-  const Pair* __restrict__ M = static_cast<const Pair*>(ja.M);
-  const int n = ja.n, nsb = ja.nsb;
-  const long ldp = ja.ldp;
-  double2* __restrict__ part = ja.part;
   constexpr int PP = S / 2;                       // column pairs per row
   constexpr int G = kThreads / PP;                // row groups in the load layout
   constexpr int LPT = kRowsSub / G;               // loads per thread per sub-tile
   constexpr int NSUB = S / kRowsSub;              // sub-tiles per block
   constexpr int TPR = kThreads / kRowsSub;        // threads per row in the row sums
   constexpr int PPT = PP / TPR;                   // pairs per thread in the row sums
-  static_assert(kRowsSub % G == 0 && PP % TPR == 0 && NSUB % 2 == 0, "block shape");
-
-  // block (P, Q), Q >= P, from the linear upper-triangle index
-  int P = 0, rem = (int)blockIdx.x - (job ? args.nblk0 : 0);
-  while (rem >= nsb - P) {
-    rem -= nsb - P;
-    ++P;
-  }
-  const int Q = P + rem;
+  static_assert(kRowsSub % G == 0 && PP % TPR == 0 && NSUB % 2 == 0 && TPR == 8, "block shape");
   const bool diag = (P == Q);
-
-  __shared__ Pair tile[kRowsSub][PP + 1];
-  __shared__ double2 xs[2][NR][S];  // x_P (rows), x_Q (columns)
   const int tid = threadIdx.x;
 
-  // load layout: column pair p, rows g0 + G q
+  // load layout: column pair p, rows g0 + G q of each sub-tile
   const int p = tid % PP, g0 = tid / PP;
   const int gc = Q * S + 2 * p;  // first global column of the pair
   const bool c0 = gc < n, c1 = gc + 1 < n;
+  const unsigned off0 = ((unsigned)g0 * (unsigned)ldp + (unsigned)(gc >> 1)) * 16u;
+  const unsigned rowstep = (unsigned)G * (unsigned)ldp * 16u;
+  const unsigned substep = (unsigned)kRowsSub * (unsigned)ldp * 16u;
   Pair ra[LPT], rb[LPT];  // two sub-tiles in flight
-  auto load = [&](Pair(&reg)[LPT], int sub) {
-#pragma unroll
-    for (int q = 0; q < LPT; ++q) {
-      const int gr = P * S + sub * kRowsSub + g0 + G * q;
-      Pair v = zero_pair<T>();
-      if (gr < n && c0) v = __builtin_nontemporal_load(M + (long)gr * ldp + (gc >> 1));
-      reg[q] = c1 ? v : T::first_only(v);  // a column beyond n reads as zero
-    }
-  };
-  load(ra, 0);
-  load(rb, 1);
+
+#define SYMV_LOAD(REG, SUB)                                                                        \
+  _Pragma("unroll") for (int q = 0; q < LPT; ++q) {                                                \
+    const Pair* a = reinterpret_cast<const Pair*>(strip + off0 + (SUB) * substep + q * rowstep);   \
+    if (EDGE) {                                                                                    \
+      const int gr = P * S + (SUB) * kRowsSub + g0 + G * q;                                        \
+      Pair v = zero_pair<T>();                                                                     \
+      if (gr < n && c0) v = __builtin_nontemporal_load(a);                                         \
+      REG[q] = c1 ? v : T::first_only(v);                                                          \
+    } else {                                                                                       \
+      REG[q] = __builtin_nontemporal_load(a);                                                      \
+    }                                                                                              \
+  }
+  SYMV_LOAD(ra, 0)
+  SYMV_LOAD(rb, 1)
   for (int t = tid; t < 2 * NR * S; t += kThreads) {
     const int side = t / (NR * S), r = (t / S) % NR, i = t % S;
     const int g = (side == 0 ? P : Q) * S + i;
-    xs[side][r][i] = (g < n) ? input_entry(ja.in, r, g) : make_double2(0.0, 0.0);
+    xs[side][r][i] = (!EDGE || g < n) ? input_entry(in, r, g) : make_double2(0.0, 0.0);
   }
 
   double cr[2][NR], ci[2][NR];  // transposed sums of the two columns
@@ -219,68 +232,58 @@ __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
   const int rrow = tid / TPR, seg = tid % TPR;  // row-sum layout
   __syncthreads();  // xs ready
 
-  auto consume = [&](Pair(&reg)[LPT], int sub) {
-    if (!diag) {
-#pragma unroll
-      for (int q = 0; q < LPT; ++q) {
-        const int lr = sub * kRowsSub + g0 + G * q;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          double ar, ai;
-          T::template entry<CONJ>(reg[q], e, ar, ai);
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const double2 xv = xs[0][r][lr];
-            cr[e][r] = fma(ar, xv.x, fma(-ai, xv.y, cr[e][r]));
-            ci[e][r] = fma(ar, xv.y, fma(ai, xv.x, ci[e][r]));
-          }
-        }
-      }
-    }
-    __syncthreads();  // the previous row sums are done with the tile
-#pragma unroll
-    for (int q = 0; q < LPT; ++q) tile[g0 + G * q][p] = reg[q];
-    if (sub + 2 < NSUB) load(reg, sub + 2);
-    __syncthreads();
-    double rr[NR], ri[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) rr[r] = ri[r] = 0.0;
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      const int pc = seg + TPR * u;  // neighbouring threads read neighbouring pairs
-      const Pair v = tile[rrow][pc];
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        double ar, ai;
-        T::template entry<CONJ>(v, e, ar, ai);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const double2 xv = xs[1][r][2 * pc + e];
-          rr[r] = fma(ar, xv.x, fma(-ai, xv.y, rr[r]));
-          ri[r] = fma(ar, xv.y, fma(ai, xv.x, ri[r]));
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-#pragma unroll
-      for (int o = TPR / 2; o > 0; o >>= 1) {
-        rr[r] += __shfl_xor(rr[r], o, 64);
-        ri[r] += __shfl_xor(ri[r], o, 64);
-      }
-    }
-    if (seg == 0) {
-      const int i = sub * kRowsSub + rrow;
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        part[(((long)P * nsb + Q) * NR + r) * S + i] = make_double2(rr[r], ri[r]);
-    }
-  };
+#define SYMV_CONSUME(REG, SUB)                                                                     \
+  {                                                                                                \
+    if (!diag) {                                                                                   \
+      _Pragma("unroll") for (int q = 0; q < LPT; ++q) {                                            \
+        const int lr = (SUB) * kRowsSub + g0 + G * q;                                              \
+        _Pragma("unroll") for (int e = 0; e < 2; ++e) {                                            \
+          double ar, ai;                                                                           \
+          T::template entry<CONJ>(REG[q], e, ar, ai);                                              \
+          _Pragma("unroll") for (int r = 0; r < NR; ++r) {                                         \
+            const double2 xv = xs[0][r][lr];                                                       \
+            cr[e][r] = fma(ar, xv.x, fma(-ai, xv.y, cr[e][r]));                                    \
+            ci[e][r] = fma(ar, xv.y, fma(ai, xv.x, ci[e][r]));                                     \
+          }                                                                                        \
+        }                                                                                          \
+      }                                                                                            \
+    }                                                                                              \
+    __syncthreads(); /* the previous row sums are done with the tile */                            \
+    _Pragma("unroll") for (int q = 0; q < LPT; ++q) tile[g0 + G * q][p] = REG[q];                  \
+    if ((SUB) + 2 < NSUB) { SYMV_LOAD(REG, (SUB) + 2) }                                            \
+    __syncthreads();                                                                               \
+    double rr[NR], ri[NR];                                                                         \
+    _Pragma("unroll") for (int r = 0; r < NR; ++r) rr[r] = ri[r] = 0.0;                            \
+    _Pragma("unroll") for (int u = 0; u < PPT; ++u) {                                              \
+      const int pc = seg + TPR * u; /* neighbouring threads read neighbouring pairs */             \
+      const Pair v = tile[rrow][pc];                                                               \
+      _Pragma("unroll") for (int e = 0; e < 2; ++e) {                                              \
+        double ar, ai;                                                                             \
+        T::template entry<CONJ>(v, e, ar, ai);                                                     \
+        _Pragma("unroll") for (int r = 0; r < NR; ++r) {                                           \
+          const double2 xv = xs[1][r][2 * pc + e];                                                 \
+          rr[r] = fma(ar, xv.x, fma(-ai, xv.y, rr[r]));                                            \
+          ri[r] = fma(ar, xv.y, fma(ai, xv.x, ri[r]));                                             \
+        }                                                                                          \
+      }                                                                                            \
+    }                                                                                              \
+    _Pragma("unroll") for (int r = 0; r < NR; ++r) {                                               \
+      rr[r] = sum8(rr[r]);                                                                         \
+      ri[r] = sum8(ri[r]);                                                                         \
+    }                                                                                              \
+    if (seg == 4) {                                                                                \
+      const int i = (SUB) * kRowsSub + rrow;                                                       \
+      _Pragma("unroll") for (int r = 0; r < NR; ++r)                                               \
+        part[(((long)P * nsb + Q) * NR + r) * S + i] = make_double2(rr[r], ri[r]);                 \
+    }                                                                                              \
+  }
 #pragma unroll 1
   for (int sub = 0; sub < NSUB; sub += 2) {
-    consume(ra, sub);
-    consume(rb, sub + 1);
+    SYMV_CONSUME(ra, sub)
+    SYMV_CONSUME(rb, sub + 1)
   }
+#undef SYMV_CONSUME
+#undef SYMV_LOAD
 
   if (!diag) {
     // reduce the transposed sums over the G row groups through LDS
@@ -303,6 +306,30 @@ __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
       part[(((long)Q * nsb + P) * NR + r) * S + c] = make_double2(sr, si);
     }
   }
+}
+
+// Partial buffer layout: part[((K * nsb + L) * NR + r) * S + i], complex128.
+template <class T, int S, int NR, bool CONJ>
+__global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
+  typedef typename T::Pair Pair;
+  const int job = (int)blockIdx.x < args.nblk0 ? 0 : 1;
+  const JobArg& ja = args.j[job];
+  const int n = ja.n, nsb = ja.nsb;
+
+  // block (P, Q), Q >= P, from the linear upper-triangle index
+  int P = 0, rem = (int)blockIdx.x - (job ? args.nblk0 : 0);
+  while (rem >= nsb - P) {
+    rem -= nsb - P;
+    ++P;
+  }
+  const int Q = P + rem;
+  __shared__ Pair tile[kRowsSub][S / 2 + 1];
+  __shared__ double2 xs[2][NR][S];  // x_P (rows), x_Q (columns)
+  const char* strip = static_cast<const char*>(ja.M) + (size_t)P * S * (size_t)ja.ldp * 16;
+  if ((Q + 1) * S <= n)  // then (P + 1) S <= n as well
+    symv_block<T, S, NR, CONJ, false>(strip, n, (int)ja.ldp, P, Q, ja.in, ja.part, nsb, tile, xs);
+  else
+    symv_block<T, S, NR, CONJ, true>(strip, n, (int)ja.ldp, P, Q, ja.in, ja.part, nsb, tile, xs);
 }
 
 // y[r][K S + i] = sum over L (in order) of part[K][L][r][i].  Workgroup
