@@ -20,34 +20,77 @@ namespace {
 // mirrors it, flips the sign and applies the requested shift.
 constexpr int kB = 64;
 
-// Scalar sweep of the 64 pivots of a diagonal tile held in registers (leaves
-// -E).  Thread t keeps the 16-entry strip (rows 16 (t / 64) .. +16, column
-// t % 64).  By symmetry the pivot row equals the pivot column, so per pivot
-// only the column is published to LDS (by the four threads that own it;
-// double-buffered, one barrier per pivot).  Branch-free update: with
-// m_j = -d (j == k) or a_kj d (j != k), row k becomes m_j and every other
-// entry (j == k ? 0 : a_ij) - a_ik m_j.
-__device__ void sweep_tile(double (&r)[16], double (*colk)[kB]) {
+// Sweep of the 64 pivots of a diagonal tile held in registers (leaves -E),
+// four pivots S = {k, .., k+3} at a time: with F = A_SS^-1,
+//   A_SS <- -F,  a_Sj <- F a_Sj,  a_iS <- a_iS F,  a_ij <- a_ij - a_iS F a_Sj,
+// which is what four scalar sweeps give.  Thread t keeps the 16-entry strip
+// (rows 16 (t / 64) .. +16, column t % 64) in registers.  By symmetry the
+// pivot rows equal the pivot columns, so per step only the four columns are
+// published to LDS ([row][4], double-buffered: one barrier per four pivots);
+// every thread then forms -F by a 4 x 4 sweep of A_SS and updates its strip
+// branch-free: with m_j = F a_Sj (j not in S) or column j - k of -F
+// (j in S), rows of S become m_j and every other entry
+// (j in S ? 0 : a_ij) - a_iS m_j.
+__device__ void sweep_tile(double (&r)[16], double (*col4)[kB][4]) {
   const int j = threadIdx.x % kB;
   const int i0 = (threadIdx.x / kB) * 16;
-  for (int k = 0; k < kB; ++k) {
-    const int bsel = k & 1;
-    if (j == k) {
+  for (int k = 0; k < kB; k += 4) {
+    const int bsel = (k >> 2) & 1;
+    if (j >= k && j < k + 4) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) colk[bsel][i0 + u] = r[u];
+      for (int u = 0; u < 16; ++u) col4[bsel][i0 + u][j - k] = r[u];
     }
     __syncthreads();
-    double ck[16];
+    // -F by a symmetric 4 x 4 sweep of A_SS[s][t] = a_{k+s, k+t}
+    double f[4][4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) ck[u] = colk[bsel][i0 + u];
-    const double d = 1.0 / colk[bsel][k];
-    const bool pj = (j == k);
-    const double m = pj ? -d : colk[bsel][j] * d;
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) f[s][t] = col4[bsel][k + s][t];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double d = 1.0 / f[q][q];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (s != q && t != q) f[s][t] = fma(-f[s][q] * d, f[q][t], f[s][t]);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (s != q) {
+          f[s][q] *= d;
+          f[q][s] *= d;
+        }
+      f[q][q] = -d;
+    }
+    const bool inS = (j >= k && j < k + 4);
+    double m[4];
+    {
+      double aSj[4];  // a_{k+t, j} = a_{j, k+t}
+#pragma unroll
+      for (int t = 0; t < 4; ++t) aSj[t] = col4[bsel][j][t];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v = fma(f[s][t], aSj[t], v);  // (-F a_Sj)_s
+        double c = f[s][0];
+#pragma unroll
+        for (int t = 1; t < 4; ++t) c = (j - k == t) ? f[s][t] : c;  // column j - k of -F
+        m[s] = inS ? c : -v;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const double keep = pj ? 0.0 : r[u];
-      const double nv = fma(-ck[u], m, keep);
-      r[u] = (i0 + u == k) ? m : nv;
+      const int i = i0 + u;
+      const double* ai = col4[bsel][i];
+      double acc = inS ? 0.0 : r[u];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = fma(-ai[s], m[s], acc);
+      double rowv = m[0];
+#pragma unroll
+      for (int s = 1; s < 4; ++s) rowv = (i - k == s) ? m[s] : rowv;
+      r[u] = (i >= k && i < k + 4) ? rowv : acc;
     }
   }
 }
@@ -55,14 +98,14 @@ __device__ void sweep_tile(double (&r)[16], double (*colk)[kB]) {
 // Sweep of diagonal tile K in place (the first pivot block only: later
 // diagonal tiles are swept by the update kernel of the previous step).
 __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld, int K) {
-  __shared__ double colk[2][kB];
+  __shared__ double col4[2][kB][4];
   const int j = threadIdx.x % kB;
   const int i0 = (threadIdx.x / kB) * 16;
   const long base = (long)K * kB;
   double r[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) r[u] = A[(base + i0 + u) * ld + base + j];
-  sweep_tile(r, colk);
+  sweep_tile(r, col4);
 #pragma unroll
   for (int u = 0; u < 16; ++u) A[(base + i0 + u) * ld + base + j] = r[u];
 }
@@ -70,67 +113,70 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld
 // Panels of pivot block K: for each J != K, U_J = A_KJ (old; tile (J, K)
 // transposed when J < K) and R_J = E U_J with E = -(tile K, K).  Writes U_J
 // and R_J to the compact panel buffers ([nb][64][64] each) and R_J back into
-// the upper tile.  Tiles are read and written row by row (coalesced); the
-// transposes happen in LDS.  Each thread computes a 4 x 4 tile of R_J.
+// the upper tile.  Workgroup (J, h) forms rows 16 h .. 16 h + 15 of R_J from
+// those rows of E and all of U_J (staged in LDS, transposed there when the
+// stored tile is A_JK); tiles are read and written row by row.
 __global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long ld, int K,
                                                    double* __restrict__ Ubuf, double* __restrict__ Rbuf) {
-  const int J = blockIdx.x;
+  const int J = blockIdx.x, h = blockIdx.y;
   if (J == K) return;
-  __shared__ double E[kB][kB];
-  __shared__ double T[kB][kB + 1];  // the stored tile: A_KJ (J > K) or A_JK (J < K)
+  constexpr int HR = kB / 4;  // rows of R_J per workgroup
+  __shared__ double E[HR][kB];
+  __shared__ double U[kB][kB + 2];  // U[q][c] = (U_J)_qc
   const long pb = (long)K * kB, jb = (long)J * kB;
   const bool up = J > K;
   for (int t = threadIdx.x; t < kB * kB; t += 256) {
     const int i = t / kB, c = t % kB;
-    E[i][c] = -A[(pb + i) * ld + pb + c];
-    T[i][c] = up ? A[(pb + i) * ld + jb + c] : A[(jb + i) * ld + pb + c];
+    if (up)
+      U[i][c] = A[(pb + i) * ld + jb + c];
+    else
+      U[c][i] = A[(jb + i) * ld + pb + c];  // stored tile is A_JK = U_J^T
+  }
+  for (int t = threadIdx.x; t < HR * kB; t += 256) {
+    const int i = t / kB, c = t % kB;
+    E[i][c] = -A[(pb + h * HR + i) * ld + pb + c];
   }
   __syncthreads();
   double* Uo = Ubuf + (long)J * kB * kB;
   double* Ro = Rbuf + (long)J * kB * kB;
-  for (int t = threadIdx.x; t < kB * kB; t += 256) {
-    const int i = t / kB, c = t % kB;
-    Uo[t] = up ? T[i][c] : T[c][i];
+  for (int t = threadIdx.x; t < HR * kB; t += 256) {
+    const int i = h * HR + t / kB, c = t % kB;
+    Uo[i * kB + c] = U[i][c];
   }
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4] = {};
+  // thread: row i = t / 16 of this quarter, columns c = 4 (t % 16) .. + 3
+  const int i = threadIdx.x / 16, c0 = (threadIdx.x % 16) * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
   for (int q = 0; q < kB; ++q) {
-    double lv[4], rv[4];
+    const double e = E[i][q];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) lv[u] = E[ty * 4 + u][q];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) rv[v] = up ? T[q][tx + 16 * v] : T[tx + 16 * v][q];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(lv[u], rv[v], acc[u][v]);
+    for (int v = 0; v < 4; ++v) acc[v] = fma(e, U[q][c0 + v], acc[v]);
   }
-  __syncthreads();  // every thread is done reading T
+  const int gi = h * HR + i;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int v = 0; v < 4; ++v) {
+    Ro[gi * kB + c0 + v] = acc[v];
+    if (up) A[(pb + gi) * ld + jb + c0 + v] = acc[v];
+  }
+  if (!up) {
+    // the stored tile is R_J^T: rows c, columns gi; stage through LDS so
+    // the writes go out row by row
+    __syncthreads();
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = ty * 4 + u, c = tx + 16 * v;
-      Ro[i * kB + c] = acc[u][v];
-      if (up)
-        T[i][c] = acc[u][v];
-      else
-        T[c][i] = acc[u][v];  // the stored tile is R_J^T
+    for (int v = 0; v < 4; ++v) U[c0 + v][i] = acc[v];  // U reused: [c][i], i < HR
+    __syncthreads();
+    for (int t = threadIdx.x; t < kB * HR; t += 256) {
+      const int c = t / HR, ii = t % HR;
+      A[(jb + c) * ld + pb + h * HR + ii] = U[c][ii];
     }
-  __syncthreads();
-  for (int t = threadIdx.x; t < kB * kB; t += 256) {
-    const int i = t / kB, c = t % kB;
-    if (up)
-      A[(pb + i) * ld + jb + c] = T[i][c];
-    else
-      A[(jb + i) * ld + pb + c] = T[i][c];
   }
 }
 
 // Rank-64 update of the upper tiles: A_IJ -= U_I^T R_J for I <= J, I, J != K.
-// One 64 x 64 tile per workgroup, 4 x 4 per thread (loaded first, so the
-// read overlaps the products), K-chunks of 32 rows of U_I and R_J in LDS.
+// One 64 x 64 tile per workgroup; thread (ty, tx) owns rows 4 ty .. + 3 and
+// columns 4 tx .. + 3 (loaded first, so the read overlaps the products).
+// K-chunks of 32 rows of U_I and R_J sit in LDS unpadded, so each thread
+// reads its four U and four R values per step as two 16-byte words each.
 // Workgroup 0 takes the next diagonal tile (K+1, K+1) and, once it is
 // updated, sweeps it: the serial sweep of the next pivot block runs while
 // the rest of the update streams.
@@ -153,32 +199,37 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
   const int J = I + rem;
   if (I == K || J == K) return;
   constexpr int KC = 32;
-  __shared__ double lds[2 * KC * (kB + 1)];
-  double(*uu)[kB + 1] = reinterpret_cast<double(*)[kB + 1]>(lds);
-  double(*rr)[kB + 1] = reinterpret_cast<double(*)[kB + 1]>(lds + KC * (kB + 1));
+  __shared__ __align__(16) double lds[2 * KC * kB];
+  double(*uu)[kB] = reinterpret_cast<double(*)[kB]>(lds);
+  double(*rr)[kB] = reinterpret_cast<double(*)[kB]>(lds + KC * kB);
   const long ib = (long)I * kB, jb = (long)J * kB;
   const double* Ui = Ubuf + (long)I * kB * kB;
   const double* Rj = Rbuf + (long)J * kB * kB;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double acc[4][4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = A[(ib + ty * 4 + u) * ld + jb + tx + 16 * v];
+  for (int u = 0; u < 4; ++u) {
+    const double2* src = reinterpret_cast<const double2*>(A + (ib + ty * 4 + u) * ld + jb + tx * 4);
+    const double2 a0 = src[0], a1 = src[1];
+    acc[u][0] = a0.x;
+    acc[u][1] = a0.y;
+    acc[u][2] = a1.x;
+    acc[u][3] = a1.y;
+  }
   for (int k0 = 0; k0 < kB; k0 += KC) {
-    for (int t = threadIdx.x; t < KC * kB; t += 256) {
-      const int q = t / kB, c = t % kB;
-      uu[q][c] = Ui[(k0 + q) * kB + c];
-      rr[q][c] = Rj[(k0 + q) * kB + c];
+    for (int t = threadIdx.x; t < KC * kB / 2; t += 256) {
+      reinterpret_cast<double2*>(lds)[t] = reinterpret_cast<const double2*>(Ui + k0 * kB)[t];
+      reinterpret_cast<double2*>(lds + KC * kB)[t] = reinterpret_cast<const double2*>(Rj + k0 * kB)[t];
     }
     __syncthreads();
 #pragma unroll 4
     for (int q = 0; q < KC; ++q) {
-      double av[4], rv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = uu[q][ty * 4 + u];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) rv[u] = rr[q][tx + 16 * u];
+      const double2 a01 = *reinterpret_cast<const double2*>(&uu[q][ty * 4]);
+      const double2 a23 = *reinterpret_cast<const double2*>(&uu[q][ty * 4 + 2]);
+      const double2 r01 = *reinterpret_cast<const double2*>(&rr[q][tx * 4]);
+      const double2 r23 = *reinterpret_cast<const double2*>(&rr[q][tx * 4 + 2]);
+      const double av[4] = {a01.x, a01.y, a23.x, a23.y};
+      const double rv[4] = {r01.x, r01.y, r23.x, r23.y};
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -187,28 +238,30 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
     __syncthreads();
   }
   if (I == nx && J == nx) {
-    // hand the tile to the sweep layout through LDS (uu and rr are free)
+    // hand the tile to the sweep layout through LDS (free after the loop)
     double* t = lds;  // [64][64]
-    static_assert(2 * KC * (kB + 1) >= kB * kB, "LDS tile");
+    static_assert(2 * KC * kB >= kB * kB, "LDS tile");
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) t[(ty * 4 + u) * kB + tx + 16 * v] = acc[u][v];
+      for (int v = 0; v < 4; ++v) t[(ty * 4 + u) * kB + tx * 4 + v] = acc[u][v];
     __syncthreads();
     const int j = threadIdx.x % kB, i0 = (threadIdx.x / kB) * 16;
     double r[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) r[u] = t[(i0 + u) * kB + j];
-    __shared__ double colk[2][kB];
-    sweep_tile(r, colk);
+    __shared__ double col4[2][kB][4];
+    sweep_tile(r, col4);
 #pragma unroll
     for (int u = 0; u < 16; ++u) A[(ib + i0 + u) * ld + jb + j] = r[u];
     return;
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) A[(ib + ty * 4 + u) * ld + jb + tx + 16 * v] = acc[u][v];
+  for (int u = 0; u < 4; ++u) {
+    double2* dst = reinterpret_cast<double2*>(A + (ib + ty * 4 + u) * ld + jb + tx * 4);
+    dst[0] = make_double2(acc[u][0], acc[u][1]);
+    dst[1] = make_double2(acc[u][2], acc[u][3]);
+  }
 }
 
 // Final pass over the upper triangle (i <= j): the swept matrix holds -A^-1
@@ -260,7 +313,7 @@ rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, hip
   hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, A, (long)n, 0);
   for (int K = 0; K < nb; ++K) {
     if (nb > 1) {
-      hipLaunchKernelGGL(k_gj_panels, dim3(nb), dim3(256), 0, s, A, (long)n, K, ubuf.as<double>(),
+      hipLaunchKernelGGL(k_gj_panels, dim3(nb, 4), dim3(256), 0, s, A, (long)n, K, ubuf.as<double>(),
                          rbuf.as<double>());
       hipLaunchKernelGGL(k_gj_update, dim3(ntiles), dim3(256), 0, s, A, (long)n, nb, K, ubuf.as<double>(),
                          rbuf.as<double>());
