@@ -12,14 +12,18 @@
 //
 // Storage: a complex matrix is four bf16 planes (Re hi, Re lo, Im hi, Im lo),
 // 8 bytes per entry -- the same as complex64; a real matrix two planes.
-// Planes are row-major [rows_pad][kpad] with rows_pad a multiple of 128 and
-// kpad a multiple of 64, zero-padded.  X is split per call into two planes
+// Planes hold rows_pad x kpad entries (rows_pad a multiple of 128, kpad of
+// 64, zero-padded) fragment-major: 32 x 32 tiles in which each wave's MFMA
+// operand for one K-step is 1 KB contiguous, so the matrix stream is read
+// in whole 1 KB wave loads.  X is split per call into two planes
 // [ncp][kpad] (column 2r + 0/1 = Re/Im of right-hand side r; ncp = 2 nrhs
 // rounded up to 32, at most 128).
 //
 // Kernel: a workgroup (4 waves) owns 128 rows and all ncp columns over one
-// slice of K (split-K for occupancy).  Each wave computes 32 rows with
-// v_mfma_f32_32x32x16_bf16; the X tile of a 64-wide K chunk is staged in LDS.
+// slice of K (split-K to about one workgroup per compute unit).  Each wave
+// computes 32 rows with v_mfma_f32_32x32x16_bf16; the X tile of a 64-wide K
+// chunk is staged in LDS (two buffers), and the next chunk's matrix rows and
+// X are loaded while the current one is multiplied.
 // Within a chunk, lane l of a wave covers k = 32 (l / 32) + 8 s + e for
 // sub-step s and element e on both operands (the contraction order is free),
 // so each lane reads 64 contiguous bytes of its matrix row.  Partial sums go
@@ -37,7 +41,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16;
 
 constexpr int kRowsWG = 128;
-constexpr int kKc = 64;          // K chunk staged per LDS pass
+constexpr int kKpad = 64;        // K padding of the planes
+constexpr int kKc = 32;          // K chunk per pipeline stage
+constexpr int kSub = kKc / 16;   // MFMA K-steps per chunk
 constexpr int kLdsK = kKc + 8;   // padded column stride in LDS (bf16 units)
 
 __device__ inline u16 bf16_bits(float x) {
@@ -46,7 +52,16 @@ __device__ inline u16 bf16_bits(float x) {
 }
 __device__ inline float bf16_val(u16 b) { return (float)__builtin_bit_cast(__bf16, b); }
 
-// complex64 [n][ld] -> planes [4][rows_pad][kpad]
+// Offset of matrix entry (i, k) in a plane stored fragment-major: 32-row x
+// 32-k tiles, each [s][lane][8] so that one wave's MFMA operand for one
+// K-step is 1 KB contiguous (lane l: row l % 32, k = 16 (l / 32) + 8 s + e).
+__device__ inline long frag_offset(long i, long k, long nkc) {
+  const long rb = i >> 5, li = i & 31, kc = k >> 5, kk = k & 31;
+  const long lane = li + 32 * (kk >> 4), sub = (kk >> 3) & 1, e = kk & 7;
+  return (((rb * nkc + kc) * 2 + sub) * 64 + lane) * 8 + e;
+}
+
+// complex64 [n][ld] -> planes [4][rows_pad x kpad], fragment-major
 __global__ void k_split_c64(const float2* __restrict__ M, long n, long ncol, long ld, u16* __restrict__ P,
                             long rows_pad, long kpad) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -59,23 +74,25 @@ __global__ void k_split_c64(const float2* __restrict__ M, long n, long ncol, lon
     im = v.y;
   }
   const long plane = rows_pad * kpad;
+  const long o = frag_offset(i, k, kpad / 32);
   const u16 rh = bf16_bits(re), ih = bf16_bits(im);
-  P[t] = rh;
-  P[plane + t] = bf16_bits(re - bf16_val(rh));
-  P[2 * plane + t] = ih;
-  P[3 * plane + t] = bf16_bits(im - bf16_val(ih));
+  P[o] = rh;
+  P[plane + o] = bf16_bits(re - bf16_val(rh));
+  P[2 * plane + o] = ih;
+  P[3 * plane + o] = bf16_bits(im - bf16_val(ih));
 }
 
-// real FP64 [n][ld] -> planes [2][rows_pad][kpad]
+// real FP64 [n][ld] -> planes [2][rows_pad x kpad], fragment-major
 __global__ void k_split_f64(const double* __restrict__ M, long n, long ld, u16* __restrict__ P, long rows_pad,
                             long kpad) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= rows_pad * kpad) return;
   const long i = t / kpad, k = t % kpad;
   const float v = (i < n && k < n) ? (float)M[i * ld + k] : 0.f;
+  const long o = frag_offset(i, k, kpad / 32);
   const u16 h = bf16_bits(v);
-  P[t] = h;
-  P[rows_pad * kpad + t] = bf16_bits(v - bf16_val(h));
+  P[o] = h;
+  P[rows_pad * kpad + o] = bf16_bits(v - bf16_val(h));
 }
 
 // X complex128 [nrhs][K] -> planes [2][ncp][kpad], column 2r + part
@@ -99,14 +116,19 @@ template <int NCT, bool CPLX>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(const u16* __restrict__ A, long rows_pad, long kpad,
                                                      const u16* __restrict__ Xs, int ncp, long kslice,
                                                      float* __restrict__ part) {
-  constexpr int NPL = CPLX ? 2 : 1;  // matrix planes pairs (Re, Im)
-  __shared__ u16 bs[2][NCT * 32][kLdsK];
+  constexpr int NPL = CPLX ? 2 : 1;             // matrix planes pairs (Re, Im)
+  constexpr int XW = 2 * NCT * 32 * (kKc / 8);  // 16-byte words of one staged X chunk (two planes)
+  constexpr int XPT = XW / 256;                 // ... per thread
+  static_assert(XW % 256 == 0 && kKc == 32, "chunk shape");
+  __shared__ u16 bs[2][2][NCT * 32][kLdsK];  // [buffer][plane][column][k]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long row0 = (long)blockIdx.x * kRowsWG + wave * 32;
   const long k_begin = (long)blockIdx.y * kslice;
   const long k_end = min(kpad, k_begin + kslice);
+  const int nch = (int)((k_end - k_begin) / kKc);
   const long plane = rows_pad * kpad;
   const long xplane = (long)ncp * kpad;
+  const long nkc = kpad / kKc;
 
   f32x16 acc[NPL][NCT];
 #pragma unroll
@@ -116,54 +138,82 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const u16* __restrict__ A, 
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[p][c][q] = 0.f;
 
-  const long my_row = row0 + (lane & 31);
-  const int khalf = (lane >> 5) * 32;
-  for (long k0 = k_begin; k0 < k_end; k0 += kKc) {
-    // stage X chunk: NCT*32 columns x 64 k, two planes; 16 B per store
-    __syncthreads();
-    for (int e = threadIdx.x; e < 2 * NCT * 32 * (kKc / 8); e += 256) {
-      const int pl = e / (NCT * 32 * (kKc / 8));
-      const int rem = e % (NCT * 32 * (kKc / 8));
-      const int col = rem / (kKc / 8), kk = (rem % (kKc / 8)) * 8;
-      const bf16x8 v = *reinterpret_cast<const bf16x8*>(Xs + pl * xplane + (long)col * kpad + k0 + kk);
-      *reinterpret_cast<bf16x8*>(&bs[pl][col][kk]) = v;
-    }
-    __syncthreads();
-    // this lane's 32 contiguous k of its row, per matrix plane
-    bf16x8 a[2 * NPL][4];
-#pragma unroll
-    for (int p = 0; p < 2 * NPL; ++p) {
-      const bf16x8* src = reinterpret_cast<const bf16x8*>(A + p * plane + my_row * kpad + k0 + khalf);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) a[p][s] = __builtin_nontemporal_load(src + s);
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      bf16x8 bh[NCT], bl[NCT];
-#pragma unroll
-      for (int c = 0; c < NCT; ++c) {
-        const int col = c * 32 + (lane & 31);
-        bh[c] = *reinterpret_cast<const bf16x8*>(&bs[0][col][khalf + 8 * s]);
-        bl[c] = *reinterpret_cast<const bf16x8*>(&bs[1][col][khalf + 8 * s]);
-      }
-      // three passes over independent accumulators (hi.hi, hi.lo, lo.hi)
-#pragma unroll
-      for (int p = 0; p < NPL; ++p)
-#pragma unroll
-        for (int c = 0; c < NCT; ++c)
-          acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2 * p][s], bh[c], acc[p][c], 0, 0, 0);
-#pragma unroll
-      for (int p = 0; p < NPL; ++p)
-#pragma unroll
-        for (int c = 0; c < NCT; ++c)
-          acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2 * p][s], bl[c], acc[p][c], 0, 0, 0);
-#pragma unroll
-      for (int p = 0; p < NPL; ++p)
-#pragma unroll
-        for (int c = 0; c < NCT; ++c)
-          acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2 * p + 1][s], bh[c], acc[p][c], 0, 0, 0);
-    }
+  // fragment-major planes: this wave's operand for chunk kc, step s is the
+  // 1 KB at ((rb nkc + kc) 2 + s) 512 elements; this lane's 16 bytes in it
+  const u16* abase = A + ((row0 >> 5) * nkc + k_begin / kKc) * 2 * 512 + lane * 8;
+  const int khalf = (lane >> 5) * (kKc / 2);
+
+#define GEMM_LOAD_A(SET, CH)                                                                     \
+  _Pragma("unroll") for (int p = 0; p < 2 * NPL; ++p)                                            \
+    _Pragma("unroll") for (int s = 0; s < kSub; ++s)                                             \
+      SET[p][s] = __builtin_nontemporal_load(                                                    \
+          reinterpret_cast<const bf16x8*>(abase + p * plane + ((long)(CH) * 2 + s) * 512));
+#define GEMM_LOAD_X(CH)                                                                          \
+  _Pragma("unroll") for (int w = 0; w < XPT; ++w) {                                              \
+    const int e = threadIdx.x + 256 * w;                                                         \
+    const int pl = e / (NCT * 32 * (kKc / 8));                                                   \
+    const int rem = e % (NCT * 32 * (kKc / 8));                                                  \
+    const int col = rem / (kKc / 8), kk = (rem % (kKc / 8)) * 8;                                 \
+    xr[w] = *reinterpret_cast<const bf16x8*>(Xs + pl * xplane + (long)col * kpad + k_begin +     \
+                                             (long)(CH) * kKc + kk);                             \
   }
+#define GEMM_STORE_X(BUF)                                                                        \
+  _Pragma("unroll") for (int w = 0; w < XPT; ++w) {                                              \
+    const int e = threadIdx.x + 256 * w;                                                         \
+    const int pl = e / (NCT * 32 * (kKc / 8));                                                   \
+    const int rem = e % (NCT * 32 * (kKc / 8));                                                  \
+    const int col = rem / (kKc / 8), kk = (rem % (kKc / 8)) * 8;                                 \
+    *reinterpret_cast<bf16x8*>(&bs[BUF][pl][col][kk]) = xr[w];                                   \
+  }
+#define GEMM_COMPUTE(SET, BUF)                                                                   \
+  _Pragma("unroll") for (int s = 0; s < kSub; ++s) {                                             \
+    bf16x8 bh[NCT], bl[NCT];                                                                     \
+    _Pragma("unroll") for (int c = 0; c < NCT; ++c) {                                            \
+      const int col = c * 32 + (lane & 31);                                                      \
+      bh[c] = *reinterpret_cast<const bf16x8*>(&bs[BUF][0][col][khalf + 8 * s]);                 \
+      bl[c] = *reinterpret_cast<const bf16x8*>(&bs[BUF][1][col][khalf + 8 * s]);                 \
+    }                                                                                            \
+    _Pragma("unroll") for (int p = 0; p < NPL; ++p)                                              \
+      _Pragma("unroll") for (int c = 0; c < NCT; ++c) {                                          \
+        acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(SET[2 * p][s], bh[c], acc[p][c], 0, 0, 0);     \
+        acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(SET[2 * p][s], bl[c], acc[p][c], 0, 0, 0);     \
+        acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(SET[2 * p + 1][s], bh[c], acc[p][c], 0, 0, 0); \
+      }                                                                                          \
+  }
+
+  // Pipeline over 32-wide K chunks: matrix operands three chunks deep in
+  // registers (sets a0, a1, a2 in rotation), X one chunk ahead in registers
+  // and double-buffered in LDS; one barrier per chunk.  Within an
+  // iteration X is loaded before the matrix rows, so waiting for X never
+  // waits for the newest matrix loads.
+  bf16x8 a0[2 * NPL][kSub], a1[2 * NPL][kSub], a2[2 * NPL][kSub];
+  bf16x8 xr[XPT];
+  GEMM_LOAD_X(0)
+  GEMM_LOAD_A(a0, 0)
+  if (nch > 1) { GEMM_LOAD_A(a1, 1) }
+  if (nch > 2) { GEMM_LOAD_A(a2, 2) }
+  GEMM_STORE_X(0)
+  if (nch > 1) { GEMM_LOAD_X(1) }
+  __syncthreads();
+#define GEMM_STEP(SET, CH)                                                                       \
+  {                                                                                              \
+    const int buf = (CH) & 1;                                                                    \
+    GEMM_COMPUTE(SET, buf)                                                                       \
+    if ((CH) + 1 < nch) { GEMM_STORE_X(buf ^ 1) }                                                \
+    if ((CH) + 2 < nch) { GEMM_LOAD_X((CH) + 2) }                                                \
+    if ((CH) + 3 < nch) { GEMM_LOAD_A(SET, (CH) + 3) }                                           \
+    __syncthreads();                                                                             \
+  }
+  for (int ch = 0; ch < nch; ch += 3) {
+    GEMM_STEP(a0, ch)
+    if (ch + 1 < nch) GEMM_STEP(a1, ch + 1)
+    if (ch + 2 < nch) GEMM_STEP(a2, ch + 2)
+  }
+#undef GEMM_STEP
+#undef GEMM_COMPUTE
+#undef GEMM_STORE_X
+#undef GEMM_LOAD_X
+#undef GEMM_LOAD_A
   // partial[slice][p][row][col]
 #pragma unroll
   for (int p = 0; p < NPL; ++p)
@@ -206,7 +256,7 @@ rfcmp_status SplitMatrix::from_c64(const float2* M, int64_t n_, int64_t ld, hipS
   n = n_;
   cplx = true;
   rows_pad = (int64_t)round_up(n, kRowsWG);
-  kpad = (int64_t)round_up(n, kKc);
+  kpad = (int64_t)round_up(n, kKpad);
   RF_TRY(planes.alloc(sizeof(u16) * 4 * rows_pad * kpad));
   const long tot = rows_pad * kpad;
   hipLaunchKernelGGL(k_split_c64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, (long)n, (long)n,
@@ -219,7 +269,7 @@ rfcmp_status SplitMatrix::from_f64(const double* M, int64_t n_, int64_t ld, hipS
   n = n_;
   cplx = false;
   rows_pad = (int64_t)round_up(n, kRowsWG);
-  kpad = (int64_t)round_up(n, kKc);
+  kpad = (int64_t)round_up(n, kKpad);
   RF_TRY(planes.alloc(sizeof(u16) * 2 * rows_pad * kpad));
   const long tot = rows_pad * kpad;
   hipLaunchKernelGGL(k_split_f64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, (long)n, (long)ld,
@@ -229,7 +279,7 @@ rfcmp_status SplitMatrix::from_f64(const double* M, int64_t n_, int64_t ld, hipS
 }
 
 size_t gemm_scratch_bytes(int64_t n, int nrhs) {
-  const int64_t rows_pad = (int64_t)round_up(n, kRowsWG), kpad = (int64_t)round_up(n, kKc);
+  const int64_t rows_pad = (int64_t)round_up(n, kRowsWG), kpad = (int64_t)round_up(n, kKpad);
   const int nr = std::min(nrhs, 64);
   const int ncp = (int)round_up(2 * nr, 32);
   return round_up(sizeof(u16) * 2 * ncp * kpad, 256) + sizeof(float) * 16 * 2 * rows_pad * ncp + 1024;
@@ -243,9 +293,11 @@ rfcmp_status gemm_bf16x3(const SplitMatrix& M, bool conj_m, const double2* X, do
     const int ncp = (int)round_up(2 * nr, 32);
     const int nct = ncp / 32;
     const long nrb = (long)(M.rows_pad / kRowsWG);
-    // split K so that the grid holds about 512 workgroups
-    long nslice = std::max(1L, std::min(16L, (512 + nrb - 1) / nrb));
-    long kslice = (long)round_up((M.kpad + nslice - 1) / nslice, kKc);
+    // split K so that the grid holds about one workgroup per compute unit
+    // (each holds one workgroup: the accumulators and two register sets of
+    // matrix rows fill the register file)
+    long nslice = std::max(1L, std::min(16L, (256 + nrb / 2) / nrb));
+    long kslice = (long)round_up((M.kpad + nslice - 1) / nslice, kKpad);
     nslice = (M.kpad + kslice - 1) / kslice;
     const int npl = M.cplx ? 2 : 1;
     const size_t xs_bytes = round_up(sizeof(u16) * 2 * ncp * M.kpad, 256);
