@@ -173,25 +173,31 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const u16* __restrict__ A, 
       bh[c] = *reinterpret_cast<const bf16x8*>(&bs[BUF][0][col][khalf + 8 * s]);                 \
       bl[c] = *reinterpret_cast<const bf16x8*>(&bs[BUF][1][col][khalf + 8 * s]);                 \
     }                                                                                            \
+    /* three passes (hi.hi, hi.lo, lo.hi), each over all accumulators, so    \
+       consecutive MFMAs never wait on one another's accumulator */          \
     _Pragma("unroll") for (int p = 0; p < NPL; ++p)                                              \
-      _Pragma("unroll") for (int c = 0; c < NCT; ++c) {                                          \
+      _Pragma("unroll") for (int c = 0; c < NCT; ++c)                                            \
         acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(SET[2 * p][s], bh[c], acc[p][c], 0, 0, 0);     \
+    _Pragma("unroll") for (int p = 0; p < NPL; ++p)                                              \
+      _Pragma("unroll") for (int c = 0; c < NCT; ++c)                                            \
         acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(SET[2 * p][s], bl[c], acc[p][c], 0, 0, 0);     \
+    _Pragma("unroll") for (int p = 0; p < NPL; ++p)                                              \
+      _Pragma("unroll") for (int c = 0; c < NCT; ++c)                                            \
         acc[p][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(SET[2 * p + 1][s], bh[c], acc[p][c], 0, 0, 0); \
-      }                                                                                          \
   }
 
-  // Pipeline over 32-wide K chunks: matrix operands three chunks deep in
-  // registers (sets a0, a1, a2 in rotation), X one chunk ahead in registers
+  // Pipeline over 32-wide K chunks: matrix operands four chunks deep in
+  // registers (sets a0 .. a3 in rotation), X one chunk ahead in registers
   // and double-buffered in LDS; one barrier per chunk.  Within an
   // iteration X is loaded before the matrix rows, so waiting for X never
   // waits for the newest matrix loads.
-  bf16x8 a0[2 * NPL][kSub], a1[2 * NPL][kSub], a2[2 * NPL][kSub];
+  bf16x8 a0[2 * NPL][kSub], a1[2 * NPL][kSub], a2[2 * NPL][kSub], a3[2 * NPL][kSub];
   bf16x8 xr[XPT];
   GEMM_LOAD_X(0)
   GEMM_LOAD_A(a0, 0)
   if (nch > 1) { GEMM_LOAD_A(a1, 1) }
   if (nch > 2) { GEMM_LOAD_A(a2, 2) }
+  if (nch > 3) { GEMM_LOAD_A(a3, 3) }
   GEMM_STORE_X(0)
   if (nch > 1) { GEMM_LOAD_X(1) }
   __syncthreads();
@@ -201,13 +207,14 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const u16* __restrict__ A, 
     GEMM_COMPUTE(SET, buf)                                                                       \
     if ((CH) + 1 < nch) { GEMM_STORE_X(buf ^ 1) }                                                \
     if ((CH) + 2 < nch) { GEMM_LOAD_X((CH) + 2) }                                                \
-    if ((CH) + 3 < nch) { GEMM_LOAD_A(SET, (CH) + 3) }                                           \
+    if ((CH) + 4 < nch) { GEMM_LOAD_A(SET, (CH) + 4) }                                           \
     __syncthreads();                                                                             \
   }
-  for (int ch = 0; ch < nch; ch += 3) {
+  for (int ch = 0; ch < nch; ch += 4) {
     GEMM_STEP(a0, ch)
     if (ch + 1 < nch) GEMM_STEP(a1, ch + 1)
     if (ch + 2 < nch) GEMM_STEP(a2, ch + 2)
+    if (ch + 3 < nch) GEMM_STEP(a3, ch + 3)
   }
 #undef GEMM_STEP
 #undef GEMM_COMPUTE
