@@ -333,35 +333,44 @@ __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
 }
 
 // y[r][K S + i] = sum over L (in order) of part[K][L][r][i].  Workgroup
-// (K, r): four threads per row each add a quarter of the slots (unrolled, so
-// the loads overlap), then the quarters are added in order through LDS.
-// Blocks [0, nsb0) of the grid reduce job 0, the rest job 1.
+// (K, r): eight threads per row each add an eighth of the slots (all loads
+// issued before the adds, so they overlap), then the eighths are added in
+// order through LDS.  Blocks [0, nsb0) of the grid reduce job 0, the rest
+// job 1.
+constexpr int kRedParts = 8;
 template <int S, int NR>
-__global__ __launch_bounds__(4 * S) void k_symv_reduce(const JobsArg args) {
-  __shared__ double2 q4[4][S];
+__global__ __launch_bounds__(kRedParts * S) void k_symv_reduce(const JobsArg args) {
+  __shared__ double2 q8[kRedParts][S];
   const int job = (int)blockIdx.x < args.nsb0 ? 0 : 1;
   const JobArg& ja = args.j[job];
   const int n = ja.n, nsb = ja.nsb;
   const int K = (int)blockIdx.x - (job ? args.nsb0 : 0), r = blockIdx.y;
   const int i = threadIdx.x % S, qt = threadIdx.x / S;
-  const int per = (nsb + 3) / 4;
-  const int L0 = qt * per, L1 = min(nsb, L0 + per);
+  const int per = (nsb + kRedParts - 1) / kRedParts;
+  const int L0 = qt * per;
   const double2* src = ja.part + (((long)K * nsb) * NR + r) * S + i;
   double sr = 0.0, si = 0.0;
-#pragma unroll 4
-  for (int L = L0; L < L1; ++L) {
-    const double2 v = src[(long)L * NR * S];
-    sr += v.x;
-    si += v.y;
+  for (int b0 = 0; b0 < per; b0 += 8) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int L = L0 + b0 + u;
+      v[u] = (b0 + u < per && L < nsb) ? src[(long)L * NR * S] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sr += v[u].x;
+      si += v[u].y;
+    }
   }
-  q4[qt][i] = make_double2(sr, si);
+  q8[qt][i] = make_double2(sr, si);
   __syncthreads();
   const int row = K * S + i;
   if (qt == 0 && row < n) {
-    double2 t = q4[0][i];
-    for (int u = 1; u < 4; ++u) {
-      t.x += q4[u][i].x;
-      t.y += q4[u][i].y;
+    double2 t = q8[0][i];
+    for (int u = 1; u < kRedParts; ++u) {
+      t.x += q8[u][i].x;
+      t.y += q8[u][i].y;
     }
     ja.y[(long)r * n + row] = t;
   }
@@ -378,7 +387,7 @@ void launch(const JobsArg& a, int nblk, int nsbsum, hipStream_t s, const char* t
     hipLaunchKernelGGL((k_symv<T, kS, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s, a);
   }
   ProfScope prof("symv_reduce", s);
-  hipLaunchKernelGGL((k_symv_reduce<kS, NR>), dim3((unsigned)nsbsum, NR), dim3(4 * kS), 0, s, a);
+  hipLaunchKernelGGL((k_symv_reduce<kS, NR>), dim3((unsigned)nsbsum, NR), dim3(kRedParts * kS), 0, s, a);
 }
 
 // Advance every source pointer of an input by r0 right-hand sides.
