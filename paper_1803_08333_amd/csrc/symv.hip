@@ -42,7 +42,9 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef double vd2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;
-constexpr int kRowsSub = 32;   // rows per sub-tile
+// rows per sub-tile for block size S: the sub-tile is 4 KB of pairs per 256 threads
+template <int S>
+constexpr int rows_sub() { return S == 128 ? 32 : 16; }
 constexpr int kMaxNR = 4;      // right-hand sides per pass
 
 // Entry e (0, 1) of a 16-byte column pair, widened to FP64 (re, im).
@@ -168,11 +170,15 @@ __device__ inline double dpp_move(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-// Sum over each aligned group of 8 lanes; lanes 4..7 of a group hold it.
-__device__ inline double sum8(double v) {
+// Sum over each aligned group of TPR (8 or 16) lanes; lanes TPR - 4 .. TPR - 1
+// of a group hold it.
+template <int TPR>
+__device__ inline double sum_lanes(double v) {
+  static_assert(TPR == 8 || TPR == 16, "group size");
   v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
   v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
-  v += dpp_move<0x114>(v);  // row_shr:4: lanes 4..7 add lanes 0..3
+  v += dpp_move<0x114>(v);  // row_shr:4: lanes 4..7 (of 8) add lanes 0..3
+  if (TPR == 16) v += dpp_move<0x118>(v);  // row_shr:8: lanes 12..15 add lanes 4..7
   return v;
 }
 
@@ -185,13 +191,14 @@ __device__ void symv_block(const char* __restrict__ strip, int n, int ldp, int P
                            const SymvInput& in, double2* __restrict__ part, int nsb,
                            typename T::Pair (*tile)[S / 2 + 1], double2 (*xs)[NR][S]) {
   typedef typename T::Pair Pair;
+  constexpr int kRowsSub = rows_sub<S>();
   constexpr int PP = S / 2;                       // column pairs per row
   constexpr int G = kThreads / PP;                // row groups in the load layout
   constexpr int LPT = kRowsSub / G;               // loads per thread per sub-tile
   constexpr int NSUB = S / kRowsSub;              // sub-tiles per block
   constexpr int TPR = kThreads / kRowsSub;        // threads per row in the row sums
   constexpr int PPT = PP / TPR;                   // pairs per thread in the row sums
-  static_assert(kRowsSub % G == 0 && PP % TPR == 0 && NSUB % 2 == 0 && TPR == 8, "block shape");
+  static_assert(kRowsSub % G == 0 && PP % TPR == 0 && NSUB % 2 == 0, "block shape");
   const bool diag = (P == Q);
   const int tid = threadIdx.x;
 
@@ -268,10 +275,10 @@ __device__ void symv_block(const char* __restrict__ strip, int n, int ldp, int P
       }                                                                                            \
     }                                                                                              \
     _Pragma("unroll") for (int r = 0; r < NR; ++r) {                                               \
-      rr[r] = sum8(rr[r]);                                                                         \
-      ri[r] = sum8(ri[r]);                                                                         \
+      rr[r] = sum_lanes<TPR>(rr[r]);                                                               \
+      ri[r] = sum_lanes<TPR>(ri[r]);                                                               \
     }                                                                                              \
-    if (seg == 4) {                                                                                \
+    if (seg == TPR - 4) {                                                                          \
       const int i = (SUB) * kRowsSub + rrow;                                                       \
       _Pragma("unroll") for (int r = 0; r < NR; ++r)                                               \
         part[(((long)P * nsb + Q) * NR + r) * S + i] = make_double2(rr[r], ri[r]);                 \
@@ -323,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
     ++P;
   }
   const int Q = P + rem;
-  __shared__ Pair tile[kRowsSub][S / 2 + 1];
+  __shared__ Pair tile[rows_sub<S>()][S / 2 + 1];
   __shared__ double2 xs[2][NR][S];  // x_P (rows), x_Q (columns)
   const char* strip = static_cast<const char*>(ja.M) + (size_t)P * S * (size_t)ja.ldp * 16;
   if ((Q + 1) * S <= n)  // then (P + 1) S <= n as well
@@ -337,9 +344,11 @@ __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
 // issued before the adds, so they overlap), then the eighths are added in
 // order through LDS.  Blocks [0, nsb0) of the grid reduce job 0, the rest
 // job 1.
-constexpr int kRedParts = 8;
+template <int S>
+constexpr int red_parts() { return 1024 / S; }
 template <int S, int NR>
-__global__ __launch_bounds__(kRedParts * S) void k_symv_reduce(const JobsArg args) {
+__global__ __launch_bounds__(1024) void k_symv_reduce(const JobsArg args) {
+  constexpr int kRedParts = red_parts<S>();
   __shared__ double2 q8[kRedParts][S];
   const int job = (int)blockIdx.x < args.nsb0 ? 0 : 1;
   const JobArg& ja = args.j[job];
@@ -376,19 +385,23 @@ __global__ __launch_bounds__(kRedParts * S) void k_symv_reduce(const JobsArg arg
   }
 }
 
-constexpr int kS = 128;
+constexpr int kSmax = 256, kSmin = 128;
 
 // The product kernel is timed under `tag` (one right-hand side) or
 // "<tag>_nr<k>" (k right-hand sides), the slot sums under "symv_reduce".
-template <class T, int NR, bool CONJ>
+template <class T, int S, int NR, bool CONJ>
 void launch(const JobsArg& a, int nblk, int nsbsum, hipStream_t s, const char* tag) {
   {
     ProfScope prof(NR == 1 ? tag : profile_tag_suffix(tag, NR), s);
-    hipLaunchKernelGGL((k_symv<T, kS, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((k_symv<T, S, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s, a);
   }
   ProfScope prof("symv_reduce", s);
-  hipLaunchKernelGGL((k_symv_reduce<kS, NR>), dim3((unsigned)nsbsum, NR), dim3(kRedParts * kS), 0, s, a);
+  hipLaunchKernelGGL((k_symv_reduce<S, NR>), dim3((unsigned)nsbsum, NR), dim3(1024), 0, s, a);
 }
+
+// Block size: 256 x 256 blocks (longer streams per workgroup, fewer slots)
+// once they still give the grid a few hundred workgroups, else 128 x 128.
+constexpr int kMinBlocks256 = 400;
 
 // Advance every source pointer of an input by r0 right-hand sides.
 SymvInput shift_input(SymvInput in, int r0) {
@@ -417,6 +430,12 @@ rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, s
     set_error("symv: needs %zu bytes of scratch, %zu given", need, scratch_bytes);
     return RFCMP_E_ARG;
   }
+  long blocks_big = 0;
+  for (int q = 0; q < njobs; ++q) {
+    const long nb = (jobs[q].n + kSmax - 1) / kSmax;
+    blocks_big += nb * (nb + 1) / 2;
+  }
+  const int S = blocks_big >= kMinBlocks256 ? kSmax : kSmin;
   for (int r0 = 0; r0 < nrhs; r0 += kMaxNR) {
     const int nr = std::min(kMaxNR, nrhs - r0);
     JobsArg a{};
@@ -428,7 +447,7 @@ rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, s
       ja.M = jb.M;
       ja.n = (int)jb.n;
       ja.ldp = (long)(jb.ld / 2);
-      ja.nsb = int((jb.n + kS - 1) / kS);
+      ja.nsb = int((jb.n + S - 1) / S);
       ja.in = shift_input(jb.in, r0);
       ja.part = reinterpret_cast<double2*>(sp);
       ja.y = jb.y + (long)r0 * jb.n;
@@ -440,12 +459,19 @@ rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, s
       nblk += ja.nsb * (ja.nsb + 1) / 2;
       nsbsum += ja.nsb;
     }
-    switch (nr) {
-      case 1: launch<T, 1, CONJ>(a, nblk, nsbsum, s, tag); break;
-      case 2: launch<T, 2, CONJ>(a, nblk, nsbsum, s, tag); break;
-      case 3: launch<T, 3, CONJ>(a, nblk, nsbsum, s, tag); break;
-      default: launch<T, 4, CONJ>(a, nblk, nsbsum, s, tag); break;
+#define RF_SYMV_NR(SV)                                                          \
+  switch (nr) {                                                                 \
+    case 1: launch<T, SV, 1, CONJ>(a, nblk, nsbsum, s, tag); break;             \
+    case 2: launch<T, SV, 2, CONJ>(a, nblk, nsbsum, s, tag); break;             \
+    case 3: launch<T, SV, 3, CONJ>(a, nblk, nsbsum, s, tag); break;             \
+    default: launch<T, SV, 4, CONJ>(a, nblk, nsbsum, s, tag); break;            \
+  }
+    if (S == kSmax) {
+      RF_SYMV_NR(kSmax)
+    } else {
+      RF_SYMV_NR(kSmin)
     }
+#undef RF_SYMV_NR
   }
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
@@ -454,9 +480,10 @@ rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, s
 }  // namespace
 
 size_t symv_scratch_bytes(int64_t n, int nrhs) {
-  const int64_t nsb = (n + kS - 1) / kS;
+  // the smaller block size needs the most slots
+  const int64_t nsb = (n + kSmin - 1) / kSmin;
   const int nr = std::min(std::max(nrhs, 1), kMaxNR);
-  return sizeof(double2) * (size_t)(nsb * nsb * nr * kS);
+  return sizeof(double2) * (size_t)(nsb * nsb * nr * kSmin);
 }
 
 rfcmp_status symv_form_input(const SymvInput& in, int64_t n, int nrhs, double2* out, hipStream_t s) {
