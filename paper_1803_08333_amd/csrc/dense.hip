@@ -1,5 +1,6 @@
 // The FP64 inverse used to build the dense projector matrices
 // (L^+ = (Sigma^T Sigma)^+, G_ll^-1, G_tp^-1) of a mesh.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -299,24 +300,20 @@ inline unsigned blocks_for(long n, int per) { return unsigned((n + per - 1) / pe
 
 }  // namespace
 
-rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, hipStream_t s) {
+rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, double* ubuf, double* rbuf,
+                         hipStream_t s) {
   if (n % kB != 0 || nvalid > n || nvalid < 0) {
     set_error("spd_inverse: n=%lld (valid %lld) not a multiple of %d", (long long)n, (long long)nvalid, kB);
     return RFCMP_E_ARG;
   }
   const int nb = int(n / kB);
   ProfScope prof("spd_inverse", s);
-  DevBuf ubuf, rbuf;  // released (after the device is idle) on return
-  RF_TRY(ubuf.alloc(sizeof(double) * n * kB));
-  RF_TRY(rbuf.alloc(sizeof(double) * n * kB));
   const unsigned ntiles = unsigned((long)nb * (nb + 1) / 2);
   hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, A, (long)n, 0);
   for (int K = 0; K < nb; ++K) {
     if (nb > 1) {
-      hipLaunchKernelGGL(k_gj_panels, dim3(nb, 4), dim3(256), 0, s, A, (long)n, K, ubuf.as<double>(),
-                         rbuf.as<double>());
-      hipLaunchKernelGGL(k_gj_update, dim3(ntiles), dim3(256), 0, s, A, (long)n, nb, K, ubuf.as<double>(),
-                         rbuf.as<double>());
+      hipLaunchKernelGGL(k_gj_panels, dim3(nb, 4), dim3(256), 0, s, A, (long)n, K, ubuf, rbuf);
+      hipLaunchKernelGGL(k_gj_update, dim3(ntiles), dim3(256), 0, s, A, (long)n, nb, K, ubuf, rbuf);
     }
   }
   const long total = (long)n * n;
@@ -336,6 +333,21 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
   MeshDev& d = m->d;
   const int64_t C = h.C, V = h.V, N = h.N;
 
+  // Scratch kept with the mesh, sized once for the largest matrix, so that
+  // nothing here is released (a release waits for the device) and the host
+  // goes on while the inverses run.
+  {
+    const int64_t nmax = (int64_t)round_up(std::max(C, V), kB);
+    const size_t nnz = (size_t)std::max<int64_t>({C + 2 * N, V + 2 * N, need_gtp ? h.cell_nb_ptr[C] : 0});
+    if (d.gj_u.bytes < sizeof(double) * nmax * kB) {
+      RF_TRY(d.gj_u.alloc(sizeof(double) * nmax * kB));
+      RF_TRY(d.gj_r.alloc(sizeof(double) * nmax * kB));
+    }
+    if (d.scat_v.bytes < sizeof(double) * nnz) {
+      RF_TRY(d.scat_ij.alloc(sizeof(int) * 2 * nnz));
+      RF_TRY(d.scat_v.alloc(sizeof(double) * nnz));
+    }
+  }
   auto build = [&](DevBuf& buf, int64_t nvalid, int64_t& ld, double inner,
                    const std::vector<int>& ij, const std::vector<double>& val,
                    bool sub_inner_after) -> rfcmp_status {
@@ -344,15 +356,16 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
     const long total = ld * ld;
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(total, 256)), dim3(256), 0, s, buf.as<double>(), (long)ld,
                        (long)nvalid, inner, total);
-    DevBuf dij, dv;
-    RF_TRY(dij.alloc(sizeof(int) * ij.size()));
-    RF_TRY(dv.alloc(sizeof(double) * val.size()));
+    DevBuf& dij = d.scat_ij;
+    DevBuf& dv = d.scat_v;
+    // pageable sources: the copies are staged before these calls return
     RF_HIP(hipMemcpyAsync(dij.p, ij.data(), sizeof(int) * ij.size(), hipMemcpyHostToDevice, s));
     RF_HIP(hipMemcpyAsync(dv.p, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_scatter_add, dim3(blocks_for((long)val.size(), 256)), dim3(256), 0, s,
                        buf.as<double>(), (long)ld, dij.as<int>(), dv.as<double>(), (long)val.size());
     RF_HIP(hipGetLastError());
-    return spd_inverse(buf.as<double>(), ld, nvalid, sub_inner_after ? inner : 0.0, s);
+    return spd_inverse(buf.as<double>(), ld, nvalid, sub_inner_after ? inner : 0.0, d.gj_u.as<double>(),
+                       d.gj_r.as<double>(), s);
   };
 
   // L + J

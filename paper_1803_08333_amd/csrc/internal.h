@@ -147,6 +147,8 @@ struct MeshDev {
   int64_t npairs = 0;
   DevBuf near;       // int [npairs][2]
   DevBuf pairB;      // complex64 [3C][ldB] cell-pair block scratch of the assembly
+  DevBuf gj_u, gj_r; // FP64 panel buffers of the inverse ([n][64] each, largest n)
+  DevBuf scat_ij, scat_v;  // coordinate lists of the projector matrices
   MeshDev();
   ~MeshDev();
 };
@@ -195,7 +197,9 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s);
 // In-place inverse of an SPD matrix, FP64: A [n][n] (n a multiple of 64)
 // holds an SPD matrix in its leading nvalid x nvalid block and the identity
 // in the padding; on return that block holds A^-1 - shift 1 1^T (exactly
-// symmetric), the padding the identity again.
-rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, hipStream_t s);
+// symmetric), the padding the identity again.  ubuf, rbuf: device scratch of
+// n * 64 doubles each.  Enqueued on s; does not wait.
+rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, double* ubuf, double* rbuf,
+                         hipStream_t s);
 
 }  // namespace rfcmp

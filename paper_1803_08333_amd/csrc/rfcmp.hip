@@ -84,7 +84,7 @@ rfcmp_status ensure_work(rfcmp_op op, int R) {
   R = std::max(R, 4);
   if (op->work.p && op->work_nrhs >= R) return RFCMP_OK;
   const MeshHost& h = op->mesh->h;
-  RF_HIP(hipDeviceSynchronize());  // the old workspace may still be in use by queued work
+  if (op->work.p) RF_HIP(hipDeviceSynchronize());  // the old workspace may still be in use by queued work
   RF_TRY(op->work.alloc(sizeof(double2) * work_doubles2(h.N, h.C, h.V, R) + 4096));
   op->work_nrhs = R;
   if (op->host_scal) (void)hipHostFree(op->host_scal);
