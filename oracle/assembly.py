@@ -32,7 +32,7 @@ import numpy as np
 from .quadrature import tri7_points
 from .singular import potentials
 
-__all__ = ["near_mask", "assemble", "near_block", "cell_embedding"]
+__all__ = ["near_mask", "assemble", "near_block", "cell_embedding", "far_rows", "block_rows", "ta_rows"]
 
 
 def near_mask(top, near_factor=2.0):
@@ -131,3 +131,49 @@ def assemble(top, k, near_factor=2.0, chunk=32, return_blocks=False):
     if return_blocks:
         return TA, Vm, Bm
     return TA, Vm
+
+
+def block_rows(top, k, cells, near_factor=2.0):
+    """Rows ``cells`` of V and of the cell-slot block matrix B, by the same
+    spec as ``assemble`` but without forming the C x C matrices (for
+    sampled checks on large meshes): (V rows [len, C], B rows [len, 3, C, 3]).
+
+    The near test uses the criterion of ``near_mask`` for the given rows
+    only; a near pair (c, c') takes the outer rule on the lower-indexed cell,
+    so for c' < c the row holds the transpose of the (c', c) block."""
+    cells = np.asarray(cells)
+    pts, w = tri7_points(top.xyz, top.tri)
+    Vr, Br = far_rows(top, k, cells, pts, w)
+    h = top.longest_edge()
+    for a, c in enumerate(cells):
+        d = np.linalg.norm(top.centroid - top.centroid[c], axis=1)
+        thr = near_factor * np.maximum(h[c], h) * (1.0 + 1e-9)
+        for cp in np.nonzero(d < thr)[0]:
+            if cp >= c:
+                blk, v = near_block(top, c, cp, k, pts, w)
+                if cp == c:
+                    blk = 0.5 * (blk + blk.T)
+            else:
+                blk, v = near_block(top, cp, c, k, pts, w)
+                blk = blk.T
+            Br[a, :, cp, :] = blk
+            Vr[a, cp] = v
+    return Vr, Br
+
+
+def ta_rows(top, k, edges, near_factor=2.0):
+    """Rows ``edges`` of T_A (complex128 [len, N]) from T_A = E B E^T: row m
+    sums the block rows of the two cell slots of RWG m, and each column n
+    collects the slots of RWG n."""
+    edges = np.asarray(edges)
+    cells = np.unique(np.concatenate([top.cplus[edges], top.cminus[edges]]))
+    _, Br = block_rows(top, k, cells, near_factor)
+    row_of = {int(c): a for a, c in enumerate(cells)}
+    out = np.zeros((len(edges), top.N), dtype=np.complex128)
+    for r, m in enumerate(edges):
+        acc = np.zeros((top.C, 3), dtype=np.complex128)
+        for c in (int(top.cplus[m]), int(top.cminus[m])):
+            i = int(np.nonzero(top.cell_edges[c] == m)[0][0])
+            acc += Br[row_of[c], i]
+        np.add.at(out[r], top.cell_edges.ravel(), acc.ravel())
+    return out

@@ -112,12 +112,13 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, long ld
 }
 
 // Panels of pivot block K: for each J != K, U_J = A_KJ (old; tile (J, K)
-// transposed when J < K) and R_J = E U_J with E = -(tile K, K).  Writes U_J
-// and R_J to the compact panel buffers ([nb][64][64] each) and R_J back into
-// the upper tile.  Workgroup (J, h) forms rows 16 h .. 16 h + 15 of R_J from
-// those rows of E and all of U_J (staged in LDS, transposed there when the
-// stored tile is A_JK); tiles are read and written row by row.
-__global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long ld, int K,
+// transposed when J < K) and R_J = E U_J with E = -(tile K, K), written to
+// the compact panel buffers ([nb][64][64] each).  Workgroup (J, h) forms rows
+// 16 h .. 16 h + 15 of R_J from those rows of E and all of U_J (staged in LDS,
+// transposed there when the stored tile is A_JK).  The tiles of A are only
+// read here: four workgroups read each tile, so the new panel R_J goes back
+// into A in the update kernel.
+__global__ __launch_bounds__(256) void k_gj_panels(const double* __restrict__ A, long ld, int K,
                                                    double* __restrict__ Ubuf, double* __restrict__ Rbuf) {
   const int J = blockIdx.x, h = blockIdx.y;
   if (J == K) return;
@@ -155,25 +156,11 @@ __global__ __launch_bounds__(256) void k_gj_panels(double* __restrict__ A, long 
   }
   const int gi = h * HR + i;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    Ro[gi * kB + c0 + v] = acc[v];
-    if (up) A[(pb + gi) * ld + jb + c0 + v] = acc[v];
-  }
-  if (!up) {
-    // the stored tile is R_J^T: rows c, columns gi; stage through LDS so
-    // the writes go out row by row
-    __syncthreads();
-#pragma unroll
-    for (int v = 0; v < 4; ++v) U[c0 + v][i] = acc[v];  // U reused: [c][i], i < HR
-    __syncthreads();
-    for (int t = threadIdx.x; t < kB * HR; t += 256) {
-      const int c = t / HR, ii = t % HR;
-      A[(jb + c) * ld + pb + h * HR + ii] = U[c][ii];
-    }
-  }
+  for (int v = 0; v < 4; ++v) Ro[gi * kB + c0 + v] = acc[v];
 }
 
-// Rank-64 update of the upper tiles: A_IJ -= U_I^T R_J for I <= J, I, J != K.
+// Rank-64 update of the upper tiles: A_IJ -= U_I^T R_J for I <= J, I, J != K;
+// the workgroups of the pivot row and column tiles store the new panel.
 // One 64 x 64 tile per workgroup; thread (ty, tx) owns rows 4 ty .. + 3 and
 // columns 4 tx .. + 3 (loaded first, so the read overlaps the products).
 // K-chunks of 32 rows of U_I and R_J sit in LDS unpadded, so each thread
@@ -198,7 +185,19 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
     ++I;
   }
   const int J = I + rem;
-  if (I == K || J == K) return;
+  if (I == K || J == K) {
+    // a tile of the pivot row or column: store the new panel, R_J into
+    // tile (K, J) for J > K, R_I^T into tile (I, K) for I < K
+    if (I == J) return;  // the pivot tile holds -E already
+    const long ib = (long)I * kB, jb = (long)J * kB;
+    const bool row = (I == K);
+    const double* Rt = Rbuf + (long)(row ? J : I) * kB * kB;
+    for (int t = threadIdx.x; t < kB * kB; t += 256) {
+      const int i = t / kB, c = t % kB;
+      A[(ib + i) * ld + jb + c] = row ? Rt[i * kB + c] : Rt[c * kB + i];
+    }
+    return;
+  }
   constexpr int KC = 32;
   __shared__ __align__(16) double lds[2 * KC * kB];
   double(*uu)[kB] = reinterpret_cast<double(*)[kB]>(lds);
@@ -439,7 +438,6 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
     RF_TRY(build(d.Gtp_inv, C, d.ldT, 0.0, ij, v, false));
     d.has_gtp = true;
   }
-  RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;
 }
 

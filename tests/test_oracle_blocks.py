@@ -3,7 +3,9 @@ import numpy as np
 import pytest
 from scipy import integrate
 
+import synth
 from oracle import assembly, quadrature, rhs, singular
+from oracle.topology import Topology
 
 from ._meshes import blocks, topo
 
@@ -232,3 +234,17 @@ def test_rhs_vs_refined_quadrature():
             f = top.cell_sign[c, i] * (x - top.xyz[top.tri[c, i]]) / (2 * top.area[c])
             ref[top.cell_edges[c, i]] += np.sum(wx * (f @ pol) * np.exp(1j * k * (x @ kh)))
     assert np.abs(e - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+def test_sampled_rows_equal_full_assembly():
+    """block_rows / ta_rows (used for sampled checks of full-size GPU blocks)
+    reproduce the rows of the full assembly exactly: same spec, same
+    functions, including near pairs on both sides of the diagonal."""
+    xyz, tri = synth.torus(12, 8, jitter=0.01, seed=3)
+    top = Topology(xyz, tri)
+    TA, V = assembly.assemble(top, 0.7)
+    cells = [0, 5, 17, top.C - 1]
+    Vr, _ = assembly.block_rows(top, 0.7, cells)
+    assert np.array_equal(Vr, V[cells])
+    edges = [0, 3, 50, top.N - 1]
+    assert np.array_equal(assembly.ta_rows(top, 0.7, edges), TA[edges])
