@@ -38,7 +38,7 @@ WORKLOAD = {"workload": "PEC sphere r=1 m, icosphere level 4 (5120 cells, 7680 R
             "mesh": "icosphere4", "ka": [1.0, 1e-4], "nrhs": 1, "tol": 1e-6}
 TOL = 1e-6
 KS = (1.0, 1e-4)
-FAR_FLOPS_PER_POINT_PAIR = 30     # see the design doc: sub 3, R^2 5, rsqrt 1, R 1, kR 1, sin+cos 2, G 3, sums 14
+FAR_FLOPS_PER_POINT_PAIR = 30     # sub 3, R^2 5, rsqrt 1, R 1, kR 1, sin+cos 2, G 3, moment sums 14 (FMA = 2)
 
 
 def parse():
@@ -138,43 +138,57 @@ def measured_traffic(tag):
     return 1024.0 * (fk * TRAFFIC_SCALE["fetch"] + wk * TRAFFIC_SCALE["write"])
 
 
-def precision_study(rf, torch, xyz, tri, kh, pol, start, nb):
+def _timed_solve(torch, op, e):
+    op.solve(e, tol=TOL, maxit=2000)          # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    j, st, info = op.solve(e, tol=TOL, maxit=2000)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3, st, info
+
+
+def precision_study(rf, torch, nb):
     """BF16x3 (precision 1) against the complex64/FP64 path (precision 0), both
-    to the same true relative residual 1e-6, on the same mesh: single plane
-    wave at both wavenumbers, and a batch of nb seeded plane waves at ka = 1.
-    Also the BF16x3 T_A product's MFMA and HBM rates from HIP events."""
+    to the same true relative residual 1e-6, on the workloads the comparison
+    is defined on: the level-4 sphere (one plane wave, ka = 1 and 1e-4), the
+    jittered 96 x 48 torus (one plane wave, ka = 0.5) and the level-5 sphere
+    (nb seeded plane waves, ka = 2), with the BF16x3 T_A product's MFMA and
+    HBM rates from HIP events on the last."""
     out = {"tol": TOL}
-    m = rf.Mesh(xyz, tri)
-    N = m.N
-    for k in KS:
+    kh, pol = synth.default_plane_wave()
+    singles = [("icosphere4", synth.icosphere(4), 1.0), ("icosphere4", synth.icosphere(4), 1e-4),
+               ("torus96x48", synth.torus(), 0.5)]
+    for name, (xyz, tri), k in singles:
+        m = rf.Mesh(xyz, tri)
+        start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
         row = {}
         for prec in (0, 1):
             op = rf.Operator(m, k, power_start=start, precision=prec)
-            e = op.rhs_planewave(kh, pol)
-            op.solve(e, tol=TOL, maxit=2000)          # warm
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            j, st, info = op.solve(e, tol=TOL, maxit=2000)
-            torch.cuda.synchronize()
-            row["bf16x3" if prec else "fp32"] = {"solve_ms": (time.perf_counter() - t0) * 1e3,
-                                                 "iters": info[0]["iters"], "rounds": info[0]["restarts"] + 1,
+            ms, st, info = _timed_solve(torch, op, op.rhs_planewave(kh, pol))
+            row["bf16x3" if prec else "fp32"] = {"solve_ms": ms, "iters": info[0]["iters"],
+                                                 "rounds": info[0]["restarts"] + 1,
                                                  "rel_residual": info[0]["rel_residual"], "status": st}
             op.close()
-        out[f"ka={k}, 1 rhs"] = row
+        out[f"{name} ka={k}, 1 rhs"] = row
+        m.close()
+    xyz, tri = synth.icosphere(5)
+    m = rf.Mesh(xyz, tri)
+    N = m.N
+    start = torch.from_numpy(synth.complex_start(N, 11)).cuda()
     kb, pb = synth.plane_waves(nb, 4)
     row = {}
     for prec in (0, 1):
-        op = rf.Operator(m, 1.0, power_start=start, precision=prec)
+        op = rf.Operator(m, 2.0, power_start=start, precision=prec)
         e = op.rhs_planewave(kb, pb)
         op.solve(e, tol=TOL, maxit=2000)
         torch.cuda.synchronize()
+        rf.profile_select(None)
         rf.profile_enable(True)
         t0 = time.perf_counter()
         j, st, info = op.solve(e, tol=TOL, maxit=2000)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
         gt, gn = rf.profile_read("gemm_ta")
-        ct, cn = rf.profile_read("cmatvec_ta")
         rf.profile_enable(False)
         r = {"solve_ms": ms, "ms_per_rhs": ms / nb, "max_iters": max(i["iters"] for i in info),
              "max_rel_residual": max(i["rel_residual"] for i in info), "status": st}
@@ -185,11 +199,9 @@ def precision_study(rf, torch, xyz, tri, kh, pol, start, nb):
                             "mfma_tflops": mfma_flops / (avg * 1e-3) / 1e12,
                             "mfma_frac": mfma_flops / (avg * 1e-3) / 1e12 / BF16_MFMA_TFLOPS,
                             "hbm_gbs": 8.0 * N * N / (avg * 1e-3) / 1e9}
-        if prec == 0 and cn:
-            r["cmatvec_ta"] = {"avg_ms": ct / cn, "launches": cn}
         row["bf16x3" if prec else "fp32"] = r
         op.close()
-    out[f"ka=1.0, {nb} rhs"] = row
+    out[f"icosphere5 ka=2.0, {nb} rhs"] = row
     m.close()
     return out
 
@@ -198,7 +210,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
-              "see DESIGN.md for how the operator would shard.", file=sys.stderr)
+              "one operator would shard by row blocks of T_A, V and L^+ with one all-gather of the input per "
+              "product.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
@@ -314,7 +327,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_precision_study:
-        res["bf16x3_vs_fp32"] = precision_study(rf, torch, xyz, tri, kh, pol, start, args.batch_rhs)
+        res["bf16x3_vs_fp32"] = precision_study(rf, torch, args.batch_rhs)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(xyz, tri, args.cpu_slab)
     print(json.dumps(res))
