@@ -118,12 +118,11 @@ BF16_MFMA_TFLOPS = 2500.0
 # 1.0).  Valid only for the kernel source they were taken on: reported as
 # null once symv.hip changes.
 TRAFFIC_SOURCE = {"path": "paper_1803_08333_amd/csrc/symv.hip",
-                  "sha256": "a889c8763e53b1df7e8a91bcef822e7735ed2c0b6b53a7f74a13632ab3f49b25"}
+                  "sha256": "2274f3ed977bd803ad18b41efa82dffe0b0b85bfbb04dc62fe4b75807c338799"}
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {  # tag: (FETCH_SIZE, WRITE_SIZE)
-    "cmatvec_ta": (117664.5, 7200.0), "cmatvec_ta_nr2": (118166.0, 14400.0),
-    "cmatvec_v": (52864.5, 3200.0), "dmatvec_lp": (52862.0, 3200.0), "dmatvec_lp_nr2": (53200.5, 6400.0),
-    "dmatvec_gll": (13822.6, 882.0)}
+    "cmatvec_ta_nr2": (120094.5, 7200.0), "cmatvec_ta+v": (174941.0, 5200.1), "cmatvec_v": (52860.5, 3200.0),
+    "dmatvec_lp": (53262.1, 3200.0), "dmatvec_lp_nr2": (54007.8, 6400.0), "dmatvec_lp+gll": (67989.1, 4082.0)}
 
 
 def measured_traffic(tag):
