@@ -353,18 +353,21 @@ rfcmp_status power_apply(const Dense& D, const Work& W) {
   const int64_t N = h.N, C = h.C, V = h.V;
   double2* va = W.pv;
   double2* vb = W.pv + 2 * N;
+  // The beta chain's two V products ride along with the two-column T_A
+  // passes of alpha and gamma: V takes two columns too, both reading the
+  // beta vector (input stride 0); the second result is not used.
+  SymvInput sb = D.sigma_t(vb);
+  sb.stride[0] = 0;
   RF_TRY(D.prod(kLP, false, D.sigma_t(va), W.c[1], 2));
-  RF_TRY(D.prod(kTA, false, D.proj_lh(va, W.c[1]), W.nB, 2));                   // T_A P_LH v
+  RF_TRY(D.pair(kTA, D.proj_lh(va, W.c[1]), W.nB, kV, sb, W.c[7], false, 2));      // T_A P_LH v | V Sig^T v
   RF_TRY(D.pair(kLP, D.sigma_t(W.nB + N), W.c[3], kGLL, D.lambda_t(W.nB), W.v2, false, 1));
-  RF_TRY(lambda_n(d, N, V, W.v2, W.nC, 1, s));                                   // alpha branch
-  RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nB + N, -1.0, W.c[3], W.nC + N, 1, s));  // gamma branch
-  RF_TRY(D.prod(kTA, true, W.nC, W.nD, 2));
+  RF_TRY(comb_mean(C, d.area.as<double>(), 0.0, nullptr, 1.0, W.c[7], W.c[8], 1.0, W.c[9], 1, s));
+  RF_TRY(power_branch(d, N, V, C, W.v2, W.nB, W.c[3], W.nC, s));                // alpha | gamma branch
+  SymvInput sw = Dense::plain(W.c[9], C);
+  sw.stride[0] = 0;
+  RF_TRY(D.pair(kTA, Dense::plain(W.nC, N), W.nD, kV, sw, W.c[10], true, 2));
   RF_TRY(D.prod(kLP, false, D.sigma_t(W.nD), W.c[5], 2));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nD, -1.0, W.c[5], W.pw, 2, s));
-  // beta
-  RF_TRY(D.prod(kV, false, D.sigma_t(vb), W.c[7], 1));
-  RF_TRY(comb_mean(C, d.area.as<double>(), 0.0, nullptr, 1.0, W.c[7], W.c[8], 1.0, W.c[9], 1, s));
-  RF_TRY(D.prod(kV, true, W.c[9], W.c[10], 1));
   RF_TRY(axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[10], W.pw + 2 * N, 1, s));
   return RFCMP_OK;
 }
@@ -377,8 +380,7 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStr
   for (int r = 0; r < 3; ++r)
     RF_HIP(hipMemcpyAsync(W.pw + r * N, start, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
   for (int it = 0; it < steps; ++it) {
-    RF_TRY(dot(N, W.pw, W.pw, W.part, W.dout, 3, s));
-    RF_TRY(normalize(N, W.dout, W.pw, W.pv, 3, s));
+    RF_TRY(normalize_rows(N, W.pw, W.pv, W.dout, 3, s));
     RF_TRY(power_apply(D, W));
   }
   RF_TRY(dot(N, W.pw, W.pw, W.part, W.dout, 3, s));

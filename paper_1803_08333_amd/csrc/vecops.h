@@ -28,6 +28,11 @@ rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double
 rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, double2* out, int nr,
                  hipStream_t s);
 int dot_partials();
+// out[r] = x[r] / |x[r]|, nrm2[r] = |x[r]|^2 (one launch)
+rfcmp_status normalize_rows(int64_t n, const double2* x, double2* out, double2* nrm2, int nr, hipStream_t s);
+// power iteration: out[0] = Lambda h, out[1] = a[1] - Sigma z  (h [V], z [C], a and out [2][N])
+rfcmp_status power_branch(const MeshDev& d, int64_t N, int64_t V, int64_t C, const double2* h, const double2* a,
+                          const double2* z, double2* out, hipStream_t s);
 // out[r] = x[r] / sqrt(re nrm2[r])
 rfcmp_status normalize(int64_t n, const double2* nrm2, const double2* x, double2* out, int nr, hipStream_t s);
 // block CG updates over nr right-hand sides (frozen where active[r] == 0)

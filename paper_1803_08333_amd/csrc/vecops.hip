@@ -149,6 +149,18 @@ __global__ void k_lambda(int N, int V, const int* __restrict__ edge_vtx, const d
   out[r * N + n] = csub(h[r * V + edge_vtx[2 * n]], h[r * V + edge_vtx[2 * n + 1]]);
 }
 
+// Power-iteration branches: out[0] = Lambda h (V -> N), out[1] = a[1] - Sigma z
+// (h and z single vectors, a two rows).
+__global__ void k_power_branch(int N, int V, int C, const int* __restrict__ edge_vtx,
+                               const int* __restrict__ edge_cell, const double2* __restrict__ h,
+                               const double2* __restrict__ a, const double2* __restrict__ z,
+                               double2* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  out[n] = csub(h[edge_vtx[2 * n]], h[edge_vtx[2 * n + 1]]);
+  out[(long)N + n] = csub(a[(long)N + n], csub(z[edge_cell[2 * n]], z[edge_cell[2 * n + 1]]));
+}
+
 // ---------------------------------------------------------------- reductions
 constexpr int kRedBlocks = 240;
 
@@ -207,6 +219,23 @@ __global__ void k_normalize(long n, const double2* __restrict__ nrm2, const doub
   const long r = blockIdx.y;
   const double s = 1.0 / sqrt(nrm2[r].x);
   out[r * n + i] = cscale(s, x[r * n + i]);
+}
+
+// out[r] = x[r] / |x[r]|_2 and nrm2[r] = |x[r]|^2, one workgroup per row
+// (fixed-order sum: strided per thread, then a tree).
+__global__ __launch_bounds__(1024) void k_normalize_rows(long n, const double2* __restrict__ x,
+                                                         double2* __restrict__ out, double2* __restrict__ nrm2) {
+  __shared__ double sr[1024], si[1024];
+  const long r = blockIdx.x;
+  double a = 0.0;
+  for (long i = threadIdx.x; i < n; i += 1024) {
+    const double2 v = x[r * n + i];
+    a += v.x * v.x + v.y * v.y;
+  }
+  const double2 t = block_sum_1024(a, 0.0, sr, si);
+  const double sc = 1.0 / sqrt(t.x);
+  if (threadIdx.x == 0) nrm2[r] = make_double2(t.x, 0.0);
+  for (long i = threadIdx.x; i < n; i += 1024) out[r * n + i] = cscale(sc, x[r * n + i]);
 }
 
 __global__ void k_sub(long n, const double2* __restrict__ a, const double2* __restrict__ b,
@@ -314,6 +343,18 @@ rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, d
   return RFCMP_OK;
 }
 int dot_partials() { return kRedBlocks; }
+rfcmp_status normalize_rows(int64_t n, const double2* x, double2* out, double2* nrm2, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize_rows, dim3(nr), dim3(1024), 0, s, (long)n, x, out, nrm2);
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+rfcmp_status power_branch(const MeshDev& d, int64_t N, int64_t V, int64_t C, const double2* h, const double2* a,
+                          const double2* z, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_branch, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, (int)N, (int)V, (int)C,
+                     d.edge_vtx.as<int>(), d.edge_cell.as<int>(), h, a, z, out);
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
 rfcmp_status normalize(int64_t n, const double2* nrm2, const double2* x, double2* out, int nr, hipStream_t s) {
   hipLaunchKernelGGL(k_normalize, g1(n, nr), dim3(256), 0, s, (long)n, nrm2, x, out);
   RF_LAUNCH_CHECK();
