@@ -368,7 +368,10 @@ __global__ __launch_bounds__(128) void k_near_pairs(long npairs, const int* __re
 
 // ---------------------------------------------------------------- gather
 // T_A[m,n] = (B[m+,n+] + B[m-,n-]) + (B[m+,n-] + B[m-,n+]) over the cell slots
-// of the two edges; the fixed pairing keeps T_A exactly symmetric.
+// of the two edges; the fixed pairing keeps T_A exactly symmetric.  Only
+// the entries with n >= kTriBlock floor(m / kTriBlock) are formed (the upper
+// triangle of kTriBlock-wide blocks, all that the symmetric products read);
+// the others are the transposed entries, bit for bit.
 __global__ __launch_bounds__(256) void k_gather_ta(int N, const int* __restrict__ slot,
                                                    const float2* __restrict__ B, long ldB,
                                                    float2* __restrict__ TA, long ldA) {
@@ -376,7 +379,7 @@ __global__ __launch_bounds__(256) void k_gather_ta(int N, const int* __restrict_
   const int sp = slot[2 * m], sm = slot[2 * m + 1];
   const float2* bp = B + (long)sp * ldB;
   const float2* bm = B + (long)sm * ldB;
-  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+  for (int n = (m / kTriBlock) * kTriBlock + threadIdx.x; n < N; n += blockDim.x) {
     const int np = slot[2 * n], nm = slot[2 * n + 1];
     const float2 pp = bp[np], mm = bm[nm], pm = bp[nm], mp = bm[np];
     const float2 s1 = make_float2(pp.x + mm.x, pp.y + mm.y);
@@ -502,7 +505,6 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   const long npairs = (long)d.npairs;
   DevBuf& dp = d.near;
   RF_HIP(hipMemsetAsync(op->Vb.p, 0, op->Vb.bytes, s));
-  RF_HIP(hipMemsetAsync(op->TA.p, 0, op->TA.bytes, s));
 
   const long nt = (long)((C + kTile - 1) / kTile);
   const long ntiles = nt * (nt + 1) / 2;

@@ -161,13 +161,19 @@ __global__ __launch_bounds__(256) void k_gj_panels(const double* __restrict__ A,
 
 // Rank-64 update of the upper tiles: A_IJ -= U_I^T R_J for I <= J, I, J != K;
 // the workgroups of the pivot row and column tiles store the new panel.
-// One 64 x 64 tile per workgroup; thread (ty, tx) owns rows 4 ty .. + 3 and
-// columns 4 tx .. + 3 (loaded first, so the read overlaps the products).
-// K-chunks of 32 rows of U_I and R_J sit in LDS unpadded, so each thread
-// reads its four U and four R values per step as two 16-byte words each.
+// One 64 x 64 tile per workgroup on the FP64 matrix cores: wave w owns the
+// 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 blocks of 16 x 16, each a
+// v_mfma_f64_16x16x4 accumulator (value v of lane l: row 4 v + l / 16,
+// column l % 16), loaded from A first so that the read overlaps the staging.
+// K-chunks of 32 rows of U_I and R_J sit in LDS fragment-major: the 4 x 16
+// operand of (row group g, column block b) is 64 consecutive doubles with
+// lane l's value (row 4 g + l / 16, column 16 b + l % 16) at position l, so
+// every operand read is one conflict-free 512-byte wave load.
 // Workgroup 0 takes the next diagonal tile (K+1, K+1) and, once it is
 // updated, sweeps it: the serial sweep of the next pivot block runs while
 // the rest of the update streams.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long ld, int nb, int K,
                                                    const double* __restrict__ Ubuf,
                                                    const double* __restrict__ Rbuf) {
@@ -199,41 +205,38 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
     return;
   }
   constexpr int KC = 32;
-  __shared__ __align__(16) double lds[2 * KC * kB];
-  double(*uu)[kB] = reinterpret_cast<double(*)[kB]>(lds);
-  double(*rr)[kB] = reinterpret_cast<double(*)[kB]>(lds + KC * kB);
+  __shared__ __align__(16) double lds[2 * KC * kB];  // U chunk, R chunk
   const long ib = (long)I * kB, jb = (long)J * kB;
   const double* Ui = Ubuf + (long)I * kB * kB;
   const double* Rj = Rbuf + (long)J * kB * kB;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4];
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int wr = w / 2, wc = w % 2;
+  const int r0 = wr * 32 + lane / 16, c0 = wc * 32 + lane % 16;
+  dbl4 acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const double2* src = reinterpret_cast<const double2*>(A + (ib + ty * 4 + u) * ld + jb + tx * 4);
-    const double2 a0 = src[0], a1 = src[1];
-    acc[u][0] = a0.x;
-    acc[u][1] = a0.y;
-    acc[u][2] = a1.x;
-    acc[u][3] = a1.y;
-  }
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = A[(ib + r0 + 16 * a + 4 * v) * ld + jb + c0 + 16 * b];
   for (int k0 = 0; k0 < kB; k0 += KC) {
     for (int t = threadIdx.x; t < KC * kB / 2; t += 256) {
-      reinterpret_cast<double2*>(lds)[t] = reinterpret_cast<const double2*>(Ui + k0 * kB)[t];
-      reinterpret_cast<double2*>(lds + KC * kB)[t] = reinterpret_cast<const double2*>(Rj + k0 * kB)[t];
+      const int q = t / (kB / 2), c = (t % (kB / 2)) * 2;
+      const int o = ((q / 4) * 4 + c / 16) * 64 + (q % 4) * 16 + c % 16;
+      *reinterpret_cast<double2*>(lds + o) = reinterpret_cast<const double2*>(Ui + (k0 + q) * kB)[c / 2];
+      *reinterpret_cast<double2*>(lds + KC * kB + o) = reinterpret_cast<const double2*>(Rj + (k0 + q) * kB)[c / 2];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int q = 0; q < KC; ++q) {
-      const double2 a01 = *reinterpret_cast<const double2*>(&uu[q][ty * 4]);
-      const double2 a23 = *reinterpret_cast<const double2*>(&uu[q][ty * 4 + 2]);
-      const double2 r01 = *reinterpret_cast<const double2*>(&rr[q][tx * 4]);
-      const double2 r23 = *reinterpret_cast<const double2*>(&rr[q][tx * 4 + 2]);
-      const double av[4] = {a01.x, a01.y, a23.x, a23.y};
-      const double rv[4] = {r01.x, r01.y, r23.x, r23.y};
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(-av[u], rv[v], acc[u][v]);
+    for (int g = 0; g < KC / 4; ++g) {
+      const double a0 = -lds[(g * 4 + wr * 2) * 64 + lane];
+      const double a1 = -lds[(g * 4 + wr * 2 + 1) * 64 + lane];
+      const double b0 = lds[KC * kB + (g * 4 + wc * 2) * 64 + lane];
+      const double b1 = lds[KC * kB + (g * 4 + wc * 2 + 1) * 64 + lane];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -242,9 +245,11 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
     double* t = lds;  // [64][64]
     static_assert(2 * KC * kB >= kB * kB, "LDS tile");
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) t[(ty * 4 + u) * kB + tx * 4 + v] = acc[u][v];
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) t[(r0 + 16 * a + 4 * v) * kB + c0 + 16 * b] = acc[a][b][v];
     __syncthreads();
     const int j = threadIdx.x % kB, i0 = (threadIdx.x / kB) * 16;
     double r[16];
@@ -257,11 +262,11 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, long 
     return;
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    double2* dst = reinterpret_cast<double2*>(A + (ib + ty * 4 + u) * ld + jb + tx * 4);
-    dst[0] = make_double2(acc[u][0], acc[u][1]);
-    dst[1] = make_double2(acc[u][2], acc[u][3]);
-  }
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(ib + r0 + 16 * a + 4 * v) * ld + jb + c0 + 16 * b] = acc[a][b][v];
 }
 
 // Final pass over the upper triangle (i <= j): the swept matrix holds -A^-1
@@ -332,39 +337,56 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
   MeshDev& d = m->d;
   const int64_t C = h.C, V = h.V, N = h.N;
 
-  // Scratch kept with the mesh, sized once for the largest matrix, so that
-  // nothing here is released (a release waits for the device) and the host
-  // goes on while the inverses run.
-  {
-    const int64_t nmax = (int64_t)round_up(std::max(C, V), kB);
-    const size_t nnz = (size_t)std::max<int64_t>({C + 2 * N, V + 2 * N, need_gtp ? h.cell_nb_ptr[C] : 0});
-    if (d.gj_u.bytes < sizeof(double) * nmax * kB) {
-      RF_TRY(d.gj_u.alloc(sizeof(double) * nmax * kB));
-      RF_TRY(d.gj_r.alloc(sizeof(double) * nmax * kB));
-    }
-    if (d.scat_v.bytes < sizeof(double) * nnz) {
-      RF_TRY(d.scat_ij.alloc(sizeof(int) * 2 * nnz));
-      RF_TRY(d.scat_v.alloc(sizeof(double) * nnz));
+  // Two internal streams: L^+ on the first, G_ll^-1 (then G_tp^-1) on the
+  // second, both after the work already enqueued on s.  Scratch is kept with
+  // the mesh per stream, sized once, so that nothing here is released (a
+  // release waits for the device) and the host goes on while the inverses run.
+  for (int q = 0; q < 2; ++q) {
+    if (!d.proj_stream[q]) {
+      RF_HIP(hipStreamCreateWithFlags(&d.proj_stream[q], hipStreamNonBlocking));
+      RF_HIP(hipEventCreateWithFlags(&d.proj_done[q], hipEventDisableTiming));
     }
   }
-  auto build = [&](DevBuf& buf, int64_t nvalid, int64_t& ld, double inner,
+  if (!d.proj_start) RF_HIP(hipEventCreateWithFlags(&d.proj_start, hipEventDisableTiming));
+  RF_HIP(hipEventRecord(d.proj_start, s));
+  {
+    const int64_t n0 = (int64_t)round_up(C, kB);
+    const int64_t n1 = (int64_t)round_up(need_gtp ? std::max(C, V) : V, kB);
+    const size_t nnz0 = (size_t)(C + 2 * N);
+    const size_t nnz1 = (size_t)std::max<int64_t>(V + 2 * N, need_gtp ? h.cell_nb_ptr[C] : 0);
+    const int64_t nn[2] = {n0, n1};
+    const size_t nz[2] = {nnz0, nnz1};
+    for (int q = 0; q < 2; ++q) {
+      RF_HIP(hipStreamWaitEvent(d.proj_stream[q], d.proj_start, 0));
+      if (d.gj_u[q].bytes < sizeof(double) * nn[q] * kB) {
+        RF_TRY(d.gj_u[q].alloc(sizeof(double) * nn[q] * kB));
+        RF_TRY(d.gj_r[q].alloc(sizeof(double) * nn[q] * kB));
+      }
+      if (d.scat_v[q].bytes < sizeof(double) * nz[q]) {
+        RF_TRY(d.scat_ij[q].alloc(sizeof(int) * 2 * nz[q]));
+        RF_TRY(d.scat_v[q].alloc(sizeof(double) * nz[q]));
+      }
+    }
+  }
+  auto build = [&](int q, DevBuf& buf, int64_t nvalid, int64_t& ld, double inner,
                    const std::vector<int>& ij, const std::vector<double>& val,
                    bool sub_inner_after) -> rfcmp_status {
+    hipStream_t ps = d.proj_stream[q];
     ld = (int64_t)round_up(nvalid, kB);
     RF_TRY(buf.alloc(sizeof(double) * ld * ld));
     const long total = ld * ld;
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(total, 256)), dim3(256), 0, s, buf.as<double>(), (long)ld,
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(total, 256)), dim3(256), 0, ps, buf.as<double>(), (long)ld,
                        (long)nvalid, inner, total);
-    DevBuf& dij = d.scat_ij;
-    DevBuf& dv = d.scat_v;
+    DevBuf& dij = d.scat_ij[q];
+    DevBuf& dv = d.scat_v[q];
     // pageable sources: the copies are staged before these calls return
-    RF_HIP(hipMemcpyAsync(dij.p, ij.data(), sizeof(int) * ij.size(), hipMemcpyHostToDevice, s));
-    RF_HIP(hipMemcpyAsync(dv.p, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_scatter_add, dim3(blocks_for((long)val.size(), 256)), dim3(256), 0, s,
+    RF_HIP(hipMemcpyAsync(dij.p, ij.data(), sizeof(int) * ij.size(), hipMemcpyHostToDevice, ps));
+    RF_HIP(hipMemcpyAsync(dv.p, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, ps));
+    hipLaunchKernelGGL(k_scatter_add, dim3(blocks_for((long)val.size(), 256)), dim3(256), 0, ps,
                        buf.as<double>(), (long)ld, dij.as<int>(), dv.as<double>(), (long)val.size());
     RF_HIP(hipGetLastError());
-    return spd_inverse(buf.as<double>(), ld, nvalid, sub_inner_after ? inner : 0.0, d.gj_u.as<double>(),
-                       d.gj_r.as<double>(), s);
+    return spd_inverse(buf.as<double>(), ld, nvalid, sub_inner_after ? inner : 0.0, d.gj_u[q].as<double>(),
+                       d.gj_r[q].as<double>(), ps);
   };
 
   // L + J
@@ -382,7 +404,7 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
       ij.push_back(a); ij.push_back(b); v.push_back(-1.0);
       ij.push_back(b); ij.push_back(a); v.push_back(-1.0);
     }
-    RF_TRY(build(d.Lp, C, d.ldL, 1.0 / double(C), ij, v, true));
+    RF_TRY(build(0, d.Lp, C, d.ldL, 1.0 / double(C), ij, v, true));
   }
   // G_ll: the diagonal sums A/6 over the cells at a vertex; the entry of the
   // edge (a, b) sums A/12 over its two cells.  Keys are unique, as the
@@ -406,7 +428,7 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
       ij.push_back(a); ij.push_back(b); v.push_back(w);
       ij.push_back(b); ij.push_back(a); v.push_back(w);
     }
-    RF_TRY(build(d.Gll_inv, V, d.ldG, 0.0, ij, v, false));
+    RF_TRY(build(1, d.Gll_inv, V, d.ldG, 0.0, ij, v, false));
   }
   if (need_gtp) {
     std::vector<int> ij;
@@ -435,9 +457,18 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
         v.push_back(val * (2.0 / 18.0));
       }
     }
-    RF_TRY(build(d.Gtp_inv, C, d.ldT, 0.0, ij, v, false));
+    RF_TRY(build(1, d.Gtp_inv, C, d.ldT, 0.0, ij, v, false));
     d.has_gtp = true;
   }
+  for (int q = 0; q < 2; ++q) RF_HIP(hipEventRecord(d.proj_done[q], d.proj_stream[q]));
+  d.proj_pending = true;
+  return RFCMP_OK;
+}
+
+rfcmp_status wait_projectors(rfcmp_mesh m, hipStream_t s) {
+  MeshDev& d = m->d;
+  if (!d.proj_pending) return RFCMP_OK;
+  for (int q = 0; q < 2; ++q) RF_HIP(hipStreamWaitEvent(s, d.proj_done[q], 0));
   return RFCMP_OK;
 }
 

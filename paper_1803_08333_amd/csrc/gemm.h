@@ -10,7 +10,8 @@ struct SplitMatrix {
   int64_t n = 0, rows_pad = 0, kpad = 0;
   bool cplx = false;
   DevBuf planes;
-  rfcmp_status from_c64(const float2* M, int64_t n, int64_t ld, hipStream_t s);
+  // tri > 0: M symmetric, stored as the upper triangle of tri-wide blocks.
+  rfcmp_status from_c64(const float2* M, int64_t n, int64_t ld, int64_t tri, hipStream_t s);
   rfcmp_status from_f64(const double* M, int64_t n, int64_t ld, hipStream_t s);
 };
 

@@ -61,15 +61,18 @@ __device__ inline long frag_offset(long i, long k, long nkc) {
   return (((rb * nkc + kc) * 2 + sub) * 64 + lane) * 8 + e;
 }
 
-// complex64 [n][ld] -> planes [4][rows_pad x kpad], fragment-major
-__global__ void k_split_c64(const float2* __restrict__ M, long n, long ncol, long ld, u16* __restrict__ P,
-                            long rows_pad, long kpad) {
+// complex64 [n][ld] -> planes [4][rows_pad x kpad], fragment-major.  tri > 0:
+// M is symmetric and only its entries with k >= tri floor(i / tri) are
+// stored; the others are read transposed.
+__global__ void k_split_c64(const float2* __restrict__ M, long n, long ncol, long ld, long tri,
+                            u16* __restrict__ P, long rows_pad, long kpad) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= rows_pad * kpad) return;
   const long i = t / kpad, k = t % kpad;
   float re = 0.f, im = 0.f;
   if (i < n && k < ncol) {
-    const float2 v = M[i * ld + k];
+    const bool lower = tri > 0 && k < (i / tri) * tri;
+    const float2 v = lower ? M[k * ld + i] : M[i * ld + k];
     re = v.x;
     im = v.y;
   }
@@ -259,7 +262,7 @@ __global__ void k_gemm_combine(const float* __restrict__ part, int nslice, int n
 
 }  // namespace
 
-rfcmp_status SplitMatrix::from_c64(const float2* M, int64_t n_, int64_t ld, hipStream_t s) {
+rfcmp_status SplitMatrix::from_c64(const float2* M, int64_t n_, int64_t ld, int64_t tri, hipStream_t s) {
   n = n_;
   cplx = true;
   rows_pad = (int64_t)round_up(n, kRowsWG);
@@ -267,7 +270,7 @@ rfcmp_status SplitMatrix::from_c64(const float2* M, int64_t n_, int64_t ld, hipS
   RF_TRY(planes.alloc(sizeof(u16) * 4 * rows_pad * kpad));
   const long tot = rows_pad * kpad;
   hipLaunchKernelGGL(k_split_c64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, (long)n, (long)n,
-                     (long)ld, planes.as<u16>(), (long)rows_pad, (long)kpad);
+                     (long)ld, (long)tri, planes.as<u16>(), (long)rows_pad, (long)kpad);
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
 }
@@ -344,7 +347,16 @@ rfcmp_status gemm_bf16x3(const SplitMatrix& M, bool conj_m, const double2* X, do
 }
 
 MeshDev::MeshDev() = default;
-MeshDev::~MeshDev() = default;
+MeshDev::~MeshDev() {
+  for (int q = 0; q < 2; ++q) {
+    if (proj_stream[q]) {
+      (void)hipStreamSynchronize(proj_stream[q]);
+      (void)hipStreamDestroy(proj_stream[q]);
+    }
+    if (proj_done[q]) (void)hipEventDestroy(proj_done[q]);
+  }
+  if (proj_start) (void)hipEventDestroy(proj_start);
+}
 
 }  // namespace rfcmp
 

@@ -147,8 +147,15 @@ struct MeshDev {
   int64_t npairs = 0;
   DevBuf near;       // int [npairs][2]
   DevBuf pairB;      // complex64 [3C][ldB] cell-pair block scratch of the assembly
-  DevBuf gj_u, gj_r; // FP64 panel buffers of the inverse ([n][64] each, largest n)
-  DevBuf scat_ij, scat_v;  // coordinate lists of the projector matrices
+  // The projector matrices are built on two internal streams (L^+ on the
+  // first, G_ll^-1 and G_tp^-1 on the second), each with its own scratch:
+  // FP64 panel buffers of the inverse and the coordinate lists.  A stream
+  // that uses them first waits for proj_done (wait_projectors).
+  DevBuf gj_u[2], gj_r[2];
+  DevBuf scat_ij[2], scat_v[2];
+  hipStream_t proj_stream[2] = {nullptr, nullptr};  // non-blocking, default priority
+  hipEvent_t proj_start = nullptr, proj_done[2] = {nullptr, nullptr};
+  bool proj_pending = false;
   MeshDev();
   ~MeshDev();
 };
@@ -161,6 +168,13 @@ struct rfcmp_mesh_s {
   int device = -1;
 };
 
+namespace rfcmp {
+// T_A is stored as the upper triangle of kTriBlock x kTriBlock blocks (row m
+// holds columns n >= kTriBlock floor(m / kTriBlock)); the rest of the buffer
+// is never written.
+constexpr int kTriBlock = 256;
+}  // namespace rfcmp
+
 struct rfcmp_op_s {
   rfcmp_op_s();
   ~rfcmp_op_s();
@@ -170,7 +184,7 @@ struct rfcmp_op_s {
   double alpha = 0, beta = 0, gamma = 0;
   double lam[3] = {0, 0, 0};
   int64_t ldA = 0, ldV = 0;  // leading dims (complex entries) of T_A and V
-  rfcmp::DevBuf TA;          // float2 [N][ldA]
+  rfcmp::DevBuf TA;          // float2 [N][ldA], block upper triangle (kTriBlock)
   rfcmp::DevBuf Vb;          // float2 [C][ldV]
   rfcmp::DevBuf work;        // complex128 workspace for work_nrhs right-hand sides
   int work_nrhs = 0;
@@ -194,6 +208,8 @@ rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, i
 
 // dense.hip
 rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s);
+// Make s wait for the projector builds enqueued by mesh_projectors.
+rfcmp_status wait_projectors(rfcmp_mesh m, hipStream_t s);
 // In-place inverse of an SPD matrix, FP64: A [n][n] (n a multiple of 64)
 // holds an SPD matrix in its leading nvalid x nvalid block and the identity
 // in the padding; on return that block holds A^-1 - shift 1 1^T (exactly

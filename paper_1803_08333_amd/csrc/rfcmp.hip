@@ -646,9 +646,9 @@ rfcmp_status ensure_split(rfcmp_op op, hipStream_t s) {
   }
   if (!op->TA16) {
     op->TA16 = std::make_unique<SplitMatrix>();
-    RF_TRY(op->TA16->from_c64(op->TA.as<float2>(), h.N, op->ldA, s));
+    RF_TRY(op->TA16->from_c64(op->TA.as<float2>(), h.N, op->ldA, kTriBlock, s));
     op->V16 = std::make_unique<SplitMatrix>();
-    RF_TRY(op->V16->from_c64(op->Vb.as<float2>(), h.C, op->ldV, s));
+    RF_TRY(op->V16->from_c64(op->Vb.as<float2>(), h.C, op->ldV, 0, s));
   }
   const size_t need = gemm_scratch_bytes(std::max(h.N, std::max(h.C, h.V)), 64);
   if (op->gemm_scratch.bytes < need) RF_TRY(op->gemm_scratch.alloc(need));
@@ -844,7 +844,8 @@ rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt, c
   RF_TRY(op->Vb.alloc(sizeof(float2) * C * op->ldV));
   RF_TRY(ensure_work(op.get(), 4));
   RF_TRY(op->symv_scratch.alloc(symv_scratch_bytes(N, 4) + symv_scratch_bytes(C, 4) + symv_scratch_bytes(V, 4)));
-  RF_TRY(assemble_blocks(op.get(), s));
+  RF_TRY(assemble_blocks(op.get(), s));  // runs beside the projector builds
+  RF_TRY(wait_projectors(m, s));
   op->alpha = std::sqrt(k);
   op->beta = 1.0 / std::sqrt(k);
   op->gamma = k;
@@ -875,13 +876,25 @@ rfcmp_status rfcmp_op_set_scalings(rfcmp_op op, double a, double b, double g) {
   return RFCMP_OK;
 }
 
+// D [n][n] = the symmetric M stored as the upper triangle of tri-wide
+// blocks (entries with k < tri floor(i / tri) read transposed).
+__global__ void k_export_tri(const float2* __restrict__ M, long n, long ld, long tri, float2* __restrict__ D) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const long i = t / n, k = t % n;
+  D[t] = k < (i / tri) * tri ? M[k * ld + i] : M[i * ld + k];
+}
+
 rfcmp_status rfcmp_op_export(rfcmp_op op, void* TA, void* V, void* stream) {
   RF_ARG(op, "op is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t N = op->mesh->h.N, C = op->mesh->h.C;
-  if (TA)
-    RF_HIP(hipMemcpy2DAsync(TA, sizeof(float2) * N, op->TA.p, sizeof(float2) * op->ldA, sizeof(float2) * N, N,
-                            hipMemcpyDeviceToDevice, s));
+  if (TA && N > 0) {
+    const long tot = (long)N * N;
+    hipLaunchKernelGGL(k_export_tri, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, op->TA.as<float2>(),
+                       (long)N, (long)op->ldA, (long)kTriBlock, static_cast<float2*>(TA));
+    RF_HIP(hipGetLastError());
+  }
   if (V)
     RF_HIP(hipMemcpy2DAsync(V, sizeof(float2) * C, op->Vb.p, sizeof(float2) * op->ldV, sizeof(float2) * C, C,
                             hipMemcpyDeviceToDevice, s));
@@ -948,7 +961,10 @@ rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* xv, void* yv,
   RF_ARG(which >= 0 && which <= 6, "unknown projector");
   hipStream_t s = static_cast<hipStream_t>(stream);
   rfcmp_mesh m = op->mesh;
-  if (which == RFCMP_PROJ_GSIGMA) RF_TRY(ensure_mesh_device(m, true, s));
+  if (which == RFCMP_PROJ_GSIGMA) {
+    RF_TRY(ensure_mesh_device(m, true, s));
+    RF_TRY(wait_projectors(m, s));
+  }
   const MeshDev& d = m->d;
   const int64_t N = m->h.N, C = m->h.C, V = m->h.V;
   const int64_t nin = (which == RFCMP_PROJ_LPINV) ? C : (which == RFCMP_PROJ_GLL_INV ? V : N);

@@ -65,43 +65,100 @@ __global__ void k_axpy_sigma(int N, int C, const int* __restrict__ edge_cell, do
 }
 
 // Sum over the workgroup (1024 threads), fixed-order tree; every thread gets the result.
+// Sum over the 1024 threads of a workgroup, returned to every thread: an
+// xor butterfly inside each wave (every lane ends with the same bits), then
+// the 16 wave sums in wave order.  sr, si: LDS of at least 16 doubles.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
 __device__ double2 block_sum_1024(double ar, double ai, double* sr, double* si) {
-  sr[threadIdx.x] = ar;
-  si[threadIdx.x] = ai;
-  __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sr[threadIdx.x] += sr[threadIdx.x + s];
-      si[threadIdx.x] += si[threadIdx.x + s];
-    }
-    __syncthreads();
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if ((threadIdx.x & 63) == 0) {
+    sr[threadIdx.x / 64] = ar;
+    si[threadIdx.x / 64] = ai;
   }
-  const double2 t = make_double2(sr[0], si[0]);
+  __syncthreads();
+  double tr = 0.0, ti = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    tr += sr[q];
+    ti += si[q];
+  }
   __syncthreads();  // sr/si may be reused
-  return t;
+  return make_double2(tr, ti);
 }
 
 // out1[c] = [A_c] (fa a[c] + fb (b[c] - mean b));  out2[c] = f2 (out1[c] - mean out1)
 // (area, a, b, out2 nullable).  One workgroup per right-hand side, so the
-// means need no second launch; each thread revisits only entries it wrote.
+// means need no second launch.  Up to kCombRegs entries per thread are kept
+// in registers between the passes (one round trip to memory); longer rows
+// revisit the entries each thread wrote.
+constexpr int kCombRegs = 8;
 __global__ __launch_bounds__(1024) void k_comb_mean(int C, const double* __restrict__ area, double fa,
                                                     const double2* __restrict__ a, double fb,
                                                     const double2* __restrict__ b, double2* __restrict__ out1,
                                                     double f2, double2* __restrict__ out2) {
-  __shared__ double sr[1024], si[1024];
+  __shared__ double sr[16], si[16];
   const long r = blockIdx.x;
+  const int t = threadIdx.x;
+  if (C <= kCombRegs * 1024) {
+    double2 av[kCombRegs], bv[kCombRegs];
+    double wv[kCombRegs];
+    double br = 0.0, bi = 0.0;
+#pragma unroll
+    for (int u = 0; u < kCombRegs; ++u) {
+      const int i = t + 1024 * u;
+      const bool in = i < C;
+      av[u] = (a && in) ? a[r * C + i] : make_double2(0.0, 0.0);
+      bv[u] = (b && in) ? b[r * C + i] : make_double2(0.0, 0.0);
+      wv[u] = (area && in) ? area[i] : 1.0;
+      br += bv[u].x;
+      bi += bv[u].y;
+    }
+    double2 mb = make_double2(0.0, 0.0);
+    if (b) {
+      const double2 tb = block_sum_1024(br, bi, sr, si);
+      mb = make_double2(tb.x / C, tb.y / C);
+    }
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int u = 0; u < kCombRegs; ++u) {
+      const int i = t + 1024 * u;
+      double2 v = cscale(fa, av[u]);
+      if (b) v = cadd(v, cscale(fb, csub(bv[u], mb)));
+      v = cscale(wv[u], v);
+      av[u] = v;
+      if (i < C) {
+        out1[r * C + i] = v;
+        ar += v.x;
+        ai += v.y;
+      }
+    }
+    if (!out2) return;
+    const double2 to = block_sum_1024(ar, ai, sr, si);
+    const double2 m1 = make_double2(to.x / C, to.y / C);
+#pragma unroll
+    for (int u = 0; u < kCombRegs; ++u) {
+      const int i = t + 1024 * u;
+      if (i < C) out2[r * C + i] = cscale(f2, csub(av[u], m1));
+    }
+    return;
+  }
   double2 mb = make_double2(0.0, 0.0);
   if (b) {
-    double ar = 0.0, ai = 0.0;
-    for (int i = threadIdx.x; i < C; i += 1024) {
-      ar += b[r * C + i].x;
-      ai += b[r * C + i].y;
+    double br = 0.0, bi = 0.0;
+    for (int i = t; i < C; i += 1024) {
+      br += b[r * C + i].x;
+      bi += b[r * C + i].y;
     }
-    const double2 t = block_sum_1024(ar, ai, sr, si);
-    mb = make_double2(t.x / C, t.y / C);
+    const double2 tb = block_sum_1024(br, bi, sr, si);
+    mb = make_double2(tb.x / C, tb.y / C);
   }
   double ar = 0.0, ai = 0.0;
-  for (int i = threadIdx.x; i < C; i += 1024) {
+  for (int i = t; i < C; i += 1024) {
     double2 v = a ? cscale(fa, a[r * C + i]) : make_double2(0.0, 0.0);
     if (b) v = cadd(v, cscale(fb, csub(b[r * C + i], mb)));
     if (area) v = cscale(area[i], v);
@@ -110,9 +167,9 @@ __global__ __launch_bounds__(1024) void k_comb_mean(int C, const double* __restr
     ai += v.y;
   }
   if (!out2) return;
-  const double2 t = block_sum_1024(ar, ai, sr, si);
-  const double2 m1 = make_double2(t.x / C, t.y / C);
-  for (int i = threadIdx.x; i < C; i += 1024) out2[r * C + i] = cscale(f2, csub(out1[r * C + i], m1));
+  const double2 to = block_sum_1024(ar, ai, sr, si);
+  const double2 m1 = make_double2(to.x / C, to.y / C);
+  for (int i = t; i < C; i += 1024) out2[r * C + i] = cscale(f2, csub(out1[r * C + i], m1));
 }
 
 // y = -(ik/alpha)(zA - Sigma s4) + Sigma g6
@@ -211,6 +268,24 @@ __global__ __launch_bounds__(256) void k_dot_final(int nb, const double2* __rest
   if (threadIdx.x == 0) out[r] = make_double2(sr[0], si[0]);
 }
 
+// out[r] = sum_i conj(a[r][i]) b[r][i] in one workgroup per row (rows up
+// to kDotOneBlock entries): strided per thread, then block_sum_1024.
+constexpr long kDotOneBlock = 1L << 16;
+__global__ __launch_bounds__(1024) void k_dot_rows(long n, const double2* __restrict__ a,
+                                                   const double2* __restrict__ b, double2* __restrict__ out) {
+  __shared__ double sr[16], si[16];
+  const long r = blockIdx.x;
+  double ar = 0.0, ai = 0.0;
+#pragma unroll 4
+  for (long i = threadIdx.x; i < n; i += 1024) {
+    const double2 x = a[r * n + i], y = b[r * n + i];
+    ar += x.x * y.x + x.y * y.y;
+    ai += x.x * y.y - x.y * y.x;
+  }
+  const double2 t = block_sum_1024(ar, ai, sr, si);
+  if (threadIdx.x == 0) out[r] = t;
+}
+
 // x[r] *= 1/sqrt(re(nrm2[r]))
 __global__ void k_normalize(long n, const double2* __restrict__ nrm2, const double2* __restrict__ x,
                             double2* __restrict__ out) {
@@ -225,7 +300,7 @@ __global__ void k_normalize(long n, const double2* __restrict__ nrm2, const doub
 // (fixed-order sum: strided per thread, then a tree).
 __global__ __launch_bounds__(1024) void k_normalize_rows(long n, const double2* __restrict__ x,
                                                          double2* __restrict__ out, double2* __restrict__ nrm2) {
-  __shared__ double sr[1024], si[1024];
+  __shared__ double sr[16], si[16];
   const long r = blockIdx.x;
   double a = 0.0;
   for (long i = threadIdx.x; i < n; i += 1024) {
@@ -337,8 +412,12 @@ rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double
 }
 rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, double2* out, int nr,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks, nr), dim3(256), 0, s, (long)n, a, b, part);
-  hipLaunchKernelGGL(k_dot_final, dim3(nr), dim3(256), 0, s, kRedBlocks, part, out);
+  if (n <= kDotOneBlock) {
+    hipLaunchKernelGGL(k_dot_rows, dim3(nr), dim3(1024), 0, s, (long)n, a, b, out);
+  } else {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks, nr), dim3(256), 0, s, (long)n, a, b, part);
+    hipLaunchKernelGGL(k_dot_final, dim3(nr), dim3(256), 0, s, kRedBlocks, part, out);
+  }
   RF_LAUNCH_CHECK();
   return RFCMP_OK;
 }
