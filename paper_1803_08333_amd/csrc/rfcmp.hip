@@ -345,7 +345,10 @@ rfcmp_status batched(int nrhs, int R, int64_t nin, int64_t nout, const double2* 
 //   O_gamma v = P_LH conj(T_A) P_LH T_A P_LH v
 //   O_beta  v = P_Sigma T_Phi^H P_mS_hat T_Phi P_Sigma v
 //             = Sig conj(V) (I - J) diag(A) (I - J) V Sig^T v
-rfcmp_status power_apply(const Dense& D, const Work& W) {
+// project_in: apply P_LH to the alpha and gamma inputs.  Only the random
+// start vector needs it: every later input is the normalised output of the
+// previous step, which ends in P_LH, and P_LH is idempotent (Sigma^T P_LH = 0).
+rfcmp_status power_apply(const Dense& D, const Work& W, bool project_in) {
   rfcmp_op op = D.op;
   hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
@@ -358,8 +361,9 @@ rfcmp_status power_apply(const Dense& D, const Work& W) {
   // beta vector (input stride 0); the second result is not used.
   SymvInput sb = D.sigma_t(vb);
   sb.stride[0] = 0;
-  RF_TRY(D.prod(kLP, false, D.sigma_t(va), W.c[1], 2));
-  RF_TRY(D.pair(kTA, D.proj_lh(va, W.c[1]), W.nB, kV, sb, W.c[7], false, 2));      // T_A P_LH v | V Sig^T v
+  if (project_in) RF_TRY(D.prod(kLP, false, D.sigma_t(va), W.c[1], 2));
+  const SymvInput ta_in = project_in ? D.proj_lh(va, W.c[1]) : Dense::plain(va, N);
+  RF_TRY(D.pair(kTA, ta_in, W.nB, kV, sb, W.c[7], false, 2));                       // T_A P_LH v | V Sig^T v
   RF_TRY(D.pair(kLP, D.sigma_t(W.nB + N), W.c[3], kGLL, D.lambda_t(W.nB), W.v2, false, 1));
   RF_TRY(comb_mean(C, d.area.as<double>(), 0.0, nullptr, 1.0, W.c[7], W.c[8], 1.0, W.c[9], 1, s));
   RF_TRY(power_branch(d, N, V, C, W.v2, W.nB, W.c[3], W.nC, s));                // alpha | gamma branch
@@ -381,7 +385,7 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStr
     RF_HIP(hipMemcpyAsync(W.pw + r * N, start, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
   for (int it = 0; it < steps; ++it) {
     RF_TRY(normalize_rows(N, W.pw, W.pv, W.dout, 3, s));
-    RF_TRY(power_apply(D, W));
+    RF_TRY(power_apply(D, W, it == 0));
   }
   RF_TRY(dot(N, W.pw, W.pw, W.part, W.dout, 3, s));
   double2 nr2[3];
