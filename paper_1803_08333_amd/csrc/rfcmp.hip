@@ -167,13 +167,15 @@ struct Dense {
     return prod(m, conj, plain(x, job(m, SymvInput{}, y).n), y, nr);
   }
   // Two independent products of the same element type in one launch.
+  // nr1 > 0: the second product takes only nr1 of the nr right-hand sides.
   rfcmp_status pair(Mat m0, const SymvInput& in0, double2* y0, Mat m1, const SymvInput& in1, double2* y1,
-                    bool conj, int nr) const {
+                    bool conj, int nr, int nr1 = 0) const {
     if (bf16) {
       RF_TRY(gemm(m0, conj, in0, y0, nr));
-      return gemm(m1, conj, in1, y1, nr);
+      return gemm(m1, conj, in1, y1, nr1 > 0 ? nr1 : nr);
     }
-    const SymvJob j[2] = {job(m0, in0, y0), job(m1, in1, y1)};
+    SymvJob j[2] = {job(m0, in0, y0), job(m1, in1, y1)};
+    j[1].nrhs = nr1;
     static const char* pair_tag[] = {"cmatvec_ta+v", "dmatvec_lp+gll", "dmatvec_lp+gtp"};
     if (complex_matrix(m0))
       return csymv_jobs(j, 2, conj, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, pair_tag[0]);
@@ -357,19 +359,15 @@ rfcmp_status power_apply(const Dense& D, const Work& W, bool project_in) {
   double2* va = W.pv;
   double2* vb = W.pv + 2 * N;
   // The beta chain's two V products ride along with the two-column T_A
-  // passes of alpha and gamma: V takes two columns too, both reading the
-  // beta vector (input stride 0); the second result is not used.
-  SymvInput sb = D.sigma_t(vb);
-  sb.stride[0] = 0;
+  // passes of alpha and gamma, with one column of their own.
+  const SymvInput sb = D.sigma_t(vb);
   if (project_in) RF_TRY(D.prod(kLP, false, D.sigma_t(va), W.c[1], 2));
   const SymvInput ta_in = project_in ? D.proj_lh(va, W.c[1]) : Dense::plain(va, N);
-  RF_TRY(D.pair(kTA, ta_in, W.nB, kV, sb, W.c[7], false, 2));                       // T_A P_LH v | V Sig^T v
+  RF_TRY(D.pair(kTA, ta_in, W.nB, kV, sb, W.c[7], false, 2, 1));                    // T_A P_LH v | V Sig^T v
   RF_TRY(D.pair(kLP, D.sigma_t(W.nB + N), W.c[3], kGLL, D.lambda_t(W.nB), W.v2, false, 1));
   RF_TRY(comb_mean(C, d.area.as<double>(), 0.0, nullptr, 1.0, W.c[7], W.c[8], 1.0, W.c[9], 1, s));
   RF_TRY(power_branch(d, N, V, C, W.v2, W.nB, W.c[3], W.nC, s));                // alpha | gamma branch
-  SymvInput sw = Dense::plain(W.c[9], C);
-  sw.stride[0] = 0;
-  RF_TRY(D.pair(kTA, Dense::plain(W.nC, N), W.nD, kV, sw, W.c[10], true, 2));
+  RF_TRY(D.pair(kTA, Dense::plain(W.nC, N), W.nD, kV, Dense::plain(W.c[9], C), W.c[10], true, 2, 1));
   RF_TRY(D.prod(kLP, false, D.sigma_t(W.nD), W.c[5], 2));
   RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nD, -1.0, W.c[5], W.pw, 2, s));
   RF_TRY(axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[10], W.pw + 2 * N, 1, s));

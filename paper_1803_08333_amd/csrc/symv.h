@@ -34,6 +34,7 @@ struct SymvJob {
   int64_t n = 0, ld = 0;
   SymvInput in;
   double2* y = nullptr;  // [nrhs][n]
+  int nrhs = 0;          // job 1 of a pair: 1 of 2 right-hand sides, or 0 = all
 };
 
 // Bytes of scratch one job of size n needs (partial sums, up to 4

@@ -316,9 +316,11 @@ __device__ void symv_block(const char* __restrict__ strip, int n, int ldp, int P
 }
 
 // Partial buffer layout: part[((K * nsb + L) * NR + r) * S + i], complex128.
-template <class T, int S, int NR, bool CONJ>
+// Job 0 has NR0 right-hand sides, job 1 NR1.
+template <class T, int S, int NR0, int NR1, bool CONJ>
 __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
   typedef typename T::Pair Pair;
+  constexpr int NRM = NR0 > NR1 ? NR0 : NR1;
   const int job = (int)blockIdx.x < args.nblk0 ? 0 : 1;
   const JobArg& ja = args.j[job];
   const int n = ja.n, nsb = ja.nsb;
@@ -331,12 +333,22 @@ __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
   }
   const int Q = P + rem;
   __shared__ Pair tile[rows_sub<S>()][S / 2 + 1];
-  __shared__ double2 xs[2][NR][S];  // x_P (rows), x_Q (columns)
+  __shared__ double2 xs[2][NRM][S];  // x_P (rows), x_Q (columns)
   const char* strip = static_cast<const char*>(ja.M) + (size_t)P * S * (size_t)ja.ldp * 16;
-  if ((Q + 1) * S <= n)  // then (P + 1) S <= n as well
-    symv_block<T, S, NR, CONJ, false>(strip, n, (int)ja.ldp, P, Q, ja.in, ja.part, nsb, tile, xs);
-  else
-    symv_block<T, S, NR, CONJ, true>(strip, n, (int)ja.ldp, P, Q, ja.in, ja.part, nsb, tile, xs);
+  const bool edge = (Q + 1) * S > n;  // else (P + 1) S <= n as well
+  if (job == 0 || NR0 == NR1) {
+    auto x0 = reinterpret_cast<double2(*)[NR0][S]>(&xs[0][0][0]);
+    if (!edge)
+      symv_block<T, S, NR0, CONJ, false>(strip, n, (int)ja.ldp, P, Q, ja.in, ja.part, nsb, tile, x0);
+    else
+      symv_block<T, S, NR0, CONJ, true>(strip, n, (int)ja.ldp, P, Q, ja.in, ja.part, nsb, tile, x0);
+  } else {
+    auto x1 = reinterpret_cast<double2(*)[NR1][S]>(&xs[0][0][0]);
+    if (!edge)
+      symv_block<T, S, NR1, CONJ, false>(strip, n, (int)ja.ldp, P, Q, ja.in, ja.part, nsb, tile, x1);
+    else
+      symv_block<T, S, NR1, CONJ, true>(strip, n, (int)ja.ldp, P, Q, ja.in, ja.part, nsb, tile, x1);
+  }
 }
 
 // y[r][K S + i] = sum over L (in order) of part[K][L][r][i].  Workgroup
@@ -346,14 +358,16 @@ __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
 // job 1.
 template <int S>
 constexpr int red_parts() { return 1024 / S; }
-template <int S, int NR>
+template <int S, int NR0, int NR1>
 __global__ __launch_bounds__(1024) void k_symv_reduce(const JobsArg args) {
   constexpr int kRedParts = red_parts<S>();
   __shared__ double2 q8[kRedParts][S];
   const int job = (int)blockIdx.x < args.nsb0 ? 0 : 1;
   const JobArg& ja = args.j[job];
   const int n = ja.n, nsb = ja.nsb;
+  const int NR = job ? NR1 : NR0;
   const int K = (int)blockIdx.x - (job ? args.nsb0 : 0), r = blockIdx.y;
+  if (r >= NR) return;
   const int i = threadIdx.x % S, qt = threadIdx.x / S;
   const int per = (nsb + kRedParts - 1) / kRedParts;
   const int L0 = qt * per;
@@ -389,14 +403,15 @@ constexpr int kSmax = 256, kSmin = 128;
 
 // The product kernel is timed under `tag` (one right-hand side) or
 // "<tag>_nr<k>" (k right-hand sides), the slot sums under "symv_reduce".
-template <class T, int S, int NR, bool CONJ>
+template <class T, int S, int NR0, int NR1, bool CONJ>
 void launch(const JobsArg& a, int nblk, int nsbsum, hipStream_t s, const char* tag) {
   {
-    ProfScope prof(NR == 1 ? tag : profile_tag_suffix(tag, NR), s);
-    hipLaunchKernelGGL((k_symv<T, S, NR, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s, a);
+    ProfScope prof(NR0 == 1 ? tag : profile_tag_suffix(tag, NR0), s);
+    hipLaunchKernelGGL((k_symv<T, S, NR0, NR1, CONJ>), dim3((unsigned)nblk), dim3(kThreads), 0, s, a);
   }
   ProfScope prof("symv_reduce", s);
-  hipLaunchKernelGGL((k_symv_reduce<S, NR>), dim3((unsigned)nsbsum, NR), dim3(1024), 0, s, a);
+  constexpr int NRM = NR0 > NR1 ? NR0 : NR1;
+  hipLaunchKernelGGL((k_symv_reduce<S, NR0, NR1>), dim3((unsigned)nsbsum, NRM), dim3(1024), 0, s, a);
 }
 
 // Block size: 256 x 256 blocks (longer streams per workgroup, fewer slots)
@@ -418,13 +433,23 @@ rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, s
     return RFCMP_E_ARG;
   }
   if (nrhs <= 0) return RFCMP_OK;
+  // right-hand sides of each job: nrhs, or fewer for job 1 (a product riding
+  // along with fewer columns; then nrhs <= kMaxNR)
+  int jn[2] = {nrhs, nrhs};
+  if (njobs == 2 && jobs[1].nrhs > 0 && jobs[1].nrhs < nrhs) {
+    if (nrhs > kMaxNR || !(nrhs == 2 && jobs[1].nrhs == 1)) {
+      set_error("symv: job 1 with %d of %d right-hand sides is not supported", jobs[1].nrhs, nrhs);
+      return RFCMP_E_ARG;
+    }
+    jn[1] = jobs[1].nrhs;
+  }
   size_t need = 0;
   for (int q = 0; q < njobs; ++q) {
     if (jobs[q].n <= 0 || jobs[q].ld % 2 != 0 || jobs[q].ld < jobs[q].n) {
       set_error("symv: job %d has n = %lld, ld = %lld", q, (long long)jobs[q].n, (long long)jobs[q].ld);
       return RFCMP_E_ARG;
     }
-    need += symv_scratch_bytes(jobs[q].n, std::min(nrhs, kMaxNR));
+    need += symv_scratch_bytes(jobs[q].n, std::min(jn[q], kMaxNR));
   }
   if (need > scratch_bytes) {
     set_error("symv: needs %zu bytes of scratch, %zu given", need, scratch_bytes);
@@ -438,6 +463,7 @@ rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, s
   const int S = blocks_big >= kMinBlocks256 ? kSmax : kSmin;
   for (int r0 = 0; r0 < nrhs; r0 += kMaxNR) {
     const int nr = std::min(kMaxNR, nrhs - r0);
+    const bool split = jn[1] != nrhs;  // job 1: one column (nr == 2 here)
     JobsArg a{};
     char* sp = static_cast<char*>(scratch);
     int nblk = 0, nsbsum = 0;
@@ -451,7 +477,7 @@ rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, s
       ja.in = shift_input(jb.in, r0);
       ja.part = reinterpret_cast<double2*>(sp);
       ja.y = jb.y + (long)r0 * jb.n;
-      sp += symv_scratch_bytes(jb.n, nr);
+      sp += symv_scratch_bytes(jb.n, q == 1 && split ? 1 : nr);
       if (q == 0) {
         a.nblk0 = ja.nsb * (ja.nsb + 1) / 2;
         a.nsb0 = ja.nsb;
@@ -460,11 +486,15 @@ rfcmp_status symv_any(const SymvJob* jobs, int njobs, int nrhs, void* scratch, s
       nsbsum += ja.nsb;
     }
 #define RF_SYMV_NR(SV)                                                          \
-  switch (nr) {                                                                 \
-    case 1: launch<T, SV, 1, CONJ>(a, nblk, nsbsum, s, tag); break;             \
-    case 2: launch<T, SV, 2, CONJ>(a, nblk, nsbsum, s, tag); break;             \
-    case 3: launch<T, SV, 3, CONJ>(a, nblk, nsbsum, s, tag); break;             \
-    default: launch<T, SV, 4, CONJ>(a, nblk, nsbsum, s, tag); break;            \
+  if (split) {                                                                  \
+    launch<T, SV, 2, 1, CONJ>(a, nblk, nsbsum, s, tag);                         \
+  } else {                                                                      \
+    switch (nr) {                                                               \
+      case 1: launch<T, SV, 1, 1, CONJ>(a, nblk, nsbsum, s, tag); break;        \
+      case 2: launch<T, SV, 2, 2, CONJ>(a, nblk, nsbsum, s, tag); break;        \
+      case 3: launch<T, SV, 3, 3, CONJ>(a, nblk, nsbsum, s, tag); break;        \
+      default: launch<T, SV, 4, 4, CONJ>(a, nblk, nsbsum, s, tag); break;       \
+    }                                                                           \
   }
     if (S == kSmax) {
       RF_SYMV_NR(kSmax)
