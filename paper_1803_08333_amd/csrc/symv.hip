@@ -228,7 +228,10 @@ __device__ void symv_block(const char* __restrict__ strip, int n, int ldp, int P
   for (int t = tid; t < 2 * NR * S; t += kThreads) {
     const int side = t / (NR * S), r = (t / S) % NR, i = t % S;
     const int g = (side == 0 ? P : Q) * S + i;
-    xs[side][r][i] = (!EDGE || g < n) ? input_entry(in, r, g) : make_double2(0.0, 0.0);
+    // x_Q is stored even columns first, then odd ones, so that the row sums
+    // (neighbouring threads, neighbouring pairs) read it without bank conflicts
+    const int slot = side ? (i & 1) * (S / 2) + (i >> 1) : i;
+    xs[side][r][slot] = (!EDGE || g < n) ? input_entry(in, r, g) : make_double2(0.0, 0.0);
   }
 
   double cr[2][NR], ci[2][NR];  // transposed sums of the two columns
@@ -268,7 +271,7 @@ __device__ void symv_block(const char* __restrict__ strip, int n, int ldp, int P
         double ar, ai;                                                                             \
         T::template entry<CONJ>(v, e, ar, ai);                                                     \
         _Pragma("unroll") for (int r = 0; r < NR; ++r) {                                           \
-          const double2 xv = xs[1][r][2 * pc + e];                                                 \
+          const double2 xv = xs[1][r][e * (S / 2) + pc];                                           \
           rr[r] = fma(ar, xv.x, fma(-ai, xv.y, rr[r]));                                            \
           ri[r] = fma(ar, xv.y, fma(ai, xv.x, ri[r]));                                             \
         }                                                                                          \
