@@ -45,6 +45,10 @@ constexpr int kThreads = 256;
 // rows per sub-tile for block size S: the sub-tile is 4 KB of pairs per 256 threads
 template <int S>
 constexpr int rows_sub() { return S == 128 ? 32 : 16; }
+// Pairs per LDS tile row: a 16-lane pass of the row sums covers 256 / S rows
+// (two at S = 128), so rows are padded to start 128 bytes apart in the banks.
+template <int S>
+constexpr int tile_ld() { return S / 2 + 8; }
 constexpr int kMaxNR = 4;      // right-hand sides per pass
 
 // Entry e (0, 1) of a 16-byte column pair, widened to FP64 (re, im).
@@ -189,7 +193,7 @@ __device__ inline double sum_lanes(double v) {
 template <class T, int S, int NR, bool CONJ, bool EDGE>
 __device__ void symv_block(const char* __restrict__ strip, int n, int ldp, int P, int Q,
                            const SymvInput& in, double2* __restrict__ part, int nsb,
-                           typename T::Pair (*tile)[S / 2 + 1], double2 (*xs)[NR][S]) {
+                           typename T::Pair (*tile)[tile_ld<S>()], double2 (*xs)[NR][S]) {
   typedef typename T::Pair Pair;
   constexpr int kRowsSub = rows_sub<S>();
   constexpr int PP = S / 2;                       // column pairs per row
@@ -299,7 +303,7 @@ __device__ void symv_block(const char* __restrict__ strip, int n, int ldp, int P
     // reduce the transposed sums over the G row groups through LDS
     __syncthreads();
     double2* red = reinterpret_cast<double2*>(&tile[0][0]);  // [G][S][NR]
-    static_assert(sizeof(double2) * G * S * NR <= sizeof(Pair) * kRowsSub * (PP + 1), "reduction fits the tile");
+    static_assert(sizeof(double2) * G * S * NR <= sizeof(Pair) * kRowsSub * tile_ld<S>(), "reduction fits the tile");
 #pragma unroll
     for (int e = 0; e < 2; ++e)
 #pragma unroll
@@ -335,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_symv(const JobsArg args) {
     ++P;
   }
   const int Q = P + rem;
-  __shared__ Pair tile[rows_sub<S>()][S / 2 + 1];
+  __shared__ Pair tile[rows_sub<S>()][tile_ld<S>()];
   __shared__ double2 xs[2][NRM][S];  // x_P (rows), x_Q (columns)
   const char* strip = static_cast<const char*>(ja.M) + (size_t)P * S * (size_t)ja.ldp * 16;
   const bool edge = (Q + 1) * S > n;  // else (P + 1) S <= n as well
