@@ -496,10 +496,15 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   DevBuf& B = d.pairB;
   if (d.near_factor != op->opt.near_factor) {
     std::vector<int32_t> pairs;
-    near_pairs(h, op->opt.near_factor, pairs);
+    if (m->near_async.valid() && m->near_async_factor == op->opt.near_factor)
+      pairs = m->near_async.get();  // started at mesh creation
+    else
+      near_pairs(h, op->opt.near_factor, pairs);
     RF_TRY(d.near.alloc(sizeof(int) * std::max<size_t>(pairs.size(), 2)));
-    RF_HIP(hipMemcpy(d.near.p, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice));
-    d.npairs = (int64_t)pairs.size() / 2;
+    d.near_host = std::move(pairs);  // the source stays alive with the mesh
+    RF_HIP(hipMemcpyAsync(d.near.p, d.near_host.data(), sizeof(int) * d.near_host.size(), hipMemcpyHostToDevice,
+                          s));
+    d.npairs = (int64_t)d.near_host.size() / 2;
     d.near_factor = op->opt.near_factor;
   }
   const long npairs = (long)d.npairs;

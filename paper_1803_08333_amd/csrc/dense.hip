@@ -300,31 +300,83 @@ __global__ void k_scatter_add(double* __restrict__ A, long ld, const int* __rest
   if (t >= nnz) return;
   A[(long)ij[2 * t] * ld + ij[2 * t + 1]] += v[t];
 }
+// L + J on top of the fill (1/C in the valid block): L = Sigma^T Sigma has 3
+// on the diagonal and -1 at the two cells of every edge (two cells share at
+// most one edge, so every entry has one writer).
+__global__ void k_build_lap(double* __restrict__ A, long ld, int C, int N, const int* __restrict__ edge_cell) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < C) A[(long)t * ld + t] += 3.0;
+  if (t < N) {
+    const long a = edge_cell[2 * t], b = edge_cell[2 * t + 1];
+    A[a * ld + b] -= 1.0;
+    A[b * ld + a] -= 1.0;
+  }
+}
+// G_ll (P1 mass matrix) on a zero fill: the entry of edge (a, b) is the sum of
+// A/12 over its two cells; the diagonal entry of a vertex sums A/6 over its
+// cells, which is the sum of the edge entries over the edges at the vertex
+// (each cell there has two of them).
+__global__ void k_build_gll(double* __restrict__ A, long ld, int V, int N, const int* __restrict__ ve_ptr,
+                            const int* __restrict__ ve_idx, const int* __restrict__ edge_vtx,
+                            const int* __restrict__ edge_cell, const double* __restrict__ area) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < V) {
+    double dsum = 0.0;
+    for (int q = ve_ptr[t]; q < ve_ptr[t + 1]; ++q) {
+      const int e = ve_idx[q];
+      dsum += (area[edge_cell[2 * e]] + area[edge_cell[2 * e + 1]]) / 12.0;
+    }
+    A[(long)t * ld + t] = dsum;
+  }
+  if (t < N) {
+    const long a = edge_vtx[2 * t], b = edge_vtx[2 * t + 1];
+    const double w = (area[edge_cell[2 * t]] + area[edge_cell[2 * t + 1]]) / 12.0;
+    A[a * ld + b] = w;
+    A[b * ld + a] = w;
+  }
+}
 inline unsigned blocks_for(long n, int per) { return unsigned((n + per - 1) / per); }
 
 }  // namespace
 
-rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, double* ubuf, double* rbuf,
-                         hipStream_t s) {
-  if (n % kB != 0 || nvalid > n || nvalid < 0) {
-    set_error("spd_inverse: n=%lld (valid %lld) not a multiple of %d", (long long)n, (long long)nvalid, kB);
-    return RFCMP_E_ARG;
-  }
-  const int nb = int(n / kB);
-  ProfScope prof("spd_inverse", s);
-  const unsigned ntiles = unsigned((long)nb * (nb + 1) / 2);
-  hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, A, (long)n, 0);
-  for (int K = 0; K < nb; ++K) {
-    if (nb > 1) {
-      hipLaunchKernelGGL(k_gj_panels, dim3(nb, 4), dim3(256), 0, s, A, (long)n, K, ubuf, rbuf);
-      hipLaunchKernelGGL(k_gj_update, dim3(ntiles), dim3(256), 0, s, A, (long)n, nb, K, ubuf, rbuf);
+rfcmp_status spd_inverse_many(const SpdInverseJob* jobs, int njobs) {
+  int steps = 0;
+  for (int q = 0; q < njobs; ++q) {
+    const SpdInverseJob& j = jobs[q];
+    if (j.n % kB != 0 || j.nvalid > j.n || j.nvalid < 0) {
+      set_error("spd_inverse: n=%lld (valid %lld) not a multiple of %d", (long long)j.n, (long long)j.nvalid, kB);
+      return RFCMP_E_ARG;
     }
+    steps = std::max(steps, int(j.n / kB));
   }
-  const long total = (long)n * n;
-  hipLaunchKernelGGL(k_gj_finish, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, A, (long)n,
-                     (long)nvalid, shift);
+  // the jobs' launches interleaved step by step, so that every stream has
+  // work queued from the start
+  for (int q = 0; q < njobs; ++q)
+    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, jobs[q].s, jobs[q].A, (long)jobs[q].n, 0);
+  for (int K = 0; K < steps; ++K)
+    for (int q = 0; q < njobs; ++q) {
+      const SpdInverseJob& j = jobs[q];
+      const int nb = int(j.n / kB);
+      if (K >= nb || nb == 1) continue;
+      const unsigned ntiles = unsigned((long)nb * (nb + 1) / 2);
+      hipLaunchKernelGGL(k_gj_panels, dim3(nb, 4), dim3(256), 0, j.s, j.A, (long)j.n, K, j.ubuf, j.rbuf);
+      hipLaunchKernelGGL(k_gj_update, dim3(ntiles), dim3(256), 0, j.s, j.A, (long)j.n, nb, K, j.ubuf, j.rbuf);
+    }
+  for (int q = 0; q < njobs; ++q) {
+    const SpdInverseJob& j = jobs[q];
+    const long total = (long)j.n * j.n;
+    hipLaunchKernelGGL(k_gj_finish, dim3(unsigned((total + 255) / 256)), dim3(256), 0, j.s, j.A, (long)j.n,
+                       (long)j.nvalid, j.shift);
+  }
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
+}
+
+rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, double* ubuf, double* rbuf,
+                         hipStream_t s) {
+  ProfScope prof("spd_inverse", s);
+  const SpdInverseJob j{A, n, nvalid, shift, ubuf, rbuf, s};
+  return spd_inverse_many(&j, 1);
 }
 
 // Build L^+, G_ll^-1 (and G_tp^-1) of a mesh on the device, in FP64.
@@ -333,14 +385,16 @@ rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, dou
 //   G_ll (P1 mass): A/6 on the diagonal, A/12 off it, per cell.
 //   G_tp: closed form of Sec. 3 (mixed dual-hat / cell Gram matrix).
 rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
+  if (need_gtp) build_cell_nb(m->h);
   const MeshHost& h = m->h;
   MeshDev& d = m->d;
   const int64_t C = h.C, V = h.V, N = h.N;
 
   // Two internal streams: L^+ on the first, G_ll^-1 (then G_tp^-1) on the
-  // second, both after the work already enqueued on s.  Scratch is kept with
-  // the mesh per stream, sized once, so that nothing here is released (a
-  // release waits for the device) and the host goes on while the inverses run.
+  // second, both after the work already enqueued on s (the mesh upload).
+  // Scratch is kept with the mesh per stream, sized once, so that nothing
+  // here is released (a release waits for the device) and the host goes on
+  // while the inverses run.
   for (int q = 0; q < 2; ++q) {
     if (!d.proj_stream[q]) {
       RF_HIP(hipStreamCreateWithFlags(&d.proj_stream[q], hipStreamNonBlocking));
@@ -350,22 +404,18 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
   if (!d.proj_start) RF_HIP(hipEventCreateWithFlags(&d.proj_start, hipEventDisableTiming));
   RF_HIP(hipEventRecord(d.proj_start, s));
   {
-    const int64_t n0 = (int64_t)round_up(C, kB);
-    const int64_t n1 = (int64_t)round_up(need_gtp ? std::max(C, V) : V, kB);
-    const size_t nnz0 = (size_t)(C + 2 * N);
-    const size_t nnz1 = (size_t)std::max<int64_t>(V + 2 * N, need_gtp ? h.cell_nb_ptr[C] : 0);
-    const int64_t nn[2] = {n0, n1};
-    const size_t nz[2] = {nnz0, nnz1};
+    const int64_t nn[2] = {(int64_t)round_up(C, kB), (int64_t)round_up(need_gtp ? std::max(C, V) : V, kB)};
     for (int q = 0; q < 2; ++q) {
       RF_HIP(hipStreamWaitEvent(d.proj_stream[q], d.proj_start, 0));
       if (d.gj_u[q].bytes < sizeof(double) * nn[q] * kB) {
         RF_TRY(d.gj_u[q].alloc(sizeof(double) * nn[q] * kB));
         RF_TRY(d.gj_r[q].alloc(sizeof(double) * nn[q] * kB));
       }
-      if (d.scat_v[q].bytes < sizeof(double) * nz[q]) {
-        RF_TRY(d.scat_ij[q].alloc(sizeof(int) * 2 * nz[q]));
-        RF_TRY(d.scat_v[q].alloc(sizeof(double) * nz[q]));
-      }
+    }
+    const size_t nnz = need_gtp ? (size_t)h.cell_nb_ptr[C] : 0;  // G_tp's coordinate list
+    if (nnz > 0 && d.scat_v.bytes < sizeof(double) * nnz) {
+      RF_TRY(d.scat_ij.alloc(sizeof(int) * 2 * nnz));
+      RF_TRY(d.scat_v.alloc(sizeof(double) * nnz));
     }
   }
   auto build = [&](int q, DevBuf& buf, int64_t nvalid, int64_t& ld, double inner,
@@ -377,8 +427,8 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
     const long total = ld * ld;
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(total, 256)), dim3(256), 0, ps, buf.as<double>(), (long)ld,
                        (long)nvalid, inner, total);
-    DevBuf& dij = d.scat_ij[q];
-    DevBuf& dv = d.scat_v[q];
+    DevBuf& dij = d.scat_ij;
+    DevBuf& dv = d.scat_v;
     // pageable sources: the copies are staged before these calls return
     RF_HIP(hipMemcpyAsync(dij.p, ij.data(), sizeof(int) * ij.size(), hipMemcpyHostToDevice, ps));
     RF_HIP(hipMemcpyAsync(dv.p, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, ps));
@@ -389,46 +439,29 @@ rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
                        d.gj_r[q].as<double>(), ps);
   };
 
-  // L + J
+  // L + J and G_ll are formed on the device from the uploaded mesh arrays
+  auto fill = [&](int q, DevBuf& buf, int64_t nvalid, int64_t& ld, double inner) -> rfcmp_status {
+    ld = (int64_t)round_up(nvalid, kB);
+    RF_TRY(buf.alloc(sizeof(double) * ld * ld));
+    const long total = ld * ld;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(total, 256)), dim3(256), 0, d.proj_stream[q], buf.as<double>(),
+                       (long)ld, (long)nvalid, inner, total);
+    return RFCMP_OK;
+  };
+  RF_TRY(fill(0, d.Lp, C, d.ldL, 1.0 / double(C)));
+  hipLaunchKernelGGL(k_build_lap, dim3(blocks_for(std::max(C, N), 256)), dim3(256), 0, d.proj_stream[0],
+                     d.Lp.as<double>(), (long)d.ldL, (int)C, (int)N, d.edge_cell.as<int>());
+  RF_TRY(fill(1, d.Gll_inv, V, d.ldG, 0.0));
+  hipLaunchKernelGGL(k_build_gll, dim3(blocks_for(std::max(V, N), 256)), dim3(256), 0, d.proj_stream[1],
+                     d.Gll_inv.as<double>(), (long)d.ldG, (int)V, (int)N, d.ve_ptr.as<int>(), d.ve_idx.as<int>(),
+                     d.edge_vtx.as<int>(), d.edge_cell.as<int>(), d.area.as<double>());
+  RF_HIP(hipGetLastError());
   {
-    std::vector<int> ij;
-    std::vector<double> v;
-    ij.reserve(2 * (C + 2 * N));
-    for (int64_t c = 0; c < C; ++c) {
-      ij.push_back(int(c));
-      ij.push_back(int(c));
-      v.push_back(3.0);
-    }
-    for (int64_t n = 0; n < N; ++n) {
-      const int a = h.edge_cell[2 * n], b = h.edge_cell[2 * n + 1];
-      ij.push_back(a); ij.push_back(b); v.push_back(-1.0);
-      ij.push_back(b); ij.push_back(a); v.push_back(-1.0);
-    }
-    RF_TRY(build(0, d.Lp, C, d.ldL, 1.0 / double(C), ij, v, true));
-  }
-  // G_ll: the diagonal sums A/6 over the cells at a vertex; the entry of the
-  // edge (a, b) sums A/12 over its two cells.  Keys are unique, as the
-  // scatter needs.
-  {
-    std::vector<double> diag(V, 0.0);
-    for (int64_t c = 0; c < C; ++c)
-      for (int i = 0; i < 3; ++i) diag[h.tri[3 * c + i]] += h.area[c] / 6.0;
-    std::vector<int> ij;
-    std::vector<double> v;
-    ij.reserve(2 * (V + 2 * N));
-    v.reserve(V + 2 * N);
-    for (int64_t a = 0; a < V; ++a) {
-      ij.push_back(int(a));
-      ij.push_back(int(a));
-      v.push_back(diag[a]);
-    }
-    for (int64_t n = 0; n < N; ++n) {
-      const int a = h.edge_vtx[2 * n], b = h.edge_vtx[2 * n + 1];
-      const double w = (h.area[h.edge_cell[2 * n]] + h.area[h.edge_cell[2 * n + 1]]) / 12.0;
-      ij.push_back(a); ij.push_back(b); v.push_back(w);
-      ij.push_back(b); ij.push_back(a); v.push_back(w);
-    }
-    RF_TRY(build(1, d.Gll_inv, V, d.ldG, 0.0, ij, v, false));
+    const SpdInverseJob jobs[2] = {
+        {d.Lp.as<double>(), d.ldL, C, 1.0 / double(C), d.gj_u[0].as<double>(), d.gj_r[0].as<double>(),
+         d.proj_stream[0]},
+        {d.Gll_inv.as<double>(), d.ldG, V, 0.0, d.gj_u[1].as<double>(), d.gj_r[1].as<double>(), d.proj_stream[1]}};
+    RF_TRY(spd_inverse_many(jobs, 2));
   }
   if (need_gtp) {
     std::vector<int> ij;

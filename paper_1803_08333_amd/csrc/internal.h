@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <future>
 #include <memory>
 #include <string>
 #include <vector>
@@ -117,7 +118,7 @@ struct MeshHost {
   std::vector<int32_t> vtx_edge_ptr;  // [V+1] CSR: edges at each vertex
   std::vector<int32_t> vtx_edge_idx;  // [2N]
   std::vector<int8_t> vtx_edge_sgn;   // [2N] Lambda[edge, vertex]
-  std::vector<int32_t> cell_nb_ptr;   // [C+1] CSR: cells sharing a vertex (incl. self)
+  std::vector<int32_t> cell_nb_ptr;   // [C+1] CSR: cells sharing a vertex (incl. self); build_cell_nb
   std::vector<int32_t> cell_nb_idx;
 };
 
@@ -146,13 +147,14 @@ struct MeshDev {
   double near_factor = -1.0;  // factor of the cached near-pair list
   int64_t npairs = 0;
   DevBuf near;       // int [npairs][2]
+  std::vector<int32_t> near_host;  // its host copy
   DevBuf pairB;      // complex64 [3C][ldB] cell-pair block scratch of the assembly
   // The projector matrices are built on two internal streams (L^+ on the
-  // first, G_ll^-1 and G_tp^-1 on the second), each with its own scratch:
-  // FP64 panel buffers of the inverse and the coordinate lists.  A stream
-  // that uses them first waits for proj_done (wait_projectors).
+  // first, G_ll^-1 and G_tp^-1 on the second), each with its own FP64 panel
+  // buffers for the inverse.  A stream that uses them first waits for
+  // proj_done (wait_projectors).
   DevBuf gj_u[2], gj_r[2];
-  DevBuf scat_ij[2], scat_v[2];
+  DevBuf scat_ij, scat_v;  // coordinate list of G_tp (second stream)
   hipStream_t proj_stream[2] = {nullptr, nullptr};  // non-blocking, default priority
   hipEvent_t proj_start = nullptr, proj_done[2] = {nullptr, nullptr};
   bool proj_pending = false;
@@ -166,6 +168,11 @@ struct rfcmp_mesh_s {
   rfcmp::MeshHost h;
   rfcmp::MeshDev d;
   int device = -1;
+  // near-pair list for near_async_factor, computed on a host thread from
+  // mesh creation on (declared last: its destructor waits for the thread
+  // before h goes)
+  double near_async_factor = -1.0;
+  std::future<std::vector<int32_t>> near_async;
 };
 
 namespace rfcmp {
@@ -199,6 +206,7 @@ namespace rfcmp {
 // mesh.cpp
 rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, int64_t nc, MeshHost& h);
 void near_pairs(const MeshHost& h, double factor, std::vector<int32_t>& out);
+void build_cell_nb(MeshHost& h);
 
 // assemble.hip
 rfcmp_status mesh_upload(rfcmp_mesh m, hipStream_t s);
@@ -217,5 +225,14 @@ rfcmp_status wait_projectors(rfcmp_mesh m, hipStream_t s);
 // n * 64 doubles each.  Enqueued on s; does not wait.
 rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, double* ubuf, double* rbuf,
                          hipStream_t s);
+// Several such inverses, each on its own stream, their launches interleaved.
+struct SpdInverseJob {
+  double* A;
+  int64_t n, nvalid;
+  double shift;
+  double *ubuf, *rbuf;
+  hipStream_t s;
+};
+rfcmp_status spd_inverse_many(const SpdInverseJob* jobs, int njobs);
 
 }  // namespace rfcmp

@@ -8,6 +8,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <system_error>
+#include <thread>
 
 #include "internal.h"
 
@@ -69,9 +71,37 @@ rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, 
       int32_t lo = std::min(a, b), hi = std::max(a, b);
       he[3 * c + i] = Half{int64_t(lo) * nv + hi, int32_t(c), int8_t(i), int8_t(a < b)};
     }
-  std::sort(he.begin(), he.end(), [](const Half& x, const Half& y) {
-    return x.key < y.key || (x.key == y.key && x.forward > y.forward);
-  });
+  // order by (key, forward first): a counting sort on the lower vertex, then
+  // an insertion sort inside each vertex's few half-edges (the same order
+  // as a comparison sort on that key)
+  {
+    std::vector<int32_t> off(nv + 1, 0);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int i = 0; i < 3; ++i) {
+        const int32_t a = tri[3 * c + (i + 1) % 3], b = tri[3 * c + (i + 2) % 3];
+        ++off[std::min(a, b) + 1];
+      }
+    for (int64_t v = 0; v < nv; ++v) off[v + 1] += off[v];
+    std::vector<Half> hs(he.size());
+    {
+      std::vector<int32_t> fill(off.begin(), off.end() - 1);
+      for (const Half& x : he) hs[fill[x.key / nv]++] = x;
+    }
+    auto before = [](const Half& x, const Half& y) {
+      return x.key < y.key || (x.key == y.key && x.forward > y.forward);
+    };
+    for (int64_t v = 0; v < nv; ++v)
+      for (int32_t i = off[v] + 1; i < off[v + 1]; ++i) {
+        const Half x = hs[i];
+        int32_t j = i - 1;
+        while (j >= off[v] && before(x, hs[j])) {
+          hs[j + 1] = hs[j];
+          --j;
+        }
+        hs[j + 1] = x;
+      }
+    he.swap(hs);
+  }
   // every undirected edge must appear exactly twice, once per direction
   std::vector<int64_t> starts;
   for (size_t i = 0; i < he.size();) {
@@ -208,7 +238,22 @@ rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, 
     }
   }
 
-  // cells sharing at least one vertex with each cell (for the mixed Gram matrix)
+  return RFCMP_OK;
+}
+
+// Cells sharing at least one vertex with each cell (for the mixed Gram
+// matrix), built on first use.
+void build_cell_nb(MeshHost& h) {
+  if (!h.cell_nb_ptr.empty()) return;
+  const int64_t nv = h.V, nc = h.C;
+  const int32_t* tri = h.tri.data();
+  std::vector<int32_t> vc_ptr(nv + 1, 0), vc_idx(3 * nc);
+  for (int64_t v = 0; v < nv; ++v) vc_ptr[v + 1] = vc_ptr[v] + h.noc[v];
+  {
+    std::vector<int32_t> fill(vc_ptr.begin(), vc_ptr.end() - 1);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int i = 0; i < 3; ++i) vc_idx[fill[tri[3 * c + i]]++] = int32_t(c);
+  }
   h.cell_nb_ptr.assign(nc + 1, 0);
   h.cell_nb_idx.clear();
   std::vector<int32_t> nb;
@@ -223,7 +268,6 @@ rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, 
     h.cell_nb_idx.insert(h.cell_nb_idx.end(), nb.begin(), nb.end());
     h.cell_nb_ptr[c + 1] = int32_t(h.cell_nb_idx.size());
   }
-  return RFCMP_OK;
 }
 
 // Near pairs c <= c': |x_c - x_c'| < factor * max(h_c, h_c') * (1 + 1e-9),
@@ -264,35 +308,55 @@ void near_pairs(const MeshHost& h, double factor, std::vector<int32_t>& out) {
     std::vector<int32_t> fill(start.begin(), start.end() - 1);
     for (int64_t c = 0; c < C; ++c) cells[fill[cbin[c]]++] = int32_t(c);  // ascending within a bin
   }
-  std::vector<int32_t> hit;
-  for (int64_t c = 0; c < C; ++c) {
-    hit.clear();
-    const int64_t b = cbin[c];
-    const int64_t bx = b / (nb[1] * nb[2]), by = (b / nb[2]) % nb[1], bz = b % nb[2];
-    const double* pc = &h.centroid[3 * c];
-    for (int64_t x = std::max<int64_t>(bx - 1, 0); x <= std::min(bx + 1, nb[0] - 1); ++x)
-      for (int64_t y = std::max<int64_t>(by - 1, 0); y <= std::min(by + 1, nb[1] - 1); ++y)
-        for (int64_t z = std::max<int64_t>(bz - 1, 0); z <= std::min(bz + 1, nb[2] - 1); ++z) {
-          const int64_t q = (x * nb[1] + y) * nb[2] + z;
-          for (int32_t i = start[q]; i < start[q + 1]; ++i) {
-            const int32_t o = cells[i];
-            if (o < c) continue;
-            const double* po = &h.centroid[3 * int64_t(o)];
-            double d2 = 0;
-            for (int d = 0; d < 3; ++d) {
-              const double t = pc[d] - po[d];
-              d2 += t * t;
+  // cells in contiguous chunks on a few threads, each chunk's pairs in cell
+  // order, concatenated in chunk order: the same list as one thread
+  auto scan = [&](int64_t c0, int64_t c1, std::vector<int32_t>& res) {
+    std::vector<int32_t> hit;
+    for (int64_t c = c0; c < c1; ++c) {
+      hit.clear();
+      const int64_t b = cbin[c];
+      const int64_t bx = b / (nb[1] * nb[2]), by = (b / nb[2]) % nb[1], bz = b % nb[2];
+      const double* pc = &h.centroid[3 * c];
+      for (int64_t x = std::max<int64_t>(bx - 1, 0); x <= std::min(bx + 1, nb[0] - 1); ++x)
+        for (int64_t y = std::max<int64_t>(by - 1, 0); y <= std::min(by + 1, nb[1] - 1); ++y)
+          for (int64_t z = std::max<int64_t>(bz - 1, 0); z <= std::min(bz + 1, nb[2] - 1); ++z) {
+            const int64_t q = (x * nb[1] + y) * nb[2] + z;
+            for (int32_t i = start[q]; i < start[q + 1]; ++i) {
+              const int32_t o = cells[i];
+              if (o < c) continue;
+              const double* po = &h.centroid[3 * int64_t(o)];
+              double d2 = 0;
+              for (int d = 0; d < 3; ++d) {
+                const double t = pc[d] - po[d];
+                d2 += t * t;
+              }
+              const double thr = factor * std::max(h.hmax[c], h.hmax[o]) * (1.0 + 1e-9);
+              if (std::sqrt(d2) < thr) hit.push_back(o);
             }
-            const double thr = factor * std::max(h.hmax[c], h.hmax[o]) * (1.0 + 1e-9);
-            if (std::sqrt(d2) < thr) hit.push_back(o);
           }
-        }
-    std::sort(hit.begin(), hit.end());
-    for (int32_t o : hit) {
-      out.push_back(int32_t(c));
-      out.push_back(o);
+      std::sort(hit.begin(), hit.end());
+      for (int32_t o : hit) {
+        res.push_back(int32_t(c));
+        res.push_back(o);
+      }
     }
+  };
+  const int64_t nthr = C >= 4096 ? std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency())) : 1;
+  std::vector<std::vector<int32_t>> part(nthr);
+  std::vector<std::thread> pool;
+  try {
+    for (int64_t t = 1; t < nthr; ++t)
+      pool.emplace_back(scan, C * t / nthr, C * (t + 1) / nthr, std::ref(part[t]));
+  } catch (const std::system_error&) {
+    // no threads to be had: the remaining chunks run here
+    for (int64_t t = int64_t(pool.size()) + 1; t < nthr; ++t) scan(C * t / nthr, C * (t + 1) / nthr, part[t]);
   }
+  scan(0, C / nthr, part[0]);
+  for (auto& th : pool) th.join();
+  size_t tot = 0;
+  for (const auto& v : part) tot += v.size();
+  out.reserve(tot);
+  for (const auto& v : part) out.insert(out.end(), v.begin(), v.end());
 }
 
 }  // namespace rfcmp

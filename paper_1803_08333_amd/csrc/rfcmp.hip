@@ -768,6 +768,22 @@ rfcmp_status rfcmp_mesh_create(const double* xyz, int64_t nv, const int32_t* tri
   *out = nullptr;
   auto m = std::make_unique<rfcmp_mesh_s>();
   RF_TRY(build_mesh_host(xyz, nv, tri, nc, m->h));
+  // the near-pair list of the default factor, on a host thread beside
+  // whatever the caller does next (the projector builds, at the latest)
+  rfcmp_options o;
+  rfcmp_options_default(&o);
+  try {
+    const MeshHost* hp = &m->h;
+    const double f = o.near_factor;
+    m->near_async = std::async(std::launch::async, [hp, f]() {
+      std::vector<int32_t> v;
+      near_pairs(*hp, f, v);
+      return v;
+    });
+    m->near_async_factor = f;
+  } catch (const std::exception&) {
+    m->near_async_factor = -1.0;  // computed when first needed
+  }
   *out = m.release();
   return RFCMP_OK;
 }
