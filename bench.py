@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-slab", type=int, default=32, help="1/slab of the test cells for the oracle sample")
     p.add_argument("--no-precision-study", action="store_true")
+    p.add_argument("--no-spectral-study", action="store_true")
     p.add_argument("--batch-rhs", type=int, default=64)
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a 1 GiB device copy (byte-counter calibration) and exit")
@@ -205,6 +206,24 @@ def precision_study(rf, torch, nb):
     return out
 
 
+def spectral_study(rf):
+    """cond(A) of the RF-CMP system against ka (1 down to the 1e-25 Hz of the
+    paper's sphere study) on icosphere levels 2-4 and the 96 x 48 torus: the
+    CG-Lanczos estimate of a solve of A i = b with a seeded generic b (the
+    library's rfcmp_solve_system), power-iteration scalings."""
+    from paper_1803_08333_amd import study
+    ks = [1.0, 1e-2, 1e-4, 1e-12, study.K_1E_25_HZ]
+    meshes = {f"icosphere{L}": synth.icosphere(L) for L in (2, 3, 4)}
+    meshes["torus96x48"] = synth.torus()
+    rows = study.condition_study(meshes, ks, seed=7)
+    out = {}
+    for r in rows:
+        out.setdefault(r["mesh"], {"N": r["N"], "cond": {}, "iters": {}})
+        out[r["mesh"]]["cond"][f"{r['k']:.3g}"] = round(r["cond"], 4)
+        out[r["mesh"]]["iters"][f"{r['k']:.3g}"] = r["iters"]
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -326,10 +345,13 @@ def main():
         "assembly_ms": asm_ms,
         "kernel_ms_per_step": {t: brk[t][0] for t in tags if brk[t][1] > 0},
         "bf16x3_vs_fp32": None,
+        "spectral_study": None,
         "roofline": roof,
     }
     if not args.no_precision_study:
         res["bf16x3_vs_fp32"] = precision_study(rf, torch, args.batch_rhs)
+    if not args.no_spectral_study:
+        res["spectral_study"] = spectral_study(rf)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(xyz, tri, args.cpu_slab)
     print(json.dumps(res))

@@ -204,6 +204,17 @@ typedef struct {
 rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol,
                          int32_t maxit, void* stream, rfcmp_info* info);
 
+/* CG on the RF-CMP system A i = b itself (eq. NewFormulation), with b given
+ * instead of formed from an excitation, and the iterate i returned instead of
+ * j = P_o i: the same iteration, stopping rule and report as rfcmp_solve
+ * (precision 0 or 1).  For spectral studies (Sec. 4, Figs. SphereF, SphereH,
+ * CubeTorus): with a generic b the Lanczos estimate in info approaches
+ * cond(A); a b formed from an excitation at very low k is dominated by one of
+ * the two blocks and leaves the other's eigenvalues out of the Krylov space.
+ * b, i: device c128 [nrhs][N], not aliased.  Errors as rfcmp_solve. */
+rfcmp_status rfcmp_solve_system(rfcmp_op op, const void* b, void* i, int32_t nrhs, double tol,
+                                int32_t maxit, void* stream, rfcmp_info* info);
+
 /* ------------------------------------------------------------ profiling */
 /* Kernel timing for benchmarks.  While enabled, the library records a HIP
  * event pair on the launch stream around every launch of its timed kernels:

@@ -82,6 +82,7 @@ EXPORTED = {
     "rfcmp_project": (_I32, [_P, _I32, _P, _P, _I32, _P]),
     "rfcmp_matvec": (_I32, [_P, _I32, _I32, _P, _P, _I32, _P]),
     "rfcmp_solve": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, ctypes.POINTER(Info)]),
+    "rfcmp_solve_system": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, ctypes.POINTER(Info)]),
     "rfcmp_profile_enable": (_I32, [_I32]),
     "rfcmp_profile_read": (_I32, [ctypes.c_char_p, _PD, _PI64]),
     "rfcmp_profile_select": (_I32, [ctypes.c_char_p]),
@@ -281,6 +282,18 @@ class Operator:
         st = _check(lib.rfcmp_solve(self.handle, _dptr(e, torch.complex128), _dptr(j), nr, tol, maxit, _stream(),
                                     info))
         return j, st, [i.as_dict() for i in info]
+
+    def solve_system(self, b, tol=1e-6, maxit=1000):
+        """CG on A i = b itself (rfcmp_solve_system).  Returns (i, status,
+        [info dict per rhs])."""
+        torch = _torch()
+        b = b.contiguous()
+        nr = b.shape[0] if b.dim() == 2 else 1
+        i = torch.empty_like(b)
+        info = (Info * nr)()
+        st = _check(lib.rfcmp_solve_system(self.handle, _dptr(b, torch.complex128), _dptr(i), nr, tol, maxit,
+                                           _stream(), info))
+        return i, st, [x.as_dict() for x in info]
 
     def close(self):
         if self.handle:

@@ -551,15 +551,20 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
 //                to 1e-4 of the current residual, i += d, true residual
 //                r = b - A i with the complex64/FP64 operator, until
 //                |r| <= tol |b|.
+// system: e is the system's own right-hand side b and j receives the iterate
+// i (no excitation mapping, no recovery).
 rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, double tol, int maxit, hipStream_t s,
-                         rfcmp_info* info) {
+                         rfcmp_info* info, bool system = false) {
   const int64_t N = op->mesh->h.N;
   const int64_t NR = (int64_t)nr * N;
   const Work W = carve(op);
   const Dense D64{op, s, false, &W};
   const Dense D16{op, s, true, &W};
   const bool split = op->opt.precision == 1;
-  RF_TRY(rhs_batch(D64, W, e, W.b0, nr));
+  if (system)
+    RF_HIP(hipMemcpyAsync(W.b0, e, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
+  else
+    RF_TRY(rhs_batch(D64, W, e, W.b0, nr));
   RF_HIP(hipMemcpyAsync(W.b, W.b0, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
   RF_HIP(hipMemsetAsync(W.d, 0, sizeof(double2) * NR, s));  // accumulated solution
   RF_TRY(dot(N, W.b, W.b, W.part, W.dout, nr, s));
@@ -616,7 +621,10 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
       info[r].rel_residual = zero ? 0.0 : rel[r];
       info[r].cond_estimate = cond[r];
     }
-  RF_TRY(recover_batch(D64, W, W.d, j, nr));
+  if (system)
+    RF_HIP(hipMemcpyAsync(j, W.d, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
+  else
+    RF_TRY(recover_batch(D64, W, W.d, j, nr));
   return st;
 }
 
@@ -1041,8 +1049,8 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
   }
 }
 
-rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,
-                         void* stream, rfcmp_info* info) {
+static rfcmp_status solve_common(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,
+                                 void* stream, rfcmp_info* info, bool system) {
   RF_ARG(op && e && j && e != j, "NULL or aliased argument");
   RF_ARG(nrhs > 0 && maxit > 0 && std::isfinite(tol) && tol > 0, "bad nrhs/maxit/tol");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1056,7 +1064,7 @@ rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, doub
     const int nr = std::min(R, nrhs - r0);
     rfcmp_status st = solve_batch(op, static_cast<const double2*>(e) + (int64_t)r0 * N,
                                   static_cast<double2*>(j) + (int64_t)r0 * N, nr, tol, maxit, s,
-                                  info ? info + r0 : nullptr);
+                                  info ? info + r0 : nullptr, system);
     if (st < 0) return st;
     if (st > worst) worst = st;
   }
@@ -1065,6 +1073,16 @@ rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, doub
   if (info)
     for (int r = 0; r < nrhs; ++r) info[r].ms_solve = ms;
   return worst;
+}
+
+rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,
+                         void* stream, rfcmp_info* info) {
+  return solve_common(op, e, j, nrhs, tol, maxit, stream, info, false);
+}
+
+rfcmp_status rfcmp_solve_system(rfcmp_op op, const void* b, void* i, int32_t nrhs, double tol, int32_t maxit,
+                                void* stream, rfcmp_info* info) {
+  return solve_common(op, b, i, nrhs, tol, maxit, stream, info, true);
 }
 
 }  // extern "C"
