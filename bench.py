@@ -224,6 +224,41 @@ def spectral_study(rf):
     return out
 
 
+def far_field_measurement(rf, torch):
+    """Far field and bistatic RCS of the library's solution (icosphere level 4,
+    x-polarised wave along +z, CG to 1e-8) on the E- and H-plane cuts at 1
+    degree (2 x 181 directions): the far-field launch time (HIP events) and,
+    at ka = 1e-4, the backscatter RCS against the closed-form Rayleigh limit
+    9 pi a^2 (ka)^4 of a small PEC sphere.  (The comparison with the full Mie
+    series on the cuts is a GPU test.)"""
+    kh, pol = synth.default_plane_wave()
+    th = np.linspace(0.0, np.pi, 181)
+    d = np.concatenate([np.stack([np.sin(th), np.zeros(181), np.cos(th)], 1),
+                        np.stack([np.zeros(181), np.sin(th), np.cos(th)], 1)])
+    xyz, tri = synth.icosphere(4)
+    m = rf.Mesh(xyz, tri)
+    out = {"directions": len(d), "cells": m.C}
+    for ka in (1.0, 1e-4):
+        op = rf.Operator(m, ka, power_start=torch.from_numpy(synth.complex_start(m.N, 11)).cuda())
+        j, st, info = op.solve(op.rhs_planewave(kh, pol), tol=1e-8, maxit=2000)
+        op.far_field(j, d)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        _, s = op.far_field(j, d)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        row = {"far_field_ms": ms, "cell_directions_per_s": m.C * len(d) / (ms * 1e-3), "iters": info[0]["iters"],
+               "rcs_backscatter": float(s[0, 180].item())}
+        if ka < 1e-2:
+            row["rayleigh_backscatter"] = 9 * np.pi * ka ** 4
+        out[f"ka={ka:g}"] = row
+        op.close()
+    m.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,12 +381,14 @@ def main():
         "kernel_ms_per_step": {t: brk[t][0] for t in tags if brk[t][1] > 0},
         "bf16x3_vs_fp32": None,
         "spectral_study": None,
+        "far_field": None,
         "roofline": roof,
     }
     if not args.no_precision_study:
         res["bf16x3_vs_fp32"] = precision_study(rf, torch, args.batch_rhs)
     if not args.no_spectral_study:
         res["spectral_study"] = spectral_study(rf)
+        res["far_field"] = far_field_measurement(rf, torch)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(xyz, tri, args.cpu_slab)
     print(json.dumps(res))

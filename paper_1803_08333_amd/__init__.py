@@ -76,6 +76,7 @@ EXPORTED = {
     "rfcmp_op_export": (_I32, [_P, _P, _P, _P]),
     "rfcmp_op_destroy": (None, [_P]),
     "rfcmp_rhs_planewave": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
+    "rfcmp_farfield": (_I32, [_P, _P, _I32, _PD, _I32, _P, _P, _P]),
     "rfcmp_precond_rhs": (_I32, [_P, _P, _P, _I32, _P]),
     "rfcmp_apply": (_I32, [_P, _P, _P, _I32, _P]),
     "rfcmp_recover": (_I32, [_P, _P, _P, _I32, _P]),
@@ -253,6 +254,20 @@ class Operator:
                         device=x.device)
         _check(fn(self.handle, *pre, _dptr(x, torch.complex128), _dptr(y), nr, _stream()))
         return y
+
+    def far_field(self, j, dirs):
+        """rfcmp_farfield: far-field vectors F [nrhs, ndir, 3] (complex128) and
+        bistatic RCS [nrhs, ndir] of RWG currents j at unit directions dirs."""
+        torch = _torch()
+        j = j.contiguous()
+        nr = j.shape[0] if j.dim() == 2 else 1
+        dirs = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        F = torch.empty((nr, len(dirs), 3), dtype=torch.complex128, device=j.device)
+        rcs = torch.empty((nr, len(dirs)), dtype=torch.float64, device=j.device)
+        _check(lib.rfcmp_farfield(self.handle, _dptr(j, torch.complex128, nr * self.mesh.N), nr,
+                                  dirs.ctypes.data_as(_PD), len(dirs),
+                                  _dptr(F), _dptr(rcs), _stream()))
+        return F, rcs
 
     def precond_rhs(self, e):
         return self._unary(lib.rfcmp_precond_rhs, e)

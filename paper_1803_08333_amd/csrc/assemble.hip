@@ -420,6 +420,72 @@ __global__ void k_rhs(int N, int nrhs, const int* __restrict__ edge_cell, const 
   e[t] = make_double2(sr, si);
 }
 
+// ---------------------------------------------------------------- far field
+// F_r(d) = int j_r exp(-i k dhat_d . x) dS: on cell c the RWG current is
+// sum_i j_m sigma_i (x - v_i)/(2 A_c) (v_i opposite local edge i) and the
+// rule's weights sum to one, so F = sum_c sum_q w_q/2 sum_i sigma_i j_m
+// (x_q - v_i) exp(-i k dhat . x_q).  sigma_r(d) = k^2/(4 pi) |F - dhat (dhat .
+// F)|^2 (unit incident amplitude).  One workgroup per (direction, right-hand
+// side): cells strided over the threads, then a fixed-order block sum (xor
+// butterflies in each wave, the four wave sums in order).
+__global__ __launch_bounds__(256) void k_farfield(int C, int N, int ndir, const int* __restrict__ cell_edge,
+                                                  const float* __restrict__ sgn, const double* __restrict__ vtx,
+                                                  double kk, const double* __restrict__ dirs, RuleArgs rule,
+                                                  const double2* __restrict__ j, double2* __restrict__ F,
+                                                  double* __restrict__ rcs) {
+  __shared__ double red[4][6];
+  const int d = blockIdx.x, r = blockIdx.y;
+  const double dh[3] = {dirs[3 * d], dirs[3 * d + 1], dirs[3 * d + 2]};
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // (re, im) of x, y, z
+  for (int c = threadIdx.x; c < C; c += 256) {
+    const double* P = vtx + (long)c * 9;
+    double2 jc[3];
+    double sg[3];
+    for (int i = 0; i < 3; ++i) {
+      jc[i] = j[(long)r * N + cell_edge[3 * c + i]];
+      sg[i] = 0.5 * (double)sgn[3 * c + i];
+    }
+    for (int q = 0; q < kQ; ++q) {
+      double x[3];
+      for (int k = 0; k < 3; ++k)
+        x[k] = rule.bary[q][0] * P[k] + rule.bary[q][1] * P[3 + k] + rule.bary[q][2] * P[6 + k];
+      double sn, cs;
+      sincos(kk * (dh[0] * x[0] + dh[1] * x[1] + dh[2] * x[2]), &sn, &cs);
+      const double wr = rule.wd[q] * cs, wi = -rule.wd[q] * sn;  // w_q exp(-i k dhat . x_q)
+      for (int k = 0; k < 3; ++k) {
+        double cr = 0.0, ci = 0.0;  // sum_i sigma_i / 2 j_m (x_q - v_i)_k
+        for (int i = 0; i < 3; ++i) {
+          const double arm = sg[i] * (x[k] - P[3 * i + k]);
+          cr += arm * jc[i].x;
+          ci += arm * jc[i].y;
+        }
+        acc[2 * k] += cr * wr - ci * wi;
+        acc[2 * k + 1] += cr * wi + ci * wr;
+      }
+    }
+  }
+  for (int q = 0; q < 6; ++q)
+    for (int m = 32; m > 0; m >>= 1) acc[q] += __shfl_xor(acc[q], m);
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 6; ++q) red[threadIdx.x >> 6][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double f[6];
+  for (int q = 0; q < 6; ++q) f[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+  double2* Fo = F + ((long)r * ndir + d) * 3;
+  for (int k = 0; k < 3; ++k) Fo[k] = make_double2(f[2 * k], f[2 * k + 1]);
+  if (rcs) {
+    const double pr = dh[0] * f[0] + dh[1] * f[2] + dh[2] * f[4];  // dhat . F
+    const double pi = dh[0] * f[1] + dh[1] * f[3] + dh[2] * f[5];
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double tr = f[2 * k] - dh[k] * pr, ti = f[2 * k + 1] - dh[k] * pi;
+      s += tr * tr + ti * ti;
+    }
+    rcs[(long)r * ndir + d] = kk * kk / (4.0 * M_PI) * s;
+  }
+}
+
 RuleArgs rule_args() {
   static const Rule r = make_rule();
   RuleArgs a;
@@ -533,6 +599,20 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
                      B.as<float2>(), (long)ldB, op->TA.as<float2>(), (long)op->ldA);
   }
   RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+
+rfcmp_status far_field(rfcmp_op op, const double2* j, int nrhs, const double* dirs, int ndir, double2* F,
+                       double* rcs, hipStream_t s) {
+  rfcmp_mesh m = op->mesh;
+  DevBuf dd;
+  RF_TRY(dd.alloc(sizeof(double) * 3 * ndir));
+  RF_HIP(hipMemcpyAsync(dd.p, dirs, sizeof(double) * 3 * ndir, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_farfield, dim3((unsigned)ndir, (unsigned)nrhs), dim3(256), 0, s, (int)m->h.C, (int)m->h.N,
+                     ndir, m->d.cell_edge.as<int>(), m->d.sgn.as<float>(), m->d.vtx.as<double>(), op->k,
+                     dd.as<double>(), rule_args(), j, F, rcs);
+  RF_HIP(hipGetLastError());
+  RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;
 }
 

@@ -945,6 +945,15 @@ rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* 
   return rhs_planewave(op, khat, pol, nrhs, static_cast<double2*>(e), static_cast<hipStream_t>(stream));
 }
 
+rfcmp_status rfcmp_farfield(rfcmp_op op, const void* j, int32_t nrhs, const double* dirs, int32_t ndir, void* F,
+                            void* rcs, void* stream) {
+  RF_ARG(op && j && dirs && F, "NULL argument");
+  RF_ARG(nrhs > 0 && ndir > 0 && nrhs <= 65535 && ndir <= (1 << 30), "nrhs and ndir must be > 0");
+  for (int d = 0; d < ndir; ++d) RF_ARG(unit(dirs + 3 * d), "directions must be unit vectors (1e-12)");
+  return far_field(op, static_cast<const double2*>(j), nrhs, dirs, ndir, static_cast<double2*>(F),
+                   static_cast<double*>(rcs), static_cast<hipStream_t>(stream));
+}
+
 rfcmp_status rfcmp_precond_rhs(rfcmp_op op, const void* e, void* b, int32_t nrhs, void* stream) {
   RF_ARG(op && e && b && e != b, "NULL or aliased argument");
   RF_ARG(nrhs > 0, "nrhs must be > 0");
