@@ -1,4 +1,5 @@
-"""Plane-wave excitation (Sec. 2 of the paper, the entries of e).
+"""Excitations (Sec. 2 of the paper, the entries of e): plane wave and
+voltage gap (the second source of the Fokker example, Sec. 4).
 
 e_m = (n x f_m, n x E^i) = int f_m . E^i dS for tangential f_m, with
 E^i(r) = pol exp(i k khat . r) (unit amplitude, e^{-i omega t} convention).
@@ -11,7 +12,7 @@ import numpy as np
 
 from .quadrature import tri7_points
 
-__all__ = ["planewave"]
+__all__ = ["planewave", "voltage_gap"]
 
 
 def planewave(top, k, khat, pol):
@@ -27,4 +28,27 @@ def planewave(top, k, khat, pol):
                 m = top.cell_edges[c, i]
                 arm = pts[c] - top.xyz[top.tri[c, i]]          # [7,3]
                 e[l, m] += top.cell_sign[c, i] / 2.0 * np.sum(w * (arm @ pol[l]) * phase[c])
+    return e
+
+
+def voltage_gap(top, edges, volts):
+    """Delta-gap excitation, e [nrhs, N] complex128.  edges [nrhs, G] (or [G])
+    RWG indices, volts complex of the same shape.
+
+    The source field of a gap of voltage V across edge m is E^i = V delta(s)
+    n_m, with s the in-plane distance from the edge and n_m its in-plane unit
+    normal pointing from c+ into c- (the direction in which f_m carries
+    current).  Then e_n = int f_n . E^i dS = V times the flux of f_n across
+    edge m: 1 for n = m (the RWG normalisation) and 0 for every other n (their
+    normal components vanish on edge m).  Gaps on the same edge add."""
+    edges = np.atleast_2d(np.asarray(edges, dtype=np.int64))
+    volts = np.atleast_2d(np.asarray(volts, dtype=np.complex128))
+    if edges.shape != volts.shape:
+        raise ValueError("edges and volts must have the same shape")
+    if edges.size and (edges.min() < 0 or edges.max() >= top.N):
+        raise ValueError("edge index out of range")
+    e = np.zeros((len(edges), top.N), dtype=np.complex128)
+    for r in range(len(edges)):
+        for m, v in zip(edges[r], volts[r]):
+            e[r, m] += v
     return e
