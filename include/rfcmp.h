@@ -125,6 +125,13 @@ typedef struct rfcmp_op_s* rfcmp_op;
  * operator. */
 rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt,
                              const void* power_start, void* stream, rfcmp_op* out);
+/* The operators of nk wavenumbers k[0..nk) on one mesh (a frequency sweep),
+ * each as rfcmp_op_create would make it, with the same options and power
+ * start vector: every operator's blocks are assembled first, beside the
+ * projector builds of a new mesh, then the scalings of each are computed.
+ * out: host rfcmp_op [nk], all NULL on error.  1 <= nk <= 1024. */
+rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, const rfcmp_options* opt,
+                                  const void* power_start, void* stream, rfcmp_op* out);
 /* Current scalings (Sec. 4).  lam (nullable, host double [3]) receives the
  * three power-iteration norm estimates (0 for k-scaling). */
 rfcmp_status rfcmp_op_scalings(rfcmp_op op, double* alpha, double* beta, double* gamma, double* lam);
@@ -140,6 +147,20 @@ void rfcmp_op_destroy(rfcmp_op op);
  * orthogonal (1e-12).  e: device c128 [nrhs][N]. */
 rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* pol,
                                  int32_t nrhs, void* e, void* stream);
+
+/* Voltage-gap (delta-gap) excitation, the second source of the Fokker
+ * example (Sec. 4): e_r[n] = sum of volts[r][g] over the gaps g with
+ * edges[r][g] = n, zero elsewhere.  A gap of voltage V across edge m is the
+ * field V delta(s) n_m (s the in-plane distance from the edge, n_m its
+ * in-plane normal from the edge's first cell into its second, the direction
+ * in which f_m carries current), and f_m has unit flux across its own edge
+ * while every other RWG function has none, so e_m = V.  With rfcmp_solve
+ * (T j = -e) the gap's input power is Re(V conj(j_m))/2 in units of 1/eta.
+ * edges: host int32 [nrhs][ngap], each in [0, N); volts: host c128
+ * [nrhs][ngap]; ngap may be 0 (e = 0); e: device c128 [nrhs][N].  Waits
+ * for the stream before returning. */
+rfcmp_status rfcmp_rhs_gap(rfcmp_mesh m, const int32_t* edges, const void* volts, int32_t ngap, int32_t nrhs,
+                           void* e, void* stream);
 
 /* Far field and bistatic radar cross section of RWG currents (Sec. 4,
  * Fig. Sphere_RCS): F_r(d) = int j_r(x) exp(-i k dhat_d . x) dS, the

@@ -71,11 +71,13 @@ EXPORTED = {
     "rfcmp_mesh_destroy": (None, [_P]),
     "rfcmp_options_default": (_I32, [ctypes.POINTER(Options)]),
     "rfcmp_op_create": (_I32, [_P, _D, ctypes.POINTER(Options), _P, _P, ctypes.POINTER(_P)]),
+    "rfcmp_op_create_many": (_I32, [_P, _PD, _I32, ctypes.POINTER(Options), _P, _P, ctypes.POINTER(_P)]),
     "rfcmp_op_scalings": (_I32, [_P, _PD, _PD, _PD, _PD]),
     "rfcmp_op_set_scalings": (_I32, [_P, _D, _D, _D]),
     "rfcmp_op_export": (_I32, [_P, _P, _P, _P]),
     "rfcmp_op_destroy": (None, [_P]),
     "rfcmp_rhs_planewave": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
+    "rfcmp_rhs_gap": (_I32, [_P, _PI32, _P, _I32, _I32, _P, _P]),
     "rfcmp_farfield": (_I32, [_P, _P, _I32, _PD, _I32, _P, _P, _P]),
     "rfcmp_precond_rhs": (_I32, [_P, _P, _P, _I32, _P]),
     "rfcmp_apply": (_I32, [_P, _P, _P, _I32, _P]),
@@ -192,6 +194,20 @@ class Mesh:
         _check(lib.rfcmp_mesh_near_pairs(self.handle, near_factor, ctypes.byref(cnt), p.ctypes.data_as(_PI32)))
         return p
 
+    def rhs_gap(self, edges, volts):
+        """rfcmp_rhs_gap: voltage-gap excitation e [nrhs, N] (complex128) of
+        gaps across the RWG edges edges [nrhs, G] (or [G]) with voltages volts
+        of the same shape."""
+        torch = _torch()
+        edges = np.ascontiguousarray(np.atleast_2d(edges), dtype=np.int32)
+        volts = np.ascontiguousarray(np.atleast_2d(volts), dtype=np.complex128)
+        if edges.shape != volts.shape:
+            raise ValueError("edges and volts must have the same shape")
+        e = torch.empty((edges.shape[0], self.N), dtype=torch.complex128, device="cuda")
+        _check(lib.rfcmp_rhs_gap(self.handle, edges.ctypes.data_as(_PI32), volts.ctypes.data_as(_P),
+                                 edges.shape[1], edges.shape[0], _dptr(e), _stream()))
+        return e
+
     def close(self):
         if self.handle:
             lib.rfcmp_mesh_destroy(self.handle)
@@ -218,6 +234,24 @@ class Operator:
         h = _P()
         _check(lib.rfcmp_op_create(mesh.handle, self.k, ctypes.byref(self.opts), ps, _stream(), ctypes.byref(h)))
         self.handle = h
+
+    @classmethod
+    def create_many(cls, mesh, ks, power_start=None, **opts):
+        """rfcmp_op_create_many: the operators of several wavenumbers on one
+        mesh, their assemblies queued ahead of the first scalings."""
+        torch = _torch()
+        ks = np.ascontiguousarray(np.atleast_1d(ks), dtype=np.float64)
+        o = options(**opts)
+        ps = None if power_start is None else _dptr(power_start, torch.complex128, mesh.N)
+        hs = (_P * len(ks))()
+        _check(lib.rfcmp_op_create_many(mesh.handle, ks.ctypes.data_as(_PD), len(ks), ctypes.byref(o), ps,
+                                        _stream(), hs))
+        out = []
+        for k, h in zip(ks, hs):
+            op = cls.__new__(cls)
+            op.mesh, op.k, op.opts, op.handle = mesh, float(k), options(**opts), _P(h)
+            out.append(op)
+        return out
 
     def scalings(self):
         a, b, g = _D(), _D(), _D()

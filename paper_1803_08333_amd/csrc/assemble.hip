@@ -20,7 +20,9 @@
 // the 1/R part is integrated over the inner cell in closed form (Wilton et al.,
 // IEEE TAP 1984; Graglia, IEEE TAP 1993), the bounded rest with 7 x 7 points,
 // the outer cell is the lower-indexed one and self blocks are symmetrised.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 
@@ -602,6 +604,24 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   return RFCMP_OK;
 }
 
+namespace {
+// Voltage-gap excitation: element t = r N + m of e takes the summed gap
+// voltage of flat index t from the sorted, duplicate-free list idx/val, found
+// by binary search, else 0.
+__global__ void k_rhs_gap(long total, const long* __restrict__ idx, const double2* __restrict__ val, int P,
+                          double2* __restrict__ e) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  int lo = 0, hi = P;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (idx[mid] < t) lo = mid + 1;
+    else hi = mid;
+  }
+  e[t] = (lo < P && idx[lo] == t) ? val[lo] : make_double2(0.0, 0.0);
+}
+}  // namespace
+
 rfcmp_status far_field(rfcmp_op op, const double2* j, int nrhs, const double* dirs, int ndir, double2* F,
                        double* rcs, hipStream_t s) {
   rfcmp_mesh m = op->mesh;
@@ -628,6 +648,42 @@ rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, i
   hipLaunchKernelGGL(k_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (int)N, nrhs,
                      m->d.edge_cell.as<int>(), m->d.edge_slot.as<int>(), m->d.vtx.as<double>(), op->k, dk.as<double>(),
                      dk.as<double>() + 3 * nrhs, rule_args(), e);
+  RF_HIP(hipGetLastError());
+  RF_HIP(hipStreamSynchronize(s));
+  return RFCMP_OK;
+}
+
+rfcmp_status rhs_gap(rfcmp_mesh m, const int32_t* edges, const double2* volts, int ngap, int nrhs, double2* e,
+                     hipStream_t s) {
+  const int64_t N = m->h.N;
+  // Flat indices r N + m in order, gaps on one edge summed in the order given.
+  std::vector<std::pair<long, double2>> g;
+  g.reserve((size_t)ngap * nrhs);
+  for (int r = 0; r < nrhs; ++r)
+    for (int q = 0; q < ngap; ++q) g.push_back({(long)r * N + edges[(long)r * ngap + q], volts[(long)r * ngap + q]});
+  std::stable_sort(g.begin(), g.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  std::vector<long> idx;
+  std::vector<double2> val;
+  for (const auto& x : g) {
+    if (!idx.empty() && idx.back() == x.first) {
+      val.back().x += x.second.x;
+      val.back().y += x.second.y;
+    } else {
+      idx.push_back(x.first);
+      val.push_back(x.second);
+    }
+  }
+  const int P = (int)idx.size();
+  DevBuf di, dv;
+  if (P) {
+    RF_TRY(di.alloc(sizeof(long) * P));
+    RF_TRY(dv.alloc(sizeof(double2) * P));
+    RF_HIP(hipMemcpyAsync(di.p, idx.data(), sizeof(long) * P, hipMemcpyHostToDevice, s));
+    RF_HIP(hipMemcpyAsync(dv.p, val.data(), sizeof(double2) * P, hipMemcpyHostToDevice, s));
+  }
+  const long total = (long)N * nrhs;
+  hipLaunchKernelGGL(k_rhs_gap, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total,
+                     P ? di.as<long>() : nullptr, P ? dv.as<double2>() : nullptr, P, e);
   RF_HIP(hipGetLastError());
   RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;

@@ -361,4 +361,6 @@ MeshDev::~MeshDev() {
 }  // namespace rfcmp
 
 rfcmp_op_s::rfcmp_op_s() = default;
-rfcmp_op_s::~rfcmp_op_s() = default;
+rfcmp_op_s::~rfcmp_op_s() {
+  if (host_scal) (void)hipHostFree(host_scal);
+}

@@ -342,7 +342,8 @@ rfcmp_status batched(int nrhs, int R, int64_t nin, int64_t nout, const double2* 
 }
 
 // One power-iteration application of the three scaling operators to the
-// normalised rows of W.pv ([3][N]: alpha, gamma, beta), result in W.pw.
+// normalised rows of W.pv ([3][N]: alpha, gamma, beta); the results,
+// normalised, replace them, with their squared norms in W.dout.
 //   O_alpha v = P_LH conj(T_A) Lam G_ll^-1 Lam^T T_A P_LH v
 //   O_gamma v = P_LH conj(T_A) P_LH T_A P_LH v
 //   O_beta  v = P_Sigma T_Phi^H P_mS_hat T_Phi P_Sigma v
@@ -369,9 +370,7 @@ rfcmp_status power_apply(const Dense& D, const Work& W, bool project_in) {
   RF_TRY(power_branch(d, N, V, C, W.v2, W.nB, W.c[3], W.nC, s));                // alpha | gamma branch
   RF_TRY(D.pair(kTA, Dense::plain(W.nC, N), W.nD, kV, Dense::plain(W.c[9], C), W.c[10], true, 2, 1));
   RF_TRY(D.prod(kLP, false, D.sigma_t(W.nD), W.c[5], 2));
-  RF_TRY(axpy_sigma(d, N, C, 1.0, false, W.nD, -1.0, W.c[5], W.pw, 2, s));
-  RF_TRY(axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[10], W.pw + 2 * N, 1, s));
-  return RFCMP_OK;
+  return power_next(d, N, C, W.nD, W.c[5], W.c[10], W.pv, W.dout, s);
 }
 
 rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStream_t s) {
@@ -381,11 +380,10 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStr
   const Dense D{op, s, false};
   for (int r = 0; r < 3; ++r)
     RF_HIP(hipMemcpyAsync(W.pw + r * N, start, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
-  for (int it = 0; it < steps; ++it) {
-    RF_TRY(normalize_rows(N, W.pw, W.pv, W.dout, 3, s));
-    RF_TRY(power_apply(D, W, it == 0));
-  }
-  RF_TRY(dot(N, W.pw, W.pw, W.part, W.dout, 3, s));
+  RF_TRY(normalize_rows(N, W.pw, W.pv, W.dout, 3, s));
+  // each application ends with the next normalised vectors in W.pv and the
+  // squared norms of the raw ones in W.dout
+  for (int it = 0; it < steps; ++it) RF_TRY(power_apply(D, W, it == 0));
   double2 nr2[3];
   RF_HIP(hipMemcpyAsync(nr2, W.dout, sizeof nr2, hipMemcpyDeviceToHost, s));
   RF_HIP(hipStreamSynchronize(s));
@@ -840,8 +838,16 @@ rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt, c
                              void* stream, rfcmp_op* out) {
   RF_ARG(out, "out is NULL");
   *out = nullptr;
+  return rfcmp_op_create_many(m, &k, 1, opt, power_start, stream, out);
+}
+
+rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, const rfcmp_options* opt,
+                                  const void* power_start, void* stream, rfcmp_op* out) {
+  RF_ARG(out, "out is NULL");
+  RF_ARG(k && nk > 0 && nk <= 1024, "need 1 to 1024 wavenumbers");
+  for (int32_t i = 0; i < nk; ++i) out[i] = nullptr;
   RF_ARG(m, "mesh is NULL");
-  RF_ARG(std::isfinite(k) && k > 0, "wavenumber must be finite and > 0");
+  for (int32_t i = 0; i < nk; ++i) RF_ARG(std::isfinite(k[i]) && k[i] > 0, "wavenumber must be finite and > 0");
   rfcmp_options o;
   rfcmp_options_default(&o);
   if (opt) o = *opt;
@@ -859,26 +865,36 @@ rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt, c
   }
   RF_TRY(ensure_mesh_device(m, o.outer_star == 1, s));
   m->device = dev;
-  auto op = std::make_unique<rfcmp_op_s>();
-  op->mesh = m;
-  op->k = k;
-  op->opt = o;
   const int64_t N = m->h.N, C = m->h.C, V = m->h.V;
-  op->ldA = (int64_t)round_up(N, 64);
-  op->ldV = (int64_t)round_up(C, 64);
-  RF_TRY(op->TA.alloc(sizeof(float2) * N * op->ldA));
-  RF_TRY(op->Vb.alloc(sizeof(float2) * C * op->ldV));
-  RF_TRY(ensure_work(op.get(), 4));
-  RF_TRY(op->symv_scratch.alloc(symv_scratch_bytes(N, 4) + symv_scratch_bytes(C, 4) + symv_scratch_bytes(V, 4)));
-  RF_TRY(assemble_blocks(op.get(), s));  // runs beside the projector builds
+  std::vector<std::unique_ptr<rfcmp_op_s>> ops(nk);
+  // Every operator's blocks first: their assembly runs beside the projector
+  // builds of a new mesh, which the scalings then wait for.
+  for (int32_t i = 0; i < nk; ++i) {
+    auto& op = ops[i];
+    op = std::make_unique<rfcmp_op_s>();
+    op->mesh = m;
+    op->k = k[i];
+    op->opt = o;
+    op->ldA = (int64_t)round_up(N, 64);
+    op->ldV = (int64_t)round_up(C, 64);
+    RF_TRY(op->TA.alloc(sizeof(float2) * N * op->ldA));
+    RF_TRY(op->Vb.alloc(sizeof(float2) * C * op->ldV));
+    RF_TRY(ensure_work(op.get(), 4));
+    RF_TRY(op->symv_scratch.alloc(symv_scratch_bytes(N, 4) + symv_scratch_bytes(C, 4) + symv_scratch_bytes(V, 4)));
+    RF_TRY(assemble_blocks(op.get(), s));
+  }
   RF_TRY(wait_projectors(m, s));
-  op->alpha = std::sqrt(k);
-  op->beta = 1.0 / std::sqrt(k);
-  op->gamma = k;
-  if (o.scaling == 0) RF_TRY(power_scalings(op.get(), static_cast<const double2*>(power_start), o.power_iters, s));
-  if (o.precision == 1) RF_TRY(ensure_split(op.get(), s));
+  for (int32_t i = 0; i < nk; ++i) {
+    rfcmp_op op = ops[i].get();
+    op->alpha = std::sqrt(k[i]);
+    op->beta = 1.0 / std::sqrt(k[i]);
+    op->gamma = k[i];
+    if (o.scaling == 0)
+      RF_TRY(power_scalings(op, static_cast<const double2*>(power_start), o.power_iters, s));
+    if (o.precision == 1) RF_TRY(ensure_split(op, s));
+  }
   RF_HIP(hipStreamSynchronize(s));
-  *out = op.release();
+  for (int32_t i = 0; i < nk; ++i) out[i] = ops[i].release();
   return RFCMP_OK;
 }
 
@@ -927,11 +943,7 @@ rfcmp_status rfcmp_op_export(rfcmp_op op, void* TA, void* V, void* stream) {
   return RFCMP_OK;
 }
 
-void rfcmp_op_destroy(rfcmp_op op) {
-  if (!op) return;
-  if (op->host_scal) (void)hipHostFree(op->host_scal);
-  delete op;
-}
+void rfcmp_op_destroy(rfcmp_op op) { delete op; }
 
 rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* pol, int32_t nrhs, void* e,
                                  void* stream) {
@@ -943,6 +955,17 @@ rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* 
     RF_ARG(std::fabs(dp) <= 1e-12, "pol must be orthogonal to khat (1e-12)");
   }
   return rhs_planewave(op, khat, pol, nrhs, static_cast<double2*>(e), static_cast<hipStream_t>(stream));
+}
+
+rfcmp_status rfcmp_rhs_gap(rfcmp_mesh m, const int32_t* edges, const void* volts, int32_t ngap, int32_t nrhs,
+                           void* e, void* stream) {
+  RF_ARG(m && e, "NULL argument");
+  RF_ARG(nrhs > 0 && nrhs <= 65535 && ngap >= 0 && ngap <= (1 << 20), "nrhs must be in [1, 65535], ngap in [0, 2^20]");
+  RF_ARG(ngap == 0 || (edges && volts), "NULL edges or volts");
+  for (int64_t t = 0; t < (int64_t)ngap * nrhs; ++t)
+    RF_ARG(edges[t] >= 0 && edges[t] < m->h.N, "gap edge index out of range");
+  return rhs_gap(m, edges, static_cast<const double2*>(volts), ngap, nrhs, static_cast<double2*>(e),
+                 static_cast<hipStream_t>(stream));
 }
 
 rfcmp_status rfcmp_farfield(rfcmp_op op, const void* j, int32_t nrhs, const double* dirs, int32_t ndir, void* F,

@@ -30,6 +30,10 @@ rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, d
 int dot_partials();
 // out[r] = x[r] / |x[r]|, nrm2[r] = |x[r]|^2 (one launch)
 rfcmp_status normalize_rows(int64_t n, const double2* x, double2* out, double2* nrm2, int nr, hipStream_t s);
+// Rows 0, 1: w_r - Sigma z5_r; row 2: Sigma z10; normalised into out [3][N],
+// squared norms into nrm2 [3].
+rfcmp_status power_next(const MeshDev& d, int64_t N, int64_t C, const double2* w, const double2* z5,
+                        const double2* z10, double2* out, double2* nrm2, hipStream_t s);
 // power iteration: out[0] = Lambda h, out[1] = a[1] - Sigma z  (h [V], z [C], a and out [2][N])
 rfcmp_status power_branch(const MeshDev& d, int64_t N, int64_t V, int64_t C, const double2* h, const double2* a,
                           const double2* z, double2* out, hipStream_t s);

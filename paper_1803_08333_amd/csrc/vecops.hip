@@ -313,6 +313,31 @@ __global__ __launch_bounds__(1024) void k_normalize_rows(long n, const double2* 
   for (long i = threadIdx.x; i < n; i += 1024) out[r * n + i] = cscale(sc, x[r * n + i]);
 }
 
+// End of one power-iteration application: the three raw vectors (rows 0
+// and 1: w_r - Sigma z5_r, row 2: Sigma z10), each row's squared norm to
+// nrm2[r], and the row divided by its norm to out.  One workgroup per row;
+// each thread rescales in the second pass the entries it wrote in the first.
+__global__ __launch_bounds__(1024) void k_power_next(int N, int C, const int* __restrict__ edge_cell,
+                                                     const double2* __restrict__ w, const double2* __restrict__ z5,
+                                                     const double2* __restrict__ z10, double2* __restrict__ out,
+                                                     double2* __restrict__ nrm2) {
+  __shared__ double sr[16], si[16];
+  const int r = blockIdx.x;
+  double2* o = out + (long)r * N;
+  const double2* z = r < 2 ? z5 + (long)r * C : z10;
+  double a = 0.0;
+  for (int n = threadIdx.x; n < N; n += 1024) {
+    const double2 zd = csub(z[edge_cell[2 * n]], z[edge_cell[2 * n + 1]]);
+    const double2 v = r < 2 ? csub(w[(long)r * N + n], zd) : zd;
+    o[n] = v;
+    a += v.x * v.x + v.y * v.y;
+  }
+  const double2 t = block_sum_1024(a, 0.0, sr, si);
+  const double sc = 1.0 / sqrt(t.x);
+  if (threadIdx.x == 0) nrm2[r] = make_double2(t.x, 0.0);
+  for (int n = threadIdx.x; n < N; n += 1024) o[n] = cscale(sc, o[n]);
+}
+
 __global__ void k_sub(long n, const double2* __restrict__ a, const double2* __restrict__ b,
                       double2* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -424,6 +449,13 @@ rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, d
 int dot_partials() { return kRedBlocks; }
 rfcmp_status normalize_rows(int64_t n, const double2* x, double2* out, double2* nrm2, int nr, hipStream_t s) {
   hipLaunchKernelGGL(k_normalize_rows, dim3(nr), dim3(1024), 0, s, (long)n, x, out, nrm2);
+  RF_HIP(hipGetLastError());
+  return RFCMP_OK;
+}
+rfcmp_status power_next(const MeshDev& d, int64_t N, int64_t C, const double2* w, const double2* z5,
+                        const double2* z10, double2* out, double2* nrm2, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_next, dim3(3), dim3(1024), 0, s, (int)N, (int)C, d.edge_cell.as<int>(), w, z5, z10,
+                     out, nrm2);
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
 }

@@ -450,3 +450,27 @@ def test_projector_inverses_large(nmajor, nminor):
     assert rel(mass(gy), y) < 1e-10
     op.close()
     m.close()
+
+
+def test_create_many_matches_single():
+    """rfcmp_op_create_many (a frequency sweep, every assembly queued ahead of
+    the scalings) gives the operators of separate rfcmp_op_create calls bit
+    for bit: blocks and power-iteration scalings."""
+    torch, rf = _gpu()
+    xyz, tri = _mesh("ico2")
+    ks = [1.0, 0.1, 1e-4]
+    m = rf.Mesh(xyz, tri)
+    start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
+    many = rf.Operator.create_many(m, ks, power_start=start)
+    m1 = rf.Mesh(xyz, tri)
+    for k, op in zip(ks, many):
+        one = rf.Operator(m1, k, power_start=start)
+        assert op.scalings() == one.scalings()
+        for a, b in zip(op.export(), one.export()):
+            assert torch.equal(a, b)
+        one.close()
+        op.close()
+    with pytest.raises(rf.RfcmpError):
+        rf.Operator.create_many(m, [1.0, -1.0], power_start=start)
+    m1.close()
+    m.close()

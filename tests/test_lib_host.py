@@ -100,3 +100,37 @@ def test_options_defaults():
     import paper_1803_08333_amd as rf
     o = rf.options()
     assert (o.near_factor, o.outer_star, o.scaling, o.power_iters, o.precision) == (2.0, 0, 0, 30, 0)
+
+
+def test_rhs_gap_argument_errors():
+    """rfcmp_rhs_gap rejects bad arguments before any device work (no GPU
+    needed): an edge out of range, nrhs = 0, missing edge or voltage arrays."""
+    import paper_1803_08333_amd as rf
+    m = rf.Mesh(*synth.icosphere(1))
+    e = ctypes.c_void_p(16)                      # never dereferenced: every call below fails validation
+    v = np.ones(2, dtype=np.complex128)
+    for edges, ng, nr in (([0, m.N], 2, 1), ([-1, 0], 2, 1), ([0, 1], 2, 0)):
+        ed = np.asarray(edges, dtype=np.int32)
+        st = rf.lib.rfcmp_rhs_gap(m.handle, ed.ctypes.data_as(rf._PI32), v.ctypes.data_as(ctypes.c_void_p),
+                                  ng, nr, e, None)
+        msg = rf.lib.rfcmp_last_error()
+        assert st < 0 and (b"nrhs" in msg or b"range" in msg), msg
+    assert rf.lib.rfcmp_rhs_gap(m.handle, None, None, 1, 1, e, None) < 0
+    with pytest.raises(ValueError):
+        m.rhs_gap([1, 2], [1.0])
+    m.close()
+
+
+def test_create_many_argument_errors():
+    """rfcmp_op_create_many rejects bad arguments before any device work and
+    leaves every output NULL."""
+    import paper_1803_08333_amd as rf
+    m = rf.Mesh(*synth.icosphere(1))
+    out = (ctypes.c_void_p * 2)(1, 1)
+    ks = np.array([1.0, 0.0])
+    o = rf.options(scaling=1)
+    st = rf.lib.rfcmp_op_create_many(m.handle, ks.ctypes.data_as(rf._PD), 0, ctypes.byref(o), None, None, out)
+    assert st < 0
+    st = rf.lib.rfcmp_op_create_many(m.handle, ks.ctypes.data_as(rf._PD), 2, ctypes.byref(o), None, None, out)
+    assert st < 0 and not out[0] and not out[1], rf.lib.rfcmp_last_error()
+    m.close()
