@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--no-precision-study", action="store_true")
     p.add_argument("--no-spectral-study", action="store_true")
     p.add_argument("--batch-rhs", type=int, default=64)
+    p.add_argument("--uneven-batch", action="store_true",
+                   help="also time the uneven batch (32 objects x 8 wavenumbers x 4 plane waves, BF16x3)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     return p.parse_args()
@@ -296,6 +298,49 @@ def voltage_gap_measurement(rf, torch):
     return out
 
 
+def uneven_batch(rf, torch):
+    """The seeded uneven batch (32 icospheres, cubes and ellipsoids, N from
+    480 to 16 200; 8 wavenumbers from 1e-3 to 5; 4 plane waves each): per
+    object one rfcmp_op_create_many over the sweep (assembly, projectors,
+    power iterations), then a 4-right-hand-side BF16x3 solve with refinement
+    to 1e-6 per wavenumber.  Whole-batch wall time, right-hand sides solved
+    per second, and the iteration counts (the top wavenumber sits next to
+    interior resonances of these bodies)."""
+    from synth import batch
+    objs = batch.uneven_objects()
+    ks = batch.sweep_wavenumbers()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, t_setup, t_solve, bad = [], 0.0, 0.0, 0
+    for o, obj in enumerate(objs):
+        ta = time.perf_counter()
+        m = rf.Mesh(obj["xyz"], obj["tri"])
+        start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
+        ops = rf.Operator.create_many(m, ks, power_start=start, precision=1)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for q, op in enumerate(ops):
+            kh, pol = batch.sweep_waves(o, q)
+            _, st, info = op.solve(op.rhs_planewave(kh, pol), tol=1e-6, maxit=4000)
+            bad += st != 0
+            iters.append((q, max(i["iters"] for i in info)))
+        torch.cuda.synchronize()
+        t_setup += tb - ta
+        t_solve += time.perf_counter() - tb
+        for op in ops:
+            op.close()
+        m.close()
+        rf.release_cached_memory()
+    wall = time.perf_counter() - t0
+    nrhs = len(objs) * len(ks) * 4
+    low = [i for q, i in iters if q < len(ks) - 1]
+    top = [i for q, i in iters if q == len(ks) - 1]
+    return {"objects": len(objs), "wavenumbers": len(ks), "rhs": nrhs, "wall_s": wall, "setup_s": t_setup,
+            "solve_s": t_solve, "rhs_per_s": nrhs / wall, "not_converged": int(bad),
+            "iters_below_top_k": {"median": float(np.median(low)), "max": int(max(low))},
+            "iters_top_k": {"median": float(np.median(top)), "max": int(max(top))}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -426,6 +471,8 @@ def main():
         res["spectral_study"] = spectral_study(rf)
         res["far_field"] = far_field_measurement(rf, torch)
         res["voltage_gap"] = voltage_gap_measurement(rf, torch)
+    if args.uneven_batch:
+        res["uneven_batch"] = uneven_batch(rf, torch)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(xyz, tri, args.cpu_slab)
     print(json.dumps(res))
