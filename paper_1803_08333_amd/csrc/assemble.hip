@@ -562,6 +562,19 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   // scratch and near-pair list live with the mesh: reused by every wavenumber
   if (!d.pairB.p) RF_TRY(d.pairB.alloc(sizeof(float2) * ldB * 3 * C));
   DevBuf& B = d.pairB;
+  RF_HIP(hipMemsetAsync(op->Vb.p, 0, op->Vb.bytes, s));
+
+  // far pairs first: they do not need the near-pair list, which a new mesh
+  // may still be computing on host threads
+  const long nt = (long)((C + kTile - 1) / kTile);
+  const long ntiles = nt * (nt + 1) / 2;
+  {
+  ProfScope prof("far_pairs", s);
+  hipLaunchKernelGGL(k_far_pairs, dim3((unsigned)ntiles), dim3(256), 0, s, (int)C, ntiles, d.cen.as<double>(),
+                     d.qoff.as<float4>(), d.fvoff.as<float4>(), d.sgn.as<float>(), (float)op->k, ra,
+                     B.as<float2>(), (long)ldB, op->Vb.as<float2>(), (long)op->ldV);
+  }
+  RF_HIP(hipGetLastError());
   if (d.near_factor != op->opt.near_factor) {
     std::vector<int32_t> pairs;
     if (m->near_async.valid() && m->near_async_factor == op->opt.near_factor)
@@ -577,17 +590,6 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   }
   const long npairs = (long)d.npairs;
   DevBuf& dp = d.near;
-  RF_HIP(hipMemsetAsync(op->Vb.p, 0, op->Vb.bytes, s));
-
-  const long nt = (long)((C + kTile - 1) / kTile);
-  const long ntiles = nt * (nt + 1) / 2;
-  {
-  ProfScope prof("far_pairs", s);
-  hipLaunchKernelGGL(k_far_pairs, dim3((unsigned)ntiles), dim3(256), 0, s, (int)C, ntiles, d.cen.as<double>(),
-                     d.qoff.as<float4>(), d.fvoff.as<float4>(), d.sgn.as<float>(), (float)op->k, ra,
-                     B.as<float2>(), (long)ldB, op->Vb.as<float2>(), (long)op->ldV);
-  }
-  RF_HIP(hipGetLastError());
   if (npairs > 0) {
     ProfScope prof("near_pairs", s);
     hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, s, npairs,

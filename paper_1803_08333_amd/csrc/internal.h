@@ -195,7 +195,8 @@ struct rfcmp_op_s {
   rfcmp::DevBuf Vb;          // float2 [C][ldV]
   rfcmp::DevBuf work;        // complex128 workspace for work_nrhs right-hand sides
   int work_nrhs = 0;
-  double* host_scal = nullptr;  // pinned, 16 + 8 * work_nrhs doubles
+  double* host_scal = nullptr;      // pinned and mapped, 16 + 8 * work_nrhs doubles
+  double* host_scal_dev = nullptr;  // its device address
   std::unique_ptr<rfcmp::SplitMatrix> TA16, V16;  // BF16x3 planes (precision 1)
   rfcmp::DevBuf gemm_scratch;
   rfcmp::DevBuf symv_scratch;  // partial sums of the symmetric products

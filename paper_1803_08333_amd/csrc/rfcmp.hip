@@ -89,7 +89,9 @@ rfcmp_status ensure_work(rfcmp_op op, int R) {
   op->work_nrhs = R;
   if (op->host_scal) (void)hipHostFree(op->host_scal);
   op->host_scal = nullptr;
-  RF_HIP(hipHostMalloc((void**)&op->host_scal, sizeof(double) * (16 + 8 * R), hipHostMallocDefault));
+  op->host_scal_dev = nullptr;
+  RF_HIP(hipHostMalloc((void**)&op->host_scal, sizeof(double) * (16 + 8 * R), hipHostMallocMapped));
+  RF_HIP(hipHostGetDevicePointer((void**)&op->host_scal_dev, op->host_scal, 0));
   return RFCMP_OK;
 }
 
@@ -458,6 +460,7 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
   const int64_t N = op->mesh->h.N;
   const int64_t NR = (int64_t)nr * N;
   double* hs = op->host_scal;  // per parity p: rho_new at 4Rp, pq at 4Rp + R; active flags at 6R
+  double* hs_dev = op->host_scal_dev;  // the same memory as the device addresses it
   const int R = W.R;
   std::vector<int> act(nr, 1);
   for (int r = 0; r < nr; ++r) iters[r] = 0;
@@ -488,14 +491,12 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
     if (it < maxit && nactive > 0) {
       const int slot = it & 1;
       RF_TRY(apply_batch(D, W, W.p, W.q, nr));
-      RF_TRY(dot(N, W.p, W.q, W.part, W.dout, nr, s));
-      RF_TRY(take_real_n(W.dout, W.pq, nr, s));
+      // the dot kernels also store the real parts for the host, straight into
+      // the mapped pinned buffer; the event below publishes them
+      RF_TRY(dot(N, W.p, W.q, W.part, W.dout, nr, s, W.pq, hs_dev + slot * 4 * R + R));
       RF_TRY(cg_xr_blk(N, nr, W.rho + cur * R, W.pq, W.active, W.x, W.r, W.p, W.q, s));
       const int nxt = 1 - cur;
-      RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, s));
-      RF_TRY(take_real_n(W.dout, W.rho + nxt * R, nr, s));
-      RF_HIP(hipMemcpyAsync(hs + slot * 4 * R, W.rho + nxt * R, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
-      RF_HIP(hipMemcpyAsync(hs + slot * 4 * R + R, W.pq, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+      RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, s, W.rho + nxt * R, hs_dev + slot * 4 * R));
       RF_HIP(hipEventRecord(ev[slot], s));
       RF_TRY(cg_p_blk(N, nr, W.rho + nxt * R, W.rho + cur * R, W.active, W.r, W.p, s));
       cur = nxt;
@@ -703,7 +704,9 @@ hipEvent_t profile_event() {
   ProfState& p = prof();
   if (p.next == p.pool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // timing only: no system-scope fence (cache write-back) at each record,
+    // which would stall the stream around every timed launch
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     p.pool.push_back(e);
   }
   return p.pool[p.next++];

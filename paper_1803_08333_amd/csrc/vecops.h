@@ -24,9 +24,11 @@ rfcmp_status left_y(const MeshDev& d, int64_t N, int64_t C, double ka, const dou
 // j = ia (x - Sigma sv) + i ib Sigma sg
 rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double ib, const double2* x,
                        const double2* sv, const double2* sg, double2* j, int nr, hipStream_t s);
-// out[r] = sum conj(a[r]) b[r]; part needs dot_partials()*nr entries
+// out[r] = sum conj(a[r]) b[r]; part needs dot_partials()*nr entries.  The
+// real parts also go to re_out[r] and host_out[r] when those are non-null
+// (host_out: the device address of mapped pinned host memory).
 rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, double2* out, int nr,
-                 hipStream_t s);
+                 hipStream_t s, double* re_out = nullptr, double* host_out = nullptr);
 int dot_partials();
 // out[r] = x[r] / |x[r]|, nrm2[r] = |x[r]|^2 (one launch)
 rfcmp_status normalize_rows(int64_t n, const double2* x, double2* out, double2* nrm2, int nr, hipStream_t s);

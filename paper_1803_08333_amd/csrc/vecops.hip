@@ -247,7 +247,8 @@ __global__ __launch_bounds__(256) void k_dot_partial(long n, const double2* __re
 }
 
 __global__ __launch_bounds__(256) void k_dot_final(int nb, const double2* __restrict__ part,
-                                                   double2* __restrict__ out) {
+                                                   double2* __restrict__ out, double* __restrict__ re_out,
+                                                   double* __restrict__ host_out) {
   __shared__ double sr[256], si[256];
   const long r = blockIdx.x;
   double ar = 0.0, ai = 0.0;
@@ -265,14 +266,19 @@ __global__ __launch_bounds__(256) void k_dot_final(int nb, const double2* __rest
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[r] = make_double2(sr[0], si[0]);
+  if (threadIdx.x == 0) {
+    out[r] = make_double2(sr[0], si[0]);
+    if (re_out) re_out[r] = sr[0];
+    if (host_out) host_out[r] = sr[0];
+  }
 }
 
 // out[r] = sum_i conj(a[r][i]) b[r][i] in one workgroup per row (rows up
 // to kDotOneBlock entries): strided per thread, then block_sum_1024.
 constexpr long kDotOneBlock = 1L << 16;
 __global__ __launch_bounds__(1024) void k_dot_rows(long n, const double2* __restrict__ a,
-                                                   const double2* __restrict__ b, double2* __restrict__ out) {
+                                                   const double2* __restrict__ b, double2* __restrict__ out,
+                                                   double* __restrict__ re_out, double* __restrict__ host_out) {
   __shared__ double sr[16], si[16];
   const long r = blockIdx.x;
   double ar = 0.0, ai = 0.0;
@@ -283,7 +289,11 @@ __global__ __launch_bounds__(1024) void k_dot_rows(long n, const double2* __rest
     ai += x.x * y.y - x.y * y.x;
   }
   const double2 t = block_sum_1024(ar, ai, sr, si);
-  if (threadIdx.x == 0) out[r] = t;
+  if (threadIdx.x == 0) {
+    out[r] = t;
+    if (re_out) re_out[r] = t.x;
+    if (host_out) host_out[r] = t.x;
+  }
 }
 
 // x[r] *= 1/sqrt(re(nrm2[r]))
@@ -436,12 +446,12 @@ rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double
   return RFCMP_OK;
 }
 rfcmp_status dot(int64_t n, const double2* a, const double2* b, double2* part, double2* out, int nr,
-                 hipStream_t s) {
+                 hipStream_t s, double* re_out, double* host_out) {
   if (n <= kDotOneBlock) {
-    hipLaunchKernelGGL(k_dot_rows, dim3(nr), dim3(1024), 0, s, (long)n, a, b, out);
+    hipLaunchKernelGGL(k_dot_rows, dim3(nr), dim3(1024), 0, s, (long)n, a, b, out, re_out, host_out);
   } else {
     hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks, nr), dim3(256), 0, s, (long)n, a, b, part);
-    hipLaunchKernelGGL(k_dot_final, dim3(nr), dim3(256), 0, s, kRedBlocks, part, out);
+    hipLaunchKernelGGL(k_dot_final, dim3(nr), dim3(256), 0, s, kRedBlocks, part, out, re_out, host_out);
   }
   RF_LAUNCH_CHECK();
   return RFCMP_OK;
