@@ -3,6 +3,9 @@
 #include <algorithm>
 #include <cmath>
 
+#include <memory>
+#include <vector>
+
 #include "internal.h"
 
 namespace rfcmp {
@@ -350,9 +353,12 @@ rfcmp_status spd_inverse_many(const SpdInverseJob* jobs, int njobs) {
     steps = std::max(steps, int(j.n / kB));
   }
   // the jobs' launches interleaved step by step, so that every stream has
-  // work queued from the start
-  for (int q = 0; q < njobs; ++q)
+  // work queued from the start; each job is timed on its own stream
+  std::vector<std::unique_ptr<ProfScope>> prof(njobs);
+  for (int q = 0; q < njobs; ++q) {
+    prof[q] = std::make_unique<ProfScope>("spd_inverse", jobs[q].s);
     hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, jobs[q].s, jobs[q].A, (long)jobs[q].n, 0);
+  }
   for (int K = 0; K < steps; ++K)
     for (int q = 0; q < njobs; ++q) {
       const SpdInverseJob& j = jobs[q];
@@ -367,6 +373,7 @@ rfcmp_status spd_inverse_many(const SpdInverseJob* jobs, int njobs) {
     const long total = (long)j.n * j.n;
     hipLaunchKernelGGL(k_gj_finish, dim3(unsigned((total + 255) / 256)), dim3(256), 0, j.s, j.A, (long)j.n,
                        (long)j.nvalid, j.shift);
+    prof[q].reset();
   }
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
@@ -374,7 +381,6 @@ rfcmp_status spd_inverse_many(const SpdInverseJob* jobs, int njobs) {
 
 rfcmp_status spd_inverse(double* A, int64_t n, int64_t nvalid, double shift, double* ubuf, double* rbuf,
                          hipStream_t s) {
-  ProfScope prof("spd_inverse", s);
   const SpdInverseJob j{A, n, nvalid, shift, ubuf, rbuf, s};
   return spd_inverse_many(&j, 1);
 }
