@@ -7,12 +7,18 @@ names of include/rfcmp.h; ``Mesh`` and ``Operator`` wrap the handles.
 
 The library must be built first (``python paper_1803_08333_amd/build.py``);
 importing this module without it raises, there is no fallback path.
+
+torch is imported before the library is loaded.  torch brings its own HIP
+runtime; when the library (linked against the system ROCm) is loaded first,
+its first HIP call in a process that later initialises torch finds no
+device, whereas with torch's runtime loaded first both see the GPU.
 """
 
 import ctypes
 import os
 
 import numpy as np
+import torch  # noqa: F401  (load order of the HIP runtimes, see above)
 
 __all__ = [
     "LIB_PATH", "RfcmpError", "Options", "Info", "Mesh", "Operator", "lib",

@@ -474,3 +474,21 @@ def test_create_many_matches_single():
         rf.Operator.create_many(m, [1.0, -1.0], power_start=start)
     m1.close()
     m.close()
+
+
+def test_package_imported_before_torch():
+    """The package loads torch's HIP runtime ahead of the library's: a fresh
+    process that imports the package first, torch second, still creates an
+    operator (with the library's runtime loaded first, its first HIP call
+    found no device)."""
+    import subprocess
+    import sys
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1803_08333_amd as rf\n"
+            "import torch, synth\n"
+            "m = rf.Mesh(*synth.icosphere(1))\n"
+            "op = rf.Operator(m, 1.0, scaling=1)\n"
+            "print('ok', op.scalings()[0])\n") % root
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.startswith("ok"), out.stderr[-2000:]
