@@ -157,8 +157,8 @@ rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* 
  * while every other RWG function has none, so e_m = V.  With rfcmp_solve
  * (T j = -e) the gap's input power is Re(V conj(j_m))/2 in units of 1/eta.
  * edges: host int32 [nrhs][ngap], each in [0, N); volts: host c128
- * [nrhs][ngap]; ngap may be 0 (e = 0); e: device c128 [nrhs][N].  Waits
- * for the stream before returning. */
+ * [nrhs][ngap]; ngap may be 0 (e = 0), ngap * nrhs <= 2^26; e: device c128
+ * [nrhs][N].  Waits for the stream before returning. */
 rfcmp_status rfcmp_rhs_gap(rfcmp_mesh m, const int32_t* edges, const void* volts, int32_t ngap, int32_t nrhs,
                            void* e, void* stream);
 

@@ -965,6 +965,7 @@ rfcmp_status rfcmp_rhs_gap(rfcmp_mesh m, const int32_t* edges, const void* volts
   RF_ARG(m && e, "NULL argument");
   RF_ARG(nrhs > 0 && nrhs <= 65535 && ngap >= 0 && ngap <= (1 << 20), "nrhs must be in [1, 65535], ngap in [0, 2^20]");
   RF_ARG(ngap == 0 || (edges && volts), "NULL edges or volts");
+  RF_ARG((int64_t)ngap * nrhs <= (int64_t)1 << 26, "at most 2^26 gaps in all");
   for (int64_t t = 0; t < (int64_t)ngap * nrhs; ++t)
     RF_ARG(edges[t] >= 0 && edges[t] < m->h.N, "gap edge index out of range");
   return rhs_gap(m, edges, static_cast<const double2*>(volts), ngap, nrhs, static_cast<double2*>(e),
