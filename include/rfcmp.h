@@ -98,10 +98,16 @@ typedef struct {
   int32_t outer_star;     /* 0 = P_Sigma (Sec. 4, default), 1 = Gram-weighted P_gSigma (Sec. 3) */
   int32_t scaling;        /* 0 = alpha/beta/gamma by power iteration (Sec. 4, default),
                              1 = alpha = sqrt(k), beta = 1/sqrt(k), gamma = k */
-  int32_t power_iters;    /* power-iteration steps, default 30 */
+  int32_t power_iters;    /* most power-iteration steps, default 30 */
   int32_t precision;      /* 0 = complex64 operator, FP64 accumulation (default);
                              1 = BF16x3 split products on MFMA for batched solves,
                                  FP64-accumulated residual refinement */
+  double power_tol;       /* early stop of the power iteration, default 1e-2: the
+                             scalings are formed every 5 steps and the iteration
+                             stops at the first check from step 10 on where each
+                             of alpha, beta, gamma moved by less than power_tol
+                             (relative) since the previous check; 0 = always
+                             power_iters steps */
 } rfcmp_options;
 rfcmp_status rfcmp_options_default(rfcmp_options* opt);
 
@@ -133,10 +139,13 @@ rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt,
 rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, const rfcmp_options* opt,
                                   const void* power_start, void* stream, rfcmp_op* out);
 /* Current scalings (Sec. 4).  lam (nullable, host double [3]) receives the
- * three power-iteration norm estimates (0 for k-scaling). */
+ * three power-iteration norm estimates (0 for k-scaling).  The number of
+ * power-iteration steps run is reported by rfcmp_op_power_steps. */
 rfcmp_status rfcmp_op_scalings(rfcmp_op op, double* alpha, double* beta, double* gamma, double* lam);
 /* Override the scalings (all > 0).  The solution j does not depend on them. */
 rfcmp_status rfcmp_op_set_scalings(rfcmp_op op, double alpha, double beta, double gamma);
+/* Power-iteration steps run when the operator was created (0 for k-scaling). */
+rfcmp_status rfcmp_op_power_steps(rfcmp_op op, int32_t* steps);
 /* Copy the blocks to caller device buffers: TA c64 [N][N], V c64 [C][C]
  * (either nullable). */
 rfcmp_status rfcmp_op_export(rfcmp_op op, void* TA, void* V, void* stream);

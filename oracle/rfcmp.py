@@ -74,18 +74,40 @@ class Preconditioner:
         Ob = lambda v: P_S @ (np.conj(self.TPhi) @ (self.MS_hat @ (self.TPhi @ (P_S @ v))))
         return Oa, Ob, Og
 
-    def power_scalings(self, start, steps=30):
-        """alpha, beta, gamma from ``steps`` power iterations from ``start``."""
+    def power_scalings(self, start, steps=30, tol=0.0):
+        """alpha, beta, gamma (Sec. 4) from power iterations from ``start``.
+
+        The three operators are iterated side by side.  With tol = 0 all
+        ``steps`` steps run.  With tol > 0 the scalings are formed every
+        POWER_CHECK steps, and the iteration stops at the first check from
+        2 POWER_CHECK steps on where each of alpha, beta, gamma moved by less
+        than tol (relative) since the previous check; ``steps`` is then the
+        most it runs.  Returns (alpha, beta, gamma, (la, lb, lg), steps run)."""
         k = self.k
-        Oa, Ob, Og = self.scaling_operators()
-        la = power_norm(Oa, start, steps)
-        lb = power_norm(Ob, start, steps)
-        lg = power_norm(Og, start, steps)
-        alpha = (k * k * la) ** 0.25
-        beta = (lb / (k * k)) ** 0.25
-        gamma = k * k * lg / alpha ** 2
+        ops = self.scaling_operators()
+        v = [start / np.linalg.norm(start) for _ in range(3)]
+        lam = [0.0, 0.0, 0.0]
+
+        def scal(la, lb, lg):
+            alpha = (k * k * la) ** 0.25
+            return alpha, (lb / (k * k)) ** 0.25, k * k * lg / alpha ** 2
+
+        prev = None
+        done = 0
+        for it in range(steps):
+            for q in range(3):
+                wv = ops[q](v[q])
+                lam[q] = np.linalg.norm(wv)
+                v[q] = wv / lam[q]
+            done = it + 1
+            if tol > 0 and done % POWER_CHECK == 0:
+                cur = scal(*lam)
+                if prev is not None and all(abs(c - p) <= tol * abs(c) for c, p in zip(cur, prev)):
+                    break
+                prev = cur
+        alpha, beta, gamma = scal(*lam)
         self.set_scalings(alpha, beta, gamma)
-        return alpha, beta, gamma, (la, lb, lg)
+        return alpha, beta, gamma, tuple(lam), done
 
     # ----- dense matrices ---------------------------------------------------
     def T(self):
@@ -156,6 +178,9 @@ class Preconditioner:
     def recover(self, i):
         """j = P_o i (eq. NewFormulation)."""
         return self.P_LH @ i / self.alpha + 1j * (self.P_s @ i) / self.beta
+
+
+POWER_CHECK = 5  # steps between convergence checks of the power iteration
 
 
 def power_norm(op, start, steps):

@@ -46,7 +46,7 @@ class RfcmpError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("near_factor", ctypes.c_double), ("outer_star", ctypes.c_int32),
                 ("scaling", ctypes.c_int32), ("power_iters", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("power_tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -80,6 +80,7 @@ EXPORTED = {
     "rfcmp_op_create_many": (_I32, [_P, _PD, _I32, ctypes.POINTER(Options), _P, _P, ctypes.POINTER(_P)]),
     "rfcmp_op_scalings": (_I32, [_P, _PD, _PD, _PD, _PD]),
     "rfcmp_op_set_scalings": (_I32, [_P, _D, _D, _D]),
+    "rfcmp_op_power_steps": (_I32, [_P, _PI32]),
     "rfcmp_op_export": (_I32, [_P, _P, _P, _P]),
     "rfcmp_op_destroy": (None, [_P]),
     "rfcmp_rhs_planewave": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
@@ -264,6 +265,12 @@ class Operator:
         lam = (_D * 3)()
         _check(lib.rfcmp_op_scalings(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(g), lam))
         return a.value, b.value, g.value, tuple(lam)
+
+    def power_steps(self):
+        """rfcmp_op_power_steps: power-iteration steps run at creation."""
+        n = _I32()
+        _check(lib.rfcmp_op_power_steps(self.handle, ctypes.byref(n)))
+        return n.value
 
     def set_scalings(self, alpha, beta, gamma):
         _check(lib.rfcmp_op_set_scalings(self.handle, alpha, beta, gamma))

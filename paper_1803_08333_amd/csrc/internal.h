@@ -187,6 +187,7 @@ struct rfcmp_op_s {
   ~rfcmp_op_s();
   rfcmp_mesh mesh = nullptr;
   double k = 0;
+  int power_steps = 0;  // power-iteration steps run (0 for k-scaling)
   rfcmp_options opt{};
   double alpha = 0, beta = 0, gamma = 0;
   double lam[3] = {0, 0, 0};

@@ -375,7 +375,23 @@ rfcmp_status power_apply(const Dense& D, const Work& W, bool project_in) {
   return power_next(d, N, C, W.nD, W.c[5], W.c[10], W.pv, W.dout, s);
 }
 
-rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStream_t s) {
+// alpha, beta, gamma from the three power-iteration norms (rows alpha,
+// gamma, beta of W.dout), reading 3 of the Sec. 4 norms
+struct Scalings {
+  double a, b, g;
+};
+Scalings scalings_of(double k, const double2 (&nr2)[3]) {
+  const double la = std::sqrt(nr2[0].x), lg = std::sqrt(nr2[1].x), lb = std::sqrt(nr2[2].x);
+  const double a = std::pow(k * k * la, 0.25);
+  return {a, std::pow(lb / (k * k), 0.25), k * k * lg / (a * a)};
+}
+
+// The three power iterations side by side, at most `steps` steps.  With
+// tol > 0 the scalings are read every kPowerCheck steps, and the iteration
+// stops at the first check from 2 kPowerCheck steps on where each of alpha,
+// beta, gamma moved by less than tol (relative) since the previous check.
+constexpr int kPowerCheck = 5;
+rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, double tol, hipStream_t s) {
   const int64_t N = op->mesh->h.N;
   RF_TRY(ensure_work(op, 4));
   const Work W = carve(op);
@@ -385,22 +401,40 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, hipStr
   RF_TRY(normalize_rows(N, W.pw, W.pv, W.dout, 3, s));
   // each application ends with the next normalised vectors in W.pv and the
   // squared norms of the raw ones in W.dout
-  for (int it = 0; it < steps; ++it) RF_TRY(power_apply(D, W, it == 0));
-  double2 nr2[3];
-  RF_HIP(hipMemcpyAsync(nr2, W.dout, sizeof nr2, hipMemcpyDeviceToHost, s));
+  double2* hn = reinterpret_cast<double2*>(op->host_scal);  // pinned
+  const double k = op->k;
+  Scalings prev{0.0, 0.0, 0.0};
+  int done = 0;
+  for (int it = 0; it < steps; ++it) {
+    RF_TRY(power_apply(D, W, it == 0));
+    done = it + 1;
+    if (tol > 0 && done % kPowerCheck == 0 && done < steps) {
+      RF_HIP(hipMemcpyAsync(hn, W.dout, sizeof(double2) * 3, hipMemcpyDeviceToHost, s));
+      RF_HIP(hipStreamSynchronize(s));
+      const double2 nr2[3] = {hn[0], hn[1], hn[2]};
+      const Scalings cur = scalings_of(k, nr2);
+      const bool conv = done >= 2 * kPowerCheck && std::fabs(cur.a - prev.a) <= tol * cur.a &&
+                        std::fabs(cur.b - prev.b) <= tol * cur.b && std::fabs(cur.g - prev.g) <= tol * cur.g;
+      prev = cur;
+      if (conv) break;
+    }
+  }
+  RF_HIP(hipMemcpyAsync(hn, W.dout, sizeof(double2) * 3, hipMemcpyDeviceToHost, s));
   RF_HIP(hipStreamSynchronize(s));
+  const double2 nr2[3] = {hn[0], hn[1], hn[2]};
   const double la = std::sqrt(nr2[0].x), lg = std::sqrt(nr2[1].x), lb = std::sqrt(nr2[2].x);
   if (!(la > 0) || !(lb > 0) || !(lg > 0) || !std::isfinite(la + lb + lg)) {
     set_error("power iteration produced a non-positive norm (%g, %g, %g)", la, lb, lg);
     return RFCMP_E_STATE;
   }
-  const double k = op->k;
+  const Scalings sc = scalings_of(k, nr2);
   op->lam[0] = la;
   op->lam[1] = lb;
   op->lam[2] = lg;
-  op->alpha = std::pow(k * k * la, 0.25);
-  op->beta = std::pow(lb / (k * k), 0.25);
-  op->gamma = k * k * lg / (op->alpha * op->alpha);
+  op->alpha = sc.a;
+  op->beta = sc.b;
+  op->gamma = sc.g;
+  op->power_steps = done;
   return RFCMP_OK;
 }
 
@@ -834,6 +868,7 @@ rfcmp_status rfcmp_options_default(rfcmp_options* o) {
   o->scaling = 0;
   o->power_iters = 30;
   o->precision = 0;
+  o->power_tol = 1e-2;
   return RFCMP_OK;
 }
 
@@ -859,6 +894,7 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
   RF_ARG(o.scaling == 0 || o.scaling == 1, "scaling must be 0 or 1");
   RF_ARG(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
   RF_ARG(o.scaling == 1 || (o.power_iters > 0 && power_start), "power scalings need power_iters > 0 and power_start");
+  RF_ARG(std::isfinite(o.power_tol) && o.power_tol >= 0, "power_tol must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   RF_HIP(hipGetDevice(&dev));
@@ -893,7 +929,7 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
     op->beta = 1.0 / std::sqrt(k[i]);
     op->gamma = k[i];
     if (o.scaling == 0)
-      RF_TRY(power_scalings(op, static_cast<const double2*>(power_start), o.power_iters, s));
+      RF_TRY(power_scalings(op, static_cast<const double2*>(power_start), o.power_iters, o.power_tol, s));
     if (o.precision == 1) RF_TRY(ensure_split(op, s));
   }
   RF_HIP(hipStreamSynchronize(s));
@@ -908,6 +944,12 @@ rfcmp_status rfcmp_op_scalings(rfcmp_op op, double* a, double* b, double* g, dou
   if (g) *g = op->gamma;
   if (lam)
     for (int i = 0; i < 3; ++i) lam[i] = op->lam[i];
+  return RFCMP_OK;
+}
+
+rfcmp_status rfcmp_op_power_steps(rfcmp_op op, int32_t* steps) {
+  RF_ARG(op && steps, "NULL argument");
+  *steps = op->power_steps;
   return RFCMP_OK;
 }
 

@@ -163,16 +163,25 @@ def test_operator_steps_exact_on_stored_blocks(name, k, star):
 
 @pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5)])
 def test_power_scalings_match_oracle(name, k):
+    """alpha, beta, gamma against the oracle's power iteration on the
+    exported blocks: 30 fixed steps (power_tol = 0), and the default early
+    stop (power_tol = 1e-2), which must stop at the same step."""
     torch, rf = _gpu()
     top, _, _ = _oracle(name, k)
     op = _gpu_op(name, k, 0, 0)
     gTA, gV = (_np(t).astype(np.complex128) for t in op.export())
     pre = rfcmp.Preconditioner(top, gTA, gV, k)
-    ref = pre.power_scalings(synth.complex_start(top.N, 11), 30)
-    a, b, g, lam = op.scalings()
-    assert abs(a - ref[0]) < 1e-10 * ref[0]
-    assert abs(b - ref[1]) < 1e-10 * ref[1]
-    assert abs(g - ref[2]) < 1e-10 * ref[2]
+    start = synth.complex_start(top.N, 11)
+    op30 = rf.Operator(_gpu_mesh(name), k, power_start=_cuda(start), scaling=0, power_tol=0.0)
+    for o, (tol, steps) in ((op30, (0.0, 30)), (op, (1e-2, 30))):
+        ref = pre.power_scalings(start, steps, tol=tol)
+        a, b, g, lam = o.scalings()
+        assert o.power_steps() == ref[4], (o.power_steps(), ref[4])
+        assert abs(a - ref[0]) < 1e-10 * ref[0]
+        assert abs(b - ref[1]) < 1e-10 * ref[1]
+        assert abs(g - ref[2]) < 1e-10 * ref[2]
+    assert op.power_steps() < 30
+    op30.close()
 
 
 @pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 0.1), ("ico2", 1e-4), ("torus_small", 0.5),

@@ -307,3 +307,27 @@ def test_middle_gram_mistake_changes_iterations_not_solution(monkeypatch):
     pre.set_scalings(1.0, 1.0, 1.0)
     A = pre.system_split()
     assert np.abs(A - A.conj().T).max() < 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5)])
+def test_power_iteration_early_stop(name, k):
+    """The adaptive stop of the power iteration: with tol = 0 the three
+    operators iterated side by side give exactly the separate power_norm
+    estimates; with tol = 1e-2 it stops at a check (a multiple of 5 steps,
+    at least 10), every scaling within 3e-2 of its 60-step value, and CG
+    needs the same number of iterations on the resulting system."""
+    top = topo(name)
+    TA, V = blocks(name, k)
+    start = synth.complex_start(top.N, 11)
+    pre = rfcmp.Preconditioner(top, TA, V, k)
+    Oa, Ob, Og = pre.scaling_operators()
+    *_, lam, n = pre.power_scalings(start, 30)
+    assert n == 30 and lam == tuple(rfcmp.power_norm(o, start, 30) for o in (Oa, Ob, Og))
+    e = rhs.planewave(top, k, *synth.default_plane_wave())[0]
+    ref = pre.power_scalings(start, 60)[:3]
+    it_ref = rfcmp.cg(lambda x: pre.system_split() @ x, pre.rhs(e), 1e-6, 1000)[1]
+    a, b, g, _, n = pre.power_scalings(start, 30, tol=1e-2)
+    assert n % rfcmp.POWER_CHECK == 0 and 2 * rfcmp.POWER_CHECK <= n < 30, n
+    assert all(abs(x - y) < 3e-2 * y for x, y in zip((a, b, g), ref))
+    A = pre.system_split()
+    assert rfcmp.cg(lambda x: A @ x, pre.rhs(e), 1e-6, 1000)[1] == it_ref
