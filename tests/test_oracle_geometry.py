@@ -234,3 +234,31 @@ def test_laplacian_pseudo_inverse_identity(name):
     rhs = np.linalg.pinv(L) + J
     assert np.abs(lhs - rhs).max() < 1e-11 * np.abs(rhs).max()
     assert np.all(np.diag(L) == 3)
+
+
+def test_uneven_batch_recipe():
+    """The seeded uneven batch: 32 closed meshes of the three kinds with the
+    recipe's size ranges, reproducible, and 4 unit plane waves per item with
+    polarisations orthogonal to their directions."""
+    from synth import batch
+    objs = batch.uneven_objects()
+    again = batch.uneven_objects()
+    assert len(objs) == 32
+    for o, p in zip(objs, again):
+        assert o["kind"] == p["kind"] and np.array_equal(o["xyz"], p["xyz"]) and np.array_equal(o["tri"], p["tri"])
+        top = Topology(o["xyz"], o["tri"])
+        assert top.genus == 0
+        if o["kind"] == "cube":
+            n = int(o["param"].split()[1])
+            assert 8 <= n <= 32 and top.C == 12 * n * n
+        else:
+            level = int(o["param"].split(",")[0].split()[1])
+            assert 2 <= level <= 4 and top.C == 20 * 4 ** level
+        if o["kind"] == "ellipsoid":
+            axes = [float(a) for a in o["param"].split("axes")[1].split(",")]
+            assert all(0.5 <= a <= 1.5 for a in axes)
+    assert {o["kind"] for o in objs} == {"icosphere", "cube", "ellipsoid"}
+    ks = batch.sweep_wavenumbers()
+    assert len(ks) == 8 and ks[0] == 1e-3 and abs(ks[-1] - 5.0) < 1e-12
+    kh, pol = batch.sweep_waves(3, 5)
+    assert kh.shape == (4, 3) and np.allclose(np.linalg.norm(kh, axis=1), 1) and np.allclose(np.sum(kh * pol, 1), 0)
