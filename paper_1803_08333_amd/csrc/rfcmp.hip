@@ -709,6 +709,7 @@ bool unit(const double* v) {
 namespace rfcmp {
 namespace {
 struct ProfState {
+  std::mutex mu;  // calls on different operators may run on several host threads
   bool on = false;
   std::vector<std::string> only;  // empty: every tag
   std::vector<hipEvent_t> pool;  // all events ever created (reused)
@@ -736,6 +737,7 @@ bool profiling_selected(const char* tag) {
 }
 hipEvent_t profile_event() {
   ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
   if (p.next == p.pool.size()) {
     hipEvent_t e;
     // timing only: no system-scope fence (cache write-back) at each record,
@@ -745,7 +747,11 @@ hipEvent_t profile_event() {
   }
   return p.pool[p.next++];
 }
-void profile_record(const char* tag, hipEvent_t a, hipEvent_t b) { prof().rec.emplace_back(tag, a, b); }
+void profile_record(const char* tag, hipEvent_t a, hipEvent_t b) {
+  ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.rec.emplace_back(tag, a, b);
+}
 }  // namespace rfcmp
 
 using namespace rfcmp;
@@ -765,6 +771,7 @@ const char* rfcmp_version(void) { return "rfcmp 0.1 (gfx950)"; }
 
 rfcmp_status rfcmp_profile_enable(int32_t on) {
   ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
   for (auto& r : p.rec) (void)hipEventSynchronize(std::get<2>(r));
   p.rec.clear();
   p.next = 0;
@@ -793,7 +800,9 @@ rfcmp_status rfcmp_profile_read(const char* tag, double* total_ms, int64_t* laun
   RF_ARG(tag && total_ms && launches, "NULL argument");
   double t = 0.0;
   int64_t n = 0;
-  for (auto& r : prof().rec) {
+  ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  for (auto& r : p.rec) {
     if (std::get<0>(r) != tag) continue;
     RF_HIP(hipEventSynchronize(std::get<2>(r)));
     float ms = 0.f;
