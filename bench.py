@@ -52,7 +52,8 @@ def parse():
     p.add_argument("--no-spectral-study", action="store_true")
     p.add_argument("--batch-rhs", type=int, default=64)
     p.add_argument("--uneven-batch", action="store_true",
-                   help="also time the uneven batch (32 objects x 8 wavenumbers x 4 plane waves, BF16x3)")
+                   help="also time the uneven batch (32 objects x 8 wavenumbers x 4 plane waves, BF16x3), "
+                        "through rfcmp_batch_solve and through one rfcmp_solve per operator")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     return p.parse_args()
@@ -298,45 +299,73 @@ def voltage_gap_measurement(rf, torch):
     return out
 
 
-def uneven_batch(rf, torch):
+def uneven_batch(rf, torch, concurrent=True, budget_gb=64.0):
     """The seeded uneven batch (32 icospheres, cubes and ellipsoids, N from
     480 to 16 200; 8 wavenumbers from 1e-3 to 5; 4 plane waves each): per
     object one rfcmp_op_create_many over the sweep (assembly, projectors,
-    power iterations), then a 4-right-hand-side BF16x3 solve with refinement
-    to 1e-6 per wavenumber.  Whole-batch wall time, right-hand sides solved
-    per second, and the iteration counts (the top wavenumber sits next to
-    interior resonances of these bodies)."""
+    power iterations), then 4-right-hand-side BF16x3 solves with refinement
+    to 1e-6.  concurrent: the objects are taken in groups whose operators
+    (complex64 blocks and their BF16x3 planes) fit in budget_gb of device
+    memory, and each group's solves go through one rfcmp_batch_solve;
+    otherwise one object at a time and one rfcmp_solve per wavenumber.
+    Whole-batch wall time, right-hand sides solved per second, and the
+    iteration counts (the top wavenumber sits next to interior resonances of
+    these bodies)."""
     from synth import batch
     objs = batch.uneven_objects()
     ks = batch.sweep_wavenumbers()
+    groups, cur, used = [], [], 0.0
+    for o, obj in enumerate(objs):
+        C = len(obj["tri"])
+        N = C * 3 // 2
+        gb = len(ks) * (N * N + C * C) * 16 / 1e9
+        if cur and (not concurrent or used + gb > budget_gb):
+            groups.append(cur)
+            cur, used = [], 0.0
+        cur.append(o)
+        used += gb
+    groups.append(cur)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, t_setup, t_solve, bad = [], 0.0, 0.0, 0
-    for o, obj in enumerate(objs):
+    for g in groups:
         ta = time.perf_counter()
-        m = rf.Mesh(obj["xyz"], obj["tri"])
-        start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
-        ops = rf.Operator.create_many(m, ks, power_start=start, precision=1)
+        meshes, ops, es, kidx = [], [], [], []
+        for o in g:
+            m = rf.Mesh(objs[o]["xyz"], objs[o]["tri"])
+            meshes.append(m)
+            start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
+            for q, op in enumerate(rf.Operator.create_many(m, ks, power_start=start, precision=1)):
+                kh, pol = batch.sweep_waves(o, q)
+                ops.append(op)
+                es.append(op.rhs_planewave(kh, pol))
+                kidx.append(q)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        for q, op in enumerate(ops):
-            kh, pol = batch.sweep_waves(o, q)
-            _, st, info = op.solve(op.rhs_planewave(kh, pol), tol=1e-6, maxit=4000)
-            bad += st != 0
-            iters.append((q, max(i["iters"] for i in info)))
+        if concurrent:
+            infos = rf.batch_solve(ops, es, tol=1e-6, maxit=4000)[2]
+        else:
+            infos = [op.solve(e, tol=1e-6, maxit=4000)[2] for op, e in zip(ops, es)]
         torch.cuda.synchronize()
         t_setup += tb - ta
         t_solve += time.perf_counter() - tb
+        for q, info in zip(kidx, infos):
+            bad += any(not i["rel_residual"] <= 1e-6 for i in info)
+            iters.append((q, max(i["iters"] for i in info)))
+        del es
         for op in ops:
             op.close()
-        m.close()
+        for m in meshes:
+            m.close()
         rf.release_cached_memory()
     wall = time.perf_counter() - t0
     nrhs = len(objs) * len(ks) * 4
     low = [i for q, i in iters if q < len(ks) - 1]
     top = [i for q, i in iters if q == len(ks) - 1]
-    return {"objects": len(objs), "wavenumbers": len(ks), "rhs": nrhs, "wall_s": wall, "setup_s": t_setup,
-            "solve_s": t_solve, "rhs_per_s": nrhs / wall, "not_converged": int(bad),
+    return {"objects": len(objs), "wavenumbers": len(ks), "rhs": nrhs,
+            "solver": "rfcmp_batch_solve" if concurrent else "rfcmp_solve", "groups": len(groups),
+            "wall_s": wall, "setup_s": t_setup, "solve_s": t_solve, "rhs_per_s": nrhs / wall,
+            "not_converged": int(bad),
             "iters_below_top_k": {"median": float(np.median(low)), "max": int(max(low))},
             "iters_top_k": {"median": float(np.median(top)), "max": int(max(top))}}
 
@@ -473,6 +502,7 @@ def main():
         res["voltage_gap"] = voltage_gap_measurement(rf, torch)
     if args.uneven_batch:
         res["uneven_batch"] = uneven_batch(rf, torch)
+        res["uneven_batch_serial"] = uneven_batch(rf, torch, concurrent=False)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(xyz, tri, args.cpu_slab)
     print(json.dumps(res))

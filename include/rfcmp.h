@@ -261,6 +261,30 @@ rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, doub
 rfcmp_status rfcmp_solve_system(rfcmp_op op, const void* b, void* i, int32_t nrhs, double tol,
                                 int32_t maxit, void* stream, rfcmp_info* info);
 
+/* rfcmp_solve for several operators at once (a batch of objects and
+ * wavenumbers, each solved as in Sec. 3.4): operator q solves T_q j_q = -e_q
+ * for nrhs[q] right-hand sides, e[q], j[q] device c128 [nrhs[q]][N_q], not
+ * aliased; tol and maxit are shared.  The solves run concurrently, up to four
+ * at a time, each on an internal stream (default priority) driven by a host
+ * thread; largest N * nrhs first.  These streams start after the work queued
+ * on `stream` before the call, and `stream` waits for them; the call returns
+ * when every solve has finished.  Each operator's result and report are those
+ * of rfcmp_solve on it alone, bit for bit.
+ *   ops: host [nops], distinct handles (two entries may share a mesh) whose
+ *        mesh lives on the calling thread's current device;
+ *   e, j, nrhs: host [nops];
+ *   info: host [sum of nrhs], nullable: the reports in ops order, ms_solve
+ *        the wall time of that operator's solve.
+ * Workspaces and BF16x3 planes are set up on `stream` before the solves
+ * start.  Returns the first error in ops order (rfcmp_last_error names the
+ * operator; the other operators are still solved), else
+ * RFCMP_W_NOT_CONVERGED if any solve stopped at maxit, else RFCMP_OK.
+ * Argument errors (NULL, aliased, nrhs <= 0, a repeated handle, another
+ * device) are found before anything is enqueued. */
+rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* const* e, void* const* j,
+                               const int32_t* nrhs, double tol, int32_t maxit, void* stream,
+                               rfcmp_info* info);
+
 /* ------------------------------------------------------------ profiling */
 /* Kernel timing for benchmarks.  While enabled, the library records a HIP
  * event pair on the launch stream around every launch of its timed kernels:

@@ -23,7 +23,7 @@ import torch  # noqa: F401  (load order of the HIP runtimes, see above)
 __all__ = [
     "LIB_PATH", "RfcmpError", "Options", "Info", "Mesh", "Operator", "lib",
     "PROJ_SIGMA", "PROJ_LH", "PROJ_GSIGMA", "PROJ_LPINV", "PROJ_GLL_INV", "PROJ_SIGMA_T", "PROJ_LAMBDA_T",
-    "EXPORTED",
+    "EXPORTED", "batch_solve",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfcmp.so")
@@ -93,6 +93,8 @@ EXPORTED = {
     "rfcmp_matvec": (_I32, [_P, _I32, _I32, _P, _P, _I32, _P]),
     "rfcmp_solve": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, ctypes.POINTER(Info)]),
     "rfcmp_solve_system": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, ctypes.POINTER(Info)]),
+    "rfcmp_batch_solve": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P), ctypes.POINTER(_P), _PI32, _D, _I32,
+                                 _P, ctypes.POINTER(Info)]),
     "rfcmp_profile_enable": (_I32, [_I32]),
     "rfcmp_profile_read": (_I32, [ctypes.c_char_p, _PD, _PI64]),
     "rfcmp_profile_select": (_I32, [ctypes.c_char_p]),
@@ -367,3 +369,27 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def batch_solve(ops, es, tol=1e-6, maxit=1000):
+    """rfcmp_batch_solve: the solves of several operators (distinct
+    ``Operator`` objects, meshes may be shared) run concurrently; es[q] holds
+    operator q's right-hand sides (c128 [nrhs][N] or [N]).  Returns
+    (js, status, [list of info dicts per operator])."""
+    torch = _torch()
+    n = len(ops)
+    if n == 0 or len(es) != n:
+        raise ValueError("need one right-hand-side tensor per operator")
+    es = [e.contiguous() for e in es]
+    js = [torch.empty_like(e) for e in es]
+    nr = [e.shape[0] if e.dim() == 2 else 1 for e in es]
+    hs = (_P * n)(*[op.handle for op in ops])
+    ep = (_P * n)(*[_dptr(e, torch.complex128, r * op.mesh.N).value for e, r, op in zip(es, nr, ops)])
+    jp = (_P * n)(*[_dptr(x).value for x in js])
+    info = (Info * sum(nr))()
+    st = _check(lib.rfcmp_batch_solve(hs, n, ep, jp, (_I32 * n)(*nr), tol, maxit, _stream(), info))
+    out, k = [], 0
+    for r in nr:
+        out.append([info[k + i].as_dict() for i in range(r)])
+        k += r
+    return js, st, out

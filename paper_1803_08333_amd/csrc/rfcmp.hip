@@ -16,11 +16,14 @@
 //   y  = -(ik/alpha)(zA - Sig s4) + Sig G6 [-(k/beta) s4 + (vw - mean vw)/(k beta)]
 // with G6 = I for P_Sigma and G_tp^-1 for P_gSigma.  Uses L^+ L = I - 1 1^T/C
 // and Sig^T P_LH = 0, Sig^T Lam = 0.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <set>
+#include <thread>
 #include <tuple>
 
 #include "gemm.h"
@@ -1136,6 +1139,10 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
   }
 }
 
+// Concurrent solves of rfcmp_batch_solve: at most one per hardware queue HIP
+// gives a process by default.
+constexpr int kBatchStreams = 4;
+
 static rfcmp_status solve_common(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,
                                  void* stream, rfcmp_info* info, bool system) {
   RF_ARG(op && e && j && e != j, "NULL or aliased argument");
@@ -1170,6 +1177,105 @@ rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, doub
 rfcmp_status rfcmp_solve_system(rfcmp_op op, const void* b, void* i, int32_t nrhs, double tol, int32_t maxit,
                                 void* stream, rfcmp_info* info) {
   return solve_common(op, b, i, nrhs, tol, maxit, stream, info, true);
+}
+
+// Several operators' solves at once.  Each is solve_common unchanged, on an
+// internal stream of its own driven by a host thread of its own: a CG
+// iteration of a small operator is bounded by launch and read-back latency
+// rather than by the device, and the solves of the other operators fill
+// those gaps.  Largest operators first, so that the last to start are short.
+rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* const* e, void* const* j,
+                               const int32_t* nrhs, double tol, int32_t maxit, void* stream, rfcmp_info* info) {
+  RF_ARG(ops && e && j && nrhs && nops > 0, "NULL argument or nops <= 0");
+  RF_ARG(maxit > 0 && std::isfinite(tol) && tol > 0, "bad maxit/tol");
+  std::vector<int64_t> off(nops + 1, 0);
+  for (int q = 0; q < nops; ++q) {
+    if (!(ops[q] && e[q] && j[q] && e[q] != j[q] && nrhs[q] > 0)) {
+      set_error("operator %d: NULL or aliased argument, or nrhs <= 0", q);
+      return RFCMP_E_ARG;
+    }
+    off[q + 1] = off[q] + nrhs[q];
+  }
+  {
+    std::vector<rfcmp_op> sorted(ops, ops + nops);
+    std::sort(sorted.begin(), sorted.end());
+    RF_ARG(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), "an operator appears twice");
+  }
+  int dev = 0;
+  RF_HIP(hipGetDevice(&dev));
+  for (int q = 0; q < nops; ++q)
+    if (ops[q]->mesh->device != dev) {
+      set_error("operator %d lives on device %d, current device is %d", q, ops[q]->mesh->device, dev);
+      return RFCMP_E_ARG;
+    }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // Workspaces and BF16x3 planes first, on the caller's stream and thread:
+  // growing a workspace synchronises the device, and the planes of a mesh
+  // that several operators share are built once.  The solves then allocate
+  // nothing.
+  for (int q = 0; q < nops; ++q) {
+    RF_TRY(ensure_work(ops[q], std::min(nrhs[q], 64)));
+    if (ops[q]->opt.precision == 1) RF_TRY(ensure_split(ops[q], s));
+  }
+  const int nw = std::min<int>(nops, kBatchStreams);
+  struct Streams {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> ev;
+    ~Streams() {
+      for (hipStream_t x : s) (void)hipStreamDestroy(x);
+      for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    }
+  } W;
+  for (int w = 0; w <= nw; ++w) {
+    hipEvent_t ev = nullptr;
+    RF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    W.ev.push_back(ev);
+  }
+  for (int w = 0; w < nw; ++w) {
+    hipStream_t x = nullptr;
+    RF_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));  // default priority
+    W.s.push_back(x);
+  }
+  RF_HIP(hipEventRecord(W.ev[nw], s));
+  for (int w = 0; w < nw; ++w) RF_HIP(hipStreamWaitEvent(W.s[w], W.ev[nw], 0));
+  std::vector<int> order(nops);
+  for (int q = 0; q < nops; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return ops[a]->mesh->h.N * nrhs[a] > ops[b]->mesh->h.N * nrhs[b]; });
+  std::atomic<int> next{0};
+  std::vector<rfcmp_status> status(nops, RFCMP_OK);
+  std::vector<std::string> msg(nops);
+  auto worker = [&](int w) {
+    const bool on_device = hipSetDevice(dev) == hipSuccess;
+    for (int t; (t = next.fetch_add(1)) < nops;) {
+      const int q = order[t];
+      if (!on_device) {
+        status[q] = RFCMP_E_HIP;
+        msg[q] = "hipSetDevice failed on a worker thread";
+        continue;
+      }
+      status[q] = solve_common(ops[q], e[q], j[q], nrhs[q], tol, maxit, W.s[w], info ? info + off[q] : nullptr,
+                               false);
+      if (status[q] < 0) msg[q] = rfcmp_last_error();
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int w = 1; w < nw; ++w) threads.emplace_back(worker, w);
+  worker(0);
+  for (std::thread& t : threads) t.join();
+  for (int w = 0; w < nw; ++w) {
+    RF_HIP(hipEventRecord(W.ev[w], W.s[w]));
+    RF_HIP(hipStreamWaitEvent(s, W.ev[w], 0));
+  }
+  rfcmp_status worst = RFCMP_OK;
+  for (int q = 0; q < nops; ++q) {
+    if (status[q] < 0) {
+      set_error("operator %d: %s", q, msg[q].c_str());
+      return status[q];
+    }
+    worst = std::max(worst, status[q]);
+  }
+  return worst;
 }
 
 }  // extern "C"

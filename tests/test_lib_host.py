@@ -135,3 +135,35 @@ def test_create_many_argument_errors():
     st = rf.lib.rfcmp_op_create_many(m.handle, ks.ctypes.data_as(rf._PD), 2, ctypes.byref(o), None, None, out)
     assert st < 0 and not out[0] and not out[1], rf.lib.rfcmp_last_error()
     m.close()
+
+
+def test_batch_solve_argument_errors():
+    """rfcmp_batch_solve rejects bad arguments before any device work (no GPU
+    needed): no operators, NULL arrays, a bad tolerance, a NULL or aliased
+    entry, nrhs = 0, the same handle twice.  The handles are never
+    dereferenced by these checks."""
+    import paper_1803_08333_amd as rf
+    P = ctypes.c_void_p
+
+    def call(ops, es, js, nr, tol=1e-6, maxit=10, n=None):
+        n = len(ops) if n is None else n
+        arr = lambda xs: (P * max(len(xs), 1))(*xs)
+        st = rf.lib.rfcmp_batch_solve(arr(ops), n, arr(es), arr(js), (ctypes.c_int32 * max(len(nr), 1))(*nr),
+                                      tol, maxit, None, None)
+        return st, rf.lib.rfcmp_last_error()
+
+    assert call([], [], [], [], n=0)[0] == -1
+    assert rf.lib.rfcmp_batch_solve(None, 1, None, None, None, 1e-6, 10, None, None) == -1
+    assert call([16], [32], [48], [1], tol=0.0)[0] == -1
+    assert call([16], [32], [48], [1], tol=float("nan"))[0] == -1
+    assert call([16], [32], [48], [1], maxit=0)[0] == -1
+    st, msg = call([16, 0], [32, 64], [48, 80], [1, 1])
+    assert st == -1 and b"operator 1" in msg, msg
+    st, msg = call([16, 24], [32, 64], [48, 64], [1, 1])
+    assert st == -1 and b"operator 1" in msg, msg
+    st, msg = call([16, 24], [32, 64], [48, 80], [1, 0])
+    assert st == -1 and b"nrhs" in msg, msg
+    st, msg = call([16, 24, 16], [32, 64, 96], [48, 80, 112], [1, 1, 1])
+    assert st == -1 and b"twice" in msg, msg
+    with pytest.raises(ValueError):
+        rf.batch_solve([], [])
