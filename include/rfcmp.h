@@ -266,9 +266,9 @@ rfcmp_status rfcmp_solve_system(rfcmp_op op, const void* b, void* i, int32_t nrh
  * for nrhs[q] right-hand sides, e[q], j[q] device c128 [nrhs[q]][N_q], not
  * aliased; tol and maxit are shared.  The solves run concurrently, up to four
  * at a time, each on an internal stream (default priority) driven by a host
- * thread; largest N * nrhs first.  These streams start after the work queued
- * on `stream` before the call, and `stream` waits for them; the call returns
- * when every solve has finished.  Each operator's result and report are those
+ * thread; largest N * nrhs first, at equal size the higher k.  These streams
+ * start after the work queued on `stream` before the call, and `stream` waits
+ * for them; the call returns when every solve has finished.  Each operator's result and report are those
  * of rfcmp_solve on it alone, bit for bit.
  *   ops: host [nops], distinct handles (two entries may share a mesh) whose
  *        mesh lives on the calling thread's current device;

@@ -1183,7 +1183,8 @@ rfcmp_status rfcmp_solve_system(rfcmp_op op, const void* b, void* i, int32_t nrh
 // internal stream of its own driven by a host thread of its own: a CG
 // iteration of a small operator is bounded by launch and read-back latency
 // rather than by the device, and the solves of the other operators fill
-// those gaps.  Largest operators first, so that the last to start are short.
+// those gaps.  Largest operators first (at equal size the higher wavenumber),
+// so that the last to start are short.
 rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* const* e, void* const* j,
                                const int32_t* nrhs, double tol, int32_t maxit, void* stream, rfcmp_info* info) {
   RF_ARG(ops && e && j && nrhs && nops > 0, "NULL argument or nops <= 0");
@@ -1240,8 +1241,11 @@ rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* co
   for (int w = 0; w < nw; ++w) RF_HIP(hipStreamWaitEvent(W.s[w], W.ev[nw], 0));
   std::vector<int> order(nops);
   for (int q = 0; q < nops; ++q) order[q] = q;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return ops[a]->mesh->h.N * nrhs[a] > ops[b]->mesh->h.N * nrhs[b]; });
+  // at equal size the higher wavenumber first: CG takes more iterations there
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int64_t sa = ops[a]->mesh->h.N * nrhs[a], sb = ops[b]->mesh->h.N * nrhs[b];
+    return sa != sb ? sa > sb : ops[a]->k > ops[b]->k;
+  });
   std::atomic<int> next{0};
   std::vector<rfcmp_status> status(nops, RFCMP_OK);
   std::vector<std::string> msg(nops);
