@@ -325,8 +325,12 @@ __global__ __launch_bounds__(1024) void k_normalize_rows(long n, const double2* 
 
 // End of one power-iteration application: the three raw vectors (rows 0
 // and 1: w_r - Sigma z5_r, row 2: Sigma z10), each row's squared norm to
-// nrm2[r], and the row divided by its norm to out.  One workgroup per row;
-// each thread rescales in the second pass the entries it wrote in the first.
+// nrm2[r], and the row divided by its norm to out.  One workgroup per row.
+// Rows of up to kPowRegs * 1024 entries stay in registers between the norm
+// and the scaling, with every thread's loads issued together (the edge's two
+// cells, then the gathers); longer rows are written, then rescaled by the
+// threads that wrote them.
+constexpr int kPowRegs = 8;
 __global__ __launch_bounds__(1024) void k_power_next(int N, int C, const int* __restrict__ edge_cell,
                                                      const double2* __restrict__ w, const double2* __restrict__ z5,
                                                      const double2* __restrict__ z10, double2* __restrict__ out,
@@ -336,6 +340,33 @@ __global__ __launch_bounds__(1024) void k_power_next(int N, int C, const int* __
   double2* o = out + (long)r * N;
   const double2* z = r < 2 ? z5 + (long)r * C : z10;
   double a = 0.0;
+  if (N <= kPowRegs * 1024) {
+    int2 cells[kPowRegs];
+    double2 v[kPowRegs];
+#pragma unroll
+    for (int u = 0; u < kPowRegs; ++u) {
+      const int n = threadIdx.x + 1024 * u;
+      cells[u] = n < N ? reinterpret_cast<const int2*>(edge_cell)[n] : make_int2(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPowRegs; ++u) {
+      const int n = threadIdx.x + 1024 * u;
+      if (n < N) {
+        const double2 zd = csub(z[cells[u].x], z[cells[u].y]);
+        v[u] = r < 2 ? csub(w[(long)r * N + n], zd) : zd;
+        a += v[u].x * v[u].x + v[u].y * v[u].y;
+      }
+    }
+    const double2 t = block_sum_1024(a, 0.0, sr, si);
+    const double sc = 1.0 / sqrt(t.x);
+    if (threadIdx.x == 0) nrm2[r] = make_double2(t.x, 0.0);
+#pragma unroll
+    for (int u = 0; u < kPowRegs; ++u) {
+      const int n = threadIdx.x + 1024 * u;
+      if (n < N) o[n] = cscale(sc, v[u]);
+    }
+    return;
+  }
   for (int n = threadIdx.x; n < N; n += 1024) {
     const double2 zd = csub(z[edge_cell[2 * n]], z[edge_cell[2 * n + 1]]);
     const double2 v = r < 2 ? csub(w[(long)r * N + n], zd) : zd;
