@@ -108,6 +108,8 @@ typedef struct {
                              of alpha, beta, gamma moved by less than power_tol
                              (relative) since the previous check; 0 = always
                              power_iters steps */
+  int32_t streams;        /* power iterations rfcmp_op_create_many runs at once,
+                             1..4, default 4 (1 = one after another on `stream`) */
 } rfcmp_options;
 rfcmp_status rfcmp_options_default(rfcmp_options* opt);
 
@@ -135,6 +137,10 @@ rfcmp_status rfcmp_op_create(rfcmp_mesh m, double k, const rfcmp_options* opt,
  * each as rfcmp_op_create would make it, with the same options and power
  * start vector: every operator's blocks are assembled first, beside the
  * projector builds of a new mesh, then the scalings of each are computed.
+ * With nk > 1 the power iterations run concurrently, up to four at a time,
+ * each on an internal stream (default priority) driven by a host thread,
+ * after the work queued on `stream`; the operators are bit-identical to
+ * those of separate rfcmp_op_create calls.
  * out: host rfcmp_op [nk], all NULL on error.  1 <= nk <= 1024. */
 rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, const rfcmp_options* opt,
                                   const void* power_start, void* stream, rfcmp_op* out);

@@ -755,6 +755,71 @@ void profile_record(const char* tag, hipEvent_t a, hipEvent_t b) {
   std::lock_guard<std::mutex> g(p.mu);
   p.rec.emplace_back(tag, a, b);
 }
+
+// Concurrent work of rfcmp_batch_solve and rfcmp_op_create_many: at most one
+// stream per hardware queue HIP gives a process by default.
+constexpr int kBatchStreams = 4;
+
+// job(q, stream) for every q of `order`, on up to max_streams internal
+// streams (non-blocking, default priority), each driven by a host thread of
+// its own that takes the next q when its job returns.  The streams start
+// after the work queued on s, and s waits for them.  status[q] and msg[q]
+// receive each job's status and error text; the return value reports the
+// streams' own set-up.  Jobs must not share mutable state.
+template <class F>
+rfcmp_status run_concurrent(const std::vector<int>& order, int max_streams, hipStream_t s, F job,
+                            std::vector<rfcmp_status>& status, std::vector<std::string>& msg) {
+  const int count = (int)order.size();
+  status.assign(count, RFCMP_OK);
+  msg.assign(count, std::string());
+  if (count == 0) return RFCMP_OK;
+  int dev = 0;
+  RF_HIP(hipGetDevice(&dev));
+  const int nw = std::max(1, std::min({count, max_streams, kBatchStreams}));
+  struct Streams {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> ev;
+    ~Streams() {
+      for (hipStream_t x : s) (void)hipStreamDestroy(x);
+      for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    }
+  } W;
+  for (int w = 0; w <= nw; ++w) {
+    hipEvent_t ev = nullptr;
+    RF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    W.ev.push_back(ev);
+  }
+  for (int w = 0; w < nw; ++w) {
+    hipStream_t x = nullptr;
+    RF_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    W.s.push_back(x);
+  }
+  RF_HIP(hipEventRecord(W.ev[nw], s));
+  for (int w = 0; w < nw; ++w) RF_HIP(hipStreamWaitEvent(W.s[w], W.ev[nw], 0));
+  std::atomic<int> next{0};
+  auto worker = [&](int w) {
+    const bool on_device = hipSetDevice(dev) == hipSuccess;
+    for (int t; (t = next.fetch_add(1)) < count;) {
+      const int q = order[t];
+      if (!on_device) {
+        status[q] = RFCMP_E_HIP;
+        msg[q] = "hipSetDevice failed on a worker thread";
+        continue;
+      }
+      status[q] = job(q, W.s[w]);
+      if (status[q] < 0) msg[q] = last_error();
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int w = 1; w < nw; ++w) threads.emplace_back(worker, w);
+  worker(0);
+  for (std::thread& t : threads) t.join();
+  for (int w = 0; w < nw; ++w) {
+    RF_HIP(hipEventRecord(W.ev[w], W.s[w]));
+    RF_HIP(hipStreamWaitEvent(s, W.ev[w], 0));
+  }
+  return RFCMP_OK;
+}
 }  // namespace rfcmp
 
 using namespace rfcmp;
@@ -881,6 +946,7 @@ rfcmp_status rfcmp_options_default(rfcmp_options* o) {
   o->power_iters = 30;
   o->precision = 0;
   o->power_tol = 1e-2;
+  o->streams = kBatchStreams;
   return RFCMP_OK;
 }
 
@@ -907,6 +973,7 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
   RF_ARG(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
   RF_ARG(o.scaling == 1 || (o.power_iters > 0 && power_start), "power scalings need power_iters > 0 and power_start");
   RF_ARG(std::isfinite(o.power_tol) && o.power_tol >= 0, "power_tol must be >= 0");
+  RF_ARG(o.streams >= 1 && o.streams <= kBatchStreams, "streams must be 1..4");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   RF_HIP(hipGetDevice(&dev));
@@ -940,9 +1007,29 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
     op->alpha = std::sqrt(k[i]);
     op->beta = 1.0 / std::sqrt(k[i]);
     op->gamma = k[i];
-    if (o.scaling == 0)
-      RF_TRY(power_scalings(op, static_cast<const double2*>(power_start), o.power_iters, o.power_tol, s));
     if (o.precision == 1) RF_TRY(ensure_split(op, s));
+  }
+  // The power iterations of several wavenumbers run concurrently (each
+  // operator's own workspace; the mesh's matrices are only read), the
+  // highest wavenumber, which takes the most steps, first.
+  const double2* start = static_cast<const double2*>(power_start);
+  if (o.scaling == 0 && (nk == 1 || o.streams == 1)) {
+    for (int i = 0; i < nk; ++i) RF_TRY(power_scalings(ops[i].get(), start, o.power_iters, o.power_tol, s));
+  } else if (o.scaling == 0) {
+    std::vector<int> order(nk);
+    for (int i = 0; i < nk; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return k[a] > k[b]; });
+    std::vector<rfcmp_status> status;
+    std::vector<std::string> msg;
+    RF_TRY(run_concurrent(
+        order, o.streams, s,
+        [&](int q, hipStream_t ws) { return power_scalings(ops[q].get(), start, o.power_iters, o.power_tol, ws); },
+        status, msg));
+    for (int i = 0; i < nk; ++i)
+      if (status[i] < 0) {
+        set_error("wavenumber %d: %s", i, msg[i].c_str());
+        return status[i];
+      }
   }
   RF_HIP(hipStreamSynchronize(s));
   for (int32_t i = 0; i < nk; ++i) out[i] = ops[i].release();
@@ -1139,10 +1226,6 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
   }
 }
 
-// Concurrent solves of rfcmp_batch_solve: at most one per hardware queue HIP
-// gives a process by default.
-constexpr int kBatchStreams = 4;
-
 static rfcmp_status solve_common(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,
                                  void* stream, rfcmp_info* info, bool system) {
   RF_ARG(op && e && j && e != j, "NULL or aliased argument");
@@ -1218,27 +1301,6 @@ rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* co
     RF_TRY(ensure_work(ops[q], std::min(nrhs[q], 64)));
     if (ops[q]->opt.precision == 1) RF_TRY(ensure_split(ops[q], s));
   }
-  const int nw = std::min<int>(nops, kBatchStreams);
-  struct Streams {
-    std::vector<hipStream_t> s;
-    std::vector<hipEvent_t> ev;
-    ~Streams() {
-      for (hipStream_t x : s) (void)hipStreamDestroy(x);
-      for (hipEvent_t x : ev) (void)hipEventDestroy(x);
-    }
-  } W;
-  for (int w = 0; w <= nw; ++w) {
-    hipEvent_t ev = nullptr;
-    RF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    W.ev.push_back(ev);
-  }
-  for (int w = 0; w < nw; ++w) {
-    hipStream_t x = nullptr;
-    RF_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));  // default priority
-    W.s.push_back(x);
-  }
-  RF_HIP(hipEventRecord(W.ev[nw], s));
-  for (int w = 0; w < nw; ++w) RF_HIP(hipStreamWaitEvent(W.s[w], W.ev[nw], 0));
   std::vector<int> order(nops);
   for (int q = 0; q < nops; ++q) order[q] = q;
   // at equal size the higher wavenumber first: CG takes more iterations there
@@ -1246,31 +1308,14 @@ rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* co
     const int64_t sa = ops[a]->mesh->h.N * nrhs[a], sb = ops[b]->mesh->h.N * nrhs[b];
     return sa != sb ? sa > sb : ops[a]->k > ops[b]->k;
   });
-  std::atomic<int> next{0};
-  std::vector<rfcmp_status> status(nops, RFCMP_OK);
-  std::vector<std::string> msg(nops);
-  auto worker = [&](int w) {
-    const bool on_device = hipSetDevice(dev) == hipSuccess;
-    for (int t; (t = next.fetch_add(1)) < nops;) {
-      const int q = order[t];
-      if (!on_device) {
-        status[q] = RFCMP_E_HIP;
-        msg[q] = "hipSetDevice failed on a worker thread";
-        continue;
-      }
-      status[q] = solve_common(ops[q], e[q], j[q], nrhs[q], tol, maxit, W.s[w], info ? info + off[q] : nullptr,
-                               false);
-      if (status[q] < 0) msg[q] = rfcmp_last_error();
-    }
-  };
-  std::vector<std::thread> threads;
-  for (int w = 1; w < nw; ++w) threads.emplace_back(worker, w);
-  worker(0);
-  for (std::thread& t : threads) t.join();
-  for (int w = 0; w < nw; ++w) {
-    RF_HIP(hipEventRecord(W.ev[w], W.s[w]));
-    RF_HIP(hipStreamWaitEvent(s, W.ev[w], 0));
-  }
+  std::vector<rfcmp_status> status;
+  std::vector<std::string> msg;
+  RF_TRY(run_concurrent(
+      order, kBatchStreams, s,
+      [&](int q, hipStream_t ws) {
+        return solve_common(ops[q], e[q], j[q], nrhs[q], tol, maxit, ws, info ? info + off[q] : nullptr, false);
+      },
+      status, msg));
   rfcmp_status worst = RFCMP_OK;
   for (int q = 0; q < nops; ++q) {
     if (status[q] < 0) {

@@ -461,20 +461,24 @@ def test_projector_inverses_large(nmajor, nminor):
     m.close()
 
 
-def test_create_many_matches_single():
+@pytest.mark.parametrize("streams", [4, 1])
+def test_create_many_matches_single(streams):
     """rfcmp_op_create_many (a frequency sweep, every assembly queued ahead of
-    the scalings) gives the operators of separate rfcmp_op_create calls bit
-    for bit: blocks and power-iteration scalings."""
+    the scalings; the power iterations on concurrent internal streams, or one
+    after another with streams = 1) gives the operators of separate
+    rfcmp_op_create calls bit for bit: blocks, power-iteration scalings and
+    step counts.  Five wavenumbers, so that four workers run more than one."""
     torch, rf = _gpu()
     xyz, tri = _mesh("ico2")
-    ks = [1.0, 0.1, 1e-4]
+    ks = [1.0, 0.1, 1e-4, 2.0, 0.5]
     m = rf.Mesh(xyz, tri)
     start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
-    many = rf.Operator.create_many(m, ks, power_start=start)
+    many = rf.Operator.create_many(m, ks, power_start=start, streams=streams)
     m1 = rf.Mesh(xyz, tri)
     for k, op in zip(ks, many):
         one = rf.Operator(m1, k, power_start=start)
         assert op.scalings() == one.scalings()
+        assert op.power_steps() == one.power_steps()
         for a, b in zip(op.export(), one.export()):
             assert torch.equal(a, b)
         one.close()

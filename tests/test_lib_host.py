@@ -99,8 +99,8 @@ def test_mesh_validation_codes():
 def test_options_defaults():
     import paper_1803_08333_amd as rf
     o = rf.options()
-    assert (o.near_factor, o.outer_star, o.scaling, o.power_iters, o.precision, o.power_tol) == (2.0, 0, 0, 30, 0,
-                                                                                                 1e-2)
+    assert (o.near_factor, o.outer_star, o.scaling, o.power_iters, o.precision, o.power_tol, o.streams) == \
+        (2.0, 0, 0, 30, 0, 1e-2, 4)
 
 
 def test_rhs_gap_argument_errors():
