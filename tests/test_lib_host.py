@@ -134,6 +134,11 @@ def test_create_many_argument_errors():
     assert st < 0
     st = rf.lib.rfcmp_op_create_many(m.handle, ks.ctypes.data_as(rf._PD), 2, ctypes.byref(o), None, None, out)
     assert st < 0 and not out[0] and not out[1], rf.lib.rfcmp_last_error()
+    ks = np.array([1.0, 2.0])
+    for streams in (0, 5, -1):
+        o = rf.options(scaling=1, streams=streams)
+        st = rf.lib.rfcmp_op_create_many(m.handle, ks.ctypes.data_as(rf._PD), 2, ctypes.byref(o), None, None, out)
+        assert st == -1 and b"streams" in rf.lib.rfcmp_last_error() and not out[0] and not out[1]
     m.close()
 
 
