@@ -394,9 +394,11 @@ def main():
 
     def step(record, **opts):
         m = rf.Mesh(xyz, tri)
-        for k, op in zip(KS, rf.Operator.create_many(m, KS, power_start=start, **opts)):
-            e = op.rhs_planewave(kh, pol)
-            j, st, info = op.solve(e, tol=TOL, maxit=2000)
+        ops = rf.Operator.create_many(m, KS, power_start=start, **opts)
+        es = [op.rhs_planewave(kh, pol) for op in ops]
+        _, _, infos = rf.batch_solve(ops, es, tol=TOL, maxit=2000)
+        for k, op, info in zip(KS, ops, infos):
+            st = 0 if info[0]["rel_residual"] <= TOL else 1
             if record:
                 a, b, g, lam = op.scalings()
                 out[k] = {"status": st, "iters": info[0]["iters"], "restarts": info[0]["restarts"],
