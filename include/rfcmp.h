@@ -301,7 +301,9 @@ rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* co
  * inverse).  rfcmp_profile_enable
  * clears the records (waiting for recorded events first); rfcmp_profile_read
  * waits for the events of one tag and returns their summed duration and
- * count.  Not thread-safe; adds two event records per timed launch. */
+ * count.  Adds two event records per timed launch.  Records from library
+ * calls on several host threads (rfcmp_batch_solve, rfcmp_op_create_many)
+ * are safe; enable, select and read must not overlap other calls. */
 rfcmp_status rfcmp_profile_enable(int32_t on);
 /* Restrict the timed kernels to a comma-separated list of tags (NULL or ""
  * = all tags), so that a timed region carries event records only where they
