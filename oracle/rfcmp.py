@@ -45,7 +45,8 @@ class Preconditioner:
         self.Gtp_inv = np.linalg.inv(self.Gtp)
         self.P_gS = Sig @ self.Lp @ self.Gtp_inv @ Sig.T
         self.P_s = self.P_S if outer_star == "sigma" else self.P_gS
-        self.MS_hat = Sig @ self.Lp @ np.diag(top.area) @ self.Lp @ Sig.T   # P_mS without 1/beta^2
+        self.Gpp_inv = np.linalg.inv(grams.gram_pp(top))
+        self.MS_hat = Sig @ self.Lp @ self.Gpp_inv @ self.Lp @ Sig.T   # P_mS without 1/beta^2
         self.ML_hat = Lam @ self.Gll_inv @ Lam.T
         self.TPhi = Sig @ V @ Sig.T
         self.alpha = self.beta = self.gamma = None

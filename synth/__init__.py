@@ -6,5 +6,5 @@ arithmetic and is shared by the tests, the benchmark, the oracle checks and
 the GPU path alike.
 """
 
-from .meshes import icosphere, torus, cube, ellipsoid, mesh_summary  # noqa: F401
+from .meshes import icosphere, graded_sphere, torus, cube, ellipsoid, mesh_summary  # noqa: F401
 from .waves import plane_waves, default_plane_wave, complex_start  # noqa: F401

@@ -223,6 +223,25 @@ def test_gram_ll(name):
     assert np.abs(G - H).max() < 1e-15
 
 
+@pytest.mark.parametrize("name", ["ico1", "cube2", "ellipsoid1"])
+def test_gram_pp_by_quadrature(name):
+    """G_pp of the cell functions p_n = 1/A_n on cell n, zero elsewhere
+    (Sec. 2): every entry integrated with the 7-point rule over every cell,
+    sum_c A_c sum_q w_q p_m(x_q) p_n(x_q).  Supports meet only on the
+    diagonal, where the integrand is the constant 1/A_c^2."""
+    top = topo(name)
+    G = grams.gram_pp(top)
+    bary, w = quadrature.tri7_barycentric()
+    H = np.zeros_like(G)
+    for c in range(top.C):
+        # p_m evaluated at cell c's points: 1/A_c for m == c, else 0
+        vals = np.zeros((top.C, len(w)))
+        vals[c, :] = 1.0 / top.area[c]
+        H += top.area[c] * np.einsum("q,mq,nq->mn", w, vals, vals)
+    assert np.abs(G - H).max() <= 1e-14 * np.abs(H).max()
+    assert np.all(np.diag(G) > 0)
+
+
 @pytest.mark.parametrize("name", ["ico1", "torus_small", "cube2"])
 def test_laplacian_pseudo_inverse_identity(name):
     """(Sig^T Sig + 1 1^T/C)^-1 = (Sig^T Sig)^+ + 1 1^T/C (Sec. 3.2)."""

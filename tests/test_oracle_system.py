@@ -297,16 +297,82 @@ def test_pins_catch_planted_mistakes(monkeypatch, mod, attr, mut, pin):
     assert good < 0.07 and bad > 3 * good
 
 
-def test_middle_gram_mistake_changes_iterations_not_solution(monkeypatch):
-    """A wrong Gram matrix inside P_m leaves j = -T^-1 e unchanged (only the
-    conditioning moves): the solution pins cannot see it, the HPD/condition
-    pin must."""
+def test_middle_gram_mistake_changes_system_not_solution(monkeypatch):
+    """A wrong Gram matrix inside P_m (G_ll doubled) changes the system
+    matrix A but not j = -T^-1 e: A i = b is equivalent to T P_o i = -e for
+    any HPD middle matrix.  So the planted mistake must move A by far more
+    than rounding while the recovered j stays put; the graded-mesh
+    conditioning pin below is what catches a wrong Gram there."""
     from oracle import grams
+    k = 0.5
+    top = topo("ico1")
+    TA, V = blocks("ico1", k)
+    e = excitation("ico1", k)
+
+    def solve():
+        pre = rfcmp.Preconditioner(top, TA, V, k)
+        pre.set_scalings(1.0, 1.0, 1.0)
+        A = pre.system_split()
+        return A, pre.recover(np.linalg.solve(A, pre.rhs(e)))
+
+    A_good, j_good = solve()
     monkeypatch.setattr(grams, "gram_ll", _gram_ll_times_two(grams.gram_ll))
-    pre = rfcmp.Preconditioner(topo("ico1"), *blocks("ico1", 0.5), 0.5)
-    pre.set_scalings(1.0, 1.0, 1.0)
+    A_bad, j_bad = solve()
+    assert rel(A_bad, A_good) > 1e-2
+    assert rel(j_bad, j_good) < 1e-10
+
+
+def _graded_condition(k=1e-3):
+    """cond(A) on a strongly graded sphere (areas spread 15x)."""
+    top = Topology(*synth.graded_sphere(1, 0.8))
+    TA, V = assembly.assemble(top, k)
+    pre = rfcmp.Preconditioner(top, TA, V, k)
+    pre.power_scalings(synth.complex_start(top.N, 11), 40)
     A = pre.system_split()
-    assert np.abs(A - A.conj().T).max() < 1e-12 * np.abs(A).max()
+    ev = np.linalg.eigvalsh(0.5 * (A + A.conj().T))
+    return ev[-1] / ev[0]
+
+
+def test_condition_bounded_on_graded_mesh():
+    """The star middle matrix P_mS = Sigma L^+ G_pp^-1 L^+ Sigma^T (Sec. 3)
+    must weigh each cell by its area (G_pp^-1 = diag(A), the inverse Gram of
+    the cell functions 1/A) for the Calderon pairing with T_Phi to hold
+    independently of the local mesh size.  On a sphere graded to a 15x spread
+    of cell areas, cond(A) stays at the uniform mesh's level (about 10 against
+    6.8); a middle matrix with diag(1/A) instead leaves cond(A) above 1000."""
+    assert _graded_condition() < 15.0
+
+
+def test_graded_pin_catches_inverted_cell_gram(monkeypatch):
+    """Plant G_pp = diag(A) (so that P_mS carries diag(1/A)): the graded-mesh
+    pin must fail."""
+    from oracle import grams
+    monkeypatch.setattr(grams, "gram_pp", lambda top: np.diag(top.area))
+    assert _graded_condition() > 100.0
+
+
+@pytest.mark.parametrize("name,k", [("ico1", 1e-3), ("ico1", 0.5), ("torus_small", 0.5)])
+def test_scaled_principal_terms_unit_norm(name, k):
+    """Reading of the Sec. 4 norms with the EFIE's k factors (i k T_A and
+    T_Phi/(i k)): with the power-iteration scalings, each principal term of
+    the system, formed here from the dense matrices,
+      (k^2/alpha^4)   P_LH^H T_A^H Lam G_ll^-1 Lam^T T_A P_LH,
+      1/(k^2 beta^4)  P_S^H T_Phi^H (bar P_mS) T_Phi P_S,
+      k^2/(alpha^2 gamma) P_LH^H T_A^H P_LH T_A P_LH,
+    has unit 2-norm.  The power iteration approaches each norm from below, so
+    each term's norm is at least 1 and, after 60 steps, within 2 %.  Without
+    the k factors the terms would be off by k^-2, k^2 and k^-2 (the test uses
+    k != 1)."""
+    top = topo(name)
+    TA, V = blocks(name, k)
+    pre = rfcmp.Preconditioner(top, TA, V, k)
+    al, be, ga, *_ = pre.power_scalings(synth.complex_start(top.N, 11), 60)
+    H = lambda M: M.conj().T
+    terms = [(k * k / al ** 4) * H(pre.P_LH) @ H(TA) @ pre.ML_hat @ TA @ pre.P_LH,
+             (1.0 / (k * k * be ** 4)) * H(pre.P_S) @ H(pre.TPhi) @ pre.MS_hat @ pre.TPhi @ pre.P_S,
+             (k * k / (al ** 2 * ga)) * H(pre.P_LH) @ H(TA) @ pre.P_LH @ TA @ pre.P_LH]
+    for t in terms:
+        assert 1.0 - 1e-9 <= np.linalg.norm(t, 2) < 1.02
 
 
 @pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5)])
