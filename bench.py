@@ -1,16 +1,22 @@
-"""Benchmark: RF-CMP EFIE solve on one MI355X.
+"""Benchmark: RF-CMP EFIE solves on one MI355X.
 
-One step = one pass of the whole hot path over the workload, from the mesh
-to the RWG currents:
-  PEC sphere r = 1 m, icosphere level 4 (C = 5120 cells, N = 7680 RWG),
-  ka = 1.0 and ka = 1e-4, one x-polarised plane wave along +z, CG to 1e-6:
-  topology, projector matrices (L^+, G_ll^-1), far/near-pair assembly of T_A
-  and V, power-iteration scalings, excitation, preconditioned rhs, CG, and
-  recovery j = P_o i -- for both wavenumbers.
+Headline workload (the largest single-GPU configuration of the benchmark
+set): PEC sphere r = 1 m, icosphere level 5 (C = 20480 cells, N = 30720 RWG),
+ka = 2.0, 64 seeded plane waves (uniform directions, random polarisation),
+BF16x3 operator products on MFMA with FP64-residual refinement to a true
+relative residual of 1e-6.  One step = one pass of the whole hot path over it:
+topology, projector set-up, far/near-pair assembly of T_A and V,
+power-iteration scalings, the 64 excitations, preconditioned right-hand
+sides, block CG with refinement, and recovery j = P_o i.  ``value`` =
+right-hand sides solved per second over the timed steps.
 
-Prints one JSON line.  ``value`` = RF-CMP solves per second over the timed
-steps (two solves per step); kernel durations come from HIP events recorded
-by the library on the launch stream during the timed steps.
+Also reported (sub-keys): the level-4 sphere at ka = 1 and 1e-4 with one wave
+each on the complex64/FP64 path (the former headline), the icosphere-2 case
+solved by the FP64 oracle in full beside the GPU (error per result), the
+precision study (BF16x3 against complex64/FP64 at equal residual), the
+spectral study, far field, voltage gap, the uneven batch, and the oracle's
+CPU baseline.  Kernel durations come from HIP events the library records on
+the launch stream.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -33,11 +39,14 @@ HBM_GBS = 8000.0
 FP32_VALU_TFLOPS = 157.3
 FP64_VALU_TFLOPS = 78.6
 
-WORKLOAD = {"workload": "PEC sphere r=1 m, icosphere level 4 (5120 cells, 7680 RWG), ka=1.0 and ka=1e-4, "
-                        "x-polarised plane wave along +z, CG to relative residual 1e-6",
-            "mesh": "icosphere4", "ka": [1.0, 1e-4], "nrhs": 1, "tol": 1e-6}
+HEADLINE = {"workload": "PEC sphere r=1 m, icosphere level 5 (20480 cells, 30720 RWG), ka=2.0, 64 seeded plane "
+                        "waves (uniform directions, random polarisation), BF16x3 products with FP64-residual "
+                        "refinement to relative residual 1e-6",
+            "mesh": "icosphere5", "ka": [2.0], "nrhs": 64, "precision": "bf16x3+fp64 refinement", "tol": 1e-6}
+SWEEP = {"workload": "PEC sphere r=1 m, icosphere level 4 (5120 cells, 7680 RWG), ka=1.0 and ka=1e-4, "
+                     "x-polarised plane wave along +z, complex64/FP64 path, CG to relative residual 1e-6",
+         "mesh": "icosphere4", "ka": [1.0, 1e-4], "nrhs": 1, "precision": "c64 blocks, fp64 projectors", "tol": 1e-6}
 TOL = 1e-6
-KS = (1.0, 1e-4)
 FAR_FLOPS_PER_POINT_PAIR = 30     # sub 3, R^2 5, rsqrt 1, R 1, kR 1, sin+cos 2, G 3, moment sums 14 (FMA = 2)
 
 
@@ -47,54 +56,95 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-slab", type=int, default=32, help="1/slab of the test cells for the oracle sample")
+    p.add_argument("--cpu-slab", type=int, default=64, help="1/slab of the test cells for the oracle sample")
+    p.add_argument("--no-oracle-case", action="store_true")
     p.add_argument("--no-precision-study", action="store_true")
     p.add_argument("--no-spectral-study", action="store_true")
     p.add_argument("--batch-rhs", type=int, default=64)
-    p.add_argument("--uneven-batch", action="store_true",
-                   help="also time the uneven batch (32 objects x 8 wavenumbers x 4 plane waves, BF16x3), "
-                        "through rfcmp_batch_solve and through one rfcmp_solve per operator")
+    p.add_argument("--no-uneven-batch", action="store_true",
+                   help="skip the uneven batch (32 objects x 8 wavenumbers x 4 plane waves, BF16x3)")
+    p.add_argument("--uneven-batch-serial", action="store_true",
+                   help="also time the uneven batch with one rfcmp_solve per operator")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     return p.parse_args()
 
 
-def cpu_baseline(xyz, tri, slab):
-    """The FP64 oracle on a bounded sample of the same workload: its far-pair
-    quadrature and near-pair integrals for every slab-th test cell of the
-    level-4 sphere at ka = 1.0 (its own functions, row by row, in the order
-    its assembly runs them).  Converted to solves/s assuming assembly is the
-    oracle's only cost, an upper bound on its throughput: setup, scalings and
-    CG are left out."""
+_BASELINE_MESH = {}
+
+
+def _oracle_rows(args):
+    """Rows of V and the cell-pair blocks for a set of test cells by the
+    oracle's own sampled-row assembly (worker of cpu_baseline; the mesh is
+    inherited from the parent process by fork)."""
+    k, rows = args
     from threadpoolctl import threadpool_limits
-    from oracle import assembly, quadrature
+    from oracle import assembly
+    with threadpool_limits(limits=1):
+        assembly.block_rows(_BASELINE_MESH["top"], k, rows)
+    return len(rows)
+
+
+def cpu_baseline(slab, head):
+    """The FP64 oracle on the host cores, on a bounded sample of the headline
+    workload (icosphere level 5, ka = 2, 64 plane waves), as it stands:
+    * assembly: its sampled-row assembly (far-pair quadrature and near-pair
+      integrals, the same functions as its full assembly) for every slab-th
+      test cell, in groups of 8 rows over one process per core;
+    * set-up and solve: its dense preconditioner (projectors, inverses), power
+      scalings and CG on the same kind of problem at icosphere level 2
+      (N = 480) with 64 plane waves, scaled to level 5 by N^3 (dense
+      set-up) and N^2 (scalings and solve: dense products);
+    solves/s = 64 / (full assembly + scaled set-up + scaled solve)."""
+    import concurrent.futures
+    from threadpoolctl import threadpool_info
+    from oracle import assembly, rfcmp, rhs
     from oracle.topology import Topology
+    k = HEADLINE["ka"][0]
+    nrhs = HEADLINE["nrhs"]
+    cores = min(os.cpu_count() or 1, 16)
+    xyz, tri = synth.icosphere(5)
     top = Topology(xyz, tri)
     C = top.C
     rows = np.arange(0, C, slab)
-    pts, w = quadrature.tri7_points(top.xyz, top.tri)
-    cores = os.cpu_count() or 1
-    with threadpool_limits(limits=cores):
-        t0 = time.perf_counter()
-        c0 = time.process_time()
-        near = assembly.near_mask(top)
-        k = 1.0
-        for s in range(0, len(rows), 8):
-            assembly.far_rows(top, k, rows[s:s + 8], pts, w)
-        for c in rows:
-            for cp in np.nonzero(near[c, c:])[0] + c:
-                assembly.near_block(top, c, cp, k, pts, w)
-        dt = time.perf_counter() - t0
-        used = max(1, int(round((time.process_time() - c0) / dt)))
-    pairs = len(rows) * C
-    pairs_per_s = pairs / dt
-    full_assembly_s = C * C / pairs_per_s
-    return {"value": 1.0 / full_assembly_s, "unit": "solves/s", "cores": used,
-            "kind": "oracle",
-            "sample": f"oracle far+near assembly of 1/{slab} of the test cells ({len(rows)} x {C} cell pairs, "
-                      f"ka=1.0) in {dt:.1f} s; solves/s = 1/(C^2 / pairs_per_s), i.e. assembly only "
-                      f"(upper bound on the oracle's throughput)",
-            "assembly_pairs_per_s": pairs_per_s}
+    t0 = time.perf_counter()
+    work = [(k, rows[i:i + 8]) for i in range(0, len(rows), 8)]
+    _BASELINE_MESH["top"] = top
+    import multiprocessing
+    with concurrent.futures.ProcessPoolExecutor(max_workers=cores,
+                                                mp_context=multiprocessing.get_context("fork")) as ex:
+        list(ex.map(_oracle_rows, work))
+    _BASELINE_MESH.clear()
+    t_asm = time.perf_counter() - t0
+    pairs_per_s = len(rows) * C / t_asm
+    asm_full = C * C / pairs_per_s
+    # dense set-up and solve at level 2
+    x3, t3 = synth.icosphere(2)
+    top3 = Topology(x3, t3)
+    TA3, V3 = assembly.assemble(top3, k)
+    t1 = time.perf_counter()
+    pre = rfcmp.Preconditioner(top3, TA3, V3, k)
+    t_setup = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    pre.power_scalings(synth.complex_start(top3.N, 11), 30, tol=1e-2)
+    kh, pol = synth.plane_waves(nrhs, 4)
+    e = rhs.planewave(top3, k, kh, pol)
+    b = pre.rhs(e.T)
+    _, its, _ = rfcmp.cg(pre.apply, b, TOL, 1000)
+    t_solve = time.perf_counter() - t1
+    scale = top.N / top3.N
+    total = asm_full + t_setup * scale ** 3 + t_solve * scale ** 2
+    threads = max((x.get("num_threads", 1) for x in threadpool_info()), default=1)
+    return {"value": nrhs / total, "unit": "solves/s", "cores": cores, "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"oracle sampled-row assembly of 1/{slab} of the level-5 test cells ({len(rows)} x {C} cell "
+                      f"pairs, ka={k}) over {cores} processes in {t_asm:.1f} s, scaled to all C^2 pairs "
+                      f"({asm_full:.0f} s); dense set-up ({t_setup:.1f} s) and power scalings + block CG on 64 "
+                      f"waves ({t_solve:.1f} s, {its} iterations) at icosphere level 2 on {threads} BLAS "
+                      f"threads, scaled by N^3 and N^2 to level 5; solves/s = 64 / total",
+            "assembly_pairs_per_s": pairs_per_s, "phases_s": {"assembly": asm_full,
+                                                             "setup": t_setup * scale ** 3,
+                                                             "scalings_and_solve": t_solve * scale ** 2},
+            "gpu_over_cpu": head["value"] / (nrhs / total)}
 
 
 def copy_calibration():
@@ -114,30 +164,33 @@ def copy_calibration():
 
 BF16_MFMA_TFLOPS = 2500.0
 
-# HBM bytes per launch of the symmetric products (k_symv, level-4 sphere) from
-# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch, mean
-# over the dispatches of the tag's instantiation), each scaled by what the
-# same counter reads for a plain 1 GiB device copy (FETCH_SIZE reads 2^19
-# KiB for 2^30 bytes fetched: scale 2.0; WRITE_SIZE reads 2^20 KiB: scale
-# 1.0).  Valid only for the kernel source they were taken on: reported as
-# null once symv.hip changes.
-TRAFFIC_SOURCE = {"path": "paper_1803_08333_amd/csrc/symv.hip",
-                  "sha256": "cbdcf6878b657550db4fe78b3d29caab17a48ac76d3c03b83ba5c46ee919e29a"}
+# HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
+# KiB per dispatch, mean over the dispatches of the tag's kernel), each scaled
+# by what the same counter reads for a plain 1 GiB device copy (FETCH_SIZE
+# reads 2^19 KiB for 2^30 bytes fetched: scale 2.0; WRITE_SIZE reads 2^20
+# KiB: scale 1.0), per workload.  Valid only for the kernel source they were
+# taken on: reported as null once that file changes.
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {  # tag: (FETCH_SIZE, WRITE_SIZE)
-    "cmatvec_ta+v": (174943.0, 5200.1), "cmatvec_ta+v_nr2": (174225.0, 8800.1), "dmatvec_lp": (53270.9, 3200.0),
-    "dmatvec_lp_nr2": (53999.6, 6400.0), "dmatvec_lp+gll": (67984.1, 4082.0)}
+TRAFFIC = {
+    "icosphere4_two_k": {
+        "source": "paper_1803_08333_amd/csrc/symv.hip",
+        "sha256": "cbdcf6878b657550db4fe78b3d29caab17a48ac76d3c03b83ba5c46ee919e29a",
+        "kib": {"cmatvec_ta+v": (174943.0, 5200.1), "cmatvec_ta+v_nr2": (174225.0, 8800.1),
+                "dmatvec_lp": (53270.9, 3200.0), "dmatvec_lp_nr2": (53999.6, 6400.0),
+                "dmatvec_lp+gll": (67984.1, 4082.0)}},
+}
 
 
-def measured_traffic(tag):
+def measured_traffic(tag, workload):
     import hashlib
-    if tag not in TRAFFIC_KIB:
+    t = TRAFFIC.get(workload)
+    if t is None or tag not in t["kib"]:
         return None
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), TRAFFIC_SOURCE["path"])
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
     with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC_SOURCE["sha256"]:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
             return None
-    fk, wk = TRAFFIC_KIB[tag]
+    fk, wk = t["kib"][tag]
     return 1024.0 * (fk * TRAFFIC_SCALE["fetch"] + wk * TRAFFIC_SCALE["write"])
 
 
@@ -370,6 +423,241 @@ def uneven_batch(rf, torch, concurrent=True, budget_gb=64.0):
             "iters_top_k": {"median": float(np.median(top)), "max": int(max(top))}}
 
 
+# ------------------------------------------------------------------ kernel models
+# Algorithmic work per launch of each timed tag (what the method must do,
+# not what the kernel happens to move):
+#   symmetric products (cmatvec_*, dmatvec_*): the n (n + 1)/2 distinct
+#     entries (8 B each: complex64 or FP64) plus x read and y written (16 B
+#     each, complex128) per right-hand side; "<a>+<b>" = two products in one
+#     launch, "_nr<k>" = k right-hand sides;
+#   far_pairs: C (C - 1)/2 unordered cell pairs x 49 point pairs x 30 flops;
+#   gather_ta: per formed T_A entry four cell-pair entries read and one entry
+#     written (8 B each), over the 256-block upper triangle;
+#   gemm_<m>: BF16x3 product, three bf16 MFMA products per real multiply-add,
+#     four real multiply-adds per complex one: 24 n^2 nr MFMA flops (complex
+#     matrices), 6 n^2 (2 nr) for the real projector matrices;
+#   spd_inverse: the symmetric Gauss-Jordan sweep reads and writes the upper
+#     triangle once per 64-wide pivot block: (n/64) * 8 n^2 bytes.
+FAR_FLOPS_PER_POINT_PAIR = 30     # sub 3, R^2 5, rsqrt 1, R 1, kR 1, sin+cos 2, G 3, moment sums 14 (FMA = 2)
+
+
+def kernel_model(tag, avg_ms, sz, nrhs):
+    """Roofline entry for one launch of `tag` (avg_ms per launch) on a mesh of
+    sizes sz = {"N", "C", "V"}; None for tags without a model."""
+    N, C, V = sz["N"], sz["C"], sz["V"]
+    sec = avg_ms * 1e-3
+    name, nr = tag, 1
+    if "_nr" in tag:
+        name, nr = tag.split("_nr")[0], int(tag.split("_nr")[1])
+    sym = {"cmatvec_ta": [N], "cmatvec_v": [C], "dmatvec_lp": [C], "dmatvec_gll": [V],
+           "cmatvec_ta+v": [N, C], "dmatvec_lp+gll": [C, V]}.get(name)
+    if sym is not None:
+        # the two-column T_A + V launches are the power iteration's, whose V
+        # product takes one column
+        nrs = [nr, 1 if (name == "cmatvec_ta+v" and nr == 2) else nr]
+        byt = sum(8.0 * n * (n + 1) / 2 + 32.0 * n * nrs[q] for q, n in enumerate(sym))
+        return {"bound": "hbm", "achieved": byt / sec / 1e9, "peak": HBM_GBS, "unit": "GB/s",
+                "algorithmic_bytes": byt}
+    if name == "far_pairs":
+        fl = C * (C - 1) / 2 * 49 * FAR_FLOPS_PER_POINT_PAIR
+        return {"bound": "alu", "achieved": fl / sec / 1e12, "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                "algorithmic_flops": fl}
+    if name == "gather_ta":
+        # rows of block b (256 of them, fewer in the last) times the columns
+        # from the block's first column on
+        entries = sum(min(256, N - 256 * b) * (N - 256 * b) for b in range((N + 255) // 256))
+        byt = 40.0 * entries
+        return {"bound": "hbm", "achieved": byt / sec / 1e9, "peak": HBM_GBS, "unit": "GB/s",
+                "algorithmic_bytes": byt}
+    if name.startswith("gemm_"):
+        n = {"gemm_ta": N, "gemm_v": C, "gemm_lp": C, "gemm_gll": V, "gemm_gtp": C}.get(name)
+        if n is None:
+            return None
+        fl = 24.0 * n * n * nrhs
+        return {"bound": "mfma", "achieved": fl / sec / 1e12, "peak": BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "algorithmic_flops": fl / 3.0, "mfma_flops": fl, "matrix_bytes": 8.0 * n * n,
+                "hbm_gbs": 8.0 * n * n / sec / 1e9}
+    if name == "spd_inverse":
+        # one launch = one inverse; the L^+ inverse (n = C) is the larger
+        byt = (C / 64.0) * 8.0 * C * C
+        return {"bound": "hbm", "achieved": byt / sec / 1e9, "peak": HBM_GBS, "unit": "GB/s",
+                "algorithmic_bytes": byt, "note": "per launch as if every launch were the L^+ inverse (n = C); "
+                                                 "the G_ll^-1 inverse (n = V) is smaller"}
+    return None
+
+
+ALL_TAGS_BASE = ["cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll", "cmatvec_ta+v", "dmatvec_lp+gll"]
+ALL_TAGS = (["far_pairs", "near_pairs", "gather_ta"] + ALL_TAGS_BASE +
+            [f"{t}_nr{r}" for t in ALL_TAGS_BASE for r in (2, 3, 4)] +
+            ["symv_reduce", "spd_inverse", "gemm_ta", "gemm_v", "gemm_lp", "gemm_gll", "gemm_gtp"])
+
+
+def run_workload(rf, torch, wl, steps, warmup, label):
+    """Time `steps` whole-path steps of one workload.  Returns the result
+    dict: value (right-hand sides solved per second), ms_per_step, per-k
+    reports, the per-kernel breakdown of one untimed profiled step, and the
+    roofline of the dominant kernel (largest total time) measured with HIP
+    events over the timed steps."""
+    xyz, tri = wl["mesh_fn"]()
+    ks = wl["ka"]
+    nrhs = wl["nrhs"]
+    prec = wl["precision_opt"]
+    N = len(tri) * 3 // 2
+    sz = {"N": N, "C": len(tri), "V": len(xyz)}
+    if nrhs == 1:
+        kh, pol = synth.default_plane_wave()
+    else:
+        kh, pol = synth.plane_waves(nrhs, wl["wave_seed"])
+    start = torch.from_numpy(synth.complex_start(N, 11)).cuda()
+    rec = {}
+
+    def step(record, **opts):
+        m = rf.Mesh(xyz, tri)
+        ops = rf.Operator.create_many(m, ks, power_start=start, precision=prec, **opts)
+        es = [op.rhs_planewave(kh, pol) for op in ops]
+        _, st, infos = rf.batch_solve(ops, es, tol=TOL, maxit=2000)
+        for k, op, info in zip(ks, ops, infos):
+            if record:
+                a, b, g, lam = op.scalings()
+                rec[k] = {"status": st, "max_iters": max(i["iters"] for i in info),
+                          "max_restarts": max(i["restarts"] for i in info),
+                          "max_rel_residual": max(i["rel_residual"] for i in info),
+                          "converged": all(i["rel_residual"] <= TOL for i in info),
+                          "solve_ms": info[0]["ms_solve"], "power_steps": op.power_steps(),
+                          "alpha": a, "beta": b, "gamma": g}
+            op.close()
+        m.close()
+        if st != 0:
+            raise RuntimeError(f"{label}: rfcmp_batch_solve returned status {st}")
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    print(f"# {label}: warmup done", file=sys.stderr, flush=True)
+
+    # one untimed step with every kernel tag timed: the breakdown and the
+    # choice of the dominant kernel (largest total time among all tags)
+    rf.profile_select(None)
+    rf.profile_enable(True)
+    step(False)
+    torch.cuda.synchronize()
+    brk = {t: rf.profile_read(t) for t in ALL_TAGS}
+    rf.profile_enable(False)
+    brk = {t: v for t, v in brk.items() if v[1] > 0}
+    ranked = sorted(brk.items(), key=lambda kv: -kv[1][0])
+    dom = ranked[0][0]
+    asm_ms = sum(brk.get(t, (0.0, 0))[0] for t in ("far_pairs", "near_pairs", "gather_ta")) / len(ks)
+
+    # timed steps: HIP events only around the dominant kernel's launches
+    rf.profile_select([dom])
+    rf.profile_enable(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i == steps - 1)
+        print(f"# {label}: step {i + 1}/{steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dtot, dn = rf.profile_read(dom)
+    rf.profile_enable(False)
+    rf.profile_select(None)
+    ms_step = (t1 - t0) * 1e3 / steps
+    avg = dtot / dn
+    roof = kernel_model(dom, avg, sz, nrhs) or {"bound": None, "achieved": None, "peak": None, "unit": None}
+    if roof.get("achieved") is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(dom, wl["name"])
+    if roof["traffic"] is not None and roof.get("algorithmic_bytes"):
+        roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes"]
+    roof.update({"kernel": dom, "avg_ms": avg, "launches": dn, "launches_per_step": dn / steps})
+    kernels = {}
+    for t, (tot, n) in ranked:
+        e = {"ms_per_step": tot, "launches": n, "avg_ms": tot / n}
+        mdl = kernel_model(t, tot / n, sz, nrhs)
+        if mdl is not None:
+            e.update({"bound": mdl["bound"], "achieved": mdl["achieved"], "unit": mdl["unit"],
+                      "frac": mdl["achieved"] / mdl["peak"]})
+        kernels[t] = e
+    return {"value": len(ks) * nrhs / (ms_step / 1e3), "ms_per_step": ms_step, "per_k": {str(k): rec[k] for k in ks},
+            "assembly_ms_per_k": asm_ms, "assembly_pairs_per_s": sz["C"] ** 2 / (asm_ms / 1e3),
+            "kernels": kernels, "roofline": roof, "dominant": dom}
+
+
+WORKLOADS = {
+    "icosphere5_64rhs": dict(HEADLINE, name="icosphere5_64rhs", mesh_fn=lambda: synth.icosphere(5),
+                             precision_opt=1, wave_seed=4),
+    "icosphere4_two_k": dict(SWEEP, name="icosphere4_two_k", mesh_fn=lambda: synth.icosphere(4),
+                             precision_opt=0, wave_seed=None),
+}
+
+
+def oracle_case(rf, torch):
+    """The icosphere-2 case (N = 480, ka = 0.1, one x-polarised wave along
+    +z, CG to 1e-8) run in full by the FP64 oracle on the host (assembly,
+    projectors, power scalings, CG) and by the GPU on both precision paths:
+    wall time of each phase of the oracle, the GPU solve time, and the error
+    of each GPU result against the oracle's j (whole, loop part, star part)."""
+    from threadpoolctl import threadpool_info
+    from oracle import assembly, rfcmp, rhs
+    from oracle.topology import Topology
+    k, tol = 0.1, 1e-8
+    xyz, tri = synth.icosphere(2)
+    kh, pol = synth.default_plane_wave()
+    ph = {}
+    t = time.perf_counter()
+    top = Topology(xyz, tri)
+    ph["topology_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    TA, V = assembly.assemble(top, k)
+    ph["assembly_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    pre = rfcmp.Preconditioner(top, TA, V, k)
+    ph["projectors_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    pre.power_scalings(synth.complex_start(top.N, 11), 30, tol=1e-2)
+    ph["scalings_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    e = rhs.planewave(top, k, kh, pol)[0]
+    b = pre.rhs(e)
+    i, its, res = rfcmp.cg(pre.apply, b, tol, 1000)
+    jref = pre.recover(i)
+    ph["rhs_and_solve_s"] = time.perf_counter() - t
+    ph["total_s"] = sum(ph.values())
+    ph["cg_iters"] = its
+    ph["blas_threads"] = max((x.get("num_threads", 1) for x in threadpool_info()), default=1)
+    out = {"workload": "icosphere level 2 (320 cells, 480 RWG), ka=0.1, x-polarised wave along +z, CG to 1e-8",
+           "oracle": ph}
+    m = rf.Mesh(xyz, tri)
+    start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
+    for prec in (0, 1):
+        op = rf.Operator(m, k, power_start=start, precision=prec)
+        eg = op.rhs_planewave(kh, pol)
+        op.solve(eg, tol=tol, maxit=1000)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        j, st, info = op.solve(eg, tol=tol, maxit=1000)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        jg = j.cpu().numpy()[0]
+        rel = lambda a, r: float(np.linalg.norm(a - r) / np.linalg.norm(r))
+        out["bf16x3" if prec else "fp32"] = {
+            "solve_ms": ms, "iters": info[0]["iters"], "status": st, "rel_residual": info[0]["rel_residual"],
+            "err_vs_oracle": rel(jg, jref), "err_loop_part": rel(pre.P_LH @ jg, pre.P_LH @ jref),
+            "err_star_part": rel(pre.P_S @ jg, pre.P_S @ jref)}
+        op.close()
+    m.close()
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -384,144 +672,47 @@ def main():
     import paper_1803_08333_amd as rf
 
     torch.cuda.init()
-    dev = torch.device("cuda:0")
-    xyz, tri = synth.icosphere(4)
-    kh, pol = synth.default_plane_wave()
-    N = len(tri) * 3 // 2
-    C = len(tri)
-    start = torch.from_numpy(synth.complex_start(N, 11)).to(dev)
-    out = {}
-
-    def step(record, **opts):
-        m = rf.Mesh(xyz, tri)
-        ops = rf.Operator.create_many(m, KS, power_start=start, **opts)
-        es = [op.rhs_planewave(kh, pol) for op in ops]
-        _, _, infos = rf.batch_solve(ops, es, tol=TOL, maxit=2000)
-        for k, op, info in zip(KS, ops, infos):
-            st = 0 if info[0]["rel_residual"] <= TOL else 1
-            if record:
-                a, b, g, lam = op.scalings()
-                out[k] = {"status": st, "iters": info[0]["iters"], "restarts": info[0]["restarts"],
-                          "rel_residual": info[0]["rel_residual"], "solve_ms": info[0]["ms_solve"],
-                          "alpha": a, "beta": b, "gamma": g}
-            op.close()
-        m.close()
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-
-    # one untimed step with every kernel tag timed: the per-kernel breakdown
-    # and the choice of the dominant kernel
-    base = ["cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll", "cmatvec_ta+v", "dmatvec_lp+gll"]
-    tags = ["far_pairs", "near_pairs", "gather_ta"] + base + [f"{t}_nr{r}" for t in base for r in (2, 3, 4)] + \
-        ["symv_reduce", "spd_inverse"]
-    rf.profile_select(None)
-    rf.profile_enable(True)
-    step(False)
-    torch.cuda.synchronize()
-    brk = {t: rf.profile_read(t) for t in tags}
-    rf.profile_enable(False)
-    asm_ms = sum(brk[t][0] for t in ("far_pairs", "near_pairs", "gather_ta")) / len(KS)
-    pairs_per_s = C * C / (asm_ms / 1e3)
-
-    # roofline of the dominant kernel (largest total time)
-    # symmetric products: the algorithmic bytes are the n (n + 1) / 2 distinct
-    # entries (8 B each) plus x read and y written (16 B each, complex128) per
-    # right-hand side; tags "<name>_nr<k>" are k right-hand sides per launch,
-    # "<a>+<b>" two products sharing one launch
-    def model(tag, avg_ms):
-        name, nr = tag, 1
-        if "_nr" in tag:
-            name, nr = tag.split("_nr")[0], int(tag.split("_nr")[1])
-        sizes = {"cmatvec_ta": [N], "cmatvec_v": [C], "dmatvec_lp": [C], "dmatvec_gll": [len(xyz)],
-                 "cmatvec_ta+v": [N, C], "dmatvec_lp+gll": [C, len(xyz)]}.get(name)
-        if sizes is not None:
-            # the two-column T_A + V launches are the power iteration's, whose
-            # V product takes one column
-            nrs = [nr, 1 if (name == "cmatvec_ta+v" and nr == 2) else nr]
-            byt = sum(8.0 * n * (n + 1) / 2 + 32.0 * n * nrs[q] for q, n in enumerate(sizes))
-            return {"bound": "hbm", "achieved": byt / (avg_ms * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s",
-                    "algorithmic_bytes": byt}
-        if tag == "far_pairs":
-            fl = C * (C - 1) / 2 * 49 * FAR_FLOPS_PER_POINT_PAIR
-            return {"bound": "alu", "achieved": fl / (avg_ms * 1e-3) / 1e12, "peak": FP32_VALU_TFLOPS,
-                    "unit": "TFLOP/s"}
-        return None
-
-    ranked = sorted((v[0], t) for t, v in brk.items() if v[1] > 0 and model(t, 1.0) is not None)
-    dom = ranked[-1][1]
-
-    # timed steps: HIP events only around the dominant kernel's launches
-    rf.profile_select([dom])
-    rf.profile_enable(True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i == args.steps - 1)
-        print(f"# step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = {dom: rf.profile_read(dom)}
-    rf.profile_enable(False)
-    rf.profile_select(None)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = len(KS) / (ms_step / 1e3)
-
-    avg = prof[dom][0] / prof[dom][1]
-    roof = model(dom, avg)
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom)
-    if roof["traffic"] is not None and "algorithmic_bytes" in roof:
-        roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes"]
-    roof["kernel"] = dom
-    roof["avg_ms"] = avg
-    roof["launches"] = prof[dom][1]
-    # The two wavenumbers' power iterations run on concurrent streams, so in
-    # the timed steps a launch of the dominant kernel may share HBM with one
-    # of the other wavenumber's.  The same step with them one after another
-    # (streams = 1, untimed) gives the kernel alone on the device.
-    rf.profile_select([dom])
-    rf.profile_enable(True)
-    step(False, streams=1)
-    torch.cuda.synchronize()
-    iso = rf.profile_read(dom)
-    rf.profile_enable(False)
-    rf.profile_select(None)
-    iso_roof = model(dom, iso[0] / iso[1])
-    roof["isolated"] = {"avg_ms": iso[0] / iso[1], "achieved": iso_roof["achieved"],
-                        "frac": iso_roof["achieved"] / iso_roof["peak"], "launches": iso[1],
-                        "note": "one untimed step with the power iterations one after another (streams = 1)"}
-
+    head = run_workload(rf, torch, WORKLOADS["icosphere5_64rhs"], args.steps, args.warmup, "icosphere5_64rhs")
+    sweep = run_workload(rf, torch, WORKLOADS["icosphere4_two_k"], max(args.steps, 5), args.warmup,
+                         "icosphere4_two_k")
     res = {
         "metric": "RF-CMP solve time + EFIE assembly pairs/s; BF16x3 vs FP32 at 1e-6 residual",
-        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64 blocks (FP32 far-pair quadrature, FP64 near pairs), FP64 accumulation and projectors",
-        "data": "synthetic (seeded icosphere, analytic plane wave)",
-        "config": WORKLOAD,
-        "solve_ms": {str(k): out[k]["solve_ms"] for k in KS},
-        "iterations": {str(k): out[k]["iters"] for k in KS},
-        "rel_residual": {str(k): out[k]["rel_residual"] for k in KS},
-        "scalings": {str(k): [out[k]["alpha"], out[k]["beta"], out[k]["gamma"]] for k in KS},
-        "assembly_pairs_per_s": pairs_per_s,
-        "assembly_ms": asm_ms,
-        "kernel_ms_per_step": {t: brk[t][0] for t in tags if brk[t][1] > 0},
-        "bf16x3_vs_fp32": None,
-        "spectral_study": None,
-        "far_field": None,
-        "roofline": roof,
+        "value": head["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3 MFMA products (FP32 accumulation) over c64 blocks, FP64 projectors and refinement "
+                 "residual; FP32 far-pair quadrature, FP64 near pairs",
+        "data": "synthetic (seeded icosphere, seeded plane waves)",
+        "config": {k: v for k, v in HEADLINE.items()},
+        "per_k": head["per_k"],
+        "assembly_pairs_per_s": head["assembly_pairs_per_s"],
+        "assembly_ms": head["assembly_ms_per_k"],
+        "kernels": head["kernels"],
+        "roofline": head["roofline"],
+        "icosphere4_two_k": {"config": SWEEP, "value": sweep["value"], "unit": "solves/s",
+                             "ms_per_step": sweep["ms_per_step"], "per_k": sweep["per_k"],
+                             "assembly_pairs_per_s": sweep["assembly_pairs_per_s"],
+                             "assembly_ms": sweep["assembly_ms_per_k"], "kernels": sweep["kernels"],
+                             "roofline": sweep["roofline"]},
     }
+    print("# headline and level-4 workloads done", file=sys.stderr, flush=True)
+    if not args.no_oracle_case:
+        res["oracle_case"] = oracle_case(rf, torch)
+        print("# oracle case done", file=sys.stderr, flush=True)
     if not args.no_precision_study:
         res["bf16x3_vs_fp32"] = precision_study(rf, torch, args.batch_rhs)
+        print("# precision study done", file=sys.stderr, flush=True)
     if not args.no_spectral_study:
         res["spectral_study"] = spectral_study(rf)
         res["far_field"] = far_field_measurement(rf, torch)
         res["voltage_gap"] = voltage_gap_measurement(rf, torch)
-    if args.uneven_batch:
+        print("# spectral study, far field, voltage gap done", file=sys.stderr, flush=True)
+    if not args.no_uneven_batch:
         res["uneven_batch"] = uneven_batch(rf, torch)
+        print("# uneven batch done", file=sys.stderr, flush=True)
+    if args.uneven_batch_serial:
         res["uneven_batch_serial"] = uneven_batch(rf, torch, concurrent=False)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(xyz, tri, args.cpu_slab)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_slab, head, res.get("oracle_case"))
     print(json.dumps(res))
 
 

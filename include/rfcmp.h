@@ -60,12 +60,35 @@ typedef enum {
  * failing call on that thread); "" if none. */
 const char* rfcmp_last_error(void);
 const char* rfcmp_version(void);
-/* Device memory.  Buffers that meshes and operators release are kept by the
- * library, per device, and handed out again for later requests of about the
+/* Device memory.  Every device buffer the library owns (blocks, projector
+ * matrices, BF16x3 planes, work vectors, assembly and product scratch) comes
+ * from the registered allocator, else from the library's own cache over
+ * hipMalloc.
+ *
+ * rfcmp_set_allocator registers a caller's device allocator (for instance a
+ * framework's caching allocator; the Python binding registers torch's):
+ *   alloc_fn(bytes, stream, ctx) returns a block of at least `bytes` on the
+ *     calling thread's current device, or NULL when it has none: the library
+ *     call that needed it then fails with RFCMP_E_OOM and leaves its outputs
+ *     untouched;
+ *   free_fn(p, bytes, stream, ctx) takes back a block alloc_fn returned
+ *     (`bytes` as requested there), on the device it came from.
+ * `stream` is always NULL: a block may be used on any stream, and the library
+ * hands it back only after the device is idle.  Both functions may be called
+ * from the library's internal host threads and must be thread-safe.  Each
+ * block goes back to the allocator that made it, even after another one has
+ * been registered.  NULL, NULL (the default) returns to the library's cache.
+ * Giving only one of the two functions is RFCMP_E_ARG.  Host call. */
+typedef void* (*rfcmp_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*rfcmp_free_fn)(void* p, size_t bytes, void* stream, void* ctx);
+rfcmp_status rfcmp_set_allocator(rfcmp_alloc_fn alloc_fn, rfcmp_free_fn free_fn, void* ctx);
+/* The library's own cache: buffers that meshes and operators release are
+ * kept, per device, and handed out again for later requests of about the
  * same size (a new operator on a mesh of the same size maps no new memory).
  * This call returns all kept memory to the driver; *freed_bytes (nullable)
  * receives the amount.  A failing allocation does the same by itself before
- * it retries once.  Host call; waits for nothing. */
+ * it retries once.  Blocks of a registered allocator are never kept here.
+ * Host call; waits for nothing. */
 rfcmp_status rfcmp_release_cached_memory(int64_t* freed_bytes);
 
 /* ------------------------------------------------------------------ mesh */

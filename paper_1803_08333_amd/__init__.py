@@ -8,14 +8,22 @@ names of include/rfcmp.h; ``Mesh`` and ``Operator`` wrap the handles.
 The library must be built first (``python paper_1803_08333_amd/build.py``);
 importing this module without it raises, there is no fallback path.
 
+Device memory: importing the module registers torch's caching allocator with
+the library (rfcmp_set_allocator), so every device buffer the library owns
+comes from torch and shows in torch.cuda.memory_allocated().  Handles still
+open at interpreter exit are closed by an exit hook, while torch is alive.
+
 torch is imported before the library is loaded.  torch brings its own HIP
 runtime; when the library (linked against the system ROCm) is loaded first,
 its first HIP call in a process that later initialises torch finds no
 device, whereas with torch's runtime loaded first both see the GPU.
 """
 
+import atexit
 import ctypes
 import os
+import threading
+import weakref
 
 import numpy as np
 import torch  # noqa: F401  (load order of the HIP runtimes, see above)
@@ -23,7 +31,7 @@ import torch  # noqa: F401  (load order of the HIP runtimes, see above)
 __all__ = [
     "LIB_PATH", "RfcmpError", "Options", "Info", "Mesh", "Operator", "lib",
     "PROJ_SIGMA", "PROJ_LH", "PROJ_GSIGMA", "PROJ_LPINV", "PROJ_GLL_INV", "PROJ_SIGMA_T", "PROJ_LAMBDA_T",
-    "EXPORTED", "batch_solve",
+    "EXPORTED", "batch_solve", "set_allocator", "use_torch_allocator",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfcmp.so")
@@ -67,8 +75,12 @@ _PI64 = ctypes.POINTER(ctypes.c_int64)
 _PI32 = ctypes.POINTER(ctypes.c_int32)
 _PD = ctypes.POINTER(ctypes.c_double)
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
 # name -> (restype, argtypes)
 EXPORTED = {
+    "rfcmp_set_allocator": (_I32, [ALLOC_FN, FREE_FN, _P]),
     "rfcmp_last_error": (ctypes.c_char_p, []),
     "rfcmp_version": (ctypes.c_char_p, []),
     "rfcmp_mesh_create": (_I32, [_PD, _I64, _PI32, _I64, ctypes.POINTER(_P)]),
@@ -145,6 +157,74 @@ def _dptr(t, dtype=None, numel=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# ------------------------------------------------------------ device memory
+_live = weakref.WeakSet()          # open Mesh / Operator objects
+_alloc_state = {"fns": None, "closing": False}
+_alloc_lock = threading.Lock()
+
+
+def set_allocator(alloc=None, free=None):
+    """rfcmp_set_allocator with Python callables: alloc(nbytes) -> device
+    address (int) or None/0 when out of memory, free(address, nbytes).  Both
+    None restores the library's own cache.  The callables run on whichever
+    thread the library allocates from and must not raise; an exception is
+    treated as out of memory (alloc) or ignored (free)."""
+    if (alloc is None) != (free is None):
+        raise ValueError("give both functions or neither")
+    if alloc is None:
+        _check(lib.rfcmp_set_allocator(ctypes.cast(None, ALLOC_FN), ctypes.cast(None, FREE_FN), None))
+        _alloc_state["fns"] = None
+        return
+
+    def _a(nbytes, stream, ctx):
+        if _alloc_state["closing"]:
+            return None
+        try:
+            return alloc(int(nbytes)) or None
+        except Exception:
+            return None
+
+    def _f(p, nbytes, stream, ctx):
+        if _alloc_state["closing"] or not p:
+            return
+        try:
+            free(int(p), int(nbytes))
+        except Exception:
+            pass
+
+    fns = (ALLOC_FN(_a), FREE_FN(_f))
+    with _alloc_lock:
+        _check(lib.rfcmp_set_allocator(fns[0], fns[1], None))
+        # every block goes back through the free function that was current
+        # when it was made: keep all registered thunks alive
+        _alloc_state.setdefault("kept", []).append(fns)
+        _alloc_state["fns"] = fns
+
+
+def use_torch_allocator():
+    """Register torch's caching allocator (the import default)."""
+    torch = _torch()
+
+    def alloc(nbytes):
+        return torch.cuda.caching_allocator_alloc(nbytes)
+
+    def free(p, nbytes):
+        torch.cuda.caching_allocator_delete(p)
+
+    set_allocator(alloc, free)
+
+
+def _close_all_at_exit():
+    # operators before meshes (an operator needs its mesh); then stop calling
+    # back into Python
+    for obj in sorted(list(_live), key=lambda o: 0 if isinstance(o, Operator) else 1):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    _alloc_state["closing"] = True
+
+
 def profile_enable(on=True):
     """rfcmp_profile_enable: start (or stop) HIP-event timing of tagged kernels."""
     _check(lib.rfcmp_profile_enable(int(bool(on))))
@@ -187,6 +267,7 @@ class Mesh:
         _check(lib.rfcmp_mesh_create(xyz.ctypes.data_as(_PD), len(xyz), tri.ctypes.data_as(_PI32), len(tri),
                                      ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
         N, V, C, g = _I64(), _I64(), _I64(), _I32()
         _check(lib.rfcmp_mesh_sizes(h, ctypes.byref(N), ctypes.byref(V), ctypes.byref(C), ctypes.byref(g)))
         self.N, self.V, self.C, self.genus = N.value, V.value, C.value, g.value
@@ -244,6 +325,7 @@ class Operator:
         h = _P()
         _check(lib.rfcmp_op_create(mesh.handle, self.k, ctypes.byref(self.opts), ps, _stream(), ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
 
     @classmethod
     def create_many(cls, mesh, ks, power_start=None, **opts):
@@ -260,6 +342,7 @@ class Operator:
         for k, h in zip(ks, hs):
             op = cls.__new__(cls)
             op.mesh, op.k, op.opts, op.handle = mesh, float(k), options(**opts), _P(h)
+            _live.add(op)
             out.append(op)
         return out
 
@@ -394,3 +477,7 @@ def batch_solve(ops, es, tol=1e-6, maxit=1000):
         out.append([info[k + i].as_dict() for i in range(r)])
         k += r
     return js, st, out
+
+
+use_torch_allocator()
+atexit.register(_close_all_at_exit)

@@ -1,15 +1,18 @@
-// Device memory cache of the library.
+// Device memory of the library.
 //
 // Every device buffer the library owns (blocks, projector matrices, work
-// vectors, scratch) is a DevBuf.  A released buffer goes onto a per-device
-// free list instead of back to the driver; the next request of about the
-// same size on that device takes it.  Building operators again and again on
-// meshes of one size (a sweep over wavenumbers, or a new mesh of the same
-// size each time) then maps no new memory after the first time.  A failed
-// hipMalloc releases the whole cache and tries once more.
+// vectors, scratch) is a DevBuf.  With an allocator registered by
+// rfcmp_set_allocator (for instance a framework's caching allocator) every
+// block comes from it and goes back to it.  Otherwise the library keeps its
+// own cache over hipMalloc: a released buffer goes onto a per-device free
+// list instead of back to the driver, and the next request of about the same
+// size on that device takes it.  Building operators again and again on meshes
+// of one size (a sweep over wavenumbers, or a new mesh of the same size each
+// time) then maps no new memory after the first time.  A failed hipMalloc
+// releases the whole cache and tries once more.
 //
 // Release waits for the device to be idle first (as hipFree would), so a
-// block on the free list is never still read or written by queued work.
+// block handed back is never still read or written by queued work.
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -33,6 +36,18 @@ Cache& cache() {
   return *c;
 }
 
+struct Hook {
+  std::mutex mu;
+  rfcmp_alloc_fn alloc_fn = nullptr;
+  rfcmp_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+};
+
+Hook& hook() {
+  static Hook* h = new Hook;
+  return *h;
+}
+
 size_t rounded(size_t n) {
   const size_t g = n >= (size_t(1) << 20) ? (size_t(2) << 20) : 256;
   return (n + g - 1) / g * g;
@@ -40,10 +55,28 @@ size_t rounded(size_t n) {
 
 }  // namespace
 
-void* dev_alloc(size_t n, size_t* got, int* device) {
+void* dev_alloc(size_t n, size_t* got, int* device, AllocOrigin* origin) {
   const size_t r = rounded(n);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  rfcmp_alloc_fn afn = nullptr;
+  AllocOrigin from;
+  {
+    Hook& h = hook();
+    std::lock_guard<std::mutex> g(h.mu);
+    afn = h.alloc_fn;
+    from.free_fn = h.free_fn;
+    from.ctx = h.ctx;
+  }
+  if (afn) {
+    void* p = afn(r, nullptr, from.ctx);
+    if (!p) return nullptr;
+    *got = r;
+    *device = dev;
+    *origin = from;
+    return p;
+  }
+  *origin = AllocOrigin{};
   Cache& c = cache();
   {
     std::lock_guard<std::mutex> g(c.mu);
@@ -73,13 +106,15 @@ void* dev_alloc(size_t n, size_t* got, int* device) {
   return p;
 }
 
-void dev_free(void* p, size_t bytes, int device) {
+void dev_free(void* p, size_t bytes, int device, const AllocOrigin& origin) {
   if (!p) return;
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != device) (void)hipSetDevice(device);
   (void)hipDeviceSynchronize();
+  if (origin.free_fn) origin.free_fn(p, bytes, nullptr, origin.ctx);
   if (cur != device) (void)hipSetDevice(cur);
+  if (origin.free_fn) return;
   Cache& c = cache();
   std::lock_guard<std::mutex> g(c.mu);
   c.blocks.insert({{device, bytes}, p});
@@ -110,6 +145,20 @@ size_t dev_cache_bytes() {
 }
 
 }  // namespace rfcmp
+
+extern "C" rfcmp_status rfcmp_set_allocator(rfcmp_alloc_fn alloc_fn, rfcmp_free_fn free_fn, void* ctx) {
+  rfcmp::clear_error();
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) {
+    rfcmp::set_error("rfcmp_set_allocator: give both functions or neither");
+    return RFCMP_E_ARG;
+  }
+  rfcmp::Hook& h = rfcmp::hook();
+  std::lock_guard<std::mutex> g(h.mu);
+  h.alloc_fn = alloc_fn;
+  h.free_fn = free_fn;
+  h.ctx = alloc_fn ? ctx : nullptr;
+  return RFCMP_OK;
+}
 
 extern "C" rfcmp_status rfcmp_release_cached_memory(int64_t* freed_bytes) {
   const size_t f = rfcmp::dev_cache_release();

@@ -33,34 +33,45 @@ void clear_error();
     if (s_ < 0) return s_;                 \
   } while (0)
 
-// Device memory cache (devmem.cpp): dev_alloc returns a block of at least n
-// bytes on the current device (its size in *got, its device in *device) or
-// nullptr; dev_free puts a block back after the device is idle.
-void* dev_alloc(size_t n, size_t* got, int* device);
-void dev_free(void* p, size_t bytes, int device);
+// Where a device block came from: the caller's allocator (rfcmp_set_allocator;
+// free_fn non-null) or the library's own cache over hipMalloc (free_fn null).
+// Each block is returned to the allocator that made it, even if another one
+// has been registered since.
+struct AllocOrigin {
+  rfcmp_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+};
+
+// Device memory (devmem.cpp): dev_alloc returns a block of at least n bytes on
+// the current device (its size in *got, its device in *device, its origin in
+// *origin) or nullptr; dev_free returns a block after the device is idle.
+void* dev_alloc(size_t n, size_t* got, int* device, AllocOrigin* origin);
+void dev_free(void* p, size_t bytes, int device, const AllocOrigin& origin);
 size_t dev_cache_release();
 size_t dev_cache_bytes();
 
-// Owning device buffer (memory from the library's cache).
+// Owning device buffer.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;     // bytes requested
   size_t capacity = 0;  // bytes of the block
   int device = -1;
+  AllocOrigin origin;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) dev_free(p, capacity, device);
+    if (p) dev_free(p, capacity, device, origin);
     p = nullptr;
     bytes = capacity = 0;
     device = -1;
+    origin = AllocOrigin{};
   }
   rfcmp_status alloc(size_t n) {
     release();
     if (n == 0) return RFCMP_OK;
-    p = dev_alloc(n, &capacity, &device);
+    p = dev_alloc(n, &capacity, &device, &origin);
     if (!p) {
       set_error("device allocation of %zu bytes failed", n);
       return RFCMP_E_OOM;

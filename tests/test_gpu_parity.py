@@ -276,10 +276,16 @@ def test_block_solve_matches_oracle(precision, name, k):
     j, st, info = op.solve(_cuda(e), tol=1e-8, maxit=400)
     j = _np(j)
     assert st == 0
+    # FP32 path: 1e-5; BF16x3 with FP64-residual refinement: 1e-6 (both
+    # against the oracle's FP64 solution on its own FP64 blocks)
+    tol = 1e-6 if precision == 1 else 1e-5
+    errs = [rel(j[r], jref[r]) for r in range(len(e))]
+    errs_s = [rel(pre.P_S @ j[r], pre.P_S @ jref[r]) for r in range(len(e))]
+    print(f"precision {precision} {name} ka={k}: max rel err {max(errs):.2e}, star part {max(errs_s):.2e}")
     for r in range(len(e)):
         assert info[r]["rel_residual"] <= 1e-8
-        assert rel(j[r], jref[r]) < 1e-5, r
-        assert rel(pre.P_S @ j[r], pre.P_S @ jref[r]) < 1e-5, r
+        assert errs[r] < tol, (r, errs[r])
+        assert errs_s[r] < tol, (r, errs_s[r])
     if precision == 1:
         assert max(i["restarts"] for i in info) >= 1       # refinement rounds happened
 

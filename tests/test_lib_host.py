@@ -172,3 +172,22 @@ def test_batch_solve_argument_errors():
     assert st == -1 and b"twice" in msg, msg
     with pytest.raises(ValueError):
         rf.batch_solve([], [])
+
+
+def test_set_allocator_arguments():
+    """rfcmp_set_allocator: both functions or neither (else RFCMP_E_ARG);
+    registering and resetting are host calls that touch no device."""
+    import paper_1803_08333_amd as rf
+    lib = rf.lib
+    none_a, none_f = ctypes.cast(None, rf.ALLOC_FN), ctypes.cast(None, rf.FREE_FN)
+    a = rf.ALLOC_FN(lambda n, s, c: None)
+    f = rf.FREE_FN(lambda p, n, s, c: None)
+    assert lib.rfcmp_set_allocator(a, none_f, None) == -1
+    assert b"both" in lib.rfcmp_last_error()
+    assert lib.rfcmp_set_allocator(none_a, f, None) == -1
+    assert lib.rfcmp_set_allocator(a, f, None) == 0
+    assert lib.rfcmp_set_allocator(none_a, none_f, None) == 0
+    with pytest.raises(ValueError):
+        rf.set_allocator(lambda n: 0, None)
+    rf.use_torch_allocator()             # the import default, restored
+    assert rf._alloc_state["fns"] is not None
