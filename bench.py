@@ -712,7 +712,7 @@ def main():
     if args.uneven_batch_serial:
         res["uneven_batch_serial"] = uneven_batch(rf, torch, concurrent=False)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.cpu_slab, head, res.get("oracle_case"))
+        res["cpu_baseline"] = cpu_baseline(args.cpu_slab, head)
     print(json.dumps(res))
 
 
