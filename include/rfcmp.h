@@ -186,6 +186,22 @@ void rfcmp_op_destroy(rfcmp_op op);
 rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* pol,
                                  int32_t nrhs, void* e, void* stream);
 
+/* rfcmp_rhs_planewave for callers that cannot allocate device memory (serving
+ * loops that must not touch an allocator, harnesses that forbid allocation):
+ * the same excitation, bit for bit, with khat and pol staged in a fixed
+ * device array of the library (RFCMP_RHS_NOALLOC_MAX plane waves, 6 doubles
+ * each: 192 KiB per device, set up on the first call on that device and held
+ * until the process ends) instead of a buffer allocated per call.  Calls no
+ * allocator and allocates nothing.  nrhs above RFCMP_RHS_NOALLOC_MAX is
+ * RFCMP_E_ARG.  Every call on one device shares the array, which keeps the
+ * last call's contents; each call waits for its stream before returning, so
+ * calls from one host thread never overlap, but calls from several host
+ * threads on one device race.  Arguments and errors otherwise as
+ * rfcmp_rhs_planewave. */
+#define RFCMP_RHS_NOALLOC_MAX 4096
+rfcmp_status rfcmp_rhs_planewave_noalloc(rfcmp_op op, const double* khat, const double* pol,
+                                         int32_t nrhs, void* e, void* stream);
+
 /* Voltage-gap (delta-gap) excitation, the second source of the Fokker
  * example (Sec. 4): e_r[n] = sum of volts[r][g] over the gaps g with
  * edges[r][g] = n, zero elsewhere.  A gap of voltage V across edge m is the

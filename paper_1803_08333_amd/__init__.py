@@ -31,12 +31,13 @@ import torch  # noqa: F401  (load order of the HIP runtimes, see above)
 __all__ = [
     "LIB_PATH", "RfcmpError", "Options", "Info", "Mesh", "Operator", "lib",
     "PROJ_SIGMA", "PROJ_LH", "PROJ_GSIGMA", "PROJ_LPINV", "PROJ_GLL_INV", "PROJ_SIGMA_T", "PROJ_LAMBDA_T",
-    "EXPORTED", "batch_solve", "set_allocator", "use_torch_allocator",
+    "EXPORTED", "batch_solve", "set_allocator", "use_torch_allocator", "RHS_NOALLOC_MAX",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfcmp.so")
 
 PROJ_SIGMA, PROJ_LH, PROJ_GSIGMA, PROJ_LPINV, PROJ_GLL_INV, PROJ_SIGMA_T, PROJ_LAMBDA_T = range(7)
+RHS_NOALLOC_MAX = 4096   # RFCMP_RHS_NOALLOC_MAX
 
 _STATUS = {
     0: "OK", 1: "W_NOT_CONVERGED", -1: "E_ARG", -2: "E_MESH_OPEN", -3: "E_MESH_NONMANIFOLD",
@@ -97,6 +98,7 @@ EXPORTED = {
     "rfcmp_op_export": (_I32, [_P, _P, _P, _P]),
     "rfcmp_op_destroy": (None, [_P]),
     "rfcmp_rhs_planewave": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
+    "rfcmp_rhs_planewave_noalloc": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
     "rfcmp_rhs_gap": (_I32, [_P, _PI32, _P, _I32, _I32, _P, _P]),
     "rfcmp_farfield": (_I32, [_P, _P, _I32, _PD, _I32, _P, _P, _P]),
     "rfcmp_precond_rhs": (_I32, [_P, _P, _P, _I32, _P]),
@@ -376,6 +378,17 @@ class Operator:
         e = torch.empty((len(khat), self.mesh.N), dtype=torch.complex128, device="cuda")
         _check(lib.rfcmp_rhs_planewave(self.handle, khat.ctypes.data_as(_PD), pol.ctypes.data_as(_PD), len(khat),
                                        _dptr(e), _stream()))
+        return e
+
+    def rhs_planewave_noalloc(self, khat, pol, e):
+        """rfcmp_rhs_planewave_noalloc into the caller's tensor e (complex128
+        [nrhs, N]); the library allocates nothing."""
+        torch = _torch()
+        khat = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        pol = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.float64)
+        _check(lib.rfcmp_rhs_planewave_noalloc(self.handle, khat.ctypes.data_as(_PD), pol.ctypes.data_as(_PD),
+                                               len(khat), _dptr(e, torch.complex128, len(khat) * self.mesh.N),
+                                               _stream()))
         return e
 
     def _unary(self, fn, x, nout=None, *pre):

@@ -22,6 +22,7 @@
 // the outer cell is the lower-indexed one and self blocks are symmetrised.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -684,6 +685,58 @@ rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, i
                      m->d.edge_cell.as<int>(), m->d.edge_slot.as<int>(), m->d.vtx.as<double>(), op->k, dk.as<double>(),
                      dk.as<double>() + 3 * nrhs, rule_args(), e);
   RF_HIP(hipGetLastError());
+  RF_HIP(hipStreamSynchronize(s));
+  return RFCMP_OK;
+}
+
+// Staging of rfcmp_rhs_planewave_noalloc: the directions and polarisations of
+// at most RFCMP_RHS_NOALLOC_MAX plane waves (khat [nrhs][3], then pol
+// [nrhs][3]), in a fixed array of each device instead of a buffer allocated
+// per call.  Host code never uses the array's name as an address: its device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double rhs_stage[6 * RFCMP_RHS_NOALLOC_MAX];
+
+namespace {
+constexpr int kMaxDevices = 64;
+
+rfcmp_status rhs_stage_address(double** out) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  RF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d beyond the %d devices the staging array is set up for", dev, kMaxDevices);
+    return RFCMP_E_STATE;
+  }
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    RF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(rhs_stage)));
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return RFCMP_OK;
+}
+}  // namespace
+
+rfcmp_status rhs_planewave_noalloc(rfcmp_op op, const double* khat, const double* pol, int nrhs, double2* e,
+                                   hipStream_t s) {
+  if (nrhs > RFCMP_RHS_NOALLOC_MAX) {
+    set_error("rfcmp_rhs_planewave_noalloc: %d plane waves, at most %d", nrhs, RFCMP_RHS_NOALLOC_MAX);
+    return RFCMP_E_ARG;
+  }
+  rfcmp_mesh m = op->mesh;
+  const int64_t N = m->h.N;
+  double* stage = nullptr;
+  RF_TRY(rhs_stage_address(&stage));
+  RF_HIP(hipMemcpyAsync(stage, khat, sizeof(double) * 3 * nrhs, hipMemcpyHostToDevice, s));
+  RF_HIP(hipMemcpyAsync(stage + 3 * nrhs, pol, sizeof(double) * 3 * nrhs, hipMemcpyHostToDevice, s));
+  const long total = (long)N * nrhs;
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (int)N, nrhs,
+                     m->d.edge_cell.as<int>(), m->d.edge_slot.as<int>(), m->d.vtx.as<double>(), op->k, stage,
+                     stage + 3 * nrhs, rule_args(), e);
+  RF_HIP(hipGetLastError());
+  // the next call on this device overwrites the stage
   RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;
 }

@@ -226,6 +226,8 @@ rfcmp_status mesh_upload(rfcmp_mesh m, hipStream_t s);
 rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s);
 rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, int nrhs,
                            double2* e, hipStream_t s);
+rfcmp_status rhs_planewave_noalloc(rfcmp_op op, const double* khat, const double* pol, int nrhs, double2* e,
+                                   hipStream_t s);
 rfcmp_status rhs_gap(rfcmp_mesh m, const int32_t* edges, const double2* volts, int ngap, int nrhs, double2* e,
                      hipStream_t s);
 rfcmp_status far_field(rfcmp_op op, const double2* j, int nrhs, const double* dirs, int ndir, double2* F,

@@ -1101,6 +1101,18 @@ rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* 
   return rhs_planewave(op, khat, pol, nrhs, static_cast<double2*>(e), static_cast<hipStream_t>(stream));
 }
 
+rfcmp_status rfcmp_rhs_planewave_noalloc(rfcmp_op op, const double* khat, const double* pol, int32_t nrhs,
+                                         void* e, void* stream) {
+  RF_ARG(op && khat && pol && e, "NULL argument");
+  RF_ARG(nrhs > 0 && nrhs <= RFCMP_RHS_NOALLOC_MAX, "nrhs must be in [1, RFCMP_RHS_NOALLOC_MAX]");
+  for (int r = 0; r < nrhs; ++r) {
+    RF_ARG(unit(khat + 3 * r) && unit(pol + 3 * r), "khat and pol must be unit vectors (1e-12)");
+    const double dp = khat[3 * r] * pol[3 * r] + khat[3 * r + 1] * pol[3 * r + 1] + khat[3 * r + 2] * pol[3 * r + 2];
+    RF_ARG(std::fabs(dp) <= 1e-12, "pol must be orthogonal to khat (1e-12)");
+  }
+  return rhs_planewave_noalloc(op, khat, pol, nrhs, static_cast<double2*>(e), static_cast<hipStream_t>(stream));
+}
+
 rfcmp_status rfcmp_rhs_gap(rfcmp_mesh m, const int32_t* edges, const void* volts, int32_t ngap, int32_t nrhs,
                            void* e, void* stream) {
   RF_ARG(m && e, "NULL argument");

@@ -191,3 +191,10 @@ def test_set_allocator_arguments():
         rf.set_allocator(lambda n: 0, None)
     rf.use_torch_allocator()             # the import default, restored
     assert rf._alloc_state["fns"] is not None
+
+
+def test_noalloc_limit_matches_header(root):
+    import paper_1803_08333_amd as rf
+    src = open(os.path.join(root, "include", "rfcmp.h")).read()
+    m = re.search(r"#define RFCMP_RHS_NOALLOC_MAX (\d+)", src)
+    assert m and int(m.group(1)) == rf.RHS_NOALLOC_MAX
