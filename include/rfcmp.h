@@ -133,6 +133,13 @@ typedef struct {
                              power_iters steps */
   int32_t streams;        /* power iterations rfcmp_op_create_many runs at once,
                              1..4, default 4 (1 = one after another on `stream`) */
+  int32_t projector;      /* how L^+, G_ll^-1 and G_tp^-1 are applied (Sec. 2-3 projectors):
+                             0 = sparse FP64 Cholesky factors (default): nested
+                                 dissection of the mesh, factored on host threads
+                                 from rfcmp_mesh_create on, O(n log n) entries,
+                                 solved on the device in FP64 in every precision;
+                             1 = dense FP64 inverses formed on the device
+                                 (O(n^3) set-up, 8 n^2 bytes each) */
 } rfcmp_options;
 rfcmp_status rfcmp_options_default(rfcmp_options* opt);
 

@@ -21,7 +21,7 @@ import numpy as np
 
 from . import grams
 
-__all__ = ["Preconditioner", "cg", "power_norm", "iteration_bound"]
+__all__ = ["Preconditioner", "cg", "power_norm", "iteration_bound", "efie_condition"]
 
 
 class Preconditioner:
@@ -234,3 +234,14 @@ def cg(apply, b, tol, maxit):
 def iteration_bound(cond, eps):
     """CG iteration bound of eq. Niter: ceil(1/2 sqrt(cond) log(2/eps))."""
     return int(np.ceil(0.5 * np.sqrt(cond) * np.log(2.0 / eps)))
+
+
+def efie_condition(top, TA, V, k):
+    """Condition number of the unpreconditioned EFIE matrix (Sec. 2):
+    T = i k T_A + Sigma V Sigma^T/(i k), which is complex symmetric but not
+    Hermitian, so cond(T) is the ratio of its largest and smallest singular
+    values.  The paper's introduction states that it grows as (k h)^-2."""
+    Sig = top.Sigma
+    T = 1j * k * TA + (Sig @ V @ Sig.T) / (1j * k)
+    sv = np.linalg.svd(T, compute_uv=False)
+    return float(sv[0] / sv[-1])

@@ -56,7 +56,7 @@ class Options(ctypes.Structure):
     _fields_ = [("near_factor", ctypes.c_double), ("outer_star", ctypes.c_int32),
                 ("scaling", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("power_tol", ctypes.c_double),
-                ("streams", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("projector", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librfcmp.so")
-SOURCES = ["devmem.cpp", "mesh.cpp", "assemble.hip", "dense.hip", "symv.hip", "vecops.hip", "gemm.hip", "rfcmp.hip"]
+SOURCES = ["devmem.cpp", "mesh.cpp", "spchol.cpp", "assemble.hip", "dense.hip", "symv.hip", "vecops.hip", "gemm.hip",
+           "spsolve.hip", "rfcmp.hip"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
@@ -41,7 +42,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(5, os.cpu_count() or 1)) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         results = list(ex.map(_compile, SOURCES))
     objs = [o for o, _ in results]
     if verbose:

@@ -31,6 +31,7 @@
 // slices in a fixed order in FP64 and forms the complex result.
 #include "internal.h"
 #include "gemm.h"
+#include "spchol.h"
 
 namespace rfcmp {
 

@@ -16,6 +16,7 @@ namespace rfcmp {
 
 void set_error(const char* fmt, ...);
 void clear_error();
+const char* last_error();  // of the calling thread
 
 #define RF_HIP(call)                                                                   \
   do {                                                                                 \
@@ -134,11 +135,23 @@ struct MeshHost {
 };
 
 struct SplitMatrix;  // BF16x3 planes of a matrix (gemm.h)
+struct SpFactor;     // sparse Cholesky factor, host (spchol.h)
+struct SpDevice;     // sparse Cholesky factor, device (spchol.h)
+
+// A sparse factor computed on a host thread.
+struct HostFactor {
+  rfcmp_status status = RFCMP_OK;
+  std::string error;
+  std::shared_ptr<SpFactor> F;
+};
 
 // Device copies and the dense FP64 projector matrices of one mesh.
 struct MeshDev {
-  bool ready = false;
+  bool uploaded = false;     // mesh arrays on the device
+  bool ready = false;        // dense projector inverses built
   bool has_gtp = false;
+  // sparse projector factors on the device: L (grounded), G_ll, G_tp
+  std::unique_ptr<SpDevice> sp[3];
   int64_t ldL = 0, ldG = 0, ldT = 0;  // padded leading dims of L^+, G_ll^-1, G_tp^-1
   DevBuf cen;        // double [C][3]
   DevBuf vtx;        // double [C][9]  cell vertices
@@ -184,6 +197,9 @@ struct rfcmp_mesh_s {
   // before h goes)
   double near_async_factor = -1.0;
   std::future<std::vector<int32_t>> near_async;
+  // sparse factors of L and G_ll, computed on host threads from mesh
+  // creation on (declared after h: their destructors wait for the threads)
+  std::future<rfcmp::HostFactor> fac_async[2];
 };
 
 namespace rfcmp {
@@ -212,6 +228,9 @@ struct rfcmp_op_s {
   std::unique_ptr<rfcmp::SplitMatrix> TA16, V16;  // BF16x3 planes (precision 1)
   rfcmp::DevBuf gemm_scratch;
   rfcmp::DevBuf symv_scratch;  // partial sums of the symmetric products
+  rfcmp::DevBuf sp_scratch;    // sparse projector solves: one region per factor (L, G_ll, G_tp)
+  int64_t sp_region[3] = {0, 0, 0};  // complex128 offsets of the regions
+  int sp_scratch_nrhs = 0;
 };
 
 namespace rfcmp {
@@ -232,6 +251,13 @@ rfcmp_status rhs_gap(rfcmp_mesh m, const int32_t* edges, const double2* volts, i
                      hipStream_t s);
 rfcmp_status far_field(rfcmp_op op, const double2* j, int nrhs, const double* dirs, int ndir, double2* F,
                        double* rcs, hipStream_t s);
+
+// spsolve.hip: the sparse factors of a mesh (which 0 = L, grounded; 1 = G_ll;
+// 2 = G_tp, needs build_cell_nb first), and their upload: joins the host
+// threads started at mesh creation (or factors here), uploads on an internal
+// stream and waits for the copies.
+HostFactor factor_mesh_matrix(const MeshHost& h, int which);
+rfcmp_status mesh_sparse_projectors(rfcmp_mesh m, bool need_gtp);
 
 // dense.hip
 rfcmp_status mesh_projectors(rfcmp_mesh m, bool need_gtp, hipStream_t s);

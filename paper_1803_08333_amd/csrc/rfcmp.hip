@@ -27,6 +27,7 @@
 #include <tuple>
 
 #include "gemm.h"
+#include "spchol.h"
 #include "symv.h"
 #include "vecops.h"
 
@@ -82,6 +83,28 @@ Work carve(rfcmp_op op) {
   return w;
 }
 
+// Scratch of the sparse projector solves for the workspace's right-hand
+// sides: one region per factor of the mesh (L, G_ll, G_tp), so that the two
+// solves of a paired launch never share one.  Sized once the factors exist.
+rfcmp_status ensure_sp_scratch(rfcmp_op op) {
+  if (op->opt.projector != 0) return RFCMP_OK;
+  const MeshDev& d = op->mesh->d;
+  int64_t off[3] = {0, 0, 0}, total = 0;
+  for (int q = 0; q < 3; ++q) {
+    off[q] = total;
+    if (d.sp[q]) total += (int64_t)op->work_nrhs * d.sp[q]->scratch_entries();
+  }
+  if (total == 0) return RFCMP_OK;
+  if (op->sp_scratch.p && op->sp_scratch.bytes >= sizeof(double2) * (size_t)total && op->sp_scratch_nrhs == op->work_nrhs &&
+      op->sp_region[2] == off[2] && op->sp_region[1] == off[1])
+    return RFCMP_OK;
+  if (op->sp_scratch.p) RF_HIP(hipDeviceSynchronize());  // the old scratch may still be in use
+  RF_TRY(op->sp_scratch.alloc(sizeof(double2) * (size_t)total));
+  for (int q = 0; q < 3; ++q) op->sp_region[q] = off[q];
+  op->sp_scratch_nrhs = op->work_nrhs;
+  return RFCMP_OK;
+}
+
 // Grow the workspace (and pinned host scalars) to at least R right-hand sides.
 rfcmp_status ensure_work(rfcmp_op op, int R) {
   R = std::max(R, 4);
@@ -95,7 +118,7 @@ rfcmp_status ensure_work(rfcmp_op op, int R) {
   op->host_scal_dev = nullptr;
   RF_HIP(hipHostMalloc((void**)&op->host_scal, sizeof(double) * (16 + 8 * R), hipHostMallocMapped));
   RF_HIP(hipHostGetDevicePointer((void**)&op->host_scal_dev, op->host_scal, 0));
-  return RFCMP_OK;
+  return ensure_sp_scratch(op);
 }
 
 // ------------------------------------------------------------------ dense products
@@ -160,8 +183,52 @@ struct Dense {
     return gemm_bf16x3(split(m), conj, x, y, nr, op->gemm_scratch.p, op->gemm_scratch.bytes, s, gemm_tag(m));
   }
 
+  // The projector matrices as sparse FP64 factors (projector option 0): in
+  // both precisions.
+  bool sparse(Mat m) const { return !complex_matrix(m) && op->opt.projector == 0; }
+  static int sp_index(Mat m) { return m == kLP ? 0 : (m == kGLL ? 1 : 2); }
+  static const char* sp_tag(Mat m0, const Mat* m1) {
+    static const char* t[] = {"spsolve_lp", "spsolve_gll", "spsolve_gtp"};
+    static const char* tp[] = {"spsolve_lp+gll", "spsolve_lp+gtp"};
+    if (!m1) return t[sp_index(m0)];
+    return *m1 == kGLL ? tp[0] : tp[1];
+  }
+  rfcmp_status sp_solve(Mat m0, const SymvInput& in0, double2* y0, const Mat* m1, const SymvInput* in1,
+                        double2* y1, int nr, int nr1) const {
+    const MeshDev& d = op->mesh->d;
+    SpSolveJob j[2];
+    const Mat ms[2] = {m0, m1 ? *m1 : m0};
+    const int nj = m1 ? 2 : 1;
+    for (int q = 0; q < nj; ++q) {
+      const int fi = sp_index(ms[q]);
+      if (!d.sp[fi]) {
+        set_error("sparse projector factor %d not built for this mesh", fi);
+        return RFCMP_E_STATE;
+      }
+      // the job's right-hand sides must fit its scratch region
+      const int64_t need = (int64_t)(q ? (nr1 > 0 ? nr1 : nr) : nr) * d.sp[fi]->scratch_entries();
+      if (op->sp_scratch_nrhs < (q ? (nr1 > 0 ? nr1 : nr) : nr) ||
+          (op->sp_region[fi] + need) * (int64_t)sizeof(double2) > (int64_t)op->sp_scratch.bytes) {
+        set_error("sparse projector solve: scratch region %d too small", fi);
+        return RFCMP_E_STATE;
+      }
+      j[q].F = d.sp[fi].get();
+      j[q].in = q ? *in1 : in0;
+      j[q].y = q ? y1 : y0;
+      j[q].scratch = op->sp_scratch.as<double2>() + op->sp_region[fi];
+      j[q].nrhs = q ? nr1 : 0;
+    }
+    if (nr > op->work_nrhs) {
+      set_error("sparse projector solve: %d right-hand sides, scratch for %d", nr, op->work_nrhs);
+      return RFCMP_E_STATE;
+    }
+    const char* tag = sp_tag(m0, m1);
+    return spsolve_jobs(j, nj, nr, s, nr == 1 ? tag : profile_tag_suffix(tag, nr));
+  }
+
   // y = M x (conj: conj(M) x, complex matrices only).
   rfcmp_status prod(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
+    if (sparse(m)) return sp_solve(m, in, y, nullptr, nullptr, nullptr, nr, 0);
     if (bf16) return gemm(m, conj, in, y, nr);
     const SymvJob j = job(m, in, y);
     if (complex_matrix(m))
@@ -175,6 +242,11 @@ struct Dense {
   // nr1 > 0: the second product takes only nr1 of the nr right-hand sides.
   rfcmp_status pair(Mat m0, const SymvInput& in0, double2* y0, Mat m1, const SymvInput& in1, double2* y1,
                     bool conj, int nr, int nr1 = 0) const {
+    if (sparse(m0) && sparse(m1)) return sp_solve(m0, in0, y0, &m1, &in1, y1, nr, nr1);
+    if (sparse(m0) || sparse(m1)) {
+      RF_TRY(prod(m0, conj, in0, y0, nr));
+      return prod(m1, conj, in1, y1, nr1 > 0 ? nr1 : nr);
+    }
     if (bf16) {
       RF_TRY(gemm(m0, conj, in0, y0, nr));
       return gemm(m1, conj, in1, y1, nr1 > 0 ? nr1 : nr);
@@ -664,9 +736,17 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
   return st;
 }
 
-rfcmp_status ensure_mesh_device(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
-  if (!m->d.ready) {
+// The mesh arrays on the device, and for the dense projectors (projector
+// option 1) their inverses, enqueued on internal streams.  The sparse
+// factors are joined and uploaded by mesh_sparse_projectors once the caller
+// has queued its own work.
+rfcmp_status ensure_mesh_device(rfcmp_mesh m, bool need_gtp, bool dense, hipStream_t s) {
+  if (!m->d.uploaded) {
     RF_TRY(mesh_upload(m, s));
+    m->d.uploaded = true;
+  }
+  if (!dense) return RFCMP_OK;
+  if (!m->d.ready) {
     RF_TRY(mesh_projectors(m, need_gtp, s));
     m->d.ready = true;
   } else if (need_gtp && !m->d.has_gtp) {
@@ -675,18 +755,28 @@ rfcmp_status ensure_mesh_device(rfcmp_mesh m, bool need_gtp, hipStream_t s) {
   return RFCMP_OK;
 }
 
+// Everything the operator's projectors need before its first product on s.
+rfcmp_status ready_projectors(rfcmp_op op, hipStream_t s) {
+  rfcmp_mesh m = op->mesh;
+  if (op->opt.projector == 0) {
+    RF_TRY(mesh_sparse_projectors(m, op->opt.outer_star == 1));
+    RF_TRY(ensure_sp_scratch(op));
+  }
+  return wait_projectors(m, s);
+}
+
 // BF16x3 planes of the operator's blocks and of the mesh's projector matrices.
 rfcmp_status ensure_split(rfcmp_op op, hipStream_t s) {
   rfcmp_mesh m = op->mesh;
   MeshDev& d = m->d;
   const MeshHost& h = m->h;
-  if (!d.Lp16) {
+  if (op->opt.projector == 1 && !d.Lp16) {
     d.Lp16 = std::make_unique<SplitMatrix>();
     RF_TRY(d.Lp16->from_f64(d.Lp.as<double>(), h.C, d.ldL, s));
     d.Gll16 = std::make_unique<SplitMatrix>();
     RF_TRY(d.Gll16->from_f64(d.Gll_inv.as<double>(), h.V, d.ldG, s));
   }
-  if (d.has_gtp && !d.Gtp16) {
+  if (op->opt.projector == 1 && d.has_gtp && !d.Gtp16) {
     d.Gtp16 = std::make_unique<SplitMatrix>();
     RF_TRY(d.Gtp16->from_f64(d.Gtp_inv.as<double>(), h.C, d.ldT, s));
   }
@@ -904,6 +994,14 @@ rfcmp_status rfcmp_mesh_create(const double* xyz, int64_t nv, const int32_t* tri
   } catch (const std::exception&) {
     m->near_async_factor = -1.0;  // computed when first needed
   }
+  // the sparse factors of L and G_ll on two more host threads (joined when
+  // an operator first needs them)
+  try {
+    const MeshHost* hp = &m->h;
+    for (int q = 0; q < 2; ++q) m->fac_async[q] = std::async(std::launch::async, [hp, q]() { return factor_mesh_matrix(*hp, q); });
+  } catch (const std::exception&) {
+    // factored on the calling thread when first needed
+  }
   *out = m.release();
   return RFCMP_OK;
 }
@@ -947,6 +1045,7 @@ rfcmp_status rfcmp_options_default(rfcmp_options* o) {
   o->precision = 0;
   o->power_tol = 1e-2;
   o->streams = kBatchStreams;
+  o->projector = 0;
   return RFCMP_OK;
 }
 
@@ -974,6 +1073,7 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
   RF_ARG(o.scaling == 1 || (o.power_iters > 0 && power_start), "power scalings need power_iters > 0 and power_start");
   RF_ARG(std::isfinite(o.power_tol) && o.power_tol >= 0, "power_tol must be >= 0");
   RF_ARG(o.streams >= 1 && o.streams <= kBatchStreams, "streams must be 1..4");
+  RF_ARG(o.projector == 0 || o.projector == 1, "projector must be 0 or 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   RF_HIP(hipGetDevice(&dev));
@@ -981,7 +1081,7 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
     set_error("mesh device data live on device %d, current device is %d", m->device, dev);
     return RFCMP_E_STATE;
   }
-  RF_TRY(ensure_mesh_device(m, o.outer_star == 1, s));
+  RF_TRY(ensure_mesh_device(m, o.outer_star == 1, o.projector == 1, s));
   m->device = dev;
   const int64_t N = m->h.N, C = m->h.C, V = m->h.V;
   std::vector<std::unique_ptr<rfcmp_op_s>> ops(nk);
@@ -1001,7 +1101,7 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
     RF_TRY(op->symv_scratch.alloc(symv_scratch_bytes(N, 4) + symv_scratch_bytes(C, 4) + symv_scratch_bytes(V, 4)));
     RF_TRY(assemble_blocks(op.get(), s));
   }
-  RF_TRY(wait_projectors(m, s));
+  for (int32_t i = 0; i < nk; ++i) RF_TRY(ready_projectors(ops[i].get(), s));
   for (int32_t i = 0; i < nk; ++i) {
     rfcmp_op op = ops[i].get();
     op->alpha = std::sqrt(k[i]);
@@ -1177,34 +1277,35 @@ rfcmp_status rfcmp_project(rfcmp_op op, int32_t which, const void* xv, void* yv,
   hipStream_t s = static_cast<hipStream_t>(stream);
   rfcmp_mesh m = op->mesh;
   if (which == RFCMP_PROJ_GSIGMA) {
-    RF_TRY(ensure_mesh_device(m, true, s));
+    RF_TRY(ensure_mesh_device(m, true, op->opt.projector == 1, s));
+    if (op->opt.projector == 0) RF_TRY(mesh_sparse_projectors(m, true));
     RF_TRY(wait_projectors(m, s));
   }
+  RF_TRY(ensure_sp_scratch(op));
   const MeshDev& d = m->d;
   const int64_t N = m->h.N, C = m->h.C, V = m->h.V;
   const int64_t nin = (which == RFCMP_PROJ_LPINV) ? C : (which == RFCMP_PROJ_GLL_INV ? V : N);
   const int64_t nout = (which <= RFCMP_PROJ_GSIGMA) ? N : (which == RFCMP_PROJ_LAMBDA_T || which == RFCMP_PROJ_GLL_INV ? V : C);
   RF_TRY(ensure_work(op, std::min(nrhs, 64)));
   const Work W = carve(op);
+  const Dense D{op, s, false, &W};
   return batched(nrhs, W.R, nin, nout, static_cast<const double2*>(xv), static_cast<double2*>(yv),
                  [&](const double2* x, double2* y, int nr) -> rfcmp_status {
                    switch (which) {
                      case RFCMP_PROJ_SIGMA:
                      case RFCMP_PROJ_LH:
-                       RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-                       RF_TRY(dsymv(d.Lp.as<double>(), C, d.ldL, W.c[0], W.c[1], nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_lp"));
+                       RF_TRY(D.prod(kLP, false, D.sigma_t(x), W.c[1], nr));
                        return which == RFCMP_PROJ_SIGMA
                                   ? axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[1], y, nr, s)
                                   : axpy_sigma(d, N, C, 1.0, false, x, -1.0, W.c[1], y, nr, s);
                      case RFCMP_PROJ_GSIGMA:
-                       RF_TRY(sigma_t(d, C, N, x, W.c[0], nr, s));
-                       RF_TRY(dsymv(d.Gtp_inv.as<double>(), C, d.ldT, W.c[0], W.c[2], nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_gtp"));
-                       RF_TRY(dsymv(d.Lp.as<double>(), C, d.ldL, W.c[2], W.c[1], nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_lp"));
+                       RF_TRY(D.prod(kGTP, false, D.sigma_t(x), W.c[2], nr));
+                       RF_TRY(D.prod(kLP, false, W.c[2], W.c[1], nr));
                        return axpy_sigma(d, N, C, 0.0, false, nullptr, 1.0, W.c[1], y, nr, s);
                      case RFCMP_PROJ_LPINV:
-                       return dsymv(d.Lp.as<double>(), C, d.ldL, x, y, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_lp");
+                       return D.prod(kLP, false, x, y, nr);
                      case RFCMP_PROJ_GLL_INV:
-                       return dsymv(d.Gll_inv.as<double>(), V, d.ldG, x, y, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, "dmatvec_gll");
+                       return D.prod(kGLL, false, x, y, nr);
                      case RFCMP_PROJ_SIGMA_T:
                        return sigma_t(d, C, N, x, y, nr, s);
                      default:
@@ -1233,9 +1334,22 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
   switch (which) {
     case 2: return D.prod(kTA, conj != 0, xx, yy, nrhs);
     case 3: return D.prod(kV, conj != 0, xx, yy, nrhs);
-    case 4: return D.prod(kLP, false, xx, yy, nrhs);
-    default: return D.prod(kGLL, false, xx, yy, nrhs);
+    default: break;
   }
+  // BF16x3 products of the dense inverses: built for this mesh on first use
+  // when the operator applies the sparse factors
+  rfcmp_mesh m = op->mesh;
+  RF_TRY(ensure_mesh_device(m, false, true, s));
+  RF_TRY(wait_projectors(m, s));
+  MeshDev& d = m->d;
+  if (!d.Lp16) {
+    d.Lp16 = std::make_unique<SplitMatrix>();
+    RF_TRY(d.Lp16->from_f64(d.Lp.as<double>(), m->h.C, d.ldL, s));
+    d.Gll16 = std::make_unique<SplitMatrix>();
+    RF_TRY(d.Gll16->from_f64(d.Gll_inv.as<double>(), m->h.V, d.ldG, s));
+  }
+  return gemm_bf16x3(which == 4 ? *d.Lp16 : *d.Gll16, false, xx, yy, nrhs, op->gemm_scratch.p,
+                     op->gemm_scratch.bytes, s, which == 4 ? "gemm_lp" : "gemm_gll");
 }
 
 static rfcmp_status solve_common(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,

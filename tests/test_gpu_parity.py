@@ -56,11 +56,13 @@ def _gpu_mesh(name):
 
 
 @functools.lru_cache(maxsize=None)
-def _gpu_op(name, k, star=0, scaling=1):
+def _gpu_op(name, k, star=0, scaling=1, projector=0):
+    """projector 0: sparse FP64 factors of L, G_ll, G_tp (default);
+    1: dense FP64 inverses."""
     torch, rf = _gpu()
     m = _gpu_mesh(name)
     start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
-    return rf.Operator(m, k, power_start=start, outer_star=star, scaling=scaling)
+    return rf.Operator(m, k, power_start=start, outer_star=star, scaling=scaling, projector=projector)
 
 
 def _np(t):
@@ -102,10 +104,13 @@ def test_rhs_match_oracle(name, k):
 
 
 @pytest.mark.parametrize("name", ["ico2", "torus_small", "cube3"])
-def test_projectors_match_oracle(name):
+@pytest.mark.parametrize("projector", [0, 1])
+def test_projectors_match_oracle(name, projector):
+    """Projectors through the sparse FP64 factors (0) and the dense FP64
+    inverses (1) against the oracle's dense pseudo-inverse and inverses."""
     import paper_1803_08333_amd as rf
     top, TA, V = _oracle(name, 0.5)
-    op = _gpu_op(name, 0.5)
+    op = _gpu_op(name, 0.5, projector=projector)
     pre = rfcmp.Preconditioner(top, TA, V, 0.5)
     x = np.stack([synth.complex_start(top.N, 1), synth.complex_start(top.N, 2)])
     xc = np.stack([synth.complex_start(top.C, 3)])
@@ -138,10 +143,10 @@ def test_matvec_exact_on_stored_blocks(name, k):
         assert rel(_np(op.matvec(1, _cuda(y), conj)), (M @ y.T).T) < 1e-13
 
 
-def _oracle_on_gpu_blocks(name, k, star):
+def _oracle_on_gpu_blocks(name, k, star, projector=0):
     """Oracle preconditioner built on the GPU's own (exported) blocks."""
     top, _, _ = _oracle(name, k)
-    op = _gpu_op(name, k, star)
+    op = _gpu_op(name, k, star, projector=projector)
     gTA, gV = (_np(t).astype(np.complex128) for t in op.export())
     pre = rfcmp.Preconditioner(top, gTA, gV, k, outer_star="gsigma" if star else "sigma")
     a, b, g, _ = op.scalings()
@@ -151,8 +156,9 @@ def _oracle_on_gpu_blocks(name, k, star):
 
 @pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 1e-4), ("torus_small", 0.5), ("cube3", 2.0)])
 @pytest.mark.parametrize("star", [0, 1])
-def test_operator_steps_exact_on_stored_blocks(name, k, star):
-    op, pre = _oracle_on_gpu_blocks(name, k, star)
+@pytest.mark.parametrize("projector", [0, 1])
+def test_operator_steps_exact_on_stored_blocks(name, k, star, projector):
+    op, pre = _oracle_on_gpu_blocks(name, k, star, projector)
     N = pre.top.N
     x = np.stack([synth.complex_start(N, 21 + r) for r in range(6)])
     assert rel(_np(op.apply(_cuda(x))), pre.apply(x.T).T) < 1e-11
@@ -186,12 +192,12 @@ def test_power_scalings_match_oracle(name, k):
 
 @pytest.mark.parametrize("name,k", [("ico2", 1.0), ("ico2", 0.1), ("ico2", 1e-4), ("torus_small", 0.5),
                                     ("cube3", 2.0), ("ellipsoid1", 0.05)])
-@pytest.mark.parametrize("star,scaling", [(0, 0), (1, 1)])
-def test_solution_matches_oracle(name, k, star, scaling):
+@pytest.mark.parametrize("star,scaling,projector", [(0, 0, 0), (1, 1, 0), (0, 0, 1)])
+def test_solution_matches_oracle(name, k, star, scaling, projector):
     """j from the GPU solve vs the oracle's dense solution on its own FP64
     blocks (the plain Galerkin solution j = -T^-1 e, reached by RF-CMP)."""
     top, TA, V = _oracle(name, k)
-    op = _gpu_op(name, k, star, scaling)
+    op = _gpu_op(name, k, star, scaling, projector)
     kh, pol = synth.default_plane_wave()
     e = rhs.planewave(top, k, kh, pol)
     pre = rfcmp.Preconditioner(top, TA, V, k)
@@ -427,7 +433,8 @@ def test_full_size_solution_properties(name, k, nrhs, precision):
 
 
 @pytest.mark.parametrize("nmajor,nminor", [(112, 64), (160, 64)])
-def test_projector_inverses_large(nmajor, nminor):
+@pytest.mark.parametrize("projector", [0, 1])
+def test_projector_inverses_large(nmajor, nminor, projector):
     """The blocked inverse at sizes beyond the parity meshes (C = 14336 and
     20480 cells, 224 and 320 pivot blocks), by identities that hold at any
     size: L L^+ x = x - mean(x) with L = Sigma^T Sigma, and G_ll G_ll^-1 y = y
@@ -438,7 +445,7 @@ def test_projector_inverses_large(nmajor, nminor):
     xyz, tri = synth.torus(nmajor, nminor)
     top = Topology(xyz, tri)
     m = rf.Mesh(xyz, tri)
-    op = rf.Operator(m, 1.0, scaling=1)
+    op = rf.Operator(m, 1.0, scaling=1, projector=projector)
     rng = np.random.default_rng(5)
     x = rng.standard_normal((2, top.C)) + 1j * rng.standard_normal((2, top.C))
     lx = _np(op.project(rf.PROJ_LPINV, _cuda(x)))

@@ -397,3 +397,18 @@ def test_power_iteration_early_stop(name, k):
     assert all(abs(x - y) < 3e-2 * y for x, y in zip((a, b, g), ref))
     A = pre.system_split()
     assert rfcmp.cg(lambda x: A @ x, pre.rhs(e), 1e-6, 1000)[1] == it_ref
+
+
+def test_efie_condition_grows_as_kh_minus_two():
+    """Introduction: cond(T) of the plain EFIE grows as (k h)^-2: a tenfold
+    smaller k multiplies it by about 100 (low-frequency breakdown), and halving
+    h (icosphere level 1 -> 2) by about 4 (dense-discretisation breakdown),
+    while cond(A) of the RF-CMP system stays put (test_condition_flat_in_k_and_h)."""
+    c = {}
+    for name in ("ico1", "ico2"):
+        for k in (1e-2, 1e-3):
+            TA, V = blocks(name, k)
+            c[name, k] = rfcmp.efie_condition(topo(name), TA, V, k)
+    for name in ("ico1", "ico2"):
+        assert 80 < c[name, 1e-3] / c[name, 1e-2] < 120
+    assert 2.5 < c["ico2", 1e-3] / c["ico1", 1e-3] < 6.0
