@@ -113,6 +113,15 @@ rfcmp_status rfcmp_mesh_edges(rfcmp_mesh m, int32_t* edge_vtx, int32_t* edge_cel
  * Writes *count; if pairs != NULL it must hold 2*count int32 (first call
  * with NULL to size it). */
 rfcmp_status rfcmp_mesh_near_pairs(rfcmp_mesh m, double near_factor, int64_t* count, int32_t* pairs);
+/* The sparse projector factors of a mesh (options.projector = 0), once an
+ * operator has needed them: which 0 = L = Sigma^T Sigma (grounded), 1 = G_ll,
+ * 2 = G_tp.  n: matrix size; supernodes and levels of the nested-dissection
+ * tree; stored: doubles on the device (the blocks of L and the inverses of
+ * its diagonal blocks, each in two orders); seconds: host time of ordering
+ * and factorisation.  Every output nullable.  RFCMP_E_STATE if that factor
+ * has not been built. */
+rfcmp_status rfcmp_mesh_factor_info(rfcmp_mesh m, int32_t which, int64_t* n, int32_t* supernodes, int32_t* levels,
+                                    int64_t* stored, double* seconds);
 void rfcmp_mesh_destroy(rfcmp_mesh m);
 
 /* -------------------------------------------------------------- options */
@@ -133,13 +142,17 @@ typedef struct {
                              power_iters steps */
   int32_t streams;        /* power iterations rfcmp_op_create_many runs at once,
                              1..4, default 4 (1 = one after another on `stream`) */
-  int32_t projector;      /* how L^+, G_ll^-1 and G_tp^-1 are applied (Sec. 2-3 projectors):
-                             0 = sparse FP64 Cholesky factors (default): nested
-                                 dissection of the mesh, factored on host threads
-                                 from rfcmp_mesh_create on, O(n log n) entries,
-                                 solved on the device in FP64 in every precision;
-                             1 = dense FP64 inverses formed on the device
-                                 (O(n^3) set-up, 8 n^2 bytes each) */
+  int32_t projector;      /* how L^+, G_ll^-1 and G_tp^-1 are applied (projectors of Sec. 2-3):
+                             1 = sparse FP64 Cholesky factors: nested dissection of
+                                 the mesh, factored on host threads from
+                                 rfcmp_mesh_create on, O(n log n) entries, solved on
+                                 the device in FP64 in every precision;
+                             2 = dense FP64 inverses formed on the device (O(n^3)
+                                 set-up, 8 n^2 bytes each, streamed per product);
+                             0 = automatic (default): 1 when precision = 1 (many
+                                 right-hand sides; FP64 projectors inside the BF16x3
+                                 solve) or C > 12288 (where the cubic set-up of 2
+                                 dominates), else 2 */
 } rfcmp_options;
 rfcmp_status rfcmp_options_default(rfcmp_options* opt);
 

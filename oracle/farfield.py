@@ -31,7 +31,7 @@ from scipy.special import spherical_jn, spherical_yn
 from .mie import _nmax, _pi_tau
 from .quadrature import tri7_points
 
-__all__ = ["far_field", "rcs", "mie_rcs"]
+__all__ = ["far_field", "far_field_split", "rcs", "mie_rcs", "rayleigh_rcs"]
 
 
 def far_field(top, k, j, dirs):
@@ -50,6 +50,46 @@ def far_field(top, k, j, dirs):
             Jq += coef[:, None, None] * arm
         out[r] = np.einsum("q,cqk,cqd->dk", w, Jq, phase)
     return out
+
+
+def far_field_split(top, k, j_loop, j_star, dirs):
+    """F of j = j_loop + j_star with the parts kept apart: a divergence-free
+    (loop) current carries no net current, int j_loop dS = 0 (j = div(j x_i)
+    componentwise on the closed surface), so its far field is
+    int j_loop (exp(-i k r_hat . r') - 1) dS', whose phase factor is formed as
+    -2 sin^2(t/2) - i sin t without cancellation; the star part uses the plain
+    phase.  At very low k both terms are O(k) while j_star is O(k) relative
+    to j_loop, so neither may go through a sum of the two currents."""
+    jl = np.atleast_2d(np.asarray(j_loop, dtype=np.complex128))
+    js = np.atleast_2d(np.asarray(j_star, dtype=np.complex128))
+    dirs = np.atleast_2d(np.asarray(dirs, dtype=np.float64))
+    pts, w = tri7_points(top.xyz, top.tri)
+    t = k * np.einsum("cqk,dk->cqd", pts, dirs)
+    ph_m1 = -2.0 * np.sin(0.5 * t) ** 2 - 1j * np.sin(t)       # exp(-i t) - 1
+    ph = np.exp(-1j * t)
+    out = np.zeros((len(jl), len(dirs), 3), dtype=np.complex128)
+    for r in range(len(jl)):
+        for jj, phase in ((jl[r], ph_m1), (js[r], ph)):
+            Jq = np.zeros(pts.shape, dtype=np.complex128)
+            for i in range(3):
+                coef = jj[top.cell_edges[:, i]] * top.cell_sign[:, i] / 2.0
+                arm = pts - top.xyz[top.tri[:, i]][:, None, :]
+                Jq += coef[:, None, None] * arm
+            out[r] += np.einsum("q,cqk,cqd->dk", w, Jq, phase)
+    return out
+
+
+def rayleigh_rcs(k, a, dirs):
+    """Low-frequency limit of the bistatic RCS of a PEC sphere of radius a
+    for E^i = x exp(i k z): the field of the induced electric dipole
+    (4 pi a^3 E^i) and magnetic dipole (-2 pi a^3 H^i),
+    sigma = 4 pi a^2 (ka)^4 ((cos th - 1/2)^2 cos^2 ph + (1 - cos(th)/2)^2 sin^2 ph),
+    with a relative error O((ka)^2); backscatter 9 pi a^2 (ka)^4."""
+    dirs = np.atleast_2d(np.asarray(dirs, dtype=np.float64))
+    ct = np.clip(dirs[:, 2], -1.0, 1.0)
+    phi = np.arctan2(dirs[:, 1], dirs[:, 0])
+    x = k * a
+    return 4.0 * np.pi * a * a * x ** 4 * ((ct - 0.5) ** 2 * np.cos(phi) ** 2 + (1.0 - 0.5 * ct) ** 2 * np.sin(phi) ** 2)
 
 
 def rcs(k, F, dirs):

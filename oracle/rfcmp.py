@@ -180,6 +180,25 @@ class Preconditioner:
         """j = P_o i (eq. NewFormulation)."""
         return self.P_LH @ i / self.alpha + 1j * (self.P_s @ i) / self.beta
 
+    def rhs_split(self, s, e1):
+        """b = -P_o^H T^H P_m e for e = Sigma s + e1 (rhs.planewave_split),
+        without forming e: the static part Sigma s lies in the range of
+        Sigma, where P_mL vanishes (Lam^T Sig = 0, P_LH Sig = 0) and
+        P_mS Sigma s = Sig L^+ G_pp^-1 (s - mean s)/beta^2 (L^+ L = I - 1 1^T/C).
+        So the O(1) static part never meets the O(k) loop part of e1."""
+        al, be, ga = self.alpha, self.beta, self.gamma
+        Sig = self.top.Sigma
+        sm = np.asarray(s) - np.mean(s, axis=0)              # s [C] or [C, m]
+        wL = self.ML_hat @ e1 / al ** 2 + self.P_LH @ e1 / ga
+        wS = (self.MS_hat @ e1 + Sig @ (self.Lp @ (self.Gpp_inv @ sm))) / be ** 2
+        return -self._left(wL, wS)
+
+    def recover_split(self, i):
+        """(j_loop, j_star) = (P_LH i/alpha, i P_s i/beta): the two parts of
+        j = P_o i kept apart (at very low k the star part is O(k) relative to
+        the loop part and would be lost in their sum)."""
+        return self.P_LH @ i / self.alpha, 1j * (self.P_s @ i) / self.beta
+
 
 POWER_CHECK = 5  # steps between convergence checks of the power iteration
 

@@ -12,7 +12,7 @@ import numpy as np
 
 from .quadrature import tri7_points
 
-__all__ = ["planewave", "voltage_gap"]
+__all__ = ["planewave", "planewave_split", "voltage_gap"]
 
 
 def planewave(top, k, khat, pol):
@@ -29,6 +29,36 @@ def planewave(top, k, khat, pol):
                 arm = pts[c] - top.xyz[top.tri[c, i]]          # [7,3]
                 e[l, m] += top.cell_sign[c, i] / 2.0 * np.sum(w * (arm @ pol[l]) * phase[c])
     return e
+
+
+def planewave_split(top, k, khat, pol):
+    """The plane-wave excitation as e = Sigma s + e1, without cancellation at
+    any k (the loop part of e is O(k) relative to e and is lost in a single
+    FP64 vector below k ~ 1e-16).
+
+    Split E^i = pol + pol (exp(i k khat . r) - 1).  The static term is the
+    gradient of pol . r, so int f_m . pol = -int div(f_m) (pol . r) = -sum_c
+    sigma_mc (pol . x_c), x_c the centroid: e_static = Sigma s with
+    s_c = -pol . x_c, in the range of Sigma exactly (divergence theorem on the
+    RWG function, whose normal component vanishes on the cell boundary except
+    across its edge, where it is continuous).  The rest, e1, is integrated with
+    the 7-point rule and exp(i t) - 1 = -2 sin^2(t/2) + i sin t.
+    Returns s [nrhs, C] and e1 [nrhs, N], complex128."""
+    khat = np.atleast_2d(np.asarray(khat, dtype=np.float64))
+    pol = np.atleast_2d(np.asarray(pol, dtype=np.float64))
+    pts, w = tri7_points(top.xyz, top.tri)
+    s = np.zeros((len(khat), top.C), dtype=np.complex128)
+    e1 = np.zeros((len(khat), top.N), dtype=np.complex128)
+    for l in range(len(khat)):
+        s[l] = -(top.centroid @ pol[l])
+        t = k * (pts @ khat[l])                                # [C,7]
+        em1 = -2.0 * np.sin(0.5 * t) ** 2 + 1j * np.sin(t)     # exp(i t) - 1
+        for c in range(top.C):
+            for i in range(3):
+                m = top.cell_edges[c, i]
+                arm = pts[c] - top.xyz[top.tri[c, i]]
+                e1[l, m] += top.cell_sign[c, i] / 2.0 * np.sum(w * (arm @ pol[l]) * em1[c])
+    return s, e1
 
 
 def voltage_gap(top, edges, volts):

@@ -32,12 +32,14 @@ __all__ = [
     "LIB_PATH", "RfcmpError", "Options", "Info", "Mesh", "Operator", "lib",
     "PROJ_SIGMA", "PROJ_LH", "PROJ_GSIGMA", "PROJ_LPINV", "PROJ_GLL_INV", "PROJ_SIGMA_T", "PROJ_LAMBDA_T",
     "EXPORTED", "batch_solve", "set_allocator", "use_torch_allocator", "RHS_NOALLOC_MAX",
+    "PROJECTOR_AUTO", "PROJECTOR_SPARSE", "PROJECTOR_DENSE",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfcmp.so")
 
 PROJ_SIGMA, PROJ_LH, PROJ_GSIGMA, PROJ_LPINV, PROJ_GLL_INV, PROJ_SIGMA_T, PROJ_LAMBDA_T = range(7)
 RHS_NOALLOC_MAX = 4096   # RFCMP_RHS_NOALLOC_MAX
+PROJECTOR_AUTO, PROJECTOR_SPARSE, PROJECTOR_DENSE = 0, 1, 2   # rfcmp_options.projector
 
 _STATUS = {
     0: "OK", 1: "W_NOT_CONVERGED", -1: "E_ARG", -2: "E_MESH_OPEN", -3: "E_MESH_NONMANIFOLD",
@@ -88,6 +90,7 @@ EXPORTED = {
     "rfcmp_mesh_sizes": (_I32, [_P, _PI64, _PI64, _PI64, _PI32]),
     "rfcmp_mesh_edges": (_I32, [_P, _PI32, _PI32, _PI32]),
     "rfcmp_mesh_near_pairs": (_I32, [_P, _D, _PI64, _PI32]),
+    "rfcmp_mesh_factor_info": (_I32, [_P, _I32, _PI64, _PI32, _PI32, _PI64, _PD]),
     "rfcmp_mesh_destroy": (None, [_P]),
     "rfcmp_options_default": (_I32, [ctypes.POINTER(Options)]),
     "rfcmp_op_create": (_I32, [_P, _D, ctypes.POINTER(Options), _P, _P, ctypes.POINTER(_P)]),
@@ -300,6 +303,17 @@ class Mesh:
         _check(lib.rfcmp_rhs_gap(self.handle, edges.ctypes.data_as(_PI32), volts.ctypes.data_as(_P),
                                  edges.shape[1], edges.shape[0], _dptr(e), _stream()))
         return e
+
+    def factor_info(self, which):
+        """rfcmp_mesh_factor_info: dict of the sparse projector factor `which`
+        (0 = L, 1 = G_ll, 2 = G_tp)."""
+        n, st = _I64(), _I64()
+        sn, lv = _I32(), _I32()
+        sec = _D()
+        _check(lib.rfcmp_mesh_factor_info(self.handle, which, ctypes.byref(n), ctypes.byref(sn), ctypes.byref(lv),
+                                          ctypes.byref(st), ctypes.byref(sec)))
+        return {"n": n.value, "supernodes": sn.value, "levels": lv.value, "stored_doubles": st.value,
+                "host_seconds": sec.value}
 
     def close(self):
         if self.handle:

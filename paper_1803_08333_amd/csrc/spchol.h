@@ -74,33 +74,60 @@ struct SpFactor {
 // independent subtrees.  Returns RFCMP_E_ARG if a pivot is not positive.
 rfcmp_status spchol_factor(const SpMatrix& A, bool grounded, int leaf, int threads, SpFactor& F);
 
-// A factor on the device, in the layout the solve reads.  For supernode s:
-//   l21 [l21_off[s] ..]: its struct rows of L, nstr x ncol column-major;
-//   linv [linv_off[s] ..]: the inverse of its lower-triangular diagonal
-//     block, ncol x ncol column-major (zero above the diagonal), formed on
-//     the host in FP64, so that the diagonal solves are products;
-//   its update vector in the solve's scratch at str_off[s] (nstr entries).
-// Supernodes are listed by height (lvl_node[lvl_off[h] .. lvl_off[h+1])):
-// the forward solve runs the heights up, the backward solve down.
+// A factor on the device, in the layout the solve reads.  The solve runs the
+// dissection levels (supernodes grouped by height) as flat phases of
+// independent row tasks:
+//   forward, heights up:
+//     fronts: each supernode's front (its entries of the vector, plus its
+//       children's update vectors at their positions: a gather list per
+//       front entry, in child order);
+//     column tasks (one per column i of a supernode): y_i = (L_ss^-1 v)_i,
+//       with the inverse of the diagonal block formed on the host in FP64;
+//     struct tasks (one per struct row t): u_t = v_t - (L_21 y)_t;
+//   backward, heights down:
+//     column tasks: z_j = y_j - (L_21^T x_struct)_j;
+//     column tasks: x_i = (L_ss^-T z)_i.
+// Every matrix is stored twice, column-major and row-major, so that each
+// phase reads it with consecutive tasks at consecutive addresses.
 struct SpDevice {
   int n = 0, nsn = 0, nlev = 0, grounded = 0;
   int max_front = 0, max_ncol = 0;
-  int64_t nstr_total = 0;
-  int64_t nnz = 0;            // doubles in l21 and linv
+  int64_t nstr_total = 0, front_total = 0;
+  int64_t nnz = 0;            // doubles of the factor as stored (both copies)
   double seconds = 0.0;       // host factorisation time
-  DevBuf perm, iperm, col0, str_off, str, map, child_off, child_idx, lvl_off, lvl_node;
-  DevBuf l21_off, linv_off, l21, linv;
+  DevBuf perm, iperm, str;
+  DevBuf fr_lvl, fr_dest, fr_xsrc, fr_ptr, fr_src;    // front gathers, by level
+  DevBuf col_lvl, col_a, col_b, col_c;                 // column tasks, by level
+  DevBuf str_lvl, str_a, str_b, str_c;                 // struct tasks, by level
+  DevBuf lanes;                                        // int4 per level: lanes per task of the four phases
+  DevBuf l21, l21t, linv, linvt;
   // complex128 entries of solve scratch per right-hand side: the permuted
-  // vector (n) and the update vectors (nstr_total)
-  int64_t scratch_entries() const { return n + nstr_total; }
+  // vector x (n), z (n), update vectors (nstr_total), fronts (front_total)
+  int64_t scratch_entries() const { return 2 * n + nstr_total + front_total; }
 };
 
 // The device arrays of a factor, formed on the host.
 struct SpArrays {
   int nlev = 0, max_ncol = 0;
-  std::vector<int> iperm, lvl_off, lvl_node;
-  std::vector<long> l21_off, linv_off;
-  std::vector<double> l21, linv;
+  int64_t front_total = 0;
+  std::vector<int> iperm;
+  std::vector<int> fr_lvl, fr_dest, fr_xsrc, fr_ptr, fr_src;
+  std::vector<int> col_lvl, str_lvl;
+  // column task (one per column i of a supernode): a = {c0, ncol, i, front
+  // offset}, b = {offset of its inverse block, offset of its L_21 block},
+  // c = {struct offset so, nstr}
+  std::vector<int> col_a, col_c;
+  std::vector<long> col_b;
+  // struct task (one per struct row t of a supernode): a = {c0, ncol, t,
+  // front offset}, b = {offset of its L_21 block + t, update index so + t},
+  // c = {nstr, 0}
+  std::vector<int> str_a, str_c;
+  std::vector<long> str_b;
+  // per level, the lanes that share one task's sum in the phases y = L^-1 v,
+  // u = v - L_21 y, z = y - L_21^T x, x = L^-T z (a power of two up to 64,
+  // chosen so that the level's tasks fill about one pass of the workgroup)
+  std::vector<int> lanes;
+  std::vector<double> l21, l21t, linv, linvt;
 };
 void spchol_arrays(const SpFactor& F, SpArrays& out);
 
