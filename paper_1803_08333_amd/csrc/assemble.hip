@@ -406,9 +406,12 @@ __global__ __launch_bounds__(256) void k_gather_ta(int N, const int* __restrict_
 
 // ---------------------------------------------------------------- excitation
 // e[r][m] = sum over the two cells of m: sigma/2 sum_q w_q (x_q - r_m).pol exp(ik khat.x_q).
+// split = 1: e1 = e - Sigma s, the plane wave less its static part pol
+// (whose excitation Sigma s, s_c = -pol . x_c, lies in the range of Sigma):
+// exp(i t) - 1 = -2 sin^2(t/2) + i sin t keeps e1's O(k) loop part at any k.
 __global__ void k_rhs(int N, int nrhs, const int* __restrict__ edge_cell, const int* __restrict__ edge_slot,
                       const double* __restrict__ vtx, double kk, const double* __restrict__ khat,
-                      const double* __restrict__ pol, RuleArgs rule, double2* __restrict__ e) {
+                      const double* __restrict__ pol, RuleArgs rule, double2* __restrict__ e, int split = 0) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long)N * nrhs) return;
   const int r = int(t / N), m = int(t % N);
@@ -426,7 +429,12 @@ __global__ void k_rhs(int N, int nrhs, const int* __restrict__ edge_cell, const 
         x[d] = rule.bary[q][0] * P[d] + rule.bary[q][1] * P[3 + d] + rule.bary[q][2] * P[6 + d];
       const double proj = (x[0] - P[3 * l]) * po[0] + (x[1] - P[3 * l + 1]) * po[1] + (x[2] - P[3 * l + 2]) * po[2];
       double sn, cs;
-      sincos(kk * (kh[0] * x[0] + kh[1] * x[1] + kh[2] * x[2]), &sn, &cs);
+      const double ph = kk * (kh[0] * x[0] + kh[1] * x[1] + kh[2] * x[2]);
+      sincos(ph, &sn, &cs);
+      if (split) {
+        const double h = sin(0.5 * ph);
+        cs = -2.0 * h * h;
+      }
       accr += rule.wd[q] * proj * cs;
       acci += rule.wd[q] * proj * sn;
     }
@@ -434,6 +442,17 @@ __global__ void k_rhs(int N, int nrhs, const int* __restrict__ edge_cell, const 
     si += sg * acci;
   }
   e[t] = make_double2(sr, si);
+}
+
+// s[r][c] = -pol_r . x_c (x_c the centroid): the static part Sigma s of the
+// plane-wave excitation (int f_m . pol = -int div(f_m) pol . r).
+__global__ void k_rhs_static(int C, int nrhs, const double* __restrict__ cen, const double* __restrict__ pol,
+                             double2* __restrict__ sv) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)C * nrhs) return;
+  const int r = int(t / C), c = int(t % C);
+  const double v = pol[3 * r] * cen[3 * c] + pol[3 * r + 1] * cen[3 * c + 1] + pol[3 * r + 2] * cen[3 * c + 2];
+  sv[t] = make_double2(-v, 0.0);
 }
 
 // ---------------------------------------------------------------- far field
@@ -444,21 +463,26 @@ __global__ void k_rhs(int N, int nrhs, const int* __restrict__ edge_cell, const 
 // F)|^2 (unit incident amplitude).  One workgroup per (direction, right-hand
 // side): cells strided over the threads, then a fixed-order block sum (xor
 // butterflies in each wave, the four wave sums in order).
+// With js != nullptr, j is the loop (divergence-free) part of the current
+// and js its star part: a loop current carries no net current, so its phase
+// factor is taken as exp(-i t) - 1 = -2 sin^2(t/2) - i sin t, without
+// cancellation at any k; js takes the plain phase.
 __global__ __launch_bounds__(256) void k_farfield(int C, int N, int ndir, const int* __restrict__ cell_edge,
                                                   const float* __restrict__ sgn, const double* __restrict__ vtx,
                                                   double kk, const double* __restrict__ dirs, RuleArgs rule,
-                                                  const double2* __restrict__ j, double2* __restrict__ F,
-                                                  double* __restrict__ rcs) {
+                                                  const double2* __restrict__ j, const double2* __restrict__ js,
+                                                  double2* __restrict__ F, double* __restrict__ rcs) {
   __shared__ double red[4][6];
   const int d = blockIdx.x, r = blockIdx.y;
   const double dh[3] = {dirs[3 * d], dirs[3 * d + 1], dirs[3 * d + 2]};
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // (re, im) of x, y, z
   for (int c = threadIdx.x; c < C; c += 256) {
     const double* P = vtx + (long)c * 9;
-    double2 jc[3];
+    double2 jc[3], jsc[3];
     double sg[3];
     for (int i = 0; i < 3; ++i) {
       jc[i] = j[(long)r * N + cell_edge[3 * c + i]];
+      jsc[i] = js ? js[(long)r * N + cell_edge[3 * c + i]] : make_double2(0.0, 0.0);
       sg[i] = 0.5 * (double)sgn[3 * c + i];
     }
     for (int q = 0; q < kQ; ++q) {
@@ -466,17 +490,26 @@ __global__ __launch_bounds__(256) void k_farfield(int C, int N, int ndir, const 
       for (int k = 0; k < 3; ++k)
         x[k] = rule.bary[q][0] * P[k] + rule.bary[q][1] * P[3 + k] + rule.bary[q][2] * P[6 + k];
       double sn, cs;
-      sincos(kk * (dh[0] * x[0] + dh[1] * x[1] + dh[2] * x[2]), &sn, &cs);
+      const double ph = kk * (dh[0] * x[0] + dh[1] * x[1] + dh[2] * x[2]);
+      sincos(ph, &sn, &cs);
       const double wr = rule.wd[q] * cs, wi = -rule.wd[q] * sn;  // w_q exp(-i k dhat . x_q)
+      double lr = wr;                                            // the loop part's phase factor
+      if (js) {
+        const double h = sin(0.5 * ph);
+        lr = -2.0 * rule.wd[q] * h * h;
+      }
       for (int k = 0; k < 3; ++k) {
         double cr = 0.0, ci = 0.0;  // sum_i sigma_i / 2 j_m (x_q - v_i)_k
+        double dr = 0.0, di = 0.0;  // the same for the star part
         for (int i = 0; i < 3; ++i) {
           const double arm = sg[i] * (x[k] - P[3 * i + k]);
           cr += arm * jc[i].x;
           ci += arm * jc[i].y;
+          dr += arm * jsc[i].x;
+          di += arm * jsc[i].y;
         }
-        acc[2 * k] += cr * wr - ci * wi;
-        acc[2 * k + 1] += cr * wi + ci * wr;
+        acc[2 * k] += (cr * lr - ci * wi) + (dr * wr - di * wi);
+        acc[2 * k + 1] += (cr * wi + ci * lr) + (dr * wi + di * wr);
       }
     }
   }
@@ -658,24 +691,24 @@ __global__ void k_rhs_gap(long total, const long* __restrict__ idx, const double
 }
 }  // namespace
 
-rfcmp_status far_field(rfcmp_op op, const double2* j, int nrhs, const double* dirs, int ndir, double2* F,
-                       double* rcs, hipStream_t s) {
+rfcmp_status far_field(rfcmp_op op, const double2* j, const double2* js, int nrhs, const double* dirs, int ndir,
+                       double2* F, double* rcs, hipStream_t s) {
   rfcmp_mesh m = op->mesh;
   DevBuf dd;
   RF_TRY(dd.alloc(sizeof(double) * 3 * ndir));
   RF_HIP(hipMemcpyAsync(dd.p, dirs, sizeof(double) * 3 * ndir, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_farfield, dim3((unsigned)ndir, (unsigned)nrhs), dim3(256), 0, s, (int)m->h.C, (int)m->h.N,
                      ndir, m->d.cell_edge.as<int>(), m->d.sgn.as<float>(), m->d.vtx.as<double>(), op->k,
-                     dd.as<double>(), rule_args(), j, F, rcs);
+                     dd.as<double>(), rule_args(), j, js, F, rcs);
   RF_HIP(hipGetLastError());
   RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;
 }
 
 rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, int nrhs, double2* e,
-                           hipStream_t s) {
+                           hipStream_t s, double2* sv) {
   rfcmp_mesh m = op->mesh;
-  const int64_t N = m->h.N;
+  const int64_t N = m->h.N, C = m->h.C;
   DevBuf dk;
   RF_TRY(dk.alloc(sizeof(double) * 6 * nrhs));
   RF_HIP(hipMemcpyAsync(dk.p, khat, sizeof(double) * 3 * nrhs, hipMemcpyHostToDevice, s));
@@ -683,8 +716,14 @@ rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, i
   const long total = (long)N * nrhs;
   hipLaunchKernelGGL(k_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (int)N, nrhs,
                      m->d.edge_cell.as<int>(), m->d.edge_slot.as<int>(), m->d.vtx.as<double>(), op->k, dk.as<double>(),
-                     dk.as<double>() + 3 * nrhs, rule_args(), e);
+                     dk.as<double>() + 3 * nrhs, rule_args(), e, sv ? 1 : 0);
   RF_HIP(hipGetLastError());
+  if (sv) {
+    const long tc = (long)C * nrhs;
+    hipLaunchKernelGGL(k_rhs_static, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, s, (int)C, nrhs,
+                       m->d.cen.as<double>(), dk.as<double>() + 3 * nrhs, sv);
+    RF_HIP(hipGetLastError());
+  }
   RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;
 }

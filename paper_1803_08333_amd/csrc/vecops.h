@@ -21,6 +21,9 @@ rfcmp_status comb_mean(int64_t C, const double* area, double fa, const double2* 
 // y = -i ka (zA - Sigma s4) + Sigma g6
 rfcmp_status left_y(const MeshDev& d, int64_t N, int64_t C, double ka, const double2* zA, const double2* s4,
                     const double2* g6, double2* y, int nr, hipStream_t s);
+// jl = ia (x - Sigma sv), js = i ib Sigma sg (the two parts of recover_j)
+rfcmp_status recover_j_split(const MeshDev& d, int64_t N, int64_t C, double ia, double ib, const double2* x,
+                             const double2* sv, const double2* sg, double2* jl, double2* js, int nr, hipStream_t s);
 // j = ia (x - Sigma sv) + i ib Sigma sg
 rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double ib, const double2* x,
                        const double2* sv, const double2* sg, double2* j, int nr, hipStream_t s);

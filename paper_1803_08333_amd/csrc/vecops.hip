@@ -197,6 +197,21 @@ __global__ void k_recover(int N, int C, const int* __restrict__ edge_cell, doubl
   j[r * N + n] = cadd(cscale(ia, csub(x[r * N + n], ps)), cimul(ib, pg));
 }
 
+// the two parts of k_recover apart: jl = ia (x - Sigma s), js = i ib Sigma sg
+__global__ void k_recover_split(int N, int C, const int* __restrict__ edge_cell, double ia, double ib,
+                                const double2* __restrict__ x, const double2* __restrict__ s,
+                                const double2* __restrict__ sg, double2* __restrict__ jl,
+                                double2* __restrict__ js) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const long r = blockIdx.y;
+  const int cp = edge_cell[2 * n], cm = edge_cell[2 * n + 1];
+  const double2 ps = csub(s[r * C + cp], s[r * C + cm]);
+  const double2 pg = csub(sg[r * C + cp], sg[r * C + cm]);
+  jl[r * N + n] = cscale(ia, csub(x[r * N + n], ps));
+  js[r * N + n] = cimul(ib, pg);
+}
+
 // out = Lambda h (n from the vertex differences)
 __global__ void k_lambda(int N, int V, const int* __restrict__ edge_vtx, const double2* __restrict__ h,
                          double2* __restrict__ out) {
@@ -473,6 +488,13 @@ rfcmp_status recover_j(const MeshDev& d, int64_t N, int64_t C, double ia, double
                        const double2* sv, const double2* sg, double2* j, int nr, hipStream_t s) {
   hipLaunchKernelGGL(k_recover, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, d.edge_cell.as<int>(), ia, ib, x,
                      sv, sg, j);
+  RF_LAUNCH_CHECK();
+  return RFCMP_OK;
+}
+rfcmp_status recover_j_split(const MeshDev& d, int64_t N, int64_t C, double ia, double ib, const double2* x,
+                             const double2* sv, const double2* sg, double2* jl, double2* js, int nr, hipStream_t s) {
+  hipLaunchKernelGGL(k_recover_split, g1(N, nr), dim3(256), 0, s, (int)N, (int)C, d.edge_cell.as<int>(), ia, ib, x,
+                     sv, sg, jl, js);
   RF_LAUNCH_CHECK();
   return RFCMP_OK;
 }
