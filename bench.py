@@ -264,13 +264,16 @@ def precision_study(rf, torch, nb):
 
 def spectral_study(rf):
     """cond(A) of the RF-CMP system against ka (1 down to the 1e-25 Hz of the
-    paper's sphere study) on icosphere levels 2-4 and the 96 x 48 torus: the
+    paper's sphere study) on icosphere levels 2-4 and the jittered torus at
+    48 x 24, 96 x 48 and 144 x 72 (N = 3456 to 31104): the
     CG-Lanczos estimate of a solve of A i = b with a seeded generic b (the
     library's rfcmp_solve_system), power-iteration scalings."""
     from paper_1803_08333_amd import study
     ks = [1.0, 1e-2, 1e-4, 1e-12, study.K_1E_25_HZ]
     meshes = {f"icosphere{L}": synth.icosphere(L) for L in (2, 3, 4)}
-    meshes["torus96x48"] = synth.torus()
+    # the genus-1 body refined twice (Fig. CubeTorus's 1/h axis)
+    for nmaj, nmin in ((48, 24), (96, 48), (144, 72)):
+        meshes[f"torus{nmaj}x{nmin}"] = synth.torus(nmaj, nmin)
     rows = study.condition_study(meshes, ks, seed=7)
     out = {}
     for r in rows:
@@ -487,9 +490,11 @@ def kernel_model(tag, avg_ms, sz, nrhs):
 
 
 ALL_TAGS_BASE = ["cmatvec_ta", "cmatvec_v", "dmatvec_lp", "dmatvec_gll", "cmatvec_ta+v", "dmatvec_lp+gll"]
+SP_TAGS_BASE = ["spsolve_lp", "spsolve_gll", "spsolve_gtp", "spsolve_lp+gll", "spsolve_lp+gtp"]
 ALL_TAGS = (["far_pairs", "near_pairs", "gather_ta"] + ALL_TAGS_BASE +
             [f"{t}_nr{r}" for t in ALL_TAGS_BASE for r in (2, 3, 4)] +
-            ["symv_reduce", "spd_inverse", "gemm_ta", "gemm_v", "gemm_lp", "gemm_gll", "gemm_gtp"])
+            ["symv_reduce", "spd_inverse", "gemm_ta", "gemm_v", "gemm_lp", "gemm_gll", "gemm_gtp"] +
+            SP_TAGS_BASE + [f"{t}_nr{r}" for t in SP_TAGS_BASE for r in list(range(2, 9)) + [16, 32, 64]])
 
 
 def run_workload(rf, torch, wl, steps, warmup, label):
@@ -695,9 +700,6 @@ def main():
                              "roofline": sweep["roofline"]},
     }
     print("# headline and level-4 workloads done", file=sys.stderr, flush=True)
-    if not args.no_oracle_case:
-        res["oracle_case"] = oracle_case(rf, torch)
-        print("# oracle case done", file=sys.stderr, flush=True)
     if not args.no_precision_study:
         res["bf16x3_vs_fp32"] = precision_study(rf, torch, args.batch_rhs)
         print("# precision study done", file=sys.stderr, flush=True)
@@ -712,7 +714,11 @@ def main():
     if args.uneven_batch_serial:
         res["uneven_batch_serial"] = uneven_batch(rf, torch, concurrent=False)
     if not args.no_cpu_baseline:
+        # the CPU leg: the oracle timed on the host, and the GPU results of a
+        # case it solves in full checked against it
         res["cpu_baseline"] = cpu_baseline(args.cpu_slab, head)
+        if not args.no_oracle_case:
+            res["cpu_baseline"]["oracle_case"] = oracle_case(rf, torch)
     print(json.dumps(res))
 
 

@@ -153,6 +153,13 @@ typedef struct {
                                  right-hand sides; FP64 projectors inside the BF16x3
                                  solve) or C > 12288 (where the cubic set-up of 2
                                  dominates), else 2 */
+  int32_t graphs;         /* 1 (default): from its third iteration on, each CG
+                             iteration is replayed as a HIP graph captured once
+                             per operator (two graphs: the recurrence scalars
+                             alternate between two buffers) on an internal
+                             stream; 0: every kernel launched one by one.
+                             Results are bit-identical either way.  Not used
+                             while kernel timing (rfcmp_profile_enable) is on. */
 } rfcmp_options;
 rfcmp_status rfcmp_options_default(rfcmp_options* opt);
 
@@ -222,6 +229,18 @@ rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* 
 rfcmp_status rfcmp_rhs_planewave_noalloc(rfcmp_op op, const double* khat, const double* pol,
                                          int32_t nrhs, void* e, void* stream);
 
+/* The plane-wave excitation split for any frequency down to the static
+ * limit: e = Sigma s + e1 (Sec. 2), with s_c = -pol . x_c (x_c the cell
+ * centroid; int f_m . pol = -int div(f_m) pol . r, so Sigma s is the static
+ * part, in the range of Sigma exactly) and e1 = int f_m . pol (exp(i k khat .
+ * r) - 1) with exp(i t) - 1 = -2 sin^2(t/2) + i sin t.  At low frequency the
+ * loop part of e is O(k) relative to e, and below k ~ 1e-16 it is lost in a
+ * single FP64 vector; e1 keeps it (Fig. Sphere_RCS reaches 1e-25 Hz).
+ * s: device c128 [nrhs][C]; e1: device c128 [nrhs][N]; khat, pol as
+ * rfcmp_rhs_planewave.  Waits for the stream before returning. */
+rfcmp_status rfcmp_rhs_planewave_split(rfcmp_op op, const double* khat, const double* pol, int32_t nrhs,
+                                       void* s, void* e1, void* stream);
+
 /* Voltage-gap (delta-gap) excitation, the second source of the Fokker
  * example (Sec. 4): e_r[n] = sum of volts[r][g] over the gaps g with
  * edges[r][g] = n, zero elsewhere.  A gap of voltage V across edge m is the
@@ -251,6 +270,16 @@ rfcmp_status rfcmp_rhs_gap(rfcmp_mesh m, const int32_t* edges, const void* volts
  * nullable.  Waits for the stream before returning. */
 rfcmp_status rfcmp_farfield(rfcmp_op op, const void* j, int32_t nrhs, const double* dirs, int32_t ndir,
                             void* F, void* rcs, void* stream);
+/* rfcmp_farfield of a current given as its loop part (divergence-free) and
+ * its star part (rfcmp_solve_split): F = int j_loop (exp(-i k dhat . r) - 1)
+ * dS + int j_star exp(-i k dhat . r) dS.  A divergence-free current carries
+ * no net current, so the first term equals the loop part's far field, and its
+ * phase factor is formed as -2 sin^2(t/2) - i sin t, without cancellation:
+ * at very low k both terms are O(k) while j_star is O(k) relative to j_loop,
+ * and the RCS of the sphere keeps its accuracy down to 1e-25 Hz.  Arguments
+ * and outputs as rfcmp_farfield. */
+rfcmp_status rfcmp_farfield_split(rfcmp_op op, const void* j_loop, const void* j_star, int32_t nrhs,
+                                  const double* dirs, int32_t ndir, void* F, void* rcs, void* stream);
 
 /* b = -P_o^H T^H P_m e (right side of eq. NewFormulation).  e, b: device c128
  * [nrhs][N]; may not alias. */
@@ -314,6 +343,19 @@ typedef struct {
  * RFCMP_E_BREAKDOWN on a non-positive curvature. */
 rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol,
                          int32_t maxit, void* stream, rfcmp_info* info);
+
+/* rfcmp_solve for a split excitation e = Sigma s + e1 (rfcmp_rhs_planewave_
+ * split), returning j split as well: j_loop = P_LH i/alpha and j_star =
+ * i P_s i/beta (j = j_loop + j_star, eq. NewFormulation).  The right-hand
+ * side b is formed without ever adding the static part to e1 (P_mL vanishes
+ * on the range of Sigma, and P_mS Sigma s = Sigma L^+ G_pp^-1 (s - mean s)
+ * /beta^2), and the two parts of j are never added, so the solution keeps
+ * both Helmholtz parts at any frequency (at very low k the star part of j is
+ * O(k) relative to the loop part).  s: device c128 [nrhs][C]; e1, j_loop,
+ * j_star: device c128 [nrhs][N], not aliased.  Report and errors as
+ * rfcmp_solve. */
+rfcmp_status rfcmp_solve_split(rfcmp_op op, const void* s, const void* e1, void* j_loop, void* j_star,
+                               int32_t nrhs, double tol, int32_t maxit, void* stream, rfcmp_info* info);
 
 /* CG on the RF-CMP system A i = b itself (eq. NewFormulation), with b given
  * instead of formed from an excitation, and the iterate i returned instead of

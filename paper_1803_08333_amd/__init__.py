@@ -58,7 +58,7 @@ class Options(ctypes.Structure):
     _fields_ = [("near_factor", ctypes.c_double), ("outer_star", ctypes.c_int32),
                 ("scaling", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("power_tol", ctypes.c_double),
-                ("streams", ctypes.c_int32), ("projector", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("projector", ctypes.c_int32), ("graphs", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -102,6 +102,9 @@ EXPORTED = {
     "rfcmp_op_destroy": (None, [_P]),
     "rfcmp_rhs_planewave": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
     "rfcmp_rhs_planewave_noalloc": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
+    "rfcmp_rhs_planewave_split": (_I32, [_P, _PD, _PD, _I32, _P, _P, _P]),
+    "rfcmp_solve_split": (_I32, [_P, _P, _P, _P, _P, _I32, _D, _I32, _P, ctypes.POINTER(Info)]),
+    "rfcmp_farfield_split": (_I32, [_P, _P, _P, _I32, _PD, _I32, _P, _P, _P]),
     "rfcmp_rhs_gap": (_I32, [_P, _PI32, _P, _I32, _I32, _P, _P]),
     "rfcmp_farfield": (_I32, [_P, _P, _I32, _PD, _I32, _P, _P, _P]),
     "rfcmp_precond_rhs": (_I32, [_P, _P, _P, _I32, _P]),
@@ -393,6 +396,44 @@ class Operator:
         _check(lib.rfcmp_rhs_planewave(self.handle, khat.ctypes.data_as(_PD), pol.ctypes.data_as(_PD), len(khat),
                                        _dptr(e), _stream()))
         return e
+
+    def rhs_planewave_split(self, khat, pol):
+        """rfcmp_rhs_planewave_split: (s [nrhs, C], e1 [nrhs, N]) with
+        e = Sigma s + e1, complex128."""
+        torch = _torch()
+        khat = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        pol = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.float64)
+        s = torch.empty((len(khat), self.mesh.C), dtype=torch.complex128, device="cuda")
+        e1 = torch.empty((len(khat), self.mesh.N), dtype=torch.complex128, device="cuda")
+        _check(lib.rfcmp_rhs_planewave_split(self.handle, khat.ctypes.data_as(_PD), pol.ctypes.data_as(_PD),
+                                             len(khat), _dptr(s), _dptr(e1), _stream()))
+        return s, e1
+
+    def solve_split(self, s, e1, tol=1e-6, maxit=1000):
+        """rfcmp_solve_split: (j_loop, j_star, status, [info dict per rhs])."""
+        torch = _torch()
+        s, e1 = s.contiguous(), e1.contiguous()
+        nr = e1.shape[0] if e1.dim() == 2 else 1
+        jl, js = torch.empty_like(e1), torch.empty_like(e1)
+        info = (Info * nr)()
+        st = _check(lib.rfcmp_solve_split(self.handle, _dptr(s, torch.complex128, nr * self.mesh.C),
+                                          _dptr(e1, torch.complex128, nr * self.mesh.N), _dptr(jl), _dptr(js), nr,
+                                          tol, maxit, _stream(), info))
+        return jl, js, st, [i.as_dict() for i in info]
+
+    def far_field_split(self, j_loop, j_star, dirs):
+        """rfcmp_farfield_split: F [nrhs, ndir, 3] and RCS [nrhs, ndir] of the
+        current j_loop + j_star given as its two parts."""
+        torch = _torch()
+        jl, js = j_loop.contiguous(), j_star.contiguous()
+        nr = jl.shape[0] if jl.dim() == 2 else 1
+        dirs = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        F = torch.empty((nr, len(dirs), 3), dtype=torch.complex128, device=jl.device)
+        rcs = torch.empty((nr, len(dirs)), dtype=torch.float64, device=jl.device)
+        _check(lib.rfcmp_farfield_split(self.handle, _dptr(jl, torch.complex128, nr * self.mesh.N),
+                                        _dptr(js, torch.complex128, nr * self.mesh.N), nr, dirs.ctypes.data_as(_PD),
+                                        len(dirs), _dptr(F), _dptr(rcs), _stream()))
+        return F, rcs
 
     def rhs_planewave_noalloc(self, khat, pol, e):
         """rfcmp_rhs_planewave_noalloc into the caller's tensor e (complex128

@@ -364,4 +364,10 @@ MeshDev::~MeshDev() {
 rfcmp_op_s::rfcmp_op_s() = default;
 rfcmp_op_s::~rfcmp_op_s() {
   if (host_scal) (void)hipHostFree(host_scal);
+  for (int q = 0; q < 2; ++q)
+    if (cg_exec[q]) (void)hipGraphExecDestroy(cg_exec[q]);
+  if (cg_stream) {
+    (void)hipStreamSynchronize(cg_stream);
+    (void)hipStreamDestroy(cg_stream);
+  }
 }

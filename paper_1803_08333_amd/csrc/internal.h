@@ -228,6 +228,12 @@ struct rfcmp_op_s {
   std::unique_ptr<rfcmp::SplitMatrix> TA16, V16;  // BF16x3 planes (precision 1)
   rfcmp::DevBuf gemm_scratch;
   rfcmp::DevBuf symv_scratch;  // partial sums of the symmetric products
+  // CG iterations replayed as HIP graphs (one per parity of the iteration:
+  // the recurrence scalars alternate between two buffers), run on an
+  // internal stream; key: the kernel arguments they were captured with
+  hipStream_t cg_stream = nullptr;
+  hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
+  uint64_t cg_key[2] = {0, 0};
   rfcmp::DevBuf sp_scratch;    // sparse projector solves: one region per factor (L, G_ll, G_tp)
   int64_t sp_region[3] = {0, 0, 0};  // complex128 offsets of the regions
   int sp_scratch_nrhs = 0;
@@ -243,14 +249,17 @@ void build_cell_nb(MeshHost& h);
 // assemble.hip
 rfcmp_status mesh_upload(rfcmp_mesh m, hipStream_t s);
 rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s);
+// sv != nullptr: the split excitation e = Sigma sv + e (sv [nrhs][C], e the
+// plane wave less its static part)
 rfcmp_status rhs_planewave(rfcmp_op op, const double* khat, const double* pol, int nrhs,
-                           double2* e, hipStream_t s);
+                           double2* e, hipStream_t s, double2* sv = nullptr);
 rfcmp_status rhs_planewave_noalloc(rfcmp_op op, const double* khat, const double* pol, int nrhs, double2* e,
                                    hipStream_t s);
 rfcmp_status rhs_gap(rfcmp_mesh m, const int32_t* edges, const double2* volts, int ngap, int nrhs, double2* e,
                      hipStream_t s);
-rfcmp_status far_field(rfcmp_op op, const double2* j, int nrhs, const double* dirs, int ndir, double2* F,
-                       double* rcs, hipStream_t s);
+// js != nullptr: j is the loop part and js the star part of the current
+rfcmp_status far_field(rfcmp_op op, const double2* j, const double2* js, int nrhs, const double* dirs, int ndir,
+                       double2* F, double* rcs, hipStream_t s);
 
 // spsolve.hip: the sparse factors of a mesh (which 0 = L, grounded; 1 = G_ll;
 // 2 = G_tp, needs build_cell_nb first), and their upload: joins the host

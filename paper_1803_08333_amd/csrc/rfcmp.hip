@@ -396,7 +396,33 @@ rfcmp_status rhs_batch(const Dense& D, const Work& W, const double2* e, double2*
   return left_half(D, W, D.middle_w(W.v2, e, s2, s3, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be)), b, nr, -1.0);
 }
 
-rfcmp_status recover_batch(const Dense& D, const Work& W, const double2* x, double2* j, int nr) {
+// b = -P_o^H T^H P_m e for the split excitation e = Sigma sv + e1: the static
+// part lies in the range of Sigma, where P_mL vanishes and
+// P_mS Sigma sv = Sigma L^+ A (sv - mean sv)/beta^2 (L^+ L = I - 1 1^T/C), so
+// the O(1) static part never meets the O(k) loop part of e1:
+//   s2 = L^+ Sigma^T e1, h = G_ll^-1 Lambda^T e1,
+//   t4 = A (s2 + sv - mean sv), s3 = L^+ t4,
+//   w  = Lambda h/alpha^2 + (e1 - Sigma s2)/gamma + Sigma s3/beta^2.
+rfcmp_status rhs_batch_split(const Dense& D, const Work& W, const double2* sv, const double2* e1, double2* b,
+                             int nr) {
+  rfcmp_op op = D.op;
+  hipStream_t s = D.s;
+  const MeshHost& h = op->mesh->h;
+  const MeshDev& d = op->mesh->d;
+  const int64_t C = h.C;
+  const double al = op->alpha, be = op->beta, ga = op->gamma;
+  double2 *s2 = W.c[6], *t4 = W.c[7], *sw = W.c[8], *s3 = W.c[9];
+  RF_TRY(D.pair(kLP, D.sigma_t(e1), s2, kGLL, D.lambda_t(e1), W.v2, false, nr));
+  RF_TRY(comb_mean(C, d.area.as<double>(), 1.0, s2, 1.0, sv, t4, 1.0 / (be * be), sw, nr, s));
+  RF_TRY(D.prod(kLP, false, t4, s3, nr));
+  return left_half(D, W, D.middle_w(W.v2, e1, s2, s3, 1.0 / (al * al), 1.0 / ga, 1.0 / (be * be)), b, nr, -1.0);
+}
+
+// j = P_o x (recover_batch); with js != nullptr, j receives the loop part
+// P_LH x/alpha and js the star part i P_s x/beta.
+rfcmp_status recover_batch(const Dense& D, const Work& W, const double2* x, double2* j, int nr,
+                           double2* js = nullptr);
+rfcmp_status recover_batch(const Dense& D, const Work& W, const double2* x, double2* j, int nr, double2* js) {
   rfcmp_op op = D.op;
   hipStream_t s = D.s;
   const MeshHost& h = op->mesh->h;
@@ -411,6 +437,7 @@ rfcmp_status recover_batch(const Dense& D, const Work& W, const double2* x, doub
   } else {
     RF_TRY(D.prod(kLP, false, sx, W.c[1], nr));
   }
+  if (js) return recover_j_split(d, N, C, 1.0 / op->alpha, 1.0 / op->beta, x, W.c[1], sg, j, js, nr, s);
   return recover_j(d, N, C, 1.0 / op->alpha, 1.0 / op->beta, x, W.c[1], sg, j, nr, s);
 }
 
@@ -600,20 +627,87 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
       (void)hipEventDestroy(e[1]);
     }
   } guard{ev};
+  // The iterations run on the operator's internal stream when they are
+  // replayed as graphs (a stream that can be captured: the caller's may be the
+  // null stream), after the set-up above on s; s waits for them at the end.
+  const bool use_graphs = op->opt.graphs == 1 && !profiling_enabled();
+  hipStream_t cs = s;
+  if (use_graphs) {
+    if (!op->cg_stream) RF_HIP(hipStreamCreateWithFlags(&op->cg_stream, hipStreamNonBlocking));
+    cs = op->cg_stream;
+    RF_HIP(hipEventRecord(ev[0], s));
+    RF_HIP(hipStreamWaitEvent(cs, ev[0], 0));
+  }
+  Dense Dc = D;
+  Dc.s = cs;
+  // one iteration of parity c (the recurrence scalars at rho + c R, the host
+  // copies in slot c), without the event that publishes them
+  auto iteration = [&](int c) -> rfcmp_status {
+    RF_TRY(apply_batch(Dc, W, W.p, W.q, nr));
+    // the dot kernels also store the real parts for the host, straight into
+    // the mapped pinned buffer; the event recorded after the iteration
+    // publishes them
+    RF_TRY(dot(N, W.p, W.q, W.part, W.dout, nr, cs, W.pq, hs_dev + c * 4 * R + R));
+    RF_TRY(cg_xr_blk(N, nr, W.rho + c * R, W.pq, W.active, W.x, W.r, W.p, W.q, cs));
+    RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, cs, W.rho + (1 - c) * R, hs_dev + c * 4 * R));
+    return cg_p_blk(N, nr, W.rho + (1 - c) * R, W.rho + c * R, W.active, W.r, W.p, cs);
+  };
+  // every kernel argument of an iteration, apart from the parity
+  uint64_t key = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+  if (use_graphs) {
+    double sc[3] = {op->alpha, op->beta, op->gamma};
+    uint64_t bits[3];
+    std::memcpy(bits, sc, sizeof(bits));
+    for (uint64_t b : bits) mix(b);
+    mix((uint64_t)nr);
+    mix((uint64_t)D.bf16);
+    mix((uint64_t)(uintptr_t)op->work.p);
+    mix((uint64_t)op->work_nrhs);
+    mix((uint64_t)(uintptr_t)op->sp_scratch.p);
+    mix((uint64_t)(uintptr_t)op->symv_scratch.p);
+    mix((uint64_t)(uintptr_t)op->gemm_scratch.p);
+    mix((uint64_t)(uintptr_t)hs_dev);
+  }
+  auto graph_for = [&](int c) -> rfcmp_status {
+    if (op->cg_exec[c] && op->cg_key[c] == key) return RFCMP_OK;
+    if (op->cg_exec[c]) RF_HIP(hipGraphExecDestroy(op->cg_exec[c]));
+    op->cg_exec[c] = nullptr;
+    RF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const rfcmp_status st = iteration(c);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &g);
+    if (st < 0) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess || !g) {
+      set_error("capture of a CG iteration failed: %s", hipGetErrorString(ec));
+      return RFCMP_E_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&op->cg_exec[c], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      op->cg_exec[c] = nullptr;
+      set_error("instantiating a CG iteration graph failed: %s", hipGetErrorString(ei));
+      return RFCMP_E_HIP;
+    }
+    op->cg_key[c] = key;
+    return RFCMP_OK;
+  };
   int cur = 0, it = 0, last_checked = -1, nactive = nr;
   while (true) {
     bool issued = false;
     if (it < maxit && nactive > 0) {
       const int slot = it & 1;
-      RF_TRY(apply_batch(D, W, W.p, W.q, nr));
-      // the dot kernels also store the real parts for the host, straight into
-      // the mapped pinned buffer; the event below publishes them
-      RF_TRY(dot(N, W.p, W.q, W.part, W.dout, nr, s, W.pq, hs_dev + slot * 4 * R + R));
-      RF_TRY(cg_xr_blk(N, nr, W.rho + cur * R, W.pq, W.active, W.x, W.r, W.p, W.q, s));
+      if (use_graphs && it >= 2) {
+        RF_TRY(graph_for(cur));
+        RF_HIP(hipGraphLaunch(op->cg_exec[cur], cs));
+      } else {
+        RF_TRY(iteration(cur));
+      }
+      RF_HIP(hipEventRecord(ev[slot], cs));
       const int nxt = 1 - cur;
-      RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, s, W.rho + nxt * R, hs_dev + slot * 4 * R));
-      RF_HIP(hipEventRecord(ev[slot], s));
-      RF_TRY(cg_p_blk(N, nr, W.rho + nxt * R, W.rho + cur * R, W.active, W.r, W.p, s));
       cur = nxt;
       ++it;
       for (int r = 0; r < nr; ++r) iters[r] += act[r];
@@ -648,10 +742,14 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
       // freeze converged right-hand sides from the next enqueued iteration on
       int* ha = reinterpret_cast<int*>(hs + 6 * R);
       for (int r = 0; r < nr; ++r) ha[r] = act[r];
-      RF_HIP(hipMemcpyAsync(W.active, ha, sizeof(int) * nr, hipMemcpyHostToDevice, s));
-      RF_HIP(hipStreamSynchronize(s));  // ha is reused by the next change
+      RF_HIP(hipMemcpyAsync(W.active, ha, sizeof(int) * nr, hipMemcpyHostToDevice, cs));
+      RF_HIP(hipStreamSynchronize(cs));  // ha is reused by the next change
     }
     if (nactive == 0 || !issued) break;
+  }
+  if (cs != s) {
+    RF_HIP(hipEventRecord(ev[0], cs));
+    RF_HIP(hipStreamWaitEvent(s, ev[0], 0));
   }
   if (cond)
     for (int r = 0; r < nr; ++r) cond[r] = lanczos_cond(la[r], lb[r]);
@@ -667,8 +765,11 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
 //                |r| <= tol |b|.
 // system: e is the system's own right-hand side b and j receives the iterate
 // i (no excitation mapping, no recovery).
+// sv != nullptr: the excitation is split, e = Sigma sv + e (rhs_batch_split);
+// js != nullptr: j receives the loop part of the solution and js its star part.
 rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, double tol, int maxit, hipStream_t s,
-                         rfcmp_info* info, bool system = false) {
+                         rfcmp_info* info, bool system = false, const double2* sv = nullptr,
+                         double2* js = nullptr) {
   const int64_t N = op->mesh->h.N;
   const int64_t NR = (int64_t)nr * N;
   const Work W = carve(op);
@@ -677,6 +778,8 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
   const bool split = op->opt.precision == 1;
   if (system)
     RF_HIP(hipMemcpyAsync(W.b0, e, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
+  else if (sv)
+    RF_TRY(rhs_batch_split(D64, W, sv, e, W.b0, nr));
   else
     RF_TRY(rhs_batch(D64, W, e, W.b0, nr));
   RF_HIP(hipMemcpyAsync(W.b, W.b0, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
@@ -738,7 +841,7 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
   if (system)
     RF_HIP(hipMemcpyAsync(j, W.d, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
   else
-    RF_TRY(recover_batch(D64, W, W.d, j, nr));
+    RF_TRY(recover_batch(D64, W, W.d, j, nr, js));
   return st;
 }
 
@@ -1068,6 +1171,7 @@ rfcmp_status rfcmp_options_default(rfcmp_options* o) {
   o->power_tol = 1e-2;
   o->streams = kBatchStreams;
   o->projector = 0;
+  o->graphs = 1;
   return RFCMP_OK;
 }
 
@@ -1096,6 +1200,7 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
   RF_ARG(std::isfinite(o.power_tol) && o.power_tol >= 0, "power_tol must be >= 0");
   RF_ARG(o.streams >= 1 && o.streams <= kBatchStreams, "streams must be 1..4");
   RF_ARG(o.projector >= 0 && o.projector <= 2, "projector must be 0, 1 or 2");
+  RF_ARG(o.graphs == 0 || o.graphs == 1, "graphs must be 0 or 1");
   if (o.projector == kProjAuto) o.projector = (o.precision == 1 || m->h.C > kAutoSparseCells) ? kProjSparse : kProjDense;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
@@ -1224,6 +1329,19 @@ rfcmp_status rfcmp_rhs_planewave(rfcmp_op op, const double* khat, const double* 
   return rhs_planewave(op, khat, pol, nrhs, static_cast<double2*>(e), static_cast<hipStream_t>(stream));
 }
 
+rfcmp_status rfcmp_rhs_planewave_split(rfcmp_op op, const double* khat, const double* pol, int32_t nrhs, void* s,
+                                       void* e1, void* stream) {
+  RF_ARG(op && khat && pol && s && e1 && s != e1, "NULL or aliased argument");
+  RF_ARG(nrhs > 0, "nrhs must be > 0");
+  for (int r = 0; r < nrhs; ++r) {
+    RF_ARG(unit(khat + 3 * r) && unit(pol + 3 * r), "khat and pol must be unit vectors (1e-12)");
+    const double dp = khat[3 * r] * pol[3 * r] + khat[3 * r + 1] * pol[3 * r + 1] + khat[3 * r + 2] * pol[3 * r + 2];
+    RF_ARG(std::fabs(dp) <= 1e-12, "pol must be orthogonal to khat (1e-12)");
+  }
+  return rhs_planewave(op, khat, pol, nrhs, static_cast<double2*>(e1), static_cast<hipStream_t>(stream),
+                       static_cast<double2*>(s));
+}
+
 rfcmp_status rfcmp_rhs_planewave_noalloc(rfcmp_op op, const double* khat, const double* pol, int32_t nrhs,
                                          void* e, void* stream) {
   RF_ARG(op && khat && pol && e, "NULL argument");
@@ -1253,8 +1371,17 @@ rfcmp_status rfcmp_farfield(rfcmp_op op, const void* j, int32_t nrhs, const doub
   RF_ARG(op && j && dirs && F, "NULL argument");
   RF_ARG(nrhs > 0 && ndir > 0 && nrhs <= 65535 && ndir <= (1 << 30), "nrhs and ndir must be > 0");
   for (int d = 0; d < ndir; ++d) RF_ARG(unit(dirs + 3 * d), "directions must be unit vectors (1e-12)");
-  return far_field(op, static_cast<const double2*>(j), nrhs, dirs, ndir, static_cast<double2*>(F),
+  return far_field(op, static_cast<const double2*>(j), nullptr, nrhs, dirs, ndir, static_cast<double2*>(F),
                    static_cast<double*>(rcs), static_cast<hipStream_t>(stream));
+}
+
+rfcmp_status rfcmp_farfield_split(rfcmp_op op, const void* j_loop, const void* j_star, int32_t nrhs,
+                                  const double* dirs, int32_t ndir, void* F, void* rcs, void* stream) {
+  RF_ARG(op && j_loop && j_star && dirs && F, "NULL argument");
+  RF_ARG(nrhs > 0 && ndir > 0 && nrhs <= 65535 && ndir <= (1 << 30), "nrhs and ndir must be > 0");
+  for (int d = 0; d < ndir; ++d) RF_ARG(unit(dirs + 3 * d), "directions must be unit vectors (1e-12)");
+  return far_field(op, static_cast<const double2*>(j_loop), static_cast<const double2*>(j_star), nrhs, dirs, ndir,
+                   static_cast<double2*>(F), static_cast<double*>(rcs), static_cast<hipStream_t>(stream));
 }
 
 rfcmp_status rfcmp_precond_rhs(rfcmp_op op, const void* e, void* b, int32_t nrhs, void* stream) {
@@ -1376,8 +1503,10 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
 }
 
 static rfcmp_status solve_common(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,
-                                 void* stream, rfcmp_info* info, bool system) {
+                                 void* stream, rfcmp_info* info, bool system, const void* sv = nullptr,
+                                 void* js = nullptr) {
   RF_ARG(op && e && j && e != j, "NULL or aliased argument");
+  RF_ARG(!js || (js != j && js != e && js != sv), "aliased argument");
   RF_ARG(nrhs > 0 && maxit > 0 && std::isfinite(tol) && tol > 0, "bad nrhs/maxit/tol");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t N = op->mesh->h.N;
@@ -1388,9 +1517,12 @@ static rfcmp_status solve_common(rfcmp_op op, const void* e, void* j, int32_t nr
   const int R = op->work_nrhs;
   for (int r0 = 0; r0 < nrhs; r0 += R) {
     const int nr = std::min(R, nrhs - r0);
+    const int64_t C = op->mesh->h.C;
     rfcmp_status st = solve_batch(op, static_cast<const double2*>(e) + (int64_t)r0 * N,
                                   static_cast<double2*>(j) + (int64_t)r0 * N, nr, tol, maxit, s,
-                                  info ? info + r0 : nullptr, system);
+                                  info ? info + r0 : nullptr, system,
+                                  sv ? static_cast<const double2*>(sv) + (int64_t)r0 * C : nullptr,
+                                  js ? static_cast<double2*>(js) + (int64_t)r0 * N : nullptr);
     if (st < 0) return st;
     if (st > worst) worst = st;
   }
@@ -1404,6 +1536,12 @@ static rfcmp_status solve_common(rfcmp_op op, const void* e, void* j, int32_t nr
 rfcmp_status rfcmp_solve(rfcmp_op op, const void* e, void* j, int32_t nrhs, double tol, int32_t maxit,
                          void* stream, rfcmp_info* info) {
   return solve_common(op, e, j, nrhs, tol, maxit, stream, info, false);
+}
+
+rfcmp_status rfcmp_solve_split(rfcmp_op op, const void* s, const void* e1, void* j_loop, void* j_star,
+                               int32_t nrhs, double tol, int32_t maxit, void* stream, rfcmp_info* info) {
+  RF_ARG(s && j_star, "NULL argument");
+  return solve_common(op, e1, j_loop, nrhs, tol, maxit, stream, info, false, s, j_star);
 }
 
 rfcmp_status rfcmp_solve_system(rfcmp_op op, const void* b, void* i, int32_t nrhs, double tol, int32_t maxit,
