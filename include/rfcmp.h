@@ -113,13 +113,14 @@ rfcmp_status rfcmp_mesh_edges(rfcmp_mesh m, int32_t* edge_vtx, int32_t* edge_cel
  * Writes *count; if pairs != NULL it must hold 2*count int32 (first call
  * with NULL to size it). */
 rfcmp_status rfcmp_mesh_near_pairs(rfcmp_mesh m, double near_factor, int64_t* count, int32_t* pairs);
-/* The sparse projector factors of a mesh (options.projector = 0), once an
- * operator has needed them: which 0 = L = Sigma^T Sigma (grounded), 1 = G_ll,
- * 2 = G_tp.  n: matrix size; supernodes and levels of the nested-dissection
- * tree; stored: doubles on the device (the blocks of L and the inverses of
- * its diagonal blocks, each in two orders); seconds: host time of ordering
- * and factorisation.  Every output nullable.  RFCMP_E_STATE if that factor
- * has not been built. */
+/* The sparse projector factors of a mesh, once an operator with sparse
+ * projectors (options.projector 1, or 0 resolved to 1) has needed them: which 0 = L = Sigma^T Sigma (grounded), 1 = G_ll,
+ * 2 = G_tp.  n: matrix size; supernodes: nodes of the nested-dissection tree;
+ * levels: launches per sweep of a solve (one for the bottom subtrees, one per
+ * height of the supernodes above them); stored: doubles on the device (the
+ * blocks of L and the inverses of its diagonal blocks, each in two orders);
+ * seconds: host time of ordering and factorisation.  Every output nullable.
+ * RFCMP_E_STATE if that factor has not been built. */
 rfcmp_status rfcmp_mesh_factor_info(rfcmp_mesh m, int32_t which, int64_t* n, int32_t* supernodes, int32_t* levels,
                                     int64_t* stored, double* seconds);
 void rfcmp_mesh_destroy(rfcmp_mesh m);
@@ -149,10 +150,9 @@ typedef struct {
                                  the device in FP64 in every precision;
                              2 = dense FP64 inverses formed on the device (O(n^3)
                                  set-up, 8 n^2 bytes each, streamed per product);
-                             0 = automatic (default): 1 when precision = 1 (many
-                                 right-hand sides; FP64 projectors inside the BF16x3
-                                 solve) or C > 12288 (where the cubic set-up of 2
-                                 dominates), else 2 */
+                             0 = automatic (default): 1 when C > 12288 (where the
+                                 cubic set-up of 2 dominates), else 2 (one streaming
+                                 pass over a small inverse beats a sparse solve) */
   int32_t graphs;         /* 1 (default): from its third iteration on, each CG
                              iteration is replayed as a HIP graph captured once
                              per operator (two graphs: the recurrence scalars
@@ -335,8 +335,9 @@ typedef struct {
  *   precision 0: CG on the complex64 / FP64 operator, restarted from the
  *                true residual when the recursive one has drifted;
  *   precision 1: iterative refinement: inner CG on the BF16x3 operator to
- *                1e-4 of the current residual, outer residual with the
- *                complex64 / FP64 operator.
+ *                max(1e-4 of the current residual, tol / 2), outer residual
+ *                with the complex64 / FP64 operator, rounds until it meets
+ *                tol.
  * e, j: device c128 [nrhs][N].  info: host [nrhs], nullable (iters counts
  * all inner iterations, restarts the residual rounds after the first).
  * Returns RFCMP_W_NOT_CONVERGED (best iterate in j) when maxit is reached,

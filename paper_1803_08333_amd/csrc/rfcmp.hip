@@ -37,8 +37,9 @@ const char* last_error();
 namespace {
 
 // projector option values; the automatic choice takes the sparse factors
-// for the BF16x3 path and for meshes where the dense inverse's cubic set-up
-// dominates (above 12288 cells: 0.36 s at 20480 against 29 ms)
+// where the dense inverse's cubic set-up dominates (above 12288 cells: 0.36 s
+// at 20480 against 29 ms), the dense inverses below, where one streaming pass
+// (22 us at 5120 cells) beats a sparse solve (about 0.25 ms)
 constexpr int kProjAuto = 0, kProjSparse = 1, kProjDense = 2;
 constexpr int64_t kAutoSparseCells = 12288;
 
@@ -233,9 +234,11 @@ struct Dense {
   }
 
   // y = M x (conj: conj(M) x, complex matrices only).
+  // The projector matrices (L^+, G_ll^-1, G_tp^-1) are applied in FP64 in
+  // both precisions; BF16x3 serves the blocks T_A and V.
   rfcmp_status prod(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
     if (sparse(m)) return sp_solve(m, in, y, nullptr, nullptr, nullptr, nr, 0);
-    if (bf16) return gemm(m, conj, in, y, nr);
+    if (bf16 && complex_matrix(m)) return gemm(m, conj, in, y, nr);
     const SymvJob j = job(m, in, y);
     if (complex_matrix(m))
       return csymv_jobs(&j, 1, conj, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, tag(m));
@@ -253,7 +256,7 @@ struct Dense {
       RF_TRY(prod(m0, conj, in0, y0, nr));
       return prod(m1, conj, in1, y1, nr1 > 0 ? nr1 : nr);
     }
-    if (bf16) {
+    if (bf16 && complex_matrix(m0)) {
       RF_TRY(gemm(m0, conj, in0, y0, nr));
       return gemm(m1, conj, in1, y1, nr1 > 0 ? nr1 : nr);
     }
@@ -760,13 +763,20 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
 //   precision 0: block CG on the complex64/FP64 operator to |r| <= tol |b|,
 //                restarted from the true residual until that meets tol too;
 //   precision 1: iterative refinement: inner block CG on the BF16x3 operator
-//                to 1e-4 of the current residual, i += d, true residual
+//                to kInnerReduction of the current residual (not below
+//                tol / 2), i += d, true residual
 //                r = b - A i with the complex64/FP64 operator, until
 //                |r| <= tol |b|.
 // system: e is the system's own right-hand side b and j receives the iterate
 // i (no excitation mapping, no recovery).
 // sv != nullptr: the excitation is split, e = Sigma sv + e (rhs_batch_split);
 // js != nullptr: j receives the loop part of the solution and js its star part.
+// Reduction the inner BF16x3 solve aims for in one round.  Deeper inner
+// solves (down to the products' own accuracy, about 1e-7) cost more Krylov
+// iterations than the FP64 residual and restart they save: on the level-5
+// sphere with 64 waves, 26 iterations against 21 in two rounds.
+constexpr double kInnerReduction = 1e-4;
+
 rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, double tol, int maxit, hipStream_t s,
                          rfcmp_info* info, bool system = false, const double2* sv = nullptr,
                          double2* js = nullptr) {
@@ -797,7 +807,7 @@ rfcmp_status solve_batch(rfcmp_op op, const double2* e, double2* j, int nr, doub
   for (int r = 0; r < nr; ++r) zero &= !(bn[r] > 0);
   for (int round = 0; round < 40 && !zero; ++round) {
     for (int r = 0; r < nr; ++r)
-      target[r] = split ? std::max(1e-4 * res[r], 0.5 * tol * bn[r]) : tol * bn[r];
+      target[r] = split ? std::max(kInnerReduction * res[r], 0.5 * tol * bn[r]) : tol * bn[r];
     int budget = maxit;
     for (int r = 0; r < nr; ++r) budget = std::min(budget, maxit - tot[r]);
     if (budget <= 0) {
@@ -874,21 +884,11 @@ rfcmp_status ready_projectors(rfcmp_op op, hipStream_t s) {
   return wait_projectors(m, s);
 }
 
-// BF16x3 planes of the operator's blocks and of the mesh's projector matrices.
+// BF16x3 planes of the operator's blocks (the projector matrices stay FP64;
+// rfcmp_matvec builds their planes on demand).
 rfcmp_status ensure_split(rfcmp_op op, hipStream_t s) {
   rfcmp_mesh m = op->mesh;
-  MeshDev& d = m->d;
   const MeshHost& h = m->h;
-  if (op->opt.projector == kProjDense && !d.Lp16) {
-    d.Lp16 = std::make_unique<SplitMatrix>();
-    RF_TRY(d.Lp16->from_f64(d.Lp.as<double>(), h.C, d.ldL, s));
-    d.Gll16 = std::make_unique<SplitMatrix>();
-    RF_TRY(d.Gll16->from_f64(d.Gll_inv.as<double>(), h.V, d.ldG, s));
-  }
-  if (op->opt.projector == kProjDense && d.has_gtp && !d.Gtp16) {
-    d.Gtp16 = std::make_unique<SplitMatrix>();
-    RF_TRY(d.Gtp16->from_f64(d.Gtp_inv.as<double>(), h.C, d.ldT, s));
-  }
   if (!op->TA16) {
     op->TA16 = std::make_unique<SplitMatrix>();
     RF_TRY(op->TA16->from_c64(op->TA.as<float2>(), h.N, op->ldA, kTriBlock, s));
@@ -1153,7 +1153,7 @@ rfcmp_status rfcmp_mesh_factor_info(rfcmp_mesh m, int32_t which, int64_t* n, int
   }
   if (n) *n = F->n;
   if (supernodes) *supernodes = F->nsn;
-  if (levels) *levels = F->nlev;
+  if (levels) *levels = F->ntop + (F->nsub > 0 ? 1 : 0);
   if (stored) *stored = F->nnz;
   if (seconds) *seconds = F->seconds;
   return RFCMP_OK;
@@ -1201,7 +1201,7 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
   RF_ARG(o.streams >= 1 && o.streams <= kBatchStreams, "streams must be 1..4");
   RF_ARG(o.projector >= 0 && o.projector <= 2, "projector must be 0, 1 or 2");
   RF_ARG(o.graphs == 0 || o.graphs == 1, "graphs must be 0 or 1");
-  if (o.projector == kProjAuto) o.projector = (o.precision == 1 || m->h.C > kAutoSparseCells) ? kProjSparse : kProjDense;
+  if (o.projector == kProjAuto) o.projector = m->h.C > kAutoSparseCells ? kProjSparse : kProjDense;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   RF_HIP(hipGetDevice(&dev));

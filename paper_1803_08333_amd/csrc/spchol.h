@@ -74,60 +74,76 @@ struct SpFactor {
 // independent subtrees.  Returns RFCMP_E_ARG if a pivot is not positive.
 rfcmp_status spchol_factor(const SpMatrix& A, bool grounded, int leaf, int threads, SpFactor& F);
 
-// A factor on the device, in the layout the solve reads.  The solve runs the
-// dissection levels (supernodes grouped by height) as flat phases of
-// independent row tasks:
-//   forward, heights up:
-//     fronts: each supernode's front (its entries of the vector, plus its
-//       children's update vectors at their positions: a gather list per
-//       front entry, in child order);
-//     column tasks (one per column i of a supernode): y_i = (L_ss^-1 v)_i,
-//       with the inverse of the diagonal block formed on the host in FP64;
-//     struct tasks (one per struct row t): u_t = v_t - (L_21 y)_t;
-//   backward, heights down:
-//     column tasks: z_j = y_j - (L_21^T x_struct)_j;
-//     column tasks: x_i = (L_ss^-T z)_i.
-// Every matrix is stored twice, column-major and row-major, so that each
-// phase reads it with consecutive tasks at consecutive addresses.
+// Entries per tile of the permutation kernels (input, output, partial sums).
+constexpr int kSpTile = 64;
+
+// A factor on the device, in the layout the solve reads.
+//
+// The supernodes split into bottom subtrees (every supernode whose subtree
+// spans at most about n/48 columns, grouped under the highest such
+// supernodes) and the top supernodes above them.  A solve is a short chain of
+// launches, each over many workgroups (and right-hand sides):
+//   input: the right-hand side formed (the operator's gathers) and permuted,
+//     a tile of entries by 16 right-hand sides per workgroup, transposed
+//     through LDS (for the Laplacian also its partial sums, then their mean);
+//   forward, bottom: one workgroup per subtree, its heights in order, one
+//     wave per supernode (the Laplacian's input mean taken off as the
+//     columns are read);
+//   forward, top: one launch per height, one workgroup per supernode;
+//   backward, top: heights down, one launch each;
+//   backward, bottom: one workgroup per subtree;
+//   output: permuted back (for the Laplacian less the mean of the result,
+//     from partial sums over tiles).
+// A supernode's forward step builds its front (its entries of the vector plus
+// its children's update vectors, gathered per front entry in child order),
+// forms y = L_ss^-1 v with the inverse of its diagonal block (formed on the
+// host in FP64) and its update vector u = v_struct - L_21 y; its backward
+// step forms z = y - L_21^T x_struct and x = L_ss^-T z.  Every matrix is stored
+// column- and row-major, so that each step reads it with neighbouring lanes at
+// neighbouring addresses.  A workgroup takes R right-hand sides at once (R
+// chosen per launch from the grid it gives and the LDS its fronts need): each
+// matrix entry it loads serves all R.
 struct SpDevice {
-  int n = 0, nsn = 0, nlev = 0, grounded = 0;
+  int n = 0, nsn = 0, grounded = 0;
   int max_front = 0, max_ncol = 0;
+  int nsub = 0, ntop = 0;                    // bottom subtrees, top heights
+  // LDS entries per right-hand side a supernode's steps need: 2 ncol + nstr
+  // (forward: the front and y; backward: x_struct and z); the largest over
+  // the bottom supernodes
+  int bot_lds = 0;
   int64_t nstr_total = 0, front_total = 0;
   int64_t nnz = 0;            // doubles of the factor as stored (both copies)
   double seconds = 0.0;       // host factorisation time
-  DevBuf perm, iperm, str;
-  DevBuf fr_lvl, fr_dest, fr_xsrc, fr_ptr, fr_src;    // front gathers, by level
-  DevBuf col_lvl, col_a, col_b, col_c;                 // column tasks, by level
-  DevBuf str_lvl, str_a, str_b, str_c;                 // struct tasks, by level
-  DevBuf lanes;                                        // int4 per level: lanes per task of the four phases
-  DevBuf l21, l21t, linv, linvt;
+  DevBuf perm, iperm, col0, str_off, str, front_off;
+  // per front entry, the child update entries that land there: fr_k slots
+  // each (fr_k = the most over the factor), unused slots -1
+  DevBuf fr_src;
+  int fr_k = 0;
+  DevBuf linv_off, l21_off, l21, l21t, linv, linvt;
+  DevBuf sub_ptr, sub_lvl, sub_nodes;        // bottom subtrees: levels and supernodes
+  DevBuf top_lvl, top_nodes;                 // top supernodes by height
+  // per top height (host copies): supernodes, and the largest LDS need
+  std::vector<int> top_count, top_lds;
   // complex128 entries of solve scratch per right-hand side: the permuted
-  // vector x (n), z (n), update vectors (nstr_total), fronts (front_total)
-  int64_t scratch_entries() const { return 2 * n + nstr_total + front_total; }
+  // vector x (n), the update vectors (nstr_total), partial sums of x over
+  // tiles of kSpTile entries, and the two means of the Laplacian solve (of
+  // the input and of the result).  The scratch holds them right-hand side
+  // fastest: entry e of right-hand side r at e * nrhs + r, so that the
+  // right-hand sides of a workgroup sit together.
+  int64_t tiles() const { return (n + kSpTile - 1) / kSpTile; }
+  int64_t scratch_entries() const { return n + nstr_total + tiles() + 2; }
 };
 
 // The device arrays of a factor, formed on the host.
 struct SpArrays {
-  int nlev = 0, max_ncol = 0;
+  int max_ncol = 0, nsub = 0, ntop = 0, bot_lds = 0;
   int64_t front_total = 0;
-  std::vector<int> iperm;
-  std::vector<int> fr_lvl, fr_dest, fr_xsrc, fr_ptr, fr_src;
-  std::vector<int> col_lvl, str_lvl;
-  // column task (one per column i of a supernode): a = {c0, ncol, i, front
-  // offset}, b = {offset of its inverse block, offset of its L_21 block},
-  // c = {struct offset so, nstr}
-  std::vector<int> col_a, col_c;
-  std::vector<long> col_b;
-  // struct task (one per struct row t of a supernode): a = {c0, ncol, t,
-  // front offset}, b = {offset of its L_21 block + t, update index so + t},
-  // c = {nstr, 0}
-  std::vector<int> str_a, str_c;
-  std::vector<long> str_b;
-  // per level, the lanes that share one task's sum in the phases y = L^-1 v,
-  // u = v - L_21 y, z = y - L_21^T x, x = L^-T z (a power of two up to 64,
-  // chosen so that the level's tasks fill about one pass of the workgroup)
-  std::vector<int> lanes;
+  std::vector<int> iperm, front_off, fr_src;
+  int fr_k = 0;
+  std::vector<long> linv_off, l21_off;
   std::vector<double> l21, l21t, linv, linvt;
+  std::vector<int> sub_ptr, sub_lvl, sub_nodes, top_lvl, top_nodes;
+  std::vector<int> top_count, top_lds;
 };
 void spchol_arrays(const SpFactor& F, SpArrays& out);
 

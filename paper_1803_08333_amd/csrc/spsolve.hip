@@ -1,14 +1,9 @@
 // Solves with the sparse projector factors on the device (FP64), and the
-// upload of a host factor.  See spchol.h.
+// upload of a host factor.  See spchol.h for the layout and the launches.
 //
-// One workgroup per right-hand side (and factor of a pair).  The input is
-// formed while it is permuted into the scratch (the operator's Sigma^T and
-// Lambda^T gathers, as in the dense products); the dissection levels are
-// then run as flat phases of independent row tasks (fronts, column tasks,
-// struct tasks forward; two column phases backward), separated by workgroup
-// barriers, and the result is permuted back.  For the grounded Laplacian
-// factor the input and the output are made mean-free (L^+).  Every sum runs
-// in a fixed order: the results do not depend on timing.
+// Every sum runs in a fixed order (fixed lane groups, fixed shuffle trees,
+// children in order): the results do not depend on timing or on how the
+// work is spread over workgroups.
 #include <algorithm>
 
 #include "spchol.h"
@@ -18,23 +13,19 @@ namespace rfcmp {
 namespace {
 
 struct SpArg {
-  int n, nlev, grounded, nrhs;
-  const int *perm, *iperm, *str;
-  const int *fr_lvl, *fr_dest, *fr_xsrc, *fr_ptr, *fr_src;
-  const int *col_lvl, *str_lvl;
-  const int4* lanes;
-  const int4* col_a;
-  const long2* col_b;
-  const int2* col_c;
-  const int4* str_a;
-  const long2* str_b;
-  const int2* str_c;
+  int n, grounded, nrhs;  // nrhs: this job's right-hand sides
+  int nsub, ntop, fr_k, ntile;
+  long nstr_total;
+  const int *perm, *iperm, *col0, *str_off, *str, *front_off, *fr_src;
+  const long *linv_off, *l21_off;
   const double *l21, *l21t, *linv, *linvt;
+  const int *sub_ptr, *sub_lvl, *sub_nodes, *top_lvl, *top_nodes;
   SymvInput in;
   double2* y;
-  double2* scratch;
-  long sstride;      // scratch entries per right-hand side
-  long nstr_total;
+  double2* scratch;  // x [n][nrhs], u [nstr_total][nrhs], partial sums [ntile][nrhs], two means [2][nrhs]
+  __device__ double2* u() const { return scratch + (long)n * nrhs; }
+  __device__ double2* psum() const { return scratch + ((long)n + nstr_total) * nrhs; }
+  __device__ double2* mean(int which) const { return scratch + ((long)n + nstr_total + ntile + which) * nrhs; }
 };
 struct SpArgs {
   SpArg a[2];
@@ -45,223 +36,330 @@ __device__ inline double2 cfma(double a, double2 v, double2 acc) {
   return make_double2(fma(a, v.x, acc.x), fma(a, v.y, acc.y));
 }
 
-// Sum over the workgroup, in a fixed order (lane sums, then wave sums in
-// order); red: LDS space of one double2 per wave.
-__device__ double2 block_sum(double2 v, double2* red) {
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o);
-    v.y += __shfl_xor(v.y, o);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double2 t = make_double2(0.0, 0.0);
-  for (int w = 0; w < W; ++w) t = cadd(t, red[w]);
-  return t;
+// Order the wave's LDS and global accesses: everything the wave wrote is
+// visible to all its lanes afterwards.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
 }
 
-constexpr int kSpThreads = 1024;
+template <int TEAM>
+__device__ inline void team_sync() {
+  if (TEAM == 64)
+    wave_sync();
+  else
+    __syncthreads();
+}
 
-// Sum over the G lanes of a task's group (G a power of two <= 64, the group
-// aligned in the wave), in a fixed order; every lane of the wave takes part.
-__device__ inline double2 group_sum(double2 v, int G) {
-  for (int o = G >> 1; o > 0; o >>= 1) {
+// Sum over the 64 lanes of a wave, in a fixed order.
+__device__ inline double2 wave_sum(double2 v) {
+  for (int o = 32; o > 0; o >>= 1) {
     v.x += __shfl_xor(v.x, o);
     v.y += __shfl_xor(v.y, o);
   }
   return v;
 }
 
-__global__ void __launch_bounds__(kSpThreads) k_spsolve(const SpArgs args) {
-  const SpArg& A = args.a[blockIdx.y];
-  const int r = blockIdx.x;
-  if (r >= A.nrhs) return;
-  __shared__ double2 red[kSpThreads / 64];
-  const int n = A.n;
-  double2* x = A.scratch + (long)r * A.sstride;
-  double2* z = x + n;
-  double2* u = z + n;
-  double2* fr = u + A.nstr_total;
-  const int tid = threadIdx.x, nt = blockDim.x;
-
-  // permuted input; mean-free for the Laplacian
-  double2 s = make_double2(0.0, 0.0);
-  for (int i = tid; i < n; i += nt) {
-    const double2 v = input_entry(A.in, r, A.perm[i]);
-    x[i] = v;
-    s = cadd(s, v);
+// Lanes of a team of T over R right-hand sides (R a power of two <= 16):
+// lane t serves right-hand side r = t mod R; G lanes (ids R apart, in one
+// wave) split each sum; S = T / (R G) rows are formed at once.  G is the
+// largest power of two with R G <= 64 and rows R G <= T.
+struct Lanes {
+  int r, g, slot, G, S;
+};
+__device__ inline Lanes lanes_of(int t, int T, int R, int rows) {
+  int G = 1;
+  while (R * G * 2 <= 64 && rows * R * G * 2 <= T) G *= 2;
+  Lanes l;
+  l.G = G;
+  l.r = t & (R - 1);
+  const int q = t / R;
+  l.g = q & (G - 1);
+  l.slot = q / G;
+  l.S = T / (R * G);
+  return l;
+}
+__device__ inline double2 group_sum(double2 v, int R, int G) {
+  for (int o = G >> 1; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o * R);
+    v.y += __shfl_xor(v.y, o * R);
   }
-  if (A.grounded) {
-    const double2 t = block_sum(s, red);
-    const double2 mean = make_double2(t.x / n, t.y / n);
-    for (int i = tid; i < n; i += nt) x[i] = make_double2(x[i].x - mean.x, x[i].y - mean.y);
+  return v;
+}
+
+// sum over j = j0 + g, j0 + g + G, ... < j1 of M[j ld + i] V[j R + r], with
+// up to sixteen loads of M in flight per lane
+__device__ inline double2 strided_dot(const double* __restrict__ M, int ld, int i, const double2* V, int R, int r,
+                                      int j0, int j1, int g, int G) {
+  double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
+  int j = j0 + g;
+#pragma unroll 2
+  for (; j + 7 * G < j1; j += 8 * G) {
+    double m[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m[e] = M[(long)(j + e * G) * ld + i];
+    a0 = cfma(m[0], V[j * R + r], a0);
+    a1 = cfma(m[1], V[(j + G) * R + r], a1);
+    a2 = cfma(m[2], V[(j + 2 * G) * R + r], a2);
+    a3 = cfma(m[3], V[(j + 3 * G) * R + r], a3);
+    a0 = cfma(m[4], V[(j + 4 * G) * R + r], a0);
+    a1 = cfma(m[5], V[(j + 5 * G) * R + r], a1);
+    a2 = cfma(m[6], V[(j + 6 * G) * R + r], a2);
+    a3 = cfma(m[7], V[(j + 7 * G) * R + r], a3);
+  }
+  for (; j < j1; j += G) a0 = cfma(M[(long)j * ld + i], V[j * R + r], a0);
+  return cadd(cadd(a0, a1), cadd(a2, a3));
+}
+
+// Forward step of supernode sn for right-hand sides r0 .. r0+R-1 on a team
+// of TEAM lanes; lds: (2 ncol + nstr) R entries.
+template <int TEAM>
+__device__ void node_forward(const SpArg& A, int sn, int t, int R, int r0, double2* lds) {
+  const int NR = A.nrhs;
+  double2* x = A.scratch;
+  double2* u = A.u();
+  const int c0 = A.col0[sn], ncol = A.col0[sn + 1] - c0;
+  const int so = A.str_off[sn], nstr = A.str_off[sn + 1] - so;
+  const int fo = A.front_off[sn], m = ncol + nstr, K = A.fr_k;
+  double2* v = lds;              // front [m][R]
+  double2* yv = lds + m * R;     // y [ncol][R]
+  {  // the front: x on the columns (less the input mean of the Laplacian)
+     // plus the children's update entries
+    const int r = t & (R - 1), rg = r0 + r;
+    const double2 mu = (A.grounded && rg < NR) ? A.mean(0)[rg] : make_double2(0.0, 0.0);
+    for (int p = t / R; p < m; p += TEAM / R) {
+      double2 val = make_double2(0.0, 0.0);
+      if (rg < NR) {
+        if (p < ncol) {
+          const double2 xv = x[(long)(c0 + p) * NR + rg];
+          val = make_double2(xv.x - mu.x, xv.y - mu.y);
+        }
+        for (int k = 0; k < K; ++k) {
+          const int q = A.fr_src[(long)(fo + p) * K + k];
+          if (q >= 0) val = cadd(val, u[(long)q * NR + rg]);
+        }
+      }
+      v[p * R + r] = val;
+    }
+  }
+  team_sync<TEAM>();
+  {  // y_i = (L_ss^-1 v)_i: columns j <= i
+    const Lanes L = lanes_of(t, TEAM, R, ncol);
+    const double* M = A.linv + A.linv_off[sn];
+    const int rg = r0 + L.r;
+    for (int base = 0; base < ncol; base += L.S) {
+      const int i = base + L.slot;
+      const double2 acc = group_sum(strided_dot(M, ncol, i, v, R, L.r, 0, i < ncol ? i + 1 : 0, L.g, L.G), R, L.G);
+      if (i < ncol && L.g == 0) {
+        yv[i * R + L.r] = acc;
+        if (rg < NR) x[(long)(c0 + i) * NR + rg] = acc;
+      }
+    }
+  }
+  team_sync<TEAM>();
+  {  // u_q = v_(ncol + q) - (L_21 y)_q
+    const Lanes L = lanes_of(t, TEAM, R, nstr);
+    const double* M = A.l21 + A.l21_off[sn];
+    const int rg = r0 + L.r;
+    for (int base = 0; base < nstr; base += L.S) {
+      const int q = base + L.slot;
+      const double2 acc = group_sum(strided_dot(M, nstr, q, yv, R, L.r, 0, q < nstr ? ncol : 0, L.g, L.G), R, L.G);
+      if (q < nstr && L.g == 0 && rg < NR) {
+        const double2 w = v[(ncol + q) * R + L.r];
+        u[(long)(so + q) * NR + rg] = make_double2(w.x - acc.x, w.y - acc.y);
+      }
+    }
+  }
+  team_sync<TEAM>();
+}
+
+// Backward step of supernode sn: x_s = L_ss^-T (y - L_21^T x_struct).
+template <int TEAM>
+__device__ void node_backward(const SpArg& A, int sn, int t, int R, int r0, double2* lds) {
+  const int NR = A.nrhs;
+  double2* x = A.scratch;
+  const int c0 = A.col0[sn], ncol = A.col0[sn + 1] - c0;
+  const int so = A.str_off[sn], nstr = A.str_off[sn + 1] - so;
+  double2* xs = lds;              // x_struct [nstr][R]
+  double2* z = lds + nstr * R;    // z [ncol][R]
+  {
+    const int r = t & (R - 1), rg = r0 + r;
+    for (int q = t / R; q < nstr; q += TEAM / R)
+      xs[q * R + r] = rg < NR ? x[(long)A.str[so + q] * NR + rg] : make_double2(0.0, 0.0);
+  }
+  team_sync<TEAM>();
+  {  // z_j = y_j - (L_21^T x_struct)_j
+    const Lanes L = lanes_of(t, TEAM, R, ncol);
+    const double* M = A.l21t + A.l21_off[sn];  // (q, j) at M[q * ncol + j]
+    const int rg = r0 + L.r;
+    for (int base = 0; base < ncol; base += L.S) {
+      const int j = base + L.slot;
+      const double2 acc = group_sum(strided_dot(M, ncol, j, xs, R, L.r, 0, j < ncol ? nstr : 0, L.g, L.G), R, L.G);
+      if (j < ncol && L.g == 0) {
+        const double2 yy = rg < NR ? x[(long)(c0 + j) * NR + rg] : make_double2(0.0, 0.0);
+        z[j * R + L.r] = make_double2(yy.x - acc.x, yy.y - acc.y);
+      }
+    }
+  }
+  team_sync<TEAM>();
+  {  // x_i = (L_ss^-T z)_i: rows j >= i
+    const Lanes L = lanes_of(t, TEAM, R, ncol);
+    const double* M = A.linvt + A.linv_off[sn];  // (i, j) of L_ss^-T at M[j * ncol + i]
+    const int rg = r0 + L.r;
+    for (int base = 0; base < ncol; base += L.S) {
+      const int i = base + L.slot;
+      const double2 acc =
+          group_sum(strided_dot(M, ncol, i, z, R, L.r, i < ncol ? i : 0, i < ncol ? ncol : 0, L.g, L.G), R, L.G);
+      if (i < ncol && L.g == 0 && rg < NR) x[(long)(c0 + i) * NR + rg] = acc;
+    }
+  }
+  team_sync<TEAM>();
+}
+
+constexpr int kSpThreads = 1024;
+constexpr int kSpTileR = 16;  // right-hand sides per workgroup of the permutation kernels
+static_assert(kSpTile * kSpTileR == kSpThreads, "one permutation tile per workgroup");
+
+// input: x = P (the right-hand side); a tile of kSpTile entries by kSpTileR
+// right-hand sides per workgroup, read along the entries and written along
+// the right-hand sides.  For the Laplacian also the tile's sums (each wave
+// holds one right-hand side of the tile).
+__global__ void __launch_bounds__(kSpThreads) k_sp_input(const SpArgs args) {
+  const SpArg& A = args.a[blockIdx.z];
+  const int g0 = blockIdx.x * kSpTile, r0 = blockIdx.y * kSpTileR, NR = A.nrhs;
+  if (g0 >= A.n || r0 >= NR) return;
+  __shared__ double2 tile[kSpTile][kSpTileR + 1];
+  const int t = threadIdx.x;
+  {
+    const int gl = t % kSpTile, rl = t / kSpTile, g = g0 + gl, r = r0 + rl;
+    const double2 v = (g < A.n && r < NR) ? input_entry(A.in, r, g) : make_double2(0.0, 0.0);
+    tile[gl][rl] = v;
+    if (A.grounded) {
+      const double2 s = wave_sum(v);
+      if (gl == 0 && r < NR) A.psum()[(long)blockIdx.x * NR + r] = s;
+    }
   }
   __syncthreads();
+  {
+    const int rl = t % kSpTileR, gl = t / kSpTileR, g = g0 + gl, r = r0 + rl;
+    if (g < A.n && r < NR) A.scratch[(long)A.iperm[g] * NR + r] = tile[gl][rl];
+  }
+}
 
-  // forward, heights up
-  for (int h = 0; h < A.nlev; ++h) {
-    // fronts: own entries plus the children's update vectors, in child order
-    for (int k = A.fr_lvl[h] + tid; k < A.fr_lvl[h + 1]; k += nt) {
-      const int xs = A.fr_xsrc[k];
-      double2 v = xs >= 0 ? x[xs] : make_double2(0.0, 0.0);
-      for (int q = A.fr_ptr[k]; q < A.fr_ptr[k + 1]; ++q) v = cadd(v, u[A.fr_src[q]]);
-      fr[A.fr_dest[k]] = v;
-    }
-    __syncthreads();
-    // y_i = (L_ss^-1 v)_i: row i of the inverse, columns j <= i
-    {
-      const int4 G4 = A.lanes[h];
-      const int G = G4.x, per = nt / G, g = tid & (G - 1), slot = tid / G;
-      for (int base = A.col_lvl[h]; base < A.col_lvl[h + 1]; base += per) {
-        const int k = base + slot;
-        double2 acc = make_double2(0.0, 0.0);
-        if (k < A.col_lvl[h + 1]) {
-          const int4 t = A.col_a[k];  // {c0, ncol, i, front}
-          const double* L = A.linv + A.col_b[k].x + t.z;  // (i, j) at L[j * ncol]
-          const double2* v = fr + t.w;
-          double2 a1 = acc, a2 = acc, a3 = acc;
-          int j = g;
-          for (; j + 3 * G <= t.z; j += 4 * G) {
-            const double l0 = L[(long)j * t.y], l1 = L[(long)(j + G) * t.y];
-            const double l2 = L[(long)(j + 2 * G) * t.y], l3 = L[(long)(j + 3 * G) * t.y];
-            acc = cfma(l0, v[j], acc);
-            a1 = cfma(l1, v[j + G], a1);
-            a2 = cfma(l2, v[j + 2 * G], a2);
-            a3 = cfma(l3, v[j + 3 * G], a3);
-          }
-          for (; j <= t.z; j += G) acc = cfma(L[(long)j * t.y], v[j], acc);
-          acc = cadd(cadd(acc, a1), cadd(a2, a3));
-        }
-        acc = group_sum(acc, G);
-        if (k < A.col_lvl[h + 1] && g == 0) {
-          const int4 t = A.col_a[k];
-          x[t.x + t.z] = acc;
-        }
-      }
-    }
-    __syncthreads();
-    // u_t = v_(ncol + t) - (L_21 y)_t
-    {
-      const int4 G4 = A.lanes[h];
-      const int G = G4.y, per = nt / G, g = tid & (G - 1), slot = tid / G;
-      for (int base = A.str_lvl[h]; base < A.str_lvl[h + 1]; base += per) {
-        const int k = base + slot;
-        double2 acc = make_double2(0.0, 0.0);
-        if (k < A.str_lvl[h + 1]) {
-          const int4 t = A.str_a[k];   // {c0, ncol, t, front}
-          const long2 b = A.str_b[k];  // {L_21 offset + t, u index}
-          const int nstr = A.str_c[k].x;
-          const double* L = A.l21 + b.x;  // (t, j) at L[j * nstr]
-          const double2* y = x + t.x;
-          double2 a1 = acc, a2 = acc, a3 = acc;
-          int j = g;
-          for (; j + 3 * G < t.y; j += 4 * G) {
-            const double l0 = L[(long)j * nstr], l1 = L[(long)(j + G) * nstr];
-            const double l2 = L[(long)(j + 2 * G) * nstr], l3 = L[(long)(j + 3 * G) * nstr];
-            acc = cfma(l0, y[j], acc);
-            a1 = cfma(l1, y[j + G], a1);
-            a2 = cfma(l2, y[j + 2 * G], a2);
-            a3 = cfma(l3, y[j + 3 * G], a3);
-          }
-          for (; j < t.y; j += G) acc = cfma(L[(long)j * nstr], y[j], acc);
-          acc = cadd(cadd(acc, a1), cadd(a2, a3));
-        }
-        acc = group_sum(acc, G);
-        if (k < A.str_lvl[h + 1] && g == 0) {
-          const int4 t = A.str_a[k];
-          const double2 v = fr[t.w + t.y + t.z];
-          u[A.str_b[k].y] = make_double2(v.x - acc.x, v.y - acc.y);
-        }
-      }
-    }
-    __syncthreads();
+// The Laplacian's partial sums of x over tiles of the permuted entries
+// (after the backward sweep).
+__global__ void __launch_bounds__(kSpThreads) k_sp_colsum(const SpArgs args) {
+  const SpArg& A = args.a[blockIdx.z];
+  const int i0 = blockIdx.x * kSpTile, r0 = blockIdx.y * kSpTileR, NR = A.nrhs;
+  if (!A.grounded || i0 >= A.n || r0 >= NR) return;
+  __shared__ double2 tile[kSpTile][kSpTileR + 1];
+  const int t = threadIdx.x;
+  {
+    const int rl = t % kSpTileR, il = t / kSpTileR, i = i0 + il, r = r0 + rl;
+    tile[il][rl] = (i < A.n && r < NR) ? A.scratch[(long)i * NR + r] : make_double2(0.0, 0.0);
   }
+  __syncthreads();
+  {
+    const int il = t % kSpTile, rl = t / kSpTile, r = r0 + rl;
+    const double2 s = wave_sum(tile[il][rl]);
+    if (il == 0 && r < NR) A.psum()[(long)blockIdx.x * NR + r] = s;
+  }
+}
 
-  // backward, heights down
-  for (int h = A.nlev - 1; h >= 0; --h) {
-    // z_j = y_j - (L_21^T x_struct)_j
-    {
-      const int4 G4 = A.lanes[h];
-      const int G = G4.z, per = nt / G, g = tid & (G - 1), slot = tid / G;
-      for (int base = A.col_lvl[h]; base < A.col_lvl[h + 1]; base += per) {
-        const int k = base + slot;
-        double2 acc = make_double2(0.0, 0.0);
-        if (k < A.col_lvl[h + 1]) {
-          const int4 t = A.col_a[k];  // {c0, ncol, j, front}
-          const int2 c = A.col_c[k];  // {so, nstr}
-          const double* L = A.l21t + A.col_b[k].y + t.z;  // (q, j) at L[q * ncol]
-          const int* srow = A.str + c.x;
-          double2 a1 = acc, a2 = acc, a3 = acc;
-          int q = g;
-          for (; q + 3 * G < c.y; q += 4 * G) {
-            const double l0 = L[(long)q * t.y], l1 = L[(long)(q + G) * t.y];
-            const double l2 = L[(long)(q + 2 * G) * t.y], l3 = L[(long)(q + 3 * G) * t.y];
-            const int r0 = srow[q], r1 = srow[q + G], r2 = srow[q + 2 * G], r3 = srow[q + 3 * G];
-            acc = cfma(l0, x[r0], acc);
-            a1 = cfma(l1, x[r1], a1);
-            a2 = cfma(l2, x[r2], a2);
-            a3 = cfma(l3, x[r3], a3);
-          }
-          for (; q < c.y; q += G) acc = cfma(L[(long)q * t.y], x[srow[q]], acc);
-          acc = cadd(cadd(acc, a1), cadd(a2, a3));
-        }
-        acc = group_sum(acc, G);
-        if (k < A.col_lvl[h + 1] && g == 0) {
-          const int4 t = A.col_a[k];
-          const double2 y = x[t.x + t.z];
-          z[t.x + t.z] = make_double2(y.x - acc.x, y.y - acc.y);
-        }
-      }
-    }
-    __syncthreads();
-    // x_i = (L_ss^-T z)_i: column i of the inverse, rows j >= i
-    {
-      const int4 G4 = A.lanes[h];
-      const int G = G4.w, per = nt / G, g = tid & (G - 1), slot = tid / G;
-      for (int base = A.col_lvl[h]; base < A.col_lvl[h + 1]; base += per) {
-        const int k = base + slot;
-        double2 acc = make_double2(0.0, 0.0);
-        if (k < A.col_lvl[h + 1]) {
-          const int4 t = A.col_a[k];
-          const double* L = A.linvt + A.col_b[k].x + t.z;  // (j, i) of the inverse at L[j * ncol]
-          const double2* zz = z + t.x;
-          double2 a1 = acc, a2 = acc, a3 = acc;
-          int j = t.z + g;
-          for (; j + 3 * G < t.y; j += 4 * G) {
-            const double l0 = L[(long)j * t.y], l1 = L[(long)(j + G) * t.y];
-            const double l2 = L[(long)(j + 2 * G) * t.y], l3 = L[(long)(j + 3 * G) * t.y];
-            acc = cfma(l0, zz[j], acc);
-            a1 = cfma(l1, zz[j + G], a1);
-            a2 = cfma(l2, zz[j + 2 * G], a2);
-            a3 = cfma(l3, zz[j + 3 * G], a3);
-          }
-          for (; j < t.y; j += G) acc = cfma(L[(long)j * t.y], zz[j], acc);
-          acc = cadd(cadd(acc, a1), cadd(a2, a3));
-        }
-        acc = group_sum(acc, G);
-        if (k < A.col_lvl[h + 1] && g == 0) {
-          const int4 t = A.col_a[k];
-          x[t.x + t.z] = acc;
-        }
-      }
-    }
-    __syncthreads();
+// The Laplacian's mean (which 0: of the input, 1: of the result) from the
+// partial sums, in a fixed order.
+__global__ void __launch_bounds__(kSpThreads) k_sp_mean(const SpArgs args, int which) {
+  const SpArg& A = args.a[blockIdx.z];
+  const int r0 = blockIdx.x * kSpTileR, NR = A.nrhs;
+  if (!A.grounded || r0 >= NR) return;
+  __shared__ double2 red[kSpThreads / kSpTileR][kSpTileR];
+  const int t = threadIdx.x, rl = t % kSpTileR, part = t / kSpTileR, r = r0 + rl;
+  constexpr int P = kSpThreads / kSpTileR;
+  double2 s = make_double2(0.0, 0.0);
+  if (r < NR)
+    for (int b = part; b < A.ntile; b += P) s = cadd(s, A.psum()[(long)b * NR + r]);
+  red[part][rl] = s;
+  __syncthreads();
+  if (t < kSpTileR && r0 + t < NR) {
+    double2 tot = make_double2(0.0, 0.0);
+    for (int q = 0; q < P; ++q) tot = cadd(tot, red[q][t]);
+    A.mean(which)[r0 + t] = make_double2(tot.x / A.n, tot.y / A.n);
   }
+}
 
-  // back to the original order; mean-free for the Laplacian
-  double2 mean = make_double2(0.0, 0.0);
-  if (A.grounded) {
-    double2 t = make_double2(0.0, 0.0);
-    for (int i = tid; i < n; i += nt) t = cadd(t, x[i]);
-    t = block_sum(t, red);
-    mean = make_double2(t.x / n, t.y / n);
+// output: y = P^T x (less the Laplacian's mean of the result); read along
+// the right-hand sides, written along the entries
+__global__ void __launch_bounds__(kSpThreads) k_sp_output(const SpArgs args) {
+  const SpArg& A = args.a[blockIdx.z];
+  const int g0 = blockIdx.x * kSpTile, r0 = blockIdx.y * kSpTileR, NR = A.nrhs;
+  if (g0 >= A.n || r0 >= NR) return;
+  __shared__ double2 tile[kSpTile][kSpTileR + 1];
+  const int t = threadIdx.x;
+  {
+    const int rl = t % kSpTileR, gl = t / kSpTileR, g = g0 + gl, r = r0 + rl;
+    double2 v = make_double2(0.0, 0.0);
+    if (g < A.n && r < NR) {
+      v = A.scratch[(long)A.iperm[g] * NR + r];
+      if (A.grounded) {
+        const double2 mu = A.mean(1)[r];
+        v = make_double2(v.x - mu.x, v.y - mu.y);
+      }
+    }
+    tile[gl][rl] = v;
   }
-  double2* yr = A.y + (long)r * n;
-  for (int g = tid; g < n; g += nt) {
-    const double2 v = x[A.iperm[g]];
-    yr[g] = make_double2(v.x - mean.x, v.y - mean.y);
+  __syncthreads();
+  {
+    const int gl = t % kSpTile, rl = t / kSpTile, g = g0 + gl, r = r0 + rl;
+    if (g < A.n && r < NR) A.y[(long)r * A.n + g] = tile[gl][rl];
   }
+}
+
+// bottom subtrees: one workgroup per (subtree, R right-hand sides, job); the
+// subtree's heights in order, one wave per supernode, `slice` LDS entries per
+// wave, at most kSpBottomWaves waves
+constexpr int kSpBottomWaves = 8;
+__global__ void __launch_bounds__(64 * kSpBottomWaves) k_sp_bottom(const SpArgs args, int backward, int R, int slice) {
+  const SpArg& A = args.a[blockIdx.z];
+  const int b = blockIdx.x, r0 = blockIdx.y * R;
+  if (b >= A.nsub || r0 >= A.nrhs) return;
+  extern __shared__ double2 lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  double2* mine = lds + (long)wave * slice;
+  const int l0 = A.sub_ptr[b], nl = A.sub_ptr[b + 1] - l0 - 1;
+  for (int q = 0; q < nl; ++q) {
+    const int l = backward ? nl - 1 - q : q;
+    for (int k = A.sub_lvl[l0 + l] + wave; k < A.sub_lvl[l0 + l + 1]; k += W) {
+      if (backward)
+        node_backward<64>(A, A.sub_nodes[k], lane, R, r0, mine);
+      else
+        node_forward<64>(A, A.sub_nodes[k], lane, R, r0, mine);
+    }
+    __syncthreads();
+  }
+}
+
+// one top height: one workgroup per (supernode, R right-hand sides, job)
+__global__ void __launch_bounds__(kSpThreads) k_sp_top(const SpArgs args, int level, int backward, int R) {
+  const SpArg& A = args.a[blockIdx.z];
+  const int r0 = blockIdx.y * R;
+  if (level >= A.ntop || r0 >= A.nrhs) return;
+  const int k = A.top_lvl[level] + blockIdx.x;
+  if (k >= A.top_lvl[level + 1]) return;
+  extern __shared__ double2 lds[];
+  if (backward)
+    node_backward<kSpThreads>(A, A.top_nodes[k], threadIdx.x, R, r0, lds);
+  else
+    node_forward<kSpThreads>(A, A.top_nodes[k], threadIdx.x, R, r0, lds);
+}
+
+// Right-hand sides per workgroup: the largest power of two up to 16 that
+// still gives about `target` workgroups over `units` units of work and whose
+// LDS (`need` entries per right-hand side, times `teams`) fits 64 KB.
+int rhs_per_group(int nrhs, int units, int target, int need, int teams) {
+  int R = 1;
+  while (R < 16 && (int64_t)nrhs * units >= (int64_t)2 * R * target) R *= 2;
+  while (R > 1 && (int64_t)teams * need * R * (int64_t)sizeof(double2) > 65536) R /= 2;
+  return R;
 }
 
 }  // namespace
@@ -272,71 +370,122 @@ rfcmp_status spsolve_jobs(const SpSolveJob* jobs, int njobs, int nrhs, hipStream
     return RFCMP_E_ARG;
   }
   SpArgs args{};
+  int nsub = 0, ntop = 0, blds = 0, ntile = 0;
+  bool grounded = false;
   for (int q = 0; q < njobs; ++q) {
     const SpDevice& F = *jobs[q].F;
     SpArg& a = args.a[q];
     a.n = F.n;
-    a.nlev = F.nlev;
     a.grounded = F.grounded;
+    a.nsub = F.nsub;
+    a.ntop = F.ntop;
+    a.fr_k = F.fr_k;
+    a.ntile = (int)F.tiles();
+    a.nstr_total = F.nstr_total;
     a.perm = F.perm.as<int>();
     a.iperm = F.iperm.as<int>();
+    a.col0 = F.col0.as<int>();
+    a.str_off = F.str_off.as<int>();
     a.str = F.str.as<int>();
-    a.fr_lvl = F.fr_lvl.as<int>();
-    a.fr_dest = F.fr_dest.as<int>();
-    a.fr_xsrc = F.fr_xsrc.as<int>();
-    a.fr_ptr = F.fr_ptr.as<int>();
+    a.front_off = F.front_off.as<int>();
     a.fr_src = F.fr_src.as<int>();
-    a.col_lvl = F.col_lvl.as<int>();
-    a.lanes = F.lanes.as<int4>();
-    a.str_lvl = F.str_lvl.as<int>();
-    a.col_a = F.col_a.as<int4>();
-    a.col_b = F.col_b.as<long2>();
-    a.col_c = F.col_c.as<int2>();
-    a.str_a = F.str_a.as<int4>();
-    a.str_b = F.str_b.as<long2>();
-    a.str_c = F.str_c.as<int2>();
+    a.linv_off = F.linv_off.as<long>();
+    a.l21_off = F.l21_off.as<long>();
     a.l21 = F.l21.as<double>();
     a.l21t = F.l21t.as<double>();
     a.linv = F.linv.as<double>();
     a.linvt = F.linvt.as<double>();
+    a.sub_ptr = F.sub_ptr.as<int>();
+    a.sub_lvl = F.sub_lvl.as<int>();
+    a.sub_nodes = F.sub_nodes.as<int>();
+    a.top_lvl = F.top_lvl.as<int>();
+    a.top_nodes = F.top_nodes.as<int>();
     a.in = jobs[q].in;
     a.y = jobs[q].y;
     a.scratch = jobs[q].scratch;
-    a.sstride = F.scratch_entries();
-    a.nstr_total = F.nstr_total;
     a.nrhs = (q == 1 && jobs[1].nrhs > 0) ? std::min(jobs[1].nrhs, nrhs) : nrhs;
+    nsub = std::max(nsub, F.nsub);
+    ntop = std::max(ntop, F.ntop);
+    blds = std::max(blds, F.bot_lds);
+    ntile = std::max(ntile, a.ntile);
+    grounded = grounded || F.grounded;
   }
+  // bottom: about 512 workgroups; as many waves as their slices fit 64 KB
+  int Rb = 1, W = 1;
+  int64_t slice = 0;
+  if (nsub > 0) {
+    Rb = rhs_per_group(nrhs, nsub, 512, blds, 4);
+    slice = (int64_t)blds * Rb;
+    if (slice * (int64_t)sizeof(double2) > 65536) {
+      set_error("spsolve: a front of %d entries does not fit the LDS", blds);
+      return RFCMP_E_STATE;
+    }
+    W = (int)std::min<int64_t>(kSpBottomWaves, 65536 / (slice * (int64_t)sizeof(double2)));
+  }
+  // top: per height, about 256 workgroups
+  std::vector<int> Rt(ntop), nodes(ntop), need(ntop);
+  for (int l = 0; l < ntop; ++l) {
+    for (int q = 0; q < njobs; ++q) {
+      const SpDevice& F = *jobs[q].F;
+      if (l < F.ntop) {
+        nodes[l] = std::max(nodes[l], F.top_count[l]);
+        need[l] = std::max(need[l], F.top_lds[l]);
+      }
+    }
+    Rt[l] = rhs_per_group(nrhs, nodes[l], 256, need[l], 1);
+    if ((int64_t)need[l] * Rt[l] * (int64_t)sizeof(double2) > 65536) {
+      set_error("spsolve: a front of %d entries does not fit the LDS", need[l]);
+      return RFCMP_E_STATE;
+    }
+  }
+  const unsigned nj = (unsigned)njobs, nrt = (unsigned)((nrhs + kSpTileR - 1) / kSpTileR);
+  const dim3 tiles((unsigned)ntile, nrt, nj);
   ProfScope prof(tag, s);
-  hipLaunchKernelGGL(k_spsolve, dim3((unsigned)nrhs, (unsigned)njobs), dim3(kSpThreads), 0, s, args);
+  hipLaunchKernelGGL(k_sp_input, tiles, dim3(kSpThreads), 0, s, args);
+  if (grounded) hipLaunchKernelGGL(k_sp_mean, dim3(nrt, 1, nj), dim3(kSpThreads), 0, s, args, 0);
+  const dim3 bgrid((unsigned)nsub, (unsigned)((nrhs + Rb - 1) / Rb), nj);
+  if (nsub > 0)
+    hipLaunchKernelGGL(k_sp_bottom, bgrid, dim3(64 * W), (size_t)(W * slice) * sizeof(double2), s, args, 0, Rb,
+                       (int)slice);
+  auto top = [&](int l, int bwd) {
+    hipLaunchKernelGGL(k_sp_top, dim3((unsigned)nodes[l], (unsigned)((nrhs + Rt[l] - 1) / Rt[l]), nj), dim3(kSpThreads),
+                       (size_t)need[l] * Rt[l] * sizeof(double2), s, args, l, bwd, Rt[l]);
+  };
+  for (int l = 0; l < ntop; ++l) top(l, 0);
+  for (int l = ntop - 1; l >= 0; --l) top(l, 1);
+  if (nsub > 0)
+    hipLaunchKernelGGL(k_sp_bottom, bgrid, dim3(64 * W), (size_t)(W * slice) * sizeof(double2), s, args, 1, Rb,
+                       (int)slice);
+  if (grounded) {
+    hipLaunchKernelGGL(k_sp_colsum, tiles, dim3(kSpThreads), 0, s, args);
+    hipLaunchKernelGGL(k_sp_mean, dim3(nrt, 1, nj), dim3(kSpThreads), 0, s, args, 1);
+  }
+  hipLaunchKernelGGL(k_sp_output, tiles, dim3(kSpThreads), 0, s, args);
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
 }
 
 void spchol_arrays(const SpFactor& F, SpArrays& a) {
   const int n = F.n, nsn = F.nsn;
-  int H = 0;
-  for (int q = 0; q < nsn; ++q) H = std::max(H, F.height[q]);
-  a.nlev = H + 1;
-  std::vector<std::vector<int>> by_h(H + 1);
-  for (int q = 0; q < nsn; ++q) by_h[F.height[q]].push_back(q);
   // block offsets and front offsets
-  std::vector<long> linv_off(nsn + 1, 0), l21_off(nsn + 1, 0);
-  std::vector<int> front_off(nsn + 1, 0);
+  a.linv_off.assign(nsn + 1, 0);
+  a.l21_off.assign(nsn + 1, 0);
+  a.front_off.assign(nsn + 1, 0);
   a.max_ncol = 0;
   for (int q = 0; q < nsn; ++q) {
     const int ncol = F.col0[q + 1] - F.col0[q], nstr = F.str_off[q + 1] - F.str_off[q];
-    linv_off[q + 1] = linv_off[q] + (long)ncol * ncol;
-    l21_off[q + 1] = l21_off[q] + (long)nstr * ncol;
-    front_off[q + 1] = front_off[q] + ncol + nstr;
+    a.linv_off[q + 1] = a.linv_off[q] + (long)ncol * ncol;
+    a.l21_off[q + 1] = a.l21_off[q] + (long)nstr * ncol;
+    a.front_off[q + 1] = a.front_off[q] + ncol + nstr;
     a.max_ncol = std::max(a.max_ncol, ncol);
   }
-  a.front_total = front_off[nsn];
+  a.front_total = a.front_off[nsn];
   // matrices: L_21 (nstr x ncol, column-major) and its transpose; the inverse
   // of the diagonal block (column-major) and its transpose
-  a.l21.assign(l21_off[nsn], 0.0);
-  a.l21t.assign(l21_off[nsn], 0.0);
-  a.linv.assign(linv_off[nsn], 0.0);
-  a.linvt.assign(linv_off[nsn], 0.0);
+  a.l21.assign(a.l21_off[nsn], 0.0);
+  a.l21t.assign(a.l21_off[nsn], 0.0);
+  a.linv.assign(a.linv_off[nsn], 0.0);
+  a.linvt.assign(a.linv_off[nsn], 0.0);
   for (int q = 0; q < nsn; ++q) {
     const int ncol = F.col0[q + 1] - F.col0[q], nstr = F.str_off[q + 1] - F.str_off[q];
     const int m = ncol + nstr;
@@ -344,87 +493,99 @@ void spchol_arrays(const SpFactor& F, SpArrays& a) {
     for (int j = 0; j < ncol; ++j)
       for (int t = 0; t < nstr; ++t) {
         const double v = P[(size_t)j * m + ncol + t];
-        a.l21[l21_off[q] + (long)j * nstr + t] = v;
-        a.l21t[l21_off[q] + (long)t * ncol + j] = v;
+        a.l21[a.l21_off[q] + (long)j * nstr + t] = v;
+        a.l21t[a.l21_off[q] + (long)t * ncol + j] = v;
       }
     // Z = L_ss^-1 column by column, by forward substitution on e_c
-    double* Z = &a.linv[linv_off[q]];
+    double* Z = &a.linv[a.linv_off[q]];
     for (int c = 0; c < ncol; ++c)
       for (int i = c; i < ncol; ++i) {
         double acc = i == c ? 1.0 : 0.0;
         for (int k = c; k < i; ++k) acc -= P[(size_t)k * m + i] * Z[(size_t)c * ncol + k];
         Z[(size_t)c * ncol + i] = acc / P[(size_t)i * m + i];
       }
-    double* ZT = &a.linvt[linv_off[q]];
+    double* ZT = &a.linvt[a.linv_off[q]];
     for (int c = 0; c < ncol; ++c)
       for (int i = 0; i < ncol; ++i) ZT[(size_t)i * ncol + c] = Z[(size_t)c * ncol + i];
   }
-  // tasks by level
-  a.fr_lvl.assign(1, 0);
-  a.col_lvl.assign(1, 0);
-  a.str_lvl.assign(1, 0);
-  a.fr_dest.clear();
-  a.fr_xsrc.clear();
-  a.fr_ptr.assign(1, 0);
-  a.fr_src.clear();
-  a.col_a.clear();
-  a.col_b.clear();
-  a.col_c.clear();
-  a.str_a.clear();
-  a.str_b.clear();
-  a.str_c.clear();
-  for (int h = 0; h <= H; ++h) {
-    for (int q : by_h[h]) {
-      const int c0 = F.col0[q], ncol = F.col0[q + 1] - c0;
-      const int so = F.str_off[q], nstr = F.str_off[q + 1] - so;
-      const int m = ncol + nstr;
-      // front gathers: per entry, the child update entries that land there
-      std::vector<std::vector<int>> src(m);
+  // front gathers: per front entry, the child update entries that land there
+  // (in child order), fr_k slots per entry
+  {
+    std::vector<std::vector<int>> src(a.front_total);
+    for (int q = 0; q < nsn; ++q)
       for (int qc = F.child_off[q]; qc < F.child_off[q + 1]; ++qc) {
         const int c = F.child_idx[qc];
-        for (int t = F.str_off[c]; t < F.str_off[c + 1]; ++t) src[F.map[t]].push_back(t);
+        for (int t = F.str_off[c]; t < F.str_off[c + 1]; ++t) src[a.front_off[q] + F.map[t]].push_back(t);
       }
-      for (int p = 0; p < m; ++p) {
-        a.fr_dest.push_back(front_off[q] + p);
-        a.fr_xsrc.push_back(p < ncol ? c0 + p : -1);
-        for (int t : src[p]) a.fr_src.push_back(t);
-        a.fr_ptr.push_back((int)a.fr_src.size());
-      }
-      for (int i = 0; i < ncol; ++i) {
-        a.col_a.insert(a.col_a.end(), {c0, ncol, i, front_off[q]});
-        a.col_b.insert(a.col_b.end(), {linv_off[q], l21_off[q]});
-        a.col_c.insert(a.col_c.end(), {so, nstr});
-      }
-      for (int t = 0; t < nstr; ++t) {
-        a.str_a.insert(a.str_a.end(), {c0, ncol, t, front_off[q]});
-        a.str_b.insert(a.str_b.end(), {l21_off[q] + t, (long)so + t});
-        a.str_c.insert(a.str_c.end(), {nstr, 0});
-      }
-    }
-    a.fr_lvl.push_back((int)a.fr_dest.size());
-    a.col_lvl.push_back((int)(a.col_a.size() / 4));
-    a.str_lvl.push_back((int)(a.str_a.size() / 4));
+    a.fr_k = 1;
+    for (const auto& v : src) a.fr_k = std::max(a.fr_k, (int)v.size());
+    a.fr_src.assign((size_t)a.front_total * a.fr_k, -1);
+    for (int64_t k = 0; k < a.front_total; ++k)
+      for (size_t e = 0; e < src[k].size(); ++e) a.fr_src[(size_t)k * a.fr_k + e] = src[k][e];
   }
-  // lanes per task: grow G while the level's tasks still fit one pass of the
-  // workgroup and each lane keeps at least four terms
-  a.lanes.clear();
+  // bottom subtrees: supernodes whose subtree spans at most `cap` columns;
+  // each maximal one is a subtree, its supernodes listed by height
+  const int cap = std::max(256, n / 48);
+  std::vector<int> first(nsn);  // first column of each supernode's subtree
+  for (int q = 0; q < nsn; ++q) {
+    first[q] = F.col0[q];
+    for (int qc = F.child_off[q]; qc < F.child_off[q + 1]; ++qc) first[q] = std::min(first[q], first[F.child_idx[qc]]);
+  }
+  std::vector<char> bottom(nsn, 0);
+  for (int q = 0; q < nsn; ++q) bottom[q] = F.col0[q + 1] - first[q] <= cap;
+  a.sub_ptr.assign(1, 0);
+  a.sub_lvl.clear();
+  a.sub_nodes.clear();
+  a.bot_lds = 0;
+  auto lds_need = [&](int p) {
+    const int ncol = F.col0[p + 1] - F.col0[p], nstr = F.str_off[p + 1] - F.str_off[p];
+    return 2 * ncol + nstr;
+  };
+  int nsub = 0;
+  for (int q = 0; q < nsn; ++q) {
+    if (!bottom[q] || (F.parent[q] >= 0 && bottom[F.parent[q]])) continue;
+    // q roots a subtree: its supernodes are those in q's column range
+    std::vector<int> members;
+    for (int p = 0; p <= q; ++p)
+      if (F.col0[p] >= first[q] && F.col0[p + 1] <= F.col0[q + 1]) members.push_back(p);
+    int hmax = 0;
+    for (int p : members) hmax = std::max(hmax, F.height[p]);
+    a.sub_lvl.push_back((int)a.sub_nodes.size());
+    for (int h = 0; h <= hmax; ++h) {
+      for (int p : members)
+        if (F.height[p] == h) {
+          a.sub_nodes.push_back(p);
+          a.bot_lds = std::max(a.bot_lds, lds_need(p));
+        }
+      a.sub_lvl.push_back((int)a.sub_nodes.size());
+    }
+    a.sub_ptr.push_back((int)a.sub_lvl.size());
+    ++nsub;
+  }
+  a.nsub = nsub;
+  // top supernodes by height
+  int H = 0;
+  for (int q = 0; q < nsn; ++q)
+    if (!bottom[q]) H = std::max(H, F.height[q]);
+  std::vector<std::vector<int>> by_h(H + 1);
+  for (int q = 0; q < nsn; ++q)
+    if (!bottom[q]) by_h[F.height[q]].push_back(q);
+  a.top_lvl.assign(1, 0);
+  a.top_nodes.clear();
+  a.top_count.clear();
+  a.top_lds.clear();
   for (int h = 0; h <= H; ++h) {
-    int ncol_sum = 0, nstr_sum = 0, ncol_max = 0, nstr_max = 0;
+    if (by_h[h].empty()) continue;
+    int need = 0;
     for (int q : by_h[h]) {
-      const int ncol = F.col0[q + 1] - F.col0[q], nstr = F.str_off[q + 1] - F.str_off[q];
-      ncol_sum += ncol;
-      nstr_sum += nstr;
-      ncol_max = std::max(ncol_max, ncol);
-      nstr_max = std::max(nstr_max, nstr);
+      a.top_nodes.push_back(q);
+      need = std::max(need, lds_need(q));
     }
-    auto pick = [](int tasks, int len) {
-      int G = 1;
-      while (G < 64 && (long)tasks * G * 2 <= kSpThreads && G * 8 <= len) G *= 2;
-      return G;
-    };
-    a.lanes.insert(a.lanes.end(), {pick(ncol_sum, ncol_max), pick(nstr_sum, ncol_max), pick(ncol_sum, nstr_max),
-                                   pick(ncol_sum, ncol_max)});
+    a.top_count.push_back((int)by_h[h].size());
+    a.top_lds.push_back(need);
+    a.top_lvl.push_back((int)a.top_nodes.size());
   }
+  a.ntop = (int)a.top_lvl.size() - 1;
   a.iperm.assign(n, 0);
   for (int i = 0; i < n; ++i) a.iperm[F.perm[i]] = i;
 }
@@ -438,7 +599,12 @@ rfcmp_status spchol_upload(const SpFactor& F, SpDevice& D, hipStream_t s) {
   D.grounded = F.grounded ? 1 : 0;
   D.max_front = F.max_front;
   D.max_ncol = a.max_ncol;
-  D.nlev = a.nlev;
+  D.nsub = a.nsub;
+  D.ntop = a.ntop;
+  D.bot_lds = a.bot_lds;
+  D.fr_k = a.fr_k;
+  D.top_count = a.top_count;
+  D.top_lds = a.top_lds;
   D.seconds = F.seconds;
   D.nstr_total = F.str_off[nsn];
   D.front_total = a.front_total;
@@ -451,25 +617,22 @@ rfcmp_status spchol_upload(const SpFactor& F, SpDevice& D, hipStream_t s) {
   auto upv = [&](DevBuf& b, const auto& v) { return up(b, v.data(), sizeof(v[0]) * v.size()); };
   RF_TRY(upv(D.perm, F.perm));
   RF_TRY(upv(D.iperm, a.iperm));
+  RF_TRY(upv(D.col0, F.col0));
+  RF_TRY(upv(D.str_off, F.str_off));
   RF_TRY(upv(D.str, F.str));
-  RF_TRY(upv(D.fr_lvl, a.fr_lvl));
-  RF_TRY(upv(D.fr_dest, a.fr_dest));
-  RF_TRY(upv(D.fr_xsrc, a.fr_xsrc));
-  RF_TRY(upv(D.fr_ptr, a.fr_ptr));
+  RF_TRY(upv(D.front_off, a.front_off));
   RF_TRY(upv(D.fr_src, a.fr_src));
-  RF_TRY(upv(D.col_lvl, a.col_lvl));
-  RF_TRY(upv(D.col_a, a.col_a));
-  RF_TRY(upv(D.col_b, a.col_b));
-  RF_TRY(upv(D.col_c, a.col_c));
-  RF_TRY(upv(D.str_lvl, a.str_lvl));
-  RF_TRY(upv(D.lanes, a.lanes));
-  RF_TRY(upv(D.str_a, a.str_a));
-  RF_TRY(upv(D.str_b, a.str_b));
-  RF_TRY(upv(D.str_c, a.str_c));
+  RF_TRY(upv(D.linv_off, a.linv_off));
+  RF_TRY(upv(D.l21_off, a.l21_off));
   RF_TRY(upv(D.l21, a.l21));
   RF_TRY(upv(D.l21t, a.l21t));
   RF_TRY(upv(D.linv, a.linv));
   RF_TRY(upv(D.linvt, a.linvt));
+  RF_TRY(upv(D.sub_ptr, a.sub_ptr));
+  RF_TRY(upv(D.sub_lvl, a.sub_lvl));
+  RF_TRY(upv(D.sub_nodes, a.sub_nodes));
+  RF_TRY(upv(D.top_lvl, a.top_lvl));
+  RF_TRY(upv(D.top_nodes, a.top_nodes));
   // the host arrays above are locals: wait for the copies
   RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;

@@ -420,6 +420,8 @@ def test_full_size_solution_properties(name, k, nrhs, precision):
     assert st == 0
     assert max(i["rel_residual"] for i in info) <= 1e-6
     res = _efie_residual(rf, torch, m, op, k, j, e)
+    print(f"{name} ka={k} nrhs={nrhs} precision={precision}: iters {max(i['iters'] for i in info)}, "
+          f"rel residual {max(i['rel_residual'] for i in info):.2e}, EFIE residual {res.max():.2e}")
     assert res.max() < 5e-5, res.max()
     if precision == 1:
         op0 = rf.Operator(m, k, power_start=start, precision=0)

@@ -87,7 +87,7 @@ def test_condition_flat_in_k_and_h():
     meshes["torus"] = synth.torus(48, 24)
     rows = study.condition_study(meshes, ks, seed=7)
     for r in rows:
-        print(r["mesh"], r["N"], r["k"], round(r["cond"], 3), r["iters"])
+        print(r["mesh"], r["N"], r["k"], round(r["cond"], 3), r["iters"], flush=True)
         assert r["status"] == 0 and r["rel_residual"] <= 1e-10
     sphere = np.array([r["cond"] for r in rows if r["mesh"] != "torus"])
     assert sphere.max() < 20
@@ -113,7 +113,7 @@ def test_torus_condition_flat_in_h():
     meshes = {f"torus{a}x{b}": synth.torus(a, b) for a, b in ((24, 12), (48, 24), (96, 48))}
     rows = study.condition_study(meshes, ks, seed=7)
     for r in rows:
-        print(r["mesh"], r["N"], r["k"], round(r["cond"], 3), r["iters"])
+        print(r["mesh"], r["N"], r["k"], round(r["cond"], 3), r["iters"], flush=True)
         assert r["status"] == 0 and r["rel_residual"] <= 1e-10
     c = [max(r["cond"] for r in rows if r["mesh"] == name) for name in meshes]
     assert max(c) < 400
