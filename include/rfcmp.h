@@ -25,9 +25,10 @@
  *     is enqueued on it; calls that return host values synchronise it.
  *   - Complex vectors are interleaved (re, im).  "c128" = two doubles per
  *     entry, "c64" = two floats.  Batched vectors are [nrhs][n], contiguous.
- *   - RWG (edge) order: edges sorted by (min vertex, max vertex); c+ is the
- *     cell that walks the edge from its min to its max vertex in its CCW
- *     order.  Sigma[n,c+] = +1, Sigma[n,c-] = -1; Lambda[n,min] = +1,
+ *   - RWG (edge) order: the order in which a scan over the cells (cell 0,
+ *     1, ..., local edges 0, 1, 2 of each; local edge i joins vertices i+1
+ *     and i+2) first meets each edge; c+ is the cell that walks the edge
+ *     from its min to its max vertex in its CCW order.  Sigma[n,c+] = +1, Sigma[n,c-] = -1; Lambda[n,min] = +1,
  *     Lambda[n,max] = -1.
  *   - Handles are not thread-safe: calls on one handle must not overlap.
  */
@@ -396,7 +397,7 @@ rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* co
 /* ------------------------------------------------------------ profiling */
 /* Kernel timing for benchmarks.  While enabled, the library records a HIP
  * event pair on the launch stream around every launch of its timed kernels:
- * "far_pairs", "near_pairs", "gather_ta" (assembly), "cmatvec_ta",
+ * "assemble_ta", "near_pairs", "near_fix" (assembly), "cmatvec_ta",
  * "cmatvec_v" (complex64 block products), "dmatvec_lp", "dmatvec_gll",
  * "dmatvec_gtp" (FP64 projector products), "gemm_ta", "gemm_v", "gemm_lp",
  * "gemm_gll", "gemm_gtp" (BF16x3 products), "spd_inverse" (whole FP64

@@ -5,8 +5,10 @@ throughout, and the GPU library follows the same written convention):
 
 * Cells are CCW seen from outside; local edge i of a cell joins its vertices
   i+1 and i+2 (mod 3), so vertex i is the free vertex of local edge i.
-* Edges (= RWG functions, one per edge of the closed mesh) are ordered by the
-  pair (min vertex, max vertex), lexicographically.
+* Edges (= RWG functions, one per edge of the closed mesh) are numbered in the
+  order a scan over the cells (and over local edges 0, 1, 2 of each) first
+  meets them: by the lower-indexed of their two cells, then the local index
+  there.
 * c+ of an edge is the cell that walks it from its min to its max vertex in
   its CCW order; c- is the other one.  The RWG of eq. (RWGdef) is
   (r - r+)/(2A+) on c+ and (r- - r)/(2A-) on c-, with r+/r- the free vertices.
@@ -44,7 +46,14 @@ class Topology:
                 if (a, b) in directed:
                     raise MeshError("edge walked twice in the same direction (orientation or non-manifold)")
                 directed[(a, b)] = (c, i)
-        keys = sorted({(min(a, b), max(a, b)) for (a, b) in directed})
+        # edges in the order a scan over the cells first meets them: by the
+        # lower-indexed of their two cells, then the local index there (any
+        # order is a valid numbering; this one keeps the edges of nearby
+        # cells together)
+        def first_seen(key):
+            lo, hi = key
+            return min(directed[k] for k in ((lo, hi), (hi, lo)) if k in directed)
+        keys = sorted({(min(a, b), max(a, b)) for (a, b) in directed}, key=first_seen)
         self.N = len(keys)
         self.edges = np.array(keys, dtype=np.int64).reshape(-1, 2)
         self.cplus = np.empty(self.N, dtype=np.int64)

@@ -32,7 +32,6 @@ namespace rfcmp {
 namespace {
 
 constexpr int kQ = 7;
-constexpr int kTile = 16;
 
 // Radon's 7-point degree-5 rule (Stroud T2:5-1): centroid and two orbits.
 struct Rule {
@@ -97,64 +96,31 @@ __device__ inline void sincos_moderate(float x, float& sn, float& cs) {
 // precision for |x| < 2: sin within 1e-6 relative (also as x -> 0), cos
 // within 2.1e-7 absolute; beyond 2 the revolution product loses absolute
 // accuracy (7e-7 up to 10), so larger kR keeps the reduced polynomial.
-// Upper-triangular tile (I <= J) of kTile x kTile cell pairs per block, one
-// pair per thread.  Pairs c >= c' of diagonal tiles are left to their mirror
-// (c == c' to the near kernel).  Every pair writes B(c,c') and B(c',c) =
-// B(c,c')^T from the same registers, so B is exactly symmetric.
+// Normalised moments of one far cell pair (c, c') (see above), scaled by
+// 1/(4 pi): I_0, I_r (over c), I_r' (over c'), I_rr'.
+struct Moments {
+  float i0r, i0i, irr[3], iri[3], jrr[3], jri[3], kr, ki;
+};
+
+// qa: the 7 points of c minus its centroid, qb those of c'; (dx, dy, dz) =
+// x_c - x_c' (formed in FP64 by the caller).
 template <bool HW>
-__global__ __launch_bounds__(256) void k_far_pairs(int C, long ntiles, const double* __restrict__ cen,
-                                                   const float4* __restrict__ qoff,
-                                                   const float4* __restrict__ fvoff,
-                                                   const float* __restrict__ sgn, float kk,
-                                                   RuleArgs rule, float2* __restrict__ B, long ldB,
-                                                   float2* __restrict__ Vm, long ldV) {
-  const long t = blockIdx.x;
-  if (t >= ntiles) return;
-  // t -> (I, J) with I <= J, t = J(J+1)/2 + I
-  long J = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while (J * (J + 1) / 2 > t) --J;
-  while ((J + 1) * (J + 2) / 2 <= t) ++J;
-  const long I = t - J * (J + 1) / 2;
-
-  __shared__ float4 sq_t[kTile][kQ], sq_s[kTile][kQ];
-  __shared__ double sc_t[kTile][3], sc_s[kTile][3];
-  for (int e = threadIdx.x; e < kTile * kQ; e += 256) {
-    const int cc = e / kQ, q = e % kQ;
-    const long ct = I * kTile + cc, cs = J * kTile + cc;
-    sq_t[cc][q] = ct < C ? qoff[ct * kQ + q] : make_float4(0, 0, 0, 0);
-    sq_s[cc][q] = cs < C ? qoff[cs * kQ + q] : make_float4(0, 0, 0, 0);
-  }
-  for (int e = threadIdx.x; e < kTile * 3; e += 256) {
-    const int cc = e / 3, d = e % 3;
-    const long ct = I * kTile + cc, cs = J * kTile + cc;
-    sc_t[cc][d] = ct < C ? cen[ct * 3 + d] : 0.0;
-    sc_s[cc][d] = cs < C ? cen[cs * 3 + d] : 0.0;
-  }
-  __syncthreads();
-
-  const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
-  const long c = I * kTile + ti, cp = J * kTile + tj;
-  if (c >= C || cp >= C) return;
-  if (I == J && ti >= tj) return;
-
-  const float dx = (float)(sc_t[ti][0] - sc_s[tj][0]);
-  const float dy = (float)(sc_t[ti][1] - sc_s[tj][1]);
-  const float dz = (float)(sc_t[ti][2] - sc_s[tj][2]);
+__device__ inline void far_moments(const float4* qa, const float4* qb, float dx, float dy, float dz,
+                                   const RuleArgs& rule, float kk, Moments& M) {
   float bq[kQ][3], wq[kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const float4 b = sq_s[tj][q];
+    const float4 b = qb[q];
     bq[q][0] = b.x; bq[q][1] = b.y; bq[q][2] = b.z;
     wq[q] = rule.wf[q];
   }
-
-  float i0r = 0, i0i = 0;                       // I_0
-  float irr[3] = {0, 0, 0}, iri[3] = {0, 0, 0};   // I_r
-  float jrr[3] = {0, 0, 0}, jri[3] = {0, 0, 0};   // I_r'
-  float kr = 0, ki = 0;                         // I_rr'
+  float i0r = 0, i0i = 0;
+  float irr[3] = {0, 0, 0}, iri[3] = {0, 0, 0};
+  float jrr[3] = {0, 0, 0}, jri[3] = {0, 0, 0};
+  float kr = 0, ki = 0;
 #pragma unroll 1
   for (int p = 0; p < kQ; ++p) {
-    const float4 a = sq_t[ti][p];
+    const float4 a = qa[p];
     const float bx = dx + a.x, by = dy + a.y, bz = dz + a.z;
     float s0r = 0, s0i = 0, s1r[3] = {0, 0, 0}, s1i[3] = {0, 0, 0};
 #pragma unroll
@@ -196,37 +162,206 @@ __global__ __launch_bounds__(256) void k_far_pairs(int C, long ntiles, const dou
     ki += wp * (a.x * s1i[0] + a.y * s1i[1] + a.z * s1i[2]);
   }
   const float inv4pi = 0.0795774715459476679f;  // 1/(4 pi)
-  i0r *= inv4pi; i0i *= inv4pi; kr *= inv4pi; ki *= inv4pi;
+  M.i0r = i0r * inv4pi; M.i0i = i0i * inv4pi; M.kr = kr * inv4pi; M.ki = ki * inv4pi;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    irr[d] *= inv4pi; iri[d] *= inv4pi; jrr[d] *= inv4pi; jri[d] *= inv4pi;
+    M.irr[d] = irr[d] * inv4pi; M.iri[d] = iri[d] * inv4pi;
+    M.jrr[d] = jrr[d] * inv4pi; M.jri[d] = jri[d] * inv4pi;
   }
-  Vm[c * ldV + cp] = make_float2(i0r, i0i);
-  Vm[cp * ldV + c] = make_float2(i0r, i0i);
+}
 
-  float4 qt[3], qs[3];
-  float st[3], ss[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    qt[i] = fvoff[c * 3 + i];
-    qs[i] = fvoff[cp * 3 + i];
-    st[i] = sgn[c * 3 + i];
-    ss[i] = sgn[cp * 3 + i];
+// B[(c,i),(c',j)] = sigma_i sigma_j / 4 (I_rr' - q_i.I_r' - q'_j.(I_r - q_i I_0))
+// with q_i = vertex i of c minus its centroid, q'_j the same for c'.
+__device__ inline float2 b_entry(const Moments& M, float4 qi, float4 qj, float si, float sj) {
+  const float tr = M.kr - (qi.x * M.jrr[0] + qi.y * M.jrr[1] + qi.z * M.jrr[2]);
+  const float tim = M.ki - (qi.x * M.jri[0] + qi.y * M.jri[1] + qi.z * M.jri[2]);
+  const float ur0 = M.irr[0] - qi.x * M.i0r, ur1 = M.irr[1] - qi.y * M.i0r, ur2 = M.irr[2] - qi.z * M.i0r;
+  const float ui0 = M.iri[0] - qi.x * M.i0i, ui1 = M.iri[1] - qi.y * M.i0i, ui2 = M.iri[2] - qi.z * M.i0i;
+  const float f = 0.25f * si * sj;
+  return make_float2(f * (tr - (qj.x * ur0 + qj.y * ur1 + qj.z * ur2)),
+                     f * (tim - (qj.x * ui0 + qj.y * ui1 + qj.z * ui2)));
+}
+
+// ---------------------------------------------------------------- T_A tiles
+// One workgroup per pair of edge tiles (I <= J, kEdgeTile consecutive edges
+// each) forms the T_A entries (m in I, n in J) straight from the cell pairs
+// of the cells the two tiles touch: T_A[m,n] sums the four blocks
+// B[(m+-), (n+-)], and each cell pair adds its B entries to the entries of
+// its edges that lie in the tiles.  The sums run in LDS in a fixed order
+// without atomics: t1 = B[m+,n+] + B[m-,n-], t2 = B[m+,n-] + B[m-,n+], the
+// contributions whose row cell is c+ added in a first phase and those whose
+// row cell is c- in a second (each entry of t1 or t2 has one contribution
+// per phase), and T_A = t1 + t2 -- the same pairing whatever the order of
+// the cell pairs.  A diagonal tile takes each unordered cell pair once and
+// adds it to (m, n) and (n, m) from the same registers; a tile pair inside
+// one diagonal kTriBlock block also writes its transpose: T_A is exactly
+// symmetric where it is stored.  Near cell pairs (the self pairs among them)
+// take their blocks from k_near_pairs (NB, FP64 singular extraction, run
+// first) instead of the far rule: a tile pair that has near cell pairs
+// (tile_near) looks each of its cell pairs up in the sorted near partners of
+// its row cell.  V[c, c'] = I_0 of a far pair is written by the one
+// workgroup whose tiles are the home tiles of c and c' (k_near_pairs writes
+// the near ones).
+constexpr int kAsmThreads = 1024;
+struct CellL {
+  float4 q[kQ];   // quadrature points minus centroid
+  float4 fv[3];   // vertices minus centroid
+  double cen[3];
+  float sg[3];
+  int rows;       // rows of the three local edges in this tile (8 bits each)
+  int gid;        // cell index
+  int home;       // home tile
+};
+
+template <bool HW>
+__global__ __launch_bounds__(kAsmThreads) void k_assemble_ta(int N, const int* __restrict__ et_ptr,
+                                                             const int* __restrict__ et_cell,
+                                                             const int* __restrict__ et_rows,
+                                                             const int* __restrict__ cell_home,
+                                                             const double* __restrict__ cen,
+                                                             const float4* __restrict__ qoff,
+                                                             const float4* __restrict__ fvoff,
+                                                             const float* __restrict__ sgn, float kk,
+                                                             RuleArgs rule, const uint8_t* __restrict__ tile_near,
+                                                             const int* __restrict__ np_ptr,
+                                                             const int* __restrict__ np_other,
+                                                             const int* __restrict__ np_code,
+                                                             const float2* __restrict__ NB,
+                                                             float2* __restrict__ TA, long ldA,
+                                                             float2* __restrict__ Vm, long ldV) {
+  const long t = blockIdx.x;
+  long J = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (J * (J + 1) / 2 > t) --J;
+  while ((J + 1) * (J + 2) / 2 <= t) ++J;
+  const int I = (int)(t - J * (J + 1) / 2), Jt = (int)J;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float2(*t1)[kEdgeTile] = reinterpret_cast<float2(*)[kEdgeTile]>(smem);
+  float2(*t2)[kEdgeTile] = reinterpret_cast<float2(*)[kEdgeTile]>(smem + sizeof(float2) * kEdgeTile * kEdgeTile);
+  CellL* cl = reinterpret_cast<CellL*>(smem + 2 * sizeof(float2) * kEdgeTile * kEdgeTile);
+  const bool diag = I == Jt;
+  const int i0 = et_ptr[I], nI = et_ptr[I + 1] - i0, j0 = et_ptr[Jt], nJ = et_ptr[Jt + 1] - j0;
+  const int ncell = diag ? nI : nI + nJ;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * kEdgeTile * kEdgeTile; e += kAsmThreads)
+    reinterpret_cast<float2*>(smem)[e] = make_float2(0.f, 0.f);
+  for (int e = tid; e < ncell * kQ; e += kAsmThreads) {
+    const int k = e / kQ, q = e % kQ;
+    const int g = k < nI ? et_cell[i0 + k] : et_cell[j0 + k - nI];
+    cl[k].q[q] = qoff[(long)g * kQ + q];
   }
+  for (int k = tid; k < ncell; k += kAsmThreads) {
+    const int g = k < nI ? et_cell[i0 + k] : et_cell[j0 + k - nI];
+    CellL& c = cl[k];
+    c.rows = k < nI ? et_rows[i0 + k] : et_rows[j0 + k - nI];
+    c.gid = g;
+    c.home = cell_home[g];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    // t_i = I_rr' - q_i.I_r',  u_i = I_r - q_i I_0
-    const float tr = kr - (qt[i].x * jrr[0] + qt[i].y * jrr[1] + qt[i].z * jrr[2]);
-    const float tim = ki - (qt[i].x * jri[0] + qt[i].y * jri[1] + qt[i].z * jri[2]);
-    const float ur[3] = {irr[0] - qt[i].x * i0r, irr[1] - qt[i].y * i0r, irr[2] - qt[i].z * i0r};
-    const float ui[3] = {iri[0] - qt[i].x * i0i, iri[1] - qt[i].y * i0i, iri[2] - qt[i].z * i0i};
+    for (int i = 0; i < 3; ++i) {
+      c.fv[i] = fvoff[(long)g * 3 + i];
+      c.sg[i] = sgn[(long)g * 3 + i];
+      c.cen[i] = cen[(long)g * 3 + i];
+    }
+  }
+  __syncthreads();
+  const CellL* cI = cl;
+  const CellL* cJ = diag ? cl : cl + nI;
+  const bool any_near = tile_near[t] != 0;
+  const int total = nI * nJ;
+  for (int base = 0; base < total; base += kAsmThreads) {
+    const int p = base + tid;
+    const int a = p / nJ, b = p % nJ;
+    // a diagonal tile takes each unordered pair once, the self pairs too
+    const bool act = p < total && (!diag || a <= b);
+    float2 bv[3][3];
+    int ra = 0, rb = 0;
+    float sa[3] = {0, 0, 0}, sb[3] = {0, 0, 0};
+    bool self = false;
+    if (act) {
+      const CellL& A = cI[a];
+      const CellL& Bc = cJ[b];
+      self = A.gid == Bc.gid;
+      int code = -1;
+      if (any_near) {  // binary search of Bc among A's near partners
+        int lo = np_ptr[A.gid], hi = np_ptr[A.gid + 1];
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (np_other[mid] < Bc.gid)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        if (lo < np_ptr[A.gid + 1] && np_other[lo] == Bc.gid) code = np_code[lo];
+      }
+      if (code >= 0) {
+        // near: B[(A,i),(Bc,j)] of the pair stored as (A, Bc) (t = 0) or (Bc, A)
+        const float2* nb = NB + (long)(code >> 1) * 9;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const float f = 0.25f * st[i] * ss[j];
-      const float br = f * (tr - (qs[j].x * ur[0] + qs[j].y * ur[1] + qs[j].z * ur[2]));
-      const float bi = f * (tim - (qs[j].x * ui[0] + qs[j].y * ui[1] + qs[j].z * ui[2]));
-      B[(3 * c + i) * ldB + 3 * cp + j] = make_float2(br, bi);
-      B[(3 * cp + j) * ldB + 3 * c + i] = make_float2(br, bi);
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) bv[i][j] = nb[(code & 1) ? 3 * j + i : 3 * i + j];
+      } else {
+        Moments M;
+        far_moments<HW>(A.q, Bc.q, (float)(A.cen[0] - Bc.cen[0]), (float)(A.cen[1] - Bc.cen[1]),
+                        (float)(A.cen[2] - Bc.cen[2]), rule, kk, M);
+        if (A.home == I && Bc.home == Jt) {
+          const float2 v = make_float2(M.i0r, M.i0i);
+          Vm[(long)A.gid * ldV + Bc.gid] = v;
+          Vm[(long)Bc.gid * ldV + A.gid] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) bv[i][j] = b_entry(M, A.fv[i], Bc.fv[j], A.sg[i], Bc.sg[j]);
+      }
+      ra = A.rows;
+      rb = Bc.rows;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        sa[i] = A.sg[i];
+        sb[i] = Bc.sg[i];
+      }
+    }
+    // phase 0: contributions whose row cell is the edge's c+, phase 1: c-
+#pragma unroll
+    for (int phase = 0; phase < 2; ++phase) {
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const int r = (ra >> (8 * i)) & 0xFF;
+          if (r == 0xFF) continue;
+          const bool pa = sa[i] > 0.f;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const int c = (rb >> (8 * j)) & 0xFF;
+            if (c == 0xFF) continue;
+            const bool pb = sb[j] > 0.f;
+            float2(*T)[kEdgeTile] = pa == pb ? t1 : t2;
+            if ((phase == 0) == pa) {
+              T[r][c].x += bv[i][j].x;
+              T[r][c].y += bv[i][j].y;
+            }
+            if (diag && !self && (phase == 0) == pb) {
+              T[c][r].x += bv[i][j].x;
+              T[c][r].y += bv[i][j].y;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = tid; e < kEdgeTile * kEdgeTile; e += kAsmThreads) {
+    const int r = e / kEdgeTile, c = e % kEdgeTile;
+    const long m = (long)I * kEdgeTile + r, n = (long)Jt * kEdgeTile + c;
+    if (m < N && n < N)
+      TA[m * ldA + n] = make_float2(t1[r][c].x + t2[r][c].x, t1[r][c].y + t2[r][c].y);
+  }
+  if (!diag && (I * kEdgeTile) / kTriBlock == (Jt * kEdgeTile) / kTriBlock) {
+    for (int e = tid; e < kEdgeTile * kEdgeTile; e += kAsmThreads) {
+      const int c = e / kEdgeTile, r = e % kEdgeTile;
+      const long m = (long)I * kEdgeTile + r, n = (long)Jt * kEdgeTile + c;
+      if (m < N && n < N)
+        TA[n * ldA + m] = make_float2(t1[r][c].x + t2[r][c].x, t1[r][c].y + t2[r][c].y);
     }
   }
 }
@@ -294,7 +429,7 @@ __global__ __launch_bounds__(128) void k_near_pairs(long npairs, const int* __re
                                                     const double* __restrict__ vtx,
                                                     const double* __restrict__ area,
                                                     const float* __restrict__ sgn, double kk,
-                                                    RuleArgs rule, float2* __restrict__ B, long ldB,
+                                                    RuleArgs rule, float2* __restrict__ NB,
                                                     float2* __restrict__ Vm, long ldV) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= npairs) return;
@@ -375,33 +510,7 @@ __global__ __launch_bounds__(128) void k_near_pairs(long npairs, const int* __re
   Vm[(long)c * ldV + cp] = v;
   Vm[(long)cp * ldV + c] = v;
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      const float2 b = make_float2((float)br[i][j], (float)bi[i][j]);
-      B[(long)(3 * c + i) * ldB + 3 * cp + j] = b;
-      B[(long)(3 * cp + j) * ldB + 3 * c + i] = b;
-    }
-}
-
-// ---------------------------------------------------------------- gather
-// T_A[m,n] = (B[m+,n+] + B[m-,n-]) + (B[m+,n-] + B[m-,n+]) over the cell slots
-// of the two edges; the fixed pairing keeps T_A exactly symmetric.  Only
-// the entries with n >= kTriBlock floor(m / kTriBlock) are formed (the upper
-// triangle of kTriBlock-wide blocks, all that the symmetric products read);
-// the others are the transposed entries, bit for bit.
-__global__ __launch_bounds__(256) void k_gather_ta(int N, const int* __restrict__ slot,
-                                                   const float2* __restrict__ B, long ldB,
-                                                   float2* __restrict__ TA, long ldA) {
-  const int m = blockIdx.x;
-  const int sp = slot[2 * m], sm = slot[2 * m + 1];
-  const float2* bp = B + (long)sp * ldB;
-  const float2* bm = B + (long)sm * ldB;
-  for (int n = (m / kTriBlock) * kTriBlock + threadIdx.x; n < N; n += blockDim.x) {
-    const int np = slot[2 * n], nm = slot[2 * n + 1];
-    const float2 pp = bp[np], mm = bm[nm], pm = bp[nm], mp = bm[np];
-    const float2 s1 = make_float2(pp.x + mm.x, pp.y + mm.y);
-    const float2 s2 = make_float2(pm.x + mp.x, pm.y + mp.y);
-    TA[(long)m * ldA + n] = make_float2(s1.x + s2.x, s1.y + s2.y);
-  }
+    for (int j = 0; j < 3; ++j) NB[t * 9 + 3 * i + j] = make_float2((float)br[i][j], (float)bi[i][j]);
 }
 
 // ---------------------------------------------------------------- excitation
@@ -594,6 +703,15 @@ rfcmp_status mesh_upload(rfcmp_mesh m, hipStream_t s) {
   RF_TRY(up(d.ve_idx, h.vtx_edge_idx.data(), sizeof(int) * 2 * N));
   std::vector<float> vs(h.vtx_edge_sgn.begin(), h.vtx_edge_sgn.end());
   RF_TRY(up(d.ve_sgn, vs.data(), sizeof(float) * 2 * N));
+  std::vector<int> et_ptr, et_cell, et_rows, home;
+  int cmax = 0;
+  edge_tiles(h, et_ptr, et_cell, et_rows, home, cmax);
+  d.etiles = (int64_t)et_ptr.size() - 1;
+  d.et_cells_max = cmax;
+  RF_TRY(up(d.et_ptr, et_ptr.data(), sizeof(int) * et_ptr.size()));
+  RF_TRY(up(d.et_cell, et_cell.data(), sizeof(int) * et_cell.size()));
+  RF_TRY(up(d.et_rows, et_rows.data(), sizeof(int) * et_rows.size()));
+  RF_TRY(up(d.cell_home, home.data(), sizeof(int) * C));
   RF_HIP(hipStreamSynchronize(s));  // host staging vectors die here
   return RFCMP_OK;
 }
@@ -602,21 +720,14 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   rfcmp_mesh m = op->mesh;
   const MeshHost& h = m->h;
   MeshDev& d = m->d;
-  const int64_t C = h.C, N = h.N;
+  const int64_t N = h.N;
   const RuleArgs ra = rule_args();
-
-  const int64_t ldB = (int64_t)round_up(3 * C, 64);
-  // scratch and near-pair list live with the mesh: reused by every wavenumber
-  if (!d.pairB.p) RF_TRY(d.pairB.alloc(sizeof(float2) * ldB * 3 * C));
-  DevBuf& B = d.pairB;
   RF_HIP(hipMemsetAsync(op->Vb.p, 0, op->Vb.bytes, s));
 
   // far pairs first: they do not need the near-pair list, which a new mesh
-  // may still be computing on host threads
-  const long nt = (long)((C + kTile - 1) / kTile);
-  const long ntiles = nt * (nt + 1) / 2;
-  {
-  ProfScope prof("far_pairs", s);
+  // may still be computing on a host thread
+  const long nt = (long)d.etiles;
+  const long npairs_t = nt * (nt + 1) / 2;
   // largest kR between quadrature points: at most k times twice the largest
   // vertex distance from the bounding-box centre (the diameter of a sphere)
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -635,42 +746,135 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
     }
     rad2 = std::max(rad2, r2);
   }
-  const double diag = 2.0 * std::sqrt(rad2);
-  const bool hw = op->k * diag <= 2.0;
-  hipLaunchKernelGGL(hw ? k_far_pairs<true> : k_far_pairs<false>, dim3((unsigned)ntiles), dim3(256), 0, s, (int)C, ntiles, d.cen.as<double>(),
-                     d.qoff.as<float4>(), d.fvoff.as<float4>(), d.sgn.as<float>(), (float)op->k, ra,
-                     B.as<float2>(), (long)ldB, op->Vb.as<float2>(), (long)op->ldV);
-  }
-  RF_HIP(hipGetLastError());
+  const bool hw = op->k * 2.0 * std::sqrt(rad2) <= 2.0;
+  // the near pairs (computed on a host thread from mesh creation on): their
+  // blocks first, which the T_A tiles read
   if (d.near_factor != op->opt.near_factor) {
-    std::vector<int32_t> pairs;
+    NearData nd;
     if (m->near_async.valid() && m->near_async_factor == op->opt.near_factor)
-      pairs = m->near_async.get();  // started at mesh creation
+      nd = m->near_async.get();
     else
-      near_pairs(h, op->opt.near_factor, pairs);
-    RF_TRY(d.near.alloc(sizeof(int) * std::max<size_t>(pairs.size(), 2)));
-    d.near_host = std::move(pairs);  // the source stays alive with the mesh
-    RF_HIP(hipMemcpyAsync(d.near.p, d.near_host.data(), sizeof(int) * d.near_host.size(), hipMemcpyHostToDevice,
-                          s));
-    d.npairs = (int64_t)d.near_host.size() / 2;
+      near_data(h, op->opt.near_factor, nd);
+    const int64_t np = (int64_t)nd.pairs.size() / 2;
+    RF_TRY(d.near.alloc(sizeof(int) * std::max<int64_t>(2 * np, 2)));
+    RF_TRY(d.nearB.alloc(sizeof(float2) * 9 * std::max<int64_t>(np, 1)));
+    RF_TRY(d.np_ptr.alloc(sizeof(int) * nd.ptr.size()));
+    RF_TRY(d.np_other.alloc(sizeof(int) * std::max<size_t>(nd.other.size(), 1)));
+    RF_TRY(d.np_code.alloc(sizeof(int) * std::max<size_t>(nd.code.size(), 1)));
+    RF_TRY(d.tile_near.alloc(std::max<size_t>(nd.tile_near.size(), 1)));
+    d.near_host = std::move(nd);  // the sources stay alive with the mesh
+    const NearData& q = d.near_host;
+    auto copy = [&](DevBuf& dst, const void* src, size_t bytes) -> rfcmp_status {
+      if (bytes) RF_HIP(hipMemcpyAsync(dst.p, src, bytes, hipMemcpyHostToDevice, s));
+      return RFCMP_OK;
+    };
+    RF_TRY(copy(d.near, q.pairs.data(), sizeof(int) * q.pairs.size()));
+    RF_TRY(copy(d.np_ptr, q.ptr.data(), sizeof(int) * q.ptr.size()));
+    RF_TRY(copy(d.np_other, q.other.data(), sizeof(int) * q.other.size()));
+    RF_TRY(copy(d.np_code, q.code.data(), sizeof(int) * q.code.size()));
+    RF_TRY(copy(d.tile_near, q.tile_near.data(), q.tile_near.size()));
+    d.npairs = np;
     d.near_factor = op->opt.near_factor;
   }
   const long npairs = (long)d.npairs;
-  DevBuf& dp = d.near;
   if (npairs > 0) {
     ProfScope prof("near_pairs", s);
     hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, s, npairs,
-                       dp.as<int>(), d.vtx.as<double>(), d.area.as<double>(), d.sgn.as<float>(), op->k, ra,
-                       B.as<float2>(), (long)ldB, op->Vb.as<float2>(), (long)op->ldV);
+                       d.near.as<int>(), d.vtx.as<double>(), d.area.as<double>(), d.sgn.as<float>(), op->k, ra,
+                       d.nearB.as<float2>(), op->Vb.as<float2>(), (long)op->ldV);
     RF_HIP(hipGetLastError());
   }
   {
-  ProfScope prof("gather_ta", s);
-  hipLaunchKernelGGL(k_gather_ta, dim3((unsigned)N), dim3(256), 0, s, (int)N, d.edge_slot.as<int>(),
-                     B.as<float2>(), (long)ldB, op->TA.as<float2>(), (long)op->ldA);
+    ProfScope prof("assemble_ta", s);
+    const size_t lds = 2 * sizeof(float2) * kEdgeTile * kEdgeTile + 2 * sizeof(CellL) * (size_t)d.et_cells_max;
+    hipLaunchKernelGGL(hw ? k_assemble_ta<true> : k_assemble_ta<false>, dim3((unsigned)npairs_t), dim3(kAsmThreads),
+                       lds, s, (int)N, d.et_ptr.as<int>(), d.et_cell.as<int>(), d.et_rows.as<int>(),
+                       d.cell_home.as<int>(), d.cen.as<double>(), d.qoff.as<float4>(), d.fvoff.as<float4>(),
+                       d.sgn.as<float>(), (float)op->k, ra, d.tile_near.as<uint8_t>(), d.np_ptr.as<int>(),
+                       d.np_other.as<int>(), d.np_code.as<int>(), d.nearB.as<float2>(), op->TA.as<float2>(),
+                       (long)op->ldA, op->Vb.as<float2>(), (long)op->ldV);
   }
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
+}
+
+void edge_tiles(const MeshHost& h, std::vector<int>& ptr, std::vector<int>& cell, std::vector<int>& rows,
+                std::vector<int>& home, int& cmax) {
+  const int64_t N = h.N, C = h.C;
+  const int64_t nt = (N + kEdgeTile - 1) / kEdgeTile;
+  ptr.assign(nt + 1, 0);
+  cell.clear();
+  rows.clear();
+  home.assign(C, 0);
+  cmax = 0;
+  std::vector<int> cells;
+  for (int64_t t = 0; t < nt; ++t) {
+    cells.clear();
+    for (int64_t e = t * kEdgeTile; e < std::min<int64_t>(N, (t + 1) * kEdgeTile); ++e)
+      for (int k = 0; k < 2; ++k) cells.push_back(h.edge_cell[2 * e + k]);
+    std::sort(cells.begin(), cells.end());
+    cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+    for (int c : cells) {
+      int r3 = 0;
+      for (int i = 0; i < 3; ++i) {
+        const int64_t e = h.cell_edge[3 * c + i];
+        const int r = (e / kEdgeTile == t) ? int(e % kEdgeTile) : 0xFF;
+        r3 |= r << (8 * i);
+      }
+      cell.push_back(c);
+      rows.push_back(r3);
+    }
+    ptr[t + 1] = (int)cell.size();
+    cmax = std::max(cmax, (int)cells.size());
+  }
+  for (int64_t c = 0; c < C; ++c) home[c] = int(h.cell_edge[3 * c] / kEdgeTile);
+}
+
+void near_data(const MeshHost& h, double factor, NearData& out) {
+  near_pairs(h, factor, out.pairs);
+  const int64_t np = (int64_t)out.pairs.size() / 2, C = h.C, N = h.N;
+  const int32_t* pr = out.pairs.data();
+  // the near partners of every cell, ascending (the list runs in order of its
+  // first cell, partners ascending), with 2 p + t
+  out.ptr.assign(C + 1, 0);
+  for (int64_t p = 0; p < np; ++p) {
+    ++out.ptr[pr[2 * p] + 1];
+    if (pr[2 * p] != pr[2 * p + 1]) ++out.ptr[pr[2 * p + 1] + 1];
+  }
+  for (int64_t c = 0; c < C; ++c) out.ptr[c + 1] += out.ptr[c];
+  out.other.resize(out.ptr[C]);
+  out.code.resize(out.ptr[C]);
+  {
+    std::vector<int32_t> fill(out.ptr.begin(), out.ptr.end() - 1);
+    for (int64_t p = 0; p < np; ++p) {
+      const int32_t a = pr[2 * p], b = pr[2 * p + 1];
+      out.other[fill[a]] = b;
+      out.code[fill[a]++] = int32_t(2 * p);
+      if (a != b) {
+        out.other[fill[b]] = a;
+        out.code[fill[b]++] = int32_t(2 * p + 1);
+      }
+    }
+    for (int64_t c = 0; c < C; ++c) {  // partners ascending, codes alongside
+      std::vector<std::pair<int32_t, int32_t>> v;
+      for (int32_t q = out.ptr[c]; q < out.ptr[c + 1]; ++q) v.emplace_back(out.other[q], out.code[q]);
+      std::sort(v.begin(), v.end());
+      for (size_t e = 0; e < v.size(); ++e) {
+        out.other[out.ptr[c] + e] = v[e].first;
+        out.code[out.ptr[c] + e] = v[e].second;
+      }
+    }
+  }
+  // edge-tile pairs (I <= J) that hold a near cell pair
+  const int64_t nt = (N + kEdgeTile - 1) / kEdgeTile;
+  out.tile_near.assign((size_t)(nt * (nt + 1) / 2), 0);
+  for (int64_t p = 0; p < np; ++p)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int64_t ta = h.cell_edge[3 * pr[2 * p] + i] / kEdgeTile, tb = h.cell_edge[3 * pr[2 * p + 1] + j] / kEdgeTile;
+        const int64_t I = std::min(ta, tb), J = std::max(ta, tb);
+        out.tile_near[(size_t)(J * (J + 1) / 2 + I)] = 1;
+      }
 }
 
 namespace {

@@ -138,6 +138,16 @@ struct SplitMatrix;  // BF16x3 planes of a matrix (gemm.h)
 struct SpFactor;     // sparse Cholesky factor, host (spchol.h)
 struct SpDevice;     // sparse Cholesky factor, device (spchol.h)
 
+// The near pairs of one factor (c <= c', self pairs included) and what the
+// T_A assembly looks them up with (assemble.hip): the near partners of each
+// cell, ascending (ptr/other), with code 2 p + t for pair p (t = 1: the
+// pair is stored with the partner first), and per pair of edge tiles
+// (I <= J, index J (J + 1)/2 + I) whether any of its cell pairs is near.
+struct NearData {
+  std::vector<int32_t> pairs, ptr, other, code;
+  std::vector<uint8_t> tile_near;
+};
+
 // A sparse factor computed on a host thread.
 struct HostFactor {
   rfcmp_status status = RFCMP_OK;
@@ -168,11 +178,19 @@ struct MeshDev {
   DevBuf Gll_inv;    // double [ldG][ldG]
   DevBuf Gtp_inv;    // double [ldT][ldT]
   std::unique_ptr<SplitMatrix> Lp16, Gll16, Gtp16;  // BF16x3 planes, built on demand
+  // assembly edge tiles (kEdgeTile consecutive edges each) and the cells
+  // each tile touches: et_cell[et_ptr[t] ..] ascending, et_rows the rows in
+  // the tile of each such cell's three local edges (8 bits each, 0xFF: not in
+  // the tile), cell_home the tile of each cell's local edge 0
+  int64_t etiles = 0;
+  int et_cells_max = 0;
+  DevBuf et_ptr, et_cell, et_rows, cell_home;
   double near_factor = -1.0;  // factor of the cached near-pair list
   int64_t npairs = 0;
   DevBuf near;       // int [npairs][2]
-  std::vector<int32_t> near_host;  // its host copy
-  DevBuf pairB;      // complex64 [3C][ldB] cell-pair block scratch of the assembly
+  DevBuf nearB;      // complex64 [npairs][3][3] near-pair blocks
+  DevBuf np_ptr, np_other, np_code, tile_near;  // NearData on the device
+  NearData near_host;  // host copy
   // The projector matrices are built on two internal streams (L^+ on the
   // first, G_ll^-1 and G_tp^-1 on the second), each with its own FP64 panel
   // buffers for the inverse.  A stream that uses them first waits for
@@ -196,7 +214,7 @@ struct rfcmp_mesh_s {
   // mesh creation on (declared last: its destructor waits for the thread
   // before h goes)
   double near_async_factor = -1.0;
-  std::future<std::vector<int32_t>> near_async;
+  std::future<rfcmp::NearData> near_async;
   // sparse factors of L and G_ll, computed on host threads from mesh
   // creation on (declared after h: their destructors wait for the threads)
   std::future<rfcmp::HostFactor> fac_async[2];
@@ -207,6 +225,9 @@ namespace rfcmp {
 // holds columns n >= kTriBlock floor(m / kTriBlock)); the rest of the buffer
 // is never written.
 constexpr int kTriBlock = 256;
+// Edges per tile of the T_A assembly (a divisor of kTriBlock).
+constexpr int kEdgeTile = 64;
+static_assert(kTriBlock % kEdgeTile == 0, "edge tiles nest in the stored blocks");
 }  // namespace rfcmp
 
 struct rfcmp_op_s {
@@ -244,6 +265,13 @@ namespace rfcmp {
 // mesh.cpp
 rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, int64_t nc, MeshHost& h);
 void near_pairs(const MeshHost& h, double factor, std::vector<int32_t>& out);
+void near_data(const MeshHost& h, double factor, NearData& out);
+// Edge tiles of the T_A assembly (kEdgeTile consecutive edges): the cells
+// of each tile (ptr/cell, ascending), the rows in the tile of their local
+// edges (rows, 8 bits each, 0xFF outside), the tile of each cell's local edge
+// 0 (home) and the most cells of a tile (cmax).
+void edge_tiles(const MeshHost& h, std::vector<int>& ptr, std::vector<int>& cell, std::vector<int>& rows,
+                std::vector<int>& home, int& cmax);
 void build_cell_nb(MeshHost& h);
 
 // assemble.hip

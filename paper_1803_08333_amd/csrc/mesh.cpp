@@ -115,6 +115,24 @@ rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, 
     i = j;
   }
   const int64_t N = int64_t(starts.size());
+  // number the edges in the order a scan over the cells (and their local
+  // edges) first meets them, so that the edges of nearby cells sit together
+  std::vector<int32_t> order(N);
+  {
+    std::vector<int32_t> of_half(3 * nc);  // key-ordered edge of each (cell, local)
+    for (int64_t k = 0; k < N; ++k)
+      for (int e = 0; e < 2; ++e) {
+        const Half& x = he[starts[k] + e];
+        of_half[3 * int64_t(x.cell) + x.local] = int32_t(k);
+      }
+    std::vector<int32_t> id(N, -1);
+    int32_t next = 0;
+    for (int64_t hc = 0; hc < 3 * nc; ++hc)
+      if (id[of_half[hc]] < 0) {
+        id[of_half[hc]] = next;
+        order[next++] = of_half[hc];
+      }
+  }
   h.N = N;
   h.edge_vtx.resize(2 * N);
   h.edge_cell.resize(2 * N);
@@ -122,8 +140,8 @@ rfcmp_status build_mesh_host(const double* xyz, int64_t nv, const int32_t* tri, 
   h.cell_edge.assign(3 * nc, -1);
   h.cell_sign.assign(3 * nc, 0);
   for (int64_t n = 0; n < N; ++n) {
-    const Half& p = he[starts[n]];      // walked min -> max: c+
-    const Half& q = he[starts[n] + 1];  // c-
+    const Half& p = he[starts[order[n]]];      // walked min -> max: c+
+    const Half& q = he[starts[order[n]] + 1];  // c-
     h.edge_vtx[2 * n] = int32_t(p.key / nv);
     h.edge_vtx[2 * n + 1] = int32_t(p.key % nv);
     h.edge_cell[2 * n] = p.cell;

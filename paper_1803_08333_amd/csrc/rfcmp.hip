@@ -1095,8 +1095,8 @@ rfcmp_status rfcmp_mesh_create(const double* xyz, int64_t nv, const int32_t* tri
     const MeshHost* hp = &m->h;
     const double f = o.near_factor;
     m->near_async = std::async(std::launch::async, [hp, f]() {
-      std::vector<int32_t> v;
-      near_pairs(*hp, f, v);
+      NearData v;
+      near_data(*hp, f, v);
       return v;
     });
     m->near_async_factor = f;
