@@ -397,11 +397,14 @@ rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* co
 /* ------------------------------------------------------------ profiling */
 /* Kernel timing for benchmarks.  While enabled, the library records a HIP
  * event pair on the launch stream around every launch of its timed kernels:
- * "assemble_ta", "near_pairs", "near_fix" (assembly), "cmatvec_ta",
- * "cmatvec_v" (complex64 block products), "dmatvec_lp", "dmatvec_gll",
- * "dmatvec_gtp" (FP64 projector products), "gemm_ta", "gemm_v", "gemm_lp",
- * "gemm_gll", "gemm_gtp" (BF16x3 products), "spd_inverse" (whole FP64
- * inverse).  rfcmp_profile_enable
+ * "assemble_ta", "near_pairs" (assembly), "cmatvec_ta", "cmatvec_v"
+ * (complex64 block products, symmetric streaming), "zgemm_ta", "zgemm_v"
+ * (complex64 block products of 8 and more right-hand sides, FP64 matrix
+ * cores), "dmatvec_lp", "dmatvec_gll", "dmatvec_gtp" (dense FP64 projector
+ * products), "spsolve_lp", "spsolve_gll", "spsolve_gtp" (sparse projector
+ * solves), "gemm_ta", "gemm_v" (BF16x3 products), "spd_inverse" (whole FP64
+ * inverse); a launch of k > 1 right-hand sides is timed as "<tag>_nr<k>"
+ * (every "zgemm" launch carries its suffix).  rfcmp_profile_enable
  * clears the records (waiting for recorded events first); rfcmp_profile_read
  * waits for the events of one tag and returns their summed duration and
  * count.  Adds two event records per timed launch.  Records from library

@@ -193,9 +193,9 @@ __device__ inline float2 b_entry(const Moments& M, float4 qi, float4 qj, float s
 // row cell is c- in a second (each entry of t1 or t2 has one contribution
 // per phase), and T_A = t1 + t2 -- the same pairing whatever the order of
 // the cell pairs.  A diagonal tile takes each unordered cell pair once and
-// adds it to (m, n) and (n, m) from the same registers; a tile pair inside
-// one diagonal kTriBlock block also writes its transpose: T_A is exactly
-// symmetric where it is stored.  Near cell pairs (the self pairs among them)
+// adds it to (m, n) and (n, m) from the same registers, and every other tile
+// pair writes its transpose too: T_A is stored whole and exactly
+// symmetric.  Near cell pairs (the self pairs among them)
 // take their blocks from k_near_pairs (NB, FP64 singular extraction, run
 // first) instead of the far rule: a tile pair that has near cell pairs
 // (tile_near) looks each of its cell pairs up in the sorted near partners of
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_ta(int N, const int* _
     if (m < N && n < N)
       TA[m * ldA + n] = make_float2(t1[r][c].x + t2[r][c].x, t1[r][c].y + t2[r][c].y);
   }
-  if (!diag && (I * kEdgeTile) / kTriBlock == (Jt * kEdgeTile) / kTriBlock) {
+  if (!diag) {  // the transpose: T_A is stored whole
     for (int e = tid; e < kEdgeTile * kEdgeTile; e += kAsmThreads) {
       const int c = e / kEdgeTile, r = e % kEdgeTile;
       const long m = (long)I * kEdgeTile + r, n = (long)Jt * kEdgeTile + c;

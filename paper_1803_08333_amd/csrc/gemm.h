@@ -22,4 +22,15 @@ size_t gemm_scratch_bytes(int64_t n, int nrhs);
 rfcmp_status gemm_bf16x3(const SplitMatrix& M, bool conj_m, const double2* X, double2* Y, int nrhs,
                          void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag);
 
+// FP64-accumulated complex products Y = M X (conj: conj(M) X) of a complex64
+// n x n matrix stored whole (row-major, ld a multiple of 4) with complex128
+// X, Y [nrhs][n], on the FP64 matrix cores (zgemm.hip): for many right-hand
+// sides, where they are bound by FP64 arithmetic.  Deterministic.
+size_t zgemm_scratch_bytes(int64_t n);
+rfcmp_status zgemm_c64(const float2* M, int64_t n, int64_t ld, bool conj, const double2* X, double2* Y, int nrhs,
+                       void* scratch, size_t scratch_bytes, hipStream_t s, const char* tag);
+// Right-hand sides from which the complex64 products take zgemm_c64 instead
+// of the symmetric streaming product.
+constexpr int kZgemmMinRhs = 8;
+
 }  // namespace rfcmp

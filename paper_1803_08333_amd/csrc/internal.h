@@ -221,9 +221,10 @@ struct rfcmp_mesh_s {
 };
 
 namespace rfcmp {
-// T_A is stored as the upper triangle of kTriBlock x kTriBlock blocks (row m
-// holds columns n >= kTriBlock floor(m / kTriBlock)); the rest of the buffer
-// is never written.
+// T_A and V are stored whole (both triangles, exactly symmetric).  The
+// symmetric streaming products read the upper triangle of kTriBlock x
+// kTriBlock blocks (row m, columns n >= kTriBlock floor(m / kTriBlock)); the
+// FP64 multi-right-hand-side products read every entry.
 constexpr int kTriBlock = 256;
 // Edges per tile of the T_A assembly (a divisor of kTriBlock).
 constexpr int kEdgeTile = 64;
@@ -248,6 +249,7 @@ struct rfcmp_op_s {
   double* host_scal_dev = nullptr;  // its device address
   std::unique_ptr<rfcmp::SplitMatrix> TA16, V16;  // BF16x3 planes (precision 1)
   rfcmp::DevBuf gemm_scratch;
+  rfcmp::DevBuf z_scratch;     // slice partials of the FP64 multi-RHS products
   rfcmp::DevBuf symv_scratch;  // partial sums of the symmetric products
   // CG iterations replayed as HIP graphs (one per parity of the iteration:
   // the recurrence scalars alternate between two buffers), run on an

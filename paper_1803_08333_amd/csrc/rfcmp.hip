@@ -112,6 +112,15 @@ rfcmp_status ensure_sp_scratch(rfcmp_op op) {
   return RFCMP_OK;
 }
 
+// Scratch of the FP64 multi-right-hand-side products (zgemm_c64): sized
+// for the larger block, T_A (n = N).
+rfcmp_status ensure_z_scratch(rfcmp_op op) {
+  const size_t need = zgemm_scratch_bytes(std::max(op->mesh->h.N, op->mesh->h.C));
+  if (op->z_scratch.bytes >= need) return RFCMP_OK;
+  if (op->z_scratch.p) RF_HIP(hipDeviceSynchronize());  // the old scratch may still be in use
+  return op->z_scratch.alloc(need);
+}
+
 // Grow the workspace (and pinned host scalars) to at least R right-hand sides.
 rfcmp_status ensure_work(rfcmp_op op, int R) {
   R = std::max(R, 4);
@@ -141,7 +150,7 @@ struct Dense {
   rfcmp_op op;
   hipStream_t s;
   bool bf16;
-  const Work* W = nullptr;  // workspace for formed inputs (BF16x3 path)
+  const Work* W = nullptr;  // workspace for formed inputs (BF16x3 and FP64 multi-RHS products)
 
   SymvJob job(Mat m, const SymvInput& in, double2* y) const {
     const MeshHost& h = op->mesh->h;
@@ -177,6 +186,22 @@ struct Dense {
     return t[m];
   }
   static bool complex_matrix(Mat m) { return m == kTA || m == kV; }
+  static const char* zgemm_tag(Mat m) { return m == kTA ? "zgemm_ta" : "zgemm_v"; }
+
+  // FP64-accumulated product on the FP64 matrix cores (many right-hand
+  // sides): form the input (unless plain) and run zgemm_c64.
+  rfcmp_status zgemm(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
+    const SymvJob j = job(m, in, y);
+    const double2* x = in.p[0];
+    if (in.mode != SymvInput::kPlain || in.stride[0] != j.n) {
+      double2* buf = j.n == op->mesh->h.N ? W->xN : W->xC;
+      RF_TRY(symv_form_input(in, j.n, nr, buf, s));
+      x = buf;
+    }
+    RF_TRY(ensure_z_scratch(op));
+    return zgemm_c64(static_cast<const float2*>(j.M), j.n, j.ld, conj, x, y, nr, op->z_scratch.p,
+                     op->z_scratch.bytes, s, zgemm_tag(m));
+  }
 
   // BF16x3: form the input (unless plain) and run the GEMM.
   rfcmp_status gemm(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
@@ -239,6 +264,7 @@ struct Dense {
   rfcmp_status prod(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
     if (sparse(m)) return sp_solve(m, in, y, nullptr, nullptr, nullptr, nr, 0);
     if (bf16 && complex_matrix(m)) return gemm(m, conj, in, y, nr);
+    if (complex_matrix(m) && nr >= kZgemmMinRhs && W) return zgemm(m, conj, in, y, nr);
     const SymvJob j = job(m, in, y);
     if (complex_matrix(m))
       return csymv_jobs(&j, 1, conj, nr, op->symv_scratch.p, op->symv_scratch.bytes, s, tag(m));
@@ -259,6 +285,10 @@ struct Dense {
     if (bf16 && complex_matrix(m0)) {
       RF_TRY(gemm(m0, conj, in0, y0, nr));
       return gemm(m1, conj, in1, y1, nr1 > 0 ? nr1 : nr);
+    }
+    if (complex_matrix(m0) && nr >= kZgemmMinRhs && W) {
+      RF_TRY(prod(m0, conj, in0, y0, nr));
+      return prod(m1, conj, in1, y1, nr1 > 0 ? nr1 : nr);
     }
     SymvJob j[2] = {job(m0, in0, y0), job(m1, in1, y1)};
     j[1].nrhs = nr1;
@@ -506,7 +536,7 @@ rfcmp_status power_scalings(rfcmp_op op, const double2* start, int steps, double
   const int64_t N = op->mesh->h.N;
   RF_TRY(ensure_work(op, 4));
   const Work W = carve(op);
-  const Dense D{op, s, false};
+  const Dense D{op, s, false, &W};
   for (int r = 0; r < 3; ++r)
     RF_HIP(hipMemcpyAsync(W.pw + r * N, start, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
   RF_TRY(normalize_rows(N, W.pw, W.pv, W.dout, 3, s));
@@ -670,6 +700,7 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
     mix((uint64_t)(uintptr_t)op->sp_scratch.p);
     mix((uint64_t)(uintptr_t)op->symv_scratch.p);
     mix((uint64_t)(uintptr_t)op->gemm_scratch.p);
+    mix((uint64_t)(uintptr_t)op->z_scratch.p);
     mix((uint64_t)(uintptr_t)hs_dev);
   }
   auto graph_for = [&](int c) -> rfcmp_status {
@@ -1391,7 +1422,7 @@ rfcmp_status rfcmp_precond_rhs(rfcmp_op op, const void* e, void* b, int32_t nrhs
   hipStream_t s = static_cast<hipStream_t>(stream);
   RF_TRY(ensure_work(op, std::min(nrhs, 64)));
   const Work W = carve(op);
-  const Dense D{op, s, false};
+  const Dense D{op, s, false, &W};
   return batched(nrhs, W.R, N, N, static_cast<const double2*>(e), static_cast<double2*>(b),
                  [&](const double2* x, double2* y, int nr) { return rhs_batch(D, W, x, y, nr); });
 }
@@ -1403,7 +1434,7 @@ rfcmp_status rfcmp_apply(rfcmp_op op, const void* x, void* y, int32_t nrhs, void
   hipStream_t s = static_cast<hipStream_t>(stream);
   RF_TRY(ensure_work(op, std::min(nrhs, 64)));
   const Work W = carve(op);
-  const Dense D{op, s, false};
+  const Dense D{op, s, false, &W};
   return batched(nrhs, W.R, N, N, static_cast<const double2*>(x), static_cast<double2*>(y),
                  [&](const double2* a, double2* b, int nr) { return apply_batch(D, W, a, b, nr); });
 }
@@ -1415,7 +1446,7 @@ rfcmp_status rfcmp_recover(rfcmp_op op, const void* i, void* j, int32_t nrhs, vo
   hipStream_t s = static_cast<hipStream_t>(stream);
   RF_TRY(ensure_work(op, std::min(nrhs, 64)));
   const Work W = carve(op);
-  const Dense D{op, s, false};
+  const Dense D{op, s, false, &W};
   return batched(nrhs, W.R, N, N, static_cast<const double2*>(i), static_cast<double2*>(j),
                  [&](const double2* a, double2* b, int nr) { return recover_batch(D, W, a, b, nr); });
 }
@@ -1471,6 +1502,13 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double2* xx = static_cast<const double2*>(x);
   double2* yy = static_cast<double2*>(y);
+  if (which <= 1 && nrhs >= kZgemmMinRhs) {
+    RF_TRY(ensure_z_scratch(op));
+    return which == 0 ? zgemm_c64(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, xx, yy, nrhs,
+                                  op->z_scratch.p, op->z_scratch.bytes, s, "zgemm_ta")
+                      : zgemm_c64(op->Vb.as<float2>(), op->mesh->h.C, op->ldV, conj != 0, xx, yy, nrhs,
+                                  op->z_scratch.p, op->z_scratch.bytes, s, "zgemm_v");
+  }
   if (which == 0)
     return csymv(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, xx, yy, nrhs, op->symv_scratch.p,
                  op->symv_scratch.bytes, s, "cmatvec_ta");

@@ -1,9 +1,10 @@
 """Element-wise parity at the bench's full sizes, for the kernels it times.
 
 The level-4 sphere (N = 7680, C = 5120) takes the 256-wide symmetric-block
-products (chosen above n = 6912), the paired T_A + V launches of the operator
-and the power iteration, and the level-5 sphere with 64 right-hand sides the
-BF16x3 GEMM at the precision study's shape.  References:
+products (chosen above n = 6912), the FP64 matrix-core products of 8 and
+more right-hand sides, the paired T_A + V launches of the operator and the
+power iteration, and the level-5 sphere with 64 right-hand sides the BF16x3
+GEMM at the precision study's shape.  References:
 * dense complex128 products of the exported complex64 blocks (exact
   conversion; only the summation order differs: 1e-13);
 * the FP64 oracle's preconditioner built on the exported blocks, for the
@@ -66,12 +67,15 @@ def _ico4_op(k):
     return op, gTA, gV, pre
 
 
-@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 5, 8, 13, 16, 21])
 @pytest.mark.parametrize("conj", [False, True])
 def test_symv_256_blocks_match_complex128(nrhs, conj):
     """rfcmp_matvec which 0 (T_A, n = 7680) and 1 (V, n = 5120) at level 4:
-    1 to 5 right-hand sides (the 4 + 1 split included), with and without
-    conjugation, against complex128 products of the exported blocks."""
+    1 to 5 right-hand sides on the symmetric streaming products (the 4 + 1
+    split included), 8 and more on the FP64 matrix-core products (16 per
+    pass: 13 and 21 leave a ragged group; they read the lower triangle that
+    the symmetric products never do), with and without conjugation, against
+    complex128 products of the exported blocks."""
     torch, rf = _gpu()
     op, gTA, gV, _ = _ico4_op(1.0)
     for which, M in ((0, gTA), (1, gV)):
