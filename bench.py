@@ -166,32 +166,34 @@ def copy_calibration():
 BF16_MFMA_TFLOPS = 2500.0
 
 # HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
-# KiB per dispatch, mean over the dispatches of the tag's kernel), each scaled
-# by what the same counter reads for a plain 1 GiB device copy (FETCH_SIZE
-# reads 2^19 KiB for 2^30 bytes fetched: scale 2.0; WRITE_SIZE reads 2^20
-# KiB: scale 1.0), per workload.  Valid only for the kernel source they were
-# taken on: reported as null once that file changes.
+# KiB per dispatch, mean over the dispatches of the tag's kernel and grid),
+# each scaled by what the same counter reads for a plain 1 GiB device copy
+# (FETCH_SIZE reads 2^19 KiB for 2^30 bytes fetched: scale 2.0; WRITE_SIZE
+# reads 2^20 KiB: scale 1.0), per workload and tag.  Valid only for the
+# kernel source they were taken on: reported as null once that file changes.
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
-    "icosphere4_two_k": {
-        "source": "paper_1803_08333_amd/csrc/symv.hip",
-        "sha256": "cbdcf6878b657550db4fe78b3d29caab17a48ac76d3c03b83ba5c46ee919e29a",
-        "kib": {"cmatvec_ta+v": (174943.0, 5200.1), "cmatvec_ta+v_nr2": (174225.0, 8800.1),
-                "dmatvec_lp": (53270.9, 3200.0), "dmatvec_lp_nr2": (53999.6, 6400.0),
-                "dmatvec_lp+gll": (67984.1, 4082.0)}},
+    "icosphere5_64rhs": {
+        "gemm_ta": {"source": "paper_1803_08333_amd/csrc/gemm.hip",
+                    "sha256": "450c66db74a7d5f462a93ac6c43010f7b3656a4dd70d11335761f4bb44e1ced2",
+                    "kib": (3747945.3, 30720.0)},
+        "zgemm_ta_nr16": {"source": "paper_1803_08333_amd/csrc/zgemm.hip",
+                          "sha256": "b5664302b0462033016131216b3dbd3467828f3d930645ce8018e85d147c534d",
+                          "kib": (3874426.7, 38400.0)},
+    },
 }
 
 
 def measured_traffic(tag, workload):
     import hashlib
-    t = TRAFFIC.get(workload)
-    if t is None or tag not in t["kib"]:
+    t = TRAFFIC.get(workload, {}).get(tag)
+    if t is None:
         return None
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
             return None
-    fk, wk = t["kib"][tag]
+    fk, wk = t["kib"]
     return 1024.0 * (fk * TRAFFIC_SCALE["fetch"] + wk * TRAFFIC_SCALE["write"])
 
 
