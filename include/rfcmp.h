@@ -154,13 +154,17 @@ typedef struct {
                              0 = automatic (default): 1 when C > 12288 (where the
                                  cubic set-up of 2 dominates), else 2 (one streaming
                                  pass over a small inverse beats a sparse solve) */
-  int32_t graphs;         /* 1 (default): from its third iteration on, each CG
-                             iteration is replayed as a HIP graph captured once
-                             per operator (two graphs: the recurrence scalars
+  int32_t graphs;         /* 1: from its third iteration on, each CG iteration
+                             is replayed as a HIP graph captured once per
+                             operator (two graphs: the recurrence scalars
                              alternate between two buffers) on an internal
-                             stream; 0: every kernel launched one by one.
-                             Results are bit-identical either way.  Not used
-                             while kernel timing (rfcmp_profile_enable) is on. */
+                             stream; 0 (default): every kernel launched one by
+                             one.  Results are bit-identical either way.  The
+                             replay saves no time on this hardware at the sizes
+                             measured, and the two captures per operator cost
+                             about 4 ms, which a batch of many small operators
+                             pays many times over.  Not used while kernel timing
+                             (rfcmp_profile_enable) is on. */
 } rfcmp_options;
 rfcmp_status rfcmp_options_default(rfcmp_options* opt);
 
@@ -172,12 +176,15 @@ typedef struct rfcmp_op_s* rfcmp_op;
  *   V[c,c']  = (A_c A_c')^-1 int_c int_c' G_k dS dS'     (complex64, C x C)
  * with G_k = exp(ikR)/(4 pi R), so T_Phi = Sigma V Sigma^T.  Far pairs use the
  * 7x7-point rule in FP32; near pairs (see rfcmp_mesh_near_pairs) extract the
- * 1/R singularity in closed form in FP64.  On the first call for a mesh the
- * projector matrices (L^+ = (Sigma^T Sigma)^+, G_ll^-1, and for outer_star = 1
- * G_tp^-1) are built on the device in FP64 and cached on the mesh; so are
- * the near-pair list and the cell-pair scratch of the assembly (complex64
- * [3C][3C], 72 C^2 bytes), freed with the mesh.  Returns after the
- * operator's work on `stream` is complete.
+ * 1/R singularity in closed form in FP64.  T_A is formed tile by tile from
+ * the cell pairs of each pair of 64-edge tiles and stored whole (both
+ * triangles, exactly symmetric); the assembly needs no scratch beyond its
+ * near-pair blocks (complex64, 72 bytes per near pair).  On the first call
+ * for a mesh the projectors (sparse FP64 Cholesky factors of
+ * Sigma^T Sigma, G_ll and, for outer_star = 1, G_tp, or their dense FP64
+ * inverses: see rfcmp_options.projector) are set up on the device and
+ * cached on the mesh, as is the near-pair list; they are freed with the
+ * mesh.  Returns after the operator's work on `stream` is complete.
  * power_start: device c128 [N], the start vector of the power iterations
  * that estimate alpha, beta, gamma (Sec. 4); required when opt->scaling == 0,
  * ignored otherwise.  opt may be NULL (defaults).  The mesh must outlive the
@@ -265,7 +272,8 @@ rfcmp_status rfcmp_rhs_gap(rfcmp_mesh m, const int32_t* edges, const void* volts
  * the accuracy follows the solve's: with tol = 1e-8 the sphere's RCS stays
  * within 0.5 % of Mie (level 4) down to ka = 1e-10; lower, the small
  * Helmholtz block of the system's right-hand side falls below the global
- * residual tolerance.
+ * residual tolerance (the split path, rfcmp_rhs_planewave_split,
+ * rfcmp_solve_split and rfcmp_farfield_split, keeps it down to 1e-25 Hz).
  * j: device c128 [nrhs][N]; dirs: host double [ndir][3], unit vectors
  * (1e-12); F: device c128 [nrhs][ndir][3]; rcs: device double [nrhs][ndir],
  * nullable.  Waits for the stream before returning. */

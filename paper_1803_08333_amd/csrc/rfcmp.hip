@@ -1135,12 +1135,18 @@ rfcmp_status rfcmp_mesh_create(const double* xyz, int64_t nv, const int32_t* tri
     m->near_async_factor = -1.0;  // computed when first needed
   }
   // the sparse factors of L and G_ll on two more host threads (joined when
-  // an operator first needs them)
-  try {
-    const MeshHost* hp = &m->h;
-    for (int q = 0; q < 2; ++q) m->fac_async[q] = std::async(std::launch::async, [hp, q]() { return factor_mesh_matrix(*hp, q); });
-  } catch (const std::exception&) {
-    // factored on the calling thread when first needed
+  // an operator first needs them), where the automatic projector choice
+  // takes them; for smaller meshes they are factored on the calling thread
+  // if an operator asks for them, so that the host threads of a batch of
+  // small meshes do not compete with the threads that drive its solves
+  if (m->h.C > kAutoSparseCells) {
+    try {
+      const MeshHost* hp = &m->h;
+      for (int q = 0; q < 2; ++q)
+        m->fac_async[q] = std::async(std::launch::async, [hp, q]() { return factor_mesh_matrix(*hp, q); });
+    } catch (const std::exception&) {
+      // factored on the calling thread when first needed
+    }
   }
   *out = m.release();
   return RFCMP_OK;
@@ -1202,7 +1208,7 @@ rfcmp_status rfcmp_options_default(rfcmp_options* o) {
   o->power_tol = 1e-2;
   o->streams = kBatchStreams;
   o->projector = 0;
-  o->graphs = 1;
+  o->graphs = 0;
   return RFCMP_OK;
 }
 

@@ -1,5 +1,5 @@
-"""CG iterations replayed as HIP graphs (options.graphs = 1, the default)
-against the same iterations launched kernel by kernel (graphs = 0): the
+"""CG iterations replayed as HIP graphs (options.graphs = 1) against the
+same iterations launched kernel by kernel (graphs = 0, the default): the
 results and reports must be bit-identical, on both precision paths, across
 repeated solves on one operator (graph reuse), after new scalings and with a
 different number of right-hand sides (recapture)."""
