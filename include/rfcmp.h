@@ -165,6 +165,20 @@ typedef struct {
                              about 4 ms, which a batch of many small operators
                              pays many times over.  Not used while kernel timing
                              (rfcmp_profile_enable) is on. */
+  double aca_tol;         /* 0 (default): T_A and V stored dense.  > 0: T_A and V
+                             compressed separately (the compression of Sec. 4's
+                             large example) as hierarchical matrices: RWG edges
+                             clustered by bisection into tiles of 64, pairs of
+                             clusters whose boxes are at least the near distance
+                             apart and min(diam) <= 2 x their distance stored as
+                             low-rank factors from adaptive cross approximation
+                             (partial pivoting, stopped when the new term's
+                             Frobenius norm is at most aca_tol times the
+                             approximation's), the other pairs of tiles dense;
+                             storage O(N log N) for a fixed wavenumber.  Needs
+                             precision 0; rfcmp_op_export writes the compressed
+                             blocks out dense.  RFCMP_E_STATE if a block needs a
+                             rank above 128. */
 } rfcmp_options;
 rfcmp_status rfcmp_options_default(rfcmp_options* opt);
 
@@ -213,6 +227,15 @@ rfcmp_status rfcmp_op_power_steps(rfcmp_op op, int32_t* steps);
 /* Copy the blocks to caller device buffers: TA c64 [N][N], V c64 [C][C]
  * (either nullable). */
 rfcmp_status rfcmp_op_export(rfcmp_op op, void* TA, void* V, void* stream);
+/* Storage of an operator's compressed blocks (options.aca_tol > 0; Sec. 4):
+ * complex64 entries of the dense blocks (pairs of 64-edge tiles of T_A and
+ * the matching cell blocks of V) and of the low-rank factors (k (m + n) per
+ * m x n block of rank k), the number of low-rank blocks of each matrix
+ * (T_A and V have the same partition), and the largest and the mean rank
+ * over both matrices.  Every output nullable.  RFCMP_E_STATE for an operator
+ * with dense blocks.  Host call. */
+rfcmp_status rfcmp_op_compression(rfcmp_op op, int64_t* dense_entries, int64_t* lowrank_entries,
+                                  int32_t* lowrank_blocks, int32_t* max_rank, double* mean_rank);
 void rfcmp_op_destroy(rfcmp_op op);
 
 /* Plane-wave excitation e_m = int f_m . pol exp(i k khat.r) dS (Sec. 2),
@@ -408,7 +431,8 @@ rfcmp_status rfcmp_batch_solve(const rfcmp_op* ops, int32_t nops, const void* co
  * "assemble_ta", "near_pairs" (assembly), "cmatvec_ta", "cmatvec_v"
  * (complex64 block products, symmetric streaming), "zgemm_ta", "zgemm_v"
  * (complex64 block products of 8 and more right-hand sides, FP64 matrix
- * cores), "dmatvec_lp", "dmatvec_gll", "dmatvec_gtp" (dense FP64 projector
+ * cores), "hm_dense", "hm_aca_ta", "hm_aca_v", "hm_matvec_ta", "hm_matvec_v"
+ * (compressed blocks: dense tiles, ACA, products), "dmatvec_lp", "dmatvec_gll", "dmatvec_gtp" (dense FP64 projector
  * products), "spsolve_lp", "spsolve_gll", "spsolve_gtp" (sparse projector
  * solves), "gemm_ta", "gemm_v" (BF16x3 products), "spd_inverse" (whole FP64
  * inverse); a launch of k > 1 right-hand sides is timed as "<tag>_nr<k>"

@@ -58,7 +58,8 @@ class Options(ctypes.Structure):
     _fields_ = [("near_factor", ctypes.c_double), ("outer_star", ctypes.c_int32),
                 ("scaling", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("power_tol", ctypes.c_double),
-                ("streams", ctypes.c_int32), ("projector", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("projector", ctypes.c_int32), ("graphs", ctypes.c_int32),
+                ("aca_tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -99,6 +100,7 @@ EXPORTED = {
     "rfcmp_op_set_scalings": (_I32, [_P, _D, _D, _D]),
     "rfcmp_op_power_steps": (_I32, [_P, _PI32]),
     "rfcmp_op_export": (_I32, [_P, _P, _P, _P]),
+    "rfcmp_op_compression": (_I32, [_P, _PI64, _PI64, _PI32, _PI32, _PD]),
     "rfcmp_op_destroy": (None, [_P]),
     "rfcmp_rhs_planewave": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
     "rfcmp_rhs_planewave_noalloc": (_I32, [_P, _PD, _PD, _I32, _P, _P]),
@@ -387,6 +389,16 @@ class Operator:
         V = torch.empty((C, C), dtype=torch.complex64, device="cuda")
         _check(lib.rfcmp_op_export(self.handle, _dptr(TA), _dptr(V), _stream()))
         return TA, V
+
+    def compression(self):
+        """rfcmp_op_compression: storage of the compressed blocks (dict)."""
+        de, le = _I64(), _I64()
+        nb, mx = _I32(), _I32()
+        mean = _D()
+        _check(lib.rfcmp_op_compression(self.handle, ctypes.byref(de), ctypes.byref(le), ctypes.byref(nb),
+                                        ctypes.byref(mx), ctypes.byref(mean)))
+        return {"dense_entries": de.value, "lowrank_entries": le.value, "lowrank_blocks": nb.value,
+                "max_rank": mx.value, "mean_rank": mean.value}
 
     def rhs_planewave(self, khat, pol):
         torch = _torch()

@@ -25,162 +25,13 @@
 #include <mutex>
 #include <vector>
 
+#include "farpair.h"
+#include "hmat.h"
 #include "internal.h"
 
 namespace rfcmp {
 
 namespace {
-
-constexpr int kQ = 7;
-
-// Radon's 7-point degree-5 rule (Stroud T2:5-1): centroid and two orbits.
-struct Rule {
-  double bary[kQ][3];
-  double w[kQ];
-};
-Rule make_rule() {
-  Rule r;
-  const double s = std::sqrt(15.0);
-  const double a1 = (6.0 - s) / 21.0, b1 = (9.0 + 2.0 * s) / 21.0;
-  const double a2 = (6.0 + s) / 21.0, b2 = (9.0 - 2.0 * s) / 21.0;
-  const double w0 = 9.0 / 40.0, w1 = (155.0 - s) / 1200.0, w2 = (155.0 + s) / 1200.0;
-  const double P[kQ][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a1, a1, b1}, {a1, b1, a1}, {b1, a1, a1},
-                           {a2, a2, b2}, {a2, b2, a2}, {b2, a2, a2}};
-  const double W[kQ] = {w0, w1, w1, w1, w2, w2, w2};
-  for (int q = 0; q < kQ; ++q) {
-    for (int d = 0; d < 3; ++d) r.bary[q][d] = P[q][d];
-    r.w[q] = W[q];
-  }
-  return r;
-}
-
-struct RuleArgs {
-  float wf[kQ];
-  double wd[kQ];
-  double bary[kQ][3];
-};
-
-// ---------------------------------------------------------------- far pairs
-// sin and cos of a moderate argument in FP32: Cody-Waite reduction by pi/2
-// (two-term split of pi/2, one rounding per step) to |r| <= pi/4, then the
-// Taylor series of sin to r^9 and of cos to r^8 (truncation below 3e-8), and
-// the quadrant rotation.  Keeps full relative accuracy as x -> 0, which the
-// imaginary part of G_k needs at low frequency.
-constexpr float kPio2Hi = (float)1.57079632679489661923;
-constexpr float kPio2Lo = (float)(1.57079632679489661923 - (double)kPio2Hi);
-constexpr float k2OverPi = (float)0.63661977236758134308;
-
-__device__ inline void sincos_moderate(float x, float& sn, float& cs) {
-  const float n = rintf(x * k2OverPi);
-  float r = fmaf(-n, kPio2Hi, x);
-  r = fmaf(-n, kPio2Lo, r);
-  const float r2 = r * r;
-  float ps = fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
-  ps = fmaf(r2, ps, 1.0f / 120.0f);
-  ps = fmaf(r2, ps, -1.0f / 6.0f);
-  const float s = fmaf(r * r2, ps, r);
-  float pc = fmaf(r2, 1.0f / 40320.0f, -1.0f / 720.0f);
-  pc = fmaf(r2, pc, 1.0f / 24.0f);
-  pc = fmaf(r2, pc, -0.5f);
-  const float c = fmaf(r2, pc, 1.0f);
-  const int q = ((int)n) & 3;
-  const float s1 = (q & 1) ? c : s;
-  const float c1 = (q & 1) ? s : c;
-  sn = (q & 2) ? -s1 : s1;
-  cs = ((q + 1) & 2) ? -c1 : c1;
-}
-
-// sin and cos of kR come from the polynomial above, or, when kR <= 2 over the
-// whole mesh (HW), from the transcendental unit (v_sin_f32 / v_cos_f32 take
-// the argument in revolutions).  Measured on the device against double
-// precision for |x| < 2: sin within 1e-6 relative (also as x -> 0), cos
-// within 2.1e-7 absolute; beyond 2 the revolution product loses absolute
-// accuracy (7e-7 up to 10), so larger kR keeps the reduced polynomial.
-// Normalised moments of one far cell pair (c, c') (see above), scaled by
-// 1/(4 pi): I_0, I_r (over c), I_r' (over c'), I_rr'.
-struct Moments {
-  float i0r, i0i, irr[3], iri[3], jrr[3], jri[3], kr, ki;
-};
-
-// qa: the 7 points of c minus its centroid, qb those of c'; (dx, dy, dz) =
-// x_c - x_c' (formed in FP64 by the caller).
-template <bool HW>
-__device__ inline void far_moments(const float4* qa, const float4* qb, float dx, float dy, float dz,
-                                   const RuleArgs& rule, float kk, Moments& M) {
-  float bq[kQ][3], wq[kQ];
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const float4 b = qb[q];
-    bq[q][0] = b.x; bq[q][1] = b.y; bq[q][2] = b.z;
-    wq[q] = rule.wf[q];
-  }
-  float i0r = 0, i0i = 0;
-  float irr[3] = {0, 0, 0}, iri[3] = {0, 0, 0};
-  float jrr[3] = {0, 0, 0}, jri[3] = {0, 0, 0};
-  float kr = 0, ki = 0;
-#pragma unroll 1
-  for (int p = 0; p < kQ; ++p) {
-    const float4 a = qa[p];
-    const float bx = dx + a.x, by = dy + a.y, bz = dz + a.z;
-    float s0r = 0, s0i = 0, s1r[3] = {0, 0, 0}, s1i[3] = {0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const float rx = bx - bq[q][0], ry = by - bq[q][1], rz = bz - bq[q][2];
-      const float R2 = rx * rx + ry * ry + rz * rz;
-      const float rinv = __frsqrt_rn(R2);
-      const float R = R2 * rinv;
-      float sn, cs;
-      if (HW) {  // the transcendental unit, argument in revolutions (kR <= 2 here)
-        const float rev = kk * R * 0.159154943091895336f;
-        sn = __builtin_amdgcn_sinf(rev);
-        cs = __builtin_amdgcn_cosf(rev);
-      } else {
-        sincos_moderate(kk * R, sn, cs);
-      }
-      const float g = wq[q] * rinv;
-      const float gr = cs * g, gi = sn * g;
-      s0r += gr;
-      s0i += gi;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        s1r[d] += bq[q][d] * gr;
-        s1i[d] += bq[q][d] * gi;
-      }
-    }
-    const float wp = rule.wf[p];
-    i0r += wp * s0r;
-    i0i += wp * s0i;
-    irr[0] += wp * a.x * s0r; iri[0] += wp * a.x * s0i;
-    irr[1] += wp * a.y * s0r; iri[1] += wp * a.y * s0i;
-    irr[2] += wp * a.z * s0r; iri[2] += wp * a.z * s0i;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      jrr[d] += wp * s1r[d];
-      jri[d] += wp * s1i[d];
-    }
-    kr += wp * (a.x * s1r[0] + a.y * s1r[1] + a.z * s1r[2]);
-    ki += wp * (a.x * s1i[0] + a.y * s1i[1] + a.z * s1i[2]);
-  }
-  const float inv4pi = 0.0795774715459476679f;  // 1/(4 pi)
-  M.i0r = i0r * inv4pi; M.i0i = i0i * inv4pi; M.kr = kr * inv4pi; M.ki = ki * inv4pi;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    M.irr[d] = irr[d] * inv4pi; M.iri[d] = iri[d] * inv4pi;
-    M.jrr[d] = jrr[d] * inv4pi; M.jri[d] = jri[d] * inv4pi;
-  }
-}
-
-// B[(c,i),(c',j)] = sigma_i sigma_j / 4 (I_rr' - q_i.I_r' - q'_j.(I_r - q_i I_0))
-// with q_i = vertex i of c minus its centroid, q'_j the same for c'.
-__device__ inline float2 b_entry(const Moments& M, float4 qi, float4 qj, float si, float sj) {
-  const float tr = M.kr - (qi.x * M.jrr[0] + qi.y * M.jrr[1] + qi.z * M.jrr[2]);
-  const float tim = M.ki - (qi.x * M.jri[0] + qi.y * M.jri[1] + qi.z * M.jri[2]);
-  const float ur0 = M.irr[0] - qi.x * M.i0r, ur1 = M.irr[1] - qi.y * M.i0r, ur2 = M.irr[2] - qi.z * M.i0r;
-  const float ui0 = M.iri[0] - qi.x * M.i0i, ui1 = M.iri[1] - qi.y * M.i0i, ui2 = M.iri[2] - qi.z * M.i0i;
-  const float f = 0.25f * si * sj;
-  return make_float2(f * (tr - (qj.x * ur0 + qj.y * ur1 + qj.z * ur2)),
-                     f * (tim - (qj.x * ui0 + qj.y * ui1 + qj.z * ui2)));
-}
 
 // ---------------------------------------------------------------- T_A tiles
 // One workgroup per pair of edge tiles (I <= J, kEdgeTile consecutive edges
@@ -228,12 +79,24 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_ta(int N, const int* _
                                                              const int* __restrict__ np_code,
                                                              const float2* __restrict__ NB,
                                                              float2* __restrict__ TA, long ldA,
-                                                             float2* __restrict__ Vm, long ldV) {
+                                                             float2* __restrict__ Vm, long ldV,
+                                                             const int2* __restrict__ lst,
+                                                             const long* __restrict__ vdoff,
+                                                             const int* __restrict__ cstart,
+                                                             const int* __restrict__ ipc,
+                                                             const float2* __restrict__ NV) {
   const long t = blockIdx.x;
-  long J = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while (J * (J + 1) / 2 > t) --J;
-  while ((J + 1) * (J + 2) / 2 <= t) ++J;
-  const int I = (int)(t - J * (J + 1) / 2), Jt = (int)J;
+  int I, Jt;
+  if (lst) {  // list mode: the dense blocks of a compressed operator
+    I = lst[t].x;
+    Jt = lst[t].y;
+  } else {
+    long J = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (J * (J + 1) / 2 > t) --J;
+    while ((J + 1) * (J + 2) / 2 <= t) ++J;
+    I = (int)(t - J * (J + 1) / 2);
+    Jt = (int)J;
+  }
   extern __shared__ __align__(16) unsigned char smem[];
   float2(*t1)[kEdgeTile] = reinterpret_cast<float2(*)[kEdgeTile]>(smem);
   float2(*t2)[kEdgeTile] = reinterpret_cast<float2(*)[kEdgeTile]>(smem + sizeof(float2) * kEdgeTile * kEdgeTile);
@@ -265,7 +128,12 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_ta(int N, const int* _
   __syncthreads();
   const CellL* cI = cl;
   const CellL* cJ = diag ? cl : cl + nI;
-  const bool any_near = tile_near[t] != 0;
+  const bool any_near = lst ? true : tile_near[t] != 0;
+  // list mode: V entries of the home cells of I and J, into the block's
+  // own dense V block (rows the cells homed in I, columns those in J)
+  const long vbase = lst ? vdoff[t] : 0;
+  const int vcI = lst ? cstart[I] : 0, vcJ = lst ? cstart[Jt] : 0;
+  const int vnJ = lst ? cstart[Jt + 1] - vcJ : 0;
   const int total = nI * nJ;
   for (int base = 0; base < total; base += kAsmThreads) {
     const int p = base + tid;
@@ -299,14 +167,26 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_ta(int N, const int* _
         for (int i = 0; i < 3; ++i)
 #pragma unroll
           for (int j = 0; j < 3; ++j) bv[i][j] = nb[(code & 1) ? 3 * j + i : 3 * i + j];
+        if (lst && A.home == I && Bc.home == Jt) {
+          const float2 v = NV[code >> 1];
+          const int la = ipc[A.gid] - vcI, lb = ipc[Bc.gid] - vcJ;
+          Vm[vbase + (long)la * vnJ + lb] = v;
+          if (diag) Vm[vbase + (long)lb * vnJ + la] = v;
+        }
       } else {
         Moments M;
         far_moments<HW>(A.q, Bc.q, (float)(A.cen[0] - Bc.cen[0]), (float)(A.cen[1] - Bc.cen[1]),
                         (float)(A.cen[2] - Bc.cen[2]), rule, kk, M);
         if (A.home == I && Bc.home == Jt) {
           const float2 v = make_float2(M.i0r, M.i0i);
-          Vm[(long)A.gid * ldV + Bc.gid] = v;
-          Vm[(long)Bc.gid * ldV + A.gid] = v;
+          if (lst) {
+            const int la = ipc[A.gid] - vcI, lb = ipc[Bc.gid] - vcJ;
+            Vm[vbase + (long)la * vnJ + lb] = v;
+            if (diag) Vm[vbase + (long)lb * vnJ + la] = v;
+          } else {
+            Vm[(long)A.gid * ldV + Bc.gid] = v;
+            Vm[(long)Bc.gid * ldV + A.gid] = v;
+          }
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -349,6 +229,14 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_ta(int N, const int* _
       }
       __syncthreads();
     }
+  }
+  if (lst) {  // the tile as it is (both triangles for a diagonal tile; zero beyond N)
+    float2* out = TA + t * (long)(kEdgeTile * kEdgeTile);
+    for (int e = tid; e < kEdgeTile * kEdgeTile; e += kAsmThreads) {
+      const int r = e / kEdgeTile, c = e % kEdgeTile;
+      out[e] = make_float2(t1[r][c].x + t2[r][c].x, t1[r][c].y + t2[r][c].y);
+    }
+    return;
   }
   for (int e = tid; e < kEdgeTile * kEdgeTile; e += kAsmThreads) {
     const int r = e / kEdgeTile, c = e % kEdgeTile;
@@ -430,7 +318,8 @@ __global__ __launch_bounds__(128) void k_near_pairs(long npairs, const int* __re
                                                     const double* __restrict__ area,
                                                     const float* __restrict__ sgn, double kk,
                                                     RuleArgs rule, float2* __restrict__ NB,
-                                                    float2* __restrict__ Vm, long ldV) {
+                                                    float2* __restrict__ Vm, long ldV,
+                                                    float2* __restrict__ NV) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= npairs) return;
   const int c = pairs[2 * t], cp = pairs[2 * t + 1];
@@ -507,8 +396,12 @@ __global__ __launch_bounds__(128) void k_near_pairs(long npairs, const int* __re
       }
   }
   const float2 v = make_float2((float)vr, (float)vi);
-  Vm[(long)c * ldV + cp] = v;
-  Vm[(long)cp * ldV + c] = v;
+  if (NV) {  // compressed operator: V of the pair, placed by the tile kernel
+    NV[t] = v;
+  } else {
+    Vm[(long)c * ldV + cp] = v;
+    Vm[(long)cp * ldV + c] = v;
+  }
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) NB[t * 9 + 3 * i + j] = make_float2((float)br[i][j], (float)bi[i][j]);
 }
@@ -644,6 +537,9 @@ __global__ __launch_bounds__(256) void k_farfield(int C, int N, int ndir, const 
   }
 }
 
+
+}  // namespace
+
 RuleArgs rule_args() {
   static const Rule r = make_rule();
   RuleArgs a;
@@ -654,8 +550,6 @@ RuleArgs rule_args() {
   }
   return a;
 }
-
-}  // namespace
 
 rfcmp_status mesh_upload(rfcmp_mesh m, hipStream_t s) {
   const MeshHost& h = m->h;
@@ -722,7 +616,8 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   MeshDev& d = m->d;
   const int64_t N = h.N;
   const RuleArgs ra = rule_args();
-  RF_HIP(hipMemsetAsync(op->Vb.p, 0, op->Vb.bytes, s));
+  HmOp* hm = op->hm.get();
+  if (!hm) RF_HIP(hipMemsetAsync(op->Vb.p, 0, op->Vb.bytes, s));
 
   // far pairs first: they do not need the near-pair list, which a new mesh
   // may still be computing on a host thread
@@ -777,12 +672,37 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
     d.near_factor = op->opt.near_factor;
   }
   const long npairs = (long)d.npairs;
+  if (hm) RF_TRY(hm->NV.alloc(sizeof(float2) * std::max<long>(npairs, 1)));
   if (npairs > 0) {
     ProfScope prof("near_pairs", s);
     hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, s, npairs,
                        d.near.as<int>(), d.vtx.as<double>(), d.area.as<double>(), d.sgn.as<float>(), op->k, ra,
-                       d.nearB.as<float2>(), op->Vb.as<float2>(), (long)op->ldV);
+                       d.nearB.as<float2>(), hm ? nullptr : op->Vb.as<float2>(), (long)op->ldV,
+                       hm ? hm->NV.as<float2>() : nullptr);
     RF_HIP(hipGetLastError());
+  }
+  if (hm) {
+    // compressed: the dense blocks (pairs of tiles of the permuted order),
+    // then ACA of the low-rank blocks
+    const HmMesh& H = *m->hm;
+    const int64_t nd = (int64_t)H.t.dense_I.size();
+    RF_TRY(hm->TAd.alloc(sizeof(float2) * kEdgeTile * kEdgeTile * std::max<int64_t>(nd, 1)));
+    RF_TRY(hm->Vd.alloc(sizeof(float2) * std::max<int64_t>(H.vd_total, 1)));
+    RF_HIP(hipMemsetAsync(hm->Vd.p, 0, hm->Vd.bytes, s));
+    if (nd > 0) {
+      ProfScope prof("hm_dense", s);
+      const size_t lds = 2 * sizeof(float2) * kEdgeTile * kEdgeTile + 2 * sizeof(CellL) * (size_t)H.t.et_cells_max;
+      hipLaunchKernelGGL(hw ? k_assemble_ta<true> : k_assemble_ta<false>, dim3((unsigned)nd), dim3(kAsmThreads),
+                         lds, s, (int)N, H.et_ptr.as<int>(), H.et_cell.as<int>(), H.et_rows.as<int>(),
+                         H.home.as<int>(), d.cen.as<double>(), d.qoff.as<float4>(), d.fvoff.as<float4>(),
+                         d.sgn.as<float>(), (float)op->k, ra, (const uint8_t*)nullptr, d.np_ptr.as<int>(),
+                         d.np_other.as<int>(), d.np_code.as<int>(), d.nearB.as<float2>(), hm->TAd.as<float2>(),
+                         (long)kEdgeTile, hm->Vd.as<float2>(), 0L, H.dense_ij.as<int2>(), H.vd_off.as<long>(),
+                         H.cell_start.as<int>(), H.iperm_c.as<int>(), hm->NV.as<float2>());
+      RF_HIP(hipGetLastError());
+    }
+    hm->dense_entries = nd * kEdgeTile * kEdgeTile + H.vd_total;
+    return hm_aca(op, hw, s);
   }
   {
     ProfScope prof("assemble_ta", s);
@@ -792,7 +712,8 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
                        d.cell_home.as<int>(), d.cen.as<double>(), d.qoff.as<float4>(), d.fvoff.as<float4>(),
                        d.sgn.as<float>(), (float)op->k, ra, d.tile_near.as<uint8_t>(), d.np_ptr.as<int>(),
                        d.np_other.as<int>(), d.np_code.as<int>(), d.nearB.as<float2>(), op->TA.as<float2>(),
-                       (long)op->ldA, op->Vb.as<float2>(), (long)op->ldV);
+                       (long)op->ldA, op->Vb.as<float2>(), (long)op->ldV, (const int2*)nullptr,
+                       (const long*)nullptr, (const int*)nullptr, (const int*)nullptr, (const float2*)nullptr);
   }
   RF_HIP(hipGetLastError());
   return RFCMP_OK;

@@ -29,6 +29,7 @@
 // so each lane reads 64 contiguous bytes of its matrix row.  Partial sums go
 // to an FP32 buffer [slice][plane][rows_pad][ncp]; a combine kernel adds the
 // slices in a fixed order in FP64 and forms the complex result.
+#include "hmat.h"
 #include "internal.h"
 #include "gemm.h"
 #include "spchol.h"

@@ -135,6 +135,8 @@ struct MeshHost {
 };
 
 struct SplitMatrix;  // BF16x3 planes of a matrix (gemm.h)
+struct HmMesh;       // cluster tree of the compressed blocks (hmat.h)
+struct HmOp;         // compressed blocks of an operator (hmat.h)
 struct SpFactor;     // sparse Cholesky factor, host (spchol.h)
 struct SpDevice;     // sparse Cholesky factor, device (spchol.h)
 
@@ -218,6 +220,11 @@ struct rfcmp_mesh_s {
   // sparse factors of L and G_ll, computed on host threads from mesh
   // creation on (declared after h: their destructors wait for the threads)
   std::future<rfcmp::HostFactor> fac_async[2];
+  // cluster tree of the compressed blocks, built with the first compressed
+  // operator (destroyed where hmat.h is complete: rfcmp_mesh_destroy)
+  std::unique_ptr<rfcmp::HmMesh> hm;
+  rfcmp_mesh_s();
+  ~rfcmp_mesh_s();
 };
 
 namespace rfcmp {
@@ -260,6 +267,9 @@ struct rfcmp_op_s {
   rfcmp::DevBuf sp_scratch;    // sparse projector solves: one region per factor (L, G_ll, G_tp)
   int64_t sp_region[3] = {0, 0, 0};  // complex128 offsets of the regions
   int sp_scratch_nrhs = 0;
+  // compressed blocks (options.aca_tol > 0): T_A and V live here, TA and Vb
+  // stay empty
+  std::unique_ptr<rfcmp::HmOp> hm;
 };
 
 namespace rfcmp {

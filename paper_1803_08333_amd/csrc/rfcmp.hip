@@ -27,6 +27,7 @@
 #include <tuple>
 
 #include "gemm.h"
+#include "hmat.h"
 #include "spchol.h"
 #include "symv.h"
 #include "vecops.h"
@@ -261,8 +262,22 @@ struct Dense {
   // y = M x (conj: conj(M) x, complex matrices only).
   // The projector matrices (L^+, G_ll^-1, G_tp^-1) are applied in FP64 in
   // both precisions; BF16x3 serves the blocks T_A and V.
+  // Compressed blocks (options.aca_tol > 0): form the input (unless plain)
+  // and run the hierarchical product.
+  rfcmp_status hprod(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
+    const int64_t n = m == kTA ? op->mesh->h.N : op->mesh->h.C;
+    const double2* x = in.p[0];
+    if (in.mode != SymvInput::kPlain || in.stride[0] != n) {
+      double2* buf = m == kTA ? W->xN : W->xC;
+      RF_TRY(symv_form_input(in, n, nr, buf, s));
+      x = buf;
+    }
+    return hm_matvec(op, m == kTA ? 0 : 1, conj, x, y, nr, s);
+  }
+
   rfcmp_status prod(Mat m, bool conj, const SymvInput& in, double2* y, int nr) const {
     if (sparse(m)) return sp_solve(m, in, y, nullptr, nullptr, nullptr, nr, 0);
+    if (op->hm && complex_matrix(m)) return hprod(m, conj, in, y, nr);
     if (bf16 && complex_matrix(m)) return gemm(m, conj, in, y, nr);
     if (complex_matrix(m) && nr >= kZgemmMinRhs && W) return zgemm(m, conj, in, y, nr);
     const SymvJob j = job(m, in, y);
@@ -278,7 +293,7 @@ struct Dense {
   rfcmp_status pair(Mat m0, const SymvInput& in0, double2* y0, Mat m1, const SymvInput& in1, double2* y1,
                     bool conj, int nr, int nr1 = 0) const {
     if (sparse(m0) && sparse(m1)) return sp_solve(m0, in0, y0, &m1, &in1, y1, nr, nr1);
-    if (sparse(m0) || sparse(m1)) {
+    if (sparse(m0) || sparse(m1) || (op->hm && complex_matrix(m0))) {
       RF_TRY(prod(m0, conj, in0, y0, nr));
       return prod(m1, conj, in1, y1, nr1 > 0 ? nr1 : nr);
     }
@@ -1209,6 +1224,7 @@ rfcmp_status rfcmp_options_default(rfcmp_options* o) {
   o->streams = kBatchStreams;
   o->projector = 0;
   o->graphs = 0;
+  o->aca_tol = 0.0;
   return RFCMP_OK;
 }
 
@@ -1238,6 +1254,8 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
   RF_ARG(o.streams >= 1 && o.streams <= kBatchStreams, "streams must be 1..4");
   RF_ARG(o.projector >= 0 && o.projector <= 2, "projector must be 0, 1 or 2");
   RF_ARG(o.graphs == 0 || o.graphs == 1, "graphs must be 0 or 1");
+  RF_ARG(std::isfinite(o.aca_tol) && o.aca_tol >= 0 && o.aca_tol < 1, "aca_tol must be in [0, 1)");
+  RF_ARG(o.aca_tol == 0 || o.precision == 0, "compressed blocks (aca_tol > 0) need precision 0");
   if (o.projector == kProjAuto) o.projector = m->h.C > kAutoSparseCells ? kProjSparse : kProjDense;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
@@ -1260,8 +1278,14 @@ rfcmp_status rfcmp_op_create_many(rfcmp_mesh m, const double* k, int32_t nk, con
     op->opt = o;
     op->ldA = (int64_t)round_up(N, 64);
     op->ldV = (int64_t)round_up(C, 64);
-    RF_TRY(op->TA.alloc(sizeof(float2) * N * op->ldA));
-    RF_TRY(op->Vb.alloc(sizeof(float2) * C * op->ldV));
+    if (o.aca_tol > 0) {
+      RF_TRY(hm_mesh_setup(m, s));
+      op->hm = std::make_unique<HmOp>();
+      op->hm->tol = o.aca_tol;
+    } else {
+      RF_TRY(op->TA.alloc(sizeof(float2) * N * op->ldA));
+      RF_TRY(op->Vb.alloc(sizeof(float2) * C * op->ldV));
+    }
     RF_TRY(ensure_work(op.get(), 4));
     RF_TRY(op->symv_scratch.alloc(symv_scratch_bytes(N, 4) + symv_scratch_bytes(C, 4) + symv_scratch_bytes(V, 4)));
     RF_TRY(assemble_blocks(op.get(), s));
@@ -1340,6 +1364,7 @@ rfcmp_status rfcmp_op_export(rfcmp_op op, void* TA, void* V, void* stream) {
   RF_ARG(op, "op is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t N = op->mesh->h.N, C = op->mesh->h.C;
+  if (op->hm) return hm_export(op, static_cast<float2*>(TA), static_cast<float2*>(V), s);
   if (TA && N > 0) {
     const long tot = (long)N * N;
     hipLaunchKernelGGL(k_export_tri, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, op->TA.as<float2>(),
@@ -1349,6 +1374,27 @@ rfcmp_status rfcmp_op_export(rfcmp_op op, void* TA, void* V, void* stream) {
   if (V)
     RF_HIP(hipMemcpy2DAsync(V, sizeof(float2) * C, op->Vb.p, sizeof(float2) * op->ldV, sizeof(float2) * C, C,
                             hipMemcpyDeviceToDevice, s));
+  return RFCMP_OK;
+}
+
+rfcmp_status rfcmp_op_compression(rfcmp_op op, int64_t* dense_entries, int64_t* lowrank_entries,
+                                  int32_t* lowrank_blocks, int32_t* max_rank, double* mean_rank) {
+  RF_ARG(op, "op is NULL");
+  if (!op->hm) {
+    set_error("operator blocks are dense (options.aca_tol = 0)");
+    return RFCMP_E_STATE;
+  }
+  const HmOp& P = *op->hm;
+  int mx = 0;
+  double sum = 0.0;
+  for (int r : P.hrankA) mx = std::max(mx, r), sum += r;
+  for (int r : P.hrankV) mx = std::max(mx, r), sum += r;
+  const size_t nb = P.hrankA.size() + P.hrankV.size();
+  if (dense_entries) *dense_entries = P.dense_entries;
+  if (lowrank_entries) *lowrank_entries = P.lr_entries;
+  if (lowrank_blocks) *lowrank_blocks = (int32_t)P.hrankA.size();
+  if (max_rank) *max_rank = mx;
+  if (mean_rank) *mean_rank = nb ? sum / (double)nb : 0.0;
   return RFCMP_OK;
 }
 
@@ -1508,6 +1554,13 @@ rfcmp_status rfcmp_matvec(rfcmp_op op, int32_t which, int32_t conj, const void* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double2* xx = static_cast<const double2*>(x);
   double2* yy = static_cast<double2*>(y);
+  if (op->hm) {
+    if (which > 1) {
+      set_error("operator with compressed blocks: BF16x3 products (which 2-5) are not available");
+      return RFCMP_E_STATE;
+    }
+    return hm_matvec(op, which, conj != 0, xx, yy, nrhs, s);
+  }
   if (which <= 1 && nrhs >= kZgemmMinRhs) {
     RF_TRY(ensure_z_scratch(op));
     return which == 0 ? zgemm_c64(op->TA.as<float2>(), op->mesh->h.N, op->ldA, conj != 0, xx, yy, nrhs,

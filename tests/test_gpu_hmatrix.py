@@ -1,0 +1,180 @@
+"""Compressed EFIE blocks (options.aca_tol > 0: T_A and V as hierarchical
+matrices with ACA low-rank blocks, the compression of Sec. 4) through the C
+ABI.
+
+What is unique is the accuracy of the compressed operator, not its factors
+(pivots are chosen in FP32 here, in FP64 in the oracle): the blocks written
+out dense must match the oracle's dense blocks (and, at sizes the oracle
+cannot assemble quickly, the library's dense blocks, themselves pinned to
+the oracle to 2e-6) to within 10 x the ACA tolerance plus the complex64
+storage floor; they must be exactly symmetric; the compressed products must
+equal the products of the written-out blocks; and the solution must match
+the dense one to within 30 x the tolerance (cond(A) < 10 amplifies an O(tol)
+operator perturbation, applied twice in A).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import assembly, rfcmp, rhs
+from oracle.topology import Topology
+
+from ._meshes import rel
+
+pytestmark = pytest.mark.gpu
+
+MESHES = {
+    "ell2": lambda: synth.ellipsoid(2, (1.3, 0.8, 0.6)),   # N = 480, two low-rank blocks
+    "torus24": lambda: synth.torus(24, 12, jitter=0.01, seed=3),  # N = 864, 17 low-rank blocks
+    "ico3": lambda: synth.icosphere(3),                    # N = 1920, 121 low-rank blocks
+    "ico4": lambda: synth.icosphere(4),                    # N = 7680
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _mesh(name):
+    return MESHES[name]()
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(name, k):
+    top = Topology(*_mesh(name))
+    TA, V = assembly.assemble(top, k)
+    return top, TA, V
+
+
+def _gpu():
+    import torch
+    import paper_1803_08333_amd as rf
+    assert torch.cuda.is_available()
+    return torch, rf
+
+
+@functools.lru_cache(maxsize=None)
+def _gpu_mesh(name):
+    torch, rf = _gpu()
+    return rf.Mesh(*_mesh(name))
+
+
+@functools.lru_cache(maxsize=None)
+def _op(name, k, aca_tol):
+    torch, rf = _gpu()
+    m = _gpu_mesh(name)
+    start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
+    return rf.Operator(m, k, power_start=start, aca_tol=aca_tol)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def _frob_rel(torch, A, B):
+    A = A.to(torch.complex128)
+    B = B.to(torch.complex128)
+    return float(torch.linalg.norm(A - B) / torch.linalg.norm(B))
+
+
+@pytest.mark.parametrize("name,k", [("ell2", 1.0), ("torus24", 0.5)])
+@pytest.mark.parametrize("tol", [1e-2, 1e-4])
+def test_blocks_against_oracle(name, k, tol):
+    torch, rf = _gpu()
+    top, TA, V = _oracle(name, k)
+    op = _op(name, k, tol)
+    HA, HV = op.export()
+    info = op.compression()
+    print(name, k, tol, info)
+    assert info["lowrank_blocks"] > 0 and 0 < info["max_rank"] <= 128
+    for H, M in ((HA, TA), (HV, V)):
+        assert torch.equal(H, H.T)
+        err = rel(_np(H).astype(np.complex128), M)
+        print("  rel. Frobenius error", err)
+        assert err < 10 * tol + 2e-6
+
+
+@pytest.mark.parametrize("name,k", [("ico3", 2.0), ("ico4", 1.0)])
+@pytest.mark.parametrize("tol", [1e-2, 1e-4])
+def test_blocks_against_dense_library(name, k, tol):
+    torch, rf = _gpu()
+    opc = _op(name, k, tol)
+    opd = _op(name, k, 0.0)
+    HA, HV = opc.export()
+    DA, DV = opd.export()
+    info = opc.compression()
+    n, c = DA.shape[0], DV.shape[0]
+    ratio = (info["dense_entries"] + info["lowrank_entries"]) / float(n * n + c * c)
+    print(name, k, tol, info, "stored / dense", ratio)
+    for H, D in ((HA, DA), (HV, DV)):
+        assert torch.equal(H, H.T)
+        err = _frob_rel(torch, H, D)
+        print("  rel. Frobenius error", err)
+        assert err < 10 * tol
+    del HA, HV, DA, DV
+
+
+@pytest.mark.parametrize("nr", [1, 3, 9])
+@pytest.mark.parametrize("conj", [False, True])
+def test_products_match_written_out_blocks(nr, conj):
+    """rfcmp_matvec of the compressed T_A and V (groups of 8 right-hand
+    sides, the last ragged) against complex128 products of the written-out
+    blocks: the factors are summed in FP64 in both, the written-out entries
+    are rounded to complex64 once, hence 2e-6."""
+    torch, rf = _gpu()
+    op = _op("ico3", 2.0, 1e-4)
+    HA, HV = op.export()
+    g = np.random.default_rng(7)
+    for which, H in ((0, HA), (1, HV)):
+        n = H.shape[0]
+        x = _cuda(g.standard_normal((nr, n)) + 1j * g.standard_normal((nr, n)))
+        y = op.matvec(which, x, conj=conj)
+        Hd = H.to(torch.complex128)
+        if conj:
+            Hd = Hd.conj()
+        ref = (Hd @ x.T).T
+        err = float(torch.linalg.norm(y - ref) / torch.linalg.norm(ref))
+        print(which, nr, conj, err)
+        assert err < 2e-6
+
+
+def test_solution_against_oracle():
+    torch, rf = _gpu()
+    name, k, tol = "torus24", 0.5, 1e-4
+    top, TA, V = _oracle(name, k)
+    kh, pol = synth.default_plane_wave()
+    e = rhs.planewave(top, k, kh, pol)
+    pre = rfcmp.Preconditioner(top, TA, V, k)
+    pre.power_scalings(synth.complex_start(top.N, 11), 30)
+    jref = pre.recover(np.linalg.solve(pre.system_split(), pre.rhs(e[0])))
+    op = _op(name, k, tol)
+    j, st, info = op.solve(_cuda(e), tol=1e-8, maxit=1000)
+    assert st == 0 and info[0]["rel_residual"] <= 1e-8
+    err = rel(_np(j)[0], jref)
+    print("compressed solution vs oracle", err, info[0]["iters"])
+    assert err < 30 * tol
+
+
+@pytest.mark.parametrize("k", [1.0, 1e-4])
+def test_solution_full_size(k):
+    """Level-4 sphere: the compressed operator's solution against the dense
+    operator's (both to 1e-8), and the iteration counts alike."""
+    torch, rf = _gpu()
+    tol = 1e-4
+    opc = _op("ico4", k, tol)
+    opd = _op("ico4", k, 0.0)
+    kh, pol = synth.plane_waves(3, 5)
+    e = opd.rhs_planewave(kh, pol)
+    jd, std, infod = opd.solve(e, tol=1e-8, maxit=1000)
+    jc, stc, infoc = opc.solve(e, tol=1e-8, maxit=1000)
+    assert std == 0 and stc == 0
+    err = float(torch.linalg.norm(jc - jd) / torch.linalg.norm(jd))
+    its = [(a["iters"], b["iters"]) for a, b in zip(infod, infoc)]
+    print("ico4", k, "compressed vs dense", err, its, opc.compression())
+    assert err < 30 * tol
+    for a, b in its:
+        assert abs(a - b) <= max(3, a // 5)
