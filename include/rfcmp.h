@@ -230,10 +230,10 @@ rfcmp_status rfcmp_op_export(rfcmp_op op, void* TA, void* V, void* stream);
 /* Storage of an operator's compressed blocks (options.aca_tol > 0; Sec. 4):
  * complex64 entries of the dense blocks (pairs of 64-edge tiles of T_A and
  * the matching cell blocks of V) and of the low-rank factors (k (m + n) per
- * m x n block of rank k), the number of low-rank blocks of each matrix
- * (T_A and V have the same partition), and the largest and the mean rank
- * over both matrices.  Every output nullable.  RFCMP_E_STATE for an operator
- * with dense blocks.  Host call. */
+ * m x n block of rank k), each as host int64 [2] (T_A, V); the number of
+ * low-rank blocks of each matrix (T_A and V have the same partition); the
+ * largest and the mean rank over both matrices.  Every output nullable.
+ * RFCMP_E_STATE for an operator with dense blocks.  Host call. */
 rfcmp_status rfcmp_op_compression(rfcmp_op op, int64_t* dense_entries, int64_t* lowrank_entries,
                                   int32_t* lowrank_blocks, int32_t* max_rank, double* mean_rank);
 void rfcmp_op_destroy(rfcmp_op op);

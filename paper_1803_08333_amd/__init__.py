@@ -392,12 +392,11 @@ class Operator:
 
     def compression(self):
         """rfcmp_op_compression: storage of the compressed blocks (dict)."""
-        de, le = _I64(), _I64()
+        de, le = (_I64 * 2)(), (_I64 * 2)()
         nb, mx = _I32(), _I32()
         mean = _D()
-        _check(lib.rfcmp_op_compression(self.handle, ctypes.byref(de), ctypes.byref(le), ctypes.byref(nb),
-                                        ctypes.byref(mx), ctypes.byref(mean)))
-        return {"dense_entries": de.value, "lowrank_entries": le.value, "lowrank_blocks": nb.value,
+        _check(lib.rfcmp_op_compression(self.handle, de, le, ctypes.byref(nb), ctypes.byref(mx), ctypes.byref(mean)))
+        return {"dense_entries": [de[0], de[1]], "lowrank_entries": [le[0], le[1]], "lowrank_blocks": nb.value,
                 "max_rank": mx.value, "mean_rank": mean.value}
 
     def rhs_planewave(self, khat, pol):

@@ -701,7 +701,8 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
                          H.cell_start.as<int>(), H.iperm_c.as<int>(), hm->NV.as<float2>());
       RF_HIP(hipGetLastError());
     }
-    hm->dense_entries = nd * kEdgeTile * kEdgeTile + H.vd_total;
+    hm->dense_entries[0] = nd * kEdgeTile * kEdgeTile;
+    hm->dense_entries[1] = H.vd_total;
     return hm_aca(op, hw, s);
   }
   {

@@ -101,7 +101,7 @@ struct HmOp {
   DevBuf zwA, zwV;          // int64 [nlr]: offsets of the projections in the product scratch
   int64_t zw_total = 0;     // complex128 entries of that scratch
   std::vector<int> hrankA, hrankV;  // host copies of the ranks
-  int64_t lr_entries = 0, dense_entries = 0;  // complex64 entries stored
+  int64_t lr_entries[2] = {0, 0}, dense_entries[2] = {0, 0};  // complex64 entries stored (T_A, V)
   int unconverged = 0;      // blocks that reached kHmKmax above the tolerance
   DevBuf xp, yp, zw;        // product scratch: permuted input, projections
 };

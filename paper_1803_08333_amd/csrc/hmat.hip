@@ -338,49 +338,67 @@ __global__ void k_hm_gather(int n, int nr, const int* __restrict__ perm, const d
 }
 
 // z = V^T x_cols and w = U^T x_rows of every low-rank block (conj: of the
-// conjugated factors), nr <= kHmR right-hand sides, one wave per factor
-// column.
+// conjugated factors), nr <= kHmR right-hand sides: a small GEMM per block
+// (k x len times len x nr) over chunks of kProjRows rows, the factor chunk
+// and the x chunk staged in LDS so that each is read from memory once;
+// thread t accumulates outputs (l, r) = t, t + 256, ... in row order.
+constexpr int kProjRows = 32;
 __global__ __launch_bounds__(256) void k_hm_proj(const HmLr* __restrict__ blk, const int* __restrict__ rank,
                                                  float2* const* __restrict__ Up, float2* const* __restrict__ Vp,
                                                  const long* __restrict__ zoff, const double2* __restrict__ xp,
                                                  int n, int nr, int conj, double2* __restrict__ zw) {
+  __shared__ float2 sm[kHmKmax][kProjRows];
+  __shared__ double2 sx[kProjRows][kHmR];
   const int b = blockIdx.x;
   const int k = rank[b];
+  if (k == 0) return;
   const HmLr B = blk[b];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double2* z = zw + zoff[b];
-  double2* wv = z + (long)k * kHmR;
+  const int tid = threadIdx.x;
   const float sgn = conj ? -1.f : 1.f;
-  for (int t = w; t < 2 * k; t += 4) {
-    const bool isz = t < k;
-    const int l = isz ? t : t - k;
-    const float2* M = isz ? Vp[b] + (long)l * B.n : Up[b] + (long)l * B.m;
-    const int len = isz ? B.n : B.m, off = isz ? B.c0 : B.r0;
-    double ar[kHmR], ai[kHmR];
+  constexpr int kOut = kHmKmax * kHmR / 256;  // outputs per thread at most
+  double2* z = zw + zoff[b];
+  for (int part = 0; part < 2; ++part) {     // 0: z from V and the columns, 1: w from U and the rows
+    const float2* M = part == 0 ? Vp[b] : Up[b];
+    const int len = part == 0 ? B.n : B.m, off = part == 0 ? B.c0 : B.r0;
+    double2* out = z + (long)part * k * kHmR;
+    double ar[kOut], ai[kOut];
 #pragma unroll
-    for (int r = 0; r < kHmR; ++r) ar[r] = ai[r] = 0.0;
-    for (int j = lane; j < len; j += 64) {
-      const float2 mv = M[j];
-      const double mx = mv.x, my = sgn * mv.y;
+    for (int q = 0; q < kOut; ++q) ar[q] = ai[q] = 0.0;
+    for (int j0 = 0; j0 < len; j0 += kProjRows) {
+      const int nj = min(kProjRows, len - j0);
+      for (int e = tid; e < k * kProjRows; e += 256) {
+        const int l = e / kProjRows, jj = e % kProjRows;
+        float2 v = jj < nj ? M[(long)l * len + j0 + jj] : make_float2(0.f, 0.f);
+        v.y *= sgn;
+        sm[l][jj] = v;
+      }
+      for (int e = tid; e < kProjRows * kHmR; e += 256) {
+        const int jj = e / kHmR, r = e % kHmR;
+        sx[jj][r] = (jj < nj && r < nr) ? xp[(long)r * n + off + j0 + jj] : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
 #pragma unroll
-      for (int r = 0; r < kHmR; ++r)
-        if (r < nr) {
-          const double2 x = xp[(long)r * n + off + j];
-          ar[r] += mx * x.x - my * x.y;
-          ai[r] += mx * x.y + my * x.x;
+      for (int q = 0; q < kOut; ++q) {
+        const int o = tid + 256 * q;
+        if (o < k * kHmR) {
+          const int l = o / kHmR, r = o % kHmR;
+          double sr = 0.0, si = 0.0;
+          for (int jj = 0; jj < nj; ++jj) {
+            const float2 mv = sm[l][jj];
+            const double2 x = sx[jj][r];
+            sr += (double)mv.x * x.x - (double)mv.y * x.y;
+            si += (double)mv.x * x.y + (double)mv.y * x.x;
+          }
+          ar[q] += sr;
+          ai[q] += si;
         }
+      }
+      __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < kHmR; ++r)
-      for (int o = 32; o > 0; o >>= 1) {
-        ar[r] += __shfl_xor(ar[r], o);
-        ai[r] += __shfl_xor(ai[r], o);
-      }
-    if (lane == 0) {
-      double2* out = (isz ? z : wv) + (long)l * kHmR;
-#pragma unroll
-      for (int r = 0; r < kHmR; ++r)
-        if (r < nr) out[r] = make_double2(ar[r], ai[r]);
+    for (int q = 0; q < kOut; ++q) {
+      const int o = tid + 256 * q;
+      if (o < k * kHmR && o % kHmR < nr) out[o] = make_double2(ar[q], ai[q]);
     }
   }
 }
@@ -643,7 +661,7 @@ rfcmp_status hm_aca(rfcmp_op op, bool hw, hipStream_t s) {
   HmOp& P = *op->hm;
   const HmTree& t = H.t;
   const int64_t nlr = (int64_t)t.lr_a.size();
-  P.lr_entries = 0;
+  P.lr_entries[0] = P.lr_entries[1] = 0;
   P.unconverged = 0;
   std::vector<long> zoff_all[2];
   int64_t zw_need = 0;
@@ -659,7 +677,7 @@ rfcmp_status hm_aca(rfcmp_op op, bool hw, hipStream_t s) {
     // bounded pool
     std::vector<long> uoff(nlr), voff(nlr), toff(nlr);
     std::vector<int64_t> pass_start{0};
-    const long pool_cap = 1L << 26;  // complex64 entries (512 MB)
+    const long pool_cap = 1L << 29;  // complex64 entries (4 GB)
     long used = 0, tused = 0, pool_max = 1, taken_max = 1;
     for (int64_t b = 0; b < nlr; ++b) {
       const long kc = std::min<long>(kHmKmax, std::min(blk[b].m, blk[b].n));
@@ -737,7 +755,7 @@ rfcmp_status hm_aca(rfcmp_op op, bool hw, hipStream_t s) {
           hv[b] = st.as<float2>() + o;
           o += (long)hr[b] * blk[b].n;
         }
-        P.lr_entries += tot;
+        P.lr_entries[kind] += tot;
         RF_HIP(hipMemcpyAsync(up.as<float2*>() + b0, hu.data() + b0, sizeof(float2*) * (b1 - b0),
                               hipMemcpyHostToDevice, s));
         RF_HIP(hipMemcpyAsync(vp.as<float2*>() + b0, hv.data() + b0, sizeof(float2*) * (b1 - b0),

@@ -220,6 +220,23 @@ void hm_build_tree(const MeshHost& h, HmTree& t) {
   for (int64_t c = 0; c < C; ++c) hm = std::max(hm, h.hmax[c]);
   t.near_dist = 2.0 * hm * (1.0 + 1e-9);
   if (N > 0) partition(t, 0, 0);
+  // low-rank blocks largest first (by rows + columns, then in partition
+  // order), so that the ACA of the largest blocks starts first
+  std::vector<int> ord(t.lr_a.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  auto size = [&](int b) {
+    const HmNode& A = t.nodes[t.lr_a[b]];
+    const HmNode& B = t.nodes[t.lr_b[b]];
+    return (A.e1 - A.e0) + (B.e1 - B.e0);
+  };
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return size(a) > size(b); });
+  std::vector<int> la(ord.size()), lb(ord.size());
+  for (size_t q = 0; q < ord.size(); ++q) {
+    la[q] = t.lr_a[ord[q]];
+    lb[q] = t.lr_b[ord[q]];
+  }
+  t.lr_a.swap(la);
+  t.lr_b.swap(lb);
 }
 
 }  // namespace rfcmp

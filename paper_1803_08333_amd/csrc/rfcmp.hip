@@ -1390,8 +1390,10 @@ rfcmp_status rfcmp_op_compression(rfcmp_op op, int64_t* dense_entries, int64_t* 
   for (int r : P.hrankA) mx = std::max(mx, r), sum += r;
   for (int r : P.hrankV) mx = std::max(mx, r), sum += r;
   const size_t nb = P.hrankA.size() + P.hrankV.size();
-  if (dense_entries) *dense_entries = P.dense_entries;
-  if (lowrank_entries) *lowrank_entries = P.lr_entries;
+  for (int q = 0; q < 2; ++q) {
+    if (dense_entries) dense_entries[q] = P.dense_entries[q];
+    if (lowrank_entries) lowrank_entries[q] = P.lr_entries[q];
+  }
   if (lowrank_blocks) *lowrank_blocks = (int32_t)P.hrankA.size();
   if (max_rank) *max_rank = mx;
   if (mean_rank) *mean_rank = nb ? sum / (double)nb : 0.0;

@@ -108,7 +108,7 @@ def test_blocks_against_dense_library(name, k, tol):
     DA, DV = opd.export()
     info = opc.compression()
     n, c = DA.shape[0], DV.shape[0]
-    ratio = (info["dense_entries"] + info["lowrank_entries"]) / float(n * n + c * c)
+    ratio = (sum(info["dense_entries"]) + sum(info["lowrank_entries"])) / float(n * n + c * c)
     print(name, k, tol, info, "stored / dense", ratio)
     for H, D in ((HA, DA), (HV, DV)):
         assert torch.equal(H, H.T)
