@@ -14,8 +14,8 @@ Also reported (sub-keys): the level-4 sphere at ka = 1 and 1e-4 with one wave
 each on the complex64/FP64 path (the former headline), the icosphere-2 case
 solved by the FP64 oracle in full beside the GPU (error per result), the
 precision study (BF16x3 against complex64/FP64 at equal residual), the
-spectral study, far field, voltage gap, the uneven batch, and the oracle's
-CPU baseline.  Kernel durations come from HIP events the library records on
+spectral study, far field, voltage gap, the compressed operator (ACA) at
+icosphere levels 5-7, the uneven batch, and the oracle's CPU baseline.  Kernel durations come from HIP events the library records on
 the launch stream.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--batch-rhs", type=int, default=64)
     p.add_argument("--no-uneven-batch", action="store_true",
                    help="skip the uneven batch (32 objects x 8 wavenumbers x 4 plane waves, BF16x3)")
+    p.add_argument("--no-compressed-study", action="store_true",
+                   help="skip the compressed operator (ACA) at icosphere levels 5-7")
     p.add_argument("--uneven-batch-serial", action="store_true",
                    help="also time the uneven batch with one rfcmp_solve per operator")
     p.add_argument("--copy-calibration", action="store_true",
@@ -431,6 +433,68 @@ def uneven_batch(rf, torch, concurrent=True, budget_gb=64.0):
             "iters_top_k": {"median": float(np.median(top)), "max": int(max(top))}}
 
 
+def compressed_study(rf, torch, levels=((5, 8), (6, 8), (7, 8))):
+    """The compressed operator (options.aca_tol = 1e-4: T_A and V as
+    hierarchical matrices with ACA low-rank blocks, the compression of the
+    paper's large example, Sec. 4) on icospheres at levels 5 (N = 30 720),
+    6 (122 880) and 7 (491 520, whose dense blocks would take 2.8 TB), ka = 2,
+    complex64 storage with FP64 accumulation: set-up time (mesh, tree, dense
+    tiles, ACA, projector factors, power iteration), storage against the
+    dense blocks, ranks, one block solve of seeded plane waves to 1e-6, and
+    the roofline of the compressed T_A product in that solve (algorithmic
+    bytes: the stored entries read once plus x in and y out)."""
+    out = {"aca_tol": 1e-4, "ka": 2.0}
+    for lvl, nw in levels:
+        xyz, tri = synth.icosphere(lvl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m = rf.Mesh(xyz, tri)
+        start = torch.from_numpy(synth.complex_start(m.N, 11)).cuda()
+        rf.profile_select(None)
+        rf.profile_enable(True)
+        op = rf.Operator(m, 2.0, power_start=start, aca_tol=1e-4)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        setup = {t: rf.profile_read(t)[0] for t in ("hm_dense", "near_pairs", "hm_aca_ta", "hm_aca_v")}
+        rf.profile_enable(False)
+        info = op.compression()
+        kh, pol = synth.plane_waves(nw, 4)
+        e = op.rhs_planewave(kh, pol)
+        rf.profile_enable(True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        j, st, inf = op.solve(e, tol=1e-6, maxit=500)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        tot, nl = rf.profile_read(f"hm_matvec_ta_nr{nw}")
+        totv, nlv = rf.profile_read(f"hm_matvec_v_nr{nw}")
+        rf.profile_enable(False)
+        N, C = m.N, m.C
+        stored = [8.0 * (info["dense_entries"][q] + info["lowrank_entries"][q]) for q in (0, 1)]
+        dense = [8.0 * N * N, 8.0 * C * C]
+        prod = None
+        if nl:
+            avg = tot / nl
+            byt = stored[0] + 32.0 * N * nw
+            prod = {"launches": nl, "avg_ms": avg, "bound": "hbm", "algorithmic_bytes": byt,
+                    "achieved": byt / (avg * 1e-3) / 1e9, "peak": HBM_GBS, "unit": "GB/s",
+                    "frac": byt / (avg * 1e-3) / 1e9 / HBM_GBS, "v_avg_ms": totv / nlv if nlv else None}
+        out[f"icosphere{lvl}"] = {
+            "N": N, "C": C, "waves": nw, "setup_s": t1 - t0, "setup_kernels_ms": setup,
+            "stored_gb": [x / 1e9 for x in stored], "dense_gb": [x / 1e9 for x in dense],
+            "stored_over_dense": sum(stored) / sum(dense), "lowrank_blocks": info["lowrank_blocks"],
+            "max_rank": info["max_rank"], "mean_rank": info["mean_rank"],
+            "solve_ms": (t3 - t2) * 1e3, "status": st, "max_iters": max(i["iters"] for i in inf),
+            "max_rel_residual": max(i["rel_residual"] for i in inf), "solves_per_s": nw / (t3 - t2),
+            "product_ta": prod}
+        print(f"# compressed operator, level {lvl} done", file=sys.stderr, flush=True)
+        op.close()
+        m.close()
+        del e, j, start
+        rf.release_cached_memory()
+    return out
+
+
 # ------------------------------------------------------------------ kernel models
 # Algorithmic work per launch of each timed tag (what the method must do,
 # not what the kernel happens to move):
@@ -712,6 +776,8 @@ def main():
         res["far_field"] = far_field_measurement(rf, torch)
         res["voltage_gap"] = voltage_gap_measurement(rf, torch)
         print("# spectral study, far field, voltage gap done", file=sys.stderr, flush=True)
+    if not args.no_compressed_study:
+        res["compressed_operator"] = compressed_study(rf, torch)
     if not args.no_uneven_batch:
         res["uneven_batch"] = uneven_batch(rf, torch)
         print("# uneven batch done", file=sys.stderr, flush=True)

@@ -338,24 +338,29 @@ __global__ void k_hm_gather(int n, int nr, const int* __restrict__ perm, const d
 }
 
 // z = V^T x_cols and w = U^T x_rows of every low-rank block (conj: of the
-// conjugated factors), nr <= kHmR right-hand sides: a small GEMM per block
-// (k x len times len x nr) over chunks of kProjRows rows, the factor chunk
-// and the x chunk staged in LDS so that each is read from memory once;
-// thread t accumulates outputs (l, r) = t, t + 256, ... in row order.
-constexpr int kProjRows = 32;
+// conjugated factors), nr <= R <= kHmR right-hand sides: a small GEMM per
+// block (k x len times len x nr) over chunks of rows, the factor chunk
+// (k x rows <= 4096 entries) and the input chunk (rows x R <= 1024) staged in
+// LDS so that each is read from memory once; thread t accumulates outputs
+// (l, r) = t, t + 256, ... in row order.
+constexpr int kProjFactor = 4096;   // complex64 entries of a staged factor chunk
+constexpr int kProjInput = 1024;    // complex128 entries of a staged input chunk
+template <int R>
 __global__ __launch_bounds__(256) void k_hm_proj(const HmLr* __restrict__ blk, const int* __restrict__ rank,
                                                  float2* const* __restrict__ Up, float2* const* __restrict__ Vp,
                                                  const long* __restrict__ zoff, const double2* __restrict__ xp,
                                                  int n, int nr, int conj, double2* __restrict__ zw) {
-  __shared__ float2 sm[kHmKmax][kProjRows];
-  __shared__ double2 sx[kProjRows][kHmR];
+  __shared__ float2 sm[kProjFactor];
+  __shared__ double2 sx[kProjInput];
   const int b = blockIdx.x;
   const int k = rank[b];
   if (k == 0) return;
   const HmLr B = blk[b];
   const int tid = threadIdx.x;
   const float sgn = conj ? -1.f : 1.f;
-  constexpr int kOut = kHmKmax * kHmR / 256;  // outputs per thread at most
+  constexpr int kOut = (kHmKmax * R + 255) / 256;  // outputs per thread at most
+  // rows per chunk: a multiple of 32, at most 256
+  const int cr = max(32, min(256, min(kProjFactor / k, kProjInput / R)) / 32 * 32);
   double2* z = zw + zoff[b];
   for (int part = 0; part < 2; ++part) {     // 0: z from V and the columns, 1: w from U and the rows
     const float2* M = part == 0 ? Vp[b] : Up[b];
@@ -364,28 +369,29 @@ __global__ __launch_bounds__(256) void k_hm_proj(const HmLr* __restrict__ blk, c
     double ar[kOut], ai[kOut];
 #pragma unroll
     for (int q = 0; q < kOut; ++q) ar[q] = ai[q] = 0.0;
-    for (int j0 = 0; j0 < len; j0 += kProjRows) {
-      const int nj = min(kProjRows, len - j0);
-      for (int e = tid; e < k * kProjRows; e += 256) {
-        const int l = e / kProjRows, jj = e % kProjRows;
+    for (int j0 = 0; j0 < len; j0 += cr) {
+      const int nj = min(cr, len - j0);
+      for (int e = tid; e < k * cr; e += 256) {
+        const int l = e / cr, jj = e % cr;
         float2 v = jj < nj ? M[(long)l * len + j0 + jj] : make_float2(0.f, 0.f);
         v.y *= sgn;
-        sm[l][jj] = v;
+        sm[e] = v;
       }
-      for (int e = tid; e < kProjRows * kHmR; e += 256) {
-        const int jj = e / kHmR, r = e % kHmR;
-        sx[jj][r] = (jj < nj && r < nr) ? xp[(long)r * n + off + j0 + jj] : make_double2(0.0, 0.0);
+      for (int e = tid; e < cr * R; e += 256) {
+        const int jj = e / R, r = e % R;
+        sx[e] = (jj < nj && r < nr) ? xp[(long)r * n + off + j0 + jj] : make_double2(0.0, 0.0);
       }
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < kOut; ++q) {
         const int o = tid + 256 * q;
-        if (o < k * kHmR) {
-          const int l = o / kHmR, r = o % kHmR;
+        if (o < k * R) {
+          const int l = o / R, r = o % R;
+          const float2* mrow = sm + l * cr;
           double sr = 0.0, si = 0.0;
           for (int jj = 0; jj < nj; ++jj) {
-            const float2 mv = sm[l][jj];
-            const double2 x = sx[jj][r];
+            const float2 mv = mrow[jj];
+            const double2 x = sx[jj * R + r];
             sr += (double)mv.x * x.x - (double)mv.y * x.y;
             si += (double)mv.x * x.y + (double)mv.y * x.x;
           }
@@ -398,7 +404,7 @@ __global__ __launch_bounds__(256) void k_hm_proj(const HmLr* __restrict__ blk, c
 #pragma unroll
     for (int q = 0; q < kOut; ++q) {
       const int o = tid + 256 * q;
-      if (o < k * kHmR && o % kHmR < nr) out[o] = make_double2(ar[q], ai[q]);
+      if (o < k * R && o % R < nr) out[(o / R) * kHmR + o % R] = make_double2(ar[q], ai[q]);
     }
   }
 }
@@ -432,95 +438,208 @@ __device__ inline int tile_rows(const TileArgs& a, int T) {
   return KIND == 0 ? min(kEdgeTile, a.n - T * kEdgeTile) : a.row0[T + 1] - a.row0[T];
 }
 
-// One workgroup per tile of output rows; thread (row i, quarter g).
-template <int KIND>
+// One workgroup per tile of output rows; thread (row i, quarter g) keeps
+// the sums of its row for every right-hand side.  Each block of the tile's
+// list is staged in LDS with coalesced loads (all threads, many loads in
+// flight), then used from there: a dense block (64 x 64, rows padded) with
+// the input of its partner tile, or up to 32 factor columns of the rows of
+// consecutive low-rank blocks with their projections (a block of rank above
+// 32 in chunks of 32).  A dense V block larger than 64 x 64 (a tile homing
+// more than 64 cells) is read directly instead.
+constexpr int kTileLd = kEdgeTile + 1;  // padded row of a staged dense block
+template <int KIND, int R>
 __global__ __launch_bounds__(256) void k_hm_tile(const TileArgs a) {
-  __shared__ double2 red[4][64][kHmR];
+  __shared__ float2 smat[kEdgeTile * kTileLd];   // dense block [r][c], or factor rows [l][i] (32 x 64)
+  __shared__ double2 sx[kEdgeTile][kHmR];         // partner input [c][r], or projections [l][r]
+  __shared__ int s_nent, s_cols, s_colent[32], s_coll[32], s_len[32], s_o[32];
+  __shared__ const float2* s_F[32];
+  __shared__ const double2* s_zb[32];
   const int T = blockIdx.x;
+  const int tid = threadIdx.x;
   const int p0 = tile_row0<KIND>(a, T), nrow = tile_rows<KIND>(a, T);
-  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int lane = tid & 63, g = tid >> 6;
   const float sgn = a.conj ? -1.f : 1.f;
   const int e0 = a.list_ptr[T], e1 = a.list_ptr[T + 1];
   for (int base = 0; base < nrow; base += 64) {
     const int i = base + lane;
     const bool valid = i < nrow;
-    double ar[kHmR], ai[kHmR];
+    const int nb = min(64, nrow - base);   // rows of this pass
+    double ar[R], ai[R];
 #pragma unroll
-    for (int r = 0; r < kHmR; ++r) ar[r] = ai[r] = 0.0;
-    auto fma_x = [&](float2 mv, long pos) {
+    for (int r = 0; r < R; ++r) ar[r] = ai[r] = 0.0;
+    auto fma_x = [&](float2 mv, const double2* x) {
       const double mx = mv.x, my = sgn * mv.y;
 #pragma unroll
-      for (int r = 0; r < kHmR; ++r)
-        if (r < a.nr) {
-          const double2 x = a.xp[(long)r * a.n + pos];
-          ar[r] += mx * x.x - my * x.y;
-          ai[r] += mx * x.y + my * x.x;
-        }
+      for (int r = 0; r < R; ++r) {
+        const double2 v = x[r];
+        ar[r] += mx * v.x - my * v.y;
+        ai[r] += mx * v.y + my * v.x;
+      }
     };
-    auto fma_z = [&](float2 mv, const double2* z) {
-      const double mx = mv.x, my = sgn * mv.y;
-#pragma unroll
-      for (int r = 0; r < kHmR; ++r)
-        if (r < a.nr) {
-          const double2 x = z[r];
-          ar[r] += mx * x.x - my * x.y;
-          ai[r] += mx * x.y + my * x.x;
+    int e = e0;
+    while (e < e1) {
+      __syncthreads();   // every wave is done with the previous batch's descriptors
+      // wave 0: the next entries that form a batch of low-rank blocks with at
+      // most 32 factor columns in all (their descriptors into LDS)
+      if (g == 0) {
+        const int ej = e + lane;
+        const int cd = ej < e1 ? a.list_ent[ej] : 0;
+        const bool lr = ej < e1 && (cd & 3) >= 2;
+        const int bj = cd >> 2;
+        const int kj = lr ? a.rank[bj] : 0;
+        int cum = kj;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int t = __shfl_up(cum, o);
+          if (lane >= o) cum += t;
         }
-    };
-    if (valid) {
-      for (int e = e0; e < e1; ++e) {
-        const int code = a.list_ent[e];
-        const int kind = code & 3, bi = code >> 2;
-        if (kind < 2) {
-          const int I = a.dense_ij[bi].x, J = a.dense_ij[bi].y;
-          if (KIND == 0) {
-            const float2* D = a.D + (long)bi * kEdgeTile * kEdgeTile;
-            if (kind == 0) {  // rows of this tile, columns of J
-              const int q0 = J * kEdgeTile;
-              for (int c = 16 * g; c < 16 * g + 16; ++c)
-                if (q0 + c < a.n) fma_x(D[i * kEdgeTile + c], q0 + c);
-            } else {          // the transpose: column i of D, rows of I
-              const int q0 = I * kEdgeTile;
-              for (int rr = 16 * g; rr < 16 * g + 16; ++rr)
-                if (q0 + rr < a.n) fma_x(D[rr * kEdgeTile + i], q0 + rr);
-            }
-          } else {
-            const float2* D = a.D + a.doff[bi];
-            const int qI = a.row0[I], nI = a.row0[I + 1] - qI;
-            const int qJ = a.row0[J], nJ = a.row0[J + 1] - qJ;
-            if (kind == 0) {
-              for (int c = g; c < nJ; c += 4) fma_x(D[(long)i * nJ + c], qJ + c);
-            } else {
-              for (int rr = g; rr < nI; rr += 4) fma_x(D[(long)rr * nJ + i], qI + rr);
-            }
-          }
-        } else {
-          const HmLr B = a.blk[bi];
-          const int k = a.rank[bi];
-          const double2* z = a.zw + a.zoff[bi];
-          if (kind == 2) {  // rows of U, times z
-            const float2* U = a.Up[bi];
-            const int o = p0 + i - B.r0;
-            for (int l = g; l < k; l += 4) fma_z(U[(long)l * B.m + o], z + (long)l * kHmR);
-          } else {          // rows of V, times w
-            const float2* Vf = a.Vp[bi];
-            const int o = p0 + i - B.c0;
-            const double2* w = z + (long)k * kHmR;
-            for (int l = g; l < k; l += 4) fma_z(Vf[(long)l * B.n + o], w + (long)l * kHmR);
+        const unsigned long long nonlr = __ballot(!lr);
+        const int first_non = nonlr ? (int)__builtin_ctzll(nonlr) : 64;
+        const bool ok = lane < first_non && lane < 32 && cum <= 32;
+        const int nent = __popcll(__ballot(ok));
+        const int cols = __shfl(cum, nent > 0 ? nent - 1 : 0);
+        if (lane == 0) {
+          s_nent = nent;
+          s_cols = nent > 0 ? cols : 0;
+        }
+        if (ok) {
+          const HmLr B = a.blk[bj];
+          const bool rows = (cd & 3) == 2;
+          s_F[lane] = rows ? a.Up[bj] : a.Vp[bj];
+          s_len[lane] = rows ? B.m : B.n;
+          s_o[lane] = p0 + base - (rows ? B.r0 : B.c0);
+          s_zb[lane] = a.zw + a.zoff[bj] + (rows ? 0 : (long)kj * kHmR);
+          for (int c = cum - kj; c < cum; ++c) {
+            s_colent[c] = lane;
+            s_coll[c] = c - (cum - kj);
           }
         }
       }
-    }
+      __syncthreads();
+      const int nbatch = s_nent;
+      if (nbatch > 0) {
+        const int cols = s_cols;
+        for (int q = tid; q < 32 * 64; q += 256) {
+          const int c = q / 64, ii = q % 64;
+          float2 v = make_float2(0.f, 0.f);
+          if (c < cols && ii < nb) {
+            const int j = s_colent[c];
+            v = s_F[j][(long)s_coll[c] * s_len[j] + s_o[j] + ii];
+          }
+          smat[c * 64 + ii] = v;
+        }
+        {
+          const int c = tid / kHmR, r = tid % kHmR;   // 32 x 8 = 256 entries
+          sx[c][r] = (c < cols && r < a.nr) ? s_zb[s_colent[c]][(long)s_coll[c] * kHmR + r] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (valid)
+          for (int c = g; c < cols; c += 4) fma_x(smat[c * 64 + lane], sx[c]);
+        e += nbatch;
+        continue;
+      }
+      const int code = a.list_ent[e];
+      const int kind = code & 3, bi = code >> 2;
+      ++e;
+      if (kind < 2) {
+        const int I = a.dense_ij[bi].x, J = a.dense_ij[bi].y;
+        int qI, nI, qJ, nJ;
+        const float2* D;
+        if (KIND == 0) {
+          qI = I * kEdgeTile;
+          qJ = J * kEdgeTile;
+          nI = min(kEdgeTile, a.n - qI);
+          nJ = min(kEdgeTile, a.n - qJ);
+          D = a.D + (long)bi * kEdgeTile * kEdgeTile;
+        } else {
+          qI = a.row0[I];
+          nI = a.row0[I + 1] - qI;
+          qJ = a.row0[J];
+          nJ = a.row0[J + 1] - qJ;
+          D = a.D + a.doff[bi];
+        }
+        const int ld = KIND == 0 ? kEdgeTile : nJ;
+        // the partner's rows: columns of D (kind 0) or its rows (kind 1)
+        const int qp = kind == 0 ? qJ : qI, np = kind == 0 ? nJ : nI;
+        if (nI > 64 || nJ > 64) {  // direct reads (only a V block of a tile homing > 64 cells)
+          if (valid) {
+            if (kind == 0) {
+              for (int c = g; c < nJ; c += 4) {
+                double2 xv[R];
 #pragma unroll
-    for (int r = 0; r < kHmR; ++r) red[g][lane][r] = make_double2(ar[r], ai[r]);
+                for (int r = 0; r < R; ++r)
+                  xv[r] = r < a.nr ? a.xp[(long)r * a.n + qJ + c] : make_double2(0.0, 0.0);
+                fma_x(D[(long)i * ld + c], xv);
+              }
+            } else {
+              for (int rr = g; rr < nI; rr += 4) {
+                double2 xv[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                  xv[r] = r < a.nr ? a.xp[(long)r * a.n + qI + rr] : make_double2(0.0, 0.0);
+                fma_x(D[(long)rr * ld + i], xv);
+              }
+            }
+          }
+          continue;
+        }
+        for (int q = tid; q < kEdgeTile * kEdgeTile; q += 256) {
+          const int r = q / kEdgeTile, c = q % kEdgeTile;
+          smat[r * kTileLd + c] = (r < nI && c < nJ) ? D[(long)r * ld + c] : make_float2(0.f, 0.f);
+        }
+        for (int q = tid; q < kEdgeTile * kHmR; q += 256) {
+          const int c = q / kHmR, r = q % kHmR;
+          sx[c][r] = (c < np && r < a.nr) ? a.xp[(long)r * a.n + qp + c] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (valid) {
+          if (kind == 0) {
+            for (int c = 16 * g; c < 16 * g + 16; ++c) fma_x(smat[(i - base) * kTileLd + c], sx[c]);
+          } else {
+            for (int rr = 16 * g; rr < 16 * g + 16; ++rr) fma_x(smat[rr * kTileLd + (i - base)], sx[rr]);
+          }
+        }
+        __syncthreads();
+      } else {
+        const HmLr B = a.blk[bi];
+        const int k = a.rank[bi];
+        const double2* zb = a.zw + a.zoff[bi] + (kind == 2 ? 0 : (long)k * kHmR);
+        const float2* F = kind == 2 ? a.Up[bi] : a.Vp[bi];
+        const int len = kind == 2 ? B.m : B.n;
+        const int o = p0 + base - (kind == 2 ? B.r0 : B.c0);   // first row of this pass in the factor
+        for (int l0 = 0; l0 < k; l0 += 32) {
+          const int nl = min(32, k - l0);
+          for (int q = tid; q < 32 * 64; q += 256) {
+            const int l = q / 64, ii = q % 64;
+            smat[l * 64 + ii] = (l < nl && ii < nb) ? F[(long)(l0 + l) * len + o + ii] : make_float2(0.f, 0.f);
+          }
+          {
+            const int l = tid / kHmR, r = tid % kHmR;   // 32 x 8 = 256 entries
+            sx[l][r] = (l < nl && r < a.nr) ? zb[(long)(l0 + l) * kHmR + r] : make_double2(0.0, 0.0);
+          }
+          __syncthreads();
+          if (valid)
+            for (int l = g; l < nl; l += 4) fma_x(smat[l * 64 + lane], sx[l]);
+          __syncthreads();
+        }
+      }
+    }
+    __syncthreads();   // the last batch's reads of smat are done
+    // the four quarters' sums in order, through LDS (smat reused)
+    double2* red = reinterpret_cast<double2*>(smat);   // [3][64][kHmR] (quarters 1..3)
+    static_assert(sizeof(smat) >= 3 * 64 * kHmR * sizeof(double2), "reduction fits the staging buffer");
+    if (g > 0)
+#pragma unroll
+      for (int r = 0; r < R; ++r) red[((g - 1) * 64 + lane) * kHmR + r] = make_double2(ar[r], ai[r]);
     __syncthreads();
     if (g == 0 && valid) {
       const int dst = a.perm[p0 + i];
-      for (int r = 0; r < a.nr; ++r) {
-        double sr = red[0][lane][r].x, si = red[0][lane][r].y;
-        for (int q = 1; q < 4; ++q) {
-          sr += red[q][lane][r].x;
-          si += red[q][lane][r].y;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (r >= a.nr) break;
+        double sr = ar[r], si = ai[r];
+        for (int q = 0; q < 3; ++q) {
+          sr += red[(q * 64 + lane) * kHmR + r].x;
+          si += red[(q * 64 + lane) * kHmR + r].y;
         }
         a.y[(long)r * a.n + dst] = make_double2(sr, si);
       }
@@ -825,15 +944,22 @@ rfcmp_status hm_matvec(rfcmp_op op, int which, bool conj, const double2* x, doub
     const long tot = (long)n * rr;
     hipLaunchKernelGGL(k_hm_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, rr, ta.perm,
                        x + (long)r0 * n, P.xp.as<double2>());
+    // kernels for 1, 2, 4 or 8 right-hand sides: the smallest that holds rr
+    const int R = rr <= 1 ? 1 : (rr <= 2 ? 2 : (rr <= 4 ? 4 : 8));
+    typedef void (*Proj)(const HmLr*, const int*, float2* const*, float2* const*, const long*, const double2*, int,
+                         int, int, double2*);
+    typedef void (*Tile)(const TileArgs);
+    const Proj proj = R == 1 ? k_hm_proj<1> : (R == 2 ? k_hm_proj<2> : (R == 4 ? k_hm_proj<4> : k_hm_proj<8>));
+    const Tile tile = which == 0 ? (R == 1 ? k_hm_tile<0, 1> : (R == 2 ? k_hm_tile<0, 2> : (R == 4 ? k_hm_tile<0, 4>
+                                                                                                    : k_hm_tile<0, 8>)))
+                                 : (R == 1 ? k_hm_tile<1, 1> : (R == 2 ? k_hm_tile<1, 2> : (R == 4 ? k_hm_tile<1, 4>
+                                                                                                    : k_hm_tile<1, 8>)));
     if (nlr > 0)
-      hipLaunchKernelGGL(k_hm_proj, dim3((unsigned)nlr), dim3(256), 0, s, ta.blk, ta.rank, ta.Up, ta.Vp, ta.zoff,
+      hipLaunchKernelGGL(proj, dim3((unsigned)nlr), dim3(256), 0, s, ta.blk, ta.rank, ta.Up, ta.Vp, ta.zoff,
                          P.xp.as<double2>(), n, rr, ta.conj, P.zw.as<double2>());
     ta.nr = rr;
     ta.y = y + (long)r0 * n;
-    if (which == 0)
-      hipLaunchKernelGGL(k_hm_tile<0>, dim3((unsigned)t.ntiles), dim3(256), 0, s, ta);
-    else
-      hipLaunchKernelGGL(k_hm_tile<1>, dim3((unsigned)t.ntiles), dim3(256), 0, s, ta);
+    hipLaunchKernelGGL(tile, dim3((unsigned)t.ntiles), dim3(256), 0, s, ta);
     RF_HIP(hipGetLastError());
   }
   return RFCMP_OK;
