@@ -64,7 +64,6 @@ struct CellL {
   int home;       // home tile
 };
 
-template <bool HW>
 __global__ __launch_bounds__(kAsmThreads) void k_assemble_ta(int N, const int* __restrict__ et_ptr,
                                                              const int* __restrict__ et_cell,
                                                              const int* __restrict__ et_rows,
@@ -175,7 +174,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_ta(int N, const int* _
         }
       } else {
         Moments M;
-        far_moments<HW>(A.q, Bc.q, (float)(A.cen[0] - Bc.cen[0]), (float)(A.cen[1] - Bc.cen[1]),
+        far_moments(A.q, Bc.q, (float)(A.cen[0] - Bc.cen[0]), (float)(A.cen[1] - Bc.cen[1]),
                         (float)(A.cen[2] - Bc.cen[2]), rule, kk, M);
         if (A.home == I && Bc.home == Jt) {
           const float2 v = make_float2(M.i0r, M.i0i);
@@ -619,29 +618,8 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
   HmOp* hm = op->hm.get();
   if (!hm) RF_HIP(hipMemsetAsync(op->Vb.p, 0, op->Vb.bytes, s));
 
-  // far pairs first: they do not need the near-pair list, which a new mesh
-  // may still be computing on a host thread
   const long nt = (long)d.etiles;
   const long npairs_t = nt * (nt + 1) / 2;
-  // largest kR between quadrature points: at most k times twice the largest
-  // vertex distance from the bounding-box centre (the diameter of a sphere)
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  const size_t nv = h.xyz.size() / 3;
-  for (size_t v = 0; v < nv; ++v)
-    for (int q = 0; q < 3; ++q) {
-      lo[q] = std::min(lo[q], h.xyz[3 * v + q]);
-      hi[q] = std::max(hi[q], h.xyz[3 * v + q]);
-    }
-  double rad2 = 0.0;
-  for (size_t v = 0; v < nv; ++v) {
-    double r2 = 0.0;
-    for (int q = 0; q < 3; ++q) {
-      const double dq = h.xyz[3 * v + q] - 0.5 * (lo[q] + hi[q]);
-      r2 += dq * dq;
-    }
-    rad2 = std::max(rad2, r2);
-  }
-  const bool hw = op->k * 2.0 * std::sqrt(rad2) <= 2.0;
   // the near pairs (computed on a host thread from mesh creation on): their
   // blocks first, which the T_A tiles read
   if (d.near_factor != op->opt.near_factor) {
@@ -692,7 +670,7 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
     if (nd > 0) {
       ProfScope prof("hm_dense", s);
       const size_t lds = 2 * sizeof(float2) * kEdgeTile * kEdgeTile + 2 * sizeof(CellL) * (size_t)H.t.et_cells_max;
-      hipLaunchKernelGGL(hw ? k_assemble_ta<true> : k_assemble_ta<false>, dim3((unsigned)nd), dim3(kAsmThreads),
+      hipLaunchKernelGGL(k_assemble_ta, dim3((unsigned)nd), dim3(kAsmThreads),
                          lds, s, (int)N, H.et_ptr.as<int>(), H.et_cell.as<int>(), H.et_rows.as<int>(),
                          H.home.as<int>(), d.cen.as<double>(), d.qoff.as<float4>(), d.fvoff.as<float4>(),
                          d.sgn.as<float>(), (float)op->k, ra, (const uint8_t*)nullptr, d.np_ptr.as<int>(),
@@ -703,12 +681,12 @@ rfcmp_status assemble_blocks(rfcmp_op op, hipStream_t s) {
     }
     hm->dense_entries[0] = nd * kEdgeTile * kEdgeTile;
     hm->dense_entries[1] = H.vd_total;
-    return hm_aca(op, hw, s);
+    return hm_aca(op, s);
   }
   {
     ProfScope prof("assemble_ta", s);
     const size_t lds = 2 * sizeof(float2) * kEdgeTile * kEdgeTile + 2 * sizeof(CellL) * (size_t)d.et_cells_max;
-    hipLaunchKernelGGL(hw ? k_assemble_ta<true> : k_assemble_ta<false>, dim3((unsigned)npairs_t), dim3(kAsmThreads),
+    hipLaunchKernelGGL(k_assemble_ta, dim3((unsigned)npairs_t), dim3(kAsmThreads),
                        lds, s, (int)N, d.et_ptr.as<int>(), d.et_cell.as<int>(), d.et_rows.as<int>(),
                        d.cell_home.as<int>(), d.cen.as<double>(), d.qoff.as<float4>(), d.fvoff.as<float4>(),
                        d.sgn.as<float>(), (float)op->k, ra, d.tile_near.as<uint8_t>(), d.np_ptr.as<int>(),

@@ -39,41 +39,25 @@ struct RuleArgs {
 };
 
 // ---------------------------------------------------------------- far pairs
-// sin and cos of a moderate argument in FP32: Cody-Waite reduction by pi/2
-// (two-term split of pi/2, one rounding per step) to |r| <= pi/4, then the
-// Taylor series of sin to r^9 and of cos to r^8 (truncation below 3e-8), and
-// the quadrant rotation.  Keeps full relative accuracy as x -> 0, which the
-// imaginary part of G_k needs at low frequency.
-constexpr float kPio2Hi = (float)1.57079632679489661923;
-constexpr float kPio2Lo = (float)(1.57079632679489661923 - (double)kPio2Hi);
-constexpr float k2OverPi = (float)0.63661977236758134308;
+// sin and cos of x = kR on the transcendental unit (v_sin_f32, v_cos_f32 take
+// the argument in revolutions).  The revolutions t = x / (2 pi) are formed as
+// an unevaluated sum: the FP32 product by the FP32 value of 1/(2 pi), its
+// rounding error by an FMA, and the product by the rest of 1/(2 pi); the
+// integer part of the product is taken off exactly, so the unit sees an
+// argument in [-1/2, 1/2] revolutions that is as accurate as x itself, for
+// any x.  sin keeps full relative accuracy as x -> 0 (the reduction is the
+// identity there), which the imaginary part of G_k needs at low frequency.
+constexpr float kInv2PiHi = (float)0.15915494309189533577;
+constexpr float kInv2PiLo = (float)(0.15915494309189533577 - (double)kInv2PiHi);
 
-__device__ inline void sincos_moderate(float x, float& sn, float& cs) {
-  const float n = rintf(x * k2OverPi);
-  float r = fmaf(-n, kPio2Hi, x);
-  r = fmaf(-n, kPio2Lo, r);
-  const float r2 = r * r;
-  float ps = fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
-  ps = fmaf(r2, ps, 1.0f / 120.0f);
-  ps = fmaf(r2, ps, -1.0f / 6.0f);
-  const float s = fmaf(r * r2, ps, r);
-  float pc = fmaf(r2, 1.0f / 40320.0f, -1.0f / 720.0f);
-  pc = fmaf(r2, pc, 1.0f / 24.0f);
-  pc = fmaf(r2, pc, -0.5f);
-  const float c = fmaf(r2, pc, 1.0f);
-  const int q = ((int)n) & 3;
-  const float s1 = (q & 1) ? c : s;
-  const float c1 = (q & 1) ? s : c;
-  sn = (q & 2) ? -s1 : s1;
-  cs = ((q + 1) & 2) ? -c1 : c1;
+__device__ inline void sincos_kr(float x, float& sn, float& cs) {
+  const float t = x * kInv2PiHi;
+  const float te = fmaf(x, kInv2PiHi, -t) + x * kInv2PiLo;
+  const float r = (t - rintf(t)) + te;
+  sn = __builtin_amdgcn_sinf(r);
+  cs = __builtin_amdgcn_cosf(r);
 }
 
-// sin and cos of kR come from the polynomial above, or, when kR <= 2 over the
-// whole mesh (HW), from the transcendental unit (v_sin_f32 / v_cos_f32 take
-// the argument in revolutions).  Measured on the device against double
-// precision for |x| < 2: sin within 1e-6 relative (also as x -> 0), cos
-// within 2.1e-7 absolute; beyond 2 the revolution product loses absolute
-// accuracy (7e-7 up to 10), so larger kR keeps the reduced polynomial.
 // Normalised moments of one far cell pair (c, c') (see above), scaled by
 // 1/(4 pi): I_0, I_r (over c), I_r' (over c'), I_rr'.
 struct Moments {
@@ -82,7 +66,6 @@ struct Moments {
 
 // qa: the 7 points of c minus its centroid, qb those of c'; (dx, dy, dz) =
 // x_c - x_c' (formed in FP64 by the caller).
-template <bool HW>
 __device__ inline void far_moments(const float4* qa, const float4* qb, float dx, float dy, float dz,
                                    const RuleArgs& rule, float kk, Moments& M) {
   float bq[kQ][3], wq[kQ];
@@ -108,13 +91,7 @@ __device__ inline void far_moments(const float4* qa, const float4* qb, float dx,
       const float rinv = __frsqrt_rn(R2);
       const float R = R2 * rinv;
       float sn, cs;
-      if (HW) {  // the transcendental unit, argument in revolutions (kR <= 2 here)
-        const float rev = kk * R * 0.159154943091895336f;
-        sn = __builtin_amdgcn_sinf(rev);
-        cs = __builtin_amdgcn_cosf(rev);
-      } else {
-        sincos_moderate(kk * R, sn, cs);
-      }
+      sincos_kr(kk * R, sn, cs);
       const float g = wq[q] * rinv;
       const float gr = cs * g, gi = sn * g;
       s0r += gr;
@@ -165,7 +142,6 @@ __device__ inline float2 b_entry(const Moments& M, float4 qi, float4 qj, float s
 RuleArgs rule_args();
 
 // V entry of a far cell pair: I_0 alone (see far_moments), scaled by 1/(4 pi).
-template <bool HW>
 __device__ inline float2 far_i0(const float4* qa, const float4* qb, float dx, float dy, float dz,
                                 const RuleArgs& rule, float kk) {
   float i0r = 0, i0i = 0;
@@ -182,13 +158,7 @@ __device__ inline float2 far_i0(const float4* qa, const float4* qb, float dx, fl
       const float rinv = __frsqrt_rn(R2);
       const float R = R2 * rinv;
       float sn, cs;
-      if (HW) {
-        const float rev = kk * R * 0.159154943091895336f;
-        sn = __builtin_amdgcn_sinf(rev);
-        cs = __builtin_amdgcn_cosf(rev);
-      } else {
-        sincos_moderate(kk * R, sn, cs);
-      }
+      sincos_kr(kk * R, sn, cs);
       const float g = rule.wf[q] * rinv;
       s0r += cs * g;
       s0i += sn * g;

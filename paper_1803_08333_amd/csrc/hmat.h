@@ -110,7 +110,7 @@ struct HmOp {
 rfcmp_status hm_mesh_setup(rfcmp_mesh m, hipStream_t s);
 // ACA of every low-rank block of T_A and V (after the dense blocks and the
 // near pairs' V entries are assembled); waits for the stream.
-rfcmp_status hm_aca(rfcmp_op op, bool hw, hipStream_t s);
+rfcmp_status hm_aca(rfcmp_op op, hipStream_t s);
 // y = M x or conj(M) x for M = T_A (which 0) or V (which 1), x, y complex128
 // [nr][n] in the mesh's numbering.
 rfcmp_status hm_matvec(rfcmp_op op, int which, bool conj, const double2* x, double2* y, int nr, hipStream_t s);

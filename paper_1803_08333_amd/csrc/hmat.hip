@@ -61,7 +61,6 @@ struct AcaArgs {
   int* flag;              // 1: stopped at kmax above the tolerance
 };
 
-template <bool HW>
 __device__ float2 ta_entry(const AcaArgs& a, int m, int n) {
   float2 b00, b01, b10, b11;
 #pragma unroll 1
@@ -70,7 +69,7 @@ __device__ float2 ta_entry(const AcaArgs& a, int m, int n) {
     const int sa = a.edge_slot[2 * m + p], sb = a.edge_slot[2 * n + q];
     const int ca = sa / 3, la = sa - 3 * ca, cb = sb / 3, lb = sb - 3 * cb;
     Moments M;
-    far_moments<HW>(a.qoff + (long)ca * kQ, a.qoff + (long)cb * kQ, (float)(a.cen[3 * ca] - a.cen[3 * cb]),
+    far_moments(a.qoff + (long)ca * kQ, a.qoff + (long)cb * kQ, (float)(a.cen[3 * ca] - a.cen[3 * cb]),
                     (float)(a.cen[3 * ca + 1] - a.cen[3 * cb + 1]), (float)(a.cen[3 * ca + 2] - a.cen[3 * cb + 2]),
                     a.rule, a.kk, M);
     const float2 v = b_entry(M, a.fvoff[3 * ca + la], a.fvoff[3 * cb + lb], a.sgn[3 * ca + la], a.sgn[3 * cb + lb]);
@@ -86,9 +85,8 @@ __device__ float2 ta_entry(const AcaArgs& a, int m, int n) {
   return make_float2((b00.x + b11.x) + (b01.x + b10.x), (b00.y + b11.y) + (b01.y + b10.y));
 }
 
-template <bool HW>
 __device__ float2 v_entry(const AcaArgs& a, int c, int cp) {
-  return far_i0<HW>(a.qoff + (long)c * kQ, a.qoff + (long)cp * kQ, (float)(a.cen[3 * c] - a.cen[3 * cp]),
+  return far_i0(a.qoff + (long)c * kQ, a.qoff + (long)cp * kQ, (float)(a.cen[3 * c] - a.cen[3 * cp]),
                     (float)(a.cen[3 * c + 1] - a.cen[3 * cp + 1]), (float)(a.cen[3 * c + 2] - a.cen[3 * cp + 2]),
                     a.rule, a.kk);
 }
@@ -167,7 +165,7 @@ __device__ inline void block_sum32(float (&v)[32], AcaLds& L) {
   __syncthreads();
 }
 
-template <int KIND, bool HW>
+template <int KIND>
 __global__ __launch_bounds__(kAcaThreads) void k_aca(const AcaArgs a, int b0) {
   const int b = b0 + blockIdx.x;
   const HmLr B = a.blk[b];
@@ -183,7 +181,7 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const AcaArgs a, int b0) {
   __syncthreads();
   auto entry = [&](int pi, int pj) -> float2 {
     const int x = a.perm[B.r0 + pi], y = a.perm[B.c0 + pj];
-    return KIND == 0 ? ta_entry<HW>(a, x, y) : v_entry<HW>(a, x, y);
+    return KIND == 0 ? ta_entry(a, x, y) : v_entry(a, x, y);
   };
   double S2 = 0.0;
   int k = 0, i = 0, tries = 0;
@@ -773,7 +771,7 @@ rfcmp_status hm_mesh_setup(rfcmp_mesh m, hipStream_t s) {
   return RFCMP_OK;
 }
 
-rfcmp_status hm_aca(rfcmp_op op, bool hw, hipStream_t s) {
+rfcmp_status hm_aca(rfcmp_op op, hipStream_t s) {
   rfcmp_mesh m = op->mesh;
   const MeshDev& d = m->d;
   const HmMesh& H = *m->hm;
@@ -856,8 +854,7 @@ rfcmp_status hm_aca(rfcmp_op op, bool hw, hipStream_t s) {
       for (size_t q = 0; q + 1 < pass_start.size(); ++q) {
         const int64_t b0 = pass_start[q], b1 = pass_start[q + 1];
         if (b1 <= b0) continue;
-        void (*kern)(const AcaArgs, int) =
-            kind == 0 ? (hw ? k_aca<0, true> : k_aca<0, false>) : (hw ? k_aca<1, true> : k_aca<1, false>);
+        void (*kern)(const AcaArgs, int) = kind == 0 ? k_aca<0> : k_aca<1>;
         hipLaunchKernelGGL(kern, dim3((unsigned)(b1 - b0)), dim3(kAcaThreads), 0, s, a, (int)b0);
         RF_HIP(hipGetLastError());
         RF_HIP(hipMemcpyAsync(hr.data() + b0, rk.as<int>() + b0, sizeof(int) * (b1 - b0), hipMemcpyDeviceToHost, s));
