@@ -179,6 +179,18 @@ typedef struct {
                              precision 0; rfcmp_op_export writes the compressed
                              blocks out dense.  RFCMP_E_STATE if a block needs a
                              rank above 128. */
+  int32_t block_cg;       /* 0: the right-hand sides of a solve run as
+                             independent CGs that share each operator pass;
+                             1: one CG over a shared block Krylov space (block
+                             CG with orthonormalised search blocks, rank-
+                             revealing: columns that lose rank are dropped from
+                             the search block), which takes fewer iterations
+                             when many right-hand sides are solved together;
+                             -1 (default): 1 for solves of 8 or more right-hand
+                             sides, else 0.  In block mode the Lanczos
+                             condition estimate is not formed (cond_estimate
+                             = 0) and every right-hand side reports the block's
+                             iteration count. */
 } rfcmp_options;
 rfcmp_status rfcmp_options_default(rfcmp_options* opt);
 

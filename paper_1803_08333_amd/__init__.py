@@ -59,7 +59,7 @@ class Options(ctypes.Structure):
                 ("scaling", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("power_tol", ctypes.c_double),
                 ("streams", ctypes.c_int32), ("projector", ctypes.c_int32), ("graphs", ctypes.c_int32),
-                ("aca_tol", ctypes.c_double)]
+                ("aca_tol", ctypes.c_double), ("block_cg", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

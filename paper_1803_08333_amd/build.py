@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librfcmp.so")
-SOURCES = ["devmem.cpp", "mesh.cpp", "spchol.cpp", "hmtree.cpp", "hmat.hip", "assemble.hip", "dense.hip", "symv.hip", "vecops.hip", "gemm.hip", "zgemm.hip",
+SOURCES = ["devmem.cpp", "mesh.cpp", "spchol.cpp", "hmtree.cpp", "hmat.hip", "blockcg.hip", "assemble.hip", "dense.hip", "symv.hip", "vecops.hip", "gemm.hip", "zgemm.hip",
            "spsolve.hip", "rfcmp.hip"]
 ARCH = "gfx950"
 

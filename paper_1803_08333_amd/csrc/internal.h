@@ -270,6 +270,7 @@ struct rfcmp_op_s {
   // compressed blocks (options.aca_tol > 0): T_A and V live here, TA and Vb
   // stay empty
   std::unique_ptr<rfcmp::HmOp> hm;
+  rfcmp::DevBuf bcg_scratch;   // block CG: Gram results, small matrices, Gram partials
 };
 
 namespace rfcmp {

@@ -101,7 +101,7 @@ def test_options_defaults():
     o = rf.options()
     assert (o.near_factor, o.outer_star, o.scaling, o.power_iters, o.precision, o.power_tol, o.streams) == \
         (2.0, 0, 0, 30, 0, 1e-2, 4)
-    assert (o.projector, o.graphs, o.aca_tol) == (0, 0, 0.0)
+    assert (o.projector, o.graphs, o.aca_tol, o.block_cg) == (0, 0, 0.0, -1)
 
 
 def test_rhs_gap_argument_errors():
@@ -141,6 +141,10 @@ def test_create_many_argument_errors():
         st = rf.lib.rfcmp_op_create_many(m.handle, ks.ctypes.data_as(rf._PD), 2, ctypes.byref(o), None, None, out)
         assert st == -1 and b"streams" in rf.lib.rfcmp_last_error() and not out[0] and not out[1]
     # compressed blocks: a tolerance in [0, 1), and precision 0 only
+    for kw in ({"block_cg": 2}, {"block_cg": -2}):
+        o = rf.options(scaling=1, **kw)
+        st = rf.lib.rfcmp_op_create_many(m.handle, ks.ctypes.data_as(rf._PD), 2, ctypes.byref(o), None, None, out)
+        assert st == -1 and b"block_cg" in rf.lib.rfcmp_last_error() and not out[0] and not out[1]
     for kw in ({"aca_tol": -1e-4}, {"aca_tol": 1.0}, {"aca_tol": float("nan")}, {"aca_tol": 1e-4, "precision": 1}):
         o = rf.options(scaling=1, **kw)
         st = rf.lib.rfcmp_op_create_many(m.handle, ks.ctypes.data_as(rf._PD), 2, ctypes.byref(o), None, None, out)
