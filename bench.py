@@ -66,6 +66,8 @@ def parse():
                    help="skip the uneven batch (32 objects x 8 wavenumbers x 4 plane waves, BF16x3)")
     p.add_argument("--no-compressed-study", action="store_true",
                    help="skip the compressed operator (ACA) at icosphere levels 5-7")
+    p.add_argument("--compressed-only", type=int, nargs="+", default=None, metavar="LEVEL",
+                   help="only the compressed-operator study, at these icosphere levels (8 waves each)")
     p.add_argument("--uneven-batch-serial", action="store_true",
                    help="also time the uneven batch with one rfcmp_solve per operator")
     p.add_argument("--copy-calibration", action="store_true",
@@ -747,6 +749,9 @@ def main():
     import paper_1803_08333_amd as rf
 
     torch.cuda.init()
+    if args.compressed_only:
+        print(json.dumps(compressed_study(rf, torch, levels=tuple((lv, 8) for lv in args.compressed_only))))
+        return
     head = run_workload(rf, torch, WORKLOADS["icosphere5_64rhs"], args.steps, args.warmup, "icosphere5_64rhs")
     sweep = run_workload(rf, torch, WORKLOADS["icosphere4_two_k"], max(args.steps, 5), args.warmup,
                          "icosphere4_two_k")
