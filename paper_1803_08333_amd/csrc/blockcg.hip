@@ -4,7 +4,7 @@
 // (both blocks staged in LDS, rows fastest, so a wave reads its X entry as a
 // broadcast and neighbouring lanes neighbouring Y entries), thread t owning
 // the outputs (i, j) = (t / 64 + 4 q, t % 64); the partials of the
-// workgroups are added in workgroup order by a second kernel.
+// workgroups are added in a fixed order by a second kernel.
 // Update: one thread per row and group of 8 output columns, the small
 // matrix in LDS.
 #include "blockcg.h"
@@ -53,17 +53,25 @@ __global__ __launch_bounds__(256) void k_gram_part(const double2* __restrict__ X
   }
 }
 
-__global__ void k_gram_sum(int a, int b, int groups, const double2* __restrict__ part, double2* __restrict__ C) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per output: lane l adds the partials of workgroups l, l + 64, ...
+// in order, then the lanes are combined by a fixed butterfly (lane 0's
+// value is stored).
+__global__ __launch_bounds__(256) void k_gram_sum(int a, int b, int groups, const double2* __restrict__ part,
+                                                  double2* __restrict__ C) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (o >= a * b) return;
   const int i = o / b, j = o % b;
   double sr = 0.0, si = 0.0;
-  for (int g = 0; g < groups; ++g) {
+  for (int g = lane; g < groups; g += 64) {
     const double2 v = part[(long)g * kBlockMax * kBlockMax + i * kBlockMax + j];
     sr += v.x;
     si += v.y;
   }
-  C[o] = make_double2(sr, si);
+  for (int m = 32; m > 0; m >>= 1) {
+    sr += __shfl_xor(sr, m);
+    si += __shfl_xor(si, m);
+  }
+  if (lane == 0) C[o] = make_double2(sr, si);
 }
 
 constexpr int kTsmmCols = 8;
@@ -122,7 +130,7 @@ rfcmp_status gram_c128(const double2* X, int a, const double2* Y, int b, int64_t
   double2* part = static_cast<double2*>(scratch);
   ProfScope prof("block_gram", s);
   hipLaunchKernelGGL(k_gram_part, dim3(kGramGroups), dim3(256), 0, s, X, a, Y, b, (long)N, part);
-  hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)((a * b + 255) / 256)), dim3(256), 0, s, a, b, kGramGroups, part, C);
+  hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)((a * b + 3) / 4)), dim3(256), 0, s, a, b, kGramGroups, part, C);
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
 }
