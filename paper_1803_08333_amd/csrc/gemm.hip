@@ -305,10 +305,24 @@ rfcmp_status gemm_bf16x3(const SplitMatrix& M, bool conj_m, const double2* X, do
     const int ncp = (int)round_up(2 * nr, 32);
     const int nct = ncp / 32;
     const long nrb = (long)(M.rows_pad / kRowsWG);
-    // split K so that the grid holds about one workgroup per compute unit
-    // (each holds one workgroup: the accumulators and two register sets of
-    // matrix rows fill the register file)
-    long nslice = std::max(1L, std::min(16L, (256 + nrb / 2) / nrb));
+    // split K so that the grid fills the compute units, one workgroup each
+    // (the accumulators and two register sets of matrix rows fill the
+    // register file): the fewest slices (at most 16) for which the last
+    // round of workgroups keeps at least 90 % of the units busy, else the
+    // fullest last round
+    long nslice = 1;
+    {
+      double best = 0.0;
+      for (long ns = 1; ns <= 16; ++ns) {
+        const long wg = nrb * ns;
+        const double fill = (double)wg / (256.0 * (double)((wg + 255) / 256));
+        if (fill > best + 1e-9) {
+          best = fill;
+          nslice = ns;
+        }
+        if (fill >= 0.9) break;
+      }
+    }
     long kslice = (long)round_up((M.kpad + nslice - 1) / nslice, kKpad);
     nslice = (M.kpad + kslice - 1) / kslice;
     const int npl = M.cplx ? 2 : 1;

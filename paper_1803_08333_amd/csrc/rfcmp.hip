@@ -116,9 +116,9 @@ rfcmp_status ensure_sp_scratch(rfcmp_op op) {
 }
 
 // Scratch of the FP64 multi-right-hand-side products (zgemm_c64): sized
-// for the larger block, T_A (n = N).
+// for both blocks (the slice count depends on the order).
 rfcmp_status ensure_z_scratch(rfcmp_op op) {
-  const size_t need = zgemm_scratch_bytes(std::max(op->mesh->h.N, op->mesh->h.C));
+  const size_t need = std::max(zgemm_scratch_bytes(op->mesh->h.N), zgemm_scratch_bytes(op->mesh->h.C));
   if (op->z_scratch.bytes >= need) return RFCMP_OK;
   if (op->z_scratch.p) RF_HIP(hipDeviceSynchronize());  // the old scratch may still be in use
   return op->z_scratch.alloc(need);

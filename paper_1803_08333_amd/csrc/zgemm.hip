@@ -4,21 +4,30 @@
 // products of T_A and V (the refinement residual, the right-hand side, the
 // FP32-path iterations) once there are enough right-hand sides that the
 // products are bound by FP64 arithmetic rather than by the matrix stream:
-// with 16 right-hand sides a pass does 128 flops per matrix entry (8 bytes),
+// with 32 right-hand sides a pass does 192 flops per matrix entry (8 bytes),
 // where the symmetric streaming product (symv.hip) can take 4.
 //
-// Real form: with M = Mr + i Mi and X = Xr + i Xi,
-//   [Yr | Yi] = Mr [Xr | Xi] + Mi [-Xi | Xr],
-// so a group of 8 right-hand sides is one 16-column MFMA operand pair.  A
-// workgroup (4 waves) owns 128 rows over one K slice; wave w takes rows
-// 32 w .. 32 w + 31 as two 16-row tiles, both groups of 8 right-hand sides
-// (two waves fit a SIMD).  Per 32-column chunk each lane loads 8 consecutive
-// complex64 entries of each of its rows (64 contiguous bytes: a wave reads
-// 16 rows x 256 bytes per tile), and MFMA step e uses entry e, so that the k index of lane l at
-// step e is chunk column 8 (l / 16) + e; the X chunk sits in LDS in the same
-// order, one 512-byte conflict-free wave read per operand.  Partial sums of
-// the K slices go to a buffer [slice][16][n] (complex128); a second kernel
-// adds the slices in order (the result does not depend on timing).
+// Three real products per complex one (Gauss): with M = Mr + i Mi and
+// X = Xr + i Xi,
+//   P1 = Mr Xr,  P2 = Mi Xi,  P3 = (Mr + Mi)(Xr + Xi),
+//   Re Y = P1 - P2,  Im Y = P3 - P1 - P2,
+// so 16 right-hand sides take three 16-column MFMA operands where the
+// four-product form takes four.  In FP64 the extra rounding of the sums is
+// of order 1e-16 relative to |M| |X|, far below the complex64 storage of M.
+// A launch serves NG groups of 16 right-hand sides (NG = 2 from 17 on), so
+// that each pass over the matrix does 3 NG MFMAs per K step.
+//
+// A workgroup (4 waves) owns 64 rows over one K slice; wave w takes rows
+// 16 w .. 16 w + 15 (two waves fit a SIMD with 32 right-hand sides, three
+// with 16; measured, one 16-row tile per wave beats two by a fifth: the
+// occupancy matters more than the reuse of the X operands).  Per 32-column
+// chunk each lane loads 8 consecutive complex64 entries of its row (64
+// contiguous bytes: a wave reads 16 rows x 256 bytes), and MFMA step e uses
+// entry e, so that the k index of lane l at step e is chunk column
+// 8 (l / 16) + e; the X chunk sits in LDS in the same order, one 512-byte
+// conflict-free wave read per operand.  Partial sums of the K slices go to a
+// buffer [slice][32][n] (complex128); a second kernel adds the slices in
+// order (the result does not depend on timing).
 #include "internal.h"
 #include "gemm.h"
 
@@ -30,41 +39,42 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
 constexpr int kZThreads = 256;
-constexpr int kZTiles = 2;                     // 16-row tiles per wave
+constexpr int kZTiles = 1;                     // 16-row tiles per wave
 constexpr int kZRowsWave = 16 * kZTiles;
 constexpr int kZRows = 4 * kZRowsWave;         // rows per workgroup
 constexpr int kZK = 32;                        // K chunk
-constexpr int kZRhs = 16;                      // right-hand sides per launch
+constexpr int kZRhs = 32;                      // right-hand sides per launch (at most)
 
-// lds[b][t][e][l]: operand b (0: [Xr | Xi], 1: [-Xi | Xr]) of right-hand-side
-// group t at step e for lane l
+// lds[g][b][e][l]: operand b (0: Xr, 1: Xi, 2: Xr + Xi) of group g at step
+// e for lane l (chunk column 8 (l / 16) + e, right-hand side 16 g + l % 16)
+template <int NG>
 struct ZStage {
-  double v[2][2][8][64];
+  double v[NG][3][8][64];
 };
 
-// X chunk into the operand order: lane ll of step e takes chunk column
-// 8 (ll / 16) + e and right-hand side 8 t + ll % 8 (Re for ll % 16 < 8).
-// The loads go to registers first (z_load_x, before the products of the
-// current chunk) and to LDS after them (z_store_x).
-constexpr int kZXPerThread = 2 * 8 * 64 / kZThreads;
-__device__ inline void z_load_x(double2 (&xr)[kZXPerThread], const double2* __restrict__ X, int n, int nr, int kc,
+// X chunk into the operand order.  The loads go to registers first
+// (z_load_x, before the products of the current chunk) and to LDS after
+// them (z_store_x).
+template <int NG>
+__device__ inline void z_load_x(double2 (&xr)[2 * NG], const double2* __restrict__ X, int n, int nr, int kc,
                                 int k_end, int tid) {
 #pragma unroll
-  for (int u = 0; u < kZXPerThread; ++u) {
+  for (int u = 0; u < 2 * NG; ++u) {
     const int idx = tid + u * kZThreads;
-    const int t = idx / 512, e = (idx / 64) % 8, ll = idx % 64;
-    const int k = kc + 8 * (ll / 16) + e, r = 8 * t + (ll % 8);
+    const int g = idx / 512, e = (idx / 64) % 8, ll = idx % 64;
+    const int k = kc + 8 * (ll / 16) + e, r = 16 * g + ll % 16;
     xr[u] = (r < nr && k < k_end) ? X[(long)r * n + k] : make_double2(0.0, 0.0);
   }
 }
-__device__ inline void z_store_x(ZStage& st, const double2 (&xr)[kZXPerThread], int tid) {
+template <int NG>
+__device__ inline void z_store_x(ZStage<NG>& st, const double2 (&xr)[2 * NG], int tid) {
 #pragma unroll
-  for (int u = 0; u < kZXPerThread; ++u) {
+  for (int u = 0; u < 2 * NG; ++u) {
     const int idx = tid + u * kZThreads;
-    const int t = idx / 512, e = (idx / 64) % 8, ll = idx % 64;
-    const bool re = (ll % 16) < 8;
-    st.v[0][t][e][ll] = re ? xr[u].x : xr[u].y;
-    st.v[1][t][e][ll] = re ? -xr[u].y : xr[u].x;
+    const int g = idx / 512, e = (idx / 64) % 8, ll = idx % 64;
+    st.v[g][0][e][ll] = xr[u].x;
+    st.v[g][1][e][ll] = xr[u].y;
+    st.v[g][2][e][ll] = xr[u].x + xr[u].y;
   }
 }
 
@@ -91,87 +101,91 @@ __device__ inline void z_load_m(float2 (&av)[kZTiles][8], const float2* __restri
   }
 }
 
-template <bool CONJ>
-__device__ inline void z_mfma(dbl4 (&acc)[kZTiles][2], const float2 (&av)[kZTiles][8], const ZStage& st, int lane) {
+template <bool CONJ, int NG>
+__device__ inline void z_mfma(dbl4 (&acc)[kZTiles][NG][3], const float2 (&av)[kZTiles][8], const ZStage<NG>& st,
+                              int lane) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const double b10 = st.v[0][0][e][lane], b20 = st.v[1][0][e][lane];
-    const double b11 = st.v[0][1][e][lane], b21 = st.v[1][1][e][lane];
-    double mr[kZTiles], mi[kZTiles];
+    double xb[NG][3];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) xb[g][b] = st.v[g][b][e][lane];
+    double mb[3][kZTiles];
 #pragma unroll
     for (int a = 0; a < kZTiles; ++a) {
-      mr[a] = (double)av[a][e].x;
-      mi[a] = CONJ ? -(double)av[a][e].y : (double)av[a][e].y;
+      mb[0][a] = (double)av[a][e].x;
+      mb[1][a] = CONJ ? -(double)av[a][e].y : (double)av[a][e].y;
+      mb[2][a] = mb[0][a] + mb[1][a];
     }
-    // the Re-part products of all the accumulators, then the Im-part ones:
-    // each accumulator's two products are 2 kZTiles instructions apart
+    // each accumulator is taken once per step, 3 NG kZTiles instructions apart
 #pragma unroll
-    for (int a = 0; a < kZTiles; ++a) {
-      acc[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(mr[a], b10, acc[a][0], 0, 0, 0);
-      acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(mr[a], b11, acc[a][1], 0, 0, 0);
-    }
+    for (int b = 0; b < 3; ++b)
 #pragma unroll
-    for (int a = 0; a < kZTiles; ++a) {
-      acc[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(mi[a], b20, acc[a][0], 0, 0, 0);
-      acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(mi[a], b21, acc[a][1], 0, 0, 0);
-    }
+      for (int a = 0; a < kZTiles; ++a)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+          acc[a][g][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(mb[b][a], xb[g][b], acc[a][g][b], 0, 0, 0);
   }
 }
 
 // Two chunks in flight: the loads of chunk c + 1 (matrix into registers, X
 // into the other LDS stage) are issued before the products of chunk c.
-template <bool CONJ>
+template <bool CONJ, int NG>
 __global__ __launch_bounds__(kZThreads) void k_zgemm(const float2* __restrict__ M, int n, long ld,
                                                      const double2* __restrict__ X, int nr, int kslice,
                                                      double2* __restrict__ part) {
-  __shared__ ZStage st[2];
+  __shared__ ZStage<NG> st[2];
   const int rb = blockIdx.x, ks = blockIdx.y;
   const int k_begin = ks * kslice, k_end = min(n, k_begin + kslice);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int row0 = rb * kZRows + w * kZRowsWave + (lane & 15);
-  dbl4 acc[kZTiles][2];
+  dbl4 acc[kZTiles][NG][3];
 #pragma unroll
   for (int a = 0; a < kZTiles; ++a)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) acc[a][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc[a][g][b] = dbl4{0.0, 0.0, 0.0, 0.0};
   float2 va[kZTiles][8], vb[kZTiles][8];
-  double2 xr[kZXPerThread];
+  double2 xr[2 * NG];
   z_load_m(va, M, n, ld, row0, k_begin, k_end, lane);
-  z_load_x(xr, X, n, nr, k_begin, k_end, tid);
-  z_store_x(st[0], xr, tid);
+  z_load_x<NG>(xr, X, n, nr, k_begin, k_end, tid);
+  z_store_x<NG>(st[0], xr, tid);
   __syncthreads();
   for (int kc = k_begin; kc < k_end; kc += 2 * kZK) {
     const int k1 = kc + kZK, k2 = kc + 2 * kZK;
     if (k1 < k_end) {
       z_load_m(vb, M, n, ld, row0, k1, k_end, lane);
-      z_load_x(xr, X, n, nr, k1, k_end, tid);
+      z_load_x<NG>(xr, X, n, nr, k1, k_end, tid);
     }
-    z_mfma<CONJ>(acc, va, st[0], lane);
+    z_mfma<CONJ, NG>(acc, va, st[0], lane);
     __builtin_amdgcn_sched_barrier(0);  // the X stores wait for their loads here, after the products
-    if (k1 < k_end) z_store_x(st[1], xr, tid);
+    if (k1 < k_end) z_store_x<NG>(st[1], xr, tid);
     __syncthreads();  // stage 1 written, stage 0 read
     if (k1 >= k_end) break;
     if (k2 < k_end) {
       z_load_m(va, M, n, ld, row0, k2, k_end, lane);
-      z_load_x(xr, X, n, nr, k2, k_end, tid);
+      z_load_x<NG>(xr, X, n, nr, k2, k_end, tid);
     }
-    z_mfma<CONJ>(acc, vb, st[1], lane);
+    z_mfma<CONJ, NG>(acc, vb, st[1], lane);
     __builtin_amdgcn_sched_barrier(0);
-    if (k2 < k_end) z_store_x(st[0], xr, tid);
+    if (k2 < k_end) z_store_x<NG>(st[0], xr, tid);
     __syncthreads();  // stage 0 written, stage 1 read
   }
-  // accumulator value v of lane l: row 4 v + l / 16 of the tile, column
-  // l % 16 (Re of right-hand side l % 8 below 8, Im above)
-  double* pd = reinterpret_cast<double*>(part + (long)ks * kZRhs * n);
+  // accumulator value v of lane l: row 4 v + l / 16 of the tile,
+  // right-hand side 16 g + l % 16
+  double2* pd = part + (long)ks * kZRhs * n;
 #pragma unroll
   for (int a = 0; a < kZTiles; ++a)
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int g = 0; g < NG; ++g)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = rb * kZRows + w * kZRowsWave + 16 * a + 4 * v + (lane >> 4);
-        const int col = lane & 15, r = 8 * t + (col % 8);
-        if (row < n && r < nr) pd[((long)r * n + row) * 2 + (col >= 8 ? 1 : 0)] = acc[a][t][v];
+        const int r = 16 * g + (lane & 15);
+        const double p1 = acc[a][g][0][v], p2 = acc[a][g][1][v], p3 = acc[a][g][2][v];
+        if (row < n && r < nr) pd[(long)r * n + row] = make_double2(p1 - p2, p3 - p1 - p2);
       }
 }
 
@@ -190,10 +204,11 @@ __global__ __launch_bounds__(256) void k_zgemm_sum(const double2* __restrict__ p
   Y[(long)r * n + i] = s;
 }
 
-// K slices of a launch: enough workgroups for a few per compute unit.
+// K slices of a launch: about 15 workgroups per compute unit (measured at
+// n = 20480 and 30720 against 2-12 slices), at most 16 slices.
 int zgemm_slices(int64_t n) {
   const int64_t rbs = (n + kZRows - 1) / kZRows;
-  return (int)std::min<int64_t>(32, std::max<int64_t>(1, (1024 + rbs - 1) / rbs));
+  return (int)std::min<int64_t>(16, std::max<int64_t>(1, (3840 + rbs / 2) / rbs));
 }
 
 }  // namespace
@@ -219,12 +234,8 @@ rfcmp_status zgemm_c64(const float2* M, int64_t n, int64_t ld, bool conj, const 
   for (int r0 = 0; r0 < nrhs; r0 += kZRhs) {
     const int nr = std::min(kZRhs, nrhs - r0);
     ProfScope prof(profile_tag_suffix(tag, nr), s);
-    if (conj)
-      hipLaunchKernelGGL(k_zgemm<true>, grid, dim3(kZThreads), 0, s, M, (int)n, (long)ld, X + (long)r0 * n, nr,
-                         kslice, part);
-    else
-      hipLaunchKernelGGL(k_zgemm<false>, grid, dim3(kZThreads), 0, s, M, (int)n, (long)ld, X + (long)r0 * n, nr,
-                         kslice, part);
+    auto kern = conj ? (nr > 16 ? k_zgemm<true, 2> : k_zgemm<true, 1>) : (nr > 16 ? k_zgemm<false, 2> : k_zgemm<false, 1>);
+    hipLaunchKernelGGL(kern, grid, dim3(kZThreads), 0, s, M, (int)n, (long)ld, X + (long)r0 * n, nr, kslice, part);
     hipLaunchKernelGGL(k_zgemm_sum, dim3((unsigned)(((long)nr * n + 255) / 256)), dim3(256), 0, s, part, (int)n, nr,
                        nsl, Y + (long)r0 * n);
   }
