@@ -179,11 +179,11 @@ TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     "icosphere5_64rhs": {
         "gemm_ta": {"source": "paper_1803_08333_amd/csrc/gemm.hip",
-                    "sha256": "9f0a0dc1bfe9df630a71b2511dd9fbb18d9fa9fe0bbc67db6126874dd01a20cc",
-                    "kib": (3747942.2, 30720.0)},
-        "zgemm_ta_nr16": {"source": "paper_1803_08333_amd/csrc/zgemm.hip",
-                          "sha256": "b5664302b0462033016131216b3dbd3467828f3d930645ce8018e85d147c534d",
-                          "kib": (3874452.7, 38400.0)},
+                    "sha256": "3f96710cb02860e6d46c1cf43c138db87da07e797632cf00169541bba40dad57",
+                    "kib": (3747947.5, 30720.0)},
+        "zgemm_ta_nr32": {"source": "paper_1803_08333_amd/csrc/zgemm.hip",
+                          "sha256": "6c2552a624e26ee57abf050493d1670743d56309a031422a97aaa2522169ef24",
+                          "kib": (3976700.9, 122880.1)},
     },
 }
 
