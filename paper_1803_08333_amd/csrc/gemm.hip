@@ -379,6 +379,7 @@ MeshDev::~MeshDev() {
 rfcmp_op_s::rfcmp_op_s() = default;
 rfcmp_op_s::~rfcmp_op_s() {
   if (host_scal) (void)hipHostFree(host_scal);
+  if (bcg_host) (void)hipHostFree(bcg_host);
   for (int q = 0; q < 2; ++q)
     if (cg_exec[q]) (void)hipGraphExecDestroy(cg_exec[q]);
   if (cg_stream) {

@@ -270,7 +270,9 @@ struct rfcmp_op_s {
   // compressed blocks (options.aca_tol > 0): T_A and V live here, TA and Vb
   // stay empty
   std::unique_ptr<rfcmp::HmOp> hm;
-  rfcmp::DevBuf bcg_scratch;   // block CG: Gram results, small matrices, Gram partials
+  rfcmp::DevBuf bcg_scratch;   // block CG: small matrices, Gram partials
+  double2* bcg_host = nullptr;      // block CG: pinned and mapped Gram results, upload staging, norms
+  double2* bcg_host_dev = nullptr;  // its device address
 };
 
 namespace rfcmp {

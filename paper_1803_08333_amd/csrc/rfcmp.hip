@@ -922,98 +922,114 @@ rfcmp_status block_cg_shared(const Dense& D, const Work& W, int nr, const double
   const int64_t N = op->mesh->h.N;
   const int64_t NR = (int64_t)nr * N;
   for (int r = 0; r < nr; ++r) iters[r] = 0;
-  const size_t small = sizeof(double2) * kBlockMax * kBlockMax;
-  const size_t need = 3 * small + gram_scratch_bytes(N);
+  constexpr size_t kSm = (size_t)kBlockMax * kBlockMax;  // entries of one small matrix
+  const size_t need = 3 * sizeof(double2) * kSm + gram_scratch_bytes(N);
   if (op->bcg_scratch.bytes < need) RF_TRY(op->bcg_scratch.alloc(need));
-  double2* dC = op->bcg_scratch.as<double2>();            // Gram results [a][b]
-  double2* dS = dC + kBlockMax * kBlockMax;                // small matrices for the updates
-  double2* dT = dS + kBlockMax * kBlockMax;
-  void* gscr = dT + kBlockMax * kBlockMax;
-  const size_t gbytes = op->bcg_scratch.bytes - 3 * small;
-  auto to_host = [&](const double2* d, int cnt, std::vector<cplx>& h) -> rfcmp_status {
-    std::vector<double2> t(cnt);
-    RF_HIP(hipMemcpyAsync(t.data(), d, sizeof(double2) * cnt, hipMemcpyDeviceToHost, s));
+  double2* dS = op->bcg_scratch.as<double2>();  // small matrices of the updates, one per use
+  double2* dT = dS + kSm;
+  double2* dU = dT + kSm;
+  void* gscr = dU + kSm;
+  const size_t gbytes = op->bcg_scratch.bytes - 3 * sizeof(double2) * kSm;
+  // Host side of an iteration: three waits on the stream.  The Gram results
+  // and the norms are written by the device straight into mapped pinned
+  // memory (slots 0-2, norms after slot 5); the small matrices go up by
+  // asynchronous copies from pinned slots 3-5, each slot rewritten only after
+  // a later wait, when its copy has completed.
+  if (!op->bcg_host) {
+    RF_HIP(hipHostMalloc((void**)&op->bcg_host, sizeof(double2) * (6 * kSm + kBlockMax), hipHostMallocMapped));
+    RF_HIP(hipHostGetDevicePointer((void**)&op->bcg_host_dev, op->bcg_host, 0));
+  }
+  double2* hslot[6];
+  double2* dslot[6];
+  for (int q = 0; q < 6; ++q) {
+    hslot[q] = op->bcg_host + q * kSm;
+    dslot[q] = op->bcg_host_dev + q * kSm;
+  }
+  const double* hrn = reinterpret_cast<const double*>(op->bcg_host + 6 * kSm);
+  double* drn = reinterpret_cast<double*>(op->bcg_host_dev + 6 * kSm);
+  auto wait = [&]() -> rfcmp_status {
     RF_HIP(hipStreamSynchronize(s));
+    return RFCMP_OK;
+  };
+  auto read = [&](int slot, int cnt, std::vector<cplx>& h) {
     h.resize(cnt);
-    for (int i = 0; i < cnt; ++i) h[i] = cplx(t[i].x, t[i].y);
-    return RFCMP_OK;
+    for (int i = 0; i < cnt; ++i) h[i] = cplx(hslot[slot][i].x, hslot[slot][i].y);
   };
-  auto to_dev = [&](const std::vector<cplx>& h, double2* d) -> rfcmp_status {
-    std::vector<double2> t(h.size());
+  auto upload = [&](const std::vector<cplx>& h, int slot, double2* d) -> rfcmp_status {
+    double2* t = hslot[slot];
     for (size_t i = 0; i < h.size(); ++i) t[i] = make_double2(h[i].real(), h[i].imag());
-    RF_HIP(hipMemcpyAsync(d, t.data(), sizeof(double2) * t.size(), hipMemcpyHostToDevice, s));
-    RF_HIP(hipStreamSynchronize(s));  // t goes out of scope
+    RF_HIP(hipMemcpyAsync(d, t, sizeof(double2) * h.size(), hipMemcpyHostToDevice, s));
     return RFCMP_OK;
   };
-  auto norms = [&](const double2* v, int cnt, std::vector<double>& out) -> rfcmp_status {
-    RF_TRY(dot(N, v, v, W.part, W.dout, cnt, s));
-    std::vector<double2> t(cnt);
-    RF_HIP(hipMemcpyAsync(t.data(), W.dout, sizeof(double2) * cnt, hipMemcpyDeviceToHost, s));
-    RF_HIP(hipStreamSynchronize(s));
-    out.resize(cnt);
-    for (int i = 0; i < cnt; ++i) out[i] = std::sqrt(std::max(t[i].x, 0.0));
-    return RFCMP_OK;
+  std::vector<double> rn(nr);
+  auto take_norms = [&]() {
+    for (int r = 0; r < nr; ++r) rn[r] = std::sqrt(std::max(hrn[r], 0.0));
   };
-  constexpr double kDrop = 1e-14;  // pivots below this fraction of the largest diagonal (norms below 1e-7)
-  RF_HIP(hipMemsetAsync(W.x, 0, sizeof(double2) * NR, s));
-  RF_HIP(hipMemcpyAsync(W.r, W.b, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
-  std::vector<double> rn;
-  RF_TRY(norms(W.r, nr, rn));
   auto done = [&]() {
     for (int r = 0; r < nr; ++r)
       if (!(rn[r] <= target[r])) return false;
     return true;
   };
-  if (done()) return RFCMP_OK;
+  constexpr double kDrop = 1e-14;  // pivots below this fraction of the largest diagonal (norms below 1e-7)
+  RF_HIP(hipMemsetAsync(W.x, 0, sizeof(double2) * NR, s));
+  RF_HIP(hipMemcpyAsync(W.r, W.b, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
   // P = R S: orthonormal basis of the residuals
+  RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, s, nullptr, drn));
+  RF_TRY(gram_c128(W.r, nr, W.r, nr, N, dslot[0], gscr, gbytes, s));
+  RF_TRY(wait());
+  take_norms();
+  if (done()) return RFCMP_OK;
   std::vector<cplx> G, S, M, C2, C3, A1, T;
-  RF_TRY(gram_c128(W.r, nr, W.r, nr, N, dC, gscr, gbytes, s));
-  RF_TRY(to_host(dC, nr * nr, G));
+  read(0, nr * nr, G);
   int p = orth_transform(G, nr, kDrop, S);
   if (p == 0) return RFCMP_OK;
-  RF_TRY(to_dev(S, dS));
-  RF_TRY(tsmm_c128(W.r, nr, dS, p, N, W.p, 1.0, false, s));
+  RF_TRY(upload(S, 5, dU));
+  RF_TRY(tsmm_c128(W.r, nr, dU, p, N, W.p, 1.0, false, s));
   int it = 0;
   while (it < maxit) {
     RF_TRY(apply_batch(D, W, W.p, W.q, p));   // Q = A P
     ++it;
-    RF_TRY(gram_c128(W.p, p, W.q, p, N, dC, gscr, gbytes, s));
-    RF_TRY(to_host(dC, p * p, M));
+    RF_TRY(gram_c128(W.p, p, W.q, p, N, dslot[0], gscr, gbytes, s));
+    RF_TRY(gram_c128(W.p, p, W.r, nr, N, dslot[1], gscr, gbytes, s));
+    RF_TRY(wait());
+    read(0, p * p, M);
     for (int i = 0; i < p; ++i)  // Hermitian part (the products are Hermitian to rounding)
       for (int j = 0; j <= i; ++j) {
         const cplx h = 0.5 * (M[i * p + j] + std::conj(M[j * p + i]));
         M[i * p + j] = h;
         M[j * p + i] = std::conj(h);
       }
-    RF_TRY(gram_c128(W.p, p, W.r, nr, N, dC, gscr, gbytes, s));
-    RF_TRY(to_host(dC, p * nr, C2));
+    read(1, p * nr, C2);
     if (!hpd_solve(M, p, C2, nr, A1)) {
       set_error("block CG breakdown at iteration %d: P^H A P not positive definite", it);
       return RFCMP_E_BREAKDOWN;
     }
-    RF_TRY(to_dev(A1, dS));
+    RF_TRY(upload(A1, 3, dS));
     RF_TRY(tsmm_c128(W.p, p, dS, nr, N, W.x, 1.0, true, s));    // X += P alpha
     RF_TRY(tsmm_c128(W.q, p, dS, nr, N, W.r, -1.0, true, s));   // R -= Q alpha
-    RF_TRY(norms(W.r, nr, rn));
+    RF_TRY(dot(N, W.r, W.r, W.part, W.dout, nr, s, nullptr, drn));
+    RF_TRY(gram_c128(W.q, p, W.r, nr, N, dslot[2], gscr, gbytes, s));
+    RF_TRY(wait());
+    take_norms();
     for (int r = 0; r < nr; ++r) iters[r] = it;
     if (done() || it >= maxit) break;
     // Y = R - P M^-1 Q^H R into W.q (Q is not needed any more)
-    RF_TRY(gram_c128(W.q, p, W.r, nr, N, dC, gscr, gbytes, s));
-    RF_TRY(to_host(dC, p * nr, C3));
+    read(2, p * nr, C3);
     if (!hpd_solve(M, p, C3, nr, T)) {
       set_error("block CG breakdown at iteration %d: P^H A P not positive definite", it);
       return RFCMP_E_BREAKDOWN;
     }
-    RF_TRY(to_dev(T, dT));
+    RF_TRY(upload(T, 4, dT));
     RF_HIP(hipMemcpyAsync(W.q, W.r, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
     RF_TRY(tsmm_c128(W.p, p, dT, nr, N, W.q, -1.0, true, s));
     // P = Y S, orthonormal
-    RF_TRY(gram_c128(W.q, nr, W.q, nr, N, dC, gscr, gbytes, s));
-    RF_TRY(to_host(dC, nr * nr, G));
+    RF_TRY(gram_c128(W.q, nr, W.q, nr, N, dslot[0], gscr, gbytes, s));
+    RF_TRY(wait());
+    read(0, nr * nr, G);
     p = orth_transform(G, nr, kDrop, S);
     if (p == 0) break;
-    RF_TRY(to_dev(S, dS));
-    RF_TRY(tsmm_c128(W.q, nr, dS, p, N, W.p, 1.0, false, s));
+    RF_TRY(upload(S, 5, dU));
+    RF_TRY(tsmm_c128(W.q, nr, dU, p, N, W.p, 1.0, false, s));
   }
   return RFCMP_OK;
 }
