@@ -544,17 +544,30 @@ def kernel_model(tag, avg_ms, sz, nrhs):
         # the matrix cores execute three real products per complex one
         # (Gauss), over 16 or 32 columns
         mf = 6.0 * n * n * (16 if nr <= 16 else 32)
+        byt = 8.0 * n * n + 32.0 * n * nr
         return {"bound": "mfma", "achieved": fl / sec / 1e12, "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "algorithmic_flops": fl, "mfma_flops": mf, "mfma_tflops": mf / sec / 1e12,
-                "matrix_bytes": 8.0 * n * n, "hbm_gbs": 8.0 * n * n / sec / 1e9}
+                "algorithmic_bytes": byt, "matrix_bytes": 8.0 * n * n, "hbm_gbs": 8.0 * n * n / sec / 1e9,
+                "floor_ms": {"hbm": byt / (HBM_GBS * 1e9) * 1e3, "mfma": fl / (FP64_MFMA_TFLOPS * 1e12) * 1e3}}
     if name.startswith("gemm_"):
         n = {"gemm_ta": N, "gemm_v": C, "gemm_lp": C, "gemm_gll": V, "gemm_gtp": C}.get(name)
         if n is None:
             return None
         fl = 24.0 * n * n * nrhs
-        return {"bound": "mfma", "achieved": fl / sec / 1e12, "peak": BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "algorithmic_flops": fl / 3.0, "mfma_flops": fl, "matrix_bytes": 8.0 * n * n,
-                "hbm_gbs": 8.0 * n * n / sec / 1e9}
+        # the bound is the resource whose floor is the longer: the bf16 planes
+        # (8 B per complex entry) plus x read and y written against HBM, or the
+        # three-pass MFMA work against the bf16 peak
+        byt = 8.0 * n * n + 32.0 * n * nrhs
+        t_hbm, t_mfma = byt / (HBM_GBS * 1e9), fl / (BF16_MFMA_TFLOPS * 1e12)
+        out = {"algorithmic_flops": fl / 3.0, "mfma_flops": fl, "mfma_tflops": fl / sec / 1e12,
+               "mfma_frac": fl / sec / 1e12 / BF16_MFMA_TFLOPS, "algorithmic_bytes": byt,
+               "matrix_bytes": 8.0 * n * n, "hbm_gbs": 8.0 * n * n / sec / 1e9,
+               "floor_ms": {"hbm": t_hbm * 1e3, "mfma": t_mfma * 1e3}}
+        if t_hbm >= t_mfma:
+            out.update({"bound": "hbm", "achieved": byt / sec / 1e9, "peak": HBM_GBS, "unit": "GB/s"})
+        else:
+            out.update({"bound": "mfma", "achieved": fl / sec / 1e12, "peak": BF16_MFMA_TFLOPS, "unit": "TFLOP/s"})
+        return out
     if name == "spd_inverse":
         # one launch = one inverse; the L^+ inverse (n = C) is the larger
         byt = (C / 64.0) * 8.0 * C * C

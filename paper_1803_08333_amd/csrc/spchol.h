@@ -80,7 +80,7 @@ constexpr int kSpTile = 64;
 // A factor on the device, in the layout the solve reads.
 //
 // The supernodes split into bottom subtrees (every supernode whose subtree
-// spans at most about n/48 columns, grouped under the highest such
+// spans at most about n/96 columns, grouped under the highest such
 // supernodes) and the top supernodes above them.  A solve is a short chain of
 // launches, each over many workgroups (and right-hand sides):
 //   input: the right-hand side formed (the operator's gathers) and permuted,

@@ -524,8 +524,12 @@ void spchol_arrays(const SpFactor& F, SpArrays& a) {
       for (size_t e = 0; e < src[k].size(); ++e) a.fr_src[(size_t)k * a.fr_k + e] = src[k][e];
   }
   // bottom subtrees: supernodes whose subtree spans at most `cap` columns;
-  // each maximal one is a subtree, its supernodes listed by height
-  const int cap = std::max(256, n / 48);
+  // each maximal one is a subtree, its supernodes listed by height.  n / 96
+  // (about 128 subtrees of a nested dissection): measured against n / 12 to
+  // n / 192 on the level-5 and level-6 spheres, the fastest 64-right-hand-side
+  // Laplacian solve at both levels (0.38 and 1.37 ms against 0.50 and 2.10 at
+  // n / 48) and the fastest G_ll solve at level 6
+  const int cap = std::max(128, n / 96);
   std::vector<int> first(nsn);  // first column of each supernode's subtree
   for (int q = 0; q < nsn; ++q) {
     first[q] = F.col0[q];
