@@ -63,28 +63,52 @@ __device__ inline long frag_offset(long i, long k, long nkc) {
   return (((rb * nkc + kc) * 2 + sub) * 64 + lane) * 8 + e;
 }
 
-// complex64 [n][ld] -> planes [4][rows_pad x kpad], fragment-major.  tri > 0:
-// M is symmetric and only its entries with k >= tri floor(i / tri) are
-// stored; the others are read transposed.
-__global__ void k_split_c64(const float2* __restrict__ M, long n, long ncol, long ld, long tri,
-                            u16* __restrict__ P, long rows_pad, long kpad) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= rows_pad * kpad) return;
-  const long i = t / kpad, k = t % kpad;
-  float re = 0.f, im = 0.f;
-  if (i < n && k < ncol) {
-    const bool lower = tri > 0 && k < (i / tri) * tri;
-    const float2 v = lower ? M[k * ld + i] : M[i * ld + k];
-    re = v.x;
-    im = v.y;
+// complex64 [n][ld] -> planes [4][rows_pad x kpad], fragment-major.  tri > 0
+// (a multiple of 32): M is symmetric and only its entries with
+// k >= tri floor(i / tri) are stored; the others are read transposed.  One
+// 32 x 32 tile (32 rows, one 32-wide K chunk: one 1024-entry fragment per
+// plane) per workgroup: the entries staged in LDS, read along k, or for a
+// tile below the stored triangle as the stored transposed tile, read along
+// i; then each plane's fragment written contiguously, 4 entries per thread.
+__global__ __launch_bounds__(256) void k_split_c64(const float2* __restrict__ M, long n, long ld, long tri,
+                                                   u16* __restrict__ P, long rows_pad, long kpad) {
+  __shared__ float2 t[32][33];  // [row][k] of the tile
+  const long kc = blockIdx.x, rb = blockIdx.y;
+  const long i0 = rb * 32, k0 = kc * 32;
+  const bool lower = tri > 0 && k0 < (i0 / tri) * tri;
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int a = e >> 5, b = e & 31;
+    if (!lower) {
+      const long i = i0 + a, k = k0 + b;
+      t[a][b] = (i < n && k < n) ? M[i * ld + k] : make_float2(0.f, 0.f);
+    } else {
+      const long k = k0 + a, i = i0 + b;
+      t[b][a] = (i < n && k < n) ? M[k * ld + i] : make_float2(0.f, 0.f);
+    }
   }
+  __syncthreads();
+  // fragment entry f: sub f / 512, lane (f / 8) % 64, e f % 8, i.e. row
+  // lane % 32 and k = 16 (lane / 32) + 8 sub + e of the tile (frag_offset)
   const long plane = rows_pad * kpad;
-  const long o = frag_offset(i, k, kpad / 32);
-  const u16 rh = bf16_bits(re), ih = bf16_bits(im);
-  P[o] = rh;
-  P[plane + o] = bf16_bits(re - bf16_val(rh));
-  P[2 * plane + o] = ih;
-  P[3 * plane + o] = bf16_bits(im - bf16_val(ih));
+  const long base = (rb * (kpad / 32) + kc) * 1024;
+  const int f0 = threadIdx.x * 4;
+  typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+  u16x4 rh, rl, ih, il;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int f = f0 + j;
+    const int sub = f >> 9, lane = (f >> 3) & 63, e = f & 7;
+    const float2 v = t[lane & 31][16 * (lane >> 5) + 8 * sub + e];
+    const u16 a = bf16_bits(v.x), c = bf16_bits(v.y);
+    rh[j] = a;
+    rl[j] = bf16_bits(v.x - bf16_val(a));
+    ih[j] = c;
+    il[j] = bf16_bits(v.y - bf16_val(c));
+  }
+  *reinterpret_cast<u16x4*>(P + base + f0) = rh;
+  *reinterpret_cast<u16x4*>(P + plane + base + f0) = rl;
+  *reinterpret_cast<u16x4*>(P + 2 * plane + base + f0) = ih;
+  *reinterpret_cast<u16x4*>(P + 3 * plane + base + f0) = il;
 }
 
 // real FP64 [n][ld] -> planes [2][rows_pad x kpad], fragment-major
@@ -269,10 +293,13 @@ rfcmp_status SplitMatrix::from_c64(const float2* M, int64_t n_, int64_t ld, int6
   cplx = true;
   rows_pad = (int64_t)round_up(n, kRowsWG);
   kpad = (int64_t)round_up(n, kKpad);
+  if (tri % 32 != 0 || rows_pad / 32 > 65535) {
+    set_error("split: tri = %lld (a multiple of 32), n = %lld", (long long)tri, (long long)n);
+    return RFCMP_E_ARG;
+  }
   RF_TRY(planes.alloc(sizeof(u16) * 4 * rows_pad * kpad));
-  const long tot = rows_pad * kpad;
-  hipLaunchKernelGGL(k_split_c64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, (long)n, (long)n,
-                     (long)ld, (long)tri, planes.as<u16>(), (long)rows_pad, (long)kpad);
+  hipLaunchKernelGGL(k_split_c64, dim3((unsigned)(kpad / 32), (unsigned)(rows_pad / 32)), dim3(256), 0, s, M,
+                     (long)n, (long)ld, (long)tri, planes.as<u16>(), (long)rows_pad, (long)kpad);
   RF_HIP(hipGetLastError());
   return RFCMP_OK;
 }
