@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "farpair.h"
@@ -734,19 +735,34 @@ void near_data(const MeshHost& h, double factor, NearData& out) {
   near_pairs(h, factor, out.pairs);
   const int64_t np = (int64_t)out.pairs.size() / 2, C = h.C, N = h.N;
   const int32_t* pr = out.pairs.data();
-  // the near partners of every cell, ascending (the list runs in order of its
-  // first cell, partners ascending), with 2 p + t
-  out.ptr.assign(C + 1, 0);
-  for (int64_t p = 0; p < np; ++p) {
-    ++out.ptr[pr[2 * p] + 1];
-    if (pr[2 * p] != pr[2 * p + 1]) ++out.ptr[pr[2 * p + 1] + 1];
-  }
-  for (int64_t c = 0; c < C; ++c) out.ptr[c + 1] += out.ptr[c];
-  out.other.resize(out.ptr[C]);
-  out.code.resize(out.ptr[C]);
-  {
-    std::vector<int32_t> fill(out.ptr.begin(), out.ptr.end() - 1);
-    for (int64_t p = 0; p < np; ++p) {
+  const int64_t nt = (N + kEdgeTile - 1) / kEdgeTile;
+  const size_t ntp = (size_t)(nt * (nt + 1) / 2);
+  // Contiguous chunks of the pair list on a few threads.  Pass 1 counts each
+  // chunk's occurrences of every cell; pass 2 places them, chunk by chunk in
+  // list order (the offsets of a chunk follow the earlier chunks' counts), so
+  // the result is the one of a single thread, and marks the chunk's tile
+  // pairs in a map of its own (or-ed together afterwards).
+  const int nthr = np >= 65536 ? (int)std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency())) : 1;
+  std::vector<std::vector<int32_t>> cnt(nthr, std::vector<int32_t>(C, 0));
+  std::vector<std::vector<uint8_t>> tmap(nthr);
+  auto chunk = [&](int t, int64_t& p0, int64_t& p1) {
+    p0 = np * t / nthr;
+    p1 = np * (t + 1) / nthr;
+  };
+  auto count = [&](int t) {
+    int64_t p0, p1;
+    chunk(t, p0, p1);
+    std::vector<int32_t>& c = cnt[t];
+    for (int64_t p = p0; p < p1; ++p) {
+      ++c[pr[2 * p]];
+      if (pr[2 * p] != pr[2 * p + 1]) ++c[pr[2 * p + 1]];
+    }
+  };
+  auto place = [&](int t) {
+    int64_t p0, p1;
+    chunk(t, p0, p1);
+    std::vector<int32_t>& fill = cnt[t];  // the chunk's offsets by now
+    for (int64_t p = p0; p < p1; ++p) {
       const int32_t a = pr[2 * p], b = pr[2 * p + 1];
       out.other[fill[a]] = b;
       out.code[fill[a]++] = int32_t(2 * p);
@@ -755,26 +771,53 @@ void near_data(const MeshHost& h, double factor, NearData& out) {
         out.code[fill[b]++] = int32_t(2 * p + 1);
       }
     }
-    for (int64_t c = 0; c < C; ++c) {  // partners ascending, codes alongside
-      std::vector<std::pair<int32_t, int32_t>> v;
-      for (int32_t q = out.ptr[c]; q < out.ptr[c + 1]; ++q) v.emplace_back(out.other[q], out.code[q]);
-      std::sort(v.begin(), v.end());
-      for (size_t e = 0; e < v.size(); ++e) {
-        out.other[out.ptr[c] + e] = v[e].first;
-        out.code[out.ptr[c] + e] = v[e].second;
+    std::vector<uint8_t>& m = tmap[t];
+    m.assign(ntp, 0);
+    for (int64_t p = p0; p < p1; ++p) {
+      int64_t ta[3], tb[3];
+      for (int i = 0; i < 3; ++i) {
+        ta[i] = h.cell_edge[3 * pr[2 * p] + i] / kEdgeTile;
+        tb[i] = h.cell_edge[3 * pr[2 * p + 1] + i] / kEdgeTile;
       }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          const int64_t I = std::min(ta[i], tb[j]), J = std::max(ta[i], tb[j]);
+          m[(size_t)(J * (J + 1) / 2 + I)] = 1;
+        }
     }
+  };
+  auto run = [&](auto&& fn) {
+    std::vector<std::thread> pool;
+    try {
+      for (int t = 1; t < nthr; ++t) pool.emplace_back(fn, t);
+    } catch (const std::system_error&) {
+      for (int t = (int)pool.size() + 1; t < nthr; ++t) fn(t);  // no threads to be had: here
+    }
+    fn(0);
+    for (auto& th : pool) th.join();
+  };
+  run(count);
+  // the near partners of every cell, ascending, with 2 p + t.  The list runs
+  // in order of its first cell, partners ascending, so placing in list order
+  // puts cell c's partners a < c (from the pairs (a, c), in order of a)
+  // before its own pairs (c, b), b >= c ascending: already sorted.
+  out.ptr.assign(C + 1, 0);
+  for (int64_t c = 0; c < C; ++c) {
+    int32_t o = out.ptr[c];
+    for (int t = 0; t < nthr; ++t) {
+      const int32_t k = cnt[t][c];
+      cnt[t][c] = o;
+      o += k;
+    }
+    out.ptr[c + 1] = o;
   }
+  out.other.resize(out.ptr[C]);
+  out.code.resize(out.ptr[C]);
+  run(place);
   // edge-tile pairs (I <= J) that hold a near cell pair
-  const int64_t nt = (N + kEdgeTile - 1) / kEdgeTile;
-  out.tile_near.assign((size_t)(nt * (nt + 1) / 2), 0);
-  for (int64_t p = 0; p < np; ++p)
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        const int64_t ta = h.cell_edge[3 * pr[2 * p] + i] / kEdgeTile, tb = h.cell_edge[3 * pr[2 * p + 1] + j] / kEdgeTile;
-        const int64_t I = std::min(ta, tb), J = std::max(ta, tb);
-        out.tile_near[(size_t)(J * (J + 1) / 2 + I)] = 1;
-      }
+  out.tile_near.assign(ntp, 0);
+  for (int t = 0; t < nthr; ++t)
+    for (size_t q = 0; q < ntp; ++q) out.tile_near[q] |= tmap[t][q];
 }
 
 namespace {
