@@ -834,6 +834,15 @@ rfcmp_status block_cg(const Dense& D, const Work& W, int nr, const double* targe
 // tall-skinny Gram products on the device and factored on the host in FP64;
 // it stops when every column of R is below its target.
 typedef std::complex<double> cplx;
+// Products of the small matrices in plain real arithmetic: the operators of
+// std::complex follow the C rules for infinities (a library call per
+// product), which the finite Gram matrices here never need.
+inline cplx cmul(cplx a, cplx b) {
+  return cplx(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+}
+inline cplx cmulc(cplx a, cplx b) {  // conj(a) b
+  return cplx(a.real() * b.real() + a.imag() * b.imag(), a.real() * b.imag() - a.imag() * b.real());
+}
 // options.block_cg = -1 takes the shared block Krylov space from this many
 // right-hand sides on (on the level-5 sphere with 64 waves: 14 iterations
 // against 21, 190 against 173 solves per second)
@@ -866,21 +875,23 @@ int orth_transform(const std::vector<cplx>& G0, int n, double rel, std::vector<c
       R[q * n + q] = rqq;
       for (int j = q + 1; j < n; ++j) R[q * n + j] = A[q * n + j] / rqq;
       for (int i = q + 1; i < n; ++i)
-        for (int j = q + 1; j < n; ++j) A[i * n + j] -= std::conj(R[q * n + i]) * R[q * n + j];
+        for (int j = q + 1; j < n; ++j) A[i * n + j] -= cmulc(R[q * n + i], R[q * n + j]);
     }
-  // R^-1 (upper triangular, q x q), by columns
-  std::vector<cplx> Ri(q * q, cplx(0.0, 0.0));
+  // R^-1 (upper triangular, q x q, real positive diagonal), by columns;
+  // column c kept contiguous (Rt[c q + k] = (R^-1)_kc)
+  std::vector<cplx> Rt(q * q, cplx(0.0, 0.0));
   for (int c = 0; c < q; ++c) {
-    Ri[c * q + c] = 1.0 / R[c * n + c];
+    cplx* col = &Rt[(size_t)c * q];
+    col[c] = 1.0 / R[c * n + c].real();
     for (int i = c - 1; i >= 0; --i) {
       cplx acc(0.0, 0.0);
-      for (int k = i + 1; k <= c; ++k) acc += R[i * n + k] * Ri[k * q + c];
-      Ri[i * q + c] = -acc / R[i * n + i];
+      for (int k = i + 1; k <= c; ++k) acc += cmul(R[i * n + k], col[k]);
+      col[i] = -acc / R[i * n + i].real();
     }
   }
   S.assign((size_t)n * q, cplx(0.0, 0.0));
   for (int k = 0; k < q; ++k)
-    for (int c = 0; c < q; ++c) S[(size_t)perm[k] * q + c] = Ri[k * q + c];
+    for (int c = 0; c < q; ++c) S[(size_t)perm[k] * q + c] = Rt[(size_t)c * q + k];
   return q;
 }
 
@@ -890,28 +901,38 @@ bool hpd_solve(const std::vector<cplx>& M, int p, const std::vector<cplx>& C, in
   std::vector<cplx> L(p * p, cplx(0.0, 0.0));
   for (int j = 0; j < p; ++j) {
     cplx d = M[j * p + j];
-    for (int k = 0; k < j; ++k) d -= L[j * p + k] * std::conj(L[j * p + k]);
+    for (int k = 0; k < j; ++k) d -= cmulc(L[j * p + k], L[j * p + k]);
     if (!(d.real() > 0.0)) return false;
     const double ljj = std::sqrt(d.real());
     L[j * p + j] = ljj;
     for (int i = j + 1; i < p; ++i) {
       cplx v = M[i * p + j];
-      for (int k = 0; k < j; ++k) v -= L[i * p + k] * std::conj(L[j * p + k]);
+      for (int k = 0; k < j; ++k) v -= cmulc(L[j * p + k], L[i * p + k]);
       L[i * p + j] = v / ljj;
     }
   }
+  // the substitutions by rows, all columns of C at once (each entry takes
+  // its terms in the order of k, as a column-by-column sweep would)
   Z = C;
-  for (int c = 0; c < m; ++c) {
-    for (int i = 0; i < p; ++i) {  // L y = c
-      cplx v = Z[i * m + c];
-      for (int k = 0; k < i; ++k) v -= L[i * p + k] * Z[k * m + c];
-      Z[i * m + c] = v / L[i * p + i];
+  for (int i = 0; i < p; ++i) {  // L y = c
+    cplx* zi = &Z[(size_t)i * m];
+    for (int k = 0; k < i; ++k) {
+      const cplx l = L[i * p + k];
+      const cplx* zk = &Z[(size_t)k * m];
+      for (int c = 0; c < m; ++c) zi[c] -= cmul(l, zk[c]);
     }
-    for (int i = p - 1; i >= 0; --i) {  // L^H z = y
-      cplx v = Z[i * m + c];
-      for (int k = i + 1; k < p; ++k) v -= std::conj(L[k * p + i]) * Z[k * m + c];
-      Z[i * m + c] = v / L[i * p + i];
+    const double d = L[i * p + i].real();
+    for (int c = 0; c < m; ++c) zi[c] /= d;
+  }
+  for (int i = p - 1; i >= 0; --i) {  // L^H z = y
+    cplx* zi = &Z[(size_t)i * m];
+    for (int k = i + 1; k < p; ++k) {
+      const cplx l = L[k * p + i];
+      const cplx* zk = &Z[(size_t)k * m];
+      for (int c = 0; c < m; ++c) zi[c] -= cmulc(l, zk[c]);
     }
+    const double d = L[i * p + i].real();
+    for (int c = 0; c < m; ++c) zi[c] /= d;
   }
   return true;
 }
