@@ -179,8 +179,8 @@ TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     "icosphere5_64rhs": {
         "gemm_ta": {"source": "paper_1803_08333_amd/csrc/gemm.hip",
-                    "sha256": "3f96710cb02860e6d46c1cf43c138db87da07e797632cf00169541bba40dad57",
-                    "kib": (3747947.5, 30720.0)},
+                    "sha256": "d40577e099774a3e2d3e31f74e7748ecc53b20c8dfe0430469d00fdc17d8faee",
+                    "kib": (3747942.3, 30720.0)},
         "zgemm_ta_nr32": {"source": "paper_1803_08333_amd/csrc/zgemm.hip",
                           "sha256": "6c2552a624e26ee57abf050493d1670743d56309a031422a97aaa2522169ef24",
                           "kib": (3976700.9, 122880.1)},

@@ -895,10 +895,10 @@ int orth_transform(const std::vector<cplx>& G0, int n, double rel, std::vector<c
   return q;
 }
 
-// Solve M Z = C for Hermitian positive definite M (p x p) and C (p x m),
-// row-major, by Cholesky; false if M is not numerically positive definite.
-bool hpd_solve(const std::vector<cplx>& M, int p, const std::vector<cplx>& C, int m, std::vector<cplx>& Z) {
-  std::vector<cplx> L(p * p, cplx(0.0, 0.0));
+// Cholesky factor L (p x p, row-major) of M; false if M is not numerically
+// positive definite.
+bool hpd_factor(const std::vector<cplx>& M, int p, std::vector<cplx>& L) {
+  L.assign((size_t)p * p, cplx(0.0, 0.0));
   for (int j = 0; j < p; ++j) {
     cplx d = M[j * p + j];
     for (int k = 0; k < j; ++k) d -= cmulc(L[j * p + k], L[j * p + k]);
@@ -911,8 +911,13 @@ bool hpd_solve(const std::vector<cplx>& M, int p, const std::vector<cplx>& C, in
       L[i * p + j] = v / ljj;
     }
   }
-  // the substitutions by rows, all columns of C at once (each entry takes
-  // its terms in the order of k, as a column-by-column sweep would)
+  return true;
+}
+
+// Z = M^-1 C from the factor of hpd_factor, C p x m row-major: the
+// substitutions by rows, all columns of C at once (each entry takes its
+// terms in the order of k, as a column-by-column sweep would).
+void hpd_subst(const std::vector<cplx>& L, int p, const std::vector<cplx>& C, int m, std::vector<cplx>& Z) {
   Z = C;
   for (int i = 0; i < p; ++i) {  // L y = c
     cplx* zi = &Z[(size_t)i * m];
@@ -934,7 +939,6 @@ bool hpd_solve(const std::vector<cplx>& M, int p, const std::vector<cplx>& C, in
     const double d = L[i * p + i].real();
     for (int c = 0; c < m; ++c) zi[c] /= d;
   }
-  return true;
 }
 
 rfcmp_status block_cg_shared(const Dense& D, const Work& W, int nr, const double* target, int maxit, int* iters) {
@@ -1000,7 +1004,7 @@ rfcmp_status block_cg_shared(const Dense& D, const Work& W, int nr, const double
   RF_TRY(wait());
   take_norms();
   if (done()) return RFCMP_OK;
-  std::vector<cplx> G, S, M, C2, C3, A1, T;
+  std::vector<cplx> G, S, M, Lm, C2, C3, A1, T;
   read(0, nr * nr, G);
   int p = orth_transform(G, nr, kDrop, S);
   if (p == 0) return RFCMP_OK;
@@ -1021,10 +1025,11 @@ rfcmp_status block_cg_shared(const Dense& D, const Work& W, int nr, const double
         M[j * p + i] = std::conj(h);
       }
     read(1, p * nr, C2);
-    if (!hpd_solve(M, p, C2, nr, A1)) {
+    if (!hpd_factor(M, p, Lm)) {
       set_error("block CG breakdown at iteration %d: P^H A P not positive definite", it);
       return RFCMP_E_BREAKDOWN;
     }
+    hpd_subst(Lm, p, C2, nr, A1);
     RF_TRY(upload(A1, 3, dS));
     RF_TRY(tsmm_c128(W.p, p, dS, nr, N, W.x, 1.0, true, s));    // X += P alpha
     RF_TRY(tsmm_c128(W.q, p, dS, nr, N, W.r, -1.0, true, s));   // R -= Q alpha
@@ -1036,10 +1041,7 @@ rfcmp_status block_cg_shared(const Dense& D, const Work& W, int nr, const double
     if (done() || it >= maxit) break;
     // Y = R - P M^-1 Q^H R into W.q (Q is not needed any more)
     read(2, p * nr, C3);
-    if (!hpd_solve(M, p, C3, nr, T)) {
-      set_error("block CG breakdown at iteration %d: P^H A P not positive definite", it);
-      return RFCMP_E_BREAKDOWN;
-    }
+    hpd_subst(Lm, p, C3, nr, T);
     RF_TRY(upload(T, 4, dT));
     RF_HIP(hipMemcpyAsync(W.q, W.r, sizeof(double2) * NR, hipMemcpyDeviceToDevice, s));
     RF_TRY(tsmm_c128(W.p, p, dT, nr, N, W.q, -1.0, true, s));
