@@ -339,8 +339,12 @@ __global__ void k_hm_gather(int n, int nr, const int* __restrict__ perm, const d
 // conjugated factors), nr <= R <= kHmR right-hand sides: a small GEMM per
 // block (k x len times len x nr) over chunks of rows, the factor chunk
 // (k x rows <= 4096 entries) and the input chunk (rows x R <= 1024) staged in
-// LDS so that each is read from memory once; thread t accumulates outputs
-// (l, r) = t, t + 256, ... in row order.
+// LDS so that each is read from memory once.  The k R outputs are spread over
+// the workgroup: with fewer than 256, G = 256 / (k R) threads (at most 8)
+// share an output, thread group g taking the rows jj = g, g + G, ... of each
+// chunk in two alternating sums, and the G partial sums are added in order at
+// the end; with more, thread t takes outputs t, t + 256, ...  Every sum runs
+// in a fixed order.
 constexpr int kProjFactor = 4096;   // complex64 entries of a staged factor chunk
 constexpr int kProjInput = 1024;    // complex128 entries of a staged input chunk
 template <int R>
@@ -357,6 +361,11 @@ __global__ __launch_bounds__(256) void k_hm_proj(const HmLr* __restrict__ blk, c
   const int tid = threadIdx.x;
   const float sgn = conj ? -1.f : 1.f;
   constexpr int kOut = (kHmKmax * R + 255) / 256;  // outputs per thread at most
+  const int nout = k * R;
+  const int G = nout >= 256 ? 1 : min(8, 256 / nout);
+  const int g = tid / (nout < 256 ? nout : 256);   // row group (G > 1 only)
+  const int ob = tid % (nout < 256 ? nout : 256);  // first output of this thread
+  const bool act = g < G;
   // rows per chunk: a multiple of 32, at most 256
   const int cr = max(32, min(256, min(kProjFactor / k, kProjInput / R)) / 32 * 32);
   double2* z = zw + zoff[b];
@@ -380,29 +389,58 @@ __global__ __launch_bounds__(256) void k_hm_proj(const HmLr* __restrict__ blk, c
         sx[e] = (jj < nj && r < nr) ? xp[(long)r * n + off + j0 + jj] : make_double2(0.0, 0.0);
       }
       __syncthreads();
+      if (act) {
 #pragma unroll
-      for (int q = 0; q < kOut; ++q) {
-        const int o = tid + 256 * q;
-        if (o < k * R) {
-          const int l = o / R, r = o % R;
-          const float2* mrow = sm + l * cr;
-          double sr = 0.0, si = 0.0;
-          for (int jj = 0; jj < nj; ++jj) {
-            const float2 mv = mrow[jj];
-            const double2 x = sx[jj * R + r];
-            sr += (double)mv.x * x.x - (double)mv.y * x.y;
-            si += (double)mv.x * x.y + (double)mv.y * x.x;
+        for (int q = 0; q < kOut; ++q) {
+          const int o = ob + 256 * q;
+          if (o < nout) {
+            const int l = o / R, r = o % R;
+            const float2* mrow = sm + l * cr;
+            double s0r = 0.0, s0i = 0.0, s1r = 0.0, s1i = 0.0;
+            int jj = g;
+            for (; jj + G < nj; jj += 2 * G) {
+              const float2 m0 = mrow[jj], m1 = mrow[jj + G];
+              const double2 x0 = sx[jj * R + r], x1 = sx[(jj + G) * R + r];
+              s0r += (double)m0.x * x0.x - (double)m0.y * x0.y;
+              s0i += (double)m0.x * x0.y + (double)m0.y * x0.x;
+              s1r += (double)m1.x * x1.x - (double)m1.y * x1.y;
+              s1i += (double)m1.x * x1.y + (double)m1.y * x1.x;
+            }
+            if (jj < nj) {
+              const float2 m0 = mrow[jj];
+              const double2 x0 = sx[jj * R + r];
+              s0r += (double)m0.x * x0.x - (double)m0.y * x0.y;
+              s0i += (double)m0.x * x0.y + (double)m0.y * x0.x;
+            }
+            ar[q] += s0r + s1r;
+            ai[q] += s0i + s1i;
           }
-          ar[q] += sr;
-          ai[q] += si;
         }
       }
       __syncthreads();
     }
+    if (G > 1) {  // the row groups' partial sums, added in order of g
+      double2* red = reinterpret_cast<double2*>(sm);  // [G][nout], 256 entries at most
+      static_assert(sizeof(sm) >= 256 * sizeof(double2), "partials fit the staging buffer");
+      if (act) red[g * nout + ob] = make_double2(ar[0], ai[0]);
+      __syncthreads();
+      if (g == 0) {
+        double sr = 0.0, si = 0.0;
+        for (int q = 0; q < G; ++q) {
+          sr += red[q * nout + ob].x;
+          si += red[q * nout + ob].y;
+        }
+        ar[0] = sr;
+        ai[0] = si;
+      }
+      __syncthreads();
+    }
+    if (g == 0) {
 #pragma unroll
-    for (int q = 0; q < kOut; ++q) {
-      const int o = tid + 256 * q;
-      if (o < k * R && o % R < nr) out[(o / R) * kHmR + o % R] = make_double2(ar[q], ai[q]);
+      for (int q = 0; q < kOut; ++q) {
+        const int o = ob + 256 * q;
+        if (o < nout && o % R < nr) out[(o / R) * kHmR + o % R] = make_double2(ar[q], ai[q]);
+      }
     }
   }
 }
