@@ -271,13 +271,13 @@ def precision_study(rf, torch, nb):
 
 def spectral_study(rf):
     """cond(A) of the RF-CMP system against ka (1 down to the 1e-25 Hz of the
-    paper's sphere study) on icosphere levels 2-4 and the jittered torus at
+    paper's sphere study) on icosphere levels 1-5 and the jittered torus at
     48 x 24, 96 x 48 and 144 x 72 (N = 3456 to 31104): the
     CG-Lanczos estimate of a solve of A i = b with a seeded generic b (the
     library's rfcmp_solve_system), power-iteration scalings."""
     from paper_1803_08333_amd import study
     ks = [1.0, 1e-2, 1e-4, 1e-12, study.K_1E_25_HZ]
-    meshes = {f"icosphere{L}": synth.icosphere(L) for L in (2, 3, 4)}
+    meshes = {f"icosphere{L}": synth.icosphere(L) for L in (1, 2, 3, 4, 5)}
     # the genus-1 body refined twice (Fig. CubeTorus's 1/h axis)
     for nmaj, nmin in ((48, 24), (96, 48), (144, 72)):
         meshes[f"torus{nmaj}x{nmin}"] = synth.torus(nmaj, nmin)

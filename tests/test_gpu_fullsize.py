@@ -147,14 +147,18 @@ def test_bf16x3_gemm_full_size_sampled_rows():
     C = 20480, 64 right-hand sides): seeded sampled rows of T_A X and V X,
     plain and conjugated, against complex128 products of the exported rows
     (3e-5, the per-product bound of the split: hi.hi + hi.lo + lo.hi in
-    FP32)."""
+    FP32).  The same rows of the FP64 matrix-core products (which 0 and 1:
+    32 right-hand sides per pass, the headline's K slices), which form the
+    right-hand side and the refinement residuals, to 1e-13 (FP64 sums of
+    exactly widened entries; only the order differs)."""
     torch, rf = _gpu()
     xyz, tri = synth.icosphere(5)
     m = rf.Mesh(xyz, tri)
     op = rf.Operator(m, 2.0, scaling=1, precision=1)
     gTA, gV = op.export()
     rng = np.random.default_rng(23)
-    for which, M, n in ((2, gTA, m.N), (3, gV, m.C)):
+    for which, M, n in ((2, gTA, m.N), (3, gV, m.C), (0, gTA, m.N), (1, gV, m.C)):
+        bound = 3e-5 if which >= 2 else 1e-13
         x = _cuda(np.stack([synth.complex_start(n, 400 + r) for r in range(64)]))
         rows = np.unique(np.r_[0, n - 1, rng.integers(0, n, 62)])
         ridx = torch.from_numpy(rows).cuda()
@@ -164,8 +168,9 @@ def test_bf16x3_gemm_full_size_sampled_rows():
             ref = (Rc @ x.T).T                      # [64][rows]
             got = op.matvec(which, x, conj)[:, ridx]
             err = (torch.linalg.norm(got - ref) / torch.linalg.norm(ref)).item()
-            print(f"BF16x3 which {which} conj {conj}: sampled-row rel err {err:.2e}")
-            assert err < 3e-5
+            col = (torch.linalg.norm(got - ref, dim=1) / torch.linalg.norm(ref, dim=1)).max().item()
+            print(f"which {which} conj {conj}: sampled-row rel err {err:.2e}, worst right-hand side {col:.2e}")
+            assert err < bound and col < 10 * bound
         del R
     del gTA, gV
     op.close()
