@@ -12,8 +12,8 @@
 //
 // Storage: a complex matrix is four bf16 planes (Re hi, Re lo, Im hi, Im lo),
 // 8 bytes per entry -- the same as complex64; a real matrix two planes.
-// Planes hold rows_pad x kpad entries (rows_pad a multiple of 128, kpad of
-// 64, zero-padded) fragment-major: 32 x 32 tiles in which each wave's MFMA
+// Planes hold rows_pad x kpad entries (rows_pad and kpad multiples of 128,
+// zero-padded) fragment-major: 32 x 32 tiles in which each wave's MFMA
 // operand for one K-step is 1 KB contiguous, so the matrix stream is read
 // in whole 1 KB wave loads.  X is split per call into two planes
 // [ncp][kpad] (column 2r + 0/1 = Re/Im of right-hand side r; ncp = 2 nrhs
@@ -43,7 +43,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16;
 
 constexpr int kRowsWG = 128;
-constexpr int kKpad = 64;        // K padding of the planes
+constexpr int kKpad = 128;       // K padding of the planes (and of the K slices: 4 chunks)
 constexpr int kKc = 32;          // K chunk per pipeline stage
 constexpr int kSub = kKc / 16;   // MFMA K-steps per chunk
 constexpr int kLdsK = kKc + 8;   // padded column stride in LDS (bf16 units)
@@ -219,31 +219,38 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const u16* __restrict__ A, 
   // registers (sets a0 .. a3 in rotation), X one chunk ahead in registers
   // and double-buffered in LDS; one barrier per chunk.  Within an
   // iteration X is loaded before the matrix rows, so waiting for X never
-  // waits for the newest matrix loads.
+  // waits for the newest matrix loads.  The chunk count is a multiple of 4
+  // (K slices of whole 128-wide blocks) and the loads past the last chunk
+  // repeat the last one, so every iteration issues the same loads: the
+  // compiler's wait counts then leave the three younger sets in flight
+  // (with loads behind branches it waits for all of them at every chunk).
   bf16x8 a0[2 * NPL][kSub], a1[2 * NPL][kSub], a2[2 * NPL][kSub], a3[2 * NPL][kSub];
   bf16x8 xr[XPT];
+  const int last = nch - 1;
   GEMM_LOAD_X(0)
+  __builtin_amdgcn_sched_barrier(0);
   GEMM_LOAD_A(a0, 0)
-  if (nch > 1) { GEMM_LOAD_A(a1, 1) }
-  if (nch > 2) { GEMM_LOAD_A(a2, 2) }
-  if (nch > 3) { GEMM_LOAD_A(a3, 3) }
+  GEMM_LOAD_A(a1, min(1, last))
+  GEMM_LOAD_A(a2, min(2, last))
+  GEMM_LOAD_A(a3, min(3, last))
   GEMM_STORE_X(0)
-  if (nch > 1) { GEMM_LOAD_X(1) }
+  GEMM_LOAD_X(min(1, last))
   __syncthreads();
 #define GEMM_STEP(SET, CH)                                                                       \
   {                                                                                              \
     const int buf = (CH) & 1;                                                                    \
     GEMM_COMPUTE(SET, buf)                                                                       \
-    if ((CH) + 1 < nch) { GEMM_STORE_X(buf ^ 1) }                                                \
-    if ((CH) + 2 < nch) { GEMM_LOAD_X((CH) + 2) }                                                \
-    if ((CH) + 4 < nch) { GEMM_LOAD_A(SET, (CH) + 4) }                                           \
+    GEMM_STORE_X(buf ^ 1)                                                                        \
+    GEMM_LOAD_X(min((CH) + 2, last))                                                             \
+    __builtin_amdgcn_sched_barrier(0); /* X's loads stay ahead of the matrix rows' */            \
+    GEMM_LOAD_A(SET, min((CH) + 4, last))                                                        \
     __syncthreads();                                                                             \
   }
   for (int ch = 0; ch < nch; ch += 4) {
     GEMM_STEP(a0, ch)
-    if (ch + 1 < nch) GEMM_STEP(a1, ch + 1)
-    if (ch + 2 < nch) GEMM_STEP(a2, ch + 2)
-    if (ch + 3 < nch) GEMM_STEP(a3, ch + 3)
+    GEMM_STEP(a1, ch + 1)
+    GEMM_STEP(a2, ch + 2)
+    GEMM_STEP(a3, ch + 3)
   }
 #undef GEMM_STEP
 #undef GEMM_COMPUTE
