@@ -179,11 +179,11 @@ TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     "icosphere5_64rhs": {
         "gemm_ta": {"source": "paper_1803_08333_amd/csrc/gemm.hip",
-                    "sha256": "d40577e099774a3e2d3e31f74e7748ecc53b20c8dfe0430469d00fdc17d8faee",
-                    "kib": (3747942.3, 30720.0)},
+                    "sha256": "3a9a7ba3393dd629b05455a8cc041999b61ce68e136862d80d6a7ab277421e29",
+                    "kib": (3757129.2, 30720.0)},
         "zgemm_ta_nr32": {"source": "paper_1803_08333_amd/csrc/zgemm.hip",
                           "sha256": "6c2552a624e26ee57abf050493d1670743d56309a031422a97aaa2522169ef24",
-                          "kib": (3976700.9, 122880.1)},
+                          "kib": (3979426.9, 122880.0)},
     },
 }
 
