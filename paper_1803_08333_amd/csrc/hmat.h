@@ -72,6 +72,16 @@ struct HmLr {
   int r0, m, c0, n;
 };
 
+// A tile list entry of one operator, resolved once its ranks are known:
+// a low-rank entry's factor (U for the rows, V for the columns), the first
+// row it covers in the permuted order, its length and rank, and the offset
+// of its projections; the list code (4 b + kind) for every entry.
+struct HmEnt {
+  const float2* F;
+  long zb;
+  int start, len, k, code;
+};
+
 // The tree of a mesh on the device, built with the first compressed
 // operator and kept with the mesh.
 struct HmMesh {
@@ -87,6 +97,7 @@ struct HmMesh {
   // I < J (its transpose), 2: low-rank block b with the tile in its rows,
   // 3: the same with the tile in its columns (the transpose)
   DevBuf list_ptr, list_ent;
+  std::vector<int> list_host;  // list_ent on the host
 };
 
 // The compressed blocks of one operator.
@@ -99,6 +110,7 @@ struct HmOp {
   DevBuf uA, vA, uV, vV;    // float2* [nlr]: U (m x k, column-major) and V (n x k) of each block
   DevBuf rankA, rankV;      // int [nlr]
   DevBuf zwA, zwV;          // int64 [nlr]: offsets of the projections in the product scratch
+  DevBuf entA, entV;        // HmEnt [list entries] of T_A and V
   int64_t zw_total = 0;     // complex128 entries of that scratch
   std::vector<int> hrankA, hrankV;  // host copies of the ranks
   int64_t lr_entries[2] = {0, 0}, dense_entries[2] = {0, 0};  // complex64 entries stored (T_A, V)

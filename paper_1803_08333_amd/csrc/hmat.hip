@@ -450,7 +450,7 @@ struct TileArgs {
   const int* perm;             // position -> mesh index
   const int* row0;             // KIND 1: cell_start (rows of tile T: [row0[T], row0[T + 1]))
   const int* list_ptr;
-  const int* list_ent;
+  const HmEnt* ent;            // the list entries, resolved
   const int2* dense_ij;
   const float2* D;             // dense blocks
   const long* doff;            // KIND 1: offsets of the dense blocks (KIND 0: b * 4096)
@@ -519,10 +519,11 @@ __global__ __launch_bounds__(256) void k_hm_tile(const TileArgs a) {
       // most 32 factor columns in all (their descriptors into LDS)
       if (g == 0) {
         const int ej = e + lane;
-        const int cd = ej < e1 ? a.list_ent[ej] : 0;
+        HmEnt E{nullptr, 0, 0, 0, 0, 0};
+        if (ej < e1) E = a.ent[ej];
+        const int cd = E.code;
         const bool lr = ej < e1 && (cd & 3) >= 2;
-        const int bj = cd >> 2;
-        const int kj = lr ? a.rank[bj] : 0;
+        const int kj = lr ? E.k : 0;
         int cum = kj;
         for (int o = 1; o < 64; o <<= 1) {
           const int t = __shfl_up(cum, o);
@@ -538,12 +539,10 @@ __global__ __launch_bounds__(256) void k_hm_tile(const TileArgs a) {
           s_cols = nent > 0 ? cols : 0;
         }
         if (ok) {
-          const HmLr B = a.blk[bj];
-          const bool rows = (cd & 3) == 2;
-          s_F[lane] = rows ? a.Up[bj] : a.Vp[bj];
-          s_len[lane] = rows ? B.m : B.n;
-          s_o[lane] = p0 + base - (rows ? B.r0 : B.c0);
-          s_zb[lane] = a.zw + a.zoff[bj] + (rows ? 0 : (long)kj * kHmR);
+          s_F[lane] = E.F;
+          s_len[lane] = E.len;
+          s_o[lane] = p0 + base - E.start;
+          s_zb[lane] = a.zw + E.zb;
           for (int c = cum - kj; c < cum; ++c) {
             s_colent[c] = lane;
             s_coll[c] = c - (cum - kj);
@@ -573,8 +572,8 @@ __global__ __launch_bounds__(256) void k_hm_tile(const TileArgs a) {
         e += nbatch;
         continue;
       }
-      const int code = a.list_ent[e];
-      const int kind = code & 3, bi = code >> 2;
+      const HmEnt E = a.ent[e];
+      const int kind = E.code & 3, bi = E.code >> 2;
       ++e;
       if (kind < 2) {
         const int I = a.dense_ij[bi].x, J = a.dense_ij[bi].y;
@@ -636,12 +635,11 @@ __global__ __launch_bounds__(256) void k_hm_tile(const TileArgs a) {
         }
         __syncthreads();
       } else {
-        const HmLr B = a.blk[bi];
-        const int k = a.rank[bi];
-        const double2* zb = a.zw + a.zoff[bi] + (kind == 2 ? 0 : (long)k * kHmR);
-        const float2* F = kind == 2 ? a.Up[bi] : a.Vp[bi];
-        const int len = kind == 2 ? B.m : B.n;
-        const int o = p0 + base - (kind == 2 ? B.r0 : B.c0);   // first row of this pass in the factor
+        const int k = E.k;
+        const double2* zb = a.zw + E.zb;
+        const float2* F = E.F;
+        const int len = E.len;
+        const int o = p0 + base - E.start;   // first row of this pass in the factor
         for (int l0 = 0; l0 < k; l0 += 32) {
           const int nl = min(32, k - l0);
           for (int q = tid; q < 32 * 64; q += 256) {
@@ -805,6 +803,7 @@ rfcmp_status hm_mesh_setup(rfcmp_mesh m, hipStream_t s) {
   RF_TRY(upload(H->list_ptr, lp, s));
   RF_TRY(upload(H->list_ent, le, s));
   RF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  H->list_host = std::move(le);
   m->hm = std::move(H);
   return RFCMP_OK;
 }
@@ -935,6 +934,23 @@ rfcmp_status hm_aca(rfcmp_op op, hipStream_t s) {
       zt += 2L * hr[b] * kHmR;
     }
     zw_need = std::max<int64_t>(zw_need, zt);
+    // the tile lists' entries resolved for this operator
+    std::vector<HmEnt> ent(H.list_host.size());
+    for (size_t e = 0; e < ent.size(); ++e) {
+      const int code = H.list_host[e], b = code >> 2;
+      HmEnt E{nullptr, 0, 0, 0, 0, code};
+      if ((code & 3) >= 2) {
+        const bool rows = (code & 3) == 2;
+        E.F = rows ? hu[b] : hv[b];
+        E.start = rows ? blk[b].r0 : blk[b].c0;
+        E.len = rows ? blk[b].m : blk[b].n;
+        E.k = hr[b];
+        E.zb = zo[b] + (rows ? 0 : (long)hr[b] * kHmR);
+      }
+      ent[e] = E;
+    }
+    RF_TRY(upload(kind == 0 ? P.entA : P.entV, ent, s));
+    RF_HIP(hipStreamSynchronize(s));  // ent goes out of scope
   }
   RF_TRY(upload(P.zwA, zoff_all[0], s));
   RF_TRY(upload(P.zwV, zoff_all[1], s));
@@ -962,7 +978,7 @@ rfcmp_status hm_matvec(rfcmp_op op, int which, bool conj, const double2* x, doub
   ta.perm = which == 0 ? H.perm_e.as<int>() : H.perm_c.as<int>();
   ta.row0 = H.cell_start.as<int>();
   ta.list_ptr = H.list_ptr.as<int>();
-  ta.list_ent = H.list_ent.as<int>();
+  ta.ent = which == 0 ? P.entA.as<HmEnt>() : P.entV.as<HmEnt>();
   ta.dense_ij = H.dense_ij.as<int2>();
   ta.D = which == 0 ? P.TAd.as<float2>() : P.Vd.as<float2>();
   ta.doff = H.vd_off.as<long>();
