@@ -755,7 +755,7 @@ def cpu_model():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path; "
               "one operator would shard by row blocks of T_A, V and L^+ with one all-gather of the input per "
               "product.", file=sys.stderr)
         sys.exit(2)
