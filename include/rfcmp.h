@@ -379,7 +379,7 @@ typedef struct {
  *   precision 0: CG on the complex64 / FP64 operator, restarted from the
  *                true residual when the recursive one has drifted;
  *   precision 1: iterative refinement: inner CG on the BF16x3 operator to
- *                max(1e-4 of the current residual, tol / 2), outer residual
+ *                max(1e-4 of the current residual, 0.75 tol), outer residual
  *                with the complex64 / FP64 operator, rounds until it meets
  *                tol.
  * e, j: device c128 [nrhs][N].  info: host [nrhs], nullable (iters counts
