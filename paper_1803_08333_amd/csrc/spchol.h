@@ -107,10 +107,13 @@ struct SpDevice {
   int n = 0, nsn = 0, grounded = 0;
   int max_front = 0, max_ncol = 0;
   int nsub = 0, ntop = 0;                    // bottom subtrees, top heights
-  // LDS entries per right-hand side a supernode's steps need: 2 ncol + nstr
-  // (forward: the front and y; backward: x_struct and z); the largest over
-  // the bottom supernodes
-  int bot_lds = 0;
+  // LDS of a bottom supernode's wave (its blocks staged): ncol + nstr
+  // entries per right-hand side (forward: the front; backward: x_struct and
+  // z), its blocks (doubles) and its gather indices (ints); the largest over
+  // the bottom supernodes, bot_fac even and bot_idx a multiple of 4; the
+  // most columns of a bottom supernode (at most 32: staged blocks hold at
+  // most 1024 entries)
+  int bot_lds = 0, bot_fac = 0, bot_idx = 0, bot_ncol = 0;
   int64_t nstr_total = 0, front_total = 0;
   int64_t nnz = 0;            // doubles of the factor as stored (both copies)
   double seconds = 0.0;       // host factorisation time
@@ -120,8 +123,17 @@ struct SpDevice {
   DevBuf fr_src;
   int fr_k = 0;
   DevBuf linv_off, l21_off, l21, l21t, linv, linvt;
-  DevBuf sub_ptr, sub_lvl, sub_nodes;        // bottom subtrees: levels and supernodes
-  DevBuf top_lvl, top_nodes;                 // top supernodes by height
+  // the blocks of each bottom supernode staged in LDS by the solve, L_ss^-1
+  // then L_21 (both column-major) contiguously, at blk_off
+  DevBuf blk_off, blk;
+  // bottom subtrees: levels, and per position the supernode's descriptor
+  // {col0, ncol, str_off, nstr}, {front_off, blk_off, 0, 0}
+  DevBuf sub_ptr, sub_lvl, sub_desc;
+  // top supernodes by height: per position the descriptor {col0, ncol,
+  // str_off, nstr}, {front_off, linv_off, l21_off, 0}; the first position of
+  // each height (host)
+  DevBuf top_desc;
+  std::vector<int> top_start;
   // per top height (host copies): supernodes, and the largest LDS need
   std::vector<int> top_count, top_lds;
   // complex128 entries of solve scratch per right-hand side: the permuted
@@ -136,13 +148,13 @@ struct SpDevice {
 
 // The device arrays of a factor, formed on the host.
 struct SpArrays {
-  int max_ncol = 0, nsub = 0, ntop = 0, bot_lds = 0;
+  int max_ncol = 0, nsub = 0, ntop = 0, bot_lds = 0, bot_fac = 0, bot_idx = 0, bot_ncol = 0;
   int64_t front_total = 0;
   std::vector<int> iperm, front_off, fr_src;
   int fr_k = 0;
-  std::vector<long> linv_off, l21_off;
-  std::vector<double> l21, l21t, linv, linvt;
-  std::vector<int> sub_ptr, sub_lvl, sub_nodes, top_lvl, top_nodes;
+  std::vector<long> linv_off, l21_off, blk_off;
+  std::vector<double> l21, l21t, linv, linvt, blk;
+  std::vector<int> sub_ptr, sub_lvl, sub_nodes, sub_desc, top_lvl, top_nodes, top_desc;
   std::vector<int> top_count, top_lds;
 };
 void spchol_arrays(const SpFactor& F, SpArrays& out);

@@ -12,14 +12,18 @@
 namespace rfcmp {
 namespace {
 
+constexpr int kSpTopMax = 40;  // top heights of a factor
+
 struct SpArg {
   int n, grounded, nrhs;  // nrhs: this job's right-hand sides
   int nsub, ntop, fr_k, ntile;
   long nstr_total;
   const int *perm, *iperm, *col0, *str_off, *str, *front_off, *fr_src;
-  const long *linv_off, *l21_off;
-  const double *l21, *l21t, *linv, *linvt;
-  const int *sub_ptr, *sub_lvl, *sub_nodes, *top_lvl, *top_nodes;
+  const long *linv_off, *l21_off, *blk_off;
+  const double *l21, *l21t, *linv, *linvt, *blk;
+  const int *sub_ptr, *sub_lvl;
+  const int4 *sub_desc, *top_desc;
+  int top_start[kSpTopMax + 1];  // first top position of each height
   SymvInput in;
   double2* y;
   double2* scratch;  // x [n][nrhs], u [nstr_total][nrhs], partial sums [ntile][nrhs], two means [2][nrhs]
@@ -111,16 +115,16 @@ __device__ inline double2 strided_dot(const double* __restrict__ M, int ld, int 
   return cadd(cadd(a0, a1), cadd(a2, a3));
 }
 
-// Forward step of supernode sn for right-hand sides r0 .. r0+R-1 on a team
-// of TEAM lanes; lds: (2 ncol + nstr) R entries.
+// Forward step of a supernode (descriptor d0 = {col0, ncol, str_off, nstr},
+// d1 = {front_off, linv_off, l21_off, 0}) for right-hand sides r0 .. r0+R-1
+// on a team of TEAM lanes; lds: (2 ncol + nstr) R entries.
 template <int TEAM>
-__device__ void node_forward(const SpArg& A, int sn, int t, int R, int r0, double2* lds) {
+__device__ void node_forward(const SpArg& A, int4 d0, int4 d1, int t, int R, int r0, double2* lds) {
   const int NR = A.nrhs;
   double2* x = A.scratch;
   double2* u = A.u();
-  const int c0 = A.col0[sn], ncol = A.col0[sn + 1] - c0;
-  const int so = A.str_off[sn], nstr = A.str_off[sn + 1] - so;
-  const int fo = A.front_off[sn], m = ncol + nstr, K = A.fr_k;
+  const int c0 = d0.x, ncol = d0.y, so = d0.z, nstr = d0.w;
+  const int fo = d1.x, m = ncol + nstr, K = A.fr_k;
   double2* v = lds;              // front [m][R]
   double2* yv = lds + m * R;     // y [ncol][R]
   {  // the front: x on the columns (less the input mean of the Laplacian)
@@ -145,7 +149,7 @@ __device__ void node_forward(const SpArg& A, int sn, int t, int R, int r0, doubl
   team_sync<TEAM>();
   {  // y_i = (L_ss^-1 v)_i: columns j <= i
     const Lanes L = lanes_of(t, TEAM, R, ncol);
-    const double* M = A.linv + A.linv_off[sn];
+    const double* M = A.linv + d1.y;
     const int rg = r0 + L.r;
     for (int base = 0; base < ncol; base += L.S) {
       const int i = base + L.slot;
@@ -159,7 +163,7 @@ __device__ void node_forward(const SpArg& A, int sn, int t, int R, int r0, doubl
   team_sync<TEAM>();
   {  // u_q = v_(ncol + q) - (L_21 y)_q
     const Lanes L = lanes_of(t, TEAM, R, nstr);
-    const double* M = A.l21 + A.l21_off[sn];
+    const double* M = A.l21 + d1.z;
     const int rg = r0 + L.r;
     for (int base = 0; base < nstr; base += L.S) {
       const int q = base + L.slot;
@@ -173,13 +177,12 @@ __device__ void node_forward(const SpArg& A, int sn, int t, int R, int r0, doubl
   team_sync<TEAM>();
 }
 
-// Backward step of supernode sn: x_s = L_ss^-T (y - L_21^T x_struct).
+// Backward step of a supernode: x_s = L_ss^-T (y - L_21^T x_struct).
 template <int TEAM>
-__device__ void node_backward(const SpArg& A, int sn, int t, int R, int r0, double2* lds) {
+__device__ void node_backward(const SpArg& A, int4 d0, int4 d1, int t, int R, int r0, double2* lds) {
   const int NR = A.nrhs;
   double2* x = A.scratch;
-  const int c0 = A.col0[sn], ncol = A.col0[sn + 1] - c0;
-  const int so = A.str_off[sn], nstr = A.str_off[sn + 1] - so;
+  const int c0 = d0.x, ncol = d0.y, so = d0.z, nstr = d0.w;
   double2* xs = lds;              // x_struct [nstr][R]
   double2* z = lds + nstr * R;    // z [ncol][R]
   {
@@ -190,7 +193,7 @@ __device__ void node_backward(const SpArg& A, int sn, int t, int R, int r0, doub
   team_sync<TEAM>();
   {  // z_j = y_j - (L_21^T x_struct)_j
     const Lanes L = lanes_of(t, TEAM, R, ncol);
-    const double* M = A.l21t + A.l21_off[sn];  // (q, j) at M[q * ncol + j]
+    const double* M = A.l21t + d1.z;  // (q, j) at M[q * ncol + j]
     const int rg = r0 + L.r;
     for (int base = 0; base < ncol; base += L.S) {
       const int j = base + L.slot;
@@ -204,7 +207,7 @@ __device__ void node_backward(const SpArg& A, int sn, int t, int R, int r0, doub
   team_sync<TEAM>();
   {  // x_i = (L_ss^-T z)_i: rows j >= i
     const Lanes L = lanes_of(t, TEAM, R, ncol);
-    const double* M = A.linvt + A.linv_off[sn];  // (i, j) of L_ss^-T at M[j * ncol + i]
+    const double* M = A.linvt + d1.y;  // (i, j) of L_ss^-T at M[j * ncol + i]
     const int rg = r0 + L.r;
     for (int base = 0; base < ncol; base += L.S) {
       const int i = base + L.slot;
@@ -314,25 +317,265 @@ __global__ void __launch_bounds__(kSpThreads) k_sp_output(const SpArgs args) {
   }
 }
 
+// A bottom supernode is solved by one wave from LDS (staged) when its blocks
+// hold at most kSpStageMax entries and its gather indices at most kSpIdxMax:
+// the wave loads the blocks, the indices and its entries of the vector with
+// all loads in flight at once, then the update entries of its children (or,
+// backward, the entries of its struct rows), and forms both products from
+// LDS, so a step costs a few round trips to memory instead of one per row.
+// A supernode that cannot be staged, and its ancestors, belong to the top.
+constexpr int kSpStageMax = 1024;
+constexpr int kSpIdxMax = 256;
+__host__ __device__ inline bool sp_staged(int ncol, int nstr, int K) {
+  return ncol * (ncol + nstr) <= kSpStageMax && (ncol + nstr) * K <= kSpIdxMax;
+}
+
+// Forward step of a staged supernode on one wave (lane 0..63, R right-hand
+// sides from r0; a lane holds rows p0 + P a, a < ROWS, of the node's columns:
+// P ROWS >= ncol).  lds: the wave's slice, the front [m][R] first; F: the
+// blocks (L_ss^-1, then L_21, both column-major, as stored contiguously per
+// staged supernode at blk + blk_off); S: the gather indices.
+template <int ROWS>
+__device__ void wave_forward(const SpArg& A, int4 d0, int4 d1, int lane, int R, int r0, double2* lds, double* F,
+                             int* S, bool leaf) {
+  const int NR = A.nrhs, K = A.fr_k;
+  double2* x = A.scratch;
+  double2* u = A.u();
+  const int c0 = d0.x, ncol = d0.y, so = d0.z, nstr = d0.w, fo = d1.x;
+  const double* B = A.blk + d1.y;
+  const int m = ncol + nstr, nn = ncol * ncol, nf = nn + ncol * nstr, nidx = leaf ? 0 : m * K;
+  const int r = lane & (R - 1), rg = r0 + r, P = 64 / R, p0 = lane / R;
+  const bool live = rg < NR;
+  const double2 zero = make_double2(0.0, 0.0);
+  double2* v = lds;
+  // the blocks, the gather indices and the node's entries of the vector (the
+  // Laplacian's input mean taken off), all issued before any is used
+  int g[kSpIdxMax / 64];
+#pragma unroll
+  for (int i = 0; i < kSpIdxMax / 64; ++i) {
+    const int e = lane + 64 * i;
+    g[i] = e < nidx ? A.fr_src[(long)fo * K + e] : -1;
+  }
+  const double2 mu = (A.grounded && live) ? A.mean(0)[rg] : zero;
+  double2 xv[ROWS];
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) {
+    const int p = p0 + P * a;
+    xv[a] = (p < ncol && live) ? x[(long)(c0 + p) * NR + rg] : zero;
+  }
+  for (int e0 = lane; e0 < nf; e0 += 512) {
+    double f[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = e0 + 64 * i < nf ? B[e0 + 64 * i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (e0 + 64 * i < nf) F[e0 + 64 * i] = f[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kSpIdxMax / 64; ++i)
+    if (lane + 64 * i < nidx) S[lane + 64 * i] = g[i];
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) {
+    const int p = p0 + P * a;
+    if (p < ncol) v[p * R + r] = make_double2(xv[a].x - mu.x, xv[a].y - mu.y);
+  }
+  for (int p = p0; p < m; p += P)
+    if (p >= ncol) v[p * R + r] = zero;
+  wave_sync();
+  // the children's update entries, added per front entry in child order
+  if (!leaf) {
+    const int nw = ((m - p0 + P - 1) / P) * K;
+    for (int w0 = 0; w0 < nw; w0 += 8) {
+      double2 t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int w = w0 + i;
+        const int q = w < nw ? S[(p0 + P * (w / K)) * K + w % K] : -1;
+        t[i] = (q >= 0 && live) ? u[(long)q * NR + rg] : zero;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int w = w0 + i;
+        if (w < nw) {
+          double2* vp = v + (p0 + P * (w / K)) * R + r;
+          *vp = cadd(*vp, t[i]);
+        }
+      }
+    }
+    wave_sync();
+  }
+  // y = L_ss^-1 v_cols (rows p0 + P a), then into the front and x
+  double2 y[ROWS];
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) y[a] = zero;
+#pragma unroll 2
+  for (int j = 0; j < ncol; ++j) {
+    const double2 vj = v[j * R + r];
+#pragma unroll
+    for (int a = 0; a < ROWS; ++a) {
+      const int i = p0 + P * a;
+      if (i < ncol && j <= i) y[a] = cfma(F[j * ncol + i], vj, y[a]);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) {
+    const int i = p0 + P * a;
+    if (i < ncol) {
+      v[i * R + r] = y[a];
+      if (live) x[(long)(c0 + i) * NR + rg] = y[a];
+    }
+  }
+  wave_sync();
+  // u = v_struct - L_21 y
+  for (int q0 = p0; q0 < nstr; q0 += ROWS * P) {
+    double2 acc[ROWS];
+#pragma unroll
+    for (int b = 0; b < ROWS; ++b) acc[b] = zero;
+#pragma unroll 2
+    for (int j = 0; j < ncol; ++j) {
+      const double2 yj = v[j * R + r];
+#pragma unroll
+      for (int b = 0; b < ROWS; ++b) {
+        const int q = q0 + P * b;
+        if (q < nstr) acc[b] = cfma(F[nn + j * nstr + q], yj, acc[b]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < ROWS; ++b) {
+      const int q = q0 + P * b;
+      if (q < nstr && live) {
+        const double2 w = v[(ncol + q) * R + r];
+        u[(long)(so + q) * NR + rg] = make_double2(w.x - acc[b].x, w.y - acc[b].y);
+      }
+    }
+  }
+  wave_sync();
+}
+
+// Backward step of a staged supernode on one wave: z = y - L_21^T x_struct,
+// x = L_ss^-T z, from the same blocks as the forward step.
+template <int ROWS>
+__device__ void wave_backward(const SpArg& A, int4 d0, int4 d1, int lane, int R, int r0, double2* lds, double* F,
+                              int* S) {
+  const int NR = A.nrhs;
+  double2* x = A.scratch;
+  const int c0 = d0.x, ncol = d0.y, so = d0.z, nstr = d0.w;
+  const double* B = A.blk + d1.y;
+  const int nn = ncol * ncol, nf = nn + ncol * nstr;
+  const int r = lane & (R - 1), rg = r0 + r, P = 64 / R, p0 = lane / R;
+  const bool live = rg < NR;
+  const double2 zero = make_double2(0.0, 0.0);
+  double2* xs = lds;             // x_struct [nstr][R]
+  double2* z = lds + nstr * R;   // z [ncol][R]
+  int g[kSpIdxMax / 64];
+#pragma unroll
+  for (int i = 0; i < kSpIdxMax / 64; ++i) {
+    const int e = lane + 64 * i;
+    g[i] = e < nstr ? A.str[so + e] : 0;
+  }
+  double2 yv[ROWS];  // the forward step's y
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) {
+    const int j = p0 + P * a;
+    yv[a] = (j < ncol && live) ? x[(long)(c0 + j) * NR + rg] : zero;
+  }
+  for (int e0 = lane; e0 < nf; e0 += 512) {
+    double f[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = e0 + 64 * i < nf ? B[e0 + 64 * i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (e0 + 64 * i < nf) F[e0 + 64 * i] = f[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kSpIdxMax / 64; ++i)
+    if (lane + 64 * i < nstr) S[lane + 64 * i] = g[i];
+  wave_sync();
+  // x_struct: the solution on the struct rows
+  for (int q0 = p0; q0 < nstr; q0 += 8 * P) {
+    double2 t[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = q0 + P * i;
+      t[i] = (q < nstr && live) ? x[(long)S[q] * NR + rg] : zero;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = q0 + P * i;
+      if (q < nstr) xs[q * R + r] = t[i];
+    }
+  }
+  wave_sync();
+  // z_j = y_j - (L_21^T x_struct)_j
+  double2 acc[ROWS];
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) acc[a] = zero;
+#pragma unroll 2
+  for (int q = 0; q < nstr; ++q) {
+    const double2 xq = xs[q * R + r];
+#pragma unroll
+    for (int a = 0; a < ROWS; ++a) {
+      const int j = p0 + P * a;
+      if (j < ncol) acc[a] = cfma(F[nn + j * nstr + q], xq, acc[a]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) {
+    const int j = p0 + P * a;
+    if (j < ncol) z[j * R + r] = make_double2(yv[a].x - acc[a].x, yv[a].y - acc[a].y);
+  }
+  wave_sync();
+  // x_i = (L_ss^-T z)_i = sum over j >= i of (L_ss^-1)_ji z_j
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) acc[a] = zero;
+#pragma unroll 2
+  for (int j = 0; j < ncol; ++j) {
+    const double2 zj = z[j * R + r];
+#pragma unroll
+    for (int a = 0; a < ROWS; ++a) {
+      const int i = p0 + P * a;
+      if (i <= j) acc[a] = cfma(F[i * ncol + j], zj, acc[a]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) {
+    const int i = p0 + P * a;
+    if (i < ncol && live) x[(long)(c0 + i) * NR + rg] = acc[a];
+  }
+  wave_sync();
+}
+
 // bottom subtrees: one workgroup per (subtree, R right-hand sides, job); the
-// subtree's heights in order, one wave per supernode, `slice` LDS entries per
-// wave, at most kSpBottomWaves waves
+// subtree's heights in order, one wave per (staged) supernode, at most
+// kSpBottomWaves waves.  A wave's LDS slice (sp_slice entries): the fronts, `vec` entries
+// per right-hand side, then the staged blocks (`fac` doubles, even) and the
+// gather indices (`idx` ints, a multiple of 4).
 constexpr int kSpBottomWaves = 8;
-__global__ void __launch_bounds__(64 * kSpBottomWaves) k_sp_bottom(const SpArgs args, int backward, int R, int slice) {
+constexpr int kSpBottomMinWaves = 3;
+constexpr int kSpBottomTarget = 512;
+__host__ __device__ inline int sp_slice(int R, int vec, int fac, int idx) { return vec * R + fac / 2 + idx / 4; }
+template <int ROWS>
+__global__ void __launch_bounds__(64 * kSpBottomWaves)
+    k_sp_bottom(const SpArgs args, int backward, int R, int vec, int fac, int idx) {
   const SpArg& A = args.a[blockIdx.z];
   const int b = blockIdx.x, r0 = blockIdx.y * R;
   if (b >= A.nsub || r0 >= A.nrhs) return;
   extern __shared__ double2 lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int slice = sp_slice(R, vec, fac, idx);
   double2* mine = lds + (long)wave * slice;
+  double* F = reinterpret_cast<double*>(mine + vec * R);
+  int* S = reinterpret_cast<int*>(F + fac);
   const int l0 = A.sub_ptr[b], nl = A.sub_ptr[b + 1] - l0 - 1;
   for (int q = 0; q < nl; ++q) {
     const int l = backward ? nl - 1 - q : q;
     for (int k = A.sub_lvl[l0 + l] + wave; k < A.sub_lvl[l0 + l + 1]; k += W) {
+      const int4 d0 = A.sub_desc[2 * k], d1 = A.sub_desc[2 * k + 1];
       if (backward)
-        node_backward<64>(A, A.sub_nodes[k], lane, R, r0, mine);
+        wave_backward<ROWS>(A, d0, d1, lane, R, r0, mine, F, S);
       else
-        node_forward<64>(A, A.sub_nodes[k], lane, R, r0, mine);
+        wave_forward<ROWS>(A, d0, d1, lane, R, r0, mine, F, S, l == 0);
     }
     __syncthreads();
   }
@@ -343,13 +586,14 @@ __global__ void __launch_bounds__(kSpThreads) k_sp_top(const SpArgs args, int le
   const SpArg& A = args.a[blockIdx.z];
   const int r0 = blockIdx.y * R;
   if (level >= A.ntop || r0 >= A.nrhs) return;
-  const int k = A.top_lvl[level] + blockIdx.x;
-  if (k >= A.top_lvl[level + 1]) return;
+  const int k = A.top_start[level] + blockIdx.x;
+  if (k >= A.top_start[level + 1]) return;
   extern __shared__ double2 lds[];
+  const int4 d0 = A.top_desc[2 * k], d1 = A.top_desc[2 * k + 1];
   if (backward)
-    node_backward<kSpThreads>(A, A.top_nodes[k], threadIdx.x, R, r0, lds);
+    node_backward<kSpThreads>(A, d0, d1, threadIdx.x, R, r0, lds);
   else
-    node_forward<kSpThreads>(A, A.top_nodes[k], threadIdx.x, R, r0, lds);
+    node_forward<kSpThreads>(A, d0, d1, threadIdx.x, R, r0, lds);
 }
 
 // Right-hand sides per workgroup: the largest power of two up to 16 that
@@ -370,7 +614,7 @@ rfcmp_status spsolve_jobs(const SpSolveJob* jobs, int njobs, int nrhs, hipStream
     return RFCMP_E_ARG;
   }
   SpArgs args{};
-  int nsub = 0, ntop = 0, blds = 0, ntile = 0;
+  int nsub = 0, ntop = 0, blds = 0, bfac = 0, bidx = 0, bncol = 0, ntile = 0;
   bool grounded = false;
   for (int q = 0; q < njobs; ++q) {
     const SpDevice& F = *jobs[q].F;
@@ -391,15 +635,21 @@ rfcmp_status spsolve_jobs(const SpSolveJob* jobs, int njobs, int nrhs, hipStream
     a.fr_src = F.fr_src.as<int>();
     a.linv_off = F.linv_off.as<long>();
     a.l21_off = F.l21_off.as<long>();
+    a.blk_off = F.blk_off.as<long>();
+    a.blk = F.blk.as<double>();
     a.l21 = F.l21.as<double>();
     a.l21t = F.l21t.as<double>();
     a.linv = F.linv.as<double>();
     a.linvt = F.linvt.as<double>();
     a.sub_ptr = F.sub_ptr.as<int>();
     a.sub_lvl = F.sub_lvl.as<int>();
-    a.sub_nodes = F.sub_nodes.as<int>();
-    a.top_lvl = F.top_lvl.as<int>();
-    a.top_nodes = F.top_nodes.as<int>();
+    a.sub_desc = F.sub_desc.as<int4>();
+    a.top_desc = F.top_desc.as<int4>();
+    if (F.ntop > kSpTopMax) {
+      set_error("spsolve: %d top heights (at most %d)", F.ntop, kSpTopMax);
+      return RFCMP_E_STATE;
+    }
+    for (int l = 0; l <= F.ntop; ++l) a.top_start[l] = F.top_start[l];
     a.in = jobs[q].in;
     a.y = jobs[q].y;
     a.scratch = jobs[q].scratch;
@@ -407,20 +657,28 @@ rfcmp_status spsolve_jobs(const SpSolveJob* jobs, int njobs, int nrhs, hipStream
     nsub = std::max(nsub, F.nsub);
     ntop = std::max(ntop, F.ntop);
     blds = std::max(blds, F.bot_lds);
+    bfac = std::max(bfac, F.bot_fac);
+    bidx = std::max(bidx, F.bot_idx);
+    bncol = std::max(bncol, F.bot_ncol);
     ntile = std::max(ntile, a.ntile);
     grounded = grounded || F.grounded;
   }
-  // bottom: about 512 workgroups; as many waves as their slices fit 64 KB
-  int Rb = 1, W = 1;
+  // bottom: about kSpBottomTarget workgroups, each of up to kSpBottomWaves
+  // waves and at least kSpBottomMinWaves where their slices fit 64 KB; the
+  // rows per lane from the widest bottom supernode
+  int Rb = 1, W = 1, rows = 1;
   int64_t slice = 0;
   if (nsub > 0) {
-    Rb = rhs_per_group(nrhs, nsub, 512, blds, 4);
-    slice = (int64_t)blds * Rb;
+    while (Rb < 16 && (int64_t)nrhs * nsub >= (int64_t)2 * Rb * kSpBottomTarget) Rb *= 2;
+    while (Rb > 1 && (int64_t)kSpBottomMinWaves * sp_slice(Rb, blds, bfac, bidx) * (int64_t)sizeof(double2) > 65536)
+      Rb /= 2;
+    slice = sp_slice(Rb, blds, bfac, bidx);
     if (slice * (int64_t)sizeof(double2) > 65536) {
       set_error("spsolve: a front of %d entries does not fit the LDS", blds);
       return RFCMP_E_STATE;
     }
     W = (int)std::min<int64_t>(kSpBottomWaves, 65536 / (slice * (int64_t)sizeof(double2)));
+    while (rows * (64 / Rb) < bncol) rows *= 2;
   }
   // top: per height, about 256 workgroups
   std::vector<int> Rt(ntop), nodes(ntop), need(ntop);
@@ -444,9 +702,21 @@ rfcmp_status spsolve_jobs(const SpSolveJob* jobs, int njobs, int nrhs, hipStream
   hipLaunchKernelGGL(k_sp_input, tiles, dim3(kSpThreads), 0, s, args);
   if (grounded) hipLaunchKernelGGL(k_sp_mean, dim3(nrt, 1, nj), dim3(kSpThreads), 0, s, args, 0);
   const dim3 bgrid((unsigned)nsub, (unsigned)((nrhs + Rb - 1) / Rb), nj);
+  auto bottom = [&](int bwd) -> rfcmp_status {
+    const size_t lds = (size_t)(W * slice) * sizeof(double2);
+    switch (rows) {
+      case 1: hipLaunchKernelGGL(k_sp_bottom<1>, bgrid, dim3(64 * W), lds, s, args, bwd, Rb, blds, bfac, bidx); break;
+      case 2: hipLaunchKernelGGL(k_sp_bottom<2>, bgrid, dim3(64 * W), lds, s, args, bwd, Rb, blds, bfac, bidx); break;
+      case 4: hipLaunchKernelGGL(k_sp_bottom<4>, bgrid, dim3(64 * W), lds, s, args, bwd, Rb, blds, bfac, bidx); break;
+      case 8: hipLaunchKernelGGL(k_sp_bottom<8>, bgrid, dim3(64 * W), lds, s, args, bwd, Rb, blds, bfac, bidx); break;
+      default:
+        set_error("spsolve: %d rows per lane", rows);
+        return RFCMP_E_STATE;
+    }
+    return RFCMP_OK;
+  };
   if (nsub > 0)
-    hipLaunchKernelGGL(k_sp_bottom, bgrid, dim3(64 * W), (size_t)(W * slice) * sizeof(double2), s, args, 0, Rb,
-                       (int)slice);
+    RF_TRY(bottom(0));
   auto top = [&](int l, int bwd) {
     hipLaunchKernelGGL(k_sp_top, dim3((unsigned)nodes[l], (unsigned)((nrhs + Rt[l] - 1) / Rt[l]), nj), dim3(kSpThreads),
                        (size_t)need[l] * Rt[l] * sizeof(double2), s, args, l, bwd, Rt[l]);
@@ -454,8 +724,7 @@ rfcmp_status spsolve_jobs(const SpSolveJob* jobs, int njobs, int nrhs, hipStream
   for (int l = 0; l < ntop; ++l) top(l, 0);
   for (int l = ntop - 1; l >= 0; --l) top(l, 1);
   if (nsub > 0)
-    hipLaunchKernelGGL(k_sp_bottom, bgrid, dim3(64 * W), (size_t)(W * slice) * sizeof(double2), s, args, 1, Rb,
-                       (int)slice);
+    RF_TRY(bottom(1));
   if (grounded) {
     hipLaunchKernelGGL(k_sp_colsum, tiles, dim3(kSpThreads), 0, s, args);
     hipLaunchKernelGGL(k_sp_mean, dim3(nrt, 1, nj), dim3(kSpThreads), 0, s, args, 1);
@@ -535,15 +804,32 @@ void spchol_arrays(const SpFactor& F, SpArrays& a) {
     first[q] = F.col0[q];
     for (int qc = F.child_off[q]; qc < F.child_off[q + 1]; ++qc) first[q] = std::min(first[q], first[F.child_idx[qc]]);
   }
+  // a bottom subtree holds staged supernodes only (children come first)
   std::vector<char> bottom(nsn, 0);
-  for (int q = 0; q < nsn; ++q) bottom[q] = F.col0[q + 1] - first[q] <= cap;
+  for (int q = 0; q < nsn; ++q) {
+    bottom[q] = F.col0[q + 1] - first[q] <= cap &&
+                sp_staged(F.col0[q + 1] - F.col0[q], F.str_off[q + 1] - F.str_off[q], a.fr_k);
+    for (int qc = F.child_off[q]; qc < F.child_off[q + 1]; ++qc) bottom[q] = bottom[q] && bottom[F.child_idx[qc]];
+  }
   a.sub_ptr.assign(1, 0);
   a.sub_lvl.clear();
   a.sub_nodes.clear();
   a.bot_lds = 0;
+  a.bot_fac = 0;
+  a.bot_idx = 0;
+  a.bot_ncol = 0;
   auto lds_need = [&](int p) {
     const int ncol = F.col0[p + 1] - F.col0[p], nstr = F.str_off[p + 1] - F.str_off[p];
     return 2 * ncol + nstr;
+  };
+  // a bottom supernode's slice: its front (per right-hand side), its blocks
+  // and its gather indices
+  auto bottom_need = [&](int p) {
+    const int ncol = F.col0[p + 1] - F.col0[p], nstr = F.str_off[p + 1] - F.str_off[p];
+    a.bot_lds = std::max(a.bot_lds, ncol + nstr);
+    a.bot_ncol = std::max(a.bot_ncol, ncol);
+    a.bot_fac = std::max(a.bot_fac, (ncol * (ncol + nstr) + 1) / 2 * 2);
+    a.bot_idx = std::max(a.bot_idx, ((ncol + nstr) * a.fr_k + 3) / 4 * 4);
   };
   int nsub = 0;
   for (int q = 0; q < nsn; ++q) {
@@ -559,7 +845,7 @@ void spchol_arrays(const SpFactor& F, SpArrays& a) {
       for (int p : members)
         if (F.height[p] == h) {
           a.sub_nodes.push_back(p);
-          a.bot_lds = std::max(a.bot_lds, lds_need(p));
+          bottom_need(p);
         }
       a.sub_lvl.push_back((int)a.sub_nodes.size());
     }
@@ -567,6 +853,22 @@ void spchol_arrays(const SpFactor& F, SpArrays& a) {
     ++nsub;
   }
   a.nsub = nsub;
+  // the staged bottom supernodes' blocks, L_ss^-1 then L_21 contiguously
+  a.blk_off.assign(nsn, 0);
+  a.blk.clear();
+  for (int p : a.sub_nodes) {
+    a.blk_off[p] = (long)a.blk.size();
+    a.blk.insert(a.blk.end(), a.linv.begin() + a.linv_off[p], a.linv.begin() + a.linv_off[p + 1]);
+    a.blk.insert(a.blk.end(), a.l21.begin() + a.l21_off[p], a.l21.begin() + a.l21_off[p + 1]);
+  }
+  // per bottom position, the supernode's columns, struct rows, front and
+  // blocks: {col0, ncol, str_off, nstr}, {front_off, blk_off, 0, 0}
+  a.sub_desc.clear();
+  for (int p : a.sub_nodes) {
+    const int ncol = F.col0[p + 1] - F.col0[p], nstr = F.str_off[p + 1] - F.str_off[p];
+    a.sub_desc.insert(a.sub_desc.end(),
+                      {F.col0[p], ncol, F.str_off[p], nstr, (int)a.front_off[p], (int)a.blk_off[p], 0, 0});
+  }
   // top supernodes by height
   int H = 0;
   for (int q = 0; q < nsn; ++q)
@@ -590,6 +892,14 @@ void spchol_arrays(const SpFactor& F, SpArrays& a) {
     a.top_lvl.push_back((int)a.top_nodes.size());
   }
   a.ntop = (int)a.top_lvl.size() - 1;
+  // per top position, the supernode's descriptor {col0, ncol, str_off, nstr},
+  // {front_off, linv_off, l21_off, 0}
+  a.top_desc.clear();
+  for (int p : a.top_nodes) {
+    const int ncol = F.col0[p + 1] - F.col0[p], nstr = F.str_off[p + 1] - F.str_off[p];
+    a.top_desc.insert(a.top_desc.end(), {F.col0[p], ncol, F.str_off[p], nstr, (int)a.front_off[p],
+                                         (int)a.linv_off[p], (int)a.l21_off[p], 0});
+  }
   a.iperm.assign(n, 0);
   for (int i = 0; i < n; ++i) a.iperm[F.perm[i]] = i;
 }
@@ -598,6 +908,11 @@ rfcmp_status spchol_upload(const SpFactor& F, SpDevice& D, hipStream_t s) {
   const int n = F.n, nsn = F.nsn;
   SpArrays a;
   spchol_arrays(F, a);
+  if (a.blk.size() > (size_t)INT32_MAX || a.front_total > INT32_MAX || a.linv_off[nsn] > INT32_MAX ||
+      a.l21_off[nsn] > INT32_MAX) {
+    set_error("spchol_upload: factor blocks beyond 32-bit offsets");
+    return RFCMP_E_ARG;
+  }
   D.n = n;
   D.nsn = nsn;
   D.grounded = F.grounded ? 1 : 0;
@@ -606,13 +921,16 @@ rfcmp_status spchol_upload(const SpFactor& F, SpDevice& D, hipStream_t s) {
   D.nsub = a.nsub;
   D.ntop = a.ntop;
   D.bot_lds = a.bot_lds;
+  D.bot_fac = a.bot_fac;
+  D.bot_idx = a.bot_idx;
+  D.bot_ncol = a.bot_ncol;
   D.fr_k = a.fr_k;
   D.top_count = a.top_count;
   D.top_lds = a.top_lds;
   D.seconds = F.seconds;
   D.nstr_total = F.str_off[nsn];
   D.front_total = a.front_total;
-  D.nnz = (int64_t)(a.l21.size() + a.l21t.size() + a.linv.size() + a.linvt.size());
+  D.nnz = (int64_t)(a.l21.size() + a.l21t.size() + a.linv.size() + a.linvt.size() + a.blk.size());
   auto up = [&](DevBuf& b, const void* src, size_t bytes) -> rfcmp_status {
     RF_TRY(b.alloc(std::max<size_t>(bytes, 16)));
     if (bytes) RF_HIP(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));
@@ -628,15 +946,17 @@ rfcmp_status spchol_upload(const SpFactor& F, SpDevice& D, hipStream_t s) {
   RF_TRY(upv(D.fr_src, a.fr_src));
   RF_TRY(upv(D.linv_off, a.linv_off));
   RF_TRY(upv(D.l21_off, a.l21_off));
+  RF_TRY(upv(D.blk_off, a.blk_off));
+  RF_TRY(upv(D.blk, a.blk));
   RF_TRY(upv(D.l21, a.l21));
   RF_TRY(upv(D.l21t, a.l21t));
   RF_TRY(upv(D.linv, a.linv));
   RF_TRY(upv(D.linvt, a.linvt));
   RF_TRY(upv(D.sub_ptr, a.sub_ptr));
   RF_TRY(upv(D.sub_lvl, a.sub_lvl));
-  RF_TRY(upv(D.sub_nodes, a.sub_nodes));
-  RF_TRY(upv(D.top_lvl, a.top_lvl));
-  RF_TRY(upv(D.top_nodes, a.top_nodes));
+  RF_TRY(upv(D.sub_desc, a.sub_desc));
+  RF_TRY(upv(D.top_desc, a.top_desc));
+  D.top_start = a.top_lvl;
   // the host arrays above are locals: wait for the copies
   RF_HIP(hipStreamSynchronize(s));
   return RFCMP_OK;

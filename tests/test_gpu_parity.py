@@ -437,22 +437,23 @@ def test_full_size_solution_properties(name, k, nrhs, precision):
     m.close()
 
 
-@pytest.mark.parametrize("nmajor,nminor", [(112, 64), (160, 64)])
+@pytest.mark.parametrize("nmajor,nminor,nrhs", [(112, 64, 2), (160, 64, 2), (160, 64, 45)])
 @pytest.mark.parametrize("projector", [1, 2])
-def test_projector_inverses_large(nmajor, nminor, projector):
+def test_projector_inverses_large(nmajor, nminor, nrhs, projector):
     """The blocked inverse at sizes beyond the parity meshes (C = 14336 and
     20480 cells, 224 and 320 pivot blocks), by identities that hold at any
     size: L L^+ x = x - mean(x) with L = Sigma^T Sigma, and G_ll G_ll^-1 y = y
     with the P1 mass matrix, both applied sparsely here from the mesh.  A
     race between the panel and update kernels once made L^+ non-finite at
-    these sizes."""
+    these sizes.  45 right-hand sides: the sparse solve's groups of 8 and 16
+    with a ragged last group."""
     torch, rf = _gpu()
     xyz, tri = synth.torus(nmajor, nminor)
     top = Topology(xyz, tri)
     m = rf.Mesh(xyz, tri)
     op = rf.Operator(m, 1.0, scaling=1, projector=projector)
     rng = np.random.default_rng(5)
-    x = rng.standard_normal((2, top.C)) + 1j * rng.standard_normal((2, top.C))
+    x = rng.standard_normal((nrhs, top.C)) + 1j * rng.standard_normal((nrhs, top.C))
     lx = _np(op.project(rf.PROJ_LPINV, _cuda(x)))
     def lap(v):  # Sigma^T Sigma v: (Sigma v)_n = v[c+] - v[c-]
         d = v[top.cplus] - v[top.cminus]
@@ -472,9 +473,9 @@ def test_projector_inverses_large(nmajor, nminor, projector):
         np.add.at(out, top.tri.ravel(), loc.ravel())
         return out
 
-    y = rng.standard_normal(top.V) + 0j
-    gy = _np(op.project(rf.PROJ_GLL_INV, _cuda(y[None, :])))[0]
-    assert rel(mass(gy), y) < 1e-10
+    y = rng.standard_normal((nrhs, top.V)) + 1j * rng.standard_normal((nrhs, top.V))
+    gy = _np(op.project(rf.PROJ_GLL_INV, _cuda(y)))
+    assert rel(np.stack([mass(v) for v in gy]), y) < 1e-10
     op.close()
     m.close()
 
