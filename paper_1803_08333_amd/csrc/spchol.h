@@ -80,15 +80,19 @@ constexpr int kSpTile = 64;
 // A factor on the device, in the layout the solve reads.
 //
 // The supernodes split into bottom subtrees (every supernode whose subtree
-// spans at most about n/96 columns, grouped under the highest such
-// supernodes) and the top supernodes above them.  A solve is a short chain of
+// spans at most about n/96 columns and holds only supernodes whose blocks
+// have at most 1024 entries, grouped under the highest such supernodes) and
+// the top supernodes above them.  A solve is a short chain of
 // launches, each over many workgroups (and right-hand sides):
 //   input: the right-hand side formed (the operator's gathers) and permuted,
 //     a tile of entries by 16 right-hand sides per workgroup, transposed
 //     through LDS (for the Laplacian also its partial sums, then their mean);
 //   forward, bottom: one workgroup per subtree, its heights in order, one
-//     wave per supernode (the Laplacian's input mean taken off as the
-//     columns are read);
+//     wave per supernode, which loads the supernode's blocks, its gather
+//     indices and its entries of the vector into LDS with all loads in
+//     flight, then its children's update entries, and forms the products
+//     from LDS (the Laplacian's input mean taken off as the columns are
+//     read);
 //   forward, top: one launch per height, one workgroup per supernode;
 //   backward, top: heights down, one launch each;
 //   backward, bottom: one workgroup per subtree;
