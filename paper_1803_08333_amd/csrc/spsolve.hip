@@ -797,7 +797,9 @@ void spchol_arrays(const SpFactor& F, SpArrays& a) {
   // (about 128 subtrees of a nested dissection): measured against n / 12 to
   // n / 192 on the level-5 and level-6 spheres, the fastest 64-right-hand-side
   // Laplacian solve at both levels (0.38 and 1.37 ms against 0.50 and 2.10 at
-  // n / 48) and the fastest G_ll solve at level 6
+  // n / 48) and the fastest G_ll solve at level 6; with the staged bottom
+  // steps still the fastest Laplacian solve at level 5 (349 us against 364 at
+  // n / 48 and 408 at n / 192)
   const int cap = std::max(128, n / 96);
   std::vector<int> first(nsn);  // first column of each supernode's subtree
   for (int q = 0; q < nsn; ++q) {
