@@ -94,7 +94,8 @@ constexpr int kSpTile = 64;
 //     from LDS (the Laplacian's input mean taken off as the columns are
 //     read);
 //   forward, top: one launch per height, one workgroup per supernode;
-//   backward, top: heights down, one launch each;
+//   backward, top: heights down, one launch each (the highest height's
+//     roots take their backward step in the forward launch);
 //   backward, bottom: one workgroup per subtree;
 //   output: permuted back (for the Laplacian less the mean of the result,
 //     from partial sums over tiles).
@@ -138,6 +139,7 @@ struct SpDevice {
   // each height (host)
   DevBuf top_desc;
   std::vector<int> top_start;
+  bool top_roots = false;  // the highest top height holds roots only (no struct rows)
   // per top height (host copies): supernodes, and the largest LDS need
   std::vector<int> top_count, top_lds;
   // complex128 entries of solve scratch per right-hand side: the permuted
@@ -160,6 +162,7 @@ struct SpArrays {
   std::vector<double> l21, l21t, linv, linvt, blk;
   std::vector<int> sub_ptr, sub_lvl, sub_nodes, sub_desc, top_lvl, top_nodes, top_desc;
   std::vector<int> top_count, top_lds;
+  bool top_roots = false;
 };
 void spchol_arrays(const SpFactor& F, SpArrays& out);
 

@@ -178,8 +178,11 @@ __device__ void node_forward(const SpArg& A, int4 d0, int4 d1, int t, int R, int
 }
 
 // Backward step of a supernode: x_s = L_ss^-T (y - L_21^T x_struct).
+// ylds: y as the forward step left it in LDS (a root, right after its
+// forward step), else null (y read from x).
 template <int TEAM>
-__device__ void node_backward(const SpArg& A, int4 d0, int4 d1, int t, int R, int r0, double2* lds) {
+__device__ void node_backward(const SpArg& A, int4 d0, int4 d1, int t, int R, int r0, double2* lds,
+                              const double2* ylds = nullptr) {
   const int NR = A.nrhs;
   double2* x = A.scratch;
   const int c0 = d0.x, ncol = d0.y, so = d0.z, nstr = d0.w;
@@ -199,7 +202,7 @@ __device__ void node_backward(const SpArg& A, int4 d0, int4 d1, int t, int R, in
       const int j = base + L.slot;
       const double2 acc = group_sum(strided_dot(M, ncol, j, xs, R, L.r, 0, j < ncol ? nstr : 0, L.g, L.G), R, L.G);
       if (j < ncol && L.g == 0) {
-        const double2 yy = rg < NR ? x[(long)(c0 + j) * NR + rg] : make_double2(0.0, 0.0);
+        const double2 yy = ylds ? ylds[j * R + L.r] : (rg < NR ? x[(long)(c0 + j) * NR + rg] : make_double2(0.0, 0.0));
         z[j * R + L.r] = make_double2(yy.x - acc.x, yy.y - acc.y);
       }
     }
@@ -581,7 +584,10 @@ __global__ void __launch_bounds__(64 * kSpBottomWaves)
   }
 }
 
-// one top height: one workgroup per (supernode, R right-hand sides, job)
+// one top height: one workgroup per (supernode, R right-hand sides, job);
+// backward 2: the forward and then the backward step (the highest height,
+// whose supernodes are roots: no struct rows, so the backward step needs
+// nothing but the forward step's result)
 __global__ void __launch_bounds__(kSpThreads) k_sp_top(const SpArgs args, int level, int backward, int R) {
   const SpArg& A = args.a[blockIdx.z];
   const int r0 = blockIdx.y * R;
@@ -590,10 +596,14 @@ __global__ void __launch_bounds__(kSpThreads) k_sp_top(const SpArgs args, int le
   if (k >= A.top_start[level + 1]) return;
   extern __shared__ double2 lds[];
   const int4 d0 = A.top_desc[2 * k], d1 = A.top_desc[2 * k + 1];
-  if (backward)
-    node_backward<kSpThreads>(A, d0, d1, threadIdx.x, R, r0, lds);
-  else
+  if (backward == 0) {
     node_forward<kSpThreads>(A, d0, d1, threadIdx.x, R, r0, lds);
+  } else if (backward == 1) {
+    node_backward<kSpThreads>(A, d0, d1, threadIdx.x, R, r0, lds);
+  } else {  // a root: the forward step leaves y at lds + ncol R, past the z the backward step writes
+    node_forward<kSpThreads>(A, d0, d1, threadIdx.x, R, r0, lds);
+    node_backward<kSpThreads>(A, d0, d1, threadIdx.x, R, r0, lds, lds + d0.y * R);
+  }
 }
 
 // Right-hand sides per workgroup: the largest power of two up to 16 that
@@ -721,8 +731,14 @@ rfcmp_status spsolve_jobs(const SpSolveJob* jobs, int njobs, int nrhs, hipStream
     hipLaunchKernelGGL(k_sp_top, dim3((unsigned)nodes[l], (unsigned)((nrhs + Rt[l] - 1) / Rt[l]), nj), dim3(kSpThreads),
                        (size_t)need[l] * Rt[l] * sizeof(double2), s, args, l, bwd, Rt[l]);
   };
-  for (int l = 0; l < ntop; ++l) top(l, 0);
-  for (int l = ntop - 1; l >= 0; --l) top(l, 1);
+  // the highest height in one launch when its supernodes are roots
+  bool roots = true;
+  for (int q = 0; q < njobs; ++q)
+    if (jobs[q].F->ntop == ntop) roots = roots && jobs[q].F->top_roots;
+  const int fused = (ntop > 0 && roots) ? 1 : 0;
+  for (int l = 0; l < ntop - fused; ++l) top(l, 0);
+  if (fused) top(ntop - 1, 2);
+  for (int l = ntop - 1 - fused; l >= 0; --l) top(l, 1);
   if (nsub > 0)
     RF_TRY(bottom(1));
   if (grounded) {
@@ -894,6 +910,10 @@ void spchol_arrays(const SpFactor& F, SpArrays& a) {
     a.top_lvl.push_back((int)a.top_nodes.size());
   }
   a.ntop = (int)a.top_lvl.size() - 1;
+  a.top_roots = true;
+  if (a.ntop > 0)
+    for (int k = a.top_lvl[a.ntop - 1]; k < a.top_lvl[a.ntop]; ++k)
+      a.top_roots = a.top_roots && F.str_off[a.top_nodes[k] + 1] == F.str_off[a.top_nodes[k]];
   // per top position, the supernode's descriptor {col0, ncol, str_off, nstr},
   // {front_off, linv_off, l21_off, 0}
   a.top_desc.clear();
@@ -926,6 +946,7 @@ rfcmp_status spchol_upload(const SpFactor& F, SpDevice& D, hipStream_t s) {
   D.bot_fac = a.bot_fac;
   D.bot_idx = a.bot_idx;
   D.bot_ncol = a.bot_ncol;
+  D.top_roots = a.top_roots;
   D.fr_k = a.fr_k;
   D.top_count = a.top_count;
   D.top_lds = a.top_lds;
