@@ -322,10 +322,11 @@ __global__ void __launch_bounds__(kSpThreads) k_sp_output(const SpArgs args) {
 
 // A bottom supernode is solved by one wave from LDS (staged) when its blocks
 // hold at most kSpStageMax entries and its gather indices at most kSpIdxMax:
-// the wave loads the blocks, the indices and its entries of the vector with
-// all loads in flight at once, then the update entries of its children (or,
-// backward, the entries of its struct rows), and forms both products from
-// LDS, so a step costs a few round trips to memory instead of one per row.
+// the wave issues the loads of the indices, its entries of the vector and
+// the blocks (512 entries per round) together, then those of the update
+// entries of its children (or, backward, the entries of its struct rows),
+// eight per lane per round, and forms both products from LDS, so a step
+// costs a few round trips to memory instead of one per row.
 // A supernode that cannot be staged, and its ancestors, belong to the top.
 constexpr int kSpStageMax = 1024;
 constexpr int kSpIdxMax = 256;
@@ -333,9 +334,10 @@ __host__ __device__ inline bool sp_staged(int ncol, int nstr, int K) {
   return ncol * (ncol + nstr) <= kSpStageMax && (ncol + nstr) * K <= kSpIdxMax;
 }
 
-// Forward step of a staged supernode on one wave (lane 0..63, R right-hand
-// sides from r0; a lane holds rows p0 + P a, a < ROWS, of the node's columns:
-// P ROWS >= ncol).  lds: the wave's slice, the front [m][R] first; F: the
+// Forward step of a staged supernode (descriptor record d0 = {col0, ncol,
+// str_off, nstr}, d1 = {front_off, blk_off, 0, 0}) on one wave (lane 0..63,
+// R right-hand sides from r0; a lane holds rows p0 + P a, a < ROWS, of the
+// node's columns: P ROWS >= ncol).  lds: the wave's slice, the front [m][R] first; F: the
 // blocks (L_ss^-1, then L_21, both column-major, as stored contiguously per
 // staged supernode at blk + blk_off); S: the gather indices.
 template <int ROWS>
