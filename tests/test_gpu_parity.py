@@ -437,7 +437,7 @@ def test_full_size_solution_properties(name, k, nrhs, precision):
     m.close()
 
 
-@pytest.mark.parametrize("nmajor,nminor,nrhs", [(112, 64, 2), (160, 64, 2), (160, 64, 45)])
+@pytest.mark.parametrize("nmajor,nminor,nrhs", [(112, 64, 2), (160, 64, 2), (160, 64, 45), (160, 64, 64)])
 @pytest.mark.parametrize("projector", [1, 2])
 def test_projector_inverses_large(nmajor, nminor, nrhs, projector):
     """The blocked inverse at sizes beyond the parity meshes (C = 14336 and
@@ -445,8 +445,9 @@ def test_projector_inverses_large(nmajor, nminor, nrhs, projector):
     size: L L^+ x = x - mean(x) with L = Sigma^T Sigma, and G_ll G_ll^-1 y = y
     with the P1 mass matrix, both applied sparsely here from the mesh.  A
     race between the panel and update kernels once made L^+ non-finite at
-    these sizes.  45 right-hand sides: the sparse solve's groups of 8 and 16
-    with a ragged last group."""
+    these sizes.  45 right-hand sides: the sparse solve's groups of 8 with a
+    ragged last group; 64: groups of 16 (four rows per lane in the bottom
+    supernodes' steps), as in the 64-wave solves."""
     torch, rf = _gpu()
     xyz, tri = synth.torus(nmajor, nminor)
     top = Topology(xyz, tri)
