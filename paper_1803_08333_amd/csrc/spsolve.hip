@@ -138,9 +138,18 @@ __device__ void node_forward(const SpArg& A, int4 d0, int4 d1, int t, int R, int
           const double2 xv = x[(long)(c0 + p) * NR + rg];
           val = make_double2(xv.x - mu.x, xv.y - mu.y);
         }
-        for (int k = 0; k < K; ++k) {
-          const int q = A.fr_src[(long)(fo + p) * K + k];
-          if (q >= 0) val = cadd(val, u[(long)q * NR + rg]);
+        // the gather indices of up to four sources first, then their
+        // entries (added in source order)
+        for (int k0 = 0; k0 < K; k0 += 4) {
+          int q[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) q[k] = k0 + k < K ? A.fr_src[(long)(fo + p) * K + k0 + k] : -1;
+          double2 w[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) w[k] = q[k] >= 0 ? u[(long)q[k] * NR + rg] : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (q[k] >= 0) val = cadd(val, w[k]);
         }
       }
       v[p * R + r] = val;
