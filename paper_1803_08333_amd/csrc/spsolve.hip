@@ -584,12 +584,27 @@ __global__ void __launch_bounds__(64 * kSpBottomWaves)
   const int l0 = A.sub_ptr[b], nl = A.sub_ptr[b + 1] - l0 - 1;
   for (int q = 0; q < nl; ++q) {
     const int l = backward ? nl - 1 - q : q;
-    for (int k = A.sub_lvl[l0 + l] + wave; k < A.sub_lvl[l0 + l + 1]; k += W) {
-      const int4 d0 = A.sub_desc[2 * k], d1 = A.sub_desc[2 * k + 1];
+    // the wave's supernodes of this height, each one's descriptor record
+    // loaded while the previous supernode is solved
+    const int kend = A.sub_lvl[l0 + l + 1];
+    int k = A.sub_lvl[l0 + l] + wave;
+    int4 d0 = make_int4(0, 0, 0, 0), d1 = d0;
+    if (k < kend) {
+      d0 = A.sub_desc[2 * k];
+      d1 = A.sub_desc[2 * k + 1];
+    }
+    for (; k < kend; k += W) {
+      int4 n0 = make_int4(0, 0, 0, 0), n1 = n0;
+      if (k + W < kend) {
+        n0 = A.sub_desc[2 * (k + W)];
+        n1 = A.sub_desc[2 * (k + W) + 1];
+      }
       if (backward)
         wave_backward<ROWS>(A, d0, d1, lane, R, r0, mine, F, S);
       else
         wave_forward<ROWS>(A, d0, d1, lane, R, r0, mine, F, S, l == 0);
+      d0 = n0;
+      d1 = n1;
     }
     __syncthreads();
   }
